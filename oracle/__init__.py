@@ -1,0 +1,371 @@
+"""Reference oracle for the BOLT oblivious map (arxiv 2509.01742).
+
+TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the
+CPU-baseline leg of the benchmark import this package.  The product path
+(the HIP library and its binding) never imports it.  It shares no code with
+that path.
+
+Two oracles live here:
+
+* ``PlainMap`` (O1) is the plain definition of the answers: a dictionary
+  with the Get/Put/Delete semantics of Sec. 2.1 (delete = a tombstone put).
+* ``OracleMap`` (O2) is a scalar, single-threaded C implementation of the
+  same oblivious procedure the GPU runs (``bolt_oracle.c``).  It covers the
+  build (PRF, P2C rounds, bitonic network, expansion network, page
+  write-out, position map) and batched access (Alg. 1 in the module order
+  of Sec. 5.1), and it records every access to the observable store.
+
+The C file is compiled by ``oracle/build.py`` into ``oracle/liboracle.so``.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+
+OK, EINVAL, ENOMEM, EDUPKEY, EOVERFLOW, EFULL, ESTATE, EBROKEN = 0, -1, -2, -3, -4, -5, -7, -99
+GET, PUT, DEL = 0, 1, 2
+ST_ABSENT, ST_FOUND, ST_UPDATED, ST_INSERTED, ST_DELETED = 0, 1, 1, 2, 3
+NONE32 = 0xFFFFFFFF
+
+
+class _Sizes(C.Structure):
+    _fields_ = [
+        ("cap", C.c_uint64), ("vs", C.c_uint32), ("c", C.c_uint32), ("alpha_pm", C.c_uint32),
+        ("Z", C.c_uint32), ("d", C.c_uint32), ("kpr", C.c_uint32), ("W", C.c_uint32),
+        ("B", C.c_uint64), ("K", C.c_uint64), ("M", C.c_uint64), ("R_pm", C.c_uint64),
+        ("page_bytes", C.c_uint64), ("stash_bound", C.c_uint64),
+    ]
+
+    def as_dict(self) -> dict:
+        return {name: int(getattr(self, name)) for name, _ in self._fields_}
+
+
+TRACE_DTYPE = np.dtype([("batch", "<u4"), ("kind", "<u4"), ("page", "<u8")])
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        from . import build as _build
+
+        _build.build()
+    lib = C.CDLL(_LIB_PATH)
+    P, U8P, U32P, U64P = C.c_void_p, C.POINTER(C.c_uint8), C.POINTER(C.c_uint32), C.POINTER(C.c_uint64)
+    lib.or_blake2s.argtypes = [P, C.c_uint32, P, C.c_uint32, P, C.c_uint64]
+    lib.or_prf.argtypes = [P, C.c_uint8, C.c_uint64, P]
+    lib.or_pair.argtypes = [C.c_uint64, C.c_uint64, C.c_uint64, P, P]
+    lib.or_sizing.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32,
+                              C.c_uint32, C.c_uint32, C.POINTER(_Sizes)]
+    lib.or_stash_bound.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint64]
+    lib.or_stash_bound.restype = C.c_uint64
+    for name, n in (("or_claim43_bound", 4), ("or_claim44_bound", 4), ("or_claim52_bits", 7)):
+        getattr(lib, name).argtypes = [C.c_double] * n
+        getattr(lib, name).restype = C.c_double
+    lib.or_bitonic_sort_u64.argtypes = [P, C.c_uint64]
+    lib.or_expand.argtypes = [P, P, C.c_uint64, C.c_uint64, P]
+    lib.or_compact.argtypes = [P, P, C.c_uint64, P]
+    lib.or_create.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32,
+                              C.c_uint32, C.c_uint32, P, C.c_int]
+    lib.or_create.restype = C.c_void_p
+    lib.or_destroy.argtypes = [P]
+    lib.or_build.argtypes = [P, P, P, C.c_uint64, C.c_int]
+    lib.or_access.argtypes = [P, P, P, P, P, P, C.c_uint32]
+    lib.or_get_sizes.argtypes = [P]
+    lib.or_get_sizes.restype = C.POINTER(_Sizes)
+    for name in ("or_obs_ptr", "or_hbm_ptr"):
+        getattr(lib, name).argtypes = [P]
+        getattr(lib, name).restype = C.c_void_p
+    lib.or_load_ptr.argtypes = [P]
+    lib.or_load_ptr.restype = C.c_void_p
+    for name in ("or_ctr", "or_live", "or_stash_live", "or_stash_highwater", "or_trace_len"):
+        getattr(lib, name).argtypes = [P]
+        getattr(lib, name).restype = C.c_uint64
+    lib.or_trace_copy.argtypes = [P, P, C.c_uint64]
+    lib.or_trace_copy.restype = C.c_uint64
+    lib.or_trace_clear.argtypes = [P]
+    lib.or_stash_copy.argtypes = [P, P, P, P, C.c_uint64]
+    lib.or_stash_copy.restype = C.c_uint64
+    lib.or_pm_copy.argtypes = [P, P, P, P, P, C.c_uint64]
+    lib.or_pm_copy.restype = C.c_uint64
+    lib.or_pm_max_row.argtypes = [P]
+    lib.or_pm_max_row.restype = C.c_uint32
+    _lib = lib
+    return lib
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+# --------------------------------------------------------------------------
+# primitives
+# --------------------------------------------------------------------------
+
+def blake2s(key: bytes, msg: bytes, nn: int = 32) -> bytes:
+    """Keyed BLAKE2s (RFC 7693)."""
+    lib = _load()
+    out = (C.c_uint8 * 32)()
+    kb = (C.c_uint8 * max(1, len(key))).from_buffer_copy(key or b"\0")
+    mb = (C.c_uint8 * max(1, len(msg))).from_buffer_copy(msg or b"\0")
+    rc = lib.or_blake2s(out, nn, kb, len(key), mb, len(msg))
+    if rc:
+        raise ValueError("bad BLAKE2s lengths")
+    return bytes(out)[:nn]
+
+
+def prf(key: bytes, domain: int, x: int) -> tuple:
+    """PRF_K(domain, x) = BLAKE2s_K(domain || LE64(x)) as four LE64 words."""
+    lib = _load()
+    w = (C.c_uint64 * 4)()
+    kb = (C.c_uint8 * 32).from_buffer_copy(key)
+    lib.or_prf(kb, domain, x, w)
+    return tuple(int(v) for v in w)
+
+
+def pair(w0: int, w1: int, B: int) -> tuple:
+    lib = _load()
+    a, b = C.c_uint32(), C.c_uint32()
+    lib.or_pair(w0, w1, B, C.byref(a), C.byref(b))
+    return a.value, b.value
+
+
+def sizing(cap, vs, c=8, alpha_pm=200, bin_slots=0, d=4, kpr=16, W=32) -> dict:
+    lib = _load()
+    s = _Sizes()
+    if lib.or_sizing(cap, vs, c, alpha_pm, bin_slots, d, kpr, W, C.byref(s)):
+        raise ValueError("invalid parameters")
+    return s.as_dict()
+
+
+def stash_bound(M, alpha_pm, Z, cap) -> int:
+    return int(_load().or_stash_bound(M, alpha_pm, Z, cap))
+
+
+def claim43_bound(K, c, lmax, N) -> float:
+    """Claim 4.3 bound on the summed HBM bin loads (O() constant 1)."""
+    return float(_load().or_claim43_bound(K, c, lmax, N))
+
+
+def claim44_bound(M, alpha, lmax, N) -> float:
+    """Claim 4.4 bound on the stash size (O() constant 1)."""
+    return float(_load().or_claim44_bound(M, alpha, lmax, N))
+
+
+def claim52_bits(N, ks_bits, vs_bits, beta1, beta2, R, d) -> float:
+    """Claim 5.2 bound on HBM usage, in bits."""
+    return float(_load().or_claim52_bits(N, ks_bits, vs_bits, beta1, beta2, R, d))
+
+
+def bitonic_sort(a) -> np.ndarray:
+    """Scalar bitonic sorting network (ascending); len(a) a power of two."""
+    x = np.ascontiguousarray(a, dtype=np.uint64).copy()
+    if _load().or_bitonic_sort_u64(_ptr(x), x.size):
+        raise ValueError("length must be a power of two")
+    return x
+
+
+def expand(target, payload, m: int):
+    """Expansion (shift) network; returns (payload per position, collision flag)."""
+    t = np.ascontiguousarray(target, dtype=np.uint32)
+    p = np.ascontiguousarray(payload, dtype=np.uint32)
+    out = np.empty(m, dtype=np.uint32)
+    rc = _load().or_expand(_ptr(t), _ptr(p), t.size, m, _ptr(out))
+    return out, rc
+
+
+def compact(keep, payload):
+    """Order-preserving compaction (shift) network; returns (out, collision flag)."""
+    k = np.ascontiguousarray(keep, dtype=np.uint8)
+    p = np.ascontiguousarray(payload, dtype=np.uint32)
+    out = np.empty(k.size, dtype=np.uint32)
+    rc = _load().or_compact(_ptr(k), _ptr(p), k.size, _ptr(out))
+    return out, rc
+
+
+# --------------------------------------------------------------------------
+# page format (shared reading of the paper's "flag bit, key, value" tuples)
+# --------------------------------------------------------------------------
+
+def decode_page(page: np.ndarray, Z: int, vs: int) -> list:
+    """[(key, value bytes)] of the real slots of one page, in slot order."""
+    page = np.asarray(page, dtype=np.uint8)
+    mask = int(page[:8].view("<u8")[0])
+    keys = page[8:8 + 8 * Z].view("<u8")
+    out = []
+    for j in range(Z):
+        if (mask >> j) & 1:
+            off = 8 + 8 * Z + j * vs
+            out.append((int(keys[j]), bytes(page[off:off + vs])))
+    return out
+
+
+# --------------------------------------------------------------------------
+# O1: the plain definition of the answers
+# --------------------------------------------------------------------------
+
+class PlainMap:
+    """Dictionary semantics of Get / Put / Delete (Sec. 2.1)."""
+
+    def __init__(self, vs: int):
+        self.vs = vs
+        self.d: dict = {}
+
+    def build(self, keys, vals) -> None:
+        vals = np.asarray(vals, dtype=np.uint8).reshape(len(keys), self.vs)
+        for k, v in zip(np.asarray(keys, dtype=np.uint64).tolist(), vals):
+            self.d[int(k)] = bytes(v)
+
+    def access(self, ops, keys, vals_in):
+        q = len(ops)
+        vals_in = np.asarray(vals_in, dtype=np.uint8).reshape(q, self.vs)
+        out = np.zeros((q, self.vs), dtype=np.uint8)
+        st = np.zeros(q, dtype=np.uint8)
+        zero = bytes(self.vs)
+        for i, (op, k) in enumerate(zip(np.asarray(ops).tolist(), np.asarray(keys, dtype=np.uint64).tolist())):
+            k = int(k)
+            had = k in self.d
+            if op == GET:
+                st[i] = ST_FOUND if had else ST_ABSENT
+                out[i] = np.frombuffer(self.d.get(k, zero), dtype=np.uint8)
+            elif op == PUT:
+                st[i] = ST_UPDATED if had else ST_INSERTED
+                self.d[k] = bytes(vals_in[i])
+            elif op == DEL:
+                st[i] = ST_DELETED if had else ST_ABSENT
+                self.d.pop(k, None)
+            else:
+                raise ValueError("bad op")
+        return out, st
+
+
+# --------------------------------------------------------------------------
+# O2: the scalar procedure
+# --------------------------------------------------------------------------
+
+class OracleMap:
+    def __init__(self, cap, vs, c=8, alpha_pm=200, bin_slots=0, d=4, kpr=16, W=32, key=bytes(32),
+                 trace=False):
+        lib = _load()
+        kb = (C.c_uint8 * 32).from_buffer_copy(bytes(key))
+        self._h = lib.or_create(cap, vs, c, alpha_pm, bin_slots, d, kpr, W, kb, 1 if trace else 0)
+        if not self._h:
+            raise ValueError("invalid parameters")
+        self._lib = lib
+        self.s = lib.or_get_sizes(self._h).contents.as_dict()
+
+    def close(self):
+        if self._h:
+            self._lib.or_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def build(self, keys, vals, mode: int = 0) -> int:
+        k = np.ascontiguousarray(keys, dtype=np.uint64)
+        v = np.ascontiguousarray(vals, dtype=np.uint8).reshape(-1)
+        assert v.size == k.size * self.s["vs"]
+        return int(self._lib.or_build(self._h, _ptr(k), _ptr(v), k.size, mode))
+
+    def access(self, ops, keys, vals_in):
+        o = np.ascontiguousarray(ops, dtype=np.uint8)
+        k = np.ascontiguousarray(keys, dtype=np.uint64)
+        q = o.size
+        vs = self.s["vs"]
+        vi = np.ascontiguousarray(vals_in, dtype=np.uint8).reshape(q * vs) if q else np.zeros(1, np.uint8)
+        vo = np.zeros(max(1, q * vs), dtype=np.uint8)
+        st = np.zeros(max(1, q), dtype=np.uint8)
+        rc = int(self._lib.or_access(self._h, _ptr(o), _ptr(k), _ptr(vi), _ptr(vo), _ptr(st), q))
+        return rc, vo[:q * vs].reshape(q, vs), st[:q]
+
+    # --- state ----------------------------------------------------------
+    def observable(self) -> np.ndarray:
+        M, pb = self.s["M"], self.s["page_bytes"]
+        p = self._lib.or_obs_ptr(self._h)
+        return np.ctypeslib.as_array(C.cast(p, C.POINTER(C.c_uint8)), shape=(M * pb,)).reshape(M, pb).copy()
+
+    def hbm_bins(self) -> np.ndarray:
+        K, pb = self.s["K"], self.s["page_bytes"]
+        if K == 0:
+            return np.zeros((0, pb), dtype=np.uint8)
+        p = self._lib.or_hbm_ptr(self._h)
+        return np.ctypeslib.as_array(C.cast(p, C.POINTER(C.c_uint8)), shape=(K * pb,)).reshape(K, pb).copy()
+
+    def loads(self) -> np.ndarray:
+        p = self._lib.or_load_ptr(self._h)
+        return np.ctypeslib.as_array(C.cast(p, C.POINTER(C.c_uint32)), shape=(self.s["B"],)).copy()
+
+    def stash(self) -> list:
+        """[(key, dest bin, value bytes)] sorted."""
+        n = int(self._lib.or_stash_copy(self._h, None, None, None, 0))
+        k = np.zeros(max(1, n), np.uint64)
+        d = np.zeros(max(1, n), np.uint32)
+        v = np.zeros(max(1, n) * self.s["vs"], np.uint8)
+        self._lib.or_stash_copy(self._h, _ptr(k), _ptr(d), _ptr(v), n)
+        vs = self.s["vs"]
+        return sorted((int(k[i]), int(d[i]), bytes(v[i * vs:(i + 1) * vs])) for i in range(n))
+
+    def pmap(self) -> list:
+        """[(row, key, p1, p2)] sorted."""
+        n = int(self._lib.or_pm_copy(self._h, None, None, None, None, 0))
+        r = np.zeros(max(1, n), np.uint64)
+        k = np.zeros(max(1, n), np.uint64)
+        a = np.zeros(max(1, n), np.uint32)
+        b = np.zeros(max(1, n), np.uint32)
+        self._lib.or_pm_copy(self._h, _ptr(r), _ptr(k), _ptr(a), _ptr(b), n)
+        return sorted((int(r[i]), int(k[i]), int(a[i]), int(b[i])) for i in range(n))
+
+    def pm_max_row(self) -> int:
+        return int(self._lib.or_pm_max_row(self._h))
+
+    def trace(self) -> np.ndarray:
+        n = int(self._lib.or_trace_len(self._h))
+        out = np.zeros(n, dtype=TRACE_DTYPE)
+        if n:
+            self._lib.or_trace_copy(self._h, _ptr(out), n)
+        return out
+
+    def trace_clear(self):
+        self._lib.or_trace_clear(self._h)
+
+    @property
+    def ctr(self):
+        return int(self._lib.or_ctr(self._h))
+
+    @property
+    def live(self):
+        return int(self._lib.or_live(self._h))
+
+    @property
+    def stash_live(self):
+        return int(self._lib.or_stash_live(self._h))
+
+    @property
+    def stash_highwater(self):
+        return int(self._lib.or_stash_highwater(self._h))
+
+    def logical_contents(self) -> dict:
+        """key -> value over HBM bins, observable pages and the stash."""
+        Z, vs = self.s["Z"], self.s["vs"]
+        out = {}
+        for arr in (self.hbm_bins(), self.observable()):
+            for page in arr:
+                for k, v in decode_page(page, Z, vs):
+                    assert k not in out, "key stored twice"
+                    out[k] = v
+        for k, _, v in self.stash():
+            assert k not in out, "key stored twice"
+            out[k] = v
+        return out
