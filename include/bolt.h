@@ -1,0 +1,241 @@
+/*
+ * bolt.h - C ABI of an oblivious key-value map on one AMD Instinct MI355X
+ * (gfx950), after BOLT (arxiv 2509.01742).
+ *
+ * The map splits K + M logical bins between the GPU's HBM (K bins, never
+ * observable) and an observable store of M fixed-size pages (pinned host
+ * memory reached over the host link, or a designated device buffer).  Every
+ * key sits in one of two random bins, the less loaded one (Sec. 4.1, Alg. 1).
+ * A lookup reads both bins whole and then moves the key to two fresh random
+ * bins, so the observable store sees two uniformly random bins per command
+ * whatever the keys, values and commands are (Claim 4.1).
+ *
+ * Conventions for every call below
+ *   - Pointers named d_* are device pointers (for example a torch tensor's
+ *     data_ptr()) owned by the caller; they must stay valid until the stream
+ *     reaches the call.  Host pointers are named host_* and are used before
+ *     the call returns.
+ *   - hip_stream is a hipStream_t (NULL = the legacy default stream).  Calls
+ *     are ordered on the stream and return before the device work ends;
+ *     results are valid after the stream has been synchronised.  Calls on one
+ *     map must not overlap from several host threads.
+ *   - A negative return is an error.  Argument errors are reported at once and
+ *     change nothing.  Errors found on the device (capacity overflow, duplicate
+ *     build keys, live keys beyond capacity) are sticky: bolt_status() reports
+ *     them after synchronising, and from then on the map is poisoned and every
+ *     call except bolt_destroy returns BOLT_ESTATE.
+ *   - Keys are any 64-bit values.  Values are value_bytes bytes each, rows of
+ *     a row-major [q][value_bytes] array.
+ */
+#ifndef BOLT_H
+#define BOLT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct bolt_map bolt_map; /* opaque, owned by the library */
+
+/* Return codes. */
+enum {
+  BOLT_OK = 0,
+  BOLT_EINVAL = -1,    /* bad argument, or a call in the wrong state */
+  BOLT_ENOMEM = -2,    /* device or pinned host allocation failed */
+  BOLT_EDUPKEY = -3,   /* bolt_build got the same key twice (keys are unique, Sec. 2.1) */
+  BOLT_EOVERFLOW = -4, /* a bin, stash or position-map row would exceed its capacity */
+  BOLT_EFULL = -5,     /* live keys would exceed the capacity (or the trace log is full) */
+  BOLT_EHIP = -6,      /* a HIP runtime call failed */
+  BOLT_ESTATE = -7     /* the map is poisoned by an earlier device-side error */
+};
+
+/* Operation codes of a command <opcode | key | payload> (Sec. 5.1 step 2).
+ * A delete is the paper's PUT with a tombstone payload, given its own code
+ * so that every value stays usable. */
+enum { BOLT_OP_GET = 0, BOLT_OP_PUT = 1, BOLT_OP_DEL = 2 };
+
+/* Per-command status byte of the fixed-length response (Sec. 5.1 step 6). */
+enum {
+  BOLT_ST_ABSENT = 0,   /* GET or DEL of a key that was not present */
+  BOLT_ST_FOUND = 1,    /* GET of a present key */
+  BOLT_ST_UPDATED = 1,  /* PUT of a present key */
+  BOLT_ST_INSERTED = 2, /* PUT of an absent key */
+  BOLT_ST_DELETED = 3   /* DEL of a present key */
+};
+
+/* Where the M observable pages live. */
+enum { BOLT_OBS_HOST_PINNED = 0, BOLT_OBS_DEVICE = 1 };
+
+/* bolt_params.flags */
+#define BOLT_F_TRACE 1u     /* record every observable access (tests; costs a little time) */
+#define BOLT_F_FIXED_KEY 2u /* use params.key as the PRF key instead of fresh OS randomness */
+
+#define BOLT_MAX_BATCH 8192u /* most commands in one access call */
+
+typedef struct {
+  uint64_t capacity;       /* N_max: most live keys the map will hold */
+  uint32_t value_bytes;    /* vs: bytes per value, a multiple of 8, at most 4096 */
+  uint32_t c;              /* mean bin load N/(K+M) (Claim 4.2); the paper's default is 8 */
+  uint32_t alpha_permille; /* alpha = K/(K+M) in 1/1000 (Claim 4.4); default 200, below 1000 */
+  uint32_t bin_slots;      /* Z, items per bin; 0 = c + ceil(log2 ceil(log2 N_max)) + 1 (Claim 4.2) */
+  uint32_t pm_choices;     /* d, position-map rows a key may use (Sec. 5.2); 1..4, default 4 */
+  uint32_t pm_keys_per_row;/* N_max / rows of the position map (Sec. 5.2); default 16 */
+  uint32_t pm_row_slots;   /* slots per position-map row, 1..32; default 32 */
+  uint32_t observable;     /* BOLT_OBS_* */
+  uint32_t flags;          /* BOLT_F_* */
+  uint64_t trace_words;    /* capacity of the trace log in 32-bit words (BOLT_F_TRACE) */
+  uint8_t key[32];         /* PRF key when BOLT_F_FIXED_KEY is set */
+} bolt_params;
+
+/* Sizes the library derives from the parameters (all integers). */
+typedef struct {
+  uint64_t B;           /* bins K + M = ceil(N_max / c) */
+  uint64_t K;           /* HBM bins = floor(alpha_permille * B / 1000) */
+  uint64_t M;           /* observable pages = B - K */
+  uint64_t Z;           /* items per bin (page capacity) */
+  uint64_t page_bytes;  /* bytes per page: u64 valid mask, Z keys, Z values, zero pad to 128 */
+  uint64_t pm_rows;     /* position-map rows = ceil(N_max / pm_keys_per_row) */
+  uint64_t stash_bound; /* ceil((1 + alpha) M / 2 + Z sqrt(M ln N_max)) (Claim 4.4, constant 1) */
+  uint64_t stash_pool;  /* stash entries allocated: stash_bound + BOLT_MAX_BATCH */
+} bolt_sizes;
+
+/* Fills p with the paper's defaults (c = 8, alpha = 0.2, d = 4, 16 keys per
+ * row, 32 slots) for the given capacity and value size.  No allocation. */
+void bolt_params_default(bolt_params* p, uint64_t capacity, uint32_t value_bytes);
+
+/* Derives the sizes of p.  Returns BOLT_EINVAL for parameters out of range. */
+int bolt_sizes_of(const bolt_params* p, bolt_sizes* out);
+
+/* Device (HBM) bytes and observable-store bytes one map with parameters p
+ * allocates: the analogue of the HBM-usage bound of Claim 5.2 for this
+ * layout.  Used to admit maps against an HBM budget.  Either pointer may be
+ * NULL. */
+int bolt_footprint(const bolt_params* p, uint64_t* hbm_bytes, uint64_t* obs_bytes);
+
+/* Creates an empty, unbuilt map on the current HIP device: allocates all
+ * state (Sec. 5.1 step 1) and derives the PRF key.  *out receives the map.
+ * Returns BOLT_EINVAL, BOLT_ENOMEM or BOLT_EHIP on failure (nothing leaks). */
+int bolt_create(const bolt_params* p, void* hip_stream, bolt_map** out);
+
+/* Oblivious build of the map from n distinct keys d_keys[n] and values
+ * d_vals[n][value_bytes] (n <= capacity, n may be 0).  This is the paper's
+ * data initialization (Sec. 5.2, "fast data initialization") done on the
+ * device without a trusted data owner: a keyed PRF gives each key two bins,
+ * P2C places it, a bitonic sorting network and a shift network lay the items
+ * into dummy-padded bins, and the pages are written in order 0..M-1, so the
+ * observable store sees the same writes for every dataset of size n.
+ * Once per map.  Duplicate keys end in BOLT_EDUPKEY (sticky). */
+int bolt_build(bolt_map* m, const uint64_t* d_keys, const void* d_vals, uint64_t n, void* hip_stream);
+
+/* Runs q <= BOLT_MAX_BATCH commands in one batch (Alg. 1 per command, Sec. 5.1
+ * steps 2-6).  d_ops[q] holds BOLT_OP_* codes, d_keys[q] the keys,
+ * d_vals_in[q][vs] the PUT payloads (read for PUT only; may be NULL if no
+ * command is a PUT).  Outputs: d_vals_out[q][vs] the value of each GET of a
+ * present key and zeros otherwise (fixed-length responses), d_status[q] a
+ * BOLT_ST_* byte.  The answers equal running the commands one at a time in
+ * index order.  Every command reads two whole bins; each page read is
+ * written back once at the end of the batch.  An op code out of range makes
+ * the device reject the whole batch (sticky BOLT_EINVAL is not used: ops are
+ * checked on the device and the batch leaves the map unchanged, status 0xFF). */
+int bolt_access_batch(bolt_map* m, const uint8_t* d_ops, const uint64_t* d_keys, const void* d_vals_in,
+                      void* d_vals_out, uint8_t* d_status, uint32_t q, void* hip_stream);
+
+/* q GETs: d_vals_out[q][vs] gets each value (zeros when absent), d_found[q]
+ * gets 1 when the key was present and 0 otherwise. */
+int bolt_get_batch(bolt_map* m, const uint64_t* d_keys, uint32_t q, void* d_vals_out, uint8_t* d_found,
+                   void* hip_stream);
+
+/* q PUTs of d_vals[q][vs]; d_status[q] gets BOLT_ST_UPDATED or BOLT_ST_INSERTED. */
+int bolt_put_batch(bolt_map* m, const uint64_t* d_keys, const void* d_vals, uint32_t q, uint8_t* d_status,
+                   void* hip_stream);
+
+/* Frees every resource of the map after waiting for its work.  NULL is a no-op. */
+int bolt_destroy(bolt_map* m);
+
+/* Synchronises the map's last stream and returns BOLT_OK or the sticky
+ * device-side error (BOLT_EOVERFLOW before BOLT_EDUPKEY before BOLT_EFULL). */
+int bolt_status(bolt_map* m);
+
+/* Derived sizes of an existing map. */
+int bolt_map_sizes(const bolt_map* m, bolt_sizes* out);
+
+/* Counters of an existing map (synchronises first). */
+typedef struct {
+  uint64_t live;            /* keys present */
+  uint64_t steps;           /* commands run so far (the tape counter) */
+  uint64_t batches;         /* access batches run */
+  uint64_t stash_live;      /* items in the eviction stash */
+  uint64_t stash_highwater; /* largest stash_live seen at the end of a batch */
+  uint32_t max_load;        /* largest bin load now */
+  uint32_t max_row;         /* fullest position-map row now */
+} bolt_stats;
+int bolt_get_stats(bolt_map* m, bolt_stats* out);
+
+/* ---------------------------------------------------------------------
+ * Trace and state readout (tests and diagnostics).  All of these
+ * synchronise the map's stream first and copy into host memory.
+ * --------------------------------------------------------------------- */
+
+/* One observable access.  batch 0 is the build; access batches count from
+ * 1.  kind 0 = read of a whole page, 1 = write of a whole page.  Within a
+ * batch the reads come in command order (two roles per command, HBM bins
+ * omitted), then the writes in ascending page order, as one canonical
+ * sequence of what the accessor did (the writes of one batch run
+ * concurrently on the device). */
+typedef struct {
+  uint32_t batch;
+  uint32_t kind;
+  uint64_t page;
+} bolt_trace_rec;
+
+/* Copies up to cap records of the trace recorded since create (or the last
+ * clear) into host_recs; *n receives the total count.  Returns BOLT_EINVAL if
+ * the map was created without BOLT_F_TRACE, BOLT_EFULL if the log filled up
+ * and records were lost. */
+int bolt_trace_read(bolt_map* m, bolt_trace_rec* host_recs, uint64_t cap, uint64_t* n);
+int bolt_trace_clear(bolt_map* m);
+
+/* Raw state: the M observable pages, the K HBM bins, the B bin loads (u32).
+ * cap is the size of the host buffer in bytes; it must hold the whole array. */
+int bolt_observable_snapshot(bolt_map* m, void* host_buf, uint64_t cap);
+int bolt_hbm_snapshot(bolt_map* m, void* host_buf, uint64_t cap);
+int bolt_loads_snapshot(bolt_map* m, uint32_t* host_buf, uint64_t cap);
+
+/* Logical stash: up to cap live entries as (key, destination bin, value);
+ * host_vals holds cap * value_bytes bytes.  *n receives the live count. */
+int bolt_stash_snapshot(bolt_map* m, uint64_t* host_keys, uint32_t* host_bins, void* host_vals, uint64_t cap,
+                        uint64_t* n);
+
+/* Logical position map: up to cap entries as (row, key, p1, p2); *n receives
+ * the entry count. */
+int bolt_pm_snapshot(bolt_map* m, uint64_t* host_rows, uint64_t* host_keys, uint32_t* host_p1,
+                     uint32_t* host_p2, uint64_t cap, uint64_t* n);
+
+/* ---------------------------------------------------------------------
+ * Device primitives of the path, exported so each can be checked alone.
+ * --------------------------------------------------------------------- */
+
+/* d_out[4 * i .. 4 * i + 3] = BLAKE2s-256 keyed with host_key[32] of the
+ * nine bytes (domain, LE64(d_x[i])), as four little-endian 64-bit words:
+ * the PRF that stands in for the key hash of Sec. 5.1 step 3 and for
+ * random_remap of Alg. 1.  n may be 0. */
+int bolt_prf(const uint8_t* host_key, uint8_t domain, const uint64_t* d_x, uint64_t n, uint64_t* d_out,
+             void* hip_stream);
+
+/* Sorts d_data[n] ascending in place with the bitonic sorting network used
+ * by the build (n must be a power of two, 1 <= n <= 2^31).  The sequence of
+ * memory accesses depends on n only. */
+int bolt_sort_u64(uint64_t* d_data, uint64_t n, void* hip_stream);
+
+/* Expansion network used by the build: d_elems[m] holds elements at
+ * positions 0..n-1 as (target << 32 | payload) with strictly increasing
+ * targets >= their position, and 0xFFFFFFFFFFFFFFFF from n on.  On return each
+ * element sits at its target and every other position holds all ones.
+ * d_tmp[m] is scratch.  Results are undefined if the targets break the rule. */
+int bolt_expand_u64(uint64_t* d_elems, uint64_t* d_tmp, uint64_t m, void* hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BOLT_H */

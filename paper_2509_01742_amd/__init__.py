@@ -1,0 +1,275 @@
+"""Python binding of the oblivious-map library ``libbolt.so`` (include/bolt.h).
+
+The binding only marshals arguments: every step of the build and of the
+batched get/put runs in the library's HIP kernels.  PyTorch supplies device
+memory and streams.  If the library is not built this module raises at
+import: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libbolt.so")
+
+BOLT_OK, BOLT_EINVAL, BOLT_ENOMEM, BOLT_EDUPKEY, BOLT_EOVERFLOW, BOLT_EFULL, BOLT_EHIP, BOLT_ESTATE = (
+    0, -1, -2, -3, -4, -5, -6, -7)
+BOLT_OP_GET, BOLT_OP_PUT, BOLT_OP_DEL = 0, 1, 2
+BOLT_ST_ABSENT, BOLT_ST_FOUND, BOLT_ST_UPDATED, BOLT_ST_INSERTED, BOLT_ST_DELETED = 0, 1, 1, 2, 3
+BOLT_OBS_HOST_PINNED, BOLT_OBS_DEVICE = 0, 1
+BOLT_F_TRACE, BOLT_F_FIXED_KEY = 1, 2
+BOLT_MAX_BATCH = 8192
+
+_NAMES = {0: "BOLT_OK", -1: "BOLT_EINVAL", -2: "BOLT_ENOMEM", -3: "BOLT_EDUPKEY", -4: "BOLT_EOVERFLOW",
+          -5: "BOLT_EFULL", -6: "BOLT_EHIP", -7: "BOLT_ESTATE"}
+
+
+class BoltError(RuntimeError):
+    def __init__(self, rc: int, what: str):
+        super().__init__("%s failed: %s (%d)" % (what, _NAMES.get(rc, "?"), rc))
+        self.rc = rc
+
+
+class bolt_params(C.Structure):
+    _fields_ = [
+        ("capacity", C.c_uint64), ("value_bytes", C.c_uint32), ("c", C.c_uint32),
+        ("alpha_permille", C.c_uint32), ("bin_slots", C.c_uint32), ("pm_choices", C.c_uint32),
+        ("pm_keys_per_row", C.c_uint32), ("pm_row_slots", C.c_uint32), ("observable", C.c_uint32),
+        ("flags", C.c_uint32), ("trace_words", C.c_uint64), ("key", C.c_uint8 * 32),
+    ]
+
+
+class bolt_sizes(C.Structure):
+    _fields_ = [(n, C.c_uint64) for n in ("B", "K", "M", "Z", "page_bytes", "pm_rows", "stash_bound", "stash_pool")]
+
+    def as_dict(self):
+        return {n: int(getattr(self, n)) for n, _ in self._fields_}
+
+
+class bolt_stats(C.Structure):
+    _fields_ = [("live", C.c_uint64), ("steps", C.c_uint64), ("batches", C.c_uint64), ("stash_live", C.c_uint64),
+                ("stash_highwater", C.c_uint64), ("max_load", C.c_uint32), ("max_row", C.c_uint32)]
+
+    def as_dict(self):
+        return {n: int(getattr(self, n)) for n, _ in self._fields_}
+
+
+class bolt_trace_rec(C.Structure):
+    _fields_ = [("batch", C.c_uint32), ("kind", C.c_uint32), ("page", C.c_uint64)]
+
+
+TRACE_DTYPE = np.dtype([("batch", "<u4"), ("kind", "<u4"), ("page", "<u8")])
+
+# (name, restype, argtypes) of every entry point in include/bolt.h
+_P, _U8, _U32, _U64, _I = C.c_void_p, C.c_uint8, C.c_uint32, C.c_uint64, C.c_int
+_SIGS = [
+    ("bolt_params_default", None, [C.POINTER(bolt_params), _U64, _U32]),
+    ("bolt_sizes_of", _I, [C.POINTER(bolt_params), C.POINTER(bolt_sizes)]),
+    ("bolt_footprint", _I, [C.POINTER(bolt_params), C.POINTER(_U64), C.POINTER(_U64)]),
+    ("bolt_create", _I, [C.POINTER(bolt_params), _P, C.POINTER(_P)]),
+    ("bolt_build", _I, [_P, _P, _P, _U64, _P]),
+    ("bolt_access_batch", _I, [_P, _P, _P, _P, _P, _P, _U32, _P]),
+    ("bolt_get_batch", _I, [_P, _P, _U32, _P, _P, _P]),
+    ("bolt_put_batch", _I, [_P, _P, _P, _U32, _P, _P]),
+    ("bolt_destroy", _I, [_P]),
+    ("bolt_status", _I, [_P]),
+    ("bolt_map_sizes", _I, [_P, C.POINTER(bolt_sizes)]),
+    ("bolt_get_stats", _I, [_P, C.POINTER(bolt_stats)]),
+    ("bolt_trace_read", _I, [_P, _P, _U64, C.POINTER(_U64)]),
+    ("bolt_trace_clear", _I, [_P]),
+    ("bolt_observable_snapshot", _I, [_P, _P, _U64]),
+    ("bolt_hbm_snapshot", _I, [_P, _P, _U64]),
+    ("bolt_loads_snapshot", _I, [_P, _P, _U64]),
+    ("bolt_stash_snapshot", _I, [_P, _P, _P, _P, _U64, C.POINTER(_U64)]),
+    ("bolt_pm_snapshot", _I, [_P, _P, _P, _P, _P, _U64, C.POINTER(_U64)]),
+    ("bolt_prf", _I, [_P, _U8, _P, _U64, _P, _P]),
+    ("bolt_sort_u64", _I, [_P, _U64, _P]),
+    ("bolt_expand_u64", _I, [_P, _P, _U64, _P]),
+]
+EXPORTED = [s[0] for s in _SIGS]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libbolt.so is not built (run __graft_entry__.build() or paper_2509_01742_amd/build.py); "
+                          "there is no fallback path")
+    lib = C.CDLL(LIB_PATH)
+    for name, res, args in _SIGS:
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    return lib
+
+
+lib = _load()
+
+# Module-level names identical to the C ABI.
+for _name, _, _ in _SIGS:
+    globals()[_name] = getattr(lib, _name)
+
+
+# --------------------------------------------------------------------------
+# marshalling helpers (torch only for device memory and streams)
+# --------------------------------------------------------------------------
+
+def _stream(stream=None):
+    import torch
+
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _dptr(t):
+    return C.c_void_p(0 if t is None else t.data_ptr())
+
+
+def check(rc: int, what: str) -> int:
+    if rc != BOLT_OK:
+        raise BoltError(rc, what)
+    return rc
+
+
+def params(capacity: int, value_bytes: int, **kw) -> bolt_params:
+    p = bolt_params()
+    bolt_params_default(C.byref(p), capacity, value_bytes)
+    key = kw.pop("key", None)
+    if key is not None:
+        key = bytes(key)
+        assert len(key) == 32
+        C.memmove(p.key, key, 32)
+        p.flags |= BOLT_F_FIXED_KEY
+    for k, v in kw.items():
+        if not hasattr(p, k):
+            raise TypeError("unknown parameter %s" % k)
+        setattr(p, k, v)
+    return p
+
+
+def sizes_of(p: bolt_params) -> dict:
+    s = bolt_sizes()
+    check(bolt_sizes_of(C.byref(p), C.byref(s)), "bolt_sizes_of")
+    return s.as_dict()
+
+
+def footprint(p: bolt_params) -> tuple:
+    h, o = C.c_uint64(), C.c_uint64()
+    check(bolt_footprint(C.byref(p), C.byref(h), C.byref(o)), "bolt_footprint")
+    return int(h.value), int(o.value)
+
+
+class Map:
+    """One oblivious map on the current device (owns a bolt_map*)."""
+
+    def __init__(self, p: bolt_params, stream=None):
+        h = C.c_void_p()
+        check(bolt_create(C.byref(p), _stream(stream), C.byref(h)), "bolt_create")
+        self.h = h
+        self.p = p
+        self.sizes = sizes_of(p)
+        self.vs = int(p.value_bytes)
+
+    def close(self):
+        if self.h is not None and self.h.value:
+            bolt_destroy(self.h)
+        self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # --- the path -------------------------------------------------------
+    def build(self, keys, vals, stream=None) -> int:
+        """keys: int64/uint64 cuda tensor [n]; vals: uint8 cuda tensor [n, vs]."""
+        n = 0 if keys is None else keys.numel()
+        return bolt_build(self.h, _dptr(keys), _dptr(vals), n, _stream(stream))
+
+    def access(self, ops, keys, vals_in, vals_out, status, stream=None) -> int:
+        q = ops.numel()
+        return bolt_access_batch(self.h, _dptr(ops), _dptr(keys), _dptr(vals_in), _dptr(vals_out), _dptr(status),
+                                 q, _stream(stream))
+
+    def get(self, keys, vals_out, found, stream=None) -> int:
+        return bolt_get_batch(self.h, _dptr(keys), keys.numel(), _dptr(vals_out), _dptr(found), _stream(stream))
+
+    def put(self, keys, vals, status, stream=None) -> int:
+        return bolt_put_batch(self.h, _dptr(keys), _dptr(vals), keys.numel(), _dptr(status), _stream(stream))
+
+    # --- state ----------------------------------------------------------
+    def status(self) -> int:
+        return bolt_status(self.h)
+
+    def stats(self) -> dict:
+        s = bolt_stats()
+        check(bolt_get_stats(self.h, C.byref(s)), "bolt_get_stats")
+        return s.as_dict()
+
+    def trace(self) -> np.ndarray:
+        n = C.c_uint64()
+        rc = bolt_trace_read(self.h, None, 0, C.byref(n))
+        if rc not in (BOLT_OK,):
+            raise BoltError(rc, "bolt_trace_read")
+        out = np.zeros(int(n.value), dtype=TRACE_DTYPE)
+        if n.value:
+            check(bolt_trace_read(self.h, out.ctypes.data_as(C.c_void_p), n.value, C.byref(n)), "bolt_trace_read")
+        return out
+
+    def trace_clear(self):
+        check(bolt_trace_clear(self.h), "bolt_trace_clear")
+
+    def observable(self) -> np.ndarray:
+        M, pb = self.sizes["M"], self.sizes["page_bytes"]
+        out = np.zeros((M, pb), dtype=np.uint8)
+        check(bolt_observable_snapshot(self.h, out.ctypes.data_as(C.c_void_p), out.nbytes), "observable_snapshot")
+        return out
+
+    def hbm_bins(self) -> np.ndarray:
+        K, pb = self.sizes["K"], self.sizes["page_bytes"]
+        out = np.zeros((K, pb), dtype=np.uint8)
+        check(bolt_hbm_snapshot(self.h, out.ctypes.data_as(C.c_void_p), out.nbytes), "hbm_snapshot")
+        return out
+
+    def loads(self) -> np.ndarray:
+        out = np.zeros(self.sizes["B"], dtype=np.uint32)
+        check(bolt_loads_snapshot(self.h, out.ctypes.data_as(C.c_void_p), out.nbytes), "loads_snapshot")
+        return out
+
+    def stash(self) -> list:
+        n = C.c_uint64()
+        check(bolt_stash_snapshot(self.h, None, None, None, 0, C.byref(n)), "stash_snapshot")
+        k = np.zeros(max(1, n.value), np.uint64)
+        b = np.zeros(max(1, n.value), np.uint32)
+        v = np.zeros(max(1, n.value) * self.vs, np.uint8)
+        check(bolt_stash_snapshot(self.h, k.ctypes.data_as(C.c_void_p), b.ctypes.data_as(C.c_void_p),
+                                  v.ctypes.data_as(C.c_void_p), n.value, C.byref(n)), "stash_snapshot")
+        vs = self.vs
+        return sorted((int(k[i]), int(b[i]), bytes(v[i * vs:(i + 1) * vs])) for i in range(int(n.value)))
+
+    def pmap(self) -> list:
+        n = C.c_uint64()
+        check(bolt_pm_snapshot(self.h, None, None, None, None, 0, C.byref(n)), "pm_snapshot")
+        m = max(1, n.value)
+        r, k = np.zeros(m, np.uint64), np.zeros(m, np.uint64)
+        a, b = np.zeros(m, np.uint32), np.zeros(m, np.uint32)
+        check(bolt_pm_snapshot(self.h, r.ctypes.data_as(C.c_void_p), k.ctypes.data_as(C.c_void_p),
+                               a.ctypes.data_as(C.c_void_p), b.ctypes.data_as(C.c_void_p), n.value, C.byref(n)),
+              "pm_snapshot")
+        return sorted((int(r[i]), int(k[i]), int(a[i]), int(b[i])) for i in range(int(n.value)))
+
+
+def prf(key: bytes, domain: int, x, out, stream=None) -> int:
+    """out[4 * i:4 * i + 4] = PRF_key(domain, x[i]) (device tensors)."""
+    kb = (C.c_uint8 * 32).from_buffer_copy(bytes(key))
+    return bolt_prf(kb, domain, _dptr(x), x.numel(), _dptr(out), _stream(stream))
+
+
+def sort_u64(data, stream=None) -> int:
+    return bolt_sort_u64(_dptr(data), data.numel(), _stream(stream))
+
+
+def expand_u64(elems, tmp, stream=None) -> int:
+    return bolt_expand_u64(_dptr(elems), _dptr(tmp), elems.numel(), _stream(stream))

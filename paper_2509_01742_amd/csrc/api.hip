@@ -1,0 +1,531 @@
+// C ABI of the oblivious map (see include/bolt.h): parameter derivation,
+// allocation of map state, argument checks, error state and readout.  All
+// of the path's arithmetic runs in the kernels of k_prim / k_build /
+// k_access; this file only sizes, allocates, launches and copies.
+#include <math.h>
+#include <string.h>
+#include <sys/random.h>
+
+#include <algorithm>
+#include <new>
+
+#include "bolt_impl.h"
+
+using namespace bolt;
+
+namespace {
+
+constexpr uint32_t kMaxZ = 62;  // keys of a page must sit in its first 64 words
+
+int derive(const bolt_params* p, Sizes* s) {
+  if (!p || p->capacity < 2 || p->value_bytes == 0 || p->value_bytes % 8 || p->value_bytes > 4096) return BOLT_EINVAL;
+  if (p->c == 0 || p->alpha_permille >= 1000 || p->pm_choices == 0 || p->pm_choices > 4) return BOLT_EINVAL;
+  if (p->pm_keys_per_row == 0 || p->pm_row_slots == 0 || p->pm_row_slots > 32) return BOLT_EINVAL;
+  if (p->observable > BOLT_OBS_DEVICE) return BOLT_EINVAL;
+  if (p->capacity > (1ull << 31)) return BOLT_EINVAL;
+  Sizes z{};
+  z.cap = p->capacity;
+  z.vs = p->value_bytes;
+  z.B = (p->capacity + p->c - 1) / p->c;  // N = c (K + M)
+  if (z.B < 2) return BOLT_EINVAL;
+  z.K = (uint64_t)p->alpha_permille * z.B / 1000;
+  z.M = z.B - z.K;
+  uint32_t l1 = 0;
+  while ((1ull << l1) < p->capacity) ++l1;
+  uint32_t l2 = 0;
+  while ((1u << l2) < l1) ++l2;
+  z.Z = p->bin_slots ? p->bin_slots : p->c + l2 + 1;  // l_max of Claim 4.2 with constant 1
+  if (z.Z == 0 || z.Z > kMaxZ) return BOLT_EINVAL;
+  z.W = p->pm_row_slots;
+  z.d = p->pm_choices;
+  z.R = (p->capacity + p->pm_keys_per_row - 1) / p->pm_keys_per_row;
+  uint64_t raw = 8 + 8 * z.Z + (uint64_t)z.vs * z.Z;
+  z.page_bytes = (raw + 127) / 128 * 128;
+  double a = (double)p->alpha_permille / 1000.0;
+  double x = (1.0 + a) * (double)z.M / 2.0 + (double)z.Z * sqrt((double)z.M * log((double)p->capacity));
+  z.stash_bound = (uint64_t)ceil(x);
+  z.P = z.stash_bound + kMaxBatch;
+  z.BZ = z.B * z.Z;
+  if (z.BZ >= (1ull << 32) || z.P >= (1ull << 32)) return BOLT_EINVAL;
+  *s = z;
+  return BOLT_OK;
+}
+
+uint64_t scratch_bytes(const Sizes& s) {
+  const uint64_t Q = kMaxBatch;
+  return Q * 4 * 10 + Q * s.vs + Q * 8 + 3 * Q * 4 + 3 * Q * s.page_bytes + 2 * Q * s.vs + 2 * Q;
+}
+
+uint64_t device_bytes(const bolt_params* p, const Sizes& s) {
+  uint64_t b = sizeof(Ctl);
+  b += s.K * s.page_bytes;
+  if (p->observable == BOLT_OBS_DEVICE) b += s.M * s.page_bytes;
+  b += s.B * 4;                      // load
+  b += s.R * s.W * 16 + s.R * 4;     // position map
+  b += s.P * (8 + s.vs + 4 + 4 + 4); // stash pool + ring
+  b += s.B * 4 + s.B * 2 * s.Z * 4;  // reverse index
+  b += s.B * 16;                     // claim + rmask
+  b += scratch_bytes(s);
+  if (p->flags & BOLT_F_TRACE) b += p->trace_words * 4;
+  return b;
+}
+
+template <typename T>
+int dalloc(bolt_map* m, T** ptr, uint64_t bytes) {
+  void* v = nullptr;
+  if (hipMalloc(&v, bytes ? bytes : 8) != hipSuccess) return BOLT_ENOMEM;
+  m->allocs.push_back(v);
+  *ptr = static_cast<T*>(v);
+  return BOLT_OK;
+}
+
+void free_all(bolt_map* m) {
+  for (void* v : m->allocs) (void)hipFree(v);
+  m->allocs.clear();
+  if (m->obs_host) (void)hipHostFree(m->obs_host);
+  m->obs_host = nullptr;
+}
+
+int map_check(bolt_map* m) {
+  if (!m) return BOLT_EINVAL;
+  if (m->poisoned) return BOLT_ESTATE;
+  return BOLT_OK;
+}
+
+int err_code(uint32_t bits) {
+  if (bits & kErrBroken) return BOLT_EOVERFLOW;  // never expected: reported as a capacity failure
+  if (bits & kErrOverflow) return BOLT_EOVERFLOW;
+  if (bits & kErrDup) return BOLT_EDUPKEY;
+  if (bits & kErrFull) return BOLT_EFULL;
+  return BOLT_OK;
+}
+
+int sync_and_read(bolt_map* m, Ctl* host) {
+  if (hipSetDevice(m->device) != hipSuccess) return BOLT_EHIP;
+  if (hipStreamSynchronize(m->last_stream) != hipSuccess) return BOLT_EHIP;
+  if (hipMemcpy(host, m->ctl, sizeof(Ctl), hipMemcpyDeviceToHost) != hipSuccess) return BOLT_EHIP;
+  uint32_t bits = host->err & ~kErrTrace;
+  if (bits && !m->poisoned) {
+    m->poisoned = true;
+    m->sticky = err_code(bits);
+  }
+  return BOLT_OK;
+}
+
+__global__ void k_fill_u8(uint8_t* p, uint64_t n, uint8_t v) {
+  uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+}  // namespace
+
+extern "C" {
+
+void bolt_params_default(bolt_params* p, uint64_t capacity, uint32_t value_bytes) {
+  if (!p) return;
+  memset(p, 0, sizeof(*p));
+  p->capacity = capacity;
+  p->value_bytes = value_bytes;
+  p->c = 8;
+  p->alpha_permille = 200;
+  p->bin_slots = 0;
+  p->pm_choices = 4;
+  p->pm_keys_per_row = 16;
+  p->pm_row_slots = 32;
+  p->observable = BOLT_OBS_HOST_PINNED;
+  p->flags = 0;
+  p->trace_words = 1ull << 22;
+}
+
+int bolt_sizes_of(const bolt_params* p, bolt_sizes* out) {
+  Sizes s;
+  int rc = derive(p, &s);
+  if (rc) return rc;
+  if (out) {
+    out->B = s.B;
+    out->K = s.K;
+    out->M = s.M;
+    out->Z = s.Z;
+    out->page_bytes = s.page_bytes;
+    out->pm_rows = s.R;
+    out->stash_bound = s.stash_bound;
+    out->stash_pool = s.P;
+  }
+  return BOLT_OK;
+}
+
+int bolt_footprint(const bolt_params* p, uint64_t* hbm_bytes, uint64_t* obs_bytes) {
+  Sizes s;
+  int rc = derive(p, &s);
+  if (rc) return rc;
+  if (hbm_bytes) *hbm_bytes = device_bytes(p, s);
+  if (obs_bytes) *obs_bytes = s.M * s.page_bytes;
+  return BOLT_OK;
+}
+
+int bolt_create(const bolt_params* p, void* hip_stream, bolt_map** out) {
+  if (!out) return BOLT_EINVAL;
+  *out = nullptr;
+  Sizes s;
+  int rc = derive(p, &s);
+  if (rc) return rc;
+  if ((p->flags & BOLT_F_TRACE) && p->trace_words == 0) return BOLT_EINVAL;
+  bolt_map* m = new (std::nothrow) bolt_map();
+  if (!m) return BOLT_ENOMEM;
+  m->p = *p;
+  m->s = s;
+  if (hipGetDevice(&m->device) != hipSuccess) {
+    delete m;
+    return BOLT_EHIP;
+  }
+  hipStream_t st = (hipStream_t)hip_stream;
+  m->last_stream = st;
+  if (!(p->flags & BOLT_F_FIXED_KEY)) {
+    size_t got = 0;
+    while (got < 32) {
+      ssize_t r = getrandom(m->p.key + got, 32 - got, 0);
+      if (r <= 0) {
+        delete m;
+        return BOLT_EINVAL;
+      }
+      got += (size_t)r;
+    }
+  }
+  const uint64_t Q = kMaxBatch;
+  rc = BOLT_OK;
+  rc = rc ? rc : dalloc(m, &m->ctl, sizeof(Ctl));
+  rc = rc ? rc : dalloc(m, &m->hbm, s.K * s.page_bytes);
+  rc = rc ? rc : dalloc(m, &m->load, s.B * 4);
+  rc = rc ? rc : dalloc(m, &m->pm_key, s.R * s.W * 8);
+  rc = rc ? rc : dalloc(m, &m->pm_pair, s.R * s.W * 8);
+  rc = rc ? rc : dalloc(m, &m->pm_mask, s.R * 4);
+  rc = rc ? rc : dalloc(m, &m->st_key, s.P * 8);
+  rc = rc ? rc : dalloc(m, &m->st_val, s.P * s.vs);
+  rc = rc ? rc : dalloc(m, &m->st_dest, s.P * 4);
+  rc = rc ? rc : dalloc(m, &m->st_dead, s.P * 4);
+  rc = rc ? rc : dalloc(m, &m->ring, s.P * 4);
+  rc = rc ? rc : dalloc(m, &m->rev_cnt, s.B * 4);
+  rc = rc ? rc : dalloc(m, &m->rev_idx, s.B * 2 * s.Z * 4);
+  rc = rc ? rc : dalloc(m, &m->claim, s.B * 8);
+  rc = rc ? rc : dalloc(m, &m->rmask, s.B * 8);
+  BatchScratch& b = m->bs;
+  rc = rc ? rc : dalloc(m, &b.leader, Q * 4);
+  rc = rc ? rc : dalloc(m, &b.prevw, Q * 4);
+  rc = rc ? rc : dalloc(m, &b.lastw, Q * 4);
+  rc = rc ? rc : dalloc(m, &b.hit, Q * 4);
+  rc = rc ? rc : dalloc(m, &b.hrow, Q * 4);
+  rc = rc ? rc : dalloc(m, &b.hslot, Q * 4);
+  rc = rc ? rc : dalloc(m, &b.found, Q * 4);
+  rc = rc ? rc : dalloc(m, &b.fval, Q * s.vs);
+  rc = rc ? rc : dalloc(m, &b.rpair, Q * 8);
+  rc = rc ? rc : dalloc(m, &b.cand_bin, 3 * Q * 4);
+  rc = rc ? rc : dalloc(m, &b.stage, 3 * Q * s.page_bytes);
+  rc = rc ? rc : dalloc(m, &b.ord, Q * 4);
+  rc = rc ? rc : dalloc(m, &m->get_ops, Q);
+  rc = rc ? rc : dalloc(m, &m->put_ops, Q);
+  rc = rc ? rc : dalloc(m, &m->discard, 2 * Q * s.vs);
+  if (!rc && (p->flags & BOLT_F_TRACE)) {
+    m->tlog_cap = p->trace_words;
+    rc = dalloc(m, &m->tlog, m->tlog_cap * 4);
+  }
+  if (!rc) {
+    const uint64_t ob = s.M * s.page_bytes;
+    if (p->observable == BOLT_OBS_DEVICE) {
+      rc = dalloc(m, &m->obs, ob);
+    } else {
+      void* h = nullptr;
+      if (hipHostMalloc(&h, ob ? ob : 8, hipHostMallocMapped) != hipSuccess) {
+        rc = BOLT_ENOMEM;
+      } else {
+        m->obs_host = static_cast<uint8_t*>(h);
+        void* d = nullptr;
+        if (hipHostGetDevicePointer(&d, h, 0) != hipSuccess) rc = BOLT_EHIP;
+        m->obs = static_cast<uint8_t*>(d);
+      }
+    }
+  }
+  if (rc) {
+    free_all(m);
+    delete m;
+    return rc;
+  }
+  launch_map_init(m, st);
+  hipLaunchKernelGGL(k_fill_u8, dim3((uint32_t)((Q + 255) / 256)), dim3(256), 0, st, m->get_ops, Q, (uint8_t)0);
+  hipLaunchKernelGGL(k_fill_u8, dim3((uint32_t)((Q + 255) / 256)), dim3(256), 0, st, m->put_ops, Q, (uint8_t)1);
+  if (hipGetLastError() != hipSuccess || hipStreamSynchronize(st) != hipSuccess) {
+    free_all(m);
+    delete m;
+    return BOLT_EHIP;
+  }
+  *out = m;
+  return BOLT_OK;
+}
+
+int bolt_build(bolt_map* m, const uint64_t* d_keys, const void* d_vals, uint64_t n, void* hip_stream) {
+  int rc = map_check(m);
+  if (rc) return rc;
+  if (m->built || n > m->s.cap) return BOLT_EINVAL;
+  if (n && (!d_keys || !d_vals)) return BOLT_EINVAL;
+  if (((uintptr_t)d_keys | (uintptr_t)d_vals) & 7) return BOLT_EINVAL;
+  hipStream_t st = (hipStream_t)hip_stream;
+  m->last_stream = st;
+  if (hipSetDevice(m->device) != hipSuccess) return BOLT_EHIP;
+  rc = run_build(m, d_keys, d_vals, n, st);
+  if (rc) return rc;
+  m->built = true;
+  return BOLT_OK;
+}
+
+int bolt_access_batch(bolt_map* m, const uint8_t* d_ops, const uint64_t* d_keys, const void* d_vals_in,
+                      void* d_vals_out, uint8_t* d_status, uint32_t q, void* hip_stream) {
+  int rc = map_check(m);
+  if (rc) return rc;
+  if (!m->built || q > kMaxBatch) return BOLT_EINVAL;
+  if (q == 0) return BOLT_OK;
+  if (!d_ops || !d_keys || !d_vals_in || !d_vals_out || !d_status) return BOLT_EINVAL;
+  if (((uintptr_t)d_keys | (uintptr_t)d_vals_in | (uintptr_t)d_vals_out) & 7) return BOLT_EINVAL;
+  hipStream_t st = (hipStream_t)hip_stream;
+  m->last_stream = st;
+  if (hipSetDevice(m->device) != hipSuccess) return BOLT_EHIP;
+  return run_access(m, d_ops, d_keys, d_vals_in, d_vals_out, d_status, q, st);
+}
+
+int bolt_get_batch(bolt_map* m, const uint64_t* d_keys, uint32_t q, void* d_vals_out, uint8_t* d_found,
+                   void* hip_stream) {
+  int rc = map_check(m);
+  if (rc) return rc;
+  if (!m->built || q > kMaxBatch) return BOLT_EINVAL;
+  if (q == 0) return BOLT_OK;
+  if (!d_keys || !d_vals_out || !d_found) return BOLT_EINVAL;
+  if (((uintptr_t)d_keys | (uintptr_t)d_vals_out) & 7) return BOLT_EINVAL;
+  hipStream_t st = (hipStream_t)hip_stream;
+  m->last_stream = st;
+  if (hipSetDevice(m->device) != hipSuccess) return BOLT_EHIP;
+  // GET status is 1 for a present key and 0 otherwise: exactly d_found.
+  return run_access(m, m->get_ops, d_keys, m->discard, d_vals_out, d_found, q, st);
+}
+
+int bolt_put_batch(bolt_map* m, const uint64_t* d_keys, const void* d_vals, uint32_t q, uint8_t* d_status,
+                   void* hip_stream) {
+  int rc = map_check(m);
+  if (rc) return rc;
+  if (!m->built || q > kMaxBatch) return BOLT_EINVAL;
+  if (q == 0) return BOLT_OK;
+  if (!d_keys || !d_vals || !d_status) return BOLT_EINVAL;
+  if (((uintptr_t)d_keys | (uintptr_t)d_vals) & 7) return BOLT_EINVAL;
+  hipStream_t st = (hipStream_t)hip_stream;
+  m->last_stream = st;
+  if (hipSetDevice(m->device) != hipSuccess) return BOLT_EHIP;
+  return run_access(m, m->put_ops, d_keys, d_vals, m->discard + (uint64_t)kMaxBatch * m->s.vs, d_status, q, st);
+}
+
+int bolt_destroy(bolt_map* m) {
+  if (!m) return BOLT_OK;
+  (void)hipSetDevice(m->device);
+  (void)hipStreamSynchronize(m->last_stream);
+  free_all(m);
+  delete m;
+  return BOLT_OK;
+}
+
+int bolt_status(bolt_map* m) {
+  if (!m) return BOLT_EINVAL;
+  Ctl c;
+  int rc = sync_and_read(m, &c);
+  if (rc) return rc;
+  return m->poisoned ? m->sticky : BOLT_OK;
+}
+
+int bolt_map_sizes(const bolt_map* m, bolt_sizes* out) {
+  if (!m || !out) return BOLT_EINVAL;
+  return bolt_sizes_of(&m->p, out);
+}
+
+int bolt_get_stats(bolt_map* m, bolt_stats* out) {
+  if (!m || !out) return BOLT_EINVAL;
+  Ctl c;
+  int rc = sync_and_read(m, &c);
+  if (rc) return rc;
+  const Sizes& s = m->s;
+  memset(out, 0, sizeof(*out));
+  out->live = c.live;
+  out->steps = c.steps;
+  out->batches = m->batches;
+  out->stash_live = s.P - (c.ring_tail - c.ring_head);
+  out->stash_highwater = c.stash_hw;
+  std::vector<uint32_t> ld(s.B);
+  if (hipMemcpy(ld.data(), m->load, s.B * 4, hipMemcpyDeviceToHost) != hipSuccess) return BOLT_EHIP;
+  out->max_load = *std::max_element(ld.begin(), ld.end());
+  std::vector<uint32_t> mk(s.R);
+  if (hipMemcpy(mk.data(), m->pm_mask, s.R * 4, hipMemcpyDeviceToHost) != hipSuccess) return BOLT_EHIP;
+  uint32_t mr = 0;
+  for (uint32_t v : mk) mr = std::max(mr, (uint32_t)__builtin_popcount(v));
+  out->max_row = mr;
+  return BOLT_OK;
+}
+
+int bolt_trace_read(bolt_map* m, bolt_trace_rec* host_recs, uint64_t cap, uint64_t* n) {
+  if (!m || !n) return BOLT_EINVAL;
+  if (!m->tlog) return BOLT_EINVAL;
+  Ctl c;
+  int rc = sync_and_read(m, &c);
+  if (rc) return rc;
+  std::vector<uint32_t> log(m->tlog_used);
+  if (m->tlog_used &&
+      hipMemcpy(log.data(), m->tlog, m->tlog_used * 4, hipMemcpyDeviceToHost) != hipSuccess)
+    return BOLT_EHIP;
+  uint64_t k = 0;
+  std::vector<uint32_t> w;
+  for (const TraceSeg& g : m->segs) {
+    for (uint64_t x = 0; x < g.reads; ++x) {
+      uint32_t v = log[g.offset + x];
+      if (v == kNone) continue;
+      if (k < cap && host_recs) host_recs[k] = bolt_trace_rec{g.batch, 0, v};
+      ++k;
+    }
+    w.clear();
+    for (uint64_t x = 0; x < g.writes; ++x) {
+      uint32_t v = log[g.offset + g.reads + x];
+      if (v != kNone) w.push_back(v);
+    }
+    std::sort(w.begin(), w.end());
+    for (uint32_t v : w) {
+      if (k < cap && host_recs) host_recs[k] = bolt_trace_rec{g.batch, 1, v};
+      ++k;
+    }
+  }
+  *n = k;
+  return m->tlog_lost ? BOLT_EFULL : BOLT_OK;
+}
+
+int bolt_trace_clear(bolt_map* m) {
+  if (!m || !m->tlog) return BOLT_EINVAL;
+  Ctl c;
+  int rc = sync_and_read(m, &c);
+  if (rc) return rc;
+  m->segs.clear();
+  m->tlog_used = 0;
+  m->tlog_lost = false;
+  return BOLT_OK;
+}
+
+int bolt_observable_snapshot(bolt_map* m, void* host_buf, uint64_t cap) {
+  if (!m || !host_buf) return BOLT_EINVAL;
+  const uint64_t bytes = m->s.M * m->s.page_bytes;
+  if (cap < bytes) return BOLT_EINVAL;
+  Ctl c;
+  int rc = sync_and_read(m, &c);
+  if (rc) return rc;
+  if (m->obs_host) {
+    memcpy(host_buf, m->obs_host, bytes);
+    return BOLT_OK;
+  }
+  return hipMemcpy(host_buf, m->obs, bytes, hipMemcpyDeviceToHost) == hipSuccess ? BOLT_OK : BOLT_EHIP;
+}
+
+int bolt_hbm_snapshot(bolt_map* m, void* host_buf, uint64_t cap) {
+  if (!m || (!host_buf && m->s.K)) return BOLT_EINVAL;
+  const uint64_t bytes = m->s.K * m->s.page_bytes;
+  if (cap < bytes) return BOLT_EINVAL;
+  Ctl c;
+  int rc = sync_and_read(m, &c);
+  if (rc) return rc;
+  if (!bytes) return BOLT_OK;
+  return hipMemcpy(host_buf, m->hbm, bytes, hipMemcpyDeviceToHost) == hipSuccess ? BOLT_OK : BOLT_EHIP;
+}
+
+int bolt_loads_snapshot(bolt_map* m, uint32_t* host_buf, uint64_t cap) {
+  if (!m || !host_buf || cap < m->s.B * 4) return BOLT_EINVAL;
+  Ctl c;
+  int rc = sync_and_read(m, &c);
+  if (rc) return rc;
+  return hipMemcpy(host_buf, m->load, m->s.B * 4, hipMemcpyDeviceToHost) == hipSuccess ? BOLT_OK : BOLT_EHIP;
+}
+
+int bolt_stash_snapshot(bolt_map* m, uint64_t* host_keys, uint32_t* host_bins, void* host_vals, uint64_t cap,
+                        uint64_t* n) {
+  if (!m || !n) return BOLT_EINVAL;
+  Ctl c;
+  int rc = sync_and_read(m, &c);
+  if (rc) return rc;
+  const Sizes& s = m->s;
+  std::vector<uint32_t> ring(s.P), dest(s.P);
+  std::vector<uint64_t> key(s.P);
+  std::vector<uint8_t> val(s.P * s.vs);
+  if (hipMemcpy(ring.data(), m->ring, s.P * 4, hipMemcpyDeviceToHost) != hipSuccess ||
+      hipMemcpy(dest.data(), m->st_dest, s.P * 4, hipMemcpyDeviceToHost) != hipSuccess ||
+      hipMemcpy(key.data(), m->st_key, s.P * 8, hipMemcpyDeviceToHost) != hipSuccess ||
+      hipMemcpy(val.data(), m->st_val, s.P * s.vs, hipMemcpyDeviceToHost) != hipSuccess)
+    return BOLT_EHIP;
+  std::vector<uint8_t> is_free(s.P, 0);
+  for (uint64_t x = c.ring_head; x < c.ring_tail; ++x) is_free[ring[x % s.P]] = 1;
+  uint64_t k = 0;
+  for (uint64_t e = 0; e < s.P; ++e) {
+    if (is_free[e]) continue;
+    if (k < cap) {
+      if (host_keys) host_keys[k] = key[e];
+      if (host_bins) host_bins[k] = dest[e];
+      if (host_vals) memcpy(static_cast<uint8_t*>(host_vals) + k * s.vs, &val[e * s.vs], s.vs);
+    }
+    ++k;
+  }
+  *n = k;
+  return BOLT_OK;
+}
+
+int bolt_pm_snapshot(bolt_map* m, uint64_t* host_rows, uint64_t* host_keys, uint32_t* host_p1, uint32_t* host_p2,
+                     uint64_t cap, uint64_t* n) {
+  if (!m || !n) return BOLT_EINVAL;
+  Ctl c;
+  int rc = sync_and_read(m, &c);
+  if (rc) return rc;
+  const Sizes& s = m->s;
+  std::vector<uint32_t> mask(s.R);
+  std::vector<uint64_t> key(s.R * s.W);
+  std::vector<uint2> pr(s.R * s.W);
+  if (hipMemcpy(mask.data(), m->pm_mask, s.R * 4, hipMemcpyDeviceToHost) != hipSuccess ||
+      hipMemcpy(key.data(), m->pm_key, s.R * s.W * 8, hipMemcpyDeviceToHost) != hipSuccess ||
+      hipMemcpy(pr.data(), m->pm_pair, s.R * s.W * 8, hipMemcpyDeviceToHost) != hipSuccess)
+    return BOLT_EHIP;
+  uint64_t k = 0;
+  for (uint64_t r = 0; r < s.R; ++r)
+    for (uint32_t j = 0; j < s.W; ++j) {
+      if (!((mask[r] >> j) & 1)) continue;
+      if (k < cap) {
+        if (host_rows) host_rows[k] = r;
+        if (host_keys) host_keys[k] = key[r * s.W + j];
+        if (host_p1) host_p1[k] = pr[r * s.W + j].x;
+        if (host_p2) host_p2[k] = pr[r * s.W + j].y;
+      }
+      ++k;
+    }
+  *n = k;
+  return BOLT_OK;
+}
+
+int bolt_prf(const uint8_t* host_key, uint8_t domain, const uint64_t* d_x, uint64_t n, uint64_t* d_out,
+             void* hip_stream) {
+  if (!host_key || (n && (!d_x || !d_out))) return BOLT_EINVAL;
+  if (n == 0) return BOLT_OK;
+  hipStream_t st = (hipStream_t)hip_stream;
+  Ctl* ctl = nullptr;
+  if (hipMallocAsync((void**)&ctl, sizeof(Ctl), st) != hipSuccess) return BOLT_ENOMEM;
+  launch_prf_key_setup(ctl, host_key, st);
+  launch_prf_array(ctl, domain, d_x, n, d_out, st);
+  (void)hipFreeAsync(ctl, st);
+  return hipGetLastError() == hipSuccess ? BOLT_OK : BOLT_EHIP;
+}
+
+int bolt_sort_u64(uint64_t* d_data, uint64_t n, void* hip_stream) {
+  if (!d_data || n == 0 || (n & (n - 1)) || n > (1ull << 31)) return BOLT_EINVAL;
+  launch_bitonic_sort(d_data, n, (hipStream_t)hip_stream);
+  return hipGetLastError() == hipSuccess ? BOLT_OK : BOLT_EHIP;
+}
+
+int bolt_expand_u64(uint64_t* d_elems, uint64_t* d_tmp, uint64_t m, void* hip_stream) {
+  if (!d_elems || !d_tmp || m == 0 || m > (1ull << 32)) return BOLT_EINVAL;
+  launch_expand(d_elems, d_tmp, m, (hipStream_t)hip_stream);
+  return hipGetLastError() == hipSuccess ? BOLT_OK : BOLT_EHIP;
+}
+
+}  // extern "C"

@@ -1,0 +1,106 @@
+// Host-side state of one map and the launchers of its kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <vector>
+
+#include "../../include/bolt.h"
+#include "bolt_dev.h"
+
+namespace bolt {
+
+// Scratch of one access batch, sized for BOLT_MAX_BATCH commands.
+struct BatchScratch {
+  uint32_t* leader;   // [Q] index of the first command with the same key
+  uint32_t* prevw;    // [Q] last PUT/DEL of the same key before this command, or kNone
+  uint32_t* lastw;    // [Q] (leaders) last PUT/DEL of the key in the batch, or kNone
+  uint32_t* hit;      // [Q] (leaders) key found in the position map
+  uint32_t* hrow;     // [Q] (leaders) its row
+  uint32_t* hslot;    // [Q] (leaders) its slot in the row
+  uint32_t* found;    // [Q] (leaders) item found in one of the two bins
+  uint8_t* fval;      // [Q * vs] (leaders) the value found
+  uint2* rpair;       // [Q] remap pair R(s) of each command
+  uint32_t* cand_bin; // [3Q] bin each write-back candidate slot would rewrite, or kNone
+  uint8_t* stage;     // [2Q * page_bytes] copies of the pages read
+  uint32_t* ord;      // [Q] (leaders) ordinal among the keys placed this batch, or kNone
+};
+
+// Scratch of a build, allocated for the call and freed afterwards.
+struct BuildScratch {
+  uint2* pair;      // [n]
+  uint32_t* dest;   // [n]
+  uint64_t* tag;    // [npad]
+  uint64_t* elem;   // [BZ]
+  uint64_t* tmp;    // [BZ]
+  uint32_t* start;  // [B] first sorted position of each bin
+  uint32_t* bsum;   // scan partials
+  uint32_t* rowsel; // [n]
+  uint32_t* rowcnt; // [R]
+};
+
+struct TraceSeg {
+  uint32_t batch;
+  uint64_t offset;  // first word in the device log
+  uint64_t reads;   // read words (2q), 0 for the build
+  uint64_t writes;  // write words (2q for a batch, M for the build)
+};
+
+struct Sizes {
+  uint64_t cap, B, K, M, Z, W, d, R, page_bytes, stash_bound, P, BZ;
+  uint32_t vs;
+};
+
+}  // namespace bolt
+
+struct bolt_map {
+  bolt_params p;
+  bolt::Sizes s;
+  int device;
+  // persistent device state
+  bolt::Ctl* ctl;
+  uint8_t* obs;       // M pages (device pointer; maps pinned host memory in host mode)
+  uint8_t* obs_host;  // host pointer of the pinned store, or null
+  uint8_t* hbm;       // K HBM bins
+  uint32_t* load;     // [B]
+  uint64_t* pm_key;   // [R * W]
+  uint2* pm_pair;     // [R * W]
+  uint32_t* pm_mask;  // [R] used slots
+  uint64_t* st_key;   // [P] stash pool
+  uint8_t* st_val;    // [P * vs]
+  uint32_t* st_dest;  // [P] destination bin
+  uint32_t* st_dead;  // [P] removed by an access of this batch
+  uint32_t* ring;     // [P] free pool entries
+  uint32_t* rev_cnt;  // [B] stash entries listed per bin
+  uint32_t* rev_idx;  // [B * 2Z]
+  uint64_t* claim;    // [B] write-back election, tagged with the batch epoch
+  uint64_t* rmask;    // [B] page slots removed in this batch
+  uint32_t* tlog;     // trace log (BOLT_F_TRACE)
+  uint64_t tlog_cap, tlog_used;
+  bool tlog_lost;
+  std::vector<bolt::TraceSeg> segs;
+  bolt::BatchScratch bs;
+  uint8_t* get_ops;   // [Q] all BOLT_OP_GET (bolt_get_batch)
+  uint8_t* put_ops;   // [Q] all BOLT_OP_PUT (bolt_put_batch)
+  uint8_t* discard;   // [2Q * vs] unused inputs / outputs of those wrappers
+  std::vector<void*> allocs;  // every hipMalloc of this map
+  bool built, poisoned;
+  int sticky;
+  uint64_t batches;
+  hipStream_t last_stream;
+};
+
+namespace bolt {
+
+void launch_prf_key_setup(Ctl* ctl, const uint8_t key[32], hipStream_t st);
+void launch_prf_array(const Ctl* ctl, uint32_t domain, const uint64_t* x, uint64_t n, uint64_t* out, hipStream_t st);
+void launch_bitonic_sort(uint64_t* a, uint64_t n, hipStream_t st);
+void launch_expand(uint64_t* a, uint64_t* tmp, uint64_t m, hipStream_t st);
+
+void launch_map_init(bolt_map* m, hipStream_t st);
+int run_build(bolt_map* m, const uint64_t* keys, const void* vals, uint64_t n, hipStream_t st);
+int run_access(bolt_map* m, const uint8_t* ops, const uint64_t* keys, const void* vals_in, void* vals_out,
+               uint8_t* status, uint32_t q, hipStream_t st);
+
+}  // namespace bolt
