@@ -70,6 +70,7 @@ enum { BOLT_OBS_HOST_PINNED = 0, BOLT_OBS_DEVICE = 1 };
 /* bolt_params.flags */
 #define BOLT_F_TRACE 1u     /* record every observable access (tests; costs a little time) */
 #define BOLT_F_FIXED_KEY 2u /* use params.key as the PRF key instead of fresh OS randomness */
+#define BOLT_F_TIMING 4u    /* time every kernel class with HIP events on its stream (benchmarks) */
 
 #define BOLT_MAX_BATCH 8192u /* most commands in one access call */
 
@@ -130,14 +131,15 @@ int bolt_build(bolt_map* m, const uint64_t* d_keys, const void* d_vals, uint64_t
 
 /* Runs q <= BOLT_MAX_BATCH commands in one batch (Alg. 1 per command, Sec. 5.1
  * steps 2-6).  d_ops[q] holds BOLT_OP_* codes, d_keys[q] the keys,
- * d_vals_in[q][vs] the PUT payloads (read for PUT only; may be NULL if no
- * command is a PUT).  Outputs: d_vals_out[q][vs] the value of each GET of a
- * present key and zeros otherwise (fixed-length responses), d_status[q] a
- * BOLT_ST_* byte.  The answers equal running the commands one at a time in
- * index order.  Every command reads two whole bins; each page read is
- * written back once at the end of the batch.  An op code out of range makes
- * the device reject the whole batch (sticky BOLT_EINVAL is not used: ops are
- * checked on the device and the batch leaves the map unchanged, status 0xFF). */
+ * d_vals_in[q][vs] the PUT payloads (read for PUT commands only, but always
+ * required).  Outputs: d_vals_out[q][vs] gets the value of each GET of a
+ * present key and zeros otherwise (fixed-length responses); d_status[q] gets
+ * a BOLT_ST_* byte.  The answers equal running the commands one at a time in
+ * index order.  Every command reads two whole bins; each page read is written
+ * back once at the end of the batch.  Op codes are checked on the device: a
+ * batch holding a code above BOLT_OP_DEL is rejected whole, leaves the map
+ * unchanged and reports status 0xFF for every command.  d_keys, d_vals_in and
+ * d_vals_out must be 8-byte aligned. */
 int bolt_access_batch(bolt_map* m, const uint8_t* d_ops, const uint64_t* d_keys, const void* d_vals_in,
                       void* d_vals_out, uint8_t* d_status, uint32_t q, void* hip_stream);
 
@@ -211,6 +213,19 @@ int bolt_stash_snapshot(bolt_map* m, uint64_t* host_keys, uint32_t* host_bins, v
  * the entry count. */
 int bolt_pm_snapshot(bolt_map* m, uint64_t* host_rows, uint64_t* host_keys, uint32_t* host_p1,
                      uint32_t* host_p2, uint64_t cap, uint64_t* n);
+
+/* Per-kernel-class device time of a map created with BOLT_F_TIMING: HIP
+ * events recorded on the launch stream around every launch, summed since
+ * create or the last reset.  Fills up to cap entries of host_out (name,
+ * launches, total milliseconds); *n receives the number of classes.
+ * Synchronises the map's stream.  BOLT_EINVAL without BOLT_F_TIMING. */
+typedef struct {
+  char name[32];
+  uint64_t launches;
+  double total_ms;
+} bolt_kernel_time;
+int bolt_kernel_times(bolt_map* m, bolt_kernel_time* host_out, uint32_t cap, uint32_t* n);
+int bolt_kernel_times_reset(bolt_map* m);
 
 /* ---------------------------------------------------------------------
  * Device primitives of the path, exported so each can be checked alone.

@@ -20,7 +20,7 @@ BOLT_OK, BOLT_EINVAL, BOLT_ENOMEM, BOLT_EDUPKEY, BOLT_EOVERFLOW, BOLT_EFULL, BOL
 BOLT_OP_GET, BOLT_OP_PUT, BOLT_OP_DEL = 0, 1, 2
 BOLT_ST_ABSENT, BOLT_ST_FOUND, BOLT_ST_UPDATED, BOLT_ST_INSERTED, BOLT_ST_DELETED = 0, 1, 1, 2, 3
 BOLT_OBS_HOST_PINNED, BOLT_OBS_DEVICE = 0, 1
-BOLT_F_TRACE, BOLT_F_FIXED_KEY = 1, 2
+BOLT_F_TRACE, BOLT_F_FIXED_KEY, BOLT_F_TIMING = 1, 2, 4
 BOLT_MAX_BATCH = 8192
 
 _NAMES = {0: "BOLT_OK", -1: "BOLT_EINVAL", -2: "BOLT_ENOMEM", -3: "BOLT_EDUPKEY", -4: "BOLT_EOVERFLOW",
@@ -61,6 +61,10 @@ class bolt_trace_rec(C.Structure):
     _fields_ = [("batch", C.c_uint32), ("kind", C.c_uint32), ("page", C.c_uint64)]
 
 
+class bolt_kernel_time(C.Structure):
+    _fields_ = [("name", C.c_char * 32), ("launches", C.c_uint64), ("total_ms", C.c_double)]
+
+
 TRACE_DTYPE = np.dtype([("batch", "<u4"), ("kind", "<u4"), ("page", "<u8")])
 
 # (name, restype, argtypes) of every entry point in include/bolt.h
@@ -85,6 +89,8 @@ _SIGS = [
     ("bolt_loads_snapshot", _I, [_P, _P, _U64]),
     ("bolt_stash_snapshot", _I, [_P, _P, _P, _P, _U64, C.POINTER(_U64)]),
     ("bolt_pm_snapshot", _I, [_P, _P, _P, _P, _P, _U64, C.POINTER(_U64)]),
+    ("bolt_kernel_times", _I, [_P, _P, _U32, C.POINTER(_U32)]),
+    ("bolt_kernel_times_reset", _I, [_P]),
     ("bolt_prf", _I, [_P, _U8, _P, _U64, _P, _P]),
     ("bolt_sort_u64", _I, [_P, _U64, _P]),
     ("bolt_expand_u64", _I, [_P, _P, _U64, _P]),
@@ -217,6 +223,16 @@ class Map:
         if n.value:
             check(bolt_trace_read(self.h, out.ctypes.data_as(C.c_void_p), n.value, C.byref(n)), "bolt_trace_read")
         return out
+
+    def kernel_times(self) -> dict:
+        """{class: (launches, total_ms)} since create or the last reset (BOLT_F_TIMING)."""
+        arr = (bolt_kernel_time * 32)()
+        n = C.c_uint32()
+        check(bolt_kernel_times(self.h, arr, 32, C.byref(n)), "bolt_kernel_times")
+        return {arr[i].name.decode(): (int(arr[i].launches), float(arr[i].total_ms)) for i in range(n.value)}
+
+    def kernel_times_reset(self):
+        check(bolt_kernel_times_reset(self.h), "bolt_kernel_times_reset")
 
     def trace_clear(self):
         check(bolt_trace_clear(self.h), "bolt_trace_clear")

@@ -249,6 +249,14 @@ int bolt_create(const bolt_params* p, void* hip_stream, bolt_map** out) {
     delete m;
     return rc;
   }
+  if (p->flags & BOLT_F_TIMING) {
+    m->timer = new (std::nothrow) KernelTimer();
+    if (!m->timer) {
+      free_all(m);
+      delete m;
+      return BOLT_ENOMEM;
+    }
+  }
   launch_map_init(m, st);
   hipLaunchKernelGGL(k_fill_u8, dim3((uint32_t)((Q + 255) / 256)), dim3(256), 0, st, m->get_ops, Q, (uint8_t)0);
   hipLaunchKernelGGL(k_fill_u8, dim3((uint32_t)((Q + 255) / 256)), dim3(256), 0, st, m->put_ops, Q, (uint8_t)1);
@@ -323,6 +331,7 @@ int bolt_destroy(bolt_map* m) {
   if (!m) return BOLT_OK;
   (void)hipSetDevice(m->device);
   (void)hipStreamSynchronize(m->last_stream);
+  delete m->timer;
   free_all(m);
   delete m;
   return BOLT_OK;
@@ -500,6 +509,28 @@ int bolt_pm_snapshot(bolt_map* m, uint64_t* host_rows, uint64_t* host_keys, uint
       ++k;
     }
   *n = k;
+  return BOLT_OK;
+}
+
+int bolt_kernel_times(bolt_map* m, bolt_kernel_time* host_out, uint32_t cap, uint32_t* n) {
+  if (!m || !n || !m->timer) return BOLT_EINVAL;
+  if (hipSetDevice(m->device) != hipSuccess || hipStreamSynchronize(m->last_stream) != hipSuccess) return BOLT_EHIP;
+  if (m->timer->collect()) return BOLT_EHIP;
+  for (uint32_t i = 0; i < (uint32_t)kkCount && i < cap && host_out; ++i) {
+    memset(&host_out[i], 0, sizeof(host_out[i]));
+    strncpy(host_out[i].name, kKernelNames[i], sizeof(host_out[i].name) - 1);
+    host_out[i].launches = m->timer->launches[i];
+    host_out[i].total_ms = m->timer->total_ms[i];
+  }
+  *n = kkCount;
+  return BOLT_OK;
+}
+
+int bolt_kernel_times_reset(bolt_map* m) {
+  if (!m || !m->timer) return BOLT_EINVAL;
+  if (hipSetDevice(m->device) != hipSuccess || hipStreamSynchronize(m->last_stream) != hipSuccess) return BOLT_EHIP;
+  if (m->timer->collect()) return BOLT_EHIP;
+  m->timer->reset();
   return BOLT_OK;
 }
 

@@ -47,6 +47,46 @@ struct TraceSeg {
   uint64_t writes;  // write words (2q for a batch, M for the build)
 };
 
+// Kernel classes timed with HIP events when a map has BOLT_F_TIMING.
+enum KernelId {
+  kkSortTile, kkSortGlobal, kkSortMerge, kkPairs, kkP2C, kkScan, kkExpand, kkWriteout, kkPmBuild, kkDupcheck,
+  kkBuildMisc, kkAccDedup, kkAccFetch, kkAccResolve, kkAccRemap, kkAccWriteback, kkAccMisc, kkCount
+};
+extern const char* const kKernelNames[kkCount];
+
+// Records a pair of events around each timed launch on its stream; the
+// elapsed times are summed when read.  Events are recycled.
+struct KernelTimer {
+  struct Rec {
+    int id;
+    hipEvent_t a, b;
+  };
+  std::vector<hipEvent_t> pool;
+  std::vector<Rec> recs;
+  double total_ms[kkCount] = {};
+  uint64_t launches[kkCount] = {};
+  int cur = -1;
+  hipEvent_t cur_a = nullptr;
+  hipEvent_t take();
+  void begin(int id, hipStream_t st);
+  void end(hipStream_t st);
+  int collect();  // after the stream is synchronised
+  void reset();
+  ~KernelTimer();
+};
+
+// Brackets launches with timer events when a timer is given.
+struct TimedScope {
+  KernelTimer* t;
+  hipStream_t st;
+  TimedScope(KernelTimer* t_, int id, hipStream_t s) : t(t_), st(s) {
+    if (t) t->begin(id, st);
+  }
+  ~TimedScope() {
+    if (t) t->end(st);
+  }
+};
+
 struct Sizes {
   uint64_t cap, B, K, M, Z, W, d, R, page_bytes, stash_bound, P, BZ;
   uint32_t vs;
@@ -89,14 +129,15 @@ struct bolt_map {
   int sticky;
   uint64_t batches;
   hipStream_t last_stream;
+  bolt::KernelTimer* timer;  // BOLT_F_TIMING, else null
 };
 
 namespace bolt {
 
 void launch_prf_key_setup(Ctl* ctl, const uint8_t key[32], hipStream_t st);
 void launch_prf_array(const Ctl* ctl, uint32_t domain, const uint64_t* x, uint64_t n, uint64_t* out, hipStream_t st);
-void launch_bitonic_sort(uint64_t* a, uint64_t n, hipStream_t st);
-void launch_expand(uint64_t* a, uint64_t* tmp, uint64_t m, hipStream_t st);
+void launch_bitonic_sort(uint64_t* a, uint64_t n, hipStream_t st, KernelTimer* tm = nullptr);
+void launch_expand(uint64_t* a, uint64_t* tmp, uint64_t m, hipStream_t st, KernelTimer* tm = nullptr);
 
 void launch_map_init(bolt_map* m, hipStream_t st);
 int run_build(bolt_map* m, const uint64_t* keys, const void* vals, uint64_t n, hipStream_t st);

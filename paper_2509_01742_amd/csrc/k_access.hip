@@ -714,7 +714,10 @@ int run_access(bolt_map* m, const uint8_t* ops, const uint64_t* keys, const void
       m->tlog_lost = true;
     }
   }
-  hipLaunchKernelGGL(k_acc_dedup, dim3(1), dim3(kDedupNT), 0, st, ops, keys, q, m->ctl, bs.leader, bs.prevw, bs.lastw);
+  {
+    TimedScope ts(m->timer, kkAccDedup, st);
+    hipLaunchKernelGGL(k_acc_dedup, dim3(1), dim3(kDedupNT), 0, st, ops, keys, q, m->ctl, bs.leader, bs.prevw, bs.lastw);
+  }
 
   FetchArgs fa;
   fa.ctl = m->ctl;
@@ -754,12 +757,18 @@ int run_access(bolt_map* m, const uint8_t* ops, const uint64_t* keys, const void
   fa.rpair = bs.rpair;
   fa.tlog_r = tlog_r;
   fa.ctlw = m->ctl;
-  hipLaunchKernelGGL(k_acc_fetch, dim3((q + 3) / 4), dim3(256), 0, st, fa);
+  {
+    TimedScope ts(m->timer, kkAccFetch, st);
+    hipLaunchKernelGGL(k_acc_fetch, dim3((q + 3) / 4), dim3(256), 0, st, fa);
+  }
 
-  hipLaunchKernelGGL(k_acc_resolve, dim3((q + 255) / 256), dim3(256), 0, st, m->ctl, ops,
-                     reinterpret_cast<const uint64_t*>(vals_in), bs.leader, bs.prevw, bs.found,
-                     reinterpret_cast<const uint64_t*>(bs.fval), q, s.vs / 8, reinterpret_cast<uint64_t*>(vals_out),
-                     status);
+  {
+    TimedScope ts(m->timer, kkAccResolve, st);
+    hipLaunchKernelGGL(k_acc_resolve, dim3((q + 255) / 256), dim3(256), 0, st, m->ctl, ops,
+                       reinterpret_cast<const uint64_t*>(vals_in), bs.leader, bs.prevw, bs.found,
+                       reinterpret_cast<const uint64_t*>(bs.fval), q, s.vs / 8, reinterpret_cast<uint64_t*>(vals_out),
+                       status);
+  }
 
   RemapArgs ra;
   ra.ctl = m->ctl;
@@ -798,7 +807,10 @@ int run_access(bolt_map* m, const uint8_t* ops, const uint64_t* keys, const void
   ra.pm_key = m->pm_key;
   ra.pm_pair = m->pm_pair;
   ra.pm_mask = m->pm_mask;
-  hipLaunchKernelGGL(k_acc_remap, dim3(1), dim3(kRemapNT), 0, st, ra);
+  {
+    TimedScope ts(m->timer, kkAccRemap, st);
+    hipLaunchKernelGGL(k_acc_remap, dim3(1), dim3(kRemapNT), 0, st, ra);
+  }
 
   WbArgs wa;
   wa.ctl = m->ctl;
@@ -822,9 +834,15 @@ int run_access(bolt_map* m, const uint8_t* ops, const uint64_t* keys, const void
   wa.st_dead = m->st_dead;
   wa.ring = m->ring;
   wa.tlog_w = tlog_w;
-  hipLaunchKernelGGL(k_acc_writeback, dim3((3 * q + 3) / 4), dim3(256), 0, st, wa);
+  {
+    TimedScope ts(m->timer, kkAccWriteback, st);
+    hipLaunchKernelGGL(k_acc_writeback, dim3((3 * q + 3) / 4), dim3(256), 0, st, wa);
+  }
 
-  hipLaunchKernelGGL(k_acc_finish, dim3(1), dim3(64), 0, st, m->ctl, q, s.P, s.stash_bound);
+  {
+    TimedScope ts(m->timer, kkAccMisc, st);
+    hipLaunchKernelGGL(k_acc_finish, dim3(1), dim3(64), 0, st, m->ctl, q, s.P, s.stash_bound);
+  }
   m->batches++;
   return hipGetLastError() == hipSuccess ? BOLT_OK : BOLT_EHIP;
 }

@@ -360,6 +360,12 @@ __global__ void k_build_finish(Ctl* ctl, uint64_t n) {
 
 static uint32_t blocks_for(uint64_t n, uint32_t nt) { return (uint32_t)((n + nt - 1) / nt); }
 
+static void free_build_scratch(BuildScratch& b, hipStream_t st) {
+  void* ptrs[] = {b.pair, b.dest, b.tag, b.elem, b.tmp, b.start, b.bsum, b.rowsel, b.rowcnt};
+  for (void* p : ptrs)
+    if (p) (void)hipFreeAsync(p, st);
+}
+
 int run_build(bolt_map* m, const uint64_t* keys, const void* vals, uint64_t n, hipStream_t st) {
   const Sizes& s = m->s;
   uint64_t npad = 1;
@@ -378,31 +384,50 @@ int run_build(bolt_map* m, const uint64_t* keys, const void* vals, uint64_t n, h
   e = e ? e : hipMallocAsync((void**)&b.rowsel, nn * sizeof(uint32_t), st);
   e = e ? e : hipMallocAsync((void**)&b.rowcnt, s.R * sizeof(uint32_t), st);
   if (e != hipSuccess) {
-    (void)hipFreeAsync(b.pair, st); (void)hipFreeAsync(b.dest, st); (void)hipFreeAsync(b.tag, st); (void)hipFreeAsync(b.elem, st);
-    (void)hipFreeAsync(b.tmp, st); (void)hipFreeAsync(b.start, st); (void)hipFreeAsync(b.bsum, st); (void)hipFreeAsync(b.rowsel, st);
-    (void)hipFreeAsync(b.rowcnt, st);
+    free_build_scratch(b, st);
     return BOLT_ENOMEM;
   }
   const uint32_t NT = 256;
   // a1
-  if (n) hipLaunchKernelGGL(k_build_pairs, dim3(blocks_for(n, NT)), dim3(NT), 0, st, m->ctl, keys, n, s.B, b.pair);
+  if (n) {
+    TimedScope ts(m->timer, kkPairs, st);
+    hipLaunchKernelGGL(k_build_pairs, dim3(blocks_for(n, NT)), dim3(NT), 0, st, m->ctl, keys, n, s.B, b.pair);
+  }
   // a2
   const uint64_t rs = (s.B + 15) / 16;
   for (uint64_t r0 = 0; r0 < n; r0 += rs) {
     uint64_t r1 = r0 + rs < n ? r0 + rs : n;
-    hipLaunchKernelGGL(k_p2c_decide, dim3(blocks_for(r1 - r0, NT)), dim3(NT), 0, st, b.pair, m->load, r0, r1, b.dest);
-    hipLaunchKernelGGL(k_p2c_add, dim3(blocks_for(r1 - r0, NT)), dim3(NT), 0, st, b.dest, r0, r1, m->load);
+    {
+      TimedScope ts(m->timer, kkP2C, st);
+      hipLaunchKernelGGL(k_p2c_decide, dim3(blocks_for(r1 - r0, NT)), dim3(NT), 0, st, b.pair, m->load, r0, r1, b.dest);
+    }
+    {
+      TimedScope ts(m->timer, kkP2C, st);
+      hipLaunchKernelGGL(k_p2c_add, dim3(blocks_for(r1 - r0, NT)), dim3(NT), 0, st, b.dest, r0, r1, m->load);
+    }
   }
-  hipLaunchKernelGGL(k_check_loads, dim3(blocks_for(s.B, NT)), dim3(NT), 0, st, m->load, s.B, (uint32_t)s.Z, m->ctl);
+  {
+    TimedScope ts(m->timer, kkBuildMisc, st);
+    hipLaunchKernelGGL(k_check_loads, dim3(blocks_for(s.B, NT)), dim3(NT), 0, st, m->load, s.B, (uint32_t)s.Z, m->ctl);
+  }
   // a3
-  hipLaunchKernelGGL(k_make_tags, dim3(blocks_for(npad, NT)), dim3(NT), 0, st, b.dest, n, npad, b.tag);
-  launch_bitonic_sort(b.tag, npad, st);
+  {
+    TimedScope ts(m->timer, kkBuildMisc, st);
+    hipLaunchKernelGGL(k_make_tags, dim3(blocks_for(npad, NT)), dim3(NT), 0, st, b.dest, n, npad, b.tag);
+  }
+  launch_bitonic_sort(b.tag, npad, st, m->timer);
   // a4
-  launch_excl_scan(m->load, s.B, b.bsum, b.start, st);
-  hipLaunchKernelGGL(k_make_elems, dim3(blocks_for(s.BZ, NT)), dim3(NT), 0, st, b.tag, n, b.start, s.B, (uint32_t)s.Z,
-                     s.BZ, b.elem, m->ctl);
+  {
+    TimedScope ts(m->timer, kkScan, st);
+    launch_excl_scan(m->load, s.B, b.bsum, b.start, st);
+  }
+  {
+    TimedScope ts(m->timer, kkScan, st);
+    hipLaunchKernelGGL(k_make_elems, dim3(blocks_for(s.BZ, NT)), dim3(NT), 0, st, b.tag, n, b.start, s.B, (uint32_t)s.Z,
+                       s.BZ, b.elem, m->ctl);
+  }
   // a5
-  launch_expand(b.elem, b.tmp, s.BZ, st);
+  launch_expand(b.elem, b.tmp, s.BZ, st, m->timer);
   // a6
   uint32_t* tl = nullptr;
   if (m->tlog) {
@@ -415,27 +440,42 @@ int run_build(bolt_map* m, const uint64_t* keys, const void* vals, uint64_t n, h
       m->tlog_lost = true;
     }
   }
-  hipLaunchKernelGGL(k_writeout, dim3(blocks_for(s.B, 4)), dim3(256), 0, st, b.elem, keys,
-                     reinterpret_cast<const uint64_t*>(vals), s.B, s.K, (uint32_t)s.Z, s.vs / 8, s.page_bytes / 8,
-                     reinterpret_cast<uint64_t*>(m->hbm), reinterpret_cast<uint64_t*>(m->obs), tl);
+  {
+    TimedScope ts(m->timer, kkWriteout, st);
+    hipLaunchKernelGGL(k_writeout, dim3(blocks_for(s.B, 4)), dim3(256), 0, st, b.elem, keys,
+                       reinterpret_cast<const uint64_t*>(vals), s.B, s.K, (uint32_t)s.Z, s.vs / 8, s.page_bytes / 8,
+                       reinterpret_cast<uint64_t*>(m->hbm), reinterpret_cast<uint64_t*>(m->obs), tl);
+  }
   // a7
   (void)hipMemsetAsync(b.rowcnt, 0, s.R * sizeof(uint32_t), st);
   const uint64_t rsm = (s.R + 15) / 16;
   for (uint64_t r0 = 0; r0 < n; r0 += rsm) {
     uint64_t r1 = r0 + rsm < n ? r0 + rsm : n;
-    hipLaunchKernelGGL(k_pm_decide, dim3(blocks_for(r1 - r0, NT)), dim3(NT), 0, st, m->ctl, keys, r0, r1, s.R,
-                       (uint32_t)s.d, b.rowcnt, b.rowsel);
-    hipLaunchKernelGGL(k_pm_add, dim3(blocks_for(r1 - r0, NT)), dim3(NT), 0, st, keys, b.pair, b.rowsel, r0, r1,
-                       (uint32_t)s.W, b.rowcnt, m->pm_key, m->pm_pair, m->ctl);
+    {
+      TimedScope ts(m->timer, kkPmBuild, st);
+      hipLaunchKernelGGL(k_pm_decide, dim3(blocks_for(r1 - r0, NT)), dim3(NT), 0, st, m->ctl, keys, r0, r1, s.R,
+                         (uint32_t)s.d, b.rowcnt, b.rowsel);
+    }
+    {
+      TimedScope ts(m->timer, kkPmBuild, st);
+      hipLaunchKernelGGL(k_pm_add, dim3(blocks_for(r1 - r0, NT)), dim3(NT), 0, st, keys, b.pair, b.rowsel, r0, r1,
+                         (uint32_t)s.W, b.rowcnt, m->pm_key, m->pm_pair, m->ctl);
+    }
   }
-  hipLaunchKernelGGL(k_pm_masks, dim3(blocks_for(s.R, NT)), dim3(NT), 0, st, b.rowcnt, s.R, (uint32_t)s.W, m->pm_mask);
-  if (n)
+  {
+    TimedScope ts(m->timer, kkPmBuild, st);
+    hipLaunchKernelGGL(k_pm_masks, dim3(blocks_for(s.R, NT)), dim3(NT), 0, st, b.rowcnt, s.R, (uint32_t)s.W, m->pm_mask);
+  }
+  if (n) {
+    TimedScope ts(m->timer, kkDupcheck, st);
     hipLaunchKernelGGL(k_pm_dupcheck, dim3(blocks_for(n, NT)), dim3(NT), 0, st, m->ctl, keys, n, s.R, (uint32_t)s.d,
                        (uint32_t)s.W, m->pm_mask, m->pm_key, m->ctl);
-  hipLaunchKernelGGL(k_build_finish, dim3(1), dim3(64), 0, st, m->ctl, n);
-  (void)hipFreeAsync(b.pair, st); (void)hipFreeAsync(b.dest, st); (void)hipFreeAsync(b.tag, st); (void)hipFreeAsync(b.elem, st);
-  (void)hipFreeAsync(b.tmp, st); (void)hipFreeAsync(b.start, st); (void)hipFreeAsync(b.bsum, st); (void)hipFreeAsync(b.rowsel, st);
-  (void)hipFreeAsync(b.rowcnt, st);
+  }
+  {
+    TimedScope ts(m->timer, kkBuildMisc, st);
+    hipLaunchKernelGGL(k_build_finish, dim3(1), dim3(64), 0, st, m->ctl, n);
+  }
+  free_build_scratch(b, st);
   return hipGetLastError() == hipSuccess ? BOLT_OK : BOLT_EHIP;
 }
 

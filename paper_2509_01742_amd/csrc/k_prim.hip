@@ -6,6 +6,63 @@
 
 namespace bolt {
 
+const char* const kKernelNames[kkCount] = {
+    "sort_tile", "sort_global", "sort_merge", "build_pairs", "p2c_rounds", "loads_scan", "expand", "page_writeout",
+    "pm_build", "dup_check", "build_misc", "acc_dedup", "acc_fetch", "acc_resolve", "acc_remap", "acc_writeback",
+    "acc_misc"};
+
+hipEvent_t KernelTimer::take() {
+  if (!pool.empty()) {
+    hipEvent_t e = pool.back();
+    pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  (void)hipEventCreate(&e);
+  return e;
+}
+
+void KernelTimer::begin(int id, hipStream_t st) {
+  cur = id;
+  cur_a = take();
+  (void)hipEventRecord(cur_a, st);
+}
+
+void KernelTimer::end(hipStream_t st) {
+  hipEvent_t b = take();
+  (void)hipEventRecord(b, st);
+  recs.push_back(Rec{cur, cur_a, b});
+  cur = -1;
+}
+
+int KernelTimer::collect() {
+  for (const Rec& r : recs) {
+    float ms = 0;
+    if (hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess) return -1;
+    total_ms[r.id] += ms;
+    launches[r.id] += 1;
+    pool.push_back(r.a);
+    pool.push_back(r.b);
+  }
+  recs.clear();
+  return 0;
+}
+
+void KernelTimer::reset() {
+  for (int i = 0; i < kkCount; ++i) {
+    total_ms[i] = 0;
+    launches[i] = 0;
+  }
+}
+
+KernelTimer::~KernelTimer() {
+  for (const Rec& r : recs) {
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+}
+
 // ---------------------------------------------------------------------------
 // PRF
 // ---------------------------------------------------------------------------
@@ -138,7 +195,9 @@ static uint32_t ilog2(uint64_t n) {
   return l;
 }
 
-static void launch_global(uint64_t* a, uint64_t n, uint32_t k_log, uint32_t jl_top, int F, hipStream_t st) {
+static void launch_global(uint64_t* a, uint64_t n, uint32_t k_log, uint32_t jl_top, int F, hipStream_t st,
+                          KernelTimer* tm) {
+  TimedScope ts(tm, kkSortGlobal, st);
   uint64_t threads = n >> F;
   dim3 grid((uint32_t)((threads + 255) / 256)), block(256);
   switch (F) {
@@ -149,21 +208,25 @@ static void launch_global(uint64_t* a, uint64_t n, uint32_t k_log, uint32_t jl_t
   }
 }
 
-void launch_bitonic_sort(uint64_t* a, uint64_t n, hipStream_t st) {
+void launch_bitonic_sort(uint64_t* a, uint64_t n, hipStream_t st, KernelTimer* tm) {
   if (n < 2) return;
   const uint32_t L = ilog2(n);
   const uint32_t logt = L < (uint32_t)kSortLogT ? L : (uint32_t)kSortLogT;
   const uint64_t tiles = n >> logt;
-  hipLaunchKernelGGL((k_bitonic_tile<kSortLogT, kSortNT>), dim3((uint32_t)tiles), dim3(kSortNT), 0, st, a, logt, 0,
-                     0u);
+  {
+    TimedScope ts(tm, kkSortTile, st);
+    hipLaunchKernelGGL((k_bitonic_tile<kSortLogT, kSortNT>), dim3((uint32_t)tiles), dim3(kSortNT), 0, st, a, logt, 0,
+                       0u);
+  }
   for (uint32_t k_log = logt + 1; k_log <= L; ++k_log) {
     int jl = (int)k_log - 1;
     while (jl >= (int)logt) {
       int F = jl - (int)logt + 1;
       if (F > kSortFMax) F = kSortFMax;
-      launch_global(a, n, k_log, (uint32_t)jl, F, st);
+      launch_global(a, n, k_log, (uint32_t)jl, F, st, tm);
       jl -= F;
     }
+    TimedScope ts(tm, kkSortMerge, st);
     hipLaunchKernelGGL((k_bitonic_tile<kSortLogT, kSortNT>), dim3((uint32_t)tiles), dim3(kSortNT), 0, st, a, logt,
                        1, k_log);
   }
@@ -187,7 +250,7 @@ __global__ void k_expand_stage(const uint64_t* __restrict__ in, uint64_t* __rest
 }
 
 // Runs all stages; the result ends in `a` (tmp is scratch of m elements).
-void launch_expand(uint64_t* a, uint64_t* tmp, uint64_t m, hipStream_t st) {
+void launch_expand(uint64_t* a, uint64_t* tmp, uint64_t m, hipStream_t st, KernelTimer* tm) {
   if (m < 2) return;
   int top = 0;
   while ((2ull << top) <= m - 1) ++top;
@@ -195,6 +258,7 @@ void launch_expand(uint64_t* a, uint64_t* tmp, uint64_t m, hipStream_t st) {
   uint64_t* dst = tmp;
   dim3 grid((uint32_t)((m + 255) / 256)), block(256);
   for (int j = top; j >= 0; --j) {
+    TimedScope ts(tm, kkExpand, st);
     hipLaunchKernelGGL(k_expand_stage, grid, block, 0, st, src, dst, m, (uint32_t)j);
     uint64_t* t = src;
     src = dst;
