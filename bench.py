@@ -62,6 +62,10 @@ def main():
     ap.add_argument("--per-call", type=int, default=2048)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-batches", type=int, default=512)
+    ap.add_argument("--no-kernel-timing", action="store_true",
+                    help="leave out the per-kernel HIP events (measures their overhead)")
+    ap.add_argument("--copy-calib", type=int, default=0,
+                    help="MiB of a plain device copy run before the steps (scales profiler byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build runs the oblivious map on a single MI355X "
@@ -93,9 +97,18 @@ def main():
     bounds = np.cumsum([0] + [b[0].size for b in wl.batches])
     obs = B.BOLT_OBS_HOST_PINNED if args.observable == "host" else B.BOLT_OBS_DEVICE
     p = B.params(wl.cap, vs, observable=obs)
-    p.flags |= B.BOLT_F_TIMING
+    if not args.no_kernel_timing:
+        p.flags |= B.BOLT_F_TIMING
     sz = B.sizes_of(p)
     stream = torch.cuda.current_stream()
+
+    if args.copy_calib:
+        src = torch.empty(args.copy_calib << 20, dtype=torch.uint8, device=dev).fill_(1)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        log("copy calibration: %d MiB device-to-device" % args.copy_calib)
 
     nsteps = args.warmup + args.steps
     t0 = time.time()
@@ -137,6 +150,8 @@ def main():
     for s in range(args.steps):
         m = maps[args.warmup + s]
         B.check(m.status(), "status")
+        if args.no_kernel_timing:
+            continue
         for k, (cnt, ms) in m.kernel_times().items():
             c0, m0 = times.get(k, (0, 0.0))
             times[k] = (c0 + cnt, m0 + ms)

@@ -76,7 +76,7 @@ enum { BOLT_OBS_HOST_PINNED = 0, BOLT_OBS_DEVICE = 1 };
 
 typedef struct {
   uint64_t capacity;       /* N_max: most live keys the map will hold */
-  uint32_t value_bytes;    /* vs: bytes per value, a multiple of 8, at most 4096 */
+  uint32_t value_bytes;    /* vs: bytes per value, a multiple of 8; a page (8 + Z (8 + vs) bytes) must fit 32 KiB */
   uint32_t c;              /* mean bin load N/(K+M) (Claim 4.2); the paper's default is 8 */
   uint32_t alpha_permille; /* alpha = K/(K+M) in 1/1000 (Claim 4.4); default 200, below 1000 */
   uint32_t bin_slots;      /* Z, items per bin; 0 = c + ceil(log2 ceil(log2 N_max)) + 1 (Claim 4.2) */

@@ -16,6 +16,7 @@ using namespace bolt;
 namespace {
 
 constexpr uint32_t kMaxZ = 62;  // keys of a page must sit in its first 64 words
+constexpr uint64_t kMaxPageBytes = 32 * 1024;  // one page is staged in a write-back wave's LDS
 
 int derive(const bolt_params* p, Sizes* s) {
   if (!p || p->capacity < 2 || p->value_bytes == 0 || p->value_bytes % 8 || p->value_bytes > 4096) return BOLT_EINVAL;
@@ -41,11 +42,13 @@ int derive(const bolt_params* p, Sizes* s) {
   z.R = (p->capacity + p->pm_keys_per_row - 1) / p->pm_keys_per_row;
   uint64_t raw = 8 + 8 * z.Z + (uint64_t)z.vs * z.Z;
   z.page_bytes = (raw + 127) / 128 * 128;
+  if (z.page_bytes > kMaxPageBytes) return BOLT_EINVAL;
   double a = (double)p->alpha_permille / 1000.0;
   double x = (1.0 + a) * (double)z.M / 2.0 + (double)z.Z * sqrt((double)z.M * log((double)p->capacity));
   z.stash_bound = (uint64_t)ceil(x);
   z.P = z.stash_bound + kMaxBatch;
   z.BZ = z.B * z.Z;
+  z.PW = (z.P + 63) / 64;
   if (z.BZ >= (1ull << 32) || z.P >= (1ull << 32)) return BOLT_EINVAL;
   *s = z;
   return BOLT_OK;
@@ -53,7 +56,8 @@ int derive(const bolt_params* p, Sizes* s) {
 
 uint64_t scratch_bytes(const Sizes& s) {
   const uint64_t Q = kMaxBatch;
-  return Q * 4 * 10 + Q * s.vs + Q * 8 + 3 * Q * 4 + 3 * Q * s.page_bytes + 2 * Q * s.vs + 2 * Q;
+  return Q * 4 * 13 + Q * s.vs + Q * 8 + 3 * Q * 4 + 2 * Q * s.page_bytes + 2 * Q * s.vs + 2 * Q + Q * 12 + 256 * 4 +
+         65 * 4;
 }
 
 uint64_t device_bytes(const bolt_params* p, const Sizes& s) {
@@ -62,7 +66,7 @@ uint64_t device_bytes(const bolt_params* p, const Sizes& s) {
   if (p->observable == BOLT_OBS_DEVICE) b += s.M * s.page_bytes;
   b += s.B * 4;                      // load
   b += s.R * s.W * 16 + s.R * 4;     // position map
-  b += s.P * (8 + s.vs + 4 + 4 + 4); // stash pool + ring
+  b += s.P * (8 + s.vs + 4 + 4) + s.PW * 8;  // stash pool + bitmap
   b += s.B * 4 + s.B * 2 * s.Z * 4;  // reverse index
   b += s.B * 16;                     // claim + rmask
   b += scratch_bytes(s);
@@ -203,7 +207,7 @@ int bolt_create(const bolt_params* p, void* hip_stream, bolt_map** out) {
   rc = rc ? rc : dalloc(m, &m->st_val, s.P * s.vs);
   rc = rc ? rc : dalloc(m, &m->st_dest, s.P * 4);
   rc = rc ? rc : dalloc(m, &m->st_dead, s.P * 4);
-  rc = rc ? rc : dalloc(m, &m->ring, s.P * 4);
+  rc = rc ? rc : dalloc(m, &m->st_used, s.PW * 8);
   rc = rc ? rc : dalloc(m, &m->rev_cnt, s.B * 4);
   rc = rc ? rc : dalloc(m, &m->rev_idx, s.B * 2 * s.Z * 4);
   rc = rc ? rc : dalloc(m, &m->claim, s.B * 8);
@@ -219,8 +223,14 @@ int bolt_create(const bolt_params* p, void* hip_stream, bolt_map** out) {
   rc = rc ? rc : dalloc(m, &b.fval, Q * s.vs);
   rc = rc ? rc : dalloc(m, &b.rpair, Q * 8);
   rc = rc ? rc : dalloc(m, &b.cand_bin, 3 * Q * 4);
-  rc = rc ? rc : dalloc(m, &b.stage, 3 * Q * s.page_bytes);
-  rc = rc ? rc : dalloc(m, &b.ord, Q * 4);
+  rc = rc ? rc : dalloc(m, &b.stage, 2 * Q * s.page_bytes);
+  rc = rc ? rc : dalloc(m, &b.fin, Q * 4);
+  rc = rc ? rc : dalloc(m, &b.chosen, Q * 4);
+  rc = rc ? rc : dalloc(m, &b.rowsel, Q * 4);
+  rc = rc ? rc : dalloc(m, &b.freed, 256 * 4);
+  rc = rc ? rc : dalloc(m, &b.pofs, 65 * 4);
+  rc = rc ? rc : dalloc(m, &b.pkey, Q * 8);
+  rc = rc ? rc : dalloc(m, &b.pidx, Q * 4);
   rc = rc ? rc : dalloc(m, &m->get_ops, Q);
   rc = rc ? rc : dalloc(m, &m->put_ops, Q);
   rc = rc ? rc : dalloc(m, &m->discard, 2 * Q * s.vs);
@@ -258,6 +268,8 @@ int bolt_create(const bolt_params* p, void* hip_stream, bolt_map** out) {
     }
   }
   launch_map_init(m, st);
+  (void)hipMemsetAsync(m->bs.freed, 0, 256 * 4, st);
+
   hipLaunchKernelGGL(k_fill_u8, dim3((uint32_t)((Q + 255) / 256)), dim3(256), 0, st, m->get_ops, Q, (uint8_t)0);
   hipLaunchKernelGGL(k_fill_u8, dim3((uint32_t)((Q + 255) / 256)), dim3(256), 0, st, m->put_ops, Q, (uint8_t)1);
   if (hipGetLastError() != hipSuccess || hipStreamSynchronize(st) != hipSuccess) {
@@ -360,7 +372,7 @@ int bolt_get_stats(bolt_map* m, bolt_stats* out) {
   out->live = c.live;
   out->steps = c.steps;
   out->batches = m->batches;
-  out->stash_live = s.P - (c.ring_tail - c.ring_head);
+  out->stash_live = c.stash_live;
   out->stash_highwater = c.stash_hw;
   std::vector<uint32_t> ld(s.B);
   if (hipMemcpy(ld.data(), m->load, s.B * 4, hipMemcpyDeviceToHost) != hipSuccess) return BOLT_EHIP;
@@ -458,16 +470,17 @@ int bolt_stash_snapshot(bolt_map* m, uint64_t* host_keys, uint32_t* host_bins, v
   int rc = sync_and_read(m, &c);
   if (rc) return rc;
   const Sizes& s = m->s;
-  std::vector<uint32_t> ring(s.P), dest(s.P);
+  std::vector<uint64_t> used(s.PW);
+  std::vector<uint32_t> dest(s.P);
   std::vector<uint64_t> key(s.P);
   std::vector<uint8_t> val(s.P * s.vs);
-  if (hipMemcpy(ring.data(), m->ring, s.P * 4, hipMemcpyDeviceToHost) != hipSuccess ||
+  if (hipMemcpy(used.data(), m->st_used, s.PW * 8, hipMemcpyDeviceToHost) != hipSuccess ||
       hipMemcpy(dest.data(), m->st_dest, s.P * 4, hipMemcpyDeviceToHost) != hipSuccess ||
       hipMemcpy(key.data(), m->st_key, s.P * 8, hipMemcpyDeviceToHost) != hipSuccess ||
       hipMemcpy(val.data(), m->st_val, s.P * s.vs, hipMemcpyDeviceToHost) != hipSuccess)
     return BOLT_EHIP;
   std::vector<uint8_t> is_free(s.P, 0);
-  for (uint64_t x = c.ring_head; x < c.ring_tail; ++x) is_free[ring[x % s.P]] = 1;
+  for (uint64_t e = 0; e < s.P; ++e) is_free[e] = !((used[e >> 6] >> (e & 63)) & 1);
   uint64_t k = 0;
   for (uint64_t e = 0; e < s.P; ++e) {
     if (is_free[e]) continue;

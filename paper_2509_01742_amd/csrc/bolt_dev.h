@@ -27,11 +27,11 @@ struct Ctl {
   uint32_t reject;       // current batch rejected (bad op code)
   uint64_t steps;        // tape counter s
   uint64_t live;         // keys present
-  uint64_t ring_head;    // stash pool ring: next free entry to hand out
-  uint64_t ring_tail;    // stash pool ring: next place to return an entry
+  uint64_t stash_live;   // stash pool entries in use at the end of the last batch
   uint64_t stash_hw;     // stash high-water mark
-  int64_t batch_delta;   // inserts - deletes of the current batch
-  uint32_t n_place;      // entries placed by the current batch
+  uint32_t b_place;      // items placed by the current batch
+  uint32_t b_ins;        // keys inserted by the current batch
+  uint32_t b_del;        // keys deleted by the current batch
   uint32_t pad;
 };
 
@@ -157,5 +157,42 @@ __device__ __forceinline__ uint32_t ld_acq32(const uint32_t* p) {
 }
 
 __device__ __forceinline__ void set_err(Ctl* ctl, uint32_t bits) { atomicOr(&ctl->err, bits); }
+
+// Adds `flag` (0/1) of every active lane to *ctr with one atomic per wave.
+__device__ __forceinline__ void wave_count(uint32_t* ctr, bool flag) {
+  const uint64_t bal = __ballot(flag);
+  if (bal && (threadIdx.x & 63) == (uint32_t)__builtin_ctzll(__ballot(1))) atomicAdd(ctr, (uint32_t)__popcll(bal));
+}
+
+// Stash pool: a bitmap of used entries (bits past the pool size are kept
+// set).  Allocation probes words from a hashed start; every thread claims
+// its own bit with atomicOr, so concurrent allocations do not contend on
+// one counter.  Returns kNone when `max_probe` words are all full.
+__device__ __forceinline__ uint32_t pool_alloc(uint64_t* used, uint64_t nwords, uint64_t start, uint32_t max_probe) {
+  uint64_t w = start % nwords;
+  for (uint32_t probe = 0; probe < max_probe; ++probe) {
+    uint64_t cur = __hip_atomic_load(&used[w], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    while (~cur) {
+      const uint64_t bit = ~cur & (0ull - ~cur);  // lowest clear bit
+      const uint64_t old = atomicOr((unsigned long long*)&used[w], (unsigned long long)bit);
+      if (!(old & bit)) return (uint32_t)(w * 64 + __builtin_ctzll(bit));
+      cur = old | bit;
+    }
+    w = w + 1 == nwords ? 0 : w + 1;
+  }
+  return kNone;
+}
+
+__device__ __forceinline__ void pool_free(uint64_t* used, uint32_t e) {
+  atomicAnd((unsigned long long*)&used[e >> 6], ~(1ull << (e & 63)));
+}
+
+__device__ __forceinline__ uint64_t alloc_hash(uint32_t epoch, uint32_t i) {
+  uint64_t x = ((uint64_t)epoch << 32) ^ (uint64_t)(i + 1) * 0x9E3779B97F4A7C15ull;
+  x ^= x >> 31;
+  x *= 0xBF58476D1CE4E5B9ull;
+  x ^= x >> 29;
+  return x;
+}
 
 }  // namespace bolt

@@ -23,8 +23,14 @@ struct BatchScratch {
   uint8_t* fval;      // [Q * vs] (leaders) the value found
   uint2* rpair;       // [Q] remap pair R(s) of each command
   uint32_t* cand_bin; // [3Q] bin each write-back candidate slot would rewrite, or kNone
-  uint8_t* stage;     // [2Q * page_bytes] copies of the pages read
-  uint32_t* ord;      // [Q] (leaders) ordinal among the keys placed this batch, or kNone
+  uint8_t* stage;     // [2Q * page_bytes] copies of the observable pages read
+  uint32_t* fin;      // [Q] (leaders) bit 0 present at the end, bit 1 found in the map
+  uint32_t* chosen;   // [Q] (leaders placed) bin chosen by P2C
+  uint32_t* rowsel;   // [Q] (keys inserted) position-map row chosen
+  uint32_t* freed;    // [256] stash entries freed this batch, in buckets
+  uint32_t* pofs;     // [65] first command of each key partition
+  uint64_t* pkey;     // [Q] keys grouped by partition
+  uint32_t* pidx;     // [Q] command indexes grouped by partition
 };
 
 // Scratch of a build, allocated for the call and freed afterwards.
@@ -88,7 +94,7 @@ struct TimedScope {
 };
 
 struct Sizes {
-  uint64_t cap, B, K, M, Z, W, d, R, page_bytes, stash_bound, P, BZ;
+  uint64_t cap, B, K, M, Z, W, d, R, page_bytes, stash_bound, P, BZ, PW;
   uint32_t vs;
 };
 
@@ -111,7 +117,7 @@ struct bolt_map {
   uint8_t* st_val;    // [P * vs]
   uint32_t* st_dest;  // [P] destination bin
   uint32_t* st_dead;  // [P] removed by an access of this batch
-  uint32_t* ring;     // [P] free pool entries
+  uint64_t* st_used;  // [ceil(P / 64)] pool bitmap, 1 = in use
   uint32_t* rev_cnt;  // [B] stash entries listed per bin
   uint32_t* rev_idx;  // [B * 2Z]
   uint64_t* claim;    // [B] write-back election, tagged with the batch epoch

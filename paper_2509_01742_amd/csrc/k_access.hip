@@ -1,25 +1,30 @@
 // Batched oblivious access (Alg. 1 per command, in the module order of
 // Sec. 5.1): decode, key search, value access, remap + eviction, response.
 //
-// One batch of q commands runs as six kernels on one stream:
-//   dedup     sort (key, index) in LDS; leader = first command of each key;
-//             for every command the last PUT/DEL of its key before it
+// One batch of q commands runs as a handful of kernels on one stream:
+//   dedup     one workgroup sorts (key, index) (registers, wave shuffles,
+//             LDS); leader = first command of each key; for every command
+//             the last PUT/DEL of its key before it
 //   fetch     one wave per command: tape T(s) -> fetch pair F(s) and remap
 //             pair R(s); leaders look their key up in the position map (d
 //             rows); read both bins whole (observable pages are copied to
 //             a staging area); the leader of a mapped key finds and removes
 //             its item (page slot or stash entry); elect one writer per bin
 //   resolve   responses of every command in index order (sequential
-//             semantics of the batch)
-//   remap     one workgroup: keys present at the end get R(s) and P2C over
-//             the post-removal loads, in rounds of ceil(B/16); the item goes
-//             to the stash pool listed under its bin; position-map updates,
-//             deletes, then inserts in rounds of ceil(R/16)
+//             semantics of the batch); final state of every key
+//   remap     keys present at the end get R(s) and P2C over the
+//             post-removal loads, in rounds of ceil(B/16) keys; the item goes
+//             to the stash pool, listed under its bin; position-map
+//             updates, deletes, then inserts in rounds of ceil(R/16).  When
+//             the batch fits one round of each (large maps) this runs
+//             thread-per-command across the chip (resolve decides, place
+//             applies, finish inserts); otherwise one workgroup runs the
+//             rounds in order
 //   writeback one wave per candidate bin: the elected writer rebuilds the
 //             bin as survivors + every live stash item listed for it,
 //             canonical order, and writes it whole (observable pages once
-//             each)
-//   finish    counters, stash bound
+//             each); the entries listed are freed
+//   finish    position-map inserts (one-round case), counters, stash bound
 #include "bolt_impl.h"
 
 namespace bolt {
@@ -69,7 +74,6 @@ __device__ uint32_t block_excl(uint32_t x, uint32_t* total) {
   }
   __syncthreads();
   uint32_t before = ws[wid];
-  // exclusive within the wave
   uint32_t wex = __shfl_up(inc, 1, 64);
   if (lane == 0) wex = 0;
   uint32_t r = MAX ? (before > wex ? before : wex) : before + wex;
@@ -81,50 +85,184 @@ __device__ uint32_t block_excl(uint32_t x, uint32_t* total) {
 // dedup + fold structure (one workgroup)
 // ---------------------------------------------------------------------------
 
-__global__ __launch_bounds__(kDedupNT) void k_acc_dedup(const uint8_t* __restrict__ ops,
-                                                        const uint64_t* __restrict__ keys, uint32_t q, Ctl* ctl,
-                                                        uint32_t* __restrict__ leader, uint32_t* __restrict__ prevw,
-                                                        uint32_t* __restrict__ lastw) {
+// (key, index) strictly before (key', index')
+__device__ __forceinline__ bool kv_less(uint64_t ka, uint32_t ia, uint64_t kb, uint32_t ib) {
+  return ka < kb || (ka == kb && ia < ib);
+}
+
+// Compare-exchange of the pairs (e, e + J) held by one thread (J < 8 known at
+// compile time, so the arrays stay in registers).
+template <uint32_t J>
+__device__ __forceinline__ void dedup_reg_stage(uint64_t k[kDedupPer], uint32_t x[kDedupPer], uint32_t base,
+                                                uint32_t kk) {
+#pragma unroll
+  for (uint32_t e = 0; e < kDedupPer; ++e) {
+    if (e & J) continue;
+    const uint32_t e2 = e + J;
+    const bool asc = ((base + e) & kk) == 0;
+    const bool lt = kv_less(k[e2], x[e2], k[e], x[e]);
+    const bool gt = kv_less(k[e], x[e], k[e2], x[e2]);
+    if (asc ? lt : gt) {
+      const uint64_t tk = k[e];
+      k[e] = k[e2];
+      k[e2] = tk;
+      const uint32_t tx = x[e];
+      x[e] = x[e2];
+      x[e2] = tx;
+    }
+  }
+}
+
+// Bitonic sort of the (key, index) pairs: thread t holds positions 8t..8t+7.
+// Strides 1..4 run inside a thread, strides 8..256 between lanes of a wave
+// (shuffles), strides 512 and up through LDS.
+__device__ __forceinline__ void dedup_sort(uint64_t k[kDedupPer], uint32_t x[kDedupPer], uint32_t npad,
+                                           uint64_t* skey, uint32_t* sidx) {
+  const uint32_t base = threadIdx.x * kDedupPer;
+  // A wave whose positions all lie at or past npad holds only padding, and
+  // no stage of a network of size npad pairs it with a real position: it
+  // skips the register and shuffle stages (it still meets every barrier).
+  const bool busy = (threadIdx.x & ~63u) * kDedupPer < npad;
+  for (uint32_t kk = 2; kk <= npad; kk <<= 1) {
+    for (uint32_t j = kk >> 1; j > 0; j >>= 1) {
+      if (!busy && j < 64 * kDedupPer) continue;
+      if (j < kDedupPer) {
+        if (j == 4) dedup_reg_stage<4>(k, x, base, kk);
+        else if (j == 2) dedup_reg_stage<2>(k, x, base, kk);
+        else dedup_reg_stage<1>(k, x, base, kk);
+      } else if (j < 64 * kDedupPer) {
+        const int d = (int)(j / kDedupPer);
+#pragma unroll
+        for (uint32_t e = 0; e < kDedupPer; ++e) {
+          const uint64_t ok = __shfl_xor(k[e], d, 64);
+          const uint32_t ox = __shfl_xor(x[e], d, 64);
+          const uint32_t p = base + e;
+          const bool keep_min = ((p & j) == 0) == ((p & kk) == 0);
+          const bool take = keep_min ? kv_less(ok, ox, k[e], x[e]) : kv_less(k[e], x[e], ok, ox);
+          if (take) {
+            k[e] = ok;
+            x[e] = ox;
+          }
+        }
+      } else {
+#pragma unroll
+        for (uint32_t e = 0; e < kDedupPer; ++e) {
+          skey[base + e] = k[e];
+          sidx[base + e] = x[e];
+        }
+        __syncthreads();
+#pragma unroll
+        for (uint32_t e = 0; e < kDedupPer; ++e) {
+          const uint32_t p = base + e;
+          const uint64_t ok = skey[p ^ j];
+          const uint32_t ox = sidx[p ^ j];
+          const bool keep_min = ((p & j) == 0) == ((p & kk) == 0);
+          const bool take = keep_min ? kv_less(ok, ox, k[e], x[e]) : kv_less(k[e], x[e], ok, ox);
+          if (take) {
+            k[e] = ok;
+            x[e] = ox;
+          }
+        }
+        __syncthreads();
+      }
+    }
+  }
+#pragma unroll
+  for (uint32_t e = 0; e < kDedupPer; ++e) {
+    skey[base + e] = k[e];
+    sidx[base + e] = x[e];
+  }
+  __syncthreads();
+}
+
+// Commands are first split into kParts partitions by a hash of their key
+// (all commands of a key land in one partition); each partition is then
+// sorted and folded by its own workgroup.
+constexpr uint32_t kParts = 64;
+
+__device__ __forceinline__ uint32_t part_of(uint64_t key) {
+  uint64_t x = key;
+  x ^= x >> 33;
+  x *= 0xFF51AFD7ED558CCDull;
+  x ^= x >> 33;
+  return (uint32_t)(x >> 58);  // top 6 bits: kParts = 64
+}
+
+// One workgroup: op check, a histogram of the partitions in LDS, their
+// offsets, then every (key, index) scattered to its partition (no global
+// atomics).  A batch with an op code above DEL is marked rejected.
+__global__ __launch_bounds__(1024) void k_acc_part(const uint8_t* __restrict__ ops, const uint64_t* __restrict__ keys,
+                                                   uint32_t q, uint32_t epoch, Ctl* ctl, uint32_t* __restrict__ pofs,
+                                                   uint64_t* __restrict__ pkey, uint32_t* __restrict__ pidx) {
+  __shared__ uint32_t hist[kParts];
+  __shared__ uint32_t base[kParts];
+  __shared__ uint32_t bad;
+  if (threadIdx.x < kParts) hist[threadIdx.x] = 0;
+  if (threadIdx.x == 0) bad = 0;
+  __syncthreads();
+  uint32_t mypart[kMaxBatch / 1024], myrank[kMaxBatch / 1024];
+#pragma unroll
+  for (uint32_t t = 0; t < kMaxBatch / 1024; ++t) {
+    const uint32_t i = threadIdx.x + t * 1024;
+    if (i < q) {
+      if (ops[i] > 2) bad = 1;
+      mypart[t] = part_of(keys[i]);
+      myrank[t] = atomicAdd(&hist[mypart[t]], 1u);
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t acc = 0;
+    for (uint32_t b = 0; b < kParts; ++b) {
+      base[b] = acc;
+      pofs[b] = acc;
+      acc += hist[b];
+    }
+    pofs[kParts] = acc;
+    if (bad) ctl->reject = epoch;
+  }
+  __syncthreads();
+#pragma unroll
+  for (uint32_t t = 0; t < kMaxBatch / 1024; ++t) {
+    const uint32_t i = threadIdx.x + t * 1024;
+    if (i < q) {
+      const uint32_t pos = base[mypart[t]] + myrank[t];
+      pkey[pos] = keys[i];
+      pidx[pos] = i;
+    }
+  }
+}
+
+// One workgroup per partition: sort its (key, index) pairs; leader = first
+// command of each key; for every command the last PUT/DEL of its key before
+// it; for every leader the last PUT/DEL of its key in the batch.
+__global__ __launch_bounds__(kDedupNT) void k_acc_group(const uint8_t* __restrict__ ops, uint32_t epoch, const Ctl* ctl,
+                                                        const uint32_t* __restrict__ pofs,
+                                                        const uint64_t* __restrict__ pkey,
+                                                        const uint32_t* __restrict__ pidx, uint32_t* __restrict__ leader,
+                                                        uint32_t* __restrict__ prevw, uint32_t* __restrict__ lastw) {
   __shared__ uint64_t skey[kMaxBatch];
   __shared__ uint32_t sidx[kMaxBatch];
   __shared__ uint32_t tot;
-  __shared__ uint32_t bad;
-  if (threadIdx.x == 0) bad = 0;
+  const uint32_t part = blockIdx.x;
+  const uint32_t off = pofs[part];
+  const uint32_t q = pofs[part + 1] - off;  // commands in this partition
+  if (q == 0 || ctl->reject == epoch) return;  // whole block
   uint32_t npad = 1;
   while (npad < q) npad <<= 1;
-  __syncthreads();
-  for (uint32_t r = threadIdx.x; r < npad; r += kDedupNT) {
-    bool real = r < q;
-    skey[r] = real ? keys[r] : kNone64;
-    sidx[r] = real ? r : kNone;
-    if (real && ops[r] > 2) bad = 1;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) ctl->reject = bad;
-  if (bad) return;  // the whole block sees the same value
-  // bitonic sort by (key, index), ascending
-  for (uint32_t k = 2; k <= npad; k <<= 1) {
-    for (uint32_t j = k >> 1; j > 0; j >>= 1) {
-      for (uint32_t p = threadIdx.x; p < npad / 2; p += kDedupNT) {
-        uint32_t i = ((p & ~(j - 1)) << 1) | (p & (j - 1));
-        uint32_t l = i + j;
-        bool asc = (i & k) == 0;
-        uint64_t ka = skey[i], kb = skey[l];
-        uint32_t ia = sidx[i], ib = sidx[l];
-        bool gt = ka > kb || (ka == kb && ia > ib);
-        if (gt == asc) {
-          skey[i] = kb;
-          skey[l] = ka;
-          sidx[i] = ib;
-          sidx[l] = ia;
-        }
-      }
-      __syncthreads();
-    }
-  }
-  // Each thread owns kDedupPer consecutive sorted positions.  Values are
-  // stored +1 so that 0 means "none".
+  uint64_t k[kDedupPer];
+  uint32_t x[kDedupPer];
   const uint32_t r0 = threadIdx.x * kDedupPer;
+#pragma unroll
+  for (uint32_t e = 0; e < kDedupPer; ++e) {
+    const uint32_t r = r0 + e;
+    const bool real = r < q;
+    k[e] = real ? pkey[off + r] : kNone64;
+    x[e] = real ? pidx[off + r] : kNone;
+  }
+  dedup_sort(k, x, npad, skey, sidx);
+  // Fold structure.  Each thread owns kDedupPer consecutive sorted
+  // positions; positions are stored +1 so that 0 means "none".
   uint32_t rs[kDedupPer], wp[kDedupPer];
   uint32_t run = 0, wmax = 0;
   for (uint32_t t = 0; t < kDedupPer; ++t) {
@@ -201,7 +339,7 @@ __global__ __launch_bounds__(256) void k_acc_fetch(FetchArgs a) {
   const uint32_t lane = threadIdx.x & 63;
   const uint32_t i = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (i >= a.q) return;
-  if (a.ctl->reject || a.ctl->err) return;
+  if (a.ctl->reject == a.epoch || a.ctl->err) return;
   uint32_t hk[8];
 #pragma unroll
   for (int j = 0; j < 8; ++j) hk[j] = a.ctl->hkey[j];
@@ -315,48 +453,36 @@ __global__ __launch_bounds__(256) void k_acc_fetch(FetchArgs a) {
   }
 }
 
-// ---------------------------------------------------------------------------
-// resolve: responses (one thread per command)
-// ---------------------------------------------------------------------------
-
-__global__ void k_acc_resolve(const Ctl* ctl, const uint8_t* __restrict__ ops, const uint64_t* __restrict__ vals_in,
-                              const uint32_t* __restrict__ leader, const uint32_t* __restrict__ prevw,
-                              const uint32_t* __restrict__ found, const uint64_t* __restrict__ fval, uint32_t q,
-                              uint32_t vw, uint64_t* __restrict__ vals_out, uint8_t* __restrict__ status) {
-  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= q) return;
-  uint64_t* out = vals_out + (uint64_t)i * vw;
-  if (ctl->reject || ctl->err) {
-    status[i] = 0xFF;
-    for (uint32_t o = 0; o < vw; ++o) out[o] = 0;
-    return;
+// Claims a free slot of row r for (key, pair); false when the row is full.
+__device__ __forceinline__ bool pm_claim(uint32_t* pm_mask, uint64_t* pm_key, uint2* pm_pair, uint32_t r, uint32_t W,
+                                         uint64_t key, uint2 pair) {
+  const uint32_t full = W >= 32 ? 0xFFFFFFFFu : ((1u << W) - 1);
+  for (uint32_t tries = 0; tries < 32; ++tries) {
+    const uint32_t mk = ld_acq32(&pm_mask[r]);
+    const uint32_t free = ~mk & full;
+    if (!free) return false;
+    const uint32_t bit = free & (0u - free);
+    const uint32_t prev = atomicOr(&pm_mask[r], bit);
+    if (!(prev & bit)) {
+      const uint32_t slot = __builtin_ctz(bit);
+      pm_key[(uint64_t)r * W + slot] = key;
+      pm_pair[(uint64_t)r * W + slot] = pair;
+      return true;
+    }
   }
-  const uint32_t L = leader[i], w = prevw[i];
-  const bool present = w != kNone ? ops[w] == 1 : found[L] != 0;
-  const uint64_t* src = w != kNone ? vals_in + (uint64_t)w * vw : fval + (uint64_t)L * vw;
-  const uint8_t op = ops[i];
-  uint8_t st;
-  if (op == 0) st = present ? 1 : 0;
-  else if (op == 1) st = present ? 1 : 2;
-  else st = present ? 3 : 0;
-  status[i] = st;
-  const bool give = op == 0 && present;
-  for (uint32_t o = 0; o < vw; ++o) out[o] = give ? src[o] : 0;
+  return false;
 }
 
 // ---------------------------------------------------------------------------
-// remap + P2C + position map (one workgroup)
+// resolve: responses and final states (one thread per command)
 // ---------------------------------------------------------------------------
 
-constexpr uint32_t kRemapNT = 1024;
-constexpr uint32_t kRemapPer = kMaxBatch / kRemapNT;
-
-struct RemapArgs {
+struct ResolveArgs {
   Ctl* ctl;
   const uint8_t* ops;
-  const uint64_t* keys;
   const uint64_t* vals_in;
   const uint32_t* leader;
+  const uint32_t* prevw;
   const uint32_t* lastw;
   const uint32_t* hit;
   const uint32_t* hrow;
@@ -364,14 +490,185 @@ struct RemapArgs {
   const uint32_t* found;
   const uint64_t* fval;
   const uint2* rpair;
+  const uint32_t* load;
+  uint32_t q, vw, fast, epoch;
+  uint64_t* vals_out;
+  uint8_t* status;
+  uint32_t* fin;
+  uint32_t* chosen;
+  uint32_t* pm_mask;
+};
+
+__global__ __launch_bounds__(256) void k_acc_resolve(ResolveArgs a) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  const bool live = i < a.q;
+  if (a.ctl->reject == a.epoch || a.ctl->err) {
+    if (live) {
+      a.status[i] = 0xFF;
+      for (uint32_t o = 0; o < a.vw; ++o) a.vals_out[(uint64_t)i * a.vw + o] = 0;
+    }
+    return;
+  }
+  bool del = false;
+  if (live) {
+    const uint32_t L = a.leader[i], w = a.prevw[i];
+    const bool present = w != kNone ? a.ops[w] == 1 : a.found[L] != 0;
+    const uint64_t* src = w != kNone ? a.vals_in + (uint64_t)w * a.vw : a.fval + (uint64_t)L * a.vw;
+    const uint8_t op = a.ops[i];
+    uint8_t st;
+    if (op == 0) st = present ? 1 : 0;
+    else if (op == 1) st = present ? 1 : 2;
+    else st = present ? 3 : 0;
+    a.status[i] = st;
+    const bool give = op == 0 && present;
+    uint64_t* out = a.vals_out + (uint64_t)i * a.vw;
+    for (uint32_t o = 0; o < a.vw; ++o) out[o] = give ? src[o] : 0;
+    if (L == i) {
+      // final state of the key at the end of the batch
+      const uint32_t lw = a.lastw[i];
+      const bool fp = lw != kNone ? a.ops[lw] == 1 : a.found[i] != 0;
+      const bool h = a.hit[i] != 0;
+      a.fin[i] = (fp ? 1u : 0u) | (h ? 2u : 0u);
+      if (a.fast) {
+        if (fp) {  // P2C over the post-removal loads (one round)
+          const uint2 rp = a.rpair[i];
+          a.chosen[i] = a.load[rp.y] < a.load[rp.x] ? rp.y : rp.x;
+        }
+        if (h && !fp) {  // deletes come before the inserts of this batch
+          atomicAnd(&a.pm_mask[a.hrow[i]], ~(1u << a.hslot[i]));
+          del = true;
+        }
+      }
+    }
+  }
+  if (a.fast) wave_count(&a.ctl->b_del, del);
+}
+
+// ---------------------------------------------------------------------------
+// place (one-round case): P2C loads, stash entries, position-map updates and
+// the row of every insert (one thread per command)
+// ---------------------------------------------------------------------------
+
+struct PlaceArgs {
+  Ctl* ctl;
+  const uint64_t* keys;
+  const uint64_t* vals_in;
+  const uint32_t* leader;
+  const uint32_t* lastw;
+  const uint32_t* fin;
+  const uint32_t* chosen;
+  const uint32_t* hrow;
+  const uint32_t* hslot;
+  const uint64_t* fval;
+  const uint2* rpair;
   uint32_t q, epoch, Z, W, d, vw;
-  uint64_t B, K, R, P, cap;
+  uint64_t K, R, PW;
   uint32_t* load;
+  uint64_t* st_used;
   uint64_t* st_key;
   uint64_t* st_val;
   uint32_t* st_dest;
   uint32_t* st_dead;
-  const uint32_t* ring;
+  uint32_t* rev_cnt;
+  uint32_t* rev_idx;
+  uint64_t* claim;
+  uint32_t* cand_bin;
+  uint2* pm_pair;
+  const uint32_t* pm_mask;
+  uint32_t* rowsel;
+};
+
+// Stores an item in a fresh stash entry listed under bin b.
+__device__ __forceinline__ bool stash_put(uint64_t* st_used, uint64_t PW, uint64_t* st_key, uint64_t* st_val,
+                                          uint32_t* st_dest, uint32_t* st_dead, uint32_t* rev_cnt,
+                                          uint32_t* rev_idx, uint32_t Z, uint32_t vw, uint32_t epoch, uint32_t i,
+                                          uint64_t key, const uint64_t* val, uint32_t b) {
+  const uint32_t e = pool_alloc(st_used, PW, alloc_hash(epoch, i), (uint32_t)PW);
+  if (e == kNone) return false;
+  st_key[e] = key;
+  for (uint32_t x = 0; x < vw; ++x) st_val[(uint64_t)e * vw + x] = val[x];
+  st_dest[e] = b;
+  st_dead[e] = 0;
+  const uint32_t ls = atomicAdd(&rev_cnt[b], 1u);
+  if (ls >= 2 * Z) return false;
+  rev_idx[(uint64_t)b * 2 * Z + ls] = e;
+  return true;
+}
+
+__global__ __launch_bounds__(256) void k_acc_place(PlaceArgs a) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (a.ctl->reject == a.epoch || a.ctl->err) return;
+  bool placed = false, ins = false;
+  if (i < a.q) {
+    a.cand_bin[2 * a.q + i] = kNone;
+    a.rowsel[i] = kNone;
+    if (a.leader[i] == i && (a.fin[i] & 1)) {
+      const uint32_t b = a.chosen[i];
+      const uint32_t old = atomicAdd(&a.load[b], 1u);
+      if (old + 1 > a.Z) set_err(a.ctl, kErrOverflow);
+      const uint32_t lw = a.lastw[i];
+      const uint64_t* src = lw != kNone ? a.vals_in + (uint64_t)lw * a.vw : a.fval + (uint64_t)i * a.vw;
+      if (!stash_put(a.st_used, a.PW, a.st_key, a.st_val, a.st_dest, a.st_dead, a.rev_cnt, a.rev_idx, a.Z, a.vw,
+                     a.epoch, i, a.keys[i], src, b))
+        set_err(a.ctl, kErrOverflow);
+      placed = true;
+      if (b < a.K) {  // HBM bins are rebuilt in this batch
+        a.cand_bin[2 * a.q + i] = b;
+        atomicMax((unsigned long long*)&a.claim[b], (unsigned long long)claim_tag(a.epoch, 2 * a.q + i));
+      }
+      if (a.fin[i] & 2) {
+        a.pm_pair[(uint64_t)a.hrow[i] * a.W + a.hslot[i]] = a.rpair[i];
+      } else {
+        // insert: the least loaded of d rows after this batch's deletes
+        uint64_t g[4];
+        const uint32_t hk[8] = {a.ctl->hkey[0], a.ctl->hkey[1], a.ctl->hkey[2], a.ctl->hkey[3],
+                                a.ctl->hkey[4], a.ctl->hkey[5], a.ctl->hkey[6], a.ctl->hkey[7]};
+        prf4(hk, kDomRows, a.keys[i], g);
+        uint32_t best = (uint32_t)__umul64hi(g[0], a.R);
+        uint32_t bc = __popc(a.pm_mask[best]);
+        for (uint32_t j = 1; j < a.d; ++j) {
+          const uint32_t r = (uint32_t)__umul64hi(g[j], a.R);
+          const uint32_t c = __popc(a.pm_mask[r]);
+          if (c < bc) {
+            bc = c;
+            best = r;
+          }
+        }
+        a.rowsel[i] = best;
+        ins = true;
+      }
+    }
+  }
+  wave_count(&a.ctl->b_place, placed);
+  wave_count(&a.ctl->b_ins, ins);
+}
+
+// ---------------------------------------------------------------------------
+// remap, several rounds (one workgroup): the same steps in round order
+// ---------------------------------------------------------------------------
+
+constexpr uint32_t kRemapNT = 1024;
+constexpr uint32_t kRemapPer = kMaxBatch / kRemapNT;
+
+struct RemapArgs {
+  Ctl* ctl;
+  const uint64_t* keys;
+  const uint64_t* vals_in;
+  const uint32_t* leader;
+  const uint32_t* lastw;
+  const uint32_t* fin;
+  const uint32_t* hrow;
+  const uint32_t* hslot;
+  const uint64_t* fval;
+  const uint2* rpair;
+  uint32_t q, epoch, Z, W, d, vw;
+  uint64_t B, K, R, PW;
+  uint32_t* load;
+  uint64_t* st_used;
+  uint64_t* st_key;
+  uint64_t* st_val;
+  uint32_t* st_dest;
+  uint32_t* st_dead;
   uint32_t* rev_cnt;
   uint32_t* rev_idx;
   uint64_t* claim;
@@ -384,24 +681,18 @@ struct RemapArgs {
 __global__ __launch_bounds__(kRemapNT) void k_acc_remap(RemapArgs a) {
   __shared__ uint32_t tot;
   __shared__ uint32_t s_skip;
-  if (threadIdx.x == 0) s_skip = (a.ctl->reject || a.ctl->err) ? 1 : 0;
+  if (threadIdx.x == 0) s_skip = (a.ctl->reject == a.epoch || a.ctl->err) ? 1 : 0;
   __syncthreads();
   if (s_skip) return;
   const uint32_t i0 = threadIdx.x * kRemapPer;
-  // final state of every key in the batch (leaders only)
-  uint32_t fin[kRemapPer];  // bit0 present, bit1 hit, bit2 insert
+  uint32_t fin[kRemapPer];  // bit0 present at the end, bit1 mapped at the start
   uint32_t nplace_mine = 0, nins_mine = 0, ndel_mine = 0;
   for (uint32_t t = 0; t < kRemapPer; ++t) {
     const uint32_t i = i0 + t;
-    fin[t] = 0;
-    if (i >= a.q || a.leader[i] != i) continue;
-    const uint32_t lw = a.lastw[i];
-    const bool present = lw != kNone ? a.ops[lw] == 1 : a.found[i] != 0;
-    const bool h = a.hit[i] != 0;
-    fin[t] = (present ? 1u : 0u) | (h ? 2u : 0u);
-    nplace_mine += present;
-    nins_mine += present && !h;
-    ndel_mine += h && !present;
+    fin[t] = (i < a.q && a.leader[i] == i) ? a.fin[i] : 0;
+    nplace_mine += fin[t] & 1;
+    nins_mine += (fin[t] & 3) == 1;
+    ndel_mine += (fin[t] & 3) == 2;
   }
   const uint32_t place0 = block_excl<kRemapNT, false>(nplace_mine, &tot);
   const uint32_t nplace = tot;
@@ -412,11 +703,6 @@ __global__ __launch_bounds__(kRemapNT) void k_acc_remap(RemapArgs a) {
   block_excl<kRemapNT, false>(ndel_mine, &tot);
   const uint32_t ndel = tot;
   __syncthreads();
-  const uint64_t head = a.ctl->ring_head, tail = a.ctl->ring_tail;
-  if ((uint64_t)nplace > tail - head) {
-    if (threadIdx.x == 0) set_err(a.ctl, kErrOverflow);
-    return;  // uniform
-  }
   // P2C in rounds of ceil(B/16) over the post-removal loads (Sec. 5.1 step 5)
   const uint64_t rs = (a.B + 15) / 16;
   uint32_t chosen[kRemapPer];
@@ -444,25 +730,16 @@ __global__ __launch_bounds__(kRemapNT) void k_acc_remap(RemapArgs a) {
     __threadfence();
     __syncthreads();
   }
-  // place every remapped item in the stash pool, listed under its bin
-  uint32_t o = place0;
+  // every remapped item goes to the stash pool, listed under its bin
   for (uint32_t t = 0; t < kRemapPer; ++t) {
     const uint32_t i = i0 + t;
     if (i < a.q) a.cand_bin[2 * a.q + i] = kNone;
     if (!(fin[t] & 1)) continue;
     const uint32_t b = chosen[t];
-    const uint32_t e = a.ring[(head + o) % a.P];
-    ++o;
     const uint32_t lw = a.lastw[i];
     const uint64_t* src = lw != kNone ? a.vals_in + (uint64_t)lw * a.vw : a.fval + (uint64_t)i * a.vw;
-    a.st_key[e] = a.keys[i];
-    for (uint32_t x = 0; x < a.vw; ++x) a.st_val[(uint64_t)e * a.vw + x] = src[x];
-    a.st_dest[e] = b;
-    a.st_dead[e] = 0;
-    const uint32_t ls = atomicAdd(&a.rev_cnt[b], 1u);
-    if (ls < 2 * a.Z)
-      a.rev_idx[(uint64_t)b * 2 * a.Z + ls] = e;
-    else
+    if (!stash_put(a.st_used, a.PW, a.st_key, a.st_val, a.st_dest, a.st_dead, a.rev_cnt, a.rev_idx, a.Z, a.vw,
+                   a.epoch, i, a.keys[i], src, b))
       set_err(a.ctl, kErrOverflow);
     if (b < a.K) {  // HBM bins are rebuilt in this batch
       a.cand_bin[2 * a.q + i] = b;
@@ -513,23 +790,8 @@ __global__ __launch_bounds__(kRemapNT) void k_acc_remap(RemapArgs a) {
     for (uint32_t t = 0; t < kRemapPer; ++t) {
       if ((fin[t] & 3) != 1) continue;
       if (io >= r0 && io < r0 + rsm) {
-        const uint32_t r = rowsel[t];
-        const uint32_t full = a.W >= 32 ? 0xFFFFFFFFu : ((1u << a.W) - 1);
-        bool done = false;
-        for (uint32_t tries = 0; tries < 32 && !done; ++tries) {
-          const uint32_t mk = ld_acq32(&a.pm_mask[r]);
-          const uint32_t free = ~mk & full;
-          if (!free) break;
-          const uint32_t bit = free & (0u - free);
-          const uint32_t prev = atomicOr(&a.pm_mask[r], bit);
-          if (!(prev & bit)) {
-            const uint32_t slot = __builtin_ctz(bit);
-            a.pm_key[(uint64_t)r * a.W + slot] = a.keys[i0 + t];
-            a.pm_pair[(uint64_t)r * a.W + slot] = a.rpair[i0 + t];
-            done = true;
-          }
-        }
-        if (!done) set_err(a.ctl, kErrOverflow);
+        if (!pm_claim(a.pm_mask, a.pm_key, a.pm_pair, rowsel[t], a.W, a.keys[i0 + t], a.rpair[i0 + t]))
+          set_err(a.ctl, kErrOverflow);
       }
       ++io;
     }
@@ -537,12 +799,9 @@ __global__ __launch_bounds__(kRemapNT) void k_acc_remap(RemapArgs a) {
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    a.ctl->ring_head = head + nplace;
-    a.ctl->n_place = nplace;
-    a.ctl->batch_delta = (int64_t)nins - (int64_t)ndel;
-    const uint64_t live = a.ctl->live + nins - ndel;
-    a.ctl->live = live;
-    if (live > a.cap) set_err(a.ctl, kErrFull);
+    a.ctl->b_place = nplace;
+    a.ctl->b_ins = nins;
+    a.ctl->b_del = ndel;
   }
 }
 
@@ -553,11 +812,11 @@ __global__ __launch_bounds__(kRemapNT) void k_acc_remap(RemapArgs a) {
 struct WbArgs {
   Ctl* ctl;
   uint32_t q, epoch, Z, vw;
-  uint64_t K, P, pw;
+  uint64_t K, pw;
   const uint32_t* cand_bin;
   const uint64_t* claim;
   uint64_t* rmask;
-  uint64_t* stage;
+  const uint64_t* stage;
   uint64_t* obs;
   uint64_t* hbm;
   uint32_t* rev_cnt;
@@ -565,94 +824,80 @@ struct WbArgs {
   const uint64_t* st_key;
   const uint64_t* st_val;
   uint32_t* st_dead;
-  uint32_t* ring;
+  uint64_t* st_used;
+  uint32_t* freed;   // [kFreeBuckets] entries freed, summed by finish
   uint32_t* tlog_w;  // [3q] or null
 };
 
 constexpr uint32_t kWbItems = 192;  // Z survivors + 2Z listed stash entries, Z <= 62
+constexpr uint32_t kFreeBuckets = 256;
 
-__global__ __launch_bounds__(256) void k_acc_writeback(WbArgs a) {
-  __shared__ uint64_t ikey[4][kWbItems];
-  __shared__ uint32_t isrc[4][kWbItems];
-  __shared__ uint32_t by_rank[4][64];
-  const uint32_t lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  const uint32_t s = blockIdx.x * 4 + wid;
-  bool active = s < 3 * a.q && !a.ctl->reject && !a.ctl->err;
-  uint32_t b = kNone;
-  if (active) {
-    b = a.cand_bin[s];
-    active = b != kNone && a.claim[b] == claim_tag(a.epoch, s);
+// Dynamic LDS of one write-back wave: the old page, then the item lists.
+__host__ __device__ constexpr uint64_t wb_lds_bytes(uint64_t pw) { return pw * 8 + kWbItems * 12 + 64 * 4; }
+
+// One wave (one workgroup) per candidate slot.  The elected writer copies
+// the bin's old page into LDS (observable pages from the stage the fetch
+// wrote, HBM bins from HBM), so the rebuilt page can be written in place
+// without any device-wide fence.
+__global__ __launch_bounds__(64) void k_acc_writeback(WbArgs a) {
+  extern __shared__ uint64_t dyn[];
+  uint64_t* old = dyn;
+  uint64_t* ikey = dyn + a.pw;
+  uint32_t* isrc = reinterpret_cast<uint32_t*>(ikey + kWbItems);
+  uint32_t* by_rank = isrc + kWbItems;
+  const uint32_t lane = threadIdx.x;
+  const uint32_t s = blockIdx.x;
+  if (s >= 3 * a.q || a.ctl->reject == a.epoch || a.ctl->err) return;  // whole block
+  const uint32_t b = a.cand_bin[s];
+  if (b == kNone || a.claim[b] != claim_tag(a.epoch, s)) return;  // whole block
+  const bool host = b >= a.K;
+  const uint64_t* src = host ? a.stage + (uint64_t)s * a.pw : a.hbm + (uint64_t)b * a.pw;
+  for (uint64_t w = lane; w < a.pw; w += 64) old[w] = src[w];
+  const uint64_t rm = a.rmask[b];
+  const uint32_t cnt = a.rev_cnt[b] < 2 * a.Z ? a.rev_cnt[b] : 2 * a.Z;
+  __syncthreads();
+  const uint64_t keep = old[0] & ~rm;
+  // survivors, in slot order
+  if (lane < a.Z && ((keep >> lane) & 1)) {
+    const uint32_t pos = __popcll(keep & ((1ull << lane) - 1));
+    ikey[pos] = old[1 + lane];
+    isrc[pos] = lane;  // page slot
   }
-  const bool host = active && b >= a.K;
-  uint64_t* stg = a.stage + (uint64_t)s * a.pw;
-  // HBM bins are rebuilt in place: copy the old bin to this slot's stage first
-  if (active && !host) {
-    for (uint64_t w = lane; w < a.pw; w += 64) stg[w] = a.hbm[(uint64_t)b * a.pw + w];
-    __threadfence();
+  const uint32_t n_surv = __popcll(keep);
+  // every entry listed under the bin: live ones move in, all are freed
+  uint32_t n_alive = 0;
+  for (uint32_t base = 0; base < cnt; base += 64) {
+    const uint32_t l = base + lane;
+    uint32_t e = kNone;
+    bool alive = false;
+    if (l < cnt) {
+      e = a.rev_idx[(uint64_t)b * 2 * a.Z + l];
+      alive = !a.st_dead[e];
+    }
+    const uint64_t bal = __ballot(alive);
+    if (alive) {
+      const uint32_t pos = n_surv + n_alive + __popcll(bal & ((1ull << lane) - 1));
+      if (pos < kWbItems) {
+        ikey[pos] = a.st_key[e];
+        isrc[pos] = 0x80000000u | e;
+      }
+    }
+    n_alive += __popcll(bal);
   }
-  uint32_t n_items = 0;
-  uint32_t n_surv = 0;
-  if (active) {
-    const uint64_t mask = ld_acq64(&stg[0]);
-    const uint64_t rm = a.rmask[b];
-    const uint64_t keep = mask & ~rm;
-    // survivors, in slot order
-    if (lane < a.Z) {
-      const bool k = (keep >> lane) & 1;
-      const uint64_t kk = ld_acq64(&stg[1 + lane]);
-      const uint32_t pos = __popcll(keep & ((1ull << lane) - 1));
-      if (k) {
-        ikey[wid][pos] = kk;
-        isrc[wid][pos] = lane;  // page slot
-      }
-    }
-    n_surv = __popcll(keep);
-    // every entry listed under the bin: live ones move in, all are freed
-    const uint32_t cnt = a.rev_cnt[b] < 2 * a.Z ? a.rev_cnt[b] : 2 * a.Z;
-    uint64_t ring_base = 0;
-    if (lane == 0 && cnt) ring_base = atomicAdd((unsigned long long*)&a.ctl->ring_tail, (unsigned long long)cnt);
-    ring_base = __shfl(ring_base, 0, 64);
-    uint32_t n_alive = 0;
-    for (uint32_t base = 0; base < cnt; base += 64) {
-      const uint32_t l = base + lane;
-      uint32_t e = kNone;
-      bool alive = false;
-      if (l < cnt) {
-        e = a.rev_idx[(uint64_t)b * 2 * a.Z + l];
-        alive = !a.st_dead[e];
-      }
-      const uint64_t bal = __ballot(alive);
-      if (alive) {
-        const uint32_t pos = n_surv + n_alive + __popcll(bal & ((1ull << lane) - 1));
-        if (pos < kWbItems) {
-          ikey[wid][pos] = a.st_key[e];
-          isrc[wid][pos] = 0x80000000u | e;
-        }
-      }
-      n_alive += __popcll(bal);
-      if (l < cnt) {
-        a.st_dead[e] = 0;
-        a.ring[(ring_base + l) % a.P] = e;
-      }
-    }
-    n_items = n_surv + n_alive;
-    if (lane == 0) {
-      a.rmask[b] = 0;
-      a.rev_cnt[b] = 0;
-      if (n_items > a.Z) set_err(a.ctl, kErrOverflow);
-    }
+  const uint32_t n_items = n_surv + n_alive;
+  if (n_items > a.Z) {  // the load bound was broken: report, write nothing
+    if (lane == 0) set_err(a.ctl, kErrOverflow);
+    return;
   }
   __syncthreads();
-  const bool go = active && n_items <= a.Z;  // wave-uniform; every wave reaches both barriers
   // canonical order: ascending key
-  if (go && lane < n_items) {
-    const uint64_t mine = ikey[wid][lane];
+  if (lane < n_items) {
+    const uint64_t mine = ikey[lane];
     uint32_t rank = 0;
-    for (uint32_t j = 0; j < n_items; ++j) rank += ikey[wid][j] < mine || (ikey[wid][j] == mine && j < lane);
-    by_rank[wid][rank] = lane;
+    for (uint32_t j = 0; j < n_items; ++j) rank += ikey[j] < mine || (ikey[j] == mine && j < lane);
+    by_rank[rank] = lane;
   }
   __syncthreads();
-  if (!go) return;
   uint64_t* dst = host ? a.obs + (uint64_t)(b - a.K) * a.pw : a.hbm + (uint64_t)b * a.pw;
   for (uint64_t w = lane; w < a.pw; w += 64) {
     uint64_t v = 0;
@@ -660,30 +905,82 @@ __global__ __launch_bounds__(256) void k_acc_writeback(WbArgs a) {
       v = n_items >= 64 ? kNone64 : ((1ull << n_items) - 1);
     } else if (w <= a.Z) {
       const uint32_t j = (uint32_t)w - 1;
-      v = j < n_items ? ikey[wid][by_rank[wid][j]] : 0;
+      v = j < n_items ? ikey[by_rank[j]] : 0;
     } else if (w < 1 + a.Z + (uint64_t)a.Z * a.vw) {
       const uint64_t off = w - 1 - a.Z;
       const uint32_t j = (uint32_t)(off / a.vw), o = (uint32_t)(off % a.vw);
       if (j < n_items) {
-        const uint32_t src = isrc[wid][by_rank[wid][j]];
-        if (src & 0x80000000u)
-          v = a.st_val[(uint64_t)(src & 0x7FFFFFFFu) * a.vw + o];
-        else
-          v = ld_acq64(&stg[1 + a.Z + (uint64_t)src * a.vw + o]);
+        const uint32_t from = isrc[by_rank[j]];
+        v = (from & 0x80000000u) ? a.st_val[(uint64_t)(from & 0x7FFFFFFFu) * a.vw + o]
+                                 : old[1 + a.Z + (uint64_t)from * a.vw + o];
       }
     }
     dst[w] = v;
   }
-  if (host && lane == 0 && a.tlog_w) a.tlog_w[s] = (uint32_t)(b - a.K);
+  // free every listed entry (its value was read above)
+  for (uint32_t l = lane; l < cnt; l += 64) {
+    const uint32_t e = a.rev_idx[(uint64_t)b * 2 * a.Z + l];
+    a.st_dead[e] = 0;
+    pool_free(a.st_used, e);
+  }
+  if (lane == 0) {
+    a.rmask[b] = 0;
+    a.rev_cnt[b] = 0;
+    if (cnt) atomicAdd(&a.freed[s % kFreeBuckets], cnt);
+    if (host && a.tlog_w) a.tlog_w[s] = (uint32_t)(b - a.K);
+  }
 }
 
-__global__ void k_acc_finish(Ctl* ctl, uint32_t q, uint64_t P, uint64_t stash_bound) {
-  if (threadIdx.x || blockIdx.x) return;
-  if (ctl->reject) return;
-  ctl->steps += q;
-  const uint64_t live_stash = P - (ctl->ring_tail - ctl->ring_head);
-  if (live_stash > ctl->stash_hw) ctl->stash_hw = live_stash;
-  if (live_stash > stash_bound) ctl->err |= kErrOverflow;
+// ---------------------------------------------------------------------------
+// finish: position-map inserts of the one-round case, then the counters
+// ---------------------------------------------------------------------------
+
+struct FinishArgs {
+  Ctl* ctl;
+  uint32_t q, W, epoch;
+  uint64_t cap, stash_bound;
+  const uint32_t* rowsel;
+  const uint64_t* keys;
+  const uint2* rpair;
+  uint32_t* freed;
+  uint64_t* pm_key;
+  uint2* pm_pair;
+  uint32_t* pm_mask;
+};
+
+__global__ __launch_bounds__(256) void k_acc_finish(FinishArgs a) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (a.ctl->reject == a.epoch) return;
+  const bool ok = !a.ctl->err;
+  if (ok && i < a.q && a.rowsel && a.rowsel[i] != kNone) {
+    if (!pm_claim(a.pm_mask, a.pm_key, a.pm_pair, a.rowsel[i], a.W, a.keys[i], a.rpair[i]))
+      set_err(a.ctl, kErrOverflow);
+  }
+  if (blockIdx.x != 0) return;
+  __shared__ uint32_t part[kFreeBuckets];
+  part[threadIdx.x] = a.freed[threadIdx.x];
+  a.freed[threadIdx.x] = 0;  // ready for the next batch
+  __syncthreads();
+  for (uint32_t h = kFreeBuckets / 2; h > 0; h >>= 1) {
+    if (threadIdx.x < h) part[threadIdx.x] += part[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    Ctl* c = a.ctl;
+    if (ok) {
+      c->steps += a.q;
+      const uint64_t st = c->stash_live + c->b_place - part[0];
+      c->stash_live = st;
+      if (st > c->stash_hw) c->stash_hw = st;
+      if (st > a.stash_bound) c->err |= kErrOverflow;
+      const uint64_t live = c->live + c->b_ins - c->b_del;
+      c->live = live;
+      if (live > a.cap) c->err |= kErrFull;
+    }
+    c->b_place = 0;
+    c->b_ins = 0;
+    c->b_del = 0;
+  }
 }
 
 // Fill of the trace segment of a batch (no memset nodes in captured graphs).
@@ -699,6 +996,7 @@ int run_access(bolt_map* m, const uint8_t* ops, const uint64_t* keys, const void
   const Sizes& s = m->s;
   const BatchScratch& bs = m->bs;
   const uint32_t epoch = (uint32_t)(m->batches + 1);
+  const bool fast = q <= (s.B + 15) / 16 && q <= (s.R + 15) / 16;
   uint32_t* tlog_r = nullptr;
   uint32_t* tlog_w = nullptr;
   if (m->tlog) {
@@ -716,7 +1014,9 @@ int run_access(bolt_map* m, const uint8_t* ops, const uint64_t* keys, const void
   }
   {
     TimedScope ts(m->timer, kkAccDedup, st);
-    hipLaunchKernelGGL(k_acc_dedup, dim3(1), dim3(kDedupNT), 0, st, ops, keys, q, m->ctl, bs.leader, bs.prevw, bs.lastw);
+    hipLaunchKernelGGL(k_acc_part, dim3(1), dim3(1024), 0, st, ops, keys, q, epoch, m->ctl, bs.pofs, bs.pkey, bs.pidx);
+    hipLaunchKernelGGL(k_acc_group, dim3(kParts), dim3(kDedupNT), 0, st, ops, epoch, m->ctl, bs.pofs, bs.pkey, bs.pidx,
+                       bs.leader, bs.prevw, bs.lastw);
   }
 
   FetchArgs fa;
@@ -762,56 +1062,111 @@ int run_access(bolt_map* m, const uint8_t* ops, const uint64_t* keys, const void
     hipLaunchKernelGGL(k_acc_fetch, dim3((q + 3) / 4), dim3(256), 0, st, fa);
   }
 
+  ResolveArgs rv;
+  rv.ctl = m->ctl;
+  rv.ops = ops;
+  rv.vals_in = reinterpret_cast<const uint64_t*>(vals_in);
+  rv.leader = bs.leader;
+  rv.prevw = bs.prevw;
+  rv.lastw = bs.lastw;
+  rv.hit = bs.hit;
+  rv.hrow = bs.hrow;
+  rv.hslot = bs.hslot;
+  rv.found = bs.found;
+  rv.fval = reinterpret_cast<const uint64_t*>(bs.fval);
+  rv.rpair = bs.rpair;
+  rv.load = m->load;
+  rv.q = q;
+  rv.vw = s.vs / 8;
+  rv.fast = fast ? 1 : 0;
+  rv.epoch = epoch;
+  rv.vals_out = reinterpret_cast<uint64_t*>(vals_out);
+  rv.status = status;
+  rv.fin = bs.fin;
+  rv.chosen = bs.chosen;
+  rv.pm_mask = m->pm_mask;
   {
     TimedScope ts(m->timer, kkAccResolve, st);
-    hipLaunchKernelGGL(k_acc_resolve, dim3((q + 255) / 256), dim3(256), 0, st, m->ctl, ops,
-                       reinterpret_cast<const uint64_t*>(vals_in), bs.leader, bs.prevw, bs.found,
-                       reinterpret_cast<const uint64_t*>(bs.fval), q, s.vs / 8, reinterpret_cast<uint64_t*>(vals_out),
-                       status);
+    hipLaunchKernelGGL(k_acc_resolve, dim3((q + 255) / 256), dim3(256), 0, st, rv);
   }
 
-  RemapArgs ra;
-  ra.ctl = m->ctl;
-  ra.ops = ops;
-  ra.keys = keys;
-  ra.vals_in = reinterpret_cast<const uint64_t*>(vals_in);
-  ra.leader = bs.leader;
-  ra.lastw = bs.lastw;
-  ra.hit = bs.hit;
-  ra.hrow = bs.hrow;
-  ra.hslot = bs.hslot;
-  ra.found = bs.found;
-  ra.fval = reinterpret_cast<const uint64_t*>(bs.fval);
-  ra.rpair = bs.rpair;
-  ra.q = q;
-  ra.epoch = epoch;
-  ra.Z = (uint32_t)s.Z;
-  ra.W = (uint32_t)s.W;
-  ra.d = (uint32_t)s.d;
-  ra.vw = s.vs / 8;
-  ra.B = s.B;
-  ra.K = s.K;
-  ra.R = s.R;
-  ra.P = s.P;
-  ra.cap = s.cap;
-  ra.load = m->load;
-  ra.st_key = m->st_key;
-  ra.st_val = reinterpret_cast<uint64_t*>(m->st_val);
-  ra.st_dest = m->st_dest;
-  ra.st_dead = m->st_dead;
-  ra.ring = m->ring;
-  ra.rev_cnt = m->rev_cnt;
-  ra.rev_idx = m->rev_idx;
-  ra.claim = m->claim;
-  ra.cand_bin = bs.cand_bin;
-  ra.pm_key = m->pm_key;
-  ra.pm_pair = m->pm_pair;
-  ra.pm_mask = m->pm_mask;
-  {
+  if (fast) {
+    PlaceArgs pa;
+    pa.ctl = m->ctl;
+    pa.keys = keys;
+    pa.vals_in = reinterpret_cast<const uint64_t*>(vals_in);
+    pa.leader = bs.leader;
+    pa.lastw = bs.lastw;
+    pa.fin = bs.fin;
+    pa.chosen = bs.chosen;
+    pa.hrow = bs.hrow;
+    pa.hslot = bs.hslot;
+    pa.fval = reinterpret_cast<const uint64_t*>(bs.fval);
+    pa.rpair = bs.rpair;
+    pa.q = q;
+    pa.epoch = epoch;
+    pa.Z = (uint32_t)s.Z;
+    pa.W = (uint32_t)s.W;
+    pa.d = (uint32_t)s.d;
+    pa.vw = s.vs / 8;
+    pa.K = s.K;
+    pa.R = s.R;
+    pa.PW = s.PW;
+    pa.load = m->load;
+    pa.st_used = m->st_used;
+    pa.st_key = m->st_key;
+    pa.st_val = reinterpret_cast<uint64_t*>(m->st_val);
+    pa.st_dest = m->st_dest;
+    pa.st_dead = m->st_dead;
+    pa.rev_cnt = m->rev_cnt;
+    pa.rev_idx = m->rev_idx;
+    pa.claim = m->claim;
+    pa.cand_bin = bs.cand_bin;
+    pa.pm_pair = m->pm_pair;
+    pa.pm_mask = m->pm_mask;
+    pa.rowsel = bs.rowsel;
+    TimedScope ts(m->timer, kkAccRemap, st);
+    hipLaunchKernelGGL(k_acc_place, dim3((q + 255) / 256), dim3(256), 0, st, pa);
+  } else {
+    RemapArgs ra;
+    ra.ctl = m->ctl;
+    ra.keys = keys;
+    ra.vals_in = reinterpret_cast<const uint64_t*>(vals_in);
+    ra.leader = bs.leader;
+    ra.lastw = bs.lastw;
+    ra.fin = bs.fin;
+    ra.hrow = bs.hrow;
+    ra.hslot = bs.hslot;
+    ra.fval = reinterpret_cast<const uint64_t*>(bs.fval);
+    ra.rpair = bs.rpair;
+    ra.q = q;
+    ra.epoch = epoch;
+    ra.Z = (uint32_t)s.Z;
+    ra.W = (uint32_t)s.W;
+    ra.d = (uint32_t)s.d;
+    ra.vw = s.vs / 8;
+    ra.B = s.B;
+    ra.K = s.K;
+    ra.R = s.R;
+    ra.PW = s.PW;
+    ra.load = m->load;
+    ra.st_used = m->st_used;
+    ra.st_key = m->st_key;
+    ra.st_val = reinterpret_cast<uint64_t*>(m->st_val);
+    ra.st_dest = m->st_dest;
+    ra.st_dead = m->st_dead;
+    ra.rev_cnt = m->rev_cnt;
+    ra.rev_idx = m->rev_idx;
+    ra.claim = m->claim;
+    ra.cand_bin = bs.cand_bin;
+    ra.pm_key = m->pm_key;
+    ra.pm_pair = m->pm_pair;
+    ra.pm_mask = m->pm_mask;
     TimedScope ts(m->timer, kkAccRemap, st);
     hipLaunchKernelGGL(k_acc_remap, dim3(1), dim3(kRemapNT), 0, st, ra);
   }
 
+  const uint32_t wb_blocks = 3 * q;
   WbArgs wa;
   wa.ctl = m->ctl;
   wa.q = q;
@@ -819,12 +1174,11 @@ int run_access(bolt_map* m, const uint8_t* ops, const uint64_t* keys, const void
   wa.Z = (uint32_t)s.Z;
   wa.vw = s.vs / 8;
   wa.K = s.K;
-  wa.P = s.P;
   wa.pw = s.page_bytes / 8;
   wa.cand_bin = bs.cand_bin;
   wa.claim = m->claim;
   wa.rmask = m->rmask;
-  wa.stage = reinterpret_cast<uint64_t*>(bs.stage);
+  wa.stage = reinterpret_cast<const uint64_t*>(bs.stage);
   wa.obs = reinterpret_cast<uint64_t*>(m->obs);
   wa.hbm = reinterpret_cast<uint64_t*>(m->hbm);
   wa.rev_cnt = m->rev_cnt;
@@ -832,16 +1186,31 @@ int run_access(bolt_map* m, const uint8_t* ops, const uint64_t* keys, const void
   wa.st_key = m->st_key;
   wa.st_val = reinterpret_cast<const uint64_t*>(m->st_val);
   wa.st_dead = m->st_dead;
-  wa.ring = m->ring;
+  wa.st_used = m->st_used;
+  wa.freed = bs.freed;
   wa.tlog_w = tlog_w;
   {
     TimedScope ts(m->timer, kkAccWriteback, st);
-    hipLaunchKernelGGL(k_acc_writeback, dim3((3 * q + 3) / 4), dim3(256), 0, st, wa);
+    hipLaunchKernelGGL(k_acc_writeback, dim3(wb_blocks), dim3(64), wb_lds_bytes(s.page_bytes / 8), st, wa);
   }
 
+  FinishArgs fn;
+  fn.ctl = m->ctl;
+  fn.q = q;
+  fn.W = (uint32_t)s.W;
+  fn.epoch = epoch;
+  fn.cap = s.cap;
+  fn.stash_bound = s.stash_bound;
+  fn.rowsel = fast ? bs.rowsel : nullptr;
+  fn.keys = keys;
+  fn.rpair = bs.rpair;
+  fn.freed = bs.freed;
+  fn.pm_key = m->pm_key;
+  fn.pm_pair = m->pm_pair;
+  fn.pm_mask = m->pm_mask;
   {
     TimedScope ts(m->timer, kkAccMisc, st);
-    hipLaunchKernelGGL(k_acc_finish, dim3(1), dim3(64), 0, st, m->ctl, q, s.P, s.stash_bound);
+    hipLaunchKernelGGL(k_acc_finish, dim3((q + 255) / 256), dim3(256), 0, st, fn);
   }
   m->batches++;
   return hipGetLastError() == hipSuccess ? BOLT_OK : BOLT_EHIP;

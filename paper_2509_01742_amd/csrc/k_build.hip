@@ -112,22 +112,27 @@ static void launch_excl_scan(const uint32_t* in, uint64_t n, uint32_t* bsum, uin
 // map init
 // ---------------------------------------------------------------------------
 
-__global__ void k_ring_init(uint32_t* ring, uint64_t P) {
-  uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < P) ring[i] = (uint32_t)i;
+// Pool bitmap: every entry free, the bits past the pool size set.
+__global__ void k_pool_init(uint64_t* used, uint64_t P, uint64_t PW) {
+  uint64_t w = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (w >= PW) return;
+  const uint64_t lo = w * 64;
+  uint64_t v = 0;
+  if (lo + 64 > P) v = ~0ull << (P - lo);  // P - lo in [1, 63] for the last word
+  used[w] = v;
 }
 
-__global__ void k_ctl_init(Ctl* ctl, uint64_t P) {
+__global__ void k_ctl_init(Ctl* ctl) {
   if (threadIdx.x || blockIdx.x) return;
   ctl->err = 0;
   ctl->reject = 0;
   ctl->steps = 0;
   ctl->live = 0;
-  ctl->ring_head = 0;
-  ctl->ring_tail = P;
+  ctl->stash_live = 0;
   ctl->stash_hw = 0;
-  ctl->batch_delta = 0;
-  ctl->n_place = 0;
+  ctl->b_place = 0;
+  ctl->b_ins = 0;
+  ctl->b_del = 0;
 }
 
 void launch_map_init(bolt_map* m, hipStream_t st) {
@@ -138,8 +143,8 @@ void launch_map_init(bolt_map* m, hipStream_t st) {
   (void)hipMemsetAsync(m->claim, 0, s.B * sizeof(uint64_t), st);
   (void)hipMemsetAsync(m->rmask, 0, s.B * sizeof(uint64_t), st);
   (void)hipMemsetAsync(m->st_dead, 0, s.P * sizeof(uint32_t), st);
-  hipLaunchKernelGGL(k_ring_init, dim3((uint32_t)((s.P + 255) / 256)), dim3(256), 0, st, m->ring, s.P);
-  hipLaunchKernelGGL(k_ctl_init, dim3(1), dim3(64), 0, st, m->ctl, s.P);
+  hipLaunchKernelGGL(k_pool_init, dim3((uint32_t)((s.PW + 255) / 256)), dim3(256), 0, st, m->st_used, s.P, s.PW);
+  hipLaunchKernelGGL(k_ctl_init, dim3(1), dim3(64), 0, st, m->ctl);
   launch_prf_key_setup(m->ctl, m->p.key, st);
 }
 
@@ -322,32 +327,23 @@ __global__ void k_pm_masks(const uint32_t* __restrict__ rowcnt, uint64_t R, uint
   mask[r] = c >= 32 ? 0xFFFFFFFFu : ((1u << c) - 1);
 }
 
-// A key found more than once among its rows was given twice.
-__global__ void k_pm_dupcheck(const Ctl* ctl, const uint64_t* __restrict__ keys, uint64_t n, uint64_t R, uint32_t d,
-                              uint32_t W, const uint32_t* __restrict__ mask, const uint64_t* __restrict__ pm_key,
-                              Ctl* ctlw) {
-  uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  uint32_t hk[8];
-#pragma unroll
-  for (int j = 0; j < 8; ++j) hk[j] = ctl->hkey[j];
-  uint64_t key = keys[i];
-  uint32_t rows[4];
-  pm_rows_of(hk, key, R, d, rows);
-  uint32_t hits = 0;
-  for (uint32_t j = 0; j < d; ++j) {
-    bool seen = false;
-    for (uint32_t jj = 0; jj < j; ++jj) seen |= rows[jj] == rows[j];
-    if (seen) continue;
-    uint32_t mk = mask[rows[j]];
-    const uint64_t* rk = pm_key + (uint64_t)rows[j] * W;
-    while (mk) {
-      uint32_t s = __builtin_ctz(mk);
-      mk &= mk - 1;
-      hits += rk[s] == key;
-    }
-  }
-  if (hits > 1) set_err(ctlw, kErrDup);
+// Duplicate check: the keys, sorted by the same network, are distinct iff no
+// two neighbours are equal.  Padding uses the largest key, so real copies of
+// that key are counted apart.
+__global__ void k_dup_fill(const uint64_t* __restrict__ keys, uint64_t n, uint64_t npad, uint64_t* __restrict__ tag,
+                           uint32_t* n_max) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= npad) return;
+  const uint64_t k = i < n ? keys[i] : kNone64;
+  tag[i] = k;
+  if (i < n && k == kNone64) atomicAdd(n_max, 1u);
+}
+
+__global__ void k_dup_adjacent(const uint64_t* __restrict__ tag, uint64_t npad, const uint32_t* n_max, Ctl* ctl) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool dup = i + 1 < npad && tag[i] == tag[i + 1] && tag[i] != kNone64;
+  if (__any(dup) && (threadIdx.x & 63) == 0) set_err(ctl, kErrDup);
+  if (i == 0 && *n_max > 1) set_err(ctl, kErrDup);
 }
 
 __global__ void k_build_finish(Ctl* ctl, uint64_t n) {
@@ -466,10 +462,16 @@ int run_build(bolt_map* m, const uint64_t* keys, const void* vals, uint64_t n, h
     TimedScope ts(m->timer, kkPmBuild, st);
     hipLaunchKernelGGL(k_pm_masks, dim3(blocks_for(s.R, NT)), dim3(NT), 0, st, b.rowcnt, s.R, (uint32_t)s.W, m->pm_mask);
   }
+  // duplicate keys (the tag buffer is free after the write-out)
   if (n) {
+    (void)hipMemsetAsync(b.bsum + nbs, 0, sizeof(uint32_t), st);
+    {
+      TimedScope ts(m->timer, kkDupcheck, st);
+      hipLaunchKernelGGL(k_dup_fill, dim3(blocks_for(npad, NT)), dim3(NT), 0, st, keys, n, npad, b.tag, b.bsum + nbs);
+    }
+    launch_bitonic_sort(b.tag, npad, st, m->timer);
     TimedScope ts(m->timer, kkDupcheck, st);
-    hipLaunchKernelGGL(k_pm_dupcheck, dim3(blocks_for(n, NT)), dim3(NT), 0, st, m->ctl, keys, n, s.R, (uint32_t)s.d,
-                       (uint32_t)s.W, m->pm_mask, m->pm_key, m->ctl);
+    hipLaunchKernelGGL(k_dup_adjacent, dim3(blocks_for(npad, NT)), dim3(NT), 0, st, b.tag, npad, b.bsum + nbs, m->ctl);
   }
   {
     TimedScope ts(m->timer, kkBuildMisc, st);

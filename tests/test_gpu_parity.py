@@ -167,6 +167,9 @@ def _mixed_batch(rng, present, fresh, q, vs, hot=5, p=(0.5, 0.35, 0.15)):
     (1 << 15, 30000, 8, {}, 4096, 12),
     (1 << 12, 4000, 8, dict(alpha_permille=500), 8192, 4),
     (512, 0, 8, {}, 64, 30),
+    # one-round batches (q <= ceil(B/16) and q <= ceil(R/16)): the thread-per-command remap
+    (1 << 20, (1 << 20) - 100, 16, {}, 4096, 8),
+    (1 << 20, 1 << 19, 8, dict(alpha_permille=0), 3000, 6),
 ])
 def test_access_parity(cap, n, vs, kw, qmax, nb):
     t = Twin(cap, vs, **kw)
