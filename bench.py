@@ -6,10 +6,14 @@ with 5 % absent keys, 90 % GET / 10 % PUT).  A step is one pass of the whole
 path: the oblivious build of the N pairs, then every batch of the stream.
 Inputs sit in HBM before the timed region starts.
 
-Prints one JSON line: ops/s of the batched get/put (value), build keys/s,
-p50/p99 batch latency, the plain per-call form (one command per call), the
-roofline of the dominant kernel from HIP events on its launch stream, and a
-CPU baseline (the oracle, single-threaded) on a bounded sample.
+The observable store is pinned host memory reached over the host link (the
+paper's setting: the store lives off the package); the same workload is also
+run with the store in a designated device buffer and reported beside it.
+
+The timed region runs without per-kernel events (they cost about a third of
+a batch).  One further step of the same workload on a map created with
+BOLT_F_TIMING records HIP events on the launch stream around every kernel;
+kernel durations, algorithmic GB/s and the roofline come from that step.
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--observable host|device]
 """
@@ -24,30 +28,161 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-HBM_PEAK_GBS = 8000.0      # MI355X HBM3E
-LINK_PEAK_GBS = 64.0       # PCIe Gen5 x16, per direction
+HBM_PEAK_GBS = 8000.0   # MI355X HBM3E
+LINK_PEAK_GBS = 64.0    # PCIe 5.0 x16, per direction
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def algorithmic_bytes(cls, launches, sz, n, npad, q_total, host_roles, vs):
-    """Bytes one launch of a kernel class must move (reads + writes), summed
-    over the launches measured.  Per-unit figures are stated in the design
-    notes; the caller passes counts for the timed region."""
-    pb, B, Z, K, M = sz["page_bytes"], sz["B"], sz["Z"], sz["K"], sz["M"]
+def kernel_bytes(cls, sz, n, npad, n_ops, host_roles):
+    """Algorithmic bytes of ONE launch of a kernel class on the resource that
+    bounds it.
+
+    sort passes (HBM): read + write every 8-byte tag, 16 B x npad.
+    expansion passes (HBM): read + write every 8-byte slot, 16 B x B*Z.
+    page write-out: the M observable pages written once (host link in host
+      mode); in device mode also the K HBM bins, the N keys + values and the
+      B*Z slots read (HBM).
+    fetch, per batch: the observable pages read, about 2 (1 - alpha) per
+      command (host link); in device mode both whole bins of every command.
+    write-back, per batch: every observable page read is written once (host
+      link); in device mode it is also read back from the stage.
+    """
+    pb, B, Z, K, M, vs = sz["page_bytes"], sz["B"], sz["Z"], sz["K"], sz["M"], sz["vs"]
+    host = sz["host"]
     if cls in ("sort_global", "sort_tile", "sort_merge"):
-        return 16 * npad * launches, "hbm"              # read + write every 8-byte tag
+        return 16 * npad, "hbm"
     if cls == "expand":
-        return 16 * B * Z * launches, "hbm"             # read + write every 8-byte slot per stage
+        return 16 * B * Z, "hbm"
     if cls == "page_writeout":
-        return (B * pb + n * (8 + vs) + B * Z * 8) * launches, "hbm+link"
+        if host:
+            return M * pb, "host_link"
+        return B * pb + n * (8 + vs) + B * Z * 8, "hbm"
     if cls == "acc_fetch":
-        return 2 * q_total * pb, "hbm+link"            # two whole bins per command
+        return (host_roles * pb, "host_link") if host else (2 * n_ops * pb, "hbm")
     if cls == "acc_writeback":
-        return host_roles * pb, "hbm+link"
+        return (host_roles * pb, "host_link") if host else (2 * host_roles * pb, "hbm")
     return None, None
+
+
+def run_mode(args, wl, dev_t, B, torch, observable):
+    n, vs = wl.n, wl.vs
+    d_keys, d_vals, d_ops, d_qk, d_qv, d_out, d_st, bounds = dev_t
+    obs = B.BOLT_OBS_HOST_PINNED if observable == "host" else B.BOLT_OBS_DEVICE
+    p = B.params(wl.cap, vs, observable=obs)
+    sz = B.sizes_of(p)
+    sz["vs"] = vs
+    sz["host"] = observable == "host"
+    stream = torch.cuda.current_stream()
+    nsteps = args.warmup + args.steps
+    t0 = time.time()
+    maps = [B.Map(p) for _ in range(nsteps)]
+    pt = B.params(wl.cap, vs, observable=obs)
+    pt.flags |= B.BOLT_F_TIMING
+    tmap = B.Map(pt)
+    torch.cuda.synchronize()
+    log("[%s] created %d maps (%.1fs); footprint hbm=%.2f GiB obs=%.2f GiB" % (
+        observable, nsteps + 1, time.time() - t0, B.footprint(p)[0] / 2**30, B.footprint(p)[1] / 2**30))
+    nb = len(bounds) - 1
+
+    def run_step(m):
+        evs = [torch.cuda.Event(enable_timing=True) for _ in range(nb + 2)]
+        evs[0].record(stream)
+        B.check(m.build(d_keys, d_vals), "bolt_build")
+        evs[1].record(stream)
+        for bi in range(nb):
+            a, b = int(bounds[bi]), int(bounds[bi + 1])
+            B.check(m.access(d_ops[a:b], d_qk[a:b], d_qv[a:b], d_out[a:b], d_st[a:b]), "bolt_access_batch")
+            evs[bi + 2].record(stream)
+        return evs
+
+    for w in range(args.warmup):
+        run_step(maps[w])
+        B.check(maps[w].status(), "warmup status")
+        maps[w].close()
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    step_events = [run_step(maps[args.warmup + s]) for s in range(args.steps)]
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_start
+    build_ms, query_ms, lat = [], [], []
+    for evs in step_events:
+        build_ms.append(evs[0].elapsed_time(evs[1]))
+        query_ms.append(evs[1].elapsed_time(evs[-1]))
+        lat.extend(evs[i].elapsed_time(evs[i + 1]) for i in range(1, len(evs) - 1))
+    for s in range(args.steps):
+        B.check(maps[args.warmup + s].status(), "status")
+    st = maps[-1].stats()
+    log("[%s] step stats: %s" % (observable, st))
+    if not (d_st.cpu().numpy()[d_ops.cpu().numpy() == 0] <= 1).all():
+        raise SystemExit("bad GET status")
+
+    # instrumented step: per-kernel HIP events on the launch stream
+    run_step(tmap)
+    B.check(tmap.status(), "status")
+    times = tmap.kernel_times()
+    tmap.close()
+
+    # plain per-call form: one command per call, on the last map
+    m = maps[-1]
+    kpc = min(args.per_call, int(bounds[-1]))
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(kpc + 1)]
+    ev[0].record(stream)
+    for i in range(kpc):
+        B.check(m.access(d_ops[i:i + 1], d_qk[i:i + 1], d_qv[i:i + 1], d_out[i:i + 1], d_st[i:i + 1]), "per-call")
+        ev[i + 1].record(stream)
+    torch.cuda.synchronize()
+    pc_lat = [ev[i].elapsed_time(ev[i + 1]) for i in range(kpc)]
+    pc_ops = kpc / (ev[0].elapsed_time(ev[-1]) / 1e3)
+    B.check(m.status(), "status")
+    for mm in maps:
+        mm.close()
+
+    K = args.steps
+    n_ops = int(bounds[-1])
+    npad = 1
+    while npad < n:
+        npad <<= 1
+    host_roles = 2 * n_ops * sz["M"] / sz["B"]  # about 2 (1 - alpha) observable pages per command
+    kernels = {}
+    for cls, (cnt, ms) in sorted(times.items(), key=lambda kv: -kv[1][1]):
+        if cnt == 0:
+            continue
+        ent = {"launches": cnt, "total_ms": round(ms, 3), "avg_us": round(1e3 * ms / cnt, 2)}
+        per, bound = kernel_bytes(cls, sz, n, npad, n_ops / nb, host_roles / nb)
+        if per is not None:
+            gbs = per / (ms / cnt / 1e3) / 1e9
+            peak = LINK_PEAK_GBS if bound == "host_link" else HBM_PEAK_GBS
+            ent.update({"bytes_per_launch": int(per), "achieved_GBps": round(gbs, 1), "bound": bound,
+                        "frac_of_peak": round(gbs / peak, 4)})
+        kernels[cls] = ent
+    lat_np = np.array(lat)
+    return {
+        "ops_per_s": n_ops * K / (sum(query_ms) / 1e3),
+        "build_keys_per_s": n * K / (sum(build_ms) / 1e3),
+        "build_ms": float(np.mean(build_ms)),
+        "query_ms": float(np.mean(query_ms)),
+        "ms_per_step": wall * 1e3 / K,
+        "lat_p50": float(np.percentile(lat_np, 50)),
+        "lat_p99": float(np.percentile(lat_np, 99)),
+        "per_call": {"ops_per_s": round(pc_ops, 1), "p50_ms": round(float(np.percentile(pc_lat, 50)), 4),
+                     "p99_ms": round(float(np.percentile(pc_lat, 99)), 4), "calls": kpc},
+        "kernels": kernels,
+        "sizes": sz,
+        "stats": st,
+    }
+
+
+def roofline_of(res, cls):
+    k = res["kernels"].get(cls)
+    if not k or "achieved_GBps" not in k:
+        return None
+    peak = LINK_PEAK_GBS if k["bound"] == "host_link" else HBM_PEAK_GBS
+    return {"bound": k["bound"], "kernel": cls, "achieved": k["achieved_GBps"], "peak": peak, "unit": "GB/s",
+            "frac": round(k["achieved_GBps"] / peak, 4), "traffic": None, "bytes_per_launch": k["bytes_per_launch"],
+            "avg_launch_us": k["avg_us"], "launches": k["launches"]}
 
 
 def main():
@@ -58,18 +193,18 @@ def main():
     ap.add_argument("--n-log2", type=int, default=24)
     ap.add_argument("--ops", type=int, default=1 << 20)
     ap.add_argument("--batch", type=int, default=4096)
-    ap.add_argument("--observable", choices=["host", "device"], default="host")
+    ap.add_argument("--observable", choices=["host", "device"], default="host",
+                    help="store of the headline figures (the other mode is reported beside them)")
+    ap.add_argument("--single-mode", action="store_true", help="do not run the other observable mode")
     ap.add_argument("--per-call", type=int, default=2048)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-batches", type=int, default=512)
-    ap.add_argument("--no-kernel-timing", action="store_true",
-                    help="leave out the per-kernel HIP events (measures their overhead)")
     ap.add_argument("--copy-calib", type=int, default=0,
-                    help="MiB of a plain device copy run before the steps (scales profiler byte counters)")
+                    help="MiB of a plain device copy run first (scales profiler byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build runs the oblivious map on a single MI355X "
-              "(multi-GPU sharding is a design note, not an implemented path); use --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU only: the oblivious map runs on a single MI355X here (sharding across "
+              "GPUs is a design note, not an implemented path); run it with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -83,25 +218,14 @@ def main():
     t0 = time.time()
     wl = synth.config2(n=n, n_ops=args.ops, batch=args.batch)
     log("workload %s: n=%d ops=%d batches=%d (%.1fs)" % (wl.name, wl.n, wl.n_ops, len(wl.batches), time.time() - t0))
-    vs = wl.vs
-    d_keys = torch.from_numpy(wl.build_keys.view(np.int64)).to(dev)
-    d_vals = torch.from_numpy(wl.build_vals).to(dev)
     ops_all = np.concatenate([b[0] for b in wl.batches])
     keys_all = np.concatenate([b[1] for b in wl.batches])
     vals_all = np.concatenate([b[2] for b in wl.batches])
-    d_ops = torch.from_numpy(ops_all).to(dev)
-    d_qk = torch.from_numpy(keys_all.view(np.int64)).to(dev)
-    d_qv = torch.from_numpy(vals_all).to(dev)
-    d_out = torch.zeros((ops_all.size, vs), dtype=torch.uint8, device=dev)
-    d_st = torch.zeros(ops_all.size, dtype=torch.uint8, device=dev)
-    bounds = np.cumsum([0] + [b[0].size for b in wl.batches])
-    obs = B.BOLT_OBS_HOST_PINNED if args.observable == "host" else B.BOLT_OBS_DEVICE
-    p = B.params(wl.cap, vs, observable=obs)
-    if not args.no_kernel_timing:
-        p.flags |= B.BOLT_F_TIMING
-    sz = B.sizes_of(p)
-    stream = torch.cuda.current_stream()
-
+    dev_t = (torch.from_numpy(wl.build_keys.view(np.int64)).to(dev), torch.from_numpy(wl.build_vals).to(dev),
+             torch.from_numpy(ops_all).to(dev), torch.from_numpy(keys_all.view(np.int64)).to(dev),
+             torch.from_numpy(vals_all).to(dev), torch.zeros((ops_all.size, wl.vs), dtype=torch.uint8, device=dev),
+             torch.zeros(ops_all.size, dtype=torch.uint8, device=dev),
+             np.cumsum([0] + [b[0].size for b in wl.batches]))
     if args.copy_calib:
         src = torch.empty(args.copy_calib << 20, dtype=torch.uint8, device=dev).fill_(1)
         dst = torch.empty_like(src)
@@ -110,130 +234,51 @@ def main():
         del src, dst
         log("copy calibration: %d MiB device-to-device" % args.copy_calib)
 
-    nsteps = args.warmup + args.steps
-    t0 = time.time()
-    maps = [B.Map(p) for _ in range(nsteps)]
-    torch.cuda.synchronize()
-    log("created %d maps (%.1fs); footprint hbm=%.2f GiB obs=%.2f GiB" % (
-        nsteps, time.time() - t0, B.footprint(p)[0] / 2**30, B.footprint(p)[1] / 2**30))
+    main_res = run_mode(args, wl, dev_t, B, torch, args.observable)
+    other = None
+    if not args.single_mode:
+        other_mode = "device" if args.observable == "host" else "host"
+        o = run_mode(args, wl, dev_t, B, torch, other_mode)
+        other = {"observable": other_mode, "ops_per_s": round(o["ops_per_s"], 1),
+                 "build_keys_per_s": round(o["build_keys_per_s"], 1),
+                 "batch_latency_ms": {"p50": round(o["lat_p50"], 4), "p99": round(o["lat_p99"], 4)},
+                 "per_call_ops_per_s": o["per_call"]["ops_per_s"], "kernels": o["kernels"]}
 
-    def run_step(m, record):
-        evs = [torch.cuda.Event(enable_timing=True) for _ in range(len(wl.batches) + 2)]
-        evs[0].record(stream)
-        B.check(m.build(d_keys, d_vals), "bolt_build")
-        evs[1].record(stream)
-        for bi in range(len(wl.batches)):
-            a, b = int(bounds[bi]), int(bounds[bi + 1])
-            B.check(m.access(d_ops[a:b], d_qk[a:b], d_qv[a:b], d_out[a:b], d_st[a:b]), "bolt_access_batch")
-            evs[bi + 2].record(stream)
-        return evs
+    # the dominant kernel of the headline step (by device time), and the
+    # HBM-bound sort pass of the build
+    ks = main_res["kernels"]
+    dominant = max((c for c in ks if "achieved_GBps" in ks[c]), key=lambda c: ks[c]["total_ms"])
+    roofline = roofline_of(main_res, dominant)
+    roofline_sort = roofline_of(main_res, "sort_global")
 
-    for w in range(args.warmup):
-        run_step(maps[w], False)
-        B.check(maps[w].status(), "warmup status")
-        maps[w].close()
-    log("warmup done")
-
-    torch.cuda.synchronize()
-    t_start = time.perf_counter()
-    step_events = []
-    for s in range(args.steps):
-        step_events.append(run_step(maps[args.warmup + s], True))
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t_start
-    build_ms, query_ms, lat = [], [], []
-    for evs in step_events:
-        build_ms.append(evs[0].elapsed_time(evs[1]))
-        query_ms.append(evs[1].elapsed_time(evs[-1]))
-        lat.extend(evs[i].elapsed_time(evs[i + 1]) for i in range(1, len(evs) - 1))
-    times = {}
-    for s in range(args.steps):
-        m = maps[args.warmup + s]
-        B.check(m.status(), "status")
-        if args.no_kernel_timing:
-            continue
-        for k, (cnt, ms) in m.kernel_times().items():
-            c0, m0 = times.get(k, (0, 0.0))
-            times[k] = (c0 + cnt, m0 + ms)
-    st = maps[-1].stats()
-    log("step stats: %s" % st)
-    # correctness spot check of the last step's answers against the workload's own values
-    vals_host = d_out.cpu().numpy()
-    st_host = d_st.cpu().numpy()
-    if not (st_host[ops_all == 0] <= 1).all():
-        raise SystemExit("bad GET status")
-
-    # plain per-call form: one command per call on the last map
-    m = maps[-1]
-    kpc = min(args.per_call, ops_all.size)
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(kpc + 1)]
-    ev[0].record(stream)
-    for i in range(kpc):
-        B.check(m.access(d_ops[i:i + 1], d_qk[i:i + 1], d_qv[i:i + 1], d_out[i:i + 1], d_st[i:i + 1]), "per-call")
-        ev[i + 1].record(stream)
-    torch.cuda.synchronize()
-    pc_lat = [ev[i].elapsed_time(ev[i + 1]) for i in range(kpc)]
-    pc_ops = kpc / (ev[0].elapsed_time(ev[-1]) / 1e3)
-    B.check(m.status(), "status")
-
-    K = args.steps
-    n_ops = int(ops_all.size)
-    ops_per_s = n_ops * K / (sum(query_ms) / 1e3)
-    build_kps = n * K / (sum(build_ms) / 1e3)
-    npad = 1
-    while npad < n:
-        npad <<= 1
-    # host-bin roles: about 2 (1 - alpha) per command
-    host_roles = 2 * n_ops * K * sz["M"] / sz["B"]
-    kernels = {}
-    dominant = None
-    for cls, (cnt, ms) in sorted(times.items(), key=lambda kv: -kv[1][1]):
-        if cnt == 0:
-            continue
-        ab, bound = algorithmic_bytes(cls, cnt, sz, n, npad, n_ops * K, host_roles, vs)
-        ent = {"launches": cnt, "total_ms": round(ms, 3), "avg_us": round(1e3 * ms / cnt, 2)}
-        if ab is not None:
-            ent["algorithmic_GBps"] = round(ab / (ms / 1e3) / 1e9, 1)
-        kernels[cls] = ent
-    # dominant HBM-bound kernel of the path: the sort passes (the build's
-    # hot loop); page I/O is reported per kernel class above
-    gcnt, gms = times.get("sort_global", (0, 0.0))
-    achieved = 16 * npad / (gms / gcnt / 1e3) / 1e9 if gcnt else 0.0
-    roofline = {"bound": "hbm", "kernel": "k_bitonic_global", "achieved": round(achieved, 1),
-                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": None, "bytes_per_launch": 16 * npad, "avg_launch_us": round(1e3 * gms / max(gcnt, 1), 2)}
-
-    cpu = None
-    if not args.no_cpu_baseline:
-        cpu = cpu_baseline(args.cpu_batches)
-
-    lat_np = np.array(lat)
+    cpu = None if args.no_cpu_baseline else cpu_baseline(args.cpu_batches)
+    sz = main_res["sizes"]
     out = {
         "metric": "oblivious get/put per sec + build keys/s at N=2^24 (1 GPU); p50/p99 latency",
-        "value": round(ops_per_s, 1),
+        "value": round(main_res["ops_per_s"], 1),
         "unit": "ops/s",
         "n_gpus": 1,
-        "steps": K,
+        "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(wall * 1e3 / K, 3),
+        "ms_per_step": round(main_res["ms_per_step"], 3),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "u64",
         "data": "synthetic",
-        "config": {"workload": wl.name, "n": n, "capacity": wl.cap, "value_bytes": vs, "ops_per_step": n_ops,
-                   "batch": args.batch, "zipf_s": 0.99, "absent_frac": 0.05, "get_frac": 0.9,
-                   "observable": args.observable, "c": 8, "alpha": 0.2, "Z": sz["Z"], "page_bytes": sz["page_bytes"]},
-        "build_keys_per_s": round(build_kps, 1),
-        "build_ms": round(float(np.mean(build_ms)), 3),
-        "query_ms": round(float(np.mean(query_ms)), 3),
-        "batch_latency_ms": {"p50": round(float(np.percentile(lat_np, 50)), 4),
-                             "p99": round(float(np.percentile(lat_np, 99)), 4)},
-        "per_call": {"ops_per_s": round(pc_ops, 1), "p50_ms": round(float(np.percentile(pc_lat, 50)), 4),
-                     "p99_ms": round(float(np.percentile(pc_lat, 99)), 4), "calls": kpc},
-        "host_link_GBps_query": round(2 * host_roles / K * sz["page_bytes"] / (np.mean(query_ms) / 1e3) / 1e9, 2),
+        "config": {"workload": wl.name, "n": n, "capacity": wl.cap, "value_bytes": wl.vs,
+                   "ops_per_step": int(ops_all.size), "batch": args.batch, "zipf_s": 0.99, "absent_frac": 0.05,
+                   "get_frac": 0.9, "observable": args.observable, "c": 8, "alpha": 0.2, "Z": sz["Z"],
+                   "page_bytes": sz["page_bytes"]},
+        "build_keys_per_s": round(main_res["build_keys_per_s"], 1),
+        "build_ms": round(main_res["build_ms"], 3),
+        "query_ms": round(main_res["query_ms"], 3),
+        "batch_latency_ms": {"p50": round(main_res["lat_p50"], 4), "p99": round(main_res["lat_p99"], 4)},
+        "per_call": main_res["per_call"],
         "roofline": roofline,
-        "kernels": kernels,
+        "roofline_sort": roofline_sort,
+        "kernels": ks,
+        "other_observable_mode": other,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -228,7 +228,7 @@ __global__ __launch_bounds__(1024) void k_acc_part(const uint8_t* __restrict__ o
     if (i < q) {
       const uint32_t pos = base[mypart[t]] + myrank[t];
       pkey[pos] = keys[i];
-      pidx[pos] = i;
+      pidx[pos] = (i << 2) | (ops[i] & 3u);  // ordering by this payload is ordering by index
     }
   }
 }
@@ -258,11 +258,12 @@ __global__ __launch_bounds__(kDedupNT) void k_acc_group(const uint8_t* __restric
     const uint32_t r = r0 + e;
     const bool real = r < q;
     k[e] = real ? pkey[off + r] : kNone64;
-    x[e] = real ? pidx[off + r] : kNone;
+    x[e] = real ? pidx[off + r] : kNone;  // command index << 2 | op
   }
   dedup_sort(k, x, npad, skey, sidx);
   // Fold structure.  Each thread owns kDedupPer consecutive sorted
-  // positions; positions are stored +1 so that 0 means "none".
+  // positions; positions are stored +1 so that 0 means "none".  The payload
+  // is index << 2 | op.
   uint32_t rs[kDedupPer], wp[kDedupPer];
   uint32_t run = 0, wmax = 0;
   for (uint32_t t = 0; t < kDedupPer; ++t) {
@@ -272,7 +273,7 @@ __global__ __launch_bounds__(kDedupNT) void k_acc_group(const uint8_t* __restric
       if (head) run = r + 1;
       rs[t] = run;
       wp[t] = wmax;  // writers strictly before r within this chunk
-      if (ops[sidx[r]] != 0) wmax = r + 1;
+      if (sidx[r] & 3u) wmax = r + 1;
     } else {
       rs[t] = 0;
       wp[t] = 0;
@@ -285,14 +286,15 @@ __global__ __launch_bounds__(kDedupNT) void k_acc_group(const uint8_t* __restric
     if (r >= q) break;
     uint32_t start = rs[t] > run_in ? rs[t] : run_in;  // 1-based run start
     uint32_t w = wp[t] > w_in ? wp[t] : w_in;          // 1-based last writer before r
-    uint32_t me = sidx[r];
-    leader[me] = sidx[start - 1];
-    prevw[me] = (w != 0 && w >= start) ? sidx[w - 1] : kNone;
+    const uint32_t me = sidx[r] >> 2;
+    const uint32_t lead = sidx[start - 1] >> 2;
+    leader[me] = lead;
+    prevw[me] = (w != 0 && w >= start) ? (sidx[w - 1] >> 2) : kNone;
     bool tail = r + 1 == q || skey[r + 1] != skey[r];
     if (tail) {
       uint32_t wl = w;
-      if (ops[me] != 0) wl = r + 1;
-      lastw[sidx[start - 1]] = (wl != 0 && wl >= start) ? sidx[wl - 1] : kNone;
+      if (sidx[r] & 3u) wl = r + 1;
+      lastw[lead] = (wl != 0 && wl >= start) ? (sidx[wl - 1] >> 2) : kNone;
     }
   }
 }

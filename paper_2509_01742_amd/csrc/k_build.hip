@@ -13,6 +13,8 @@
 //       (Sec. 5.2), in rounds of ceil(R/16) keys; then a duplicate check.
 //
 // Grid shapes and trip counts depend only on n and the map's sizes.
+#include <algorithm>
+
 #include "bolt_impl.h"
 
 namespace bolt {
@@ -391,15 +393,18 @@ int run_build(bolt_map* m, const uint64_t* keys, const void* vals, uint64_t n, h
   }
   // a2
   const uint64_t rs = (s.B + 15) / 16;
-  for (uint64_t r0 = 0; r0 < n; r0 += rs) {
-    uint64_t r1 = r0 + rs < n ? r0 + rs : n;
-    {
-      TimedScope ts(m->timer, kkP2C, st);
-      hipLaunchKernelGGL(k_p2c_decide, dim3(blocks_for(r1 - r0, NT)), dim3(NT), 0, st, b.pair, m->load, r0, r1, b.dest);
-    }
-    {
-      TimedScope ts(m->timer, kkP2C, st);
-      hipLaunchKernelGGL(k_p2c_add, dim3(blocks_for(r1 - r0, NT)), dim3(NT), 0, st, b.dest, r0, r1, m->load);
+  {
+    for (uint64_t r0 = 0; r0 < n; r0 += rs) {
+      uint64_t r1 = r0 + rs < n ? r0 + rs : n;
+      {
+        TimedScope ts(m->timer, kkP2C, st);
+        hipLaunchKernelGGL(k_p2c_decide, dim3(blocks_for(r1 - r0, NT)), dim3(NT), 0, st, b.pair, m->load, r0, r1,
+                           b.dest);
+      }
+      {
+        TimedScope ts(m->timer, kkP2C, st);
+        hipLaunchKernelGGL(k_p2c_add, dim3(blocks_for(r1 - r0, NT)), dim3(NT), 0, st, b.dest, r0, r1, m->load);
+      }
     }
   }
   {
@@ -445,17 +450,19 @@ int run_build(bolt_map* m, const uint64_t* keys, const void* vals, uint64_t n, h
   // a7
   (void)hipMemsetAsync(b.rowcnt, 0, s.R * sizeof(uint32_t), st);
   const uint64_t rsm = (s.R + 15) / 16;
-  for (uint64_t r0 = 0; r0 < n; r0 += rsm) {
-    uint64_t r1 = r0 + rsm < n ? r0 + rsm : n;
-    {
-      TimedScope ts(m->timer, kkPmBuild, st);
-      hipLaunchKernelGGL(k_pm_decide, dim3(blocks_for(r1 - r0, NT)), dim3(NT), 0, st, m->ctl, keys, r0, r1, s.R,
-                         (uint32_t)s.d, b.rowcnt, b.rowsel);
-    }
-    {
-      TimedScope ts(m->timer, kkPmBuild, st);
-      hipLaunchKernelGGL(k_pm_add, dim3(blocks_for(r1 - r0, NT)), dim3(NT), 0, st, keys, b.pair, b.rowsel, r0, r1,
-                         (uint32_t)s.W, b.rowcnt, m->pm_key, m->pm_pair, m->ctl);
+  {
+    for (uint64_t r0 = 0; r0 < n; r0 += rsm) {
+      uint64_t r1 = r0 + rsm < n ? r0 + rsm : n;
+      {
+        TimedScope ts(m->timer, kkPmBuild, st);
+        hipLaunchKernelGGL(k_pm_decide, dim3(blocks_for(r1 - r0, NT)), dim3(NT), 0, st, m->ctl, keys, r0, r1, s.R,
+                           (uint32_t)s.d, b.rowcnt, b.rowsel);
+      }
+      {
+        TimedScope ts(m->timer, kkPmBuild, st);
+        hipLaunchKernelGGL(k_pm_add, dim3(blocks_for(r1 - r0, NT)), dim3(NT), 0, st, keys, b.pair, b.rowsel, r0, r1,
+                           (uint32_t)s.W, b.rowcnt, m->pm_key, m->pm_pair, m->ctl);
+      }
     }
   }
   {

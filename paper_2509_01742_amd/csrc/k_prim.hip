@@ -235,18 +235,119 @@ void launch_bitonic_sort(uint64_t* a, uint64_t n, hipStream_t st, KernelTimer* t
 // ---------------------------------------------------------------------------
 // Expansion network.  Element = (target << 32 | payload); all ones = empty.
 // Stage j moves an element right by 2^j when bit j of (target - position)
-// is set; each output position reads both candidates.
+// is set; each output position reads both candidates (stay / arrive), so
+// the memory accesses depend only on m.
+//
+// Stages run from the top bit down.  The stages with stride >= 2^kExpLow run
+// as global passes, F of them per pass: along one residue class modulo the
+// group's lowest stride the F stages are a small expansion network over
+// consecutive coordinates, so a thread pulls 2F - 1 ... (2^(F+1) - 1)
+// elements of its strip into registers and emits the last 2^F.  The stages
+// below 2^kExpLow then run in LDS on tiles of kExpTile outputs, each tile
+// loading the kExpHalo elements to its left (no element moves further than
+// 2^kExpLow - 1 in those stages).
 // ---------------------------------------------------------------------------
 
+constexpr int kExpLow = 10;
+constexpr uint32_t kExpTile = 4096;
+constexpr uint32_t kExpHalo = 1u << kExpLow;
+
+__device__ __forceinline__ uint64_t exp_step(uint64_t cur, uint64_t prev, uint64_t pos, uint64_t h) {
+  const bool stay = cur != kNone64 && !(((cur >> 32) - pos) & h);
+  const bool arrive = prev != kNone64 && pos >= h && (((prev >> 32) - (pos - h)) & h);
+  return stay ? cur : (arrive ? prev : kNone64);
+}
+
+// One stage per pass (used for m too small for the fused forms).
 __global__ void k_expand_stage(const uint64_t* __restrict__ in, uint64_t* __restrict__ out, uint64_t m, uint32_t j) {
   uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= m) return;
   const uint64_t h = 1ull << j;
-  uint64_t x = in[p];
-  uint64_t y = p >= h ? in[p - h] : kNone64;
-  bool stay = x != kNone64 && !(((x >> 32) - p) & h);
-  bool arrive = y != kNone64 && (((y >> 32) - (p - h)) & h);
-  out[p] = stay ? x : (arrive ? y : kNone64);
+  out[p] = exp_step(in[p], p >= h ? in[p - h] : kNone64, p, h);
+}
+
+// Stages jlow + F - 1 .. jlow in one pass.  Thread = (residue r, block of
+// 2^F coordinates c0..); coordinate c is position c * 2^jlow + r.
+template <int F>
+__global__ __launch_bounds__(256) void k_expand_fused(const uint64_t* __restrict__ in, uint64_t* __restrict__ out,
+                                                      uint64_t m, uint32_t jlow) {
+  constexpr int NB = 1 << F;      // outputs per thread
+  constexpr int NW = 2 * NB - 1;  // window: NB - 1 to the left
+  const uint64_t hl = 1ull << jlow;
+  const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const uint64_t r = t & (hl - 1);
+  const uint64_t c0 = (t >> jlow) * NB;
+  const uint64_t ncoord = (m + hl - 1) >> jlow;
+  if (c0 >= ncoord) return;
+  uint64_t v[NW];
+#pragma unroll
+  for (int k = 0; k < NW; ++k) {
+    const int64_t c = (int64_t)c0 - (NB - 1) + k;
+    const uint64_t pos = (uint64_t)c * hl + r;
+    v[k] = (c >= 0 && pos < m) ? in[pos] : kNone64;
+  }
+#pragma unroll
+  for (int f = F - 1; f >= 0; --f) {
+    const int d = 1 << f;
+    const uint64_t h = hl << f;
+#pragma unroll
+    for (int k = NW - 1; k >= 0; --k) {  // descending: v[k - d] is still the old value
+      const int64_t c = (int64_t)c0 - (NB - 1) + k;
+      const uint64_t pos = (uint64_t)c * hl + r;
+      const uint64_t prev = k >= d ? v[k - d] : kNone64;
+      v[k] = c >= 0 ? exp_step(v[k], prev, pos, h) : kNone64;
+    }
+  }
+#pragma unroll
+  for (int k = NB - 1; k < NW; ++k) {
+    const uint64_t pos = (c0 + (k - (NB - 1))) * hl + r;
+    if (pos < m) out[pos] = v[k];
+  }
+}
+
+// Stages jtop .. 0 (jtop < kExpLow) on LDS tiles with a left halo.
+__global__ __launch_bounds__(256) void k_expand_tile(const uint64_t* __restrict__ in, uint64_t* __restrict__ out,
+                                                     uint64_t m, int jtop) {
+  __shared__ uint64_t A[kExpTile + kExpHalo];
+  __shared__ uint64_t Bf[kExpTile + kExpHalo];
+  const uint64_t p0 = (uint64_t)blockIdx.x * kExpTile;
+  constexpr uint32_t NWIN = kExpTile + kExpHalo;
+  for (uint32_t x = threadIdx.x; x < NWIN; x += 256) {
+    const int64_t pos = (int64_t)p0 - (int64_t)kExpHalo + x;
+    A[x] = (pos >= 0 && (uint64_t)pos < m) ? in[pos] : kNone64;
+  }
+  __syncthreads();
+  uint64_t* cur = A;
+  uint64_t* nxt = Bf;
+  for (int j = jtop; j >= 0; --j) {
+    const uint32_t h = 1u << j;
+    for (uint32_t x = threadIdx.x; x < NWIN; x += 256) {
+      const int64_t pos = (int64_t)p0 - (int64_t)kExpHalo + x;
+      const uint64_t prev = x >= h ? cur[x - h] : kNone64;
+      nxt[x] = pos >= 0 ? exp_step(cur[x], prev, (uint64_t)pos, h) : kNone64;
+    }
+    __syncthreads();
+    uint64_t* t = cur;
+    cur = nxt;
+    nxt = t;
+  }
+  for (uint32_t x = threadIdx.x; x < kExpTile; x += 256) {
+    const uint64_t pos = p0 + x;
+    if (pos < m) out[pos] = cur[kExpHalo + x];
+  }
+}
+
+static void launch_fused(const uint64_t* in, uint64_t* out, uint64_t m, uint32_t jlow, int F, hipStream_t st) {
+  const uint64_t hl = 1ull << jlow;
+  const uint64_t ncoord = (m + hl - 1) >> jlow;
+  const uint64_t threads = ((ncoord + (1u << F) - 1) >> F) * hl;
+  dim3 grid((uint32_t)((threads + 255) / 256)), block(256);
+  switch (F) {
+    case 1: hipLaunchKernelGGL(k_expand_fused<1>, grid, block, 0, st, in, out, m, jlow); break;
+    case 2: hipLaunchKernelGGL(k_expand_fused<2>, grid, block, 0, st, in, out, m, jlow); break;
+    case 3: hipLaunchKernelGGL(k_expand_fused<3>, grid, block, 0, st, in, out, m, jlow); break;
+    default: hipLaunchKernelGGL(k_expand_fused<4>, grid, block, 0, st, in, out, m, jlow); break;
+  }
 }
 
 // Runs all stages; the result ends in `a` (tmp is scratch of m elements).
@@ -256,10 +357,21 @@ void launch_expand(uint64_t* a, uint64_t* tmp, uint64_t m, hipStream_t st, Kerne
   while ((2ull << top) <= m - 1) ++top;
   uint64_t* src = a;
   uint64_t* dst = tmp;
-  dim3 grid((uint32_t)((m + 255) / 256)), block(256);
-  for (int j = top; j >= 0; --j) {
+  int j = top;
+  while (j >= kExpLow) {  // global passes, up to 4 stages each
+    int F = j - kExpLow + 1;
+    if (F > 4) F = 4;
     TimedScope ts(tm, kkExpand, st);
-    hipLaunchKernelGGL(k_expand_stage, grid, block, 0, st, src, dst, m, (uint32_t)j);
+    launch_fused(src, dst, m, (uint32_t)(j - F + 1), F, st);
+    uint64_t* t = src;
+    src = dst;
+    dst = t;
+    j -= F;
+  }
+  {  // the low stages on LDS tiles
+    TimedScope ts(tm, kkExpand, st);
+    hipLaunchKernelGGL(k_expand_tile, dim3((uint32_t)((m + kExpTile - 1) / kExpTile)), dim3(256), 0, st, src, dst, m,
+                       j);
     uint64_t* t = src;
     src = dst;
     dst = t;
