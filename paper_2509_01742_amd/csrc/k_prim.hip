@@ -306,13 +306,13 @@ __global__ __launch_bounds__(256) void k_expand_fused(const uint64_t* __restrict
 }
 
 // Stages jtop .. 0 (jtop < kExpLow) on LDS tiles with a left halo.
-__global__ __launch_bounds__(256) void k_expand_tile(const uint64_t* __restrict__ in, uint64_t* __restrict__ out,
+__global__ __launch_bounds__(1024) void k_expand_tile(const uint64_t* __restrict__ in, uint64_t* __restrict__ out,
                                                      uint64_t m, int jtop) {
   __shared__ uint64_t A[kExpTile + kExpHalo];
   __shared__ uint64_t Bf[kExpTile + kExpHalo];
   const uint64_t p0 = (uint64_t)blockIdx.x * kExpTile;
   constexpr uint32_t NWIN = kExpTile + kExpHalo;
-  for (uint32_t x = threadIdx.x; x < NWIN; x += 256) {
+  for (uint32_t x = threadIdx.x; x < NWIN; x += 1024) {
     const int64_t pos = (int64_t)p0 - (int64_t)kExpHalo + x;
     A[x] = (pos >= 0 && (uint64_t)pos < m) ? in[pos] : kNone64;
   }
@@ -321,7 +321,7 @@ __global__ __launch_bounds__(256) void k_expand_tile(const uint64_t* __restrict_
   uint64_t* nxt = Bf;
   for (int j = jtop; j >= 0; --j) {
     const uint32_t h = 1u << j;
-    for (uint32_t x = threadIdx.x; x < NWIN; x += 256) {
+    for (uint32_t x = threadIdx.x; x < NWIN; x += 1024) {
       const int64_t pos = (int64_t)p0 - (int64_t)kExpHalo + x;
       const uint64_t prev = x >= h ? cur[x - h] : kNone64;
       nxt[x] = pos >= 0 ? exp_step(cur[x], prev, (uint64_t)pos, h) : kNone64;
@@ -331,7 +331,7 @@ __global__ __launch_bounds__(256) void k_expand_tile(const uint64_t* __restrict_
     cur = nxt;
     nxt = t;
   }
-  for (uint32_t x = threadIdx.x; x < kExpTile; x += 256) {
+  for (uint32_t x = threadIdx.x; x < kExpTile; x += 1024) {
     const uint64_t pos = p0 + x;
     if (pos < m) out[pos] = cur[kExpHalo + x];
   }
@@ -370,7 +370,7 @@ void launch_expand(uint64_t* a, uint64_t* tmp, uint64_t m, hipStream_t st, Kerne
   }
   {  // the low stages on LDS tiles
     TimedScope ts(tm, kkExpand, st);
-    hipLaunchKernelGGL(k_expand_tile, dim3((uint32_t)((m + kExpTile - 1) / kExpTile)), dim3(256), 0, st, src, dst, m,
+    hipLaunchKernelGGL(k_expand_tile, dim3((uint32_t)((m + kExpTile - 1) / kExpTile)), dim3(1024), 0, st, src, dst, m,
                        j);
     uint64_t* t = src;
     src = dst;
