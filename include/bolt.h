@@ -152,6 +152,25 @@ int bolt_get_batch(bolt_map* m, const uint64_t* d_keys, uint32_t q, void* d_vals
 int bolt_put_batch(bolt_map* m, const uint64_t* d_keys, const void* d_vals, uint32_t q, uint8_t* d_status,
                    void* hip_stream);
 
+/* One batch of commands for one map (the arguments of bolt_access_batch). */
+typedef struct {
+  const uint8_t* d_ops;
+  const uint64_t* d_keys;
+  const void* d_vals_in;
+  void* d_vals_out;
+  uint8_t* d_status;
+  uint32_t q;
+} bolt_batch;
+
+/* Runs one batch on each of `count` distinct maps (all on the current
+ * device), every phase of the access path as one launch for all of them.
+ * Each map gets exactly the result bolt_access_batch would give it; maps of
+ * any size and batches of any size up to BOLT_MAX_BATCH mix freely.  This is
+ * the multi-map batching of the build's systems layer: it removes the
+ * per-map launch cost that dominates small maps and small batches.  A map
+ * may appear once per call.  Batches with q = 0 are skipped. */
+int bolt_access_many(bolt_map* const* maps, const bolt_batch* batches, uint32_t count, void* hip_stream);
+
 /* Frees every resource of the map after waiting for its work.  NULL is a no-op. */
 int bolt_destroy(bolt_map* m);
 

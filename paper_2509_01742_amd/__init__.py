@@ -65,6 +65,11 @@ class bolt_kernel_time(C.Structure):
     _fields_ = [("name", C.c_char * 32), ("launches", C.c_uint64), ("total_ms", C.c_double)]
 
 
+class bolt_batch(C.Structure):
+    _fields_ = [("d_ops", C.c_void_p), ("d_keys", C.c_void_p), ("d_vals_in", C.c_void_p),
+                ("d_vals_out", C.c_void_p), ("d_status", C.c_void_p), ("q", C.c_uint32)]
+
+
 TRACE_DTYPE = np.dtype([("batch", "<u4"), ("kind", "<u4"), ("page", "<u8")])
 
 # (name, restype, argtypes) of every entry point in include/bolt.h
@@ -76,6 +81,7 @@ _SIGS = [
     ("bolt_create", _I, [C.POINTER(bolt_params), _P, C.POINTER(_P)]),
     ("bolt_build", _I, [_P, _P, _P, _U64, _P]),
     ("bolt_access_batch", _I, [_P, _P, _P, _P, _P, _P, _U32, _P]),
+    ("bolt_access_many", _I, [_P, _P, _U32, _P]),
     ("bolt_get_batch", _I, [_P, _P, _U32, _P, _P, _P]),
     ("bolt_put_batch", _I, [_P, _P, _P, _U32, _P, _P]),
     ("bolt_destroy", _I, [_P]),
@@ -275,6 +281,21 @@ class Map:
                                a.ctypes.data_as(C.c_void_p), b.ctypes.data_as(C.c_void_p), n.value, C.byref(n)),
               "pm_snapshot")
         return sorted((int(r[i]), int(k[i]), int(a[i]), int(b[i])) for i in range(int(n.value)))
+
+
+def access_many(maps, batches, stream=None) -> int:
+    """One batch per map, every phase launched once for all maps.
+
+    maps: sequence of Map; batches: sequence of (ops, keys, vals_in, vals_out, status) device tensors."""
+    n = len(maps)
+    if n != len(batches):
+        raise ValueError("one batch per map")
+    hs = (C.c_void_p * max(n, 1))(*[m.h for m in maps])
+    bs = (bolt_batch * max(n, 1))()
+    for i, (ops, keys, vin, vout, status) in enumerate(batches):
+        bs[i] = bolt_batch(_dptr(ops).value, _dptr(keys).value, _dptr(vin).value, _dptr(vout).value,
+                           _dptr(status).value, 0 if ops is None else ops.numel())
+    return bolt_access_many(hs, bs, n, _stream(stream))
 
 
 def prf(key: bytes, domain: int, x, out, stream=None) -> int:

@@ -9,6 +9,8 @@
 #include <algorithm>
 #include <new>
 
+#include <vector>
+
 #include "bolt_impl.h"
 
 using namespace bolt;
@@ -308,6 +310,38 @@ int bolt_access_batch(bolt_map* m, const uint8_t* d_ops, const uint64_t* d_keys,
   m->last_stream = st;
   if (hipSetDevice(m->device) != hipSuccess) return BOLT_EHIP;
   return run_access(m, d_ops, d_keys, d_vals_in, d_vals_out, d_status, q, st);
+}
+
+int bolt_access_many(bolt_map* const* maps, const bolt_batch* batches, uint32_t count, void* hip_stream) {
+  if (count == 0) return BOLT_OK;
+  if (!maps || !batches) return BOLT_EINVAL;
+  std::vector<bolt_map*> live;
+  std::vector<bolt_batch> work;
+  live.reserve(count);
+  work.reserve(count);
+  for (uint32_t i = 0; i < count; ++i) {
+    bolt_map* m = maps[i];
+    int rc = map_check(m);
+    if (rc) return rc;
+    const bolt_batch& b = batches[i];
+    if (!m->built || b.q > kMaxBatch) return BOLT_EINVAL;
+    if (m->device != maps[0]->device) return BOLT_EINVAL;
+    for (uint32_t j = 0; j < i; ++j)
+      if (maps[j] == m) return BOLT_EINVAL;  // one batch per map and call
+    if (b.q == 0) continue;
+    if (!b.d_ops || !b.d_keys || !b.d_vals_in || !b.d_vals_out || !b.d_status) return BOLT_EINVAL;
+    if (((uintptr_t)b.d_keys | (uintptr_t)b.d_vals_in | (uintptr_t)b.d_vals_out) & 7) return BOLT_EINVAL;
+    live.push_back(m);
+    work.push_back(b);
+  }
+  if (live.empty()) return BOLT_OK;
+  hipStream_t st = (hipStream_t)hip_stream;
+  if (hipSetDevice(live[0]->device) != hipSuccess) return BOLT_EHIP;
+  for (bolt_map* m : live) m->last_stream = st;
+  if (live.size() == 1)
+    return run_access(live[0], work[0].d_ops, work[0].d_keys, work[0].d_vals_in, work[0].d_vals_out,
+                      work[0].d_status, work[0].q, st);
+  return run_access_many(live.data(), work.data(), (uint32_t)live.size(), st);
 }
 
 int bolt_get_batch(bolt_map* m, const uint64_t* d_keys, uint32_t q, void* d_vals_out, uint8_t* d_found,

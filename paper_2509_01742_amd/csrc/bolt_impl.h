@@ -149,5 +149,6 @@ void launch_map_init(bolt_map* m, hipStream_t st);
 int run_build(bolt_map* m, const uint64_t* keys, const void* vals, uint64_t n, hipStream_t st);
 int run_access(bolt_map* m, const uint8_t* ops, const uint64_t* keys, const void* vals_in, void* vals_out,
                uint8_t* status, uint32_t q, hipStream_t st);
+int run_access_many(bolt_map* const* maps, const bolt_batch* batches, uint32_t count, hipStream_t st);
 
 }  // namespace bolt

@@ -25,9 +25,200 @@
 //             canonical order, and writes it whole (observable pages once
 //             each); the entries listed are freed
 //   finish    position-map inserts (one-round case), counters, stash bound
+#include <string.h>
+
+#include <vector>
+
 #include "bolt_impl.h"
 
 namespace bolt {
+
+struct PartArgs {
+  const uint8_t* ops;
+  const uint64_t* keys;
+  uint32_t q, epoch;
+  Ctl* ctl;
+  uint32_t* pofs;
+  uint64_t* pkey;
+  uint32_t* pidx;
+};
+
+struct GroupArgs {
+  uint32_t epoch;
+  const Ctl* ctl;
+  const uint32_t* pofs;
+  const uint64_t* pkey;
+  const uint32_t* pidx;
+  uint32_t* leader;
+  uint32_t* prevw;
+  uint32_t* lastw;
+};
+
+struct FetchArgs {
+  const Ctl* ctl;
+  const uint8_t* ops;
+  const uint64_t* keys;
+  const uint32_t* leader;
+  uint32_t q, epoch;
+  uint64_t B, K, R;
+  uint32_t Z, W, d, vw;
+  uint64_t pw;  // page words
+  const uint64_t* pm_key;
+  const uint2* pm_pair;
+  const uint32_t* pm_mask;
+  const uint64_t* obs;
+  const uint64_t* hbm;
+  const uint32_t* rev_cnt;
+  const uint32_t* rev_idx;
+  const uint64_t* st_key;
+  const uint64_t* st_val;
+  uint32_t* st_dead;
+  uint32_t* load;
+  uint64_t* claim;
+  uint64_t* rmask;
+  uint64_t* stage;
+  uint32_t* cand_bin;
+  uint32_t* hit;
+  uint32_t* hrow;
+  uint32_t* hslot;
+  uint32_t* found;
+  uint64_t* fval;
+  uint2* rpair;
+  uint32_t* tlog_r;  // [2q] or null
+  Ctl* ctlw;
+};
+
+struct ResolveArgs {
+  Ctl* ctl;
+  const uint8_t* ops;
+  const uint64_t* vals_in;
+  const uint32_t* leader;
+  const uint32_t* prevw;
+  const uint32_t* lastw;
+  const uint32_t* hit;
+  const uint32_t* hrow;
+  const uint32_t* hslot;
+  const uint32_t* found;
+  const uint64_t* fval;
+  const uint2* rpair;
+  const uint32_t* load;
+  uint32_t q, vw, fast, epoch;
+  uint64_t* vals_out;
+  uint8_t* status;
+  uint32_t* fin;
+  uint32_t* chosen;
+  uint32_t* pm_mask;
+};
+
+struct PlaceArgs {
+  uint32_t enabled;  // this map's batch takes the one-round path
+  Ctl* ctl;
+  const uint64_t* keys;
+  const uint64_t* vals_in;
+  const uint32_t* leader;
+  const uint32_t* lastw;
+  const uint32_t* fin;
+  const uint32_t* chosen;
+  const uint32_t* hrow;
+  const uint32_t* hslot;
+  const uint64_t* fval;
+  const uint2* rpair;
+  uint32_t q, epoch, Z, W, d, vw;
+  uint64_t K, R, PW;
+  uint32_t* load;
+  uint64_t* st_used;
+  uint64_t* st_key;
+  uint64_t* st_val;
+  uint32_t* st_dest;
+  uint32_t* st_dead;
+  uint32_t* rev_cnt;
+  uint32_t* rev_idx;
+  uint64_t* claim;
+  uint32_t* cand_bin;
+  uint2* pm_pair;
+  const uint32_t* pm_mask;
+  uint32_t* rowsel;
+};
+
+struct RemapArgs {
+  uint32_t enabled;  // this map's batch takes the several-round path
+  Ctl* ctl;
+  const uint64_t* keys;
+  const uint64_t* vals_in;
+  const uint32_t* leader;
+  const uint32_t* lastw;
+  const uint32_t* fin;
+  const uint32_t* hrow;
+  const uint32_t* hslot;
+  const uint64_t* fval;
+  const uint2* rpair;
+  uint32_t q, epoch, Z, W, d, vw;
+  uint64_t B, K, R, PW;
+  uint32_t* load;
+  uint64_t* st_used;
+  uint64_t* st_key;
+  uint64_t* st_val;
+  uint32_t* st_dest;
+  uint32_t* st_dead;
+  uint32_t* rev_cnt;
+  uint32_t* rev_idx;
+  uint64_t* claim;
+  uint32_t* cand_bin;
+  uint64_t* pm_key;
+  uint2* pm_pair;
+  uint32_t* pm_mask;
+};
+
+struct WbArgs {
+  Ctl* ctl;
+  uint32_t q, epoch, Z, vw;
+  uint64_t K, pw;
+  const uint32_t* cand_bin;
+  const uint64_t* claim;
+  uint64_t* rmask;
+  const uint64_t* stage;
+  uint64_t* obs;
+  uint64_t* hbm;
+  uint32_t* rev_cnt;
+  const uint32_t* rev_idx;
+  const uint64_t* st_key;
+  const uint64_t* st_val;
+  uint32_t* st_dead;
+  uint64_t* st_used;
+  uint32_t* freed;   // [kFreeBuckets] entries freed, summed by finish
+  uint32_t* tlog_w;  // [3q] or null
+};
+
+struct FinishArgs {
+  Ctl* ctl;
+  uint32_t q, W, epoch;
+  uint64_t cap, stash_bound;
+  const uint32_t* rowsel;
+  const uint64_t* keys;
+  const uint2* rpair;
+  uint32_t* freed;
+  uint64_t* pm_key;
+  uint2* pm_pair;
+  uint32_t* pm_mask;
+};
+
+// Every kernel argument of one map's batch.  A multi-map launch reads the
+// plan of map blockIdx.y from a device table; a single-map launch passes
+// the argument block by value.
+struct AccessPlan {
+  PartArgs pt;
+  GroupArgs gr;
+  FetchArgs fa;
+  ResolveArgs rv;
+  PlaceArgs pa;
+  RemapArgs ra;
+  WbArgs wa;
+  FinishArgs fn;
+  uint32_t q, fast;
+  uint64_t wb_lds;
+};
+
+#define BOLT_PICK(T, field) const T& a = MULTI ? tab[blockIdx.y].field : a1
 
 constexpr uint32_t kDedupNT = 1024;
 constexpr uint32_t kDedupPer = kMaxBatch / kDedupNT;  // 8 sorted positions per thread
@@ -191,9 +382,16 @@ __device__ __forceinline__ uint32_t part_of(uint64_t key) {
 // One workgroup: op check, a histogram of the partitions in LDS, their
 // offsets, then every (key, index) scattered to its partition (no global
 // atomics).  A batch with an op code above DEL is marked rejected.
-__global__ __launch_bounds__(1024) void k_acc_part(const uint8_t* __restrict__ ops, const uint64_t* __restrict__ keys,
-                                                   uint32_t q, uint32_t epoch, Ctl* ctl, uint32_t* __restrict__ pofs,
-                                                   uint64_t* __restrict__ pkey, uint32_t* __restrict__ pidx) {
+template <bool MULTI>
+__global__ __launch_bounds__(1024) void k_acc_part(PartArgs a1, const AccessPlan* tab) {
+  BOLT_PICK(PartArgs, pt);
+  const uint8_t* __restrict__ ops = a.ops;
+  const uint64_t* __restrict__ keys = a.keys;
+  const uint32_t q = a.q, epoch = a.epoch;
+  Ctl* ctl = a.ctl;
+  uint32_t* __restrict__ pofs = a.pofs;
+  uint64_t* __restrict__ pkey = a.pkey;
+  uint32_t* __restrict__ pidx = a.pidx;
   __shared__ uint32_t hist[kParts];
   __shared__ uint32_t base[kParts];
   __shared__ uint32_t bad;
@@ -236,11 +434,17 @@ __global__ __launch_bounds__(1024) void k_acc_part(const uint8_t* __restrict__ o
 // One workgroup per partition: sort its (key, index) pairs; leader = first
 // command of each key; for every command the last PUT/DEL of its key before
 // it; for every leader the last PUT/DEL of its key in the batch.
-__global__ __launch_bounds__(kDedupNT) void k_acc_group(const uint8_t* __restrict__ ops, uint32_t epoch, const Ctl* ctl,
-                                                        const uint32_t* __restrict__ pofs,
-                                                        const uint64_t* __restrict__ pkey,
-                                                        const uint32_t* __restrict__ pidx, uint32_t* __restrict__ leader,
-                                                        uint32_t* __restrict__ prevw, uint32_t* __restrict__ lastw) {
+template <bool MULTI>
+__global__ __launch_bounds__(kDedupNT) void k_acc_group(GroupArgs a1, const AccessPlan* tab) {
+  BOLT_PICK(GroupArgs, gr);
+  const uint32_t epoch = a.epoch;
+  const Ctl* ctl = a.ctl;
+  const uint32_t* __restrict__ pofs = a.pofs;
+  const uint64_t* __restrict__ pkey = a.pkey;
+  const uint32_t* __restrict__ pidx = a.pidx;
+  uint32_t* __restrict__ leader = a.leader;
+  uint32_t* __restrict__ prevw = a.prevw;
+  uint32_t* __restrict__ lastw = a.lastw;
   __shared__ uint64_t skey[kMaxBatch];
   __shared__ uint32_t sidx[kMaxBatch];
   __shared__ uint32_t tot;
@@ -303,41 +507,11 @@ __global__ __launch_bounds__(kDedupNT) void k_acc_group(const uint8_t* __restric
 // fetch: one wave per command
 // ---------------------------------------------------------------------------
 
-struct FetchArgs {
-  const Ctl* ctl;
-  const uint8_t* ops;
-  const uint64_t* keys;
-  const uint32_t* leader;
-  uint32_t q, epoch;
-  uint64_t B, K, R;
-  uint32_t Z, W, d, vw;
-  uint64_t pw;  // page words
-  const uint64_t* pm_key;
-  const uint2* pm_pair;
-  const uint32_t* pm_mask;
-  const uint64_t* obs;
-  const uint64_t* hbm;
-  const uint32_t* rev_cnt;
-  const uint32_t* rev_idx;
-  const uint64_t* st_key;
-  const uint64_t* st_val;
-  uint32_t* st_dead;
-  uint32_t* load;
-  uint64_t* claim;
-  uint64_t* rmask;
-  uint64_t* stage;
-  uint32_t* cand_bin;
-  uint32_t* hit;
-  uint32_t* hrow;
-  uint32_t* hslot;
-  uint32_t* found;
-  uint64_t* fval;
-  uint2* rpair;
-  uint32_t* tlog_r;  // [2q] or null
-  Ctl* ctlw;
-};
 
-__global__ __launch_bounds__(256) void k_acc_fetch(FetchArgs a) {
+
+template <bool MULTI>
+__global__ __launch_bounds__(256) void k_acc_fetch(FetchArgs a1, const AccessPlan* tab) {
+  BOLT_PICK(FetchArgs, fa);
   const uint32_t lane = threadIdx.x & 63;
   const uint32_t i = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (i >= a.q) return;
@@ -479,29 +653,11 @@ __device__ __forceinline__ bool pm_claim(uint32_t* pm_mask, uint64_t* pm_key, ui
 // resolve: responses and final states (one thread per command)
 // ---------------------------------------------------------------------------
 
-struct ResolveArgs {
-  Ctl* ctl;
-  const uint8_t* ops;
-  const uint64_t* vals_in;
-  const uint32_t* leader;
-  const uint32_t* prevw;
-  const uint32_t* lastw;
-  const uint32_t* hit;
-  const uint32_t* hrow;
-  const uint32_t* hslot;
-  const uint32_t* found;
-  const uint64_t* fval;
-  const uint2* rpair;
-  const uint32_t* load;
-  uint32_t q, vw, fast, epoch;
-  uint64_t* vals_out;
-  uint8_t* status;
-  uint32_t* fin;
-  uint32_t* chosen;
-  uint32_t* pm_mask;
-};
 
-__global__ __launch_bounds__(256) void k_acc_resolve(ResolveArgs a) {
+
+template <bool MULTI>
+__global__ __launch_bounds__(256) void k_acc_resolve(ResolveArgs a1, const AccessPlan* tab) {
+  BOLT_PICK(ResolveArgs, rv);
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   const bool live = i < a.q;
   if (a.ctl->reject == a.epoch || a.ctl->err) {
@@ -551,34 +707,7 @@ __global__ __launch_bounds__(256) void k_acc_resolve(ResolveArgs a) {
 // the row of every insert (one thread per command)
 // ---------------------------------------------------------------------------
 
-struct PlaceArgs {
-  Ctl* ctl;
-  const uint64_t* keys;
-  const uint64_t* vals_in;
-  const uint32_t* leader;
-  const uint32_t* lastw;
-  const uint32_t* fin;
-  const uint32_t* chosen;
-  const uint32_t* hrow;
-  const uint32_t* hslot;
-  const uint64_t* fval;
-  const uint2* rpair;
-  uint32_t q, epoch, Z, W, d, vw;
-  uint64_t K, R, PW;
-  uint32_t* load;
-  uint64_t* st_used;
-  uint64_t* st_key;
-  uint64_t* st_val;
-  uint32_t* st_dest;
-  uint32_t* st_dead;
-  uint32_t* rev_cnt;
-  uint32_t* rev_idx;
-  uint64_t* claim;
-  uint32_t* cand_bin;
-  uint2* pm_pair;
-  const uint32_t* pm_mask;
-  uint32_t* rowsel;
-};
+
 
 // Stores an item in a fresh stash entry listed under bin b.
 __device__ __forceinline__ bool stash_put(uint64_t* st_used, uint64_t PW, uint64_t* st_key, uint64_t* st_val,
@@ -597,7 +726,10 @@ __device__ __forceinline__ bool stash_put(uint64_t* st_used, uint64_t PW, uint64
   return true;
 }
 
-__global__ __launch_bounds__(256) void k_acc_place(PlaceArgs a) {
+template <bool MULTI>
+__global__ __launch_bounds__(256) void k_acc_place(PlaceArgs a1, const AccessPlan* tab) {
+  BOLT_PICK(PlaceArgs, pa);
+  if (!a.enabled) return;
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (a.ctl->reject == a.epoch || a.ctl->err) return;
   bool placed = false, ins = false;
@@ -652,35 +784,12 @@ __global__ __launch_bounds__(256) void k_acc_place(PlaceArgs a) {
 constexpr uint32_t kRemapNT = 1024;
 constexpr uint32_t kRemapPer = kMaxBatch / kRemapNT;
 
-struct RemapArgs {
-  Ctl* ctl;
-  const uint64_t* keys;
-  const uint64_t* vals_in;
-  const uint32_t* leader;
-  const uint32_t* lastw;
-  const uint32_t* fin;
-  const uint32_t* hrow;
-  const uint32_t* hslot;
-  const uint64_t* fval;
-  const uint2* rpair;
-  uint32_t q, epoch, Z, W, d, vw;
-  uint64_t B, K, R, PW;
-  uint32_t* load;
-  uint64_t* st_used;
-  uint64_t* st_key;
-  uint64_t* st_val;
-  uint32_t* st_dest;
-  uint32_t* st_dead;
-  uint32_t* rev_cnt;
-  uint32_t* rev_idx;
-  uint64_t* claim;
-  uint32_t* cand_bin;
-  uint64_t* pm_key;
-  uint2* pm_pair;
-  uint32_t* pm_mask;
-};
 
-__global__ __launch_bounds__(kRemapNT) void k_acc_remap(RemapArgs a) {
+
+template <bool MULTI>
+__global__ __launch_bounds__(kRemapNT) void k_acc_remap(RemapArgs a1, const AccessPlan* tab) {
+  BOLT_PICK(RemapArgs, ra);
+  if (!a.enabled) return;
   __shared__ uint32_t tot;
   __shared__ uint32_t s_skip;
   if (threadIdx.x == 0) s_skip = (a.ctl->reject == a.epoch || a.ctl->err) ? 1 : 0;
@@ -811,25 +920,7 @@ __global__ __launch_bounds__(kRemapNT) void k_acc_remap(RemapArgs a) {
 // write-back with eviction: one wave per candidate slot
 // ---------------------------------------------------------------------------
 
-struct WbArgs {
-  Ctl* ctl;
-  uint32_t q, epoch, Z, vw;
-  uint64_t K, pw;
-  const uint32_t* cand_bin;
-  const uint64_t* claim;
-  uint64_t* rmask;
-  const uint64_t* stage;
-  uint64_t* obs;
-  uint64_t* hbm;
-  uint32_t* rev_cnt;
-  const uint32_t* rev_idx;
-  const uint64_t* st_key;
-  const uint64_t* st_val;
-  uint32_t* st_dead;
-  uint64_t* st_used;
-  uint32_t* freed;   // [kFreeBuckets] entries freed, summed by finish
-  uint32_t* tlog_w;  // [3q] or null
-};
+
 
 constexpr uint32_t kWbItems = 192;  // Z survivors + 2Z listed stash entries, Z <= 62
 constexpr uint32_t kFreeBuckets = 256;
@@ -841,7 +932,9 @@ __host__ __device__ constexpr uint64_t wb_lds_bytes(uint64_t pw) { return pw * 8
 // the bin's old page into LDS (observable pages from the stage the fetch
 // wrote, HBM bins from HBM), so the rebuilt page can be written in place
 // without any device-wide fence.
-__global__ __launch_bounds__(64) void k_acc_writeback(WbArgs a) {
+template <bool MULTI>
+__global__ __launch_bounds__(64) void k_acc_writeback(WbArgs a1, const AccessPlan* tab) {
+  BOLT_PICK(WbArgs, wa);
   extern __shared__ uint64_t dyn[];
   uint64_t* old = dyn;
   uint64_t* ikey = dyn + a.pw;
@@ -937,20 +1030,11 @@ __global__ __launch_bounds__(64) void k_acc_writeback(WbArgs a) {
 // finish: position-map inserts of the one-round case, then the counters
 // ---------------------------------------------------------------------------
 
-struct FinishArgs {
-  Ctl* ctl;
-  uint32_t q, W, epoch;
-  uint64_t cap, stash_bound;
-  const uint32_t* rowsel;
-  const uint64_t* keys;
-  const uint2* rpair;
-  uint32_t* freed;
-  uint64_t* pm_key;
-  uint2* pm_pair;
-  uint32_t* pm_mask;
-};
 
-__global__ __launch_bounds__(256) void k_acc_finish(FinishArgs a) {
+
+template <bool MULTI>
+__global__ __launch_bounds__(256) void k_acc_finish(FinishArgs a1, const AccessPlan* tab) {
+  BOLT_PICK(FinishArgs, fn);
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (a.ctl->reject == a.epoch) return;
   const bool ok = !a.ctl->err;
@@ -993,8 +1077,9 @@ __global__ void k_fill_u32(uint32_t* p, uint64_t n, uint32_t v) {
 
 // ---------------------------------------------------------------------------
 
-int run_access(bolt_map* m, const uint8_t* ops, const uint64_t* keys, const void* vals_in, void* vals_out,
-               uint8_t* status, uint32_t q, hipStream_t st) {
+// Fills every kernel argument of one map's batch; reserves its trace words.
+static void plan_access(bolt_map* m, const uint8_t* ops, const uint64_t* keys, const void* vals_in, void* vals_out,
+                        uint8_t* status, uint32_t q, hipStream_t st, AccessPlan& P) {
   const Sizes& s = m->s;
   const BatchScratch& bs = m->bs;
   const uint32_t epoch = (uint32_t)(m->batches + 1);
@@ -1014,14 +1099,18 @@ int run_access(bolt_map* m, const uint8_t* ops, const uint64_t* keys, const void
       m->tlog_lost = true;
     }
   }
-  {
-    TimedScope ts(m->timer, kkAccDedup, st);
-    hipLaunchKernelGGL(k_acc_part, dim3(1), dim3(1024), 0, st, ops, keys, q, epoch, m->ctl, bs.pofs, bs.pkey, bs.pidx);
-    hipLaunchKernelGGL(k_acc_group, dim3(kParts), dim3(kDedupNT), 0, st, ops, epoch, m->ctl, bs.pofs, bs.pkey, bs.pidx,
-                       bs.leader, bs.prevw, bs.lastw);
-  }
+  memset(&P, 0, sizeof(P));
+  P.q = q;
+  P.fast = fast ? 1 : 0;
+  P.wb_lds = wb_lds_bytes(s.page_bytes / 8);
+  const uint32_t vw = s.vs / 8;
+  const uint64_t* vin = reinterpret_cast<const uint64_t*>(vals_in);
+  const uint64_t* fval = reinterpret_cast<const uint64_t*>(bs.fval);
 
-  FetchArgs fa;
+  P.pt = PartArgs{ops, keys, q, epoch, m->ctl, bs.pofs, bs.pkey, bs.pidx};
+  P.gr = GroupArgs{epoch, m->ctl, bs.pofs, bs.pkey, bs.pidx, bs.leader, bs.prevw, bs.lastw};
+
+  FetchArgs& fa = P.fa;
   fa.ctl = m->ctl;
   fa.ops = ops;
   fa.keys = keys;
@@ -1034,7 +1123,7 @@ int run_access(bolt_map* m, const uint8_t* ops, const uint64_t* keys, const void
   fa.Z = (uint32_t)s.Z;
   fa.W = (uint32_t)s.W;
   fa.d = (uint32_t)s.d;
-  fa.vw = s.vs / 8;
+  fa.vw = vw;
   fa.pw = s.page_bytes / 8;
   fa.pm_key = m->pm_key;
   fa.pm_pair = m->pm_pair;
@@ -1059,15 +1148,11 @@ int run_access(bolt_map* m, const uint8_t* ops, const uint64_t* keys, const void
   fa.rpair = bs.rpair;
   fa.tlog_r = tlog_r;
   fa.ctlw = m->ctl;
-  {
-    TimedScope ts(m->timer, kkAccFetch, st);
-    hipLaunchKernelGGL(k_acc_fetch, dim3((q + 3) / 4), dim3(256), 0, st, fa);
-  }
 
-  ResolveArgs rv;
+  ResolveArgs& rv = P.rv;
   rv.ctl = m->ctl;
   rv.ops = ops;
-  rv.vals_in = reinterpret_cast<const uint64_t*>(vals_in);
+  rv.vals_in = vin;
   rv.leader = bs.leader;
   rv.prevw = bs.prevw;
   rv.lastw = bs.lastw;
@@ -1075,106 +1160,97 @@ int run_access(bolt_map* m, const uint8_t* ops, const uint64_t* keys, const void
   rv.hrow = bs.hrow;
   rv.hslot = bs.hslot;
   rv.found = bs.found;
-  rv.fval = reinterpret_cast<const uint64_t*>(bs.fval);
+  rv.fval = fval;
   rv.rpair = bs.rpair;
   rv.load = m->load;
   rv.q = q;
-  rv.vw = s.vs / 8;
-  rv.fast = fast ? 1 : 0;
+  rv.vw = vw;
+  rv.fast = P.fast;
   rv.epoch = epoch;
   rv.vals_out = reinterpret_cast<uint64_t*>(vals_out);
   rv.status = status;
   rv.fin = bs.fin;
   rv.chosen = bs.chosen;
   rv.pm_mask = m->pm_mask;
-  {
-    TimedScope ts(m->timer, kkAccResolve, st);
-    hipLaunchKernelGGL(k_acc_resolve, dim3((q + 255) / 256), dim3(256), 0, st, rv);
-  }
 
-  if (fast) {
-    PlaceArgs pa;
-    pa.ctl = m->ctl;
-    pa.keys = keys;
-    pa.vals_in = reinterpret_cast<const uint64_t*>(vals_in);
-    pa.leader = bs.leader;
-    pa.lastw = bs.lastw;
-    pa.fin = bs.fin;
-    pa.chosen = bs.chosen;
-    pa.hrow = bs.hrow;
-    pa.hslot = bs.hslot;
-    pa.fval = reinterpret_cast<const uint64_t*>(bs.fval);
-    pa.rpair = bs.rpair;
-    pa.q = q;
-    pa.epoch = epoch;
-    pa.Z = (uint32_t)s.Z;
-    pa.W = (uint32_t)s.W;
-    pa.d = (uint32_t)s.d;
-    pa.vw = s.vs / 8;
-    pa.K = s.K;
-    pa.R = s.R;
-    pa.PW = s.PW;
-    pa.load = m->load;
-    pa.st_used = m->st_used;
-    pa.st_key = m->st_key;
-    pa.st_val = reinterpret_cast<uint64_t*>(m->st_val);
-    pa.st_dest = m->st_dest;
-    pa.st_dead = m->st_dead;
-    pa.rev_cnt = m->rev_cnt;
-    pa.rev_idx = m->rev_idx;
-    pa.claim = m->claim;
-    pa.cand_bin = bs.cand_bin;
-    pa.pm_pair = m->pm_pair;
-    pa.pm_mask = m->pm_mask;
-    pa.rowsel = bs.rowsel;
-    TimedScope ts(m->timer, kkAccRemap, st);
-    hipLaunchKernelGGL(k_acc_place, dim3((q + 255) / 256), dim3(256), 0, st, pa);
-  } else {
-    RemapArgs ra;
-    ra.ctl = m->ctl;
-    ra.keys = keys;
-    ra.vals_in = reinterpret_cast<const uint64_t*>(vals_in);
-    ra.leader = bs.leader;
-    ra.lastw = bs.lastw;
-    ra.fin = bs.fin;
-    ra.hrow = bs.hrow;
-    ra.hslot = bs.hslot;
-    ra.fval = reinterpret_cast<const uint64_t*>(bs.fval);
-    ra.rpair = bs.rpair;
-    ra.q = q;
-    ra.epoch = epoch;
-    ra.Z = (uint32_t)s.Z;
-    ra.W = (uint32_t)s.W;
-    ra.d = (uint32_t)s.d;
-    ra.vw = s.vs / 8;
-    ra.B = s.B;
-    ra.K = s.K;
-    ra.R = s.R;
-    ra.PW = s.PW;
-    ra.load = m->load;
-    ra.st_used = m->st_used;
-    ra.st_key = m->st_key;
-    ra.st_val = reinterpret_cast<uint64_t*>(m->st_val);
-    ra.st_dest = m->st_dest;
-    ra.st_dead = m->st_dead;
-    ra.rev_cnt = m->rev_cnt;
-    ra.rev_idx = m->rev_idx;
-    ra.claim = m->claim;
-    ra.cand_bin = bs.cand_bin;
-    ra.pm_key = m->pm_key;
-    ra.pm_pair = m->pm_pair;
-    ra.pm_mask = m->pm_mask;
-    TimedScope ts(m->timer, kkAccRemap, st);
-    hipLaunchKernelGGL(k_acc_remap, dim3(1), dim3(kRemapNT), 0, st, ra);
-  }
+  PlaceArgs& pa = P.pa;
+  pa.enabled = P.fast;
+  pa.ctl = m->ctl;
+  pa.keys = keys;
+  pa.vals_in = vin;
+  pa.leader = bs.leader;
+  pa.lastw = bs.lastw;
+  pa.fin = bs.fin;
+  pa.chosen = bs.chosen;
+  pa.hrow = bs.hrow;
+  pa.hslot = bs.hslot;
+  pa.fval = fval;
+  pa.rpair = bs.rpair;
+  pa.q = q;
+  pa.epoch = epoch;
+  pa.Z = (uint32_t)s.Z;
+  pa.W = (uint32_t)s.W;
+  pa.d = (uint32_t)s.d;
+  pa.vw = vw;
+  pa.K = s.K;
+  pa.R = s.R;
+  pa.PW = s.PW;
+  pa.load = m->load;
+  pa.st_used = m->st_used;
+  pa.st_key = m->st_key;
+  pa.st_val = reinterpret_cast<uint64_t*>(m->st_val);
+  pa.st_dest = m->st_dest;
+  pa.st_dead = m->st_dead;
+  pa.rev_cnt = m->rev_cnt;
+  pa.rev_idx = m->rev_idx;
+  pa.claim = m->claim;
+  pa.cand_bin = bs.cand_bin;
+  pa.pm_pair = m->pm_pair;
+  pa.pm_mask = m->pm_mask;
+  pa.rowsel = bs.rowsel;
 
-  const uint32_t wb_blocks = 3 * q;
-  WbArgs wa;
+  RemapArgs& ra = P.ra;
+  ra.enabled = !P.fast;
+  ra.ctl = m->ctl;
+  ra.keys = keys;
+  ra.vals_in = vin;
+  ra.leader = bs.leader;
+  ra.lastw = bs.lastw;
+  ra.fin = bs.fin;
+  ra.hrow = bs.hrow;
+  ra.hslot = bs.hslot;
+  ra.fval = fval;
+  ra.rpair = bs.rpair;
+  ra.q = q;
+  ra.epoch = epoch;
+  ra.Z = (uint32_t)s.Z;
+  ra.W = (uint32_t)s.W;
+  ra.d = (uint32_t)s.d;
+  ra.vw = vw;
+  ra.B = s.B;
+  ra.K = s.K;
+  ra.R = s.R;
+  ra.PW = s.PW;
+  ra.load = m->load;
+  ra.st_used = m->st_used;
+  ra.st_key = m->st_key;
+  ra.st_val = reinterpret_cast<uint64_t*>(m->st_val);
+  ra.st_dest = m->st_dest;
+  ra.st_dead = m->st_dead;
+  ra.rev_cnt = m->rev_cnt;
+  ra.rev_idx = m->rev_idx;
+  ra.claim = m->claim;
+  ra.cand_bin = bs.cand_bin;
+  ra.pm_key = m->pm_key;
+  ra.pm_pair = m->pm_pair;
+  ra.pm_mask = m->pm_mask;
+
+  WbArgs& wa = P.wa;
   wa.ctl = m->ctl;
   wa.q = q;
   wa.epoch = epoch;
   wa.Z = (uint32_t)s.Z;
-  wa.vw = s.vs / 8;
+  wa.vw = vw;
   wa.K = s.K;
   wa.pw = s.page_bytes / 8;
   wa.cand_bin = bs.cand_bin;
@@ -1191,12 +1267,8 @@ int run_access(bolt_map* m, const uint8_t* ops, const uint64_t* keys, const void
   wa.st_used = m->st_used;
   wa.freed = bs.freed;
   wa.tlog_w = tlog_w;
-  {
-    TimedScope ts(m->timer, kkAccWriteback, st);
-    hipLaunchKernelGGL(k_acc_writeback, dim3(wb_blocks), dim3(64), wb_lds_bytes(s.page_bytes / 8), st, wa);
-  }
 
-  FinishArgs fn;
+  FinishArgs& fn = P.fn;
   fn.ctl = m->ctl;
   fn.q = q;
   fn.W = (uint32_t)s.W;
@@ -1210,11 +1282,77 @@ int run_access(bolt_map* m, const uint8_t* ops, const uint64_t* keys, const void
   fn.pm_key = m->pm_key;
   fn.pm_pair = m->pm_pair;
   fn.pm_mask = m->pm_mask;
+  m->batches++;
+}
+
+int run_access(bolt_map* m, const uint8_t* ops, const uint64_t* keys, const void* vals_in, void* vals_out,
+               uint8_t* status, uint32_t q, hipStream_t st) {
+  AccessPlan P;
+  plan_access(m, ops, keys, vals_in, vals_out, status, q, st, P);
+  const AccessPlan* none = nullptr;
+  {
+    TimedScope ts(m->timer, kkAccDedup, st);
+    hipLaunchKernelGGL(k_acc_part<false>, dim3(1), dim3(1024), 0, st, P.pt, none);
+    hipLaunchKernelGGL(k_acc_group<false>, dim3(kParts), dim3(kDedupNT), 0, st, P.gr, none);
+  }
+  {
+    TimedScope ts(m->timer, kkAccFetch, st);
+    hipLaunchKernelGGL(k_acc_fetch<false>, dim3((q + 3) / 4), dim3(256), 0, st, P.fa, none);
+  }
+  {
+    TimedScope ts(m->timer, kkAccResolve, st);
+    hipLaunchKernelGGL(k_acc_resolve<false>, dim3((q + 255) / 256), dim3(256), 0, st, P.rv, none);
+  }
+  {
+    TimedScope ts(m->timer, kkAccRemap, st);
+    if (P.fast)
+      hipLaunchKernelGGL(k_acc_place<false>, dim3((q + 255) / 256), dim3(256), 0, st, P.pa, none);
+    else
+      hipLaunchKernelGGL(k_acc_remap<false>, dim3(1), dim3(kRemapNT), 0, st, P.ra, none);
+  }
+  {
+    TimedScope ts(m->timer, kkAccWriteback, st);
+    hipLaunchKernelGGL(k_acc_writeback<false>, dim3(3 * q), dim3(64), P.wb_lds, st, P.wa, none);
+  }
   {
     TimedScope ts(m->timer, kkAccMisc, st);
-    hipLaunchKernelGGL(k_acc_finish, dim3((q + 255) / 256), dim3(256), 0, st, fn);
+    hipLaunchKernelGGL(k_acc_finish<false>, dim3((q + 255) / 256), dim3(256), 0, st, P.fn, none);
   }
-  m->batches++;
+  return hipGetLastError() == hipSuccess ? BOLT_OK : BOLT_EHIP;
+}
+
+// One batch for each of `count` distinct maps, every phase one launch for
+// all of them (map = blockIdx.y).  The plans go to the device in one copy.
+int run_access_many(bolt_map* const* maps, const bolt_batch* batches, uint32_t count, hipStream_t st) {
+  std::vector<AccessPlan> plans(count);
+  uint32_t qmax = 0;
+  uint64_t lds = 0;
+  bool any_fast = false, any_slow = false;
+  for (uint32_t i = 0; i < count; ++i) {
+    const bolt_batch& b = batches[i];
+    plan_access(maps[i], b.d_ops, b.d_keys, b.d_vals_in, b.d_vals_out, b.d_status, b.q, st, plans[i]);
+    qmax = b.q > qmax ? b.q : qmax;
+    lds = plans[i].wb_lds > lds ? plans[i].wb_lds : lds;
+    any_fast |= plans[i].fast != 0;
+    any_slow |= plans[i].fast == 0;
+  }
+  AccessPlan* tab = nullptr;
+  const size_t bytes = sizeof(AccessPlan) * count;
+  if (hipMallocAsync((void**)&tab, bytes, st) != hipSuccess) return BOLT_ENOMEM;
+  if (hipMemcpyAsync(tab, plans.data(), bytes, hipMemcpyHostToDevice, st) != hipSuccess) {
+    (void)hipFreeAsync(tab, st);
+    return BOLT_EHIP;
+  }
+  const uint32_t C = count;
+  hipLaunchKernelGGL(k_acc_part<true>, dim3(1, C), dim3(1024), 0, st, plans[0].pt, tab);
+  hipLaunchKernelGGL(k_acc_group<true>, dim3(kParts, C), dim3(kDedupNT), 0, st, plans[0].gr, tab);
+  hipLaunchKernelGGL(k_acc_fetch<true>, dim3((qmax + 3) / 4, C), dim3(256), 0, st, plans[0].fa, tab);
+  hipLaunchKernelGGL(k_acc_resolve<true>, dim3((qmax + 255) / 256, C), dim3(256), 0, st, plans[0].rv, tab);
+  if (any_fast) hipLaunchKernelGGL(k_acc_place<true>, dim3((qmax + 255) / 256, C), dim3(256), 0, st, plans[0].pa, tab);
+  if (any_slow) hipLaunchKernelGGL(k_acc_remap<true>, dim3(1, C), dim3(kRemapNT), 0, st, plans[0].ra, tab);
+  hipLaunchKernelGGL(k_acc_writeback<true>, dim3(3 * qmax, C), dim3(64), lds, st, plans[0].wa, tab);
+  hipLaunchKernelGGL(k_acc_finish<true>, dim3((qmax + 255) / 256, C), dim3(256), 0, st, plans[0].fn, tab);
+  (void)hipFreeAsync(tab, st);
   return hipGetLastError() == hipSuccess ? BOLT_OK : BOLT_EHIP;
 }
 
