@@ -152,6 +152,16 @@ int bolt_get_batch(bolt_map* m, const uint64_t* d_keys, uint32_t q, void* d_vals
 int bolt_put_batch(bolt_map* m, const uint64_t* d_keys, const void* d_vals, uint32_t q, uint8_t* d_status,
                    void* hip_stream);
 
+/* Builds `count` distinct, not yet built maps (all on the current device)
+ * from their own key/value arrays: map i from d_keys[i], d_vals[i] and n[i],
+ * with the layout and errors of bolt_build.  Every phase of the build runs as
+ * one launch for all maps (map = second grid dimension), so many small maps
+ * cost about as many launches as the largest one alone.  Each map ends
+ * exactly as bolt_build would leave it.  Arguments are checked for every
+ * map before anything runs; a map may appear once per call. */
+int bolt_build_many(bolt_map* const* maps, const uint64_t* const* d_keys, const void* const* d_vals,
+                    const uint64_t* n, uint32_t count, void* hip_stream);
+
 /* One batch of commands for one map (the arguments of bolt_access_batch). */
 typedef struct {
   const uint8_t* d_ops;

@@ -82,6 +82,7 @@ _SIGS = [
     ("bolt_build", _I, [_P, _P, _P, _U64, _P]),
     ("bolt_access_batch", _I, [_P, _P, _P, _P, _P, _P, _U32, _P]),
     ("bolt_access_many", _I, [_P, _P, _U32, _P]),
+    ("bolt_build_many", _I, [_P, _P, _P, _P, _U32, _P]),
     ("bolt_get_batch", _I, [_P, _P, _U32, _P, _P, _P]),
     ("bolt_put_batch", _I, [_P, _P, _P, _U32, _P, _P]),
     ("bolt_destroy", _I, [_P]),
@@ -281,6 +282,19 @@ class Map:
                                a.ctypes.data_as(C.c_void_p), b.ctypes.data_as(C.c_void_p), n.value, C.byref(n)),
               "pm_snapshot")
         return sorted((int(r[i]), int(k[i]), int(a[i]), int(b[i])) for i in range(int(n.value)))
+
+
+def build_many(maps, inputs, stream=None) -> int:
+    """Builds every map of `maps` from its (keys, vals) device tensors, one launch per phase for all."""
+    n = len(maps)
+    if n != len(inputs):
+        raise ValueError("one input per map")
+    k = max(n, 1)
+    hs = (C.c_void_p * k)(*[m.h for m in maps])
+    ks = (C.c_void_p * k)(*[_dptr(a).value for a, _ in inputs])
+    vs = (C.c_void_p * k)(*[_dptr(b).value for _, b in inputs])
+    ns = (C.c_uint64 * k)(*[0 if a is None else a.numel() for a, _ in inputs])
+    return bolt_build_many(hs, ks, vs, ns, n, _stream(stream))
 
 
 def access_many(maps, batches, stream=None) -> int:

@@ -298,6 +298,33 @@ int bolt_build(bolt_map* m, const uint64_t* d_keys, const void* d_vals, uint64_t
   return BOLT_OK;
 }
 
+int bolt_build_many(bolt_map* const* maps, const uint64_t* const* d_keys, const void* const* d_vals,
+                    const uint64_t* n, uint32_t count, void* hip_stream) {
+  if (count == 0) return BOLT_OK;
+  if (!maps || !d_keys || !d_vals || !n) return BOLT_EINVAL;
+  for (uint32_t i = 0; i < count; ++i) {
+    bolt_map* m = maps[i];
+    int rc = map_check(m);
+    if (rc) return rc;
+    if (m->built || n[i] > m->s.cap) return BOLT_EINVAL;
+    if (m->device != maps[0]->device) return BOLT_EINVAL;
+    if (n[i] && (!d_keys[i] || !d_vals[i])) return BOLT_EINVAL;
+    if (((uintptr_t)d_keys[i] | (uintptr_t)d_vals[i]) & 7) return BOLT_EINVAL;
+    for (uint32_t j = 0; j < i; ++j)
+      if (maps[j] == m) return BOLT_EINVAL;
+  }
+  hipStream_t st = (hipStream_t)hip_stream;
+  if (hipSetDevice(maps[0]->device) != hipSuccess) return BOLT_EHIP;
+  int rc = count == 1 ? run_build(maps[0], d_keys[0], d_vals[0], n[0], st)
+                      : run_build_many(maps, d_keys, d_vals, n, count, st);
+  if (rc) return rc;
+  for (uint32_t i = 0; i < count; ++i) {
+    maps[i]->last_stream = st;
+    maps[i]->built = true;
+  }
+  return BOLT_OK;
+}
+
 int bolt_access_batch(bolt_map* m, const uint8_t* d_ops, const uint64_t* d_keys, const void* d_vals_in,
                       void* d_vals_out, uint8_t* d_status, uint32_t q, void* hip_stream) {
   int rc = map_check(m);

@@ -33,19 +33,6 @@ struct BatchScratch {
   uint32_t* pidx;     // [Q] command indexes grouped by partition
 };
 
-// Scratch of a build, allocated for the call and freed afterwards.
-struct BuildScratch {
-  uint2* pair;      // [n]
-  uint32_t* dest;   // [n]
-  uint64_t* tag;    // [npad]
-  uint64_t* elem;   // [BZ]
-  uint64_t* tmp;    // [BZ]
-  uint32_t* start;  // [B] first sorted position of each bin
-  uint32_t* bsum;   // scan partials
-  uint32_t* rowsel; // [n]
-  uint32_t* rowcnt; // [R]
-};
-
 struct TraceSeg {
   uint32_t batch;
   uint64_t offset;  // first word in the device log
@@ -142,11 +129,26 @@ namespace bolt {
 
 void launch_prf_key_setup(Ctl* ctl, const uint8_t key[32], hipStream_t st);
 void launch_prf_array(const Ctl* ctl, uint32_t domain, const uint64_t* x, uint64_t n, uint64_t* out, hipStream_t st);
+// One array of a many-array network launch: data, scratch of the same
+// length (expansion only), and the length (a power of two for the sort).
+struct NetSeg {
+  uint64_t* a;
+  uint64_t* b;
+  uint64_t n;
+};
+
 void launch_bitonic_sort(uint64_t* a, uint64_t n, hipStream_t st, KernelTimer* tm = nullptr);
+void launch_bitonic_sort_many(const NetSeg* segs, uint32_t count, uint64_t nmax, hipStream_t st);
 void launch_expand(uint64_t* a, uint64_t* tmp, uint64_t m, hipStream_t st, KernelTimer* tm = nullptr);
+// As launch_expand without the final copy: returns the buffer holding the result.
+uint64_t* launch_expand_inplace(uint64_t* a, uint64_t* tmp, uint64_t m, hipStream_t st, KernelTimer* tm = nullptr);
+// Returns true when every array's result ended in its scratch (b).
+bool launch_expand_many(const NetSeg* segs, uint32_t count, uint64_t mmax, hipStream_t st);
 
 void launch_map_init(bolt_map* m, hipStream_t st);
 int run_build(bolt_map* m, const uint64_t* keys, const void* vals, uint64_t n, hipStream_t st);
+int run_build_many(bolt_map* const* maps, const uint64_t* const* keys, const void* const* vals, const uint64_t* n,
+                   uint32_t count, hipStream_t st);
 int run_access(bolt_map* m, const uint8_t* ops, const uint64_t* keys, const void* vals_in, void* vals_out,
                uint8_t* status, uint32_t q, hipStream_t st);
 int run_access_many(bolt_map* const* maps, const bolt_batch* batches, uint32_t count, hipStream_t st);

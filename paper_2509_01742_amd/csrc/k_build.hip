@@ -13,7 +13,10 @@
 //       (Sec. 5.2), in rounds of ceil(R/16) keys; then a duplicate check.
 //
 // Grid shapes and trip counts depend only on n and the map's sizes.
+#include <string.h>
+
 #include <algorithm>
+#include <vector>
 
 #include "bolt_impl.h"
 
@@ -58,56 +61,88 @@ constexpr int kScanNT = 256;
 constexpr int kScanPer = 16;
 constexpr uint32_t kScanChunk = kScanNT * kScanPer;
 
-__global__ __launch_bounds__(kScanNT) void k_scan_reduce(const uint32_t* __restrict__ in, uint64_t n,
-                                                         uint32_t* __restrict__ bsum) {
+// Everything one map's build needs on the device: its sizes, state, inputs
+// and scratch.  A many-map launch reads the plan of map blockIdx.y from a
+// table; a one-map launch takes it by value.
+struct BuildPlan {
+  Ctl* ctl;
+  const uint64_t* keys;
+  const uint64_t* vals;
+  uint64_t n, npad, B, K, BZ, R, pw;
+  uint64_t rs, rsm;  // keys per P2C round, keys per position-map round
+  uint32_t Z, vw, W, d, nbs;
+  uint64_t* hbm;
+  uint64_t* obs;
+  uint32_t* tlog;  // write-out trace (M words) or null
+  uint32_t* load;
+  uint64_t* pm_key;
+  uint2* pm_pair;
+  uint32_t* pm_mask;
+  // scratch
+  uint2* pair;      // [n]
+  uint32_t* dest;   // [n]
+  uint64_t* tag;    // [npad]
+  uint64_t* elem;   // [BZ]
+  uint64_t* tmp;    // [BZ]
+  uint32_t* start;  // [B] first sorted position of each bin
+  uint32_t* bsum;   // [nbs + 1] scan partials, then the max-key counter
+  uint32_t* rowsel; // [n]
+  uint32_t* rowcnt; // [R]
+};
+
+#define BOLT_PLAN const BuildPlan& P = MULTI ? tab[blockIdx.y] : p1
+#define BOLT_PLAN_ARGS BuildPlan p1, const BuildPlan* tab
+
+// Exclusive scan of the bin loads into the first sorted position of each bin.
+template <bool MULTI>
+__global__ __launch_bounds__(kScanNT) void k_scan_reduce(BOLT_PLAN_ARGS) {
+  BOLT_PLAN;
+  if (blockIdx.x >= P.nbs) return;  // whole block
   const uint64_t base = (uint64_t)blockIdx.x * kScanChunk + (uint64_t)threadIdx.x * kScanPer;
   uint32_t s = 0;
 #pragma unroll
-  for (int i = 0; i < kScanPer; ++i) s += base + i < n ? in[base + i] : 0;
+  for (int i = 0; i < kScanPer; ++i) s += base + i < P.B ? P.load[base + i] : 0;
   __shared__ uint32_t tot;
   block_excl_scan<kScanNT>(s, &tot);
-  if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
+  if (threadIdx.x == 0) P.bsum[blockIdx.x] = tot;
 }
 
-// Exclusive scan of nb block sums in one block, chunk by chunk.
-__global__ __launch_bounds__(kScanNT) void k_scan_top(uint32_t* bsum, uint32_t nb) {
+// Exclusive scan of the block sums in one block, chunk by chunk.
+template <bool MULTI>
+__global__ __launch_bounds__(kScanNT) void k_scan_top(BOLT_PLAN_ARGS) {
+  BOLT_PLAN;
   __shared__ uint32_t tot;
   uint32_t carry = 0;
-  for (uint32_t c = 0; c < nb; c += kScanNT) {
+  for (uint32_t c = 0; c < P.nbs; c += kScanNT) {
     uint32_t i = c + threadIdx.x;
-    uint32_t v = i < nb ? bsum[i] : 0;
+    uint32_t v = i < P.nbs ? P.bsum[i] : 0;
     uint32_t e = block_excl_scan<kScanNT>(v, &tot);
     __syncthreads();
-    if (i < nb) bsum[i] = carry + e;
+    if (i < P.nbs) P.bsum[i] = carry + e;
     carry += tot;
     __syncthreads();
   }
 }
 
-__global__ __launch_bounds__(kScanNT) void k_scan_down(const uint32_t* __restrict__ in, uint64_t n,
-                                                       const uint32_t* __restrict__ bsum, uint32_t* __restrict__ out) {
+template <bool MULTI>
+__global__ __launch_bounds__(kScanNT) void k_scan_down(BOLT_PLAN_ARGS) {
+  BOLT_PLAN;
+  if (blockIdx.x >= P.nbs) return;  // whole block
   const uint64_t base = (uint64_t)blockIdx.x * kScanChunk + (uint64_t)threadIdx.x * kScanPer;
   uint32_t v[kScanPer];
   uint32_t s = 0;
 #pragma unroll
   for (int i = 0; i < kScanPer; ++i) {
-    v[i] = base + i < n ? in[base + i] : 0;
+    v[i] = base + i < P.B ? P.load[base + i] : 0;
     s += v[i];
   }
   __shared__ uint32_t tot;
-  uint32_t e = block_excl_scan<kScanNT>(s, &tot) + bsum[blockIdx.x];
+  uint32_t e = block_excl_scan<kScanNT>(s, &tot) + P.bsum[blockIdx.x];
 #pragma unroll
   for (int i = 0; i < kScanPer; ++i) {
-    if (base + i < n) out[base + i] = e;
+    if (base + i < P.B) P.start[base + i] = e;
     e += v[i];
   }
-}
-
-static void launch_excl_scan(const uint32_t* in, uint64_t n, uint32_t* bsum, uint32_t* out, hipStream_t st) {
-  uint32_t nb = (uint32_t)((n + kScanChunk - 1) / kScanChunk);
-  hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(kScanNT), 0, st, in, n, bsum);
-  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kScanNT), 0, st, bsum, nb);
-  hipLaunchKernelGGL(k_scan_down, dim3(nb), dim3(kScanNT), 0, st, in, n, bsum, out);
 }
 
 // ---------------------------------------------------------------------------
@@ -154,89 +189,101 @@ void launch_map_init(bolt_map* m, hipStream_t st) {
 // a1 + a2
 // ---------------------------------------------------------------------------
 
-__global__ void k_build_pairs(const Ctl* ctl, const uint64_t* __restrict__ keys, uint64_t n, uint64_t B,
-                              uint2* __restrict__ pair) {
+template <bool MULTI>
+__global__ void k_build_pairs(BOLT_PLAN_ARGS) {
+  BOLT_PLAN;
   uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
+  if (i >= P.n) return;
   uint32_t hk[8];
 #pragma unroll
-  for (int j = 0; j < 8; ++j) hk[j] = ctl->hkey[j];
+  for (int j = 0; j < 8; ++j) hk[j] = P.ctl->hkey[j];
   uint64_t w[4];
-  prf4(hk, kDomPair, keys[i], w);
+  prf4(hk, kDomPair, P.keys[i], w);
   uint32_t a, b;
-  pair_of(w[0], w[1], B, a, b);
-  pair[i] = make_uint2(a, b);
+  pair_of(w[0], w[1], P.B, a, b);
+  P.pair[i] = make_uint2(a, b);
 }
 
-__global__ void k_p2c_decide(const uint2* __restrict__ pair, const uint32_t* __restrict__ load, uint64_t r0,
-                             uint64_t r1, uint32_t* __restrict__ dest) {
+template <bool MULTI>
+__global__ void k_p2c_decide(BOLT_PLAN_ARGS, uint32_t round) {
+  BOLT_PLAN;
+  const uint64_t r0 = (uint64_t)round * P.rs, r1 = r0 + P.rs < P.n ? r0 + P.rs : P.n;
   uint64_t i = r0 + (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= r1) return;
-  uint2 p = pair[i];
-  dest[i] = load[p.y] < load[p.x] ? p.y : p.x;
+  uint2 p = P.pair[i];
+  P.dest[i] = P.load[p.y] < P.load[p.x] ? p.y : p.x;
 }
 
-__global__ void k_p2c_add(const uint32_t* __restrict__ dest, uint64_t r0, uint64_t r1, uint32_t* load) {
+template <bool MULTI>
+__global__ void k_p2c_add(BOLT_PLAN_ARGS, uint32_t round) {
+  BOLT_PLAN;
+  const uint64_t r0 = (uint64_t)round * P.rs, r1 = r0 + P.rs < P.n ? r0 + P.rs : P.n;
   uint64_t i = r0 + (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= r1) return;
-  atomicAdd(&load[dest[i]], 1u);
+  atomicAdd(&P.load[P.dest[i]], 1u);
 }
 
-__global__ void k_check_loads(const uint32_t* __restrict__ load, uint64_t B, uint32_t Z, Ctl* ctl) {
+template <bool MULTI>
+__global__ void k_check_loads(BOLT_PLAN_ARGS) {
+  BOLT_PLAN;
   uint64_t b = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  bool bad = b < B && load[b] > Z;
-  if (__any(bad) && (threadIdx.x & 63) == 0) set_err(ctl, kErrOverflow);
+  bool bad = b < P.B && P.load[b] > P.Z;
+  if (__any(bad) && (threadIdx.x & 63) == 0) set_err(P.ctl, kErrOverflow);
 }
 
 // ---------------------------------------------------------------------------
 // a3 + a4
 // ---------------------------------------------------------------------------
 
-__global__ void k_make_tags(const uint32_t* __restrict__ dest, uint64_t n, uint64_t npad, uint64_t* __restrict__ tag) {
+template <bool MULTI>
+__global__ void k_make_tags(BOLT_PLAN_ARGS) {
+  BOLT_PLAN;
   uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= npad) return;
-  uint64_t b = i < n ? dest[i] : 0xFFFFFFFFull;
-  tag[i] = (b << 32) | (uint32_t)i;
+  if (i >= P.npad) return;
+  uint64_t b = i < P.n ? P.dest[i] : 0xFFFFFFFFull;
+  P.tag[i] = (b << 32) | (uint32_t)i;
 }
 
 // Element for slot placement: (bin * Z + rank) << 32 | input index.
-__global__ void k_make_elems(const uint64_t* __restrict__ tag, uint64_t n, const uint32_t* __restrict__ start,
-                             uint64_t B, uint32_t Z, uint64_t BZ, uint64_t* __restrict__ elem, Ctl* ctl) {
+template <bool MULTI>
+__global__ void k_make_elems(BOLT_PLAN_ARGS) {
+  BOLT_PLAN;
   uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= BZ) return;
+  if (i >= P.BZ) return;
   uint64_t e = kNone64;
-  if (i < n) {
-    uint64_t t = tag[i];
+  if (i < P.n) {
+    uint64_t t = P.tag[i];
     uint32_t b = (uint32_t)(t >> 32);
-    uint64_t rank = b < B ? i - start[b] : Z;
-    if (rank < Z)
-      e = (((uint64_t)b * Z + rank) << 32) | (uint32_t)t;
+    uint64_t rank = b < P.B ? i - P.start[b] : P.Z;
+    if (rank < P.Z)
+      e = (((uint64_t)b * P.Z + rank) << 32) | (uint32_t)t;
     else
-      set_err(ctl, kErrOverflow);
+      set_err(P.ctl, kErrOverflow);
   }
-  elem[i] = e;
+  P.elem[i] = e;
 }
 
 // ---------------------------------------------------------------------------
-// a6: one wave per bin.
+// a6: one wave per bin.  `flip`: the expansion result is in tmp, not elem.
 // ---------------------------------------------------------------------------
 
-__global__ __launch_bounds__(256) void k_writeout(const uint64_t* __restrict__ elem, const uint64_t* __restrict__ keys,
-                                                  const uint64_t* __restrict__ vals, uint64_t B, uint64_t K, uint32_t Z,
-                                                  uint32_t vw, uint64_t pw, uint64_t* __restrict__ hbm,
-                                                  uint64_t* __restrict__ obs, uint32_t* __restrict__ tlog) {
+template <bool MULTI>
+__global__ __launch_bounds__(256) void k_writeout(BOLT_PLAN_ARGS, uint32_t flip) {
+  BOLT_PLAN;
   __shared__ uint32_t by_rank[4][64];
   __shared__ uint64_t key_rank[4][64];
+  const uint64_t* __restrict__ elem = flip ? P.tmp : P.elem;
+  const uint32_t Z = P.Z, vw = P.vw;
   const uint32_t lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const uint64_t b = (uint64_t)blockIdx.x * 4 + wid;
-  const bool active = b < B;  // no early return: the barrier below needs every wave
+  const bool active = b < P.B;  // no early return: the barrier below needs every wave
   uint32_t src = kNone;
   uint64_t key = 0;
   if (active && lane < Z) {
     uint64_t e = elem[b * Z + lane];
     if (e != kNone64) {
       src = (uint32_t)e;
-      key = keys[src];
+      key = P.keys[src];
     }
   }
   const bool valid = src != kNone;
@@ -256,7 +303,8 @@ __global__ __launch_bounds__(256) void k_writeout(const uint64_t* __restrict__ e
   }
   __syncthreads();
   if (!active) return;
-  uint64_t* dst = b < K ? hbm + b * pw : obs + (b - K) * pw;
+  const uint64_t pw = P.pw;
+  uint64_t* dst = b < P.K ? P.hbm + b * pw : P.obs + (b - P.K) * pw;
   for (uint64_t w = lane; w < pw; w += 64) {
     uint64_t v = 0;
     if (w == 0) {
@@ -267,11 +315,11 @@ __global__ __launch_bounds__(256) void k_writeout(const uint64_t* __restrict__ e
     } else if (w < 1 + Z + (uint64_t)Z * vw) {
       uint64_t off = w - 1 - Z;
       uint32_t j = (uint32_t)(off / vw), o = (uint32_t)(off % vw);
-      v = j < cnt ? vals[(uint64_t)by_rank[wid][j] * vw + o] : 0;
+      v = j < cnt ? P.vals[(uint64_t)by_rank[wid][j] * vw + o] : 0;
     }
     dst[w] = v;
   }
-  if (tlog && b >= K && lane == 0) tlog[b - K] = (uint32_t)(b - K);
+  if (P.tlog && b >= P.K && lane == 0) P.tlog[b - P.K] = (uint32_t)(b - P.K);
 }
 
 // ---------------------------------------------------------------------------
@@ -287,153 +335,160 @@ __device__ __forceinline__ void pm_rows_of(const uint32_t hk[8], uint64_t key, u
   for (uint32_t j = d; j < 4; ++j) rows[j] = rows[0];
 }
 
-__global__ void k_pm_decide(const Ctl* ctl, const uint64_t* __restrict__ keys, uint64_t r0, uint64_t r1, uint64_t R,
-                            uint32_t d, const uint32_t* __restrict__ rowcnt, uint32_t* __restrict__ rowsel) {
+// Row counters and the max-key counter start at zero (a kernel, not a
+// memset, so the sequence can be captured in a graph).
+template <bool MULTI>
+__global__ void k_build_zero(BOLT_PLAN_ARGS) {
+  BOLT_PLAN;
+  uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < P.R) P.rowcnt[i] = 0;
+  if (i == 0) P.bsum[P.nbs] = 0;
+}
+
+template <bool MULTI>
+__global__ void k_pm_decide(BOLT_PLAN_ARGS, uint32_t round) {
+  BOLT_PLAN;
+  const uint64_t r0 = (uint64_t)round * P.rsm, r1 = r0 + P.rsm < P.n ? r0 + P.rsm : P.n;
   uint64_t i = r0 + (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= r1) return;
   uint32_t hk[8];
 #pragma unroll
-  for (int j = 0; j < 8; ++j) hk[j] = ctl->hkey[j];
+  for (int j = 0; j < 8; ++j) hk[j] = P.ctl->hkey[j];
   uint32_t rows[4];
-  pm_rows_of(hk, keys[i], R, d, rows);
-  uint32_t best = rows[0], bc = rowcnt[rows[0]];
-  for (uint32_t j = 1; j < d; ++j) {
-    uint32_t c = rowcnt[rows[j]];
+  pm_rows_of(hk, P.keys[i], P.R, P.d, rows);
+  uint32_t best = rows[0], bc = P.rowcnt[rows[0]];
+  for (uint32_t j = 1; j < P.d; ++j) {
+    uint32_t c = P.rowcnt[rows[j]];
     if (c < bc) {
       bc = c;
       best = rows[j];
     }
   }
-  rowsel[i] = best;
+  P.rowsel[i] = best;
 }
 
-__global__ void k_pm_add(const uint64_t* __restrict__ keys, const uint2* __restrict__ pair,
-                         const uint32_t* __restrict__ rowsel, uint64_t r0, uint64_t r1, uint32_t W, uint32_t* rowcnt,
-                         uint64_t* __restrict__ pm_key, uint2* __restrict__ pm_pair, Ctl* ctl) {
+template <bool MULTI>
+__global__ void k_pm_add(BOLT_PLAN_ARGS, uint32_t round) {
+  BOLT_PLAN;
+  const uint64_t r0 = (uint64_t)round * P.rsm, r1 = r0 + P.rsm < P.n ? r0 + P.rsm : P.n;
   uint64_t i = r0 + (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= r1) return;
-  uint32_t r = rowsel[i];
-  uint32_t slot = atomicAdd(&rowcnt[r], 1u);
-  if (slot < W) {
-    pm_key[(uint64_t)r * W + slot] = keys[i];
-    pm_pair[(uint64_t)r * W + slot] = pair[i];
+  uint32_t r = P.rowsel[i];
+  uint32_t slot = atomicAdd(&P.rowcnt[r], 1u);
+  if (slot < P.W) {
+    P.pm_key[(uint64_t)r * P.W + slot] = P.keys[i];
+    P.pm_pair[(uint64_t)r * P.W + slot] = P.pair[i];
   } else {
-    set_err(ctl, kErrOverflow);
+    set_err(P.ctl, kErrOverflow);
   }
 }
 
-__global__ void k_pm_masks(const uint32_t* __restrict__ rowcnt, uint64_t R, uint32_t W, uint32_t* __restrict__ mask) {
+template <bool MULTI>
+__global__ void k_pm_masks(BOLT_PLAN_ARGS) {
+  BOLT_PLAN;
   uint64_t r = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= R) return;
-  uint32_t c = rowcnt[r] < W ? rowcnt[r] : W;
-  mask[r] = c >= 32 ? 0xFFFFFFFFu : ((1u << c) - 1);
+  if (r >= P.R) return;
+  uint32_t c = P.rowcnt[r] < P.W ? P.rowcnt[r] : P.W;
+  P.pm_mask[r] = c >= 32 ? 0xFFFFFFFFu : ((1u << c) - 1);
 }
 
 // Duplicate check: the keys, sorted by the same network, are distinct iff no
 // two neighbours are equal.  Padding uses the largest key, so real copies of
-// that key are counted apart.
-__global__ void k_dup_fill(const uint64_t* __restrict__ keys, uint64_t n, uint64_t npad, uint64_t* __restrict__ tag,
-                           uint32_t* n_max) {
+// that key are counted apart (bsum[nbs]).
+template <bool MULTI>
+__global__ void k_dup_fill(BOLT_PLAN_ARGS) {
+  BOLT_PLAN;
   const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= npad) return;
-  const uint64_t k = i < n ? keys[i] : kNone64;
-  tag[i] = k;
-  if (i < n && k == kNone64) atomicAdd(n_max, 1u);
+  if (i >= P.npad) return;
+  const uint64_t k = i < P.n ? P.keys[i] : kNone64;
+  P.tag[i] = k;
+  if (i < P.n && k == kNone64) atomicAdd(&P.bsum[P.nbs], 1u);
 }
 
-__global__ void k_dup_adjacent(const uint64_t* __restrict__ tag, uint64_t npad, const uint32_t* n_max, Ctl* ctl) {
+template <bool MULTI>
+__global__ void k_dup_adjacent(BOLT_PLAN_ARGS) {
+  BOLT_PLAN;
   const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const bool dup = i + 1 < npad && tag[i] == tag[i + 1] && tag[i] != kNone64;
-  if (__any(dup) && (threadIdx.x & 63) == 0) set_err(ctl, kErrDup);
-  if (i == 0 && *n_max > 1) set_err(ctl, kErrDup);
+  const bool dup = i + 1 < P.npad && P.tag[i] == P.tag[i + 1] && P.tag[i] != kNone64;
+  if (__any(dup) && (threadIdx.x & 63) == 0) set_err(P.ctl, kErrDup);
+  if (i == 0 && P.bsum[P.nbs] > 1) set_err(P.ctl, kErrDup);
 }
 
-__global__ void k_build_finish(Ctl* ctl, uint64_t n) {
+template <bool MULTI>
+__global__ void k_build_finish(BOLT_PLAN_ARGS) {
+  BOLT_PLAN;
   if (threadIdx.x || blockIdx.x) return;
-  ctl->live = n;
-  ctl->steps = 0;
+  P.ctl->live = P.n;
+  P.ctl->steps = 0;
 }
 
 // ---------------------------------------------------------------------------
+// Host side: plans, one scratch arena per call, and the launch sequence
+// shared by the one-map and the many-map forms.
+// ---------------------------------------------------------------------------
 
 static uint32_t blocks_for(uint64_t n, uint32_t nt) { return (uint32_t)((n + nt - 1) / nt); }
+static uint64_t align256(uint64_t x) { return (x + 255) & ~255ull; }
 
-static void free_build_scratch(BuildScratch& b, hipStream_t st) {
-  void* ptrs[] = {b.pair, b.dest, b.tag, b.elem, b.tmp, b.start, b.bsum, b.rowsel, b.rowcnt};
-  for (void* p : ptrs)
-    if (p) (void)hipFreeAsync(p, st);
-}
-
-int run_build(bolt_map* m, const uint64_t* keys, const void* vals, uint64_t n, hipStream_t st) {
-  const Sizes& s = m->s;
+// Scratch bytes of one map's build of n keys.
+static uint64_t build_scratch_bytes(const Sizes& s, uint64_t n) {
   uint64_t npad = 1;
   while (npad < n) npad <<= 1;
-  BuildScratch b{};
-  size_t nn = n ? n : 1;
-  uint32_t nbs = (uint32_t)((s.B + kScanChunk - 1) / kScanChunk);
-  hipError_t e = hipSuccess;
-  e = e ? e : hipMallocAsync((void**)&b.pair, nn * sizeof(uint2), st);
-  e = e ? e : hipMallocAsync((void**)&b.dest, nn * sizeof(uint32_t), st);
-  e = e ? e : hipMallocAsync((void**)&b.tag, npad * sizeof(uint64_t), st);
-  e = e ? e : hipMallocAsync((void**)&b.elem, s.BZ * sizeof(uint64_t), st);
-  e = e ? e : hipMallocAsync((void**)&b.tmp, s.BZ * sizeof(uint64_t), st);
-  e = e ? e : hipMallocAsync((void**)&b.start, s.B * sizeof(uint32_t), st);
-  e = e ? e : hipMallocAsync((void**)&b.bsum, (nbs + 1) * sizeof(uint32_t), st);
-  e = e ? e : hipMallocAsync((void**)&b.rowsel, nn * sizeof(uint32_t), st);
-  e = e ? e : hipMallocAsync((void**)&b.rowcnt, s.R * sizeof(uint32_t), st);
-  if (e != hipSuccess) {
-    free_build_scratch(b, st);
-    return BOLT_ENOMEM;
-  }
-  const uint32_t NT = 256;
-  // a1
-  if (n) {
-    TimedScope ts(m->timer, kkPairs, st);
-    hipLaunchKernelGGL(k_build_pairs, dim3(blocks_for(n, NT)), dim3(NT), 0, st, m->ctl, keys, n, s.B, b.pair);
-  }
-  // a2
-  const uint64_t rs = (s.B + 15) / 16;
-  {
-    for (uint64_t r0 = 0; r0 < n; r0 += rs) {
-      uint64_t r1 = r0 + rs < n ? r0 + rs : n;
-      {
-        TimedScope ts(m->timer, kkP2C, st);
-        hipLaunchKernelGGL(k_p2c_decide, dim3(blocks_for(r1 - r0, NT)), dim3(NT), 0, st, b.pair, m->load, r0, r1,
-                           b.dest);
-      }
-      {
-        TimedScope ts(m->timer, kkP2C, st);
-        hipLaunchKernelGGL(k_p2c_add, dim3(blocks_for(r1 - r0, NT)), dim3(NT), 0, st, b.dest, r0, r1, m->load);
-      }
-    }
-  }
-  {
-    TimedScope ts(m->timer, kkBuildMisc, st);
-    hipLaunchKernelGGL(k_check_loads, dim3(blocks_for(s.B, NT)), dim3(NT), 0, st, m->load, s.B, (uint32_t)s.Z, m->ctl);
-  }
-  // a3
-  {
-    TimedScope ts(m->timer, kkBuildMisc, st);
-    hipLaunchKernelGGL(k_make_tags, dim3(blocks_for(npad, NT)), dim3(NT), 0, st, b.dest, n, npad, b.tag);
-  }
-  launch_bitonic_sort(b.tag, npad, st, m->timer);
-  // a4
-  {
-    TimedScope ts(m->timer, kkScan, st);
-    launch_excl_scan(m->load, s.B, b.bsum, b.start, st);
-  }
-  {
-    TimedScope ts(m->timer, kkScan, st);
-    hipLaunchKernelGGL(k_make_elems, dim3(blocks_for(s.BZ, NT)), dim3(NT), 0, st, b.tag, n, b.start, s.B, (uint32_t)s.Z,
-                       s.BZ, b.elem, m->ctl);
-  }
-  // a5
-  launch_expand(b.elem, b.tmp, s.BZ, st, m->timer);
-  // a6
-  uint32_t* tl = nullptr;
+  const uint64_t nn = n ? n : 1;
+  const uint64_t nbs = (s.B + kScanChunk - 1) / kScanChunk;
+  return align256(nn * 8) + align256(nn * 4) + align256(npad * 8) + 2 * align256(s.BZ * 8) + align256(s.B * 4) +
+         align256((nbs + 1) * 4) + align256(nn * 4) + align256(s.R * 4);
+}
+
+// Fills one map's plan; carves its scratch from `arena` (advanced).
+static void plan_build(bolt_map* m, const uint64_t* keys, const void* vals, uint64_t n, uint8_t*& arena,
+                       BuildPlan& P) {
+  const Sizes& s = m->s;
+  memset(&P, 0, sizeof(P));
+  uint64_t npad = 1;
+  while (npad < n) npad <<= 1;
+  const uint64_t nn = n ? n : 1;
+  P.ctl = m->ctl;
+  P.keys = keys;
+  P.vals = reinterpret_cast<const uint64_t*>(vals);
+  P.n = n;
+  P.npad = npad;
+  P.B = s.B;
+  P.K = s.K;
+  P.BZ = s.BZ;
+  P.R = s.R;
+  P.pw = s.page_bytes / 8;
+  P.rs = (s.B + 15) / 16;
+  P.rsm = (s.R + 15) / 16;
+  P.Z = (uint32_t)s.Z;
+  P.vw = s.vs / 8;
+  P.W = (uint32_t)s.W;
+  P.d = (uint32_t)s.d;
+  P.nbs = (uint32_t)((s.B + kScanChunk - 1) / kScanChunk);
+  P.hbm = reinterpret_cast<uint64_t*>(m->hbm);
+  P.obs = reinterpret_cast<uint64_t*>(m->obs);
+  P.load = m->load;
+  P.pm_key = m->pm_key;
+  P.pm_pair = m->pm_pair;
+  P.pm_mask = m->pm_mask;
+  auto take = [&arena](uint64_t bytes) {
+    uint8_t* p = arena;
+    arena += align256(bytes);
+    return p;
+  };
+  P.pair = reinterpret_cast<uint2*>(take(nn * 8));
+  P.dest = reinterpret_cast<uint32_t*>(take(nn * 4));
+  P.tag = reinterpret_cast<uint64_t*>(take(npad * 8));
+  P.elem = reinterpret_cast<uint64_t*>(take(s.BZ * 8));
+  P.tmp = reinterpret_cast<uint64_t*>(take(s.BZ * 8));
+  P.start = reinterpret_cast<uint32_t*>(take(s.B * 4));
+  P.bsum = reinterpret_cast<uint32_t*>(take(((uint64_t)P.nbs + 1) * 4));
+  P.rowsel = reinterpret_cast<uint32_t*>(take(nn * 4));
+  P.rowcnt = reinterpret_cast<uint32_t*>(take(s.R * 4));
+  P.tlog = nullptr;
   if (m->tlog) {
     if (m->tlog_used + s.M <= m->tlog_cap) {
-      tl = m->tlog + m->tlog_used;
+      P.tlog = m->tlog + m->tlog_used;
       TraceSeg g{0, m->tlog_used, 0, s.M};
       m->segs.push_back(g);
       m->tlog_used += s.M;
@@ -441,50 +496,159 @@ int run_build(bolt_map* m, const uint64_t* keys, const void* vals, uint64_t n, h
       m->tlog_lost = true;
     }
   }
-  {
-    TimedScope ts(m->timer, kkWriteout, st);
-    hipLaunchKernelGGL(k_writeout, dim3(blocks_for(s.B, 4)), dim3(256), 0, st, b.elem, keys,
-                       reinterpret_cast<const uint64_t*>(vals), s.B, s.K, (uint32_t)s.Z, s.vs / 8, s.page_bytes / 8,
-                       reinterpret_cast<uint64_t*>(m->hbm), reinterpret_cast<uint64_t*>(m->obs), tl);
+}
+
+#define BL(K, gx, nt, ...) hipLaunchKernelGGL(K<MULTI>, dim3((gx), C), dim3(nt), 0, st, p1, tab, ##__VA_ARGS__)
+
+// The build sequence (a1 .. a7 and the duplicate check).  The grids and
+// trip counts come from the largest map; each map's blocks past its own
+// sizes return at once.
+template <bool MULTI>
+static void build_launches(const std::vector<BuildPlan>& plans, const BuildPlan* tab, const NetSeg* dsort,
+                           const NetSeg* dexp, hipStream_t st, KernelTimer* tm) {
+  const BuildPlan& p1 = plans[0];
+  const uint32_t C = MULTI ? (uint32_t)plans.size() : 1;
+  uint64_t n = 0, npad = 0, B = 0, BZ = 0, R = 0, nbs = 0, rp = 0, rm = 0;
+  for (const BuildPlan& P : plans) {
+    n = std::max(n, P.n);
+    npad = std::max(npad, P.npad);
+    B = std::max(B, P.B);
+    BZ = std::max(BZ, P.BZ);
+    R = std::max(R, P.R);
+    nbs = std::max(nbs, (uint64_t)P.nbs);
+    rp = std::max(rp, (P.n + P.rs - 1) / P.rs);
+    rm = std::max(rm, (P.n + P.rsm - 1) / P.rsm);
   }
-  // a7
-  (void)hipMemsetAsync(b.rowcnt, 0, s.R * sizeof(uint32_t), st);
-  const uint64_t rsm = (s.R + 15) / 16;
-  {
-    for (uint64_t r0 = 0; r0 < n; r0 += rsm) {
-      uint64_t r1 = r0 + rsm < n ? r0 + rsm : n;
-      {
-        TimedScope ts(m->timer, kkPmBuild, st);
-        hipLaunchKernelGGL(k_pm_decide, dim3(blocks_for(r1 - r0, NT)), dim3(NT), 0, st, m->ctl, keys, r0, r1, s.R,
-                           (uint32_t)s.d, b.rowcnt, b.rowsel);
-      }
-      {
-        TimedScope ts(m->timer, kkPmBuild, st);
-        hipLaunchKernelGGL(k_pm_add, dim3(blocks_for(r1 - r0, NT)), dim3(NT), 0, st, keys, b.pair, b.rowsel, r0, r1,
-                           (uint32_t)s.W, b.rowcnt, m->pm_key, m->pm_pair, m->ctl);
-      }
+  uint64_t rs_max = 0, rsm_max = 0;
+  for (const BuildPlan& P : plans) {
+    rs_max = std::max(rs_max, std::min(P.rs, P.n));
+    rsm_max = std::max(rsm_max, std::min(P.rsm, P.n));
+  }
+  const uint32_t NT = 256;
+  // a1
+  if (n) {
+    TimedScope ts(tm, kkPairs, st);
+    BL(k_build_pairs, blocks_for(n, NT), NT);
+  }
+  // a2: rounds of ceil(B/16) keys
+  for (uint32_t r = 0; r < rp; ++r) {
+    {
+      TimedScope ts(tm, kkP2C, st);
+      BL(k_p2c_decide, blocks_for(rs_max, NT), NT, r);
     }
+    TimedScope ts(tm, kkP2C, st);
+    BL(k_p2c_add, blocks_for(rs_max, NT), NT, r);
   }
   {
-    TimedScope ts(m->timer, kkPmBuild, st);
-    hipLaunchKernelGGL(k_pm_masks, dim3(blocks_for(s.R, NT)), dim3(NT), 0, st, b.rowcnt, s.R, (uint32_t)s.W, m->pm_mask);
+    TimedScope ts(tm, kkBuildMisc, st);
+    BL(k_check_loads, blocks_for(B, NT), NT);
+  }
+  // a3
+  {
+    TimedScope ts(tm, kkBuildMisc, st);
+    BL(k_make_tags, blocks_for(npad, NT), NT);
+  }
+  if (MULTI)
+    launch_bitonic_sort_many(dsort, C, npad, st);
+  else
+    launch_bitonic_sort(p1.tag, p1.npad, st, tm);
+  // a4
+  {
+    TimedScope ts(tm, kkScan, st);
+    BL(k_scan_reduce, (uint32_t)nbs, kScanNT);
+    BL(k_scan_top, 1, kScanNT);
+    BL(k_scan_down, (uint32_t)nbs, kScanNT);
+  }
+  {
+    TimedScope ts(tm, kkScan, st);
+    BL(k_make_elems, blocks_for(BZ, NT), NT);
+  }
+  // a5
+  uint32_t flip = 0;
+  if (MULTI)
+    flip = launch_expand_many(dexp, C, BZ, st) ? 1 : 0;
+  else
+    flip = launch_expand_inplace(p1.elem, p1.tmp, p1.BZ, st, tm) != p1.elem ? 1 : 0;
+  // a6
+  {
+    TimedScope ts(tm, kkWriteout, st);
+    BL(k_writeout, blocks_for(B, 4), 256, flip);
+  }
+  // a7: rounds of ceil(R/16) keys
+  {
+    TimedScope ts(tm, kkPmBuild, st);
+    BL(k_build_zero, blocks_for(R, NT), NT);
+  }
+  for (uint32_t r = 0; r < rm; ++r) {
+    {
+      TimedScope ts(tm, kkPmBuild, st);
+      BL(k_pm_decide, blocks_for(rsm_max, NT), NT, r);
+    }
+    TimedScope ts(tm, kkPmBuild, st);
+    BL(k_pm_add, blocks_for(rsm_max, NT), NT, r);
+  }
+  {
+    TimedScope ts(tm, kkPmBuild, st);
+    BL(k_pm_masks, blocks_for(R, NT), NT);
   }
   // duplicate keys (the tag buffer is free after the write-out)
   if (n) {
-    (void)hipMemsetAsync(b.bsum + nbs, 0, sizeof(uint32_t), st);
     {
-      TimedScope ts(m->timer, kkDupcheck, st);
-      hipLaunchKernelGGL(k_dup_fill, dim3(blocks_for(npad, NT)), dim3(NT), 0, st, keys, n, npad, b.tag, b.bsum + nbs);
+      TimedScope ts(tm, kkDupcheck, st);
+      BL(k_dup_fill, blocks_for(npad, NT), NT);
     }
-    launch_bitonic_sort(b.tag, npad, st, m->timer);
-    TimedScope ts(m->timer, kkDupcheck, st);
-    hipLaunchKernelGGL(k_dup_adjacent, dim3(blocks_for(npad, NT)), dim3(NT), 0, st, b.tag, npad, b.bsum + nbs, m->ctl);
+    if (MULTI)
+      launch_bitonic_sort_many(dsort, C, npad, st);
+    else
+      launch_bitonic_sort(p1.tag, p1.npad, st, tm);
+    TimedScope ts(tm, kkDupcheck, st);
+    BL(k_dup_adjacent, blocks_for(npad, NT), NT);
   }
   {
-    TimedScope ts(m->timer, kkBuildMisc, st);
-    hipLaunchKernelGGL(k_build_finish, dim3(1), dim3(64), 0, st, m->ctl, n);
+    TimedScope ts(tm, kkBuildMisc, st);
+    BL(k_build_finish, 1, 64);
   }
-  free_build_scratch(b, st);
+}
+
+#undef BL
+
+int run_build(bolt_map* m, const uint64_t* keys, const void* vals, uint64_t n, hipStream_t st) {
+  uint8_t* arena = nullptr;
+  if (hipMallocAsync((void**)&arena, build_scratch_bytes(m->s, n), st) != hipSuccess) return BOLT_ENOMEM;
+  std::vector<BuildPlan> plans(1);
+  uint8_t* cur = arena;
+  plan_build(m, keys, vals, n, cur, plans[0]);
+  build_launches<false>(plans, nullptr, nullptr, nullptr, st, m->timer);
+  (void)hipFreeAsync(arena, st);
+  return hipGetLastError() == hipSuccess ? BOLT_OK : BOLT_EHIP;
+}
+
+int run_build_many(bolt_map* const* maps, const uint64_t* const* keys, const void* const* vals, const uint64_t* n,
+                   uint32_t count, hipStream_t st) {
+  uint64_t bytes = align256((uint64_t)count * sizeof(BuildPlan)) + 2 * align256((uint64_t)count * sizeof(NetSeg));
+  for (uint32_t i = 0; i < count; ++i) bytes += build_scratch_bytes(maps[i]->s, n[i]);
+  uint8_t* arena = nullptr;
+  if (hipMallocAsync((void**)&arena, bytes, st) != hipSuccess) return BOLT_ENOMEM;
+  BuildPlan* dtab = reinterpret_cast<BuildPlan*>(arena);
+  NetSeg* dsort = reinterpret_cast<NetSeg*>(arena + align256((uint64_t)count * sizeof(BuildPlan)));
+  NetSeg* dexp = dsort + count;  // same 256-byte alignment not needed for the second table
+  uint8_t* cur = arena + align256((uint64_t)count * sizeof(BuildPlan)) + 2 * align256((uint64_t)count * sizeof(NetSeg));
+  std::vector<BuildPlan> plans(count);
+  std::vector<NetSeg> segs(2 * (size_t)count);
+  for (uint32_t i = 0; i < count; ++i) {
+    plan_build(maps[i], keys[i], vals[i], n[i], cur, plans[i]);
+    segs[i] = NetSeg{plans[i].tag, nullptr, plans[i].npad};
+    segs[count + i] = NetSeg{plans[i].elem, plans[i].tmp, plans[i].BZ};
+  }
+  hipError_t e = hipMemcpyAsync(dtab, plans.data(), count * sizeof(BuildPlan), hipMemcpyHostToDevice, st);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(dsort, segs.data(), 2 * (size_t)count * sizeof(NetSeg), hipMemcpyHostToDevice, st);
+  if (e != hipSuccess) {
+    (void)hipFreeAsync(arena, st);
+    return BOLT_EHIP;
+  }
+  build_launches<true>(plans, dtab, dsort, dexp, st, nullptr);
+  (void)hipFreeAsync(arena, st);
   return hipGetLastError() == hipSuccess ? BOLT_OK : BOLT_EHIP;
 }
 

@@ -109,6 +109,12 @@ void launch_prf_array(const Ctl* ctl, uint32_t domain, const uint64_t* x, uint64
 // Stages with j < T run in LDS on tiles of T elements; stages with j >= T run
 // as global passes, F strides per pass, each thread holding 2^F elements in
 // registers.
+//
+// Every kernel has a one-array form and a many-array form (MULTI): the
+// latter sorts array blockIdx.y of a table, each of its own power-of-two
+// length, with one launch per stage group for all of them.  The stage
+// sequence of a length-2^L network is a prefix of that of any longer one,
+// so an array simply sits out the stages past its own length.
 // ---------------------------------------------------------------------------
 
 __device__ __forceinline__ void cmpex(uint64_t& x, uint64_t& y, bool asc) {
@@ -118,12 +124,32 @@ __device__ __forceinline__ void cmpex(uint64_t& x, uint64_t& y, bool asc) {
   y = asc ? hi : lo;
 }
 
+__host__ __device__ __forceinline__ uint32_t ilog2_ceil(uint64_t n) {
+  uint32_t l = 0;
+  while ((1ull << l) < n) ++l;
+  return l;
+}
+
+constexpr int kSortLogT = 13;  // 8192-element LDS tiles (64 KiB)
+constexpr int kSortNT = 1024;
+constexpr int kSortFMax = 4;
+
 // LDS stages on one tile.  Mode 0: full tile sort, k = 2 .. T.  Mode 1: the
 // tail of merge step k (strides T/2 .. 1).
-template <int LOGT, int NT>
-__global__ __launch_bounds__(NT) void k_bitonic_tile(uint64_t* __restrict__ a, uint32_t logt, int mode,
-                                                     uint32_t k_log) {
+template <int LOGT, int NT, bool MULTI>
+__global__ __launch_bounds__(NT) void k_bitonic_tile(uint64_t* __restrict__ a1, uint32_t logt1, int mode,
+                                                     uint32_t k_log, const NetSeg* segs) {
   __shared__ uint64_t s[1 << LOGT];
+  uint64_t* __restrict__ a = a1;
+  uint32_t logt = logt1;
+  if (MULTI) {
+    const NetSeg g = segs[blockIdx.y];
+    const uint32_t L = ilog2_ceil(g.n);
+    if (mode == 1 && L < k_log) return;  // whole block: this array is shorter
+    logt = L < (uint32_t)LOGT ? L : (uint32_t)LOGT;
+    if (blockIdx.x >= (g.n >> logt)) return;
+    a = g.a;
+  }
   const uint32_t T = 1u << logt;
   const uint64_t base = (uint64_t)blockIdx.x * T;
   for (uint32_t x = threadIdx.x; x < T; x += NT) s[x] = a[base + x];
@@ -163,9 +189,17 @@ __global__ __launch_bounds__(NT) void k_bitonic_tile(uint64_t* __restrict__ a, u
 
 // F consecutive strides 2^(jl_top) .. 2^(jl_top - F + 1) of merge step k in
 // one pass over the array.
-template <int F>
-__global__ __launch_bounds__(256) void k_bitonic_global(uint64_t* __restrict__ a, uint64_t n, uint32_t k_log,
-                                                        uint32_t jl_top) {
+template <int F, bool MULTI>
+__global__ __launch_bounds__(256) void k_bitonic_global(uint64_t* __restrict__ a1, uint64_t n1, uint32_t k_log,
+                                                        uint32_t jl_top, const NetSeg* segs) {
+  uint64_t* __restrict__ a = a1;
+  uint64_t n = n1;
+  if (MULTI) {
+    const NetSeg g = segs[blockIdx.y];
+    if (ilog2_ceil(g.n) < k_log) return;
+    a = g.a;
+    n = g.n;
+  }
   const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= (n >> F)) return;
   const uint32_t low = jl_top - F + 1;
@@ -185,51 +219,47 @@ __global__ __launch_bounds__(256) void k_bitonic_global(uint64_t* __restrict__ a
   for (int x = 0; x < (1 << F); ++x) a[i0 + ((uint64_t)x << low)] = e[x];
 }
 
-constexpr int kSortLogT = 13;  // 8192-element LDS tiles (64 KiB)
-constexpr int kSortNT = 1024;
-constexpr int kSortFMax = 4;
-
-static uint32_t ilog2(uint64_t n) {
-  uint32_t l = 0;
-  while ((1ull << l) < n) ++l;
-  return l;
-}
-
-static void launch_global(uint64_t* a, uint64_t n, uint32_t k_log, uint32_t jl_top, int F, hipStream_t st,
+// One sort schedule for one array (segs == nullptr) or for `count` arrays
+// of the device table `segs` whose longest has length nmax.
+template <bool MULTI>
+static void sort_schedule(uint64_t* a, uint64_t nmax, const NetSeg* segs, uint32_t count, hipStream_t st,
                           KernelTimer* tm) {
-  TimedScope ts(tm, kkSortGlobal, st);
-  uint64_t threads = n >> F;
-  dim3 grid((uint32_t)((threads + 255) / 256)), block(256);
-  switch (F) {
-    case 1: hipLaunchKernelGGL(k_bitonic_global<1>, grid, block, 0, st, a, n, k_log, jl_top); break;
-    case 2: hipLaunchKernelGGL(k_bitonic_global<2>, grid, block, 0, st, a, n, k_log, jl_top); break;
-    case 3: hipLaunchKernelGGL(k_bitonic_global<3>, grid, block, 0, st, a, n, k_log, jl_top); break;
-    default: hipLaunchKernelGGL(k_bitonic_global<4>, grid, block, 0, st, a, n, k_log, jl_top); break;
-  }
-}
-
-void launch_bitonic_sort(uint64_t* a, uint64_t n, hipStream_t st, KernelTimer* tm) {
-  if (n < 2) return;
-  const uint32_t L = ilog2(n);
+  if (nmax < 2) return;
+  const uint32_t L = ilog2_ceil(nmax);
   const uint32_t logt = L < (uint32_t)kSortLogT ? L : (uint32_t)kSortLogT;
-  const uint64_t tiles = n >> logt;
+  const uint64_t tiles = nmax >> logt;
   {
     TimedScope ts(tm, kkSortTile, st);
-    hipLaunchKernelGGL((k_bitonic_tile<kSortLogT, kSortNT>), dim3((uint32_t)tiles), dim3(kSortNT), 0, st, a, logt, 0,
-                       0u);
+    hipLaunchKernelGGL((k_bitonic_tile<kSortLogT, kSortNT, MULTI>), dim3((uint32_t)tiles, count), dim3(kSortNT), 0,
+                       st, a, logt, 0, 0u, segs);
   }
   for (uint32_t k_log = logt + 1; k_log <= L; ++k_log) {
     int jl = (int)k_log - 1;
     while (jl >= (int)logt) {
       int F = jl - (int)logt + 1;
       if (F > kSortFMax) F = kSortFMax;
-      launch_global(a, n, k_log, (uint32_t)jl, F, st, tm);
+      TimedScope ts(tm, kkSortGlobal, st);
+      const dim3 grid((uint32_t)(((nmax >> F) + 255) / 256), count), block(256);
+      switch (F) {
+        case 1: hipLaunchKernelGGL((k_bitonic_global<1, MULTI>), grid, block, 0, st, a, nmax, k_log, (uint32_t)jl, segs); break;
+        case 2: hipLaunchKernelGGL((k_bitonic_global<2, MULTI>), grid, block, 0, st, a, nmax, k_log, (uint32_t)jl, segs); break;
+        case 3: hipLaunchKernelGGL((k_bitonic_global<3, MULTI>), grid, block, 0, st, a, nmax, k_log, (uint32_t)jl, segs); break;
+        default: hipLaunchKernelGGL((k_bitonic_global<4, MULTI>), grid, block, 0, st, a, nmax, k_log, (uint32_t)jl, segs); break;
+      }
       jl -= F;
     }
     TimedScope ts(tm, kkSortMerge, st);
-    hipLaunchKernelGGL((k_bitonic_tile<kSortLogT, kSortNT>), dim3((uint32_t)tiles), dim3(kSortNT), 0, st, a, logt,
-                       1, k_log);
+    hipLaunchKernelGGL((k_bitonic_tile<kSortLogT, kSortNT, MULTI>), dim3((uint32_t)tiles, count), dim3(kSortNT), 0,
+                       st, a, logt, 1, k_log, segs);
   }
+}
+
+void launch_bitonic_sort(uint64_t* a, uint64_t n, hipStream_t st, KernelTimer* tm) {
+  sort_schedule<false>(a, n, nullptr, 1, st, tm);
+}
+
+void launch_bitonic_sort_many(const NetSeg* segs, uint32_t count, uint64_t nmax, hipStream_t st) {
+  if (count) sort_schedule<true>(nullptr, nmax, segs, count, st, nullptr);
 }
 
 // ---------------------------------------------------------------------------
@@ -246,6 +276,10 @@ void launch_bitonic_sort(uint64_t* a, uint64_t n, hipStream_t st, KernelTimer* t
 // below 2^kExpLow then run in LDS on tiles of kExpTile outputs, each tile
 // loading the kExpHalo elements to its left (no element moves further than
 // 2^kExpLow - 1 in those stages).
+//
+// A stage with 2^j >= m is the identity (target - position < m), so the
+// many-array form runs the longest array's stages on every array.  Passes
+// alternate between an array and its scratch; `flip` says which way.
 // ---------------------------------------------------------------------------
 
 constexpr int kExpLow = 10;
@@ -258,19 +292,26 @@ __device__ __forceinline__ uint64_t exp_step(uint64_t cur, uint64_t prev, uint64
   return stay ? cur : (arrive ? prev : kNone64);
 }
 
-// One stage per pass (used for m too small for the fused forms).
-__global__ void k_expand_stage(const uint64_t* __restrict__ in, uint64_t* __restrict__ out, uint64_t m, uint32_t j) {
-  uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= m) return;
-  const uint64_t h = 1ull << j;
-  out[p] = exp_step(in[p], p >= h ? in[p - h] : kNone64, p, h);
+template <bool MULTI>
+__device__ __forceinline__ bool exp_pick(const NetSeg* segs, uint32_t flip, const uint64_t*& in, uint64_t*& out,
+                                         uint64_t& m) {
+  if (!MULTI) return true;
+  const NetSeg g = segs[blockIdx.y];
+  in = flip ? g.b : g.a;
+  out = flip ? g.a : g.b;
+  m = g.n;
+  return m >= 1;  // a one-element array is copied through unchanged
 }
 
 // Stages jlow + F - 1 .. jlow in one pass.  Thread = (residue r, block of
 // 2^F coordinates c0..); coordinate c is position c * 2^jlow + r.
-template <int F>
-__global__ __launch_bounds__(256) void k_expand_fused(const uint64_t* __restrict__ in, uint64_t* __restrict__ out,
-                                                      uint64_t m, uint32_t jlow) {
+template <int F, bool MULTI>
+__global__ __launch_bounds__(256) void k_expand_fused(const uint64_t* __restrict__ in1, uint64_t* __restrict__ out1,
+                                                      uint64_t m1, uint32_t jlow, const NetSeg* segs, uint32_t flip) {
+  const uint64_t* in = in1;
+  uint64_t* out = out1;
+  uint64_t m = m1;
+  if (!exp_pick<MULTI>(segs, flip, in, out, m)) return;
   constexpr int NB = 1 << F;      // outputs per thread
   constexpr int NW = 2 * NB - 1;  // window: NB - 1 to the left
   const uint64_t hl = 1ull << jlow;
@@ -278,7 +319,7 @@ __global__ __launch_bounds__(256) void k_expand_fused(const uint64_t* __restrict
   const uint64_t r = t & (hl - 1);
   const uint64_t c0 = (t >> jlow) * NB;
   const uint64_t ncoord = (m + hl - 1) >> jlow;
-  if (c0 >= ncoord) return;
+  if (c0 >= ncoord || r >= m) return;
   uint64_t v[NW];
 #pragma unroll
   for (int k = 0; k < NW; ++k) {
@@ -306,11 +347,17 @@ __global__ __launch_bounds__(256) void k_expand_fused(const uint64_t* __restrict
 }
 
 // Stages jtop .. 0 (jtop < kExpLow) on LDS tiles with a left halo.
-__global__ __launch_bounds__(1024) void k_expand_tile(const uint64_t* __restrict__ in, uint64_t* __restrict__ out,
-                                                     uint64_t m, int jtop) {
+template <bool MULTI>
+__global__ __launch_bounds__(1024) void k_expand_tile(const uint64_t* __restrict__ in1, uint64_t* __restrict__ out1,
+                                                     uint64_t m1, int jtop, const NetSeg* segs, uint32_t flip) {
+  const uint64_t* in = in1;
+  uint64_t* out = out1;
+  uint64_t m = m1;
+  if (!exp_pick<MULTI>(segs, flip, in, out, m)) return;
+  const uint64_t p0 = (uint64_t)blockIdx.x * kExpTile;
+  if (p0 >= m) return;  // whole block
   __shared__ uint64_t A[kExpTile + kExpHalo];
   __shared__ uint64_t Bf[kExpTile + kExpHalo];
-  const uint64_t p0 = (uint64_t)blockIdx.x * kExpTile;
   constexpr uint32_t NWIN = kExpTile + kExpHalo;
   for (uint32_t x = threadIdx.x; x < NWIN; x += 1024) {
     const int64_t pos = (int64_t)p0 - (int64_t)kExpHalo + x;
@@ -337,46 +384,60 @@ __global__ __launch_bounds__(1024) void k_expand_tile(const uint64_t* __restrict
   }
 }
 
-static void launch_fused(const uint64_t* in, uint64_t* out, uint64_t m, uint32_t jlow, int F, hipStream_t st) {
-  const uint64_t hl = 1ull << jlow;
-  const uint64_t ncoord = (m + hl - 1) >> jlow;
-  const uint64_t threads = ((ncoord + (1u << F) - 1) >> F) * hl;
-  dim3 grid((uint32_t)((threads + 255) / 256)), block(256);
-  switch (F) {
-    case 1: hipLaunchKernelGGL(k_expand_fused<1>, grid, block, 0, st, in, out, m, jlow); break;
-    case 2: hipLaunchKernelGGL(k_expand_fused<2>, grid, block, 0, st, in, out, m, jlow); break;
-    case 3: hipLaunchKernelGGL(k_expand_fused<3>, grid, block, 0, st, in, out, m, jlow); break;
-    default: hipLaunchKernelGGL(k_expand_fused<4>, grid, block, 0, st, in, out, m, jlow); break;
-  }
-}
-
-// Runs all stages; the result ends in `a` (tmp is scratch of m elements).
-void launch_expand(uint64_t* a, uint64_t* tmp, uint64_t m, hipStream_t st, KernelTimer* tm) {
-  if (m < 2) return;
+// Runs every stage for one array (segs == nullptr: a / tmp of length mmax)
+// or for the arrays of a device table.  Returns true when the result ended
+// in the scratch buffer (tmp, or each entry's b).
+template <bool MULTI>
+static bool expand_schedule(uint64_t* a, uint64_t* tmp, uint64_t mmax, const NetSeg* segs, uint32_t count,
+                            hipStream_t st, KernelTimer* tm) {
+  if (mmax < 2) return false;
   int top = 0;
-  while ((2ull << top) <= m - 1) ++top;
+  while ((2ull << top) <= mmax - 1) ++top;
   uint64_t* src = a;
   uint64_t* dst = tmp;
+  uint32_t flip = 0;
   int j = top;
   while (j >= kExpLow) {  // global passes, up to 4 stages each
     int F = j - kExpLow + 1;
     if (F > 4) F = 4;
     TimedScope ts(tm, kkExpand, st);
-    launch_fused(src, dst, m, (uint32_t)(j - F + 1), F, st);
+    const uint32_t jlow = (uint32_t)(j - F + 1);
+    const uint64_t hl = 1ull << jlow;
+    const uint64_t ncoord = (mmax + hl - 1) >> jlow;
+    const uint64_t threads = ((ncoord + (1u << F) - 1) >> F) * hl;
+    const dim3 grid((uint32_t)((threads + 255) / 256), count), block(256);
+    switch (F) {
+      case 1: hipLaunchKernelGGL((k_expand_fused<1, MULTI>), grid, block, 0, st, src, dst, mmax, jlow, segs, flip); break;
+      case 2: hipLaunchKernelGGL((k_expand_fused<2, MULTI>), grid, block, 0, st, src, dst, mmax, jlow, segs, flip); break;
+      case 3: hipLaunchKernelGGL((k_expand_fused<3, MULTI>), grid, block, 0, st, src, dst, mmax, jlow, segs, flip); break;
+      default: hipLaunchKernelGGL((k_expand_fused<4, MULTI>), grid, block, 0, st, src, dst, mmax, jlow, segs, flip); break;
+    }
     uint64_t* t = src;
     src = dst;
     dst = t;
+    flip ^= 1;
     j -= F;
   }
   {  // the low stages on LDS tiles
     TimedScope ts(tm, kkExpand, st);
-    hipLaunchKernelGGL(k_expand_tile, dim3((uint32_t)((m + kExpTile - 1) / kExpTile)), dim3(1024), 0, st, src, dst, m,
-                       j);
-    uint64_t* t = src;
-    src = dst;
-    dst = t;
+    hipLaunchKernelGGL((k_expand_tile<MULTI>), dim3((uint32_t)((mmax + kExpTile - 1) / kExpTile), count), dim3(1024),
+                       0, st, src, dst, mmax, j, segs, flip);
+    flip ^= 1;
   }
-  if (src != a) (void)hipMemcpyAsync(a, src, m * sizeof(uint64_t), hipMemcpyDeviceToDevice, st);
+  return flip != 0;
+}
+
+uint64_t* launch_expand_inplace(uint64_t* a, uint64_t* tmp, uint64_t m, hipStream_t st, KernelTimer* tm) {
+  return expand_schedule<false>(a, tmp, m, nullptr, 1, st, tm) ? tmp : a;
+}
+
+void launch_expand(uint64_t* a, uint64_t* tmp, uint64_t m, hipStream_t st, KernelTimer* tm) {
+  uint64_t* r = launch_expand_inplace(a, tmp, m, st, tm);
+  if (r != a) (void)hipMemcpyAsync(a, r, m * sizeof(uint64_t), hipMemcpyDeviceToDevice, st);
+}
+
+bool launch_expand_many(const NetSeg* segs, uint32_t count, uint64_t mmax, hipStream_t st) {
+  return count ? expand_schedule<true>(nullptr, nullptr, mmax, segs, count, st, nullptr) : false;
 }
 
 }  // namespace bolt

@@ -132,27 +132,108 @@ def test_access_many_argument_errors():
     assert a.g.stats()["steps"] == 0  # nothing ran
 
 
+# (capacity, keys, value bytes, params): tiny, empty, one-key, odd sizes,
+# a device-observable map, and maps past one sort tile and one expansion tile.
+BUILD_MIX = [
+    (64, 0, 8, {}), (64, 1, 8, {}), (64, 64, 8, {}), (1000, 777, 16, dict(alpha_permille=0)),
+    (4096, 3000, 64, {}), (1 << 14, (1 << 14) - 5, 8, dict(alpha_permille=10)),
+    (5000, 4321, 24, dict(alpha_permille=999)), (1 << 16, 1 << 16, 8, {}), (100000, 99999, 64, dict(c=4)),
+    (3000, 2900, 16, dict(observable=1)), (1 << 17, 100000, 8, dict(pm_choices=2, pm_keys_per_row=8)),
+]
+
+
+def test_build_many_matches_oracle_then_access_many():
+    import torch
+    import paper_2509_01742_amd as B
+
+    twins, inputs, keys = [], [], []
+    for j, (cap, n, vs, kw) in enumerate(BUILD_MIX):
+        t = Twin(cap, vs, key=bytes((5 * j + i) & 255 for i in range(32)), **kw)
+        k, v = workload(n, vs, 900 + j)
+        assert t.o.build(k, v) == 0
+        twins.append(t)
+        inputs.append((dev_u64(k) if n else None, dev_u8(v) if n else None))
+        keys.append(k)
+    order = list(range(len(BUILD_MIX)))[::-1]  # the largest map first
+    assert B.build_many([twins[j].g for j in order], [inputs[j] for j in order]) == 0
+    torch.cuda.synchronize()
+    for j, t in enumerate(twins):
+        assert t.g.status() == 0, j
+        t.assert_same_state()
+    # then one access round on all of them, checked against the oracle
+    rng = np.random.default_rng(7)
+    batches, host = [], []
+    for j, (cap, n, vs, kw) in enumerate(BUILD_MIX):
+        present = set(int(x) for x in keys[j])
+        q = int(rng.integers(1, min(cap, 2000) + 1))
+        ops, ks, vals = _mixed_batch(rng, present, synth.keys(5000, 31 + j, offset=10**8), q, vs)
+        if len(present) > cap - q:
+            ops[ops == 1] = 2
+        batches.append((dev_u8(ops), dev_u64(ks), dev_u8(vals), torch.zeros((q, vs), dtype=torch.uint8, device="cuda"),
+                        torch.zeros(q, dtype=torch.uint8, device="cuda")))
+        host.append((ops, ks, vals))
+    assert B.access_many([t.g for t in twins], batches) == 0
+    torch.cuda.synchronize()
+    for j, t in enumerate(twins):
+        rc_o, vo_o, st_o = t.o.access(*host[j])
+        assert rc_o == 0 and t.g.status() == 0, j
+        assert np.array_equal(batches[j][4].cpu().numpy(), st_o), j
+        assert np.array_equal(batches[j][3].cpu().numpy(), vo_o), j
+        t.assert_same_state()
+
+
+def test_build_many_errors_stay_per_map():
+    import torch
+    import paper_2509_01742_amd as B
+
+    good, dup, full = Twin(2000, 8), Twin(2000, 8), Twin(256, 8, pm_row_slots=1, pm_keys_per_row=64)
+    kg, vg = workload(1500, 8, 11)
+    kd, vd = workload(1500, 8, 12)
+    kd[700] = kd[3]  # a repeated key
+    kf, vf = workload(200, 8, 13)
+    assert good.o.build(kg, vg) == 0 and dup.o.build(kd, vd) == O.EDUPKEY and full.o.build(kf, vf) == O.EOVERFLOW
+    maps = [good.g, dup.g, full.g]
+    assert B.build_many(maps, [(dev_u64(kg), dev_u8(vg)), (dev_u64(kd), dev_u8(vd)), (dev_u64(kf), dev_u8(vf))]) == 0
+    torch.cuda.synchronize()
+    assert good.g.status() == 0 and dup.g.status() == B.BOLT_EDUPKEY and full.g.status() == B.BOLT_EOVERFLOW
+    good.assert_same_state()
+    # argument errors: nothing runs
+    fresh = [Twin(500, 8), Twin(500, 8)]
+    k, v = workload(400, 8, 14)
+    one = (dev_u64(k), dev_u8(v))
+    assert B.build_many([fresh[0].g, fresh[0].g], [one, one]) == B.BOLT_EINVAL
+    assert B.build_many([fresh[0].g, good.g], [one, one]) == B.BOLT_EINVAL  # already built
+    big = workload(600, 8, 15)
+    assert B.build_many([fresh[0].g, fresh[1].g], [one, (dev_u64(big[0]), dev_u8(big[1]))]) == B.BOLT_EINVAL
+    assert B.build_many([fresh[0].g, fresh[1].g], [one, one]) == 0
+    torch.cuda.synchronize()
+    assert fresh[0].o.build(k, v) == 0
+    fresh[0].assert_same_state()
+
+
 def _gpu_map(cap, vs, key):
     import paper_2509_01742_amd as B
 
     return B.Map(B.params(cap, vs, key=key))
 
 
-def test_access_many_equals_per_call_at_full_size():
-    """Sixty-four maps of 2^10..2^22 keys with one GET batch each of up to
-    8192 commands: the batched call and sixty-four one-map calls on twin maps
-    leave identical answers and pages, and every answer is the value the key
-    was built with (absent keys answer not-found with a zero value)."""
+def test_many_equals_per_call_at_full_size():
+    """Sixty-four maps of 2^10..2^22 keys, each built and then given one GET
+    batch of up to 8192 commands: the batched build and access and sixty-four
+    one-map calls on twin maps leave identical pages and answers, and every
+    answer is the value the key was built with (absent keys answer not-found
+    with a zero value)."""
     import torch
     import paper_2509_01742_amd as B
 
     work = synth.config4()
-    many, single, batches, expect = [], [], [], []
+    many, single, batches, expect, inputs = [], [], [], [], []
     for j, w in enumerate(work):
         key = bytes((j + i * 3) & 255 for i in range(32))
         g1, g2 = _gpu_map(w.cap, w.vs, key), _gpu_map(w.cap, w.vs, key)
         dk, dv = dev_u64(w.build_keys), dev_u8(w.build_vals)
-        assert g1.build(dk, dv) == 0 and g2.build(dk, dv) == 0
+        inputs.append((dk, dv))
+        assert g2.build(dk, dv) == 0
         ops, keys, _ = w.batches[0]
         q = ops.size
         batches.append((dev_u8(ops), dev_u64(keys), dev_u8(np.zeros((q, w.vs))),
@@ -166,7 +247,12 @@ def test_access_many_equals_per_call_at_full_size():
         expect.append((hit.astype(np.uint8), vals))
         many.append(g1)
         single.append(g2)
+    assert B.build_many(many, inputs) == 0  # the batched build, against 64 one-map builds
     torch.cuda.synchronize()
+    for j in range(len(work)):
+        assert many[j].status() == 0
+        assert np.array_equal(many[j].observable(), single[j].observable()), j
+        assert np.array_equal(many[j].hbm_bins(), single[j].hbm_bins()), j
     assert B.access_many(many, batches) == 0
     torch.cuda.synchronize()
     got = [(b[3].cpu().numpy().copy(), b[4].cpu().numpy().copy()) for b in batches]
