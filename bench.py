@@ -199,6 +199,7 @@ def main():
     ap.add_argument("--per-call", type=int, default=2048)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-batches", type=int, default=512)
+    ap.add_argument("--no-multi", action="store_true", help="skip the 64-map batched figures")
     ap.add_argument("--copy-calib", type=int, default=0,
                     help="MiB of a plain device copy run first (scales profiler byte counters)")
     args = ap.parse_args()
@@ -251,6 +252,10 @@ def main():
     roofline = roofline_of(main_res, dominant)
     roofline_sort = roofline_of(main_res, "sort_global")
 
+    multi = None
+    if not args.no_multi:
+        multi = run_multi(B, torch)
+        log("multi-map: %s" % json.dumps(multi))
     cpu = None if args.no_cpu_baseline else cpu_baseline(args.cpu_batches)
     sz = main_res["sizes"]
     out = {
@@ -279,9 +284,76 @@ def main():
         "roofline_sort": roofline_sort,
         "kernels": ks,
         "other_observable_mode": other,
+        "multi_map": multi,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
+
+
+def run_multi(B, torch, reps=3):
+    """Sixty-four maps (N log-uniform in 2^10..2^22, u64 keys and values),
+    each built and then given one GET batch of U[1, 8192] commands (uniform
+    present keys, 10 % absent): the many-map calls against 64 one-map calls
+    on the same GPU.  Fresh maps for every build repetition (a map is built
+    once); map creation is outside the timed regions."""
+    import synth
+
+    work = synth.config4()
+    dev = torch.device("cuda:0")
+    ins = [(torch.from_numpy(w.build_keys.view(np.int64)).to(dev), torch.from_numpy(w.build_vals).to(dev))
+           for w in work]
+    bts = []
+    for w in work:
+        ops, keys, _ = w.batches[0]
+        q = ops.size
+        bts.append((torch.from_numpy(ops).to(dev), torch.from_numpy(keys.view(np.int64)).to(dev),
+                    torch.zeros((q, w.vs), dtype=torch.uint8, device=dev),
+                    torch.zeros((q, w.vs), dtype=torch.uint8, device=dev),
+                    torch.zeros(q, dtype=torch.uint8, device=dev)))
+    total_keys = sum(w.n for w in work)
+    total_ops = sum(w.batches[0][0].size for w in work)
+
+    def fresh():
+        return [B.Map(B.params(w.cap, w.vs)) for w in work]
+
+    tb_many, tb_one, ta_many, ta_one = [], [], [], []
+    for r in range(reps):
+        ms, ones = fresh(), fresh()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        B.check(B.build_many(ms, ins), "bolt_build_many")
+        torch.cuda.synchronize()
+        tb_many.append(time.perf_counter() - t)
+        t = time.perf_counter()
+        for m, (k, v) in zip(ones, ins):
+            B.check(m.build(k, v), "bolt_build")
+        torch.cuda.synchronize()
+        tb_one.append(time.perf_counter() - t)
+        for _ in range(3):
+            t = time.perf_counter()
+            B.check(B.access_many(ms, bts), "bolt_access_many")
+            torch.cuda.synchronize()
+            ta_many.append(time.perf_counter() - t)
+            t = time.perf_counter()
+            for m, b in zip(ones, bts):
+                B.check(m.access(*b), "bolt_access_batch")
+            torch.cuda.synchronize()
+            ta_one.append(time.perf_counter() - t)
+        for m in ms + ones:
+            assert m.status() == 0
+            m.close()
+    med = lambda a: float(np.median(a))
+    return {"workload": "64 maps, N log-uniform in [2^10, 2^22], u64 keys/values, one GET batch each of U[1, 8192] "
+                        "(10 % absent); observable store in pinned host memory",
+            "maps": len(work), "total_keys": total_keys, "total_ops": total_ops,
+            "build_keys_per_s": {"many_map": round(total_keys / med(tb_many), 1),
+                                 "per_call": round(total_keys / med(tb_one), 1),
+                                 "speedup": round(med(tb_one) / med(tb_many), 3)},
+            "access_ops_per_s": {"many_map": round(total_ops / med(ta_many), 1),
+                                 "per_call": round(total_ops / med(ta_one), 1),
+                                 "speedup": round(med(ta_one) / med(ta_many), 3)},
+            "ms": {"build_many": round(1e3 * med(tb_many), 3), "build_per_call": round(1e3 * med(tb_one), 3),
+                   "access_many": round(1e3 * med(ta_many), 3), "access_per_call": round(1e3 * med(ta_one), 3)}}
 
 
 def cpu_baseline(n_batches):

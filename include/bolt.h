@@ -47,7 +47,8 @@ enum {
   BOLT_EOVERFLOW = -4, /* a bin, stash or position-map row would exceed its capacity */
   BOLT_EFULL = -5,     /* live keys would exceed the capacity (or the trace log is full) */
   BOLT_EHIP = -6,      /* a HIP runtime call failed */
-  BOLT_ESTATE = -7     /* the map is poisoned by an earlier device-side error */
+  BOLT_ESTATE = -7,    /* the map is poisoned by an earlier device-side error */
+  BOLT_ETIMEOUT = -8   /* a server wait ended before the work did */
 };
 
 /* Operation codes of a command <opcode | key | payload> (Sec. 5.1 step 2).
@@ -255,6 +256,108 @@ typedef struct {
 } bolt_kernel_time;
 int bolt_kernel_times(bolt_map* m, bolt_kernel_time* host_out, uint32_t cap, uint32_t* n);
 int bolt_kernel_times_reset(bolt_map* m);
+
+/* ---------------------------------------------------------------------
+ * Serving: many maps resident on the device behind one request loop.
+ *
+ * The library runs the loop on a thread of its own.  The caller's
+ * requests are host buffers (the paper's command and response buffers,
+ * Sec. 5.1); the loop copies commands to the device, runs them and copies
+ * the responses back into the caller's buffers.
+ *   - Admission: a map opened on the server is created and built on the
+ *     device when its footprint (bolt_footprint's device bytes plus its
+ *     command staging) fits the HBM budget next to the maps already there.
+ *     Maps are admitted in the order they were opened; requests to a map
+ *     that waits for admission wait with it.  Closing a map returns its
+ *     share once its queued requests are done.
+ *   - Continuous batching: whenever a map is idle and has queued requests,
+ *     the loop takes its queue head, as many whole requests as fit
+ *     max_batch commands, in submission order.  Every map taken in one turn
+ *     of the loop runs as one bolt_access_many on a free stream; requests
+ *     that arrive while groups run go into the next turn, on another stream,
+ *     so the work of different maps overlaps on the device.
+ *   - Results: the commands of one map run in submission order with the
+ *     semantics of bolt_access_batch, so a request's responses are the same
+ *     whether it runs alone or among others (requests of other maps never
+ *     change them).
+ *   - Latency: completion time minus the arrival time given at submission
+ *     (bolt_now_ns clock), so time spent waiting for admission, a stream or
+ *     the map counts.
+ * --------------------------------------------------------------------- */
+
+typedef struct bolt_server bolt_server; /* opaque, owned by the library */
+
+typedef struct {
+  uint64_t hbm_budget; /* device bytes the server's maps may hold together (0 = no limit) */
+  uint32_t streams;    /* HIP streams for groups in flight at once, 1..16 (0 = 4) */
+  uint32_t max_batch;  /* most commands of one map in one launch, 1..BOLT_MAX_BATCH (0 = BOLT_MAX_BATCH);
+                          also the largest request */
+  uint32_t flags;      /* must be 0 */
+} bolt_server_params;
+
+typedef struct {
+  uint64_t submitted, completed, failed; /* requests since the last reset */
+  uint64_t commands;                     /* commands of the completed requests */
+  uint64_t launches;                     /* groups launched */
+  uint64_t queued, queue_peak;           /* requests waiting for launch: now, most at once */
+  uint64_t maps_admitted;                /* admissions since the last reset */
+  uint64_t maps_resident, maps_waiting;  /* now */
+  uint64_t hbm_used, hbm_peak;           /* budgeted device bytes: now, most at once */
+  double lat_p50_ms, lat_p99_ms, lat_max_ms, lat_mean_ms; /* arrival to completion */
+  double span_s;                         /* first arrival to last completion */
+  double mean_group_maps, mean_group_commands;
+} bolt_server_stats;
+
+/* Map states reported by bolt_server_map_state. */
+enum { BOLT_SRV_WAITING = 0, BOLT_SRV_BUILDING = 1, BOLT_SRV_RESIDENT = 2, BOLT_SRV_CLOSED = 3, BOLT_SRV_FAILED = 4 };
+
+/* CLOCK_MONOTONIC in nanoseconds: the clock of arrival times. */
+uint64_t bolt_now_ns(void);
+
+/* Starts a server on the current device.  params may be NULL (defaults). */
+int bolt_server_create(const bolt_server_params* params, bolt_server** out);
+
+/* Registers a map with its build input (copied before the call returns;
+ * host_keys[n], host_vals[n * value_bytes]).  Tracing and timing flags are
+ * refused.  BOLT_EFULL if its footprint alone exceeds the budget.  The map
+ * is built when admitted; a build error fails its queued requests. */
+int bolt_server_open_map(bolt_server* srv, const bolt_params* params, const uint64_t* host_keys,
+                         const void* host_vals, uint64_t n, uint32_t* map_id);
+
+/* Closes a map: requests already queued still run; later submits fail. */
+int bolt_server_close_map(bolt_server* srv, uint32_t map_id);
+
+/* *state = BOLT_SRV_*; *err (may be NULL) = the error that failed the map. */
+int bolt_server_map_state(bolt_server* srv, uint32_t map_id, int* state, int* err);
+
+/* The device map behind map_id while it is resident (NULL otherwise), for
+ * inspection between requests; no call on it may overlap the server's work. */
+bolt_map* bolt_server_map(bolt_server* srv, uint32_t map_id);
+
+/* Queues a request of q commands (1 <= q <= max_batch) for a map.  The five
+ * host buffers are the request's commands and responses, laid out as in
+ * bolt_access_batch; they must stay valid until the request completes.
+ * Op codes above BOLT_OP_DEL are refused here (BOLT_EINVAL).  arrival_ns = 0
+ * stamps the request now.  *ticket names the request. */
+int bolt_server_submit(bolt_server* srv, uint32_t map_id, const uint8_t* host_ops, const uint64_t* host_keys,
+                       const void* host_vals_in, void* host_vals_out, uint8_t* host_status, uint32_t q,
+                       uint64_t arrival_ns, uint64_t* ticket);
+
+/* *result = 1 while the request is pending, else its return code. */
+int bolt_server_poll(bolt_server* srv, uint64_t ticket, int* result);
+
+/* Waits for one request: its return code, or BOLT_ETIMEOUT. */
+int bolt_server_wait(bolt_server* srv, uint64_t ticket, uint32_t timeout_ms);
+
+/* Waits until every submitted request has finished, or BOLT_ETIMEOUT. */
+int bolt_server_drain(bolt_server* srv, uint32_t timeout_ms);
+
+int bolt_server_get_stats(bolt_server* srv, bolt_server_stats* out);
+int bolt_server_reset_stats(bolt_server* srv);
+
+/* Stops the loop, waits for the device and frees every map of the server.
+ * Requests still pending are abandoned.  NULL is a no-op. */
+int bolt_server_destroy(bolt_server* srv);
 
 /* ---------------------------------------------------------------------
  * Device primitives of the path, exported so each can be checked alone.

@@ -22,9 +22,11 @@ BOLT_ST_ABSENT, BOLT_ST_FOUND, BOLT_ST_UPDATED, BOLT_ST_INSERTED, BOLT_ST_DELETE
 BOLT_OBS_HOST_PINNED, BOLT_OBS_DEVICE = 0, 1
 BOLT_F_TRACE, BOLT_F_FIXED_KEY, BOLT_F_TIMING = 1, 2, 4
 BOLT_MAX_BATCH = 8192
+BOLT_ETIMEOUT = -8
+BOLT_SRV_WAITING, BOLT_SRV_BUILDING, BOLT_SRV_RESIDENT, BOLT_SRV_CLOSED, BOLT_SRV_FAILED = 0, 1, 2, 3, 4
 
 _NAMES = {0: "BOLT_OK", -1: "BOLT_EINVAL", -2: "BOLT_ENOMEM", -3: "BOLT_EDUPKEY", -4: "BOLT_EOVERFLOW",
-          -5: "BOLT_EFULL", -6: "BOLT_EHIP", -7: "BOLT_ESTATE"}
+          -5: "BOLT_EFULL", -6: "BOLT_EHIP", -7: "BOLT_ESTATE", -8: "BOLT_ETIMEOUT"}
 
 
 class BoltError(RuntimeError):
@@ -70,6 +72,22 @@ class bolt_batch(C.Structure):
                 ("d_vals_out", C.c_void_p), ("d_status", C.c_void_p), ("q", C.c_uint32)]
 
 
+class bolt_server_params(C.Structure):
+    _fields_ = [("hbm_budget", C.c_uint64), ("streams", C.c_uint32), ("max_batch", C.c_uint32),
+                ("flags", C.c_uint32)]
+
+
+class bolt_server_stats(C.Structure):
+    _fields_ = [(n, C.c_uint64) for n in ("submitted", "completed", "failed", "commands", "launches", "queued",
+                                           "queue_peak", "maps_admitted", "maps_resident", "maps_waiting",
+                                           "hbm_used", "hbm_peak")] + \
+               [(n, C.c_double) for n in ("lat_p50_ms", "lat_p99_ms", "lat_max_ms", "lat_mean_ms", "span_s",
+                                          "mean_group_maps", "mean_group_commands")]
+
+    def as_dict(self):
+        return {n: getattr(self, n) for n, _ in self._fields_}
+
+
 TRACE_DTYPE = np.dtype([("batch", "<u4"), ("kind", "<u4"), ("page", "<u8")])
 
 # (name, restype, argtypes) of every entry point in include/bolt.h
@@ -98,6 +116,19 @@ _SIGS = [
     ("bolt_pm_snapshot", _I, [_P, _P, _P, _P, _P, _U64, C.POINTER(_U64)]),
     ("bolt_kernel_times", _I, [_P, _P, _U32, C.POINTER(_U32)]),
     ("bolt_kernel_times_reset", _I, [_P]),
+    ("bolt_now_ns", _U64, []),
+    ("bolt_server_create", _I, [C.POINTER(bolt_server_params), C.POINTER(_P)]),
+    ("bolt_server_open_map", _I, [_P, C.POINTER(bolt_params), _P, _P, _U64, C.POINTER(_U32)]),
+    ("bolt_server_close_map", _I, [_P, _U32]),
+    ("bolt_server_map_state", _I, [_P, _U32, C.POINTER(_I), C.POINTER(_I)]),
+    ("bolt_server_map", _P, [_P, _U32]),
+    ("bolt_server_submit", _I, [_P, _U32, _P, _P, _P, _P, _P, _U32, _U64, C.POINTER(_U64)]),
+    ("bolt_server_poll", _I, [_P, _U64, C.POINTER(_I)]),
+    ("bolt_server_wait", _I, [_P, _U64, _U32]),
+    ("bolt_server_drain", _I, [_P, _U32]),
+    ("bolt_server_get_stats", _I, [_P, C.POINTER(bolt_server_stats)]),
+    ("bolt_server_reset_stats", _I, [_P]),
+    ("bolt_server_destroy", _I, [_P]),
     ("bolt_prf", _I, [_P, _U8, _P, _U64, _P, _P]),
     ("bolt_sort_u64", _I, [_P, _U64, _P]),
     ("bolt_expand_u64", _I, [_P, _P, _U64, _P]),
@@ -310,6 +341,91 @@ def access_many(maps, batches, stream=None) -> int:
         bs[i] = bolt_batch(_dptr(ops).value, _dptr(keys).value, _dptr(vin).value, _dptr(vout).value,
                            _dptr(status).value, 0 if ops is None else ops.numel())
     return bolt_access_many(hs, bs, n, _stream(stream))
+
+
+class Server:
+    """A serving loop over many resident maps (requests are host numpy arrays)."""
+
+    def __init__(self, hbm_budget: int = 0, streams: int = 0, max_batch: int = 0):
+        sp = bolt_server_params(hbm_budget, streams, max_batch, 0)
+        h = C.c_void_p()
+        check(bolt_server_create(C.byref(sp), C.byref(h)), "bolt_server_create")
+        self.h = h
+        self._live = {}  # ticket -> the request's buffers (kept alive until done)
+
+    def close(self):
+        if self.h is not None and self.h.value:
+            bolt_server_destroy(self.h)
+        self.h = None
+        self._live.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def open_map(self, p: bolt_params, keys, vals) -> int:
+        k = np.ascontiguousarray(keys, dtype=np.uint64)
+        v = np.ascontiguousarray(vals, dtype=np.uint8)
+        mid = C.c_uint32()
+        check(bolt_server_open_map(self.h, C.byref(p), k.ctypes.data_as(C.c_void_p), v.ctypes.data_as(C.c_void_p),
+                                   k.size, C.byref(mid)), "bolt_server_open_map")
+        return mid.value
+
+    def close_map(self, mid: int) -> int:
+        return bolt_server_close_map(self.h, mid)
+
+    def map_state(self, mid: int):
+        st, err = C.c_int(), C.c_int()
+        check(bolt_server_map_state(self.h, mid, C.byref(st), C.byref(err)), "bolt_server_map_state")
+        return st.value, err.value
+
+    def submit(self, mid: int, ops, keys, vals_in, arrival_ns: int = 0):
+        """Queues one request; returns (ticket, vals_out, status), the last two
+        filled when the request completes."""
+        ops = np.ascontiguousarray(ops, dtype=np.uint8)
+        keys = np.ascontiguousarray(keys, dtype=np.uint64)
+        vals_in = np.ascontiguousarray(vals_in, dtype=np.uint8)
+        q = ops.size
+        vs = vals_in.size // max(q, 1)
+        vout = np.zeros((q, vs), np.uint8)
+        st = np.zeros(q, np.uint8)
+        t = C.c_uint64()
+        rc = bolt_server_submit(self.h, mid, ops.ctypes.data_as(C.c_void_p), keys.ctypes.data_as(C.c_void_p),
+                                vals_in.ctypes.data_as(C.c_void_p), vout.ctypes.data_as(C.c_void_p),
+                                st.ctypes.data_as(C.c_void_p), q, arrival_ns, C.byref(t))
+        if rc != BOLT_OK:
+            return rc, None, None
+        self._live[t.value] = (ops, keys, vals_in, vout, st)
+        return t.value, vout, st
+
+    def poll(self, ticket: int) -> int:
+        r = C.c_int()
+        check(bolt_server_poll(self.h, ticket, C.byref(r)), "bolt_server_poll")
+        if r.value != 1:
+            self._live.pop(ticket, None)
+        return r.value
+
+    def wait(self, ticket: int, timeout_ms: int = 60000) -> int:
+        rc = bolt_server_wait(self.h, ticket, timeout_ms)
+        if rc != BOLT_ETIMEOUT:
+            self._live.pop(ticket, None)
+        return rc
+
+    def drain(self, timeout_ms: int = 120000) -> int:
+        rc = bolt_server_drain(self.h, timeout_ms)
+        if rc == BOLT_OK:
+            self._live.clear()
+        return rc
+
+    def stats(self) -> dict:
+        s = bolt_server_stats()
+        check(bolt_server_get_stats(self.h, C.byref(s)), "bolt_server_get_stats")
+        return s.as_dict()
+
+    def reset_stats(self):
+        check(bolt_server_reset_stats(self.h), "bolt_server_reset_stats")
 
 
 def prf(key: bytes, domain: int, x, out, stream=None) -> int:

@@ -5,14 +5,14 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SOURCES = ["api.hip", "k_prim.hip", "k_build.hip", "k_access.hip"]
+SOURCES = ["api.hip", "k_prim.hip", "k_build.hip", "k_access.hip", "serve.hip"]
 LIB = os.path.join(HERE, "libbolt.so")
 
 
 def hipcc_flags():
     return [
         "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
-        # no packed-fp32 instructions (some of their forms misbehave on the test machines)
+        # keep packed-FP32 instructions out of the generated code
         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
         "-Wno-unused-result", "-I", os.path.join(ROOT, "include"),
     ]
