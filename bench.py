@@ -200,6 +200,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-batches", type=int, default=512)
     ap.add_argument("--no-multi", action="store_true", help="skip the 64-map batched figures")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving figures")
+    ap.add_argument("--serve-seconds", type=float, default=3.0, help="steady window of each open-loop serving run")
     ap.add_argument("--copy-calib", type=int, default=0,
                     help="MiB of a plain device copy run first (scales profiler byte counters)")
     args = ap.parse_args()
@@ -252,6 +254,9 @@ def main():
     roofline = roofline_of(main_res, dominant)
     roofline_sort = roofline_of(main_res, "sort_global")
 
+    serving = None
+    if not args.no_serving:
+        serving = run_serving(B, seconds=args.serve_seconds)
     multi = None
     if not args.no_multi:
         multi = run_multi(B, torch)
@@ -285,6 +290,7 @@ def main():
         "kernels": ks,
         "other_observable_mode": other,
         "multi_map": multi,
+        "serving": serving,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
@@ -354,6 +360,163 @@ def run_multi(B, torch, reps=3):
                                  "speedup": round(med(ta_one) / med(ta_many), 3)},
             "ms": {"build_many": round(1e3 * med(tb_many), 3), "build_per_call": round(1e3 * med(tb_one), 3),
                    "access_many": round(1e3 * med(ta_many), 3), "access_per_call": round(1e3 * med(ta_one), 3)}}
+
+
+def run_serving(B, seconds=3.0, rot_seconds=2.0, warm=1.0, pool=1 << 16, seed=0xB0170000 + 55):
+    """Sixteen maps (N log-uniform in 2^16..2^24, 64-byte values) behind the
+    serving loop.  The HBM budget holds twelve of them at a time: each run
+    serves twelve maps for its first half, then closes four and lets four
+    waiting ones in, whose builds are admitted as the closed maps leave.  Requests
+    arrive as a Poisson process (size floor(2^(12u)) clipped to [1, 4096],
+    90 % GET / 10 % PUT, Zipf 0.99 keys over the map's keys, none absent).
+    A request's commands are a slice of a per-map pool drawn the same way,
+    so the run allocates nothing per request.  First the saturation rate
+    (a backlog served as fast as the loop goes), then runs at 0.5x and 0.8x
+    of it, each a warm-up, a steady window (twelve resident maps) and a
+    rotation window (four maps close, four waiting ones are admitted and
+    built while the load goes on; requests to them include their build).
+    Latency is arrival to completion."""
+    import ctypes as C
+
+    import synth
+
+    rng = np.random.Generator(np.random.PCG64(seed))
+    specs = synth.config5_maps()
+    vs = 64
+    maps = []  # (n, keys, vals)
+    for n, k, v, _ in specs:
+        maps.append((n, k, v))
+    fps = [B.server_footprint(B.params(n, vs)) for n, _, _ in maps]  # what admission counts
+    # the budget holds maps 0..11 exactly; at half time of the first run the
+    # four largest of them leave for maps 12..15 (smaller together), and the
+    # second run swaps them back
+    budget = sum(fps[0:12])
+    big4 = sorted(range(12), key=lambda j: -fps[j])[:4]
+    assert sum(fps[j] for j in range(12, 16)) <= sum(fps[j] for j in big4)
+    # command pools: ops 90/10, Zipf(0.99) keys over the map's keys
+    pools = []
+    for n, k, v in maps:
+        ops = np.where(rng.random(pool) < 0.1, 1, 0).astype(np.uint8)
+        ranks = synth.zipf_ranks(n, pool, 0.99, rng)
+        keys = k[ranks]  # the keys are random, so hot ranks are spread over the key space
+        vals = rng.integers(0, 256, (pool, vs), dtype=np.uint8)
+        outv = np.zeros((pool, vs), np.uint8)
+        outs = np.zeros(pool, np.uint8)
+        pools.append((ops, np.ascontiguousarray(keys), vals, outv, outs))
+    srv = B.Server(hbm_budget=budget, streams=4)
+    t0 = time.perf_counter()
+    ids = {}
+    for j in range(12):
+        ids[j] = srv.open_map(B.params(maps[j][0], vs), maps[j][1], maps[j][2])
+    pending = {j: srv.open_map(B.params(maps[j][0], vs), maps[j][1], maps[j][2]) for j in range(12, 16)}  # wait
+
+    def wait_resident(js, limit=120.0):
+        t = time.perf_counter()
+        while any(srv.map_state(ids[j])[0] != B.BOLT_SRV_RESIDENT for j in js):
+            if time.perf_counter() - t > limit:
+                raise RuntimeError("maps not admitted: %s" % [srv.map_state(ids[j]) for j in js])
+            time.sleep(0.01)
+
+    wait_resident(range(12))
+    assert all(srv.map_state(i)[0] == B.BOLT_SRV_WAITING for i in pending.values())
+    setup_s = time.perf_counter() - t0
+    log("serving: 12 maps resident after %.1fs (budget %.2f GiB, all 16 need %.2f GiB)"
+        % (setup_s, budget / 2**30, sum(fps) / 2**30))
+    tk = C.c_uint64()
+    h = srv.h
+
+    def submit(j, q, arrival_ns):
+        ops, keys, vals, outv, outs = pools[j]
+        off = int(rng.integers(0, pool - q + 1))
+        rc = B.bolt_server_submit(h, ids[j], ops.ctypes.data + off, keys.ctypes.data + 8 * off,
+                                  vals.ctypes.data + vs * off, outv.ctypes.data + vs * off, outs.ctypes.data + off,
+                                  q, arrival_ns, C.byref(tk))
+        if rc != 0:
+            raise RuntimeError("submit: %d" % rc)
+        return q
+
+    def req_size():
+        return int(min(4096, max(1, int(2 ** (12 * rng.random())))))
+
+    # saturation: a backlog over the twelve resident maps
+    srv.reset_stats()
+    now = B.bolt_now_ns()
+    live = sorted(ids)
+    for _ in range(6000):
+        submit(live[int(rng.integers(0, len(live)))], req_size(), now)
+    B.check(srv.drain(300000), "drain")
+    sat = srv.stats()
+    sat_rps = sat["completed"] / sat["span_s"]
+    sat_ops = sat["commands"] / sat["span_s"]
+    log("serving saturation: %.0f req/s, %.3g ops/s" % (sat_rps, sat_ops))
+    out = {"workload": "16 maps, N log-uniform in [2^16, 2^24], 64-byte values; Poisson request batches of "
+                       "floor(2^(12u)) in [1, 4096] commands, 90 % GET / 10 % PUT, Zipf 0.99, none absent; "
+                       "12 maps resident under the HBM budget, 4 rotated per run",
+           "hbm_budget_bytes": budget, "all_maps_bytes": int(sum(fps)), "setup_s": round(setup_s, 2),
+           "saturation": {"req_per_s": round(sat_rps, 1), "ops_per_s": round(sat_ops, 1),
+                          "lat_p50_ms": round(sat["lat_p50_ms"], 3), "lat_p99_ms": round(sat["lat_p99_ms"], 3),
+                          "mean_group_maps": round(sat["mean_group_maps"], 2),
+                          "mean_group_commands": round(sat["mean_group_commands"], 1)},
+           "runs": []}
+    # open-loop runs; each rotates four maps at half time
+    rot = [(big4, list(range(12, 16))), (list(range(12, 16)), big4)]
+    for run, frac in enumerate((0.5, 0.8)):
+        rate = frac * sat_rps
+        closing, opening = rot[run]
+        if run:  # the maps to admit mid-run are opened (and wait) before the run
+            pending = {j: srv.open_map(B.params(maps[j][0], vs), maps[j][1], maps[j][2]) for j in opening}
+        assert all(srv.map_state(pending[j])[0] == B.BOLT_SRV_WAITING for j in opening)
+        srv.reset_stats()
+        start = B.bolt_now_ns()
+        t_warm = start + int(warm * 1e9)
+        t_rot = t_warm + int(seconds * 1e9)
+        t_end = t_rot + int(rot_seconds * 1e9)
+        t = start
+        phase = 0  # 0 warm-up, 1 steady, 2 rotation
+        steady = None
+
+        def summary(st, secs):
+            span = max(st["span_s"], 1e-9)
+            return {"seconds": secs, "requests": st["completed"], "failed": st["failed"],
+                    "completed_req_per_s": round(st["completed"] / span, 1),
+                    "ops_per_s": round(st["commands"] / span, 1),
+                    "lat_p50_ms": round(st["lat_p50_ms"], 3), "lat_p99_ms": round(st["lat_p99_ms"], 3),
+                    "lat_max_ms": round(st["lat_max_ms"], 3), "queue_peak": st["queue_peak"],
+                    "mean_group_maps": round(st["mean_group_maps"], 2),
+                    "mean_group_commands": round(st["mean_group_commands"], 1),
+                    "maps_admitted": st["maps_admitted"], "hbm_peak_bytes": st["hbm_peak"]}
+
+        while True:
+            t += int(rng.exponential(1.0 / rate) * 1e9)
+            if t >= t_end:
+                break
+            if phase == 0 and t >= t_warm:
+                while B.bolt_now_ns() < t_warm:
+                    pass
+                srv.reset_stats()
+                phase = 1
+            if phase == 1 and t >= t_rot:
+                while B.bolt_now_ns() < t_rot:
+                    pass
+                steady = summary(srv.stats(), seconds)
+                srv.reset_stats()
+                for j in closing:
+                    B.check(srv.close_map(ids.pop(j)), "close_map")
+                for j in opening:
+                    ids[j] = pending[j]
+                live = sorted(ids)
+                phase = 2
+            while B.bolt_now_ns() < t:
+                pass
+            submit(live[int(rng.integers(0, len(live)))], req_size(), t)
+        B.check(srv.drain(300000), "drain")
+        rotation = summary(srv.stats(), rot_seconds)
+        lag = (B.bolt_now_ns() - t_end) / 1e9
+        out["runs"].append({"load": frac, "offered_req_per_s": round(rate, 1), "steady": steady,
+                            "rotation": rotation, "drain_s": round(lag, 3), "warmup_s": warm})
+        log("serving at %.1fx: %s" % (frac, json.dumps(out["runs"][-1])))
+    srv.close()
+    return out
 
 
 def cpu_baseline(n_batches):

@@ -314,6 +314,11 @@ enum { BOLT_SRV_WAITING = 0, BOLT_SRV_BUILDING = 1, BOLT_SRV_RESIDENT = 2, BOLT_
 /* CLOCK_MONOTONIC in nanoseconds: the clock of arrival times. */
 uint64_t bolt_now_ns(void);
 
+/* Device bytes a map with these parameters holds on a server whose batches
+ * are at most max_batch commands (0 = BOLT_MAX_BATCH): the amount admission
+ * counts against the budget. */
+int bolt_server_footprint(const bolt_params* params, uint32_t max_batch, uint64_t* bytes);
+
 /* Starts a server on the current device.  params may be NULL (defaults). */
 int bolt_server_create(const bolt_server_params* params, bolt_server** out);
 

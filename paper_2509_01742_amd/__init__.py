@@ -117,6 +117,7 @@ _SIGS = [
     ("bolt_kernel_times", _I, [_P, _P, _U32, C.POINTER(_U32)]),
     ("bolt_kernel_times_reset", _I, [_P]),
     ("bolt_now_ns", _U64, []),
+    ("bolt_server_footprint", _I, [C.POINTER(bolt_params), _U32, C.POINTER(_U64)]),
     ("bolt_server_create", _I, [C.POINTER(bolt_server_params), C.POINTER(_P)]),
     ("bolt_server_open_map", _I, [_P, C.POINTER(bolt_params), _P, _P, _U64, C.POINTER(_U32)]),
     ("bolt_server_close_map", _I, [_P, _U32]),
@@ -341,6 +342,12 @@ def access_many(maps, batches, stream=None) -> int:
         bs[i] = bolt_batch(_dptr(ops).value, _dptr(keys).value, _dptr(vin).value, _dptr(vout).value,
                            _dptr(status).value, 0 if ops is None else ops.numel())
     return bolt_access_many(hs, bs, n, _stream(stream))
+
+
+def server_footprint(p: bolt_params, max_batch: int = 0) -> int:
+    b = C.c_uint64()
+    check(bolt_server_footprint(C.byref(p), max_batch, C.byref(b)), "bolt_server_footprint")
+    return int(b.value)
 
 
 class Server:

@@ -8,6 +8,10 @@
 //               device footprint (bolt_footprint plus its command staging)
 //               fits the HBM budget; until then its requests wait.  Closing
 //               a map frees its share and admits the next waiting one.
+//               Creating, building and freeing maps (allocations, the
+//               build's input copies, device-wide frees) run on a builder
+//               thread, so the serving loop never stalls on them; maps
+//               admitted together are built with one multi-map build.
 //   batching    continuous: on every turn of the loop, each admitted map
 //               that is idle and has queued requests takes its queue head,
 //               as many whole requests as fit one batch, in FIFO order; all
@@ -58,7 +62,9 @@ struct Req {
   uint64_t t_arr;
 };
 
-enum MapState { kWaiting = 0, kBuilding = 1, kResident = 2, kClosed = 3, kFailed = 4 };
+// kQueued: admitted, waiting for the builder; kRetiring: its resources are
+// being freed (then kClosed or kFailed).
+enum MapState { kWaiting, kQueued, kBuilding, kResident, kRetiring, kClosed, kFailed };
 
 // Command staging of one map: [ops Q][keys Q][vals_in Q*vs][vals_out Q*vs]
 // [status Q][error word].
@@ -85,15 +91,14 @@ struct SMap {
   bool charged = false;  // footprint counted against the budget
   int err = 0;
   uint64_t footprint = 0;
-  std::vector<uint64_t> build_keys;  // until built
-  std::vector<uint8_t> build_vals;
+  uint64_t* h_bkeys = nullptr;  // build input in pinned host memory, until built
+  uint8_t* h_bvals = nullptr;
   uint64_t n = 0;
   bolt_map* m = nullptr;
   Stage host, dev;
-  uint64_t* d_bkeys = nullptr;  // build inputs on the device, while building
+  uint64_t* d_bkeys = nullptr;  // build input on the device, while building
   uint8_t* d_bvals = nullptr;
-  hipEvent_t built = nullptr;
-  hipStream_t build_stream = nullptr;
+  MapState retire_to = kClosed;
   std::deque<Req> queue;
 };
 
@@ -119,6 +124,9 @@ struct bolt_server {
   std::condition_variable cv_work;  // the loop waits here when idle
   std::condition_variable cv_done;  // clients wait here for completions
   std::thread loop;
+  std::thread builder;
+  std::condition_variable cv_build;  // the builder waits here for jobs
+  std::vector<SMap*> build_jobs, retire_jobs;
   bool stop = false;
   std::vector<SMap*> maps;
   std::vector<hipStream_t> streams;
@@ -146,6 +154,7 @@ uint64_t map_footprint(const bolt_params* p, uint32_t Q) {
   return hbm + s.bytes;
 }
 
+// Frees everything a map holds.  Builder thread (or destroy) only.
 void release_map(SMap* sm) {
   if (sm->m) (void)bolt_destroy(sm->m);
   sm->m = nullptr;
@@ -156,12 +165,10 @@ void release_map(SMap* sm) {
   if (sm->d_bvals) (void)hipFree(sm->d_bvals);
   sm->d_bkeys = nullptr;
   sm->d_bvals = nullptr;
-  if (sm->built) (void)hipEventDestroy(sm->built);
-  sm->built = nullptr;
-  if (sm->build_stream) (void)hipStreamDestroy(sm->build_stream);
-  sm->build_stream = nullptr;
-  std::vector<uint64_t>().swap(sm->build_keys);
-  std::vector<uint8_t>().swap(sm->build_vals);
+  if (sm->h_bkeys) (void)hipHostFree(sm->h_bkeys);
+  if (sm->h_bvals) (void)hipHostFree(sm->h_bvals);
+  sm->h_bkeys = nullptr;
+  sm->h_bvals = nullptr;
 }
 
 void finish_req(bolt_server* s, const Req& r, int32_t rc, uint64_t t_done) {
@@ -183,65 +190,22 @@ void fail_queue(bolt_server* s, SMap* sm, int32_t rc) {
   s->cv_done.notify_all();
 }
 
-// Frees a map's device and host resources and its share of the budget.
+// Hands a map to the builder to be freed; runs under the lock.  Its share
+// of the budget returns when the memory is really free.
 void retire(bolt_server* s, SMap* sm, MapState to) {
-  release_map(sm);
-  if (sm->charged) s->hbm_used -= sm->footprint;
-  sm->charged = false;
-  sm->state = to;
+  sm->state = kRetiring;
+  sm->retire_to = to;
+  s->retire_jobs.push_back(sm);
+  s->cv_build.notify_one();
 }
 
-// Starts the build of a waiting map whose footprint fits.  Runs under the lock.
-int start_build(bolt_server* s, SMap* sm) {
-  int rc = BOLT_OK;
-  if (hipStreamCreateWithFlags(&sm->build_stream, hipStreamNonBlocking) != hipSuccess) return BOLT_EHIP;
-  rc = bolt_create(&sm->p, sm->build_stream, &sm->m);
-  if (rc) return rc;
-  const uint32_t Q = s->prm.max_batch;
-  sm->host.layout(Q, sm->vs);
-  sm->dev.layout(Q, sm->vs);
-  if (hipHostMalloc((void**)&sm->host.base, sm->host.bytes, hipHostMallocDefault) != hipSuccess) return BOLT_ENOMEM;
-  if (hipMalloc((void**)&sm->dev.base, sm->dev.bytes) != hipSuccess) return BOLT_ENOMEM;
-  if (sm->n) {
-    if (hipMalloc((void**)&sm->d_bkeys, sm->n * 8) != hipSuccess) return BOLT_ENOMEM;
-    if (hipMalloc((void**)&sm->d_bvals, sm->n * sm->vs) != hipSuccess) return BOLT_ENOMEM;
-    if (hipMemcpyAsync(sm->d_bkeys, sm->build_keys.data(), sm->n * 8, hipMemcpyHostToDevice, sm->build_stream) !=
-            hipSuccess ||
-        hipMemcpyAsync(sm->d_bvals, sm->build_vals.data(), sm->n * sm->vs, hipMemcpyHostToDevice,
-                       sm->build_stream) != hipSuccess)
-      return BOLT_EHIP;
-  }
-  rc = bolt_build(sm->m, sm->d_bkeys, sm->d_bvals, sm->n, sm->build_stream);
-  if (rc) return rc;
-  if (hipEventCreateWithFlags(&sm->built, hipEventDisableTiming) != hipSuccess) return BOLT_EHIP;
-  if (hipEventRecord(sm->built, sm->build_stream) != hipSuccess) return BOLT_EHIP;
-  sm->state = kBuilding;
-  return BOLT_OK;
-}
-
-// Admission and retirement; runs under the lock.  Returns true if anything changed.
+// Admission and retirement decisions; runs under the lock.  Returns true if
+// anything changed.
 bool admit(bolt_server* s) {
   bool changed = false;
   for (SMap* sm : s->maps) {
-    if (sm->state == kBuilding && hipEventQuery(sm->built) == hipSuccess) {
-      int rc = bolt_status(sm->m);
-      if (sm->d_bkeys) (void)hipFree(sm->d_bkeys);
-      if (sm->d_bvals) (void)hipFree(sm->d_bvals);
-      sm->d_bkeys = nullptr;
-      sm->d_bvals = nullptr;
-      std::vector<uint64_t>().swap(sm->build_keys);
-      std::vector<uint8_t>().swap(sm->build_vals);
-      if (rc) {
-        sm->err = rc;
-        fail_queue(s, sm, rc);
-        retire(s, sm, kFailed);
-      } else {
-        sm->state = kResident;
-      }
-      changed = true;
-    }
     // a closed map leaves once its last request is done
-    if (sm->closing && !sm->busy && sm->queue.empty() && (sm->state == kResident || sm->state == kFailed)) {
+    if (sm->closing && !sm->busy && sm->queue.empty() && sm->state == kResident) {
       retire(s, sm, kClosed);
       changed = true;
     }
@@ -261,15 +225,109 @@ bool admit(bolt_server* s) {
     sm->charged = true;
     s->hbm_peak = std::max(s->hbm_peak, s->hbm_used);
     s->st_admitted++;
-    int rc = start_build(s, sm);
-    if (rc) {
-      sm->err = rc;
-      fail_queue(s, sm, rc);
-      retire(s, sm, kFailed);
-    }
+    sm->state = kQueued;
+    s->build_jobs.push_back(sm);
+    s->cv_build.notify_one();
     changed = true;
   }
   return changed;
+}
+
+// Device-side set-up of one admitted map: the map, its command staging and
+// its build input on the device.  Builder thread, without the lock.
+int prepare(bolt_server* s, SMap* sm, hipStream_t st) {
+  int rc = bolt_create(&sm->p, st, &sm->m);
+  if (rc) return rc;
+  const uint32_t Q = s->prm.max_batch;
+  sm->host.layout(Q, sm->vs);
+  sm->dev.layout(Q, sm->vs);
+  if (hipHostMalloc((void**)&sm->host.base, sm->host.bytes, hipHostMallocDefault) != hipSuccess) return BOLT_ENOMEM;
+  if (hipMalloc((void**)&sm->dev.base, sm->dev.bytes) != hipSuccess) return BOLT_ENOMEM;
+  if (sm->n) {
+    if (hipMalloc((void**)&sm->d_bkeys, sm->n * 8) != hipSuccess) return BOLT_ENOMEM;
+    if (hipMalloc((void**)&sm->d_bvals, sm->n * sm->vs) != hipSuccess) return BOLT_ENOMEM;
+    if (hipMemcpyAsync(sm->d_bkeys, sm->h_bkeys, sm->n * 8, hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipMemcpyAsync(sm->d_bvals, sm->h_bvals, sm->n * sm->vs, hipMemcpyHostToDevice, st) != hipSuccess)
+      return BOLT_EHIP;
+  }
+  return BOLT_OK;
+}
+
+void run_builder(bolt_server* s) {
+  (void)hipSetDevice(s->device);
+  hipStream_t st = nullptr;
+  (void)hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+  std::unique_lock<std::mutex> lk(s->mu);
+  while (!s->stop) {
+    if (s->build_jobs.empty() && s->retire_jobs.empty()) {
+      s->cv_build.wait(lk);
+      continue;
+    }
+    std::vector<SMap*> builds, retires;
+    builds.swap(s->build_jobs);
+    retires.swap(s->retire_jobs);
+    for (SMap* sm : builds) sm->state = kBuilding;
+    lk.unlock();
+    // frees first: they may make room for the next admissions
+    for (SMap* sm : retires) release_map(sm);
+    std::vector<int> rc(builds.size(), BOLT_OK);
+    std::vector<bolt_map*> ms;
+    std::vector<const uint64_t*> ks;
+    std::vector<const void*> vs;
+    std::vector<uint64_t> ns;
+    std::vector<size_t> at;
+    for (size_t i = 0; i < builds.size(); ++i) {
+      rc[i] = prepare(s, builds[i], st);
+      if (rc[i] == BOLT_OK) {
+        ms.push_back(builds[i]->m);
+        ks.push_back(builds[i]->d_bkeys);
+        vs.push_back(builds[i]->d_bvals);
+        ns.push_back(builds[i]->n);
+        at.push_back(i);
+      }
+    }
+    if (!ms.empty()) {
+      int b = bolt_build_many(ms.data(), ks.data(), vs.data(), ns.data(), (uint32_t)ms.size(), st);
+      if (b == BOLT_OK && hipStreamSynchronize(st) != hipSuccess) b = BOLT_EHIP;
+      for (size_t j = 0; j < at.size(); ++j) {
+        SMap* sm = builds[at[j]];
+        rc[at[j]] = b != BOLT_OK ? b : bolt_status(sm->m);  // build errors are the map's own
+        if (sm->d_bkeys) (void)hipFree(sm->d_bkeys);
+        if (sm->d_bvals) (void)hipFree(sm->d_bvals);
+        sm->d_bkeys = nullptr;
+        sm->d_bvals = nullptr;
+        if (sm->h_bkeys) (void)hipHostFree(sm->h_bkeys);
+        if (sm->h_bvals) (void)hipHostFree(sm->h_bvals);
+        sm->h_bkeys = nullptr;
+        sm->h_bvals = nullptr;
+      }
+    }
+    for (size_t i = 0; i < builds.size(); ++i)
+      if (rc[i] != BOLT_OK) release_map(builds[i]);
+    lk.lock();
+    for (SMap* sm : retires) {
+      if (sm->charged) s->hbm_used -= sm->footprint;
+      sm->charged = false;
+      sm->state = sm->retire_to;
+    }
+    for (size_t i = 0; i < builds.size(); ++i) {
+      SMap* sm = builds[i];
+      if (rc[i] == BOLT_OK) {
+        sm->state = kResident;
+      } else {
+        sm->err = rc[i];
+        fail_queue(s, sm, rc[i]);
+        if (sm->charged) s->hbm_used -= sm->footprint;
+        sm->charged = false;
+        sm->state = kFailed;
+      }
+    }
+    s->cv_work.notify_one();  // new residents, or room for waiting maps
+    s->cv_done.notify_all();
+  }
+  lk.unlock();
+  (void)hipStreamSynchronize(st);
+  (void)hipStreamDestroy(st);
 }
 
 // Completion of launched groups; runs under the lock.
@@ -402,10 +460,8 @@ void run_loop(bolt_server* s) {
     did |= admit(s);
     did |= launch(s);
     if (did) continue;
-    bool building = false;
-    for (SMap* sm : s->maps) building |= sm->state == kBuilding;
-    if (s->inflight.empty() && !building) {
-      s->cv_work.wait(lk);  // nothing on the device: sleep until a submit, open or close
+    if (s->inflight.empty()) {
+      s->cv_work.wait(lk);  // nothing in flight: sleep until a submit, open, close or build
     } else {
       // device work outstanding: poll its events, giving the lock up in between
       lk.unlock();
@@ -422,6 +478,17 @@ bool valid_ticket(bolt_server* s, uint64_t t) { return t < s->results.size(); }
 extern "C" {
 
 uint64_t bolt_now_ns(void) { return now_ns(); }
+
+int bolt_server_footprint(const bolt_params* p, uint32_t max_batch, uint64_t* bytes) {
+  if (!p || !bytes) return BOLT_EINVAL;
+  if (max_batch == 0) max_batch = kMaxBatch;
+  if (max_batch > kMaxBatch) return BOLT_EINVAL;
+  bolt_sizes z;
+  int rc = bolt_sizes_of(p, &z);
+  if (rc) return rc;
+  *bytes = map_footprint(p, max_batch);
+  return BOLT_OK;
+}
 
 int bolt_server_create(const bolt_server_params* prm, bolt_server** out) {
   if (!out) return BOLT_EINVAL;
@@ -450,6 +517,7 @@ int bolt_server_create(const bolt_server_params* prm, bolt_server** out) {
   }
   std::reverse(s->free_streams.begin(), s->free_streams.end());
   s->loop = std::thread(run_loop, s);
+  s->builder = std::thread(run_builder, s);
   *out = s;
   return BOLT_OK;
 }
@@ -471,13 +539,15 @@ int bolt_server_open_map(bolt_server* s, const bolt_params* p, const uint64_t* h
   sm->vs = p->value_bytes;
   sm->n = n;
   sm->footprint = fp;
-  try {
-    sm->build_keys.assign(host_keys, host_keys + n);
-    const uint8_t* hv = static_cast<const uint8_t*>(host_vals);
-    sm->build_vals.assign(hv, hv + n * sm->vs);
-  } catch (...) {
-    delete sm;
-    return BOLT_ENOMEM;
+  if (n) {  // the build input goes to pinned memory now, so its copy to the device is a plain DMA later
+    if (hipHostMalloc((void**)&sm->h_bkeys, n * 8, hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void**)&sm->h_bvals, n * sm->vs, hipHostMallocDefault) != hipSuccess) {
+      release_map(sm);
+      delete sm;
+      return BOLT_ENOMEM;
+    }
+    memcpy(sm->h_bkeys, host_keys, n * 8);
+    memcpy(sm->h_bvals, host_vals, n * sm->vs);
   }
   {
     std::lock_guard<std::mutex> g(s->mu);
@@ -504,8 +574,17 @@ int bolt_server_map_state(bolt_server* s, uint32_t map_id, int* state, int* err)
   if (!s || !state) return BOLT_EINVAL;
   std::lock_guard<std::mutex> g(s->mu);
   if (map_id >= s->maps.size()) return BOLT_EINVAL;
-  *state = (int)s->maps[map_id]->state;
-  if (err) *err = s->maps[map_id]->err;
+  const SMap* sm = s->maps[map_id];
+  MapState m = sm->state == kRetiring ? sm->retire_to : sm->state;
+  switch (m) {
+    case kWaiting: *state = BOLT_SRV_WAITING; break;
+    case kQueued:
+    case kBuilding: *state = BOLT_SRV_BUILDING; break;
+    case kResident: *state = BOLT_SRV_RESIDENT; break;
+    case kFailed: *state = BOLT_SRV_FAILED; break;
+    default: *state = BOLT_SRV_CLOSED; break;
+  }
+  if (err) *err = sm->err;
   return BOLT_OK;
 }
 
@@ -519,7 +598,7 @@ int bolt_server_submit(bolt_server* s, uint32_t map_id, const uint8_t* host_ops,
     if (map_id >= s->maps.size()) return BOLT_EINVAL;
     SMap* sm = s->maps[map_id];
     if (q > s->prm.max_batch || sm->closing || sm->state == kClosed) return BOLT_EINVAL;
-    if (sm->state == kFailed) return BOLT_ESTATE;
+    if (sm->err || sm->state == kFailed) return BOLT_ESTATE;
     // a bad op code would reject the whole coalesced batch: refuse it here
     for (uint32_t i = 0; i < q; ++i)
       if (host_ops[i] > BOLT_OP_DEL) return BOLT_EINVAL;
@@ -579,7 +658,7 @@ int bolt_server_get_stats(bolt_server* s, bolt_server_stats* out) {
     out->queue_peak = s->st_queue_peak;
     out->maps_admitted = s->st_admitted;
     for (SMap* sm : s->maps) {
-      out->maps_resident += sm->state == kResident || sm->state == kBuilding;
+      out->maps_resident += sm->state == kResident || sm->state == kBuilding || sm->state == kQueued;
       out->maps_waiting += sm->state == kWaiting;
     }
     out->hbm_used = s->hbm_used;
@@ -632,10 +711,11 @@ int bolt_server_destroy(bolt_server* s) {
     s->stop = true;
   }
   s->cv_work.notify_one();
+  s->cv_build.notify_one();
   if (s->loop.joinable()) s->loop.join();
+  if (s->builder.joinable()) s->builder.join();
   for (hipStream_t st : s->streams) (void)hipStreamSynchronize(st);
   for (SMap* sm : s->maps) {
-    if (sm->build_stream) (void)hipStreamSynchronize(sm->build_stream);
     release_map(sm);
     delete sm;
   }
