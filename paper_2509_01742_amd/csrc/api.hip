@@ -52,6 +52,9 @@ int derive(const bolt_params* p, Sizes* s) {
   z.BZ = z.B * z.Z;
   z.PW = (z.P + 63) / 64;
   if (z.BZ >= (1ull << 32) || z.P >= (1ull << 32)) return BOLT_EINVAL;
+  // the build's P2C and position-map rounds are numbered in 16 bits
+  const uint64_t rs = (z.B + 15) / 16, rsm = (z.R + 15) / 16;
+  if ((z.cap + rs - 1) / rs > 0xFFFF || (z.cap + rsm - 1) / rsm > 0xFFFF) return BOLT_EINVAL;
   *s = z;
   return BOLT_OK;
 }
@@ -90,6 +93,11 @@ void free_all(bolt_map* m) {
   m->allocs.clear();
   if (m->obs_host) (void)hipHostFree(m->obs_host);
   m->obs_host = nullptr;
+  if (m->side) (void)hipStreamDestroy(m->side);
+  if (m->ev_fork) (void)hipEventDestroy(m->ev_fork);
+  if (m->ev_join) (void)hipEventDestroy(m->ev_join);
+  m->side = nullptr;
+  m->ev_fork = m->ev_join = nullptr;
 }
 
 int map_check(bolt_map* m) {
@@ -261,6 +269,13 @@ int bolt_create(const bolt_params* p, void* hip_stream, bolt_map** out) {
     delete m;
     return rc;
   }
+  if (hipStreamCreateWithFlags(&m->side, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&m->ev_fork, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&m->ev_join, hipEventDisableTiming) != hipSuccess) {
+    free_all(m);
+    delete m;
+    return BOLT_EHIP;
+  }
   if (p->flags & BOLT_F_TIMING) {
     m->timer = new (std::nothrow) KernelTimer();
     if (!m->timer) {
@@ -404,6 +419,7 @@ int bolt_destroy(bolt_map* m) {
   if (!m) return BOLT_OK;
   (void)hipSetDevice(m->device);
   (void)hipStreamSynchronize(m->last_stream);
+  if (m->side) (void)hipStreamSynchronize(m->side);
   delete m->timer;
   free_all(m);
   delete m;

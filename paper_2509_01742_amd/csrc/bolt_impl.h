@@ -123,6 +123,10 @@ struct bolt_map {
   uint64_t batches;
   hipStream_t last_stream;
   bolt::KernelTimer* timer;  // BOLT_F_TIMING, else null
+  // The build's position-map rounds run on `side`, forked from and joined
+  // back to the caller's stream with the two events.
+  hipStream_t side;
+  hipEvent_t ev_fork, ev_join;
 };
 
 namespace bolt {

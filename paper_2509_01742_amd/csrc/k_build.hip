@@ -86,8 +86,7 @@ struct BuildPlan {
   uint64_t* tmp;    // [BZ]
   uint32_t* start;  // [B] first sorted position of each bin
   uint32_t* bsum;   // [nbs + 1] scan partials, then the max-key counter
-  uint32_t* rowsel; // [n]
-  uint32_t* rowcnt; // [R]
+  uint64_t* rstate; // [R] row fill word of the position-map rounds
 };
 
 #define BOLT_PLAN const BuildPlan& P = MULTI ? tab[blockIdx.y] : p1
@@ -204,20 +203,55 @@ __global__ void k_build_pairs(BOLT_PLAN_ARGS) {
   P.pair[i] = make_uint2(a, b);
 }
 
+// A row's count during the position-map rounds, as one 64-bit word updated
+// with compare-and-swap: [last round that added : 16][count when that round
+// began : 24][count now : 24].  A key of round r reads the count at the
+// start of its round from either field, whether or not other keys of the
+// round have already added, so one launch per round both decides and adds
+// (rounds are numbered from 1; the word starts at zero).
+constexpr uint64_t kCntMask = 0xFFFFFFull;
+
+__device__ __forceinline__ uint32_t round_start_count(uint64_t w, uint32_t r) {
+  return (uint32_t)((w >> 48) == r ? (w >> 24) & kCntMask : w & kCntMask);
+}
+
+// Adds one in round r; returns the count before (the new item's slot).
+// `old` is a recent read of the word (a guess: a stale one costs a retry).
+__device__ __forceinline__ uint32_t round_add(uint64_t* word, uint64_t old, uint32_t r, Ctl* ctl) {
+  unsigned long long* p = reinterpret_cast<unsigned long long*>(word);
+  while (true) {
+    const uint64_t cur = old & kCntMask;
+    if (cur == kCntMask) {  // saturated: far beyond any capacity
+      set_err(ctl, kErrOverflow);
+      return (uint32_t)cur;
+    }
+    const uint64_t base = (old >> 48) == r ? (old >> 24) & kCntMask : cur;
+    const uint64_t nw = ((uint64_t)r << 48) | (base << 24) | (cur + 1);
+    const uint64_t prev = atomicCAS(p, (unsigned long long)old, (unsigned long long)nw);
+    if (prev == old) return (uint32_t)cur;
+    old = prev;
+  }
+}
+
+// One P2C round (numbered from 1) in two launches: every key of the round
+// picks the less loaded of its two bins as loaded when the round began
+// (ties to the first bin), then all of them add.  (A fused round with the
+// round-tagged words above costs a compare-and-swap round trip per key,
+// slower here than a fire-and-forget add plus one more launch.)
 template <bool MULTI>
 __global__ void k_p2c_decide(BOLT_PLAN_ARGS, uint32_t round) {
   BOLT_PLAN;
-  const uint64_t r0 = (uint64_t)round * P.rs, r1 = r0 + P.rs < P.n ? r0 + P.rs : P.n;
+  const uint64_t r0 = (uint64_t)(round - 1) * P.rs, r1 = r0 + P.rs < P.n ? r0 + P.rs : P.n;
   uint64_t i = r0 + (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= r1) return;
-  uint2 p = P.pair[i];
+  const uint2 p = P.pair[i];
   P.dest[i] = P.load[p.y] < P.load[p.x] ? p.y : p.x;
 }
 
 template <bool MULTI>
 __global__ void k_p2c_add(BOLT_PLAN_ARGS, uint32_t round) {
   BOLT_PLAN;
-  const uint64_t r0 = (uint64_t)round * P.rs, r1 = r0 + P.rs < P.n ? r0 + P.rs : P.n;
+  const uint64_t r0 = (uint64_t)(round - 1) * P.rs, r1 = r0 + P.rs < P.n ? r0 + P.rs : P.n;
   uint64_t i = r0 + (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= r1) return;
   atomicAdd(&P.load[P.dest[i]], 1u);
@@ -341,43 +375,42 @@ template <bool MULTI>
 __global__ void k_build_zero(BOLT_PLAN_ARGS) {
   BOLT_PLAN;
   uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < P.R) P.rowcnt[i] = 0;
+  if (i < P.R) P.rstate[i] = 0;
+  if (i < P.B) P.load[i] = 0;
   if (i == 0) P.bsum[P.nbs] = 0;
 }
 
+// One position-map round (numbered from 1): each key goes to the least
+// filled of its d rows as filled when the round began (ties to the first),
+// into the next free slot.
 template <bool MULTI>
-__global__ void k_pm_decide(BOLT_PLAN_ARGS, uint32_t round) {
+__global__ void k_pm_round(BOLT_PLAN_ARGS, uint32_t round) {
   BOLT_PLAN;
-  const uint64_t r0 = (uint64_t)round * P.rsm, r1 = r0 + P.rsm < P.n ? r0 + P.rsm : P.n;
+  const uint64_t r0 = (uint64_t)(round - 1) * P.rsm, r1 = r0 + P.rsm < P.n ? r0 + P.rsm : P.n;
   uint64_t i = r0 + (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= r1) return;
   uint32_t hk[8];
 #pragma unroll
   for (int j = 0; j < 8; ++j) hk[j] = P.ctl->hkey[j];
+  const uint64_t key = P.keys[i];
   uint32_t rows[4];
-  pm_rows_of(hk, P.keys[i], P.R, P.d, rows);
-  uint32_t best = rows[0], bc = P.rowcnt[rows[0]];
+  pm_rows_of(hk, key, P.R, P.d, rows);
+  uint32_t best = rows[0];
+  uint64_t bw = P.rstate[rows[0]];  // plain loads, as in the P2C round
+  uint32_t bc = round_start_count(bw, round);
   for (uint32_t j = 1; j < P.d; ++j) {
-    uint32_t c = P.rowcnt[rows[j]];
+    const uint64_t w = P.rstate[rows[j]];
+    const uint32_t c = round_start_count(w, round);
     if (c < bc) {
       bc = c;
       best = rows[j];
+      bw = w;
     }
   }
-  P.rowsel[i] = best;
-}
-
-template <bool MULTI>
-__global__ void k_pm_add(BOLT_PLAN_ARGS, uint32_t round) {
-  BOLT_PLAN;
-  const uint64_t r0 = (uint64_t)round * P.rsm, r1 = r0 + P.rsm < P.n ? r0 + P.rsm : P.n;
-  uint64_t i = r0 + (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= r1) return;
-  uint32_t r = P.rowsel[i];
-  uint32_t slot = atomicAdd(&P.rowcnt[r], 1u);
+  const uint32_t slot = round_add(&P.rstate[best], bw, round, P.ctl);
   if (slot < P.W) {
-    P.pm_key[(uint64_t)r * P.W + slot] = P.keys[i];
-    P.pm_pair[(uint64_t)r * P.W + slot] = P.pair[i];
+    P.pm_key[(uint64_t)best * P.W + slot] = key;
+    P.pm_pair[(uint64_t)best * P.W + slot] = P.pair[i];
   } else {
     set_err(P.ctl, kErrOverflow);
   }
@@ -388,7 +421,8 @@ __global__ void k_pm_masks(BOLT_PLAN_ARGS) {
   BOLT_PLAN;
   uint64_t r = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= P.R) return;
-  uint32_t c = P.rowcnt[r] < P.W ? P.rowcnt[r] : P.W;
+  const uint32_t cnt = (uint32_t)(P.rstate[r] & kCntMask);
+  uint32_t c = cnt < P.W ? cnt : P.W;
   P.pm_mask[r] = c >= 32 ? 0xFFFFFFFFu : ((1u << c) - 1);
 }
 
@@ -437,7 +471,7 @@ static uint64_t build_scratch_bytes(const Sizes& s, uint64_t n) {
   const uint64_t nn = n ? n : 1;
   const uint64_t nbs = (s.B + kScanChunk - 1) / kScanChunk;
   return align256(nn * 8) + align256(nn * 4) + align256(npad * 8) + 2 * align256(s.BZ * 8) + align256(s.B * 4) +
-         align256((nbs + 1) * 4) + align256(nn * 4) + align256(s.R * 4);
+         align256((nbs + 1) * 4) + align256(s.R * 8);
 }
 
 // Fills one map's plan; carves its scratch from `arena` (advanced).
@@ -483,8 +517,7 @@ static void plan_build(bolt_map* m, const uint64_t* keys, const void* vals, uint
   P.tmp = reinterpret_cast<uint64_t*>(take(s.BZ * 8));
   P.start = reinterpret_cast<uint32_t*>(take(s.B * 4));
   P.bsum = reinterpret_cast<uint32_t*>(take(((uint64_t)P.nbs + 1) * 4));
-  P.rowsel = reinterpret_cast<uint32_t*>(take(nn * 4));
-  P.rowcnt = reinterpret_cast<uint32_t*>(take(s.R * 4));
+  P.rstate = reinterpret_cast<uint64_t*>(take(s.R * 8));
   P.tlog = nullptr;
   if (m->tlog) {
     if (m->tlog_used + s.M <= m->tlog_cap) {
@@ -499,13 +532,15 @@ static void plan_build(bolt_map* m, const uint64_t* keys, const void* vals, uint
 }
 
 #define BL(K, gx, nt, ...) hipLaunchKernelGGL(K<MULTI>, dim3((gx), C), dim3(nt), 0, st, p1, tab, ##__VA_ARGS__)
+#define BLS(K, gx, nt, ...) hipLaunchKernelGGL(K<MULTI>, dim3((gx), C), dim3(nt), 0, side, p1, tab, ##__VA_ARGS__)
 
 // The build sequence (a1 .. a7 and the duplicate check).  The grids and
 // trip counts come from the largest map; each map's blocks past its own
 // sizes return at once.
 template <bool MULTI>
 static void build_launches(const std::vector<BuildPlan>& plans, const BuildPlan* tab, const NetSeg* dsort,
-                           const NetSeg* dexp, hipStream_t st, KernelTimer* tm) {
+                           const NetSeg* dexp, hipStream_t st, hipStream_t side, hipEvent_t ev_fork,
+                           hipEvent_t ev_join, KernelTimer* tm) {
   const BuildPlan& p1 = plans[0];
   const uint32_t C = MULTI ? (uint32_t)plans.size() : 1;
   uint64_t n = 0, npad = 0, B = 0, BZ = 0, R = 0, nbs = 0, rp = 0, rm = 0;
@@ -525,13 +560,30 @@ static void build_launches(const std::vector<BuildPlan>& plans, const BuildPlan*
     rsm_max = std::max(rsm_max, std::min(P.rsm, P.n));
   }
   const uint32_t NT = 256;
+  {
+    TimedScope ts(tm, kkBuildMisc, st);
+    BL(k_build_zero, blocks_for(std::max(B, R), NT), NT);
+  }
   // a1
   if (n) {
     TimedScope ts(tm, kkPairs, st);
     BL(k_build_pairs, blocks_for(n, NT), NT);
   }
+  // a7 on the side stream: the position-map rounds need only the keys and
+  // their pairs, so their chain of small launches overlaps a2 .. a6
+  (void)hipEventRecord(ev_fork, st);
+  (void)hipStreamWaitEvent(side, ev_fork, 0);
+  for (uint32_t r = 1; r <= rm; ++r) {
+    TimedScope ts(tm, kkPmBuild, side);
+    BLS(k_pm_round, blocks_for(rsm_max, NT), NT, r);
+  }
+  {
+    TimedScope ts(tm, kkPmBuild, side);
+    BLS(k_pm_masks, blocks_for(R, NT), NT);
+  }
+  (void)hipEventRecord(ev_join, side);
   // a2: rounds of ceil(B/16) keys
-  for (uint32_t r = 0; r < rp; ++r) {
+  for (uint32_t r = 1; r <= rp; ++r) {
     {
       TimedScope ts(tm, kkP2C, st);
       BL(k_p2c_decide, blocks_for(rs_max, NT), NT, r);
@@ -574,23 +626,6 @@ static void build_launches(const std::vector<BuildPlan>& plans, const BuildPlan*
     TimedScope ts(tm, kkWriteout, st);
     BL(k_writeout, blocks_for(B, 4), 256, flip);
   }
-  // a7: rounds of ceil(R/16) keys
-  {
-    TimedScope ts(tm, kkPmBuild, st);
-    BL(k_build_zero, blocks_for(R, NT), NT);
-  }
-  for (uint32_t r = 0; r < rm; ++r) {
-    {
-      TimedScope ts(tm, kkPmBuild, st);
-      BL(k_pm_decide, blocks_for(rsm_max, NT), NT, r);
-    }
-    TimedScope ts(tm, kkPmBuild, st);
-    BL(k_pm_add, blocks_for(rsm_max, NT), NT, r);
-  }
-  {
-    TimedScope ts(tm, kkPmBuild, st);
-    BL(k_pm_masks, blocks_for(R, NT), NT);
-  }
   // duplicate keys (the tag buffer is free after the write-out)
   if (n) {
     {
@@ -604,6 +639,7 @@ static void build_launches(const std::vector<BuildPlan>& plans, const BuildPlan*
     TimedScope ts(tm, kkDupcheck, st);
     BL(k_dup_adjacent, blocks_for(npad, NT), NT);
   }
+  (void)hipStreamWaitEvent(st, ev_join, 0);
   {
     TimedScope ts(tm, kkBuildMisc, st);
     BL(k_build_finish, 1, 64);
@@ -611,6 +647,7 @@ static void build_launches(const std::vector<BuildPlan>& plans, const BuildPlan*
 }
 
 #undef BL
+#undef BLS
 
 int run_build(bolt_map* m, const uint64_t* keys, const void* vals, uint64_t n, hipStream_t st) {
   uint8_t* arena = nullptr;
@@ -618,7 +655,7 @@ int run_build(bolt_map* m, const uint64_t* keys, const void* vals, uint64_t n, h
   std::vector<BuildPlan> plans(1);
   uint8_t* cur = arena;
   plan_build(m, keys, vals, n, cur, plans[0]);
-  build_launches<false>(plans, nullptr, nullptr, nullptr, st, m->timer);
+  build_launches<false>(plans, nullptr, nullptr, nullptr, st, m->side, m->ev_fork, m->ev_join, m->timer);
   (void)hipFreeAsync(arena, st);
   return hipGetLastError() == hipSuccess ? BOLT_OK : BOLT_EHIP;
 }
@@ -647,7 +684,7 @@ int run_build_many(bolt_map* const* maps, const uint64_t* const* keys, const voi
     (void)hipFreeAsync(arena, st);
     return BOLT_EHIP;
   }
-  build_launches<true>(plans, dtab, dsort, dexp, st, nullptr);
+  build_launches<true>(plans, dtab, dsort, dexp, st, maps[0]->side, maps[0]->ev_fork, maps[0]->ev_join, nullptr);
   (void)hipFreeAsync(arena, st);
   return hipGetLastError() == hipSuccess ? BOLT_OK : BOLT_EHIP;
 }

@@ -130,52 +130,199 @@ __host__ __device__ __forceinline__ uint32_t ilog2_ceil(uint64_t n) {
   return l;
 }
 
-constexpr int kSortLogT = 13;  // 8192-element LDS tiles (64 KiB)
-constexpr int kSortNT = 1024;
+constexpr int kSortLogT = 13;  // 8192-element tiles (64 KiB of LDS for the transposes)
 constexpr int kSortFMax = 4;
 
-// LDS stages on one tile.  Mode 0: full tile sort, k = 2 .. T.  Mode 1: the
-// tail of merge step k (strides T/2 .. 1).
-template <int LOGT, int NT, bool MULTI>
-__global__ __launch_bounds__(NT) void k_bitonic_tile(uint64_t* __restrict__ a1, uint32_t logt1, int mode,
-                                                     uint32_t k_log, const NetSeg* segs) {
-  __shared__ uint64_t s[1 << LOGT];
-  uint64_t* __restrict__ a = a1;
-  uint32_t logt = logt1;
-  if (MULTI) {
-    const NetSeg g = segs[blockIdx.y];
-    const uint32_t L = ilog2_ceil(g.n);
-    if (mode == 1 && L < k_log) return;  // whole block: this array is shorter
-    logt = L < (uint32_t)LOGT ? L : (uint32_t)LOGT;
-    if (blockIdx.x >= (g.n >> logt)) return;
-    a = g.a;
+// ---- tile of 8192 elements, 512 threads, 16 elements per thread --------
+//
+// Two register layouts of a tile: in the "row" layout thread t holds
+// elements r * 512 + t (r = 0..15), so loads and stores are coalesced and
+// the strides 512..4096 pair two registers of one thread; in the "column"
+// layout thread t holds elements 16 t + r, so the strides 1..8 pair two
+// registers and the strides 16..256 pair the same register of lanes
+// 1..16 apart in one wave (exchanged by lane shuffles).  A stage therefore
+// never touches LDS; LDS only transposes between the two layouts (with the
+// low four index bits XOR-swizzled by the next four, so neither layout's
+// accesses conflict on banks).  A full tile sort is 91 network stages and
+// 10 transposes; the tail of a longer merge step is 13 stages and 2.
+
+constexpr int kRegNT = 512;
+constexpr int kRegE = 16;
+
+__device__ __forceinline__ uint32_t tswz(uint32_t i) { return i ^ ((i >> 4) & 15u); }
+
+// x := min(x, y) if takemin else max(x, y)
+__device__ __forceinline__ uint64_t minmax(uint64_t x, uint64_t y, bool takemin) {
+  return ((x < y) == takemin) ? x : y;
+}
+
+// Row -> column layout through LDS (and back).
+__device__ __forceinline__ void rows_to_cols(uint64_t (&v)[kRegE], uint64_t* lds, uint32_t t) {
+  __syncthreads();  // earlier readers of lds are done
+#pragma unroll
+  for (int r = 0; r < kRegE; ++r) lds[tswz((uint32_t)r * kRegNT + t)] = v[r];
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < kRegE; ++r) v[r] = lds[tswz(t * kRegE + (uint32_t)r)];
+}
+
+__device__ __forceinline__ void cols_to_rows(uint64_t (&v)[kRegE], uint64_t* lds, uint32_t t) {
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < kRegE; ++r) lds[tswz(t * kRegE + (uint32_t)r)] = v[r];
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < kRegE; ++r) v[r] = lds[tswz((uint32_t)r * kRegNT + t)];
+}
+
+// Direction of merge step K for an element whose index bits >= 4 are those
+// of `hi` (base + 16 t in the column layout): ascending when bit K is clear.
+template <int K>
+__device__ __forceinline__ bool asc_of(uint64_t hi) {
+  return ((hi >> K) & 1) == 0;
+}
+
+// Column layout, stride 2^JL with JL <= 3: registers r and r + 2^JL.
+template <int K, int JL>
+__device__ __forceinline__ void col_reg_stage(uint64_t (&v)[kRegE], uint64_t hi) {
+  constexpr int m = 1 << JL;
+#pragma unroll
+  for (int r = 0; r < kRegE; ++r) {
+    if (r & m) continue;
+    bool asc;
+    if constexpr (K <= 3)
+      asc = ((r >> K) & 1) == 0;
+    else
+      asc = asc_of<K>(hi);
+    const uint64_t x = v[r], y = v[r + m];
+    v[r] = minmax(x, y, asc);
+    v[r + m] = minmax(x, y, !asc);
   }
+}
+
+// The value of lane (lane XOR D), D in {1, 2, 4, 8, 16}: DPP quad
+// permutations for 1 and 2 (plain VALU), the LDS crossbar's bit-mask
+// swizzle (no LDS memory, no address operand) for 4, 8 and 16.
+template <int D>
+__device__ __forceinline__ uint32_t xor_lane32(uint32_t x) {
+  if constexpr (D == 1)
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0xB1, 0xF, 0xF, false);  // quad_perm [1,0,3,2]
+  else if constexpr (D == 2)
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x4E, 0xF, 0xF, false);  // quad_perm [2,3,0,1]
+  else
+    return (uint32_t)__builtin_amdgcn_ds_swizzle((int)x, 0x1F | (D << 10));  // and 0x1F, or 0, xor D
+}
+
+template <int D>
+__device__ __forceinline__ uint64_t xor_lane(uint64_t x) {
+  const uint32_t lo = xor_lane32<D>((uint32_t)x), hi = xor_lane32<D>((uint32_t)(x >> 32));
+  return ((uint64_t)hi << 32) | lo;
+}
+
+// Column layout, stride 2^JL with 4 <= JL <= 8: lanes 2^(JL-4) apart.
+template <int K, int JL>
+__device__ __forceinline__ void col_lane_stage(uint64_t (&v)[kRegE], uint64_t hi, uint32_t t) {
+  constexpr int d = 1 << (JL - 4);
+  const bool lower = ((t >> (JL - 4)) & 1) == 0;
+  const bool takemin = lower == asc_of<K>(hi);
+#pragma unroll
+  for (int r = 0; r < kRegE; ++r) {
+    const uint64_t y = xor_lane<d>(v[r]);
+    v[r] = minmax(v[r], y, takemin);
+  }
+}
+
+// Column layout: strides 2^JL .. 1 of merge step K.
+template <int K, int JL>
+__device__ __forceinline__ void col_stages(uint64_t (&v)[kRegE], uint64_t hi, uint32_t t) {
+  if constexpr (JL >= 4)
+    col_lane_stage<K, JL>(v, hi, t);
+  else
+    col_reg_stage<K, JL>(v, hi);
+  if constexpr (JL > 0) col_stages<K, JL - 1>(v, hi, t);
+}
+
+// Row layout, stride 2^JL with 9 <= JL <= 12: registers r and r + 2^(JL-9).
+// For K <= 12 the direction is bit K - 9 of r; above, bit K of the tile base.
+template <int K, int JL>
+__device__ __forceinline__ void row_stages(uint64_t (&v)[kRegE], uint64_t base) {
+  constexpr int m = 1 << (JL - 9);
+#pragma unroll
+  for (int r = 0; r < kRegE; ++r) {
+    if (r & m) continue;
+    bool asc;
+    if constexpr (K <= 12)
+      asc = ((r >> (K - 9)) & 1) == 0;
+    else
+      asc = asc_of<K>(base);
+    const uint64_t x = v[r], y = v[r + m];
+    v[r] = minmax(x, y, asc);
+    v[r + m] = minmax(x, y, !asc);
+  }
+  if constexpr (JL > 9) row_stages<K, JL - 1>(v, base);
+}
+
+// Merge steps K .. 9 of a full tile sort, all in the column layout.
+template <int K>
+__device__ __forceinline__ void tile_low_steps(uint64_t (&v)[kRegE], uint64_t hi, uint32_t t) {
+  col_stages<K, K - 1>(v, hi, t);
+  if constexpr (K < 9) tile_low_steps<K + 1>(v, hi, t);
+}
+
+// Merge steps K .. 13: long strides in rows, then the rest in columns.
+template <int K>
+__device__ __forceinline__ void tile_high_steps(uint64_t (&v)[kRegE], uint64_t* lds, uint64_t base, uint64_t hi,
+                                                uint32_t t) {
+  cols_to_rows(v, lds, t);
+  row_stages<K, K - 1>(v, base);
+  rows_to_cols(v, lds, t);
+  col_stages<K, 8>(v, hi, t);
+  if constexpr (K < 13) tile_high_steps<K + 1>(v, lds, base, hi, t);
+}
+
+// Full sort (mode 0) or the strides 4096 .. 1 of merge step k_log > 13
+// (mode 1) of the 8192-element tile at `base`.
+__device__ __forceinline__ void tile_sort_regs(uint64_t* __restrict__ a, uint64_t base, int mode, uint32_t k_log,
+                                               uint64_t* lds) {
+  const uint32_t t = threadIdx.x;
+  uint64_t v[kRegE];
+#pragma unroll
+  for (int r = 0; r < kRegE; ++r) v[r] = a[base + (uint32_t)r * kRegNT + t];
+  const uint64_t hi = base + (uint64_t)t * kRegE;
+  if (mode == 0) {
+    rows_to_cols(v, lds, t);
+    tile_low_steps<1>(v, hi, t);
+    tile_high_steps<10>(v, lds, base, hi, t);
+  } else {
+    // one step k_log > 13: the direction is bit k_log of base for the whole tile
+    const bool asc = ((base >> k_log) & 1) == 0;
+    const uint64_t h = asc ? 0 : (1ull << 14);  // a stand-in whose bit 14 carries the direction
+    row_stages<14, 12>(v, h);
+    rows_to_cols(v, lds, t);
+    col_stages<14, 8>(v, h, t);
+  }
+  cols_to_rows(v, lds, t);
+#pragma unroll
+  for (int r = 0; r < kRegE; ++r) a[base + (uint32_t)r * kRegNT + t] = v[r];
+}
+
+// LDS stages on one tile of T = 2^logt <= 8192 elements, one stage per
+// pass (tiles shorter than 8192: arrays below 8192 elements).  Mode 0: full
+// tile sort.  Mode 1: the tail of merge step k (strides T/2 .. 1).
+__device__ __forceinline__ void tile_sort_lds(uint64_t* __restrict__ a, uint64_t base, uint32_t logt, int mode,
+                                              uint32_t k_log, uint64_t* s) {
   const uint32_t T = 1u << logt;
-  const uint64_t base = (uint64_t)blockIdx.x * T;
-  for (uint32_t x = threadIdx.x; x < T; x += NT) s[x] = a[base + x];
+  for (uint32_t x = threadIdx.x; x < T; x += kRegNT) s[x] = a[base + x];
   __syncthreads();
   const uint32_t half = T >> 1;
-  if (mode == 0) {
-    for (uint32_t kl = 1; kl <= logt; ++kl) {
-      for (int jl = (int)kl - 1; jl >= 0; --jl) {
-        const uint32_t j = 1u << jl;
-        for (uint32_t p = threadIdx.x; p < half; p += NT) {
-          uint32_t i = ((p >> jl) << (jl + 1)) | (p & (j - 1));
-          bool asc = (((base + i) >> kl) & 1) == 0;
-          uint64_t x = s[i], y = s[i + j];
-          cmpex(x, y, asc);
-          s[i] = x;
-          s[i + j] = y;
-        }
-        __syncthreads();
-      }
-    }
-  } else {
-    const bool asc = ((base >> k_log) & 1) == 0;
-    for (int jl = (int)logt - 1; jl >= 0; --jl) {
+  const uint32_t kl0 = mode == 0 ? 1 : logt;
+  for (uint32_t kl = kl0; kl <= logt; ++kl) {
+    for (int jl = (int)kl - 1; jl >= 0; --jl) {
       const uint32_t j = 1u << jl;
-      for (uint32_t p = threadIdx.x; p < half; p += NT) {
+      for (uint32_t p = threadIdx.x; p < half; p += kRegNT) {
         uint32_t i = ((p >> jl) << (jl + 1)) | (p & (j - 1));
+        const uint32_t kk = mode == 0 ? kl : k_log;
+        bool asc = (((base + i) >> kk) & 1) == 0;
         uint64_t x = s[i], y = s[i + j];
         cmpex(x, y, asc);
         s[i] = x;
@@ -184,7 +331,30 @@ __global__ __launch_bounds__(NT) void k_bitonic_tile(uint64_t* __restrict__ a1, 
       __syncthreads();
     }
   }
-  for (uint32_t x = threadIdx.x; x < T; x += NT) a[base + x] = s[x];
+  for (uint32_t x = threadIdx.x; x < T; x += kRegNT) a[base + x] = s[x];
+}
+
+// One launch of the tile stages: 8192-element tiles in registers, shorter
+// (whole-array) tiles in LDS.
+template <bool MULTI>
+__global__ __launch_bounds__(kRegNT, 4) void k_bitonic_tile(uint64_t* __restrict__ a1, uint32_t logt1, int mode,
+                                                         uint32_t k_log, const NetSeg* segs) {
+  __shared__ uint64_t lds[1 << kSortLogT];
+  uint64_t* __restrict__ a = a1;
+  uint32_t logt = logt1;
+  if (MULTI) {
+    const NetSeg g = segs[blockIdx.y];
+    const uint32_t L = ilog2_ceil(g.n);
+    if (mode == 1 && L < k_log) return;  // whole block: this array is shorter
+    logt = L < (uint32_t)kSortLogT ? L : (uint32_t)kSortLogT;
+    if (blockIdx.x >= (g.n >> logt)) return;
+    a = g.a;
+  }
+  const uint64_t base = (uint64_t)blockIdx.x << logt;
+  if (logt == (uint32_t)kSortLogT)
+    tile_sort_regs(a, base, mode, k_log, lds);
+  else
+    tile_sort_lds(a, base, logt, mode, k_log, lds);
 }
 
 // F consecutive strides 2^(jl_top) .. 2^(jl_top - F + 1) of merge step k in
@@ -230,8 +400,8 @@ static void sort_schedule(uint64_t* a, uint64_t nmax, const NetSeg* segs, uint32
   const uint64_t tiles = nmax >> logt;
   {
     TimedScope ts(tm, kkSortTile, st);
-    hipLaunchKernelGGL((k_bitonic_tile<kSortLogT, kSortNT, MULTI>), dim3((uint32_t)tiles, count), dim3(kSortNT), 0,
-                       st, a, logt, 0, 0u, segs);
+    hipLaunchKernelGGL((k_bitonic_tile<MULTI>), dim3((uint32_t)tiles, count), dim3(kRegNT), 0, st, a, logt, 0, 0u,
+                       segs);
   }
   for (uint32_t k_log = logt + 1; k_log <= L; ++k_log) {
     int jl = (int)k_log - 1;
@@ -249,8 +419,8 @@ static void sort_schedule(uint64_t* a, uint64_t nmax, const NetSeg* segs, uint32
       jl -= F;
     }
     TimedScope ts(tm, kkSortMerge, st);
-    hipLaunchKernelGGL((k_bitonic_tile<kSortLogT, kSortNT, MULTI>), dim3((uint32_t)tiles, count), dim3(kSortNT), 0,
-                       st, a, logt, 1, k_log, segs);
+    hipLaunchKernelGGL((k_bitonic_tile<MULTI>), dim3((uint32_t)tiles, count), dim3(kRegNT), 0, st, a, logt, 1,
+                       k_log, segs);
   }
 }
 
