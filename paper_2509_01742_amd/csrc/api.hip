@@ -61,8 +61,7 @@ int derive(const bolt_params* p, Sizes* s) {
 
 uint64_t scratch_bytes(const Sizes& s) {
   const uint64_t Q = kMaxBatch;
-  return Q * 4 * 13 + Q * s.vs + Q * 8 + 3 * Q * 4 + 2 * Q * s.page_bytes + 2 * Q * s.vs + 2 * Q + Q * 12 + 256 * 4 +
-         65 * 4;
+  return Q * 4 * 13 + Q * s.vs + Q * 8 + 3 * Q * 4 + 2 * Q * s.page_bytes + 2 * Q * s.vs + 2 * Q + Q * 24 + 256 * 4;
 }
 
 uint64_t device_bytes(const bolt_params* p, const Sizes& s) {
@@ -238,9 +237,8 @@ int bolt_create(const bolt_params* p, void* hip_stream, bolt_map** out) {
   rc = rc ? rc : dalloc(m, &b.chosen, Q * 4);
   rc = rc ? rc : dalloc(m, &b.rowsel, Q * 4);
   rc = rc ? rc : dalloc(m, &b.freed, 256 * 4);
-  rc = rc ? rc : dalloc(m, &b.pofs, 65 * 4);
-  rc = rc ? rc : dalloc(m, &b.pkey, Q * 8);
-  rc = rc ? rc : dalloc(m, &b.pidx, Q * 4);
+  rc = rc ? rc : dalloc(m, &b.fpair, Q * 8);
+  rc = rc ? rc : dalloc(m, &b.rows, Q * 16);
   rc = rc ? rc : dalloc(m, &m->get_ops, Q);
   rc = rc ? rc : dalloc(m, &m->put_ops, Q);
   rc = rc ? rc : dalloc(m, &m->discard, 2 * Q * s.vs);

@@ -28,9 +28,8 @@ struct BatchScratch {
   uint32_t* chosen;   // [Q] (leaders placed) bin chosen by P2C
   uint32_t* rowsel;   // [Q] (keys inserted) position-map row chosen
   uint32_t* freed;    // [256] stash entries freed this batch, in buckets
-  uint32_t* pofs;     // [65] first command of each key partition
-  uint64_t* pkey;     // [Q] keys grouped by partition
-  uint32_t* pidx;     // [Q] command indexes grouped by partition
+  uint2* fpair;       // [Q] fetch pair F(s) of each command
+  uint4* rows;        // [Q] position-map rows of each command's key
 };
 
 struct TraceSeg {

@@ -33,25 +33,18 @@
 
 namespace bolt {
 
-struct PartArgs {
+struct GroupArgs {
   const uint8_t* ops;
   const uint64_t* keys;
   uint32_t q, epoch;
+  uint64_t B, R;
   Ctl* ctl;
-  uint32_t* pofs;
-  uint64_t* pkey;
-  uint32_t* pidx;
-};
-
-struct GroupArgs {
-  uint32_t epoch;
-  const Ctl* ctl;
-  const uint32_t* pofs;
-  const uint64_t* pkey;
-  const uint32_t* pidx;
   uint32_t* leader;
   uint32_t* prevw;
   uint32_t* lastw;
+  uint2* fpair;
+  uint2* rpair;
+  uint4* rows;
 };
 
 struct FetchArgs {
@@ -59,6 +52,8 @@ struct FetchArgs {
   const uint8_t* ops;
   const uint64_t* keys;
   const uint32_t* leader;
+  const uint2* fpair;
+  const uint4* rows;
   uint32_t q, epoch;
   uint64_t B, K, R;
   uint32_t Z, W, d, vw;
@@ -206,7 +201,6 @@ struct FinishArgs {
 // plan of map blockIdx.y from a device table; a single-map launch passes
 // the argument block by value.
 struct AccessPlan {
-  PartArgs pt;
   GroupArgs gr;
   FetchArgs fa;
   ResolveArgs rv;
@@ -379,69 +373,21 @@ __device__ __forceinline__ uint32_t part_of(uint64_t key) {
   return (uint32_t)(x >> 58);  // top 6 bits: kParts = 64
 }
 
-// One workgroup: op check, a histogram of the partitions in LDS, their
-// offsets, then every (key, index) scattered to its partition (no global
-// atomics).  A batch with an op code above DEL is marked rejected.
-template <bool MULTI>
-__global__ __launch_bounds__(1024) void k_acc_part(PartArgs a1, const AccessPlan* tab) {
-  BOLT_PICK(PartArgs, pt);
-  const uint8_t* __restrict__ ops = a.ops;
-  const uint64_t* __restrict__ keys = a.keys;
-  const uint32_t q = a.q, epoch = a.epoch;
-  Ctl* ctl = a.ctl;
-  uint32_t* __restrict__ pofs = a.pofs;
-  uint64_t* __restrict__ pkey = a.pkey;
-  uint32_t* __restrict__ pidx = a.pidx;
-  __shared__ uint32_t hist[kParts];
-  __shared__ uint32_t base[kParts];
-  __shared__ uint32_t bad;
-  if (threadIdx.x < kParts) hist[threadIdx.x] = 0;
-  if (threadIdx.x == 0) bad = 0;
-  __syncthreads();
-  uint32_t mypart[kMaxBatch / 1024], myrank[kMaxBatch / 1024];
-#pragma unroll
-  for (uint32_t t = 0; t < kMaxBatch / 1024; ++t) {
-    const uint32_t i = threadIdx.x + t * 1024;
-    if (i < q) {
-      if (ops[i] > 2) bad = 1;
-      mypart[t] = part_of(keys[i]);
-      myrank[t] = atomicAdd(&hist[mypart[t]], 1u);
-    }
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    uint32_t acc = 0;
-    for (uint32_t b = 0; b < kParts; ++b) {
-      base[b] = acc;
-      pofs[b] = acc;
-      acc += hist[b];
-    }
-    pofs[kParts] = acc;
-    if (bad) ctl->reject = epoch;
-  }
-  __syncthreads();
-#pragma unroll
-  for (uint32_t t = 0; t < kMaxBatch / 1024; ++t) {
-    const uint32_t i = threadIdx.x + t * 1024;
-    if (i < q) {
-      const uint32_t pos = base[mypart[t]] + myrank[t];
-      pkey[pos] = keys[i];
-      pidx[pos] = (i << 2) | (ops[i] & 3u);  // ordering by this payload is ordering by index
-    }
-  }
-}
-
-// One workgroup per partition: sort its (key, index) pairs; leader = first
-// command of each key; for every command the last PUT/DEL of its key before
-// it; for every leader the last PUT/DEL of its key in the batch.
+// One workgroup per partition (kParts of them).  First the workgroup
+// computes the PRF outputs of its slice of the commands (the batch split in
+// kParts equal slices, one PRF per thread): the fetch pair F(s) and remap
+// pair R(s) of tape step s, and the key's position-map rows.  Then it picks
+// the commands of its partition out of the whole batch (all commands of a
+// key land in one partition), sorts their (key, index) pairs, and derives
+// for each command its leader (first command of its key), the last PUT/DEL
+// of its key before it, and for each leader the last PUT/DEL of its key in
+// the batch.  A batch with an op code above DEL is marked rejected.
 template <bool MULTI>
 __global__ __launch_bounds__(kDedupNT) void k_acc_group(GroupArgs a1, const AccessPlan* tab) {
   BOLT_PICK(GroupArgs, gr);
-  const uint32_t epoch = a.epoch;
-  const Ctl* ctl = a.ctl;
-  const uint32_t* __restrict__ pofs = a.pofs;
-  const uint64_t* __restrict__ pkey = a.pkey;
-  const uint32_t* __restrict__ pidx = a.pidx;
+  const uint8_t* __restrict__ ops = a.ops;
+  const uint64_t* __restrict__ keys = a.keys;
+  const uint32_t qall = a.q;
   uint32_t* __restrict__ leader = a.leader;
   uint32_t* __restrict__ prevw = a.prevw;
   uint32_t* __restrict__ lastw = a.lastw;
@@ -449,9 +395,57 @@ __global__ __launch_bounds__(kDedupNT) void k_acc_group(GroupArgs a1, const Acce
   __shared__ uint32_t sidx[kMaxBatch];
   __shared__ uint32_t tot;
   const uint32_t part = blockIdx.x;
-  const uint32_t off = pofs[part];
-  const uint32_t q = pofs[part + 1] - off;  // commands in this partition
-  if (q == 0 || ctl->reject == epoch) return;  // whole block
+  {  // PRF outputs of this block's slice, two PRFs per command
+    const uint32_t cs = (qall + kParts - 1) / kParts;
+    const uint32_t i = part * cs + (threadIdx.x >> 1);
+    if ((threadIdx.x >> 1) < cs && i < qall) {
+      uint32_t hk[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) hk[j] = a.ctl->hkey[j];
+      uint64_t w[4];
+      if ((threadIdx.x & 1) == 0) {
+        prf4(hk, kDomTape, a.ctl->steps + i, w);
+        uint32_t f1, f2, r1, r2;
+        pair_of(w[0], w[1], a.B, f1, f2);
+        pair_of(w[2], w[3], a.B, r1, r2);
+        a.fpair[i] = make_uint2(f1, f2);
+        a.rpair[i] = make_uint2(r1, r2);
+      } else {
+        prf4(hk, kDomRows, keys[i], w);
+        a.rows[i] = make_uint4((uint32_t)__umul64hi(w[0], a.R), (uint32_t)__umul64hi(w[1], a.R),
+                               (uint32_t)__umul64hi(w[2], a.R), (uint32_t)__umul64hi(w[3], a.R));
+      }
+    }
+  }
+  // this partition's commands, in index order (the order does not matter:
+  // they are sorted next)
+  uint32_t mine = 0;
+  bool bad = false;
+#pragma unroll
+  for (uint32_t u = 0; u < kMaxBatch / kDedupNT; ++u) {
+    const uint32_t i = threadIdx.x + u * kDedupNT;
+    if (i < qall) {
+      mine += part_of(keys[i]) == part;
+      bad |= ops[i] > 2;
+    }
+  }
+  if (__any(bad) && (threadIdx.x & 63) == 0) a.ctl->reject = a.epoch;  // same value from every writer
+  uint32_t at = block_excl<kDedupNT, false>(mine, &tot);
+#pragma unroll
+  for (uint32_t u = 0; u < kMaxBatch / kDedupNT; ++u) {
+    const uint32_t i = threadIdx.x + u * kDedupNT;
+    if (i < qall) {
+      const uint64_t key = keys[i];
+      if (part_of(key) == part) {
+        skey[at] = key;
+        sidx[at] = (i << 2) | (ops[i] & 3u);  // ordering by this payload is ordering by index
+        ++at;
+      }
+    }
+  }
+  __syncthreads();
+  const uint32_t q = tot;  // commands in this partition
+  if (q == 0) return;      // whole block
   uint32_t npad = 1;
   while (npad < q) npad <<= 1;
   uint64_t k[kDedupPer];
@@ -461,9 +455,10 @@ __global__ __launch_bounds__(kDedupNT) void k_acc_group(GroupArgs a1, const Acce
   for (uint32_t e = 0; e < kDedupPer; ++e) {
     const uint32_t r = r0 + e;
     const bool real = r < q;
-    k[e] = real ? pkey[off + r] : kNone64;
-    x[e] = real ? pidx[off + r] : kNone;  // command index << 2 | op
+    k[e] = real ? skey[r] : kNone64;
+    x[e] = real ? sidx[r] : kNone;  // command index << 2 | op
   }
+  __syncthreads();  // the sort reuses skey / sidx
   dedup_sort(k, x, npad, skey, sidx);
   // Fold structure.  Each thread owns kDedupPer consecutive sorted
   // positions; positions are stored +1 so that 0 means "none".  The payload
@@ -516,29 +511,17 @@ __global__ __launch_bounds__(256) void k_acc_fetch(FetchArgs a1, const AccessPla
   const uint32_t i = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (i >= a.q) return;
   if (a.ctl->reject == a.epoch || a.ctl->err) return;
-  uint32_t hk[8];
-#pragma unroll
-  for (int j = 0; j < 8; ++j) hk[j] = a.ctl->hkey[j];
-  const uint64_t s = a.ctl->steps + i;
-  uint64_t w[4];
-  prf4(hk, kDomTape, s, w);
-  uint32_t f1, f2, r1, r2;
-  pair_of(w[0], w[1], a.B, f1, f2);
-  pair_of(w[2], w[3], a.B, r1, r2);
-  if (lane == 0) a.rpair[i] = make_uint2(r1, r2);
+  const uint2 fp = a.fpair[i];  // F(s), from the dedup kernel
+  const uint32_t f1 = fp.x, f2 = fp.y;
   const uint64_t key = a.keys[i];
   const bool is_leader = a.leader[i] == i;
   // key search (Sec. 5.1 step 3): d rows, 16 lanes per row, 2 slots per lane
   bool hit = false;
   uint32_t hrow = 0, hslot = 0, p1 = f1, p2 = f2;
   if (is_leader) {
-    uint32_t rows[4];
-    uint64_t g[4];
-    prf4(hk, kDomRows, key, g);
-#pragma unroll
-    for (int j = 0; j < 4; ++j) rows[j] = (uint32_t)__umul64hi(g[j], a.R);
+    const uint4 rw = a.rows[i];
     const uint32_t j = lane >> 4;
-    const uint32_t row = rows[j];
+    const uint32_t row = j == 0 ? rw.x : j == 1 ? rw.y : j == 2 ? rw.z : rw.w;
     const uint32_t s0 = (lane & 15) * 2;
     bool m0 = false, m1 = false;
     if (j < a.d) {
@@ -1107,14 +1090,15 @@ static void plan_access(bolt_map* m, const uint8_t* ops, const uint64_t* keys, c
   const uint64_t* vin = reinterpret_cast<const uint64_t*>(vals_in);
   const uint64_t* fval = reinterpret_cast<const uint64_t*>(bs.fval);
 
-  P.pt = PartArgs{ops, keys, q, epoch, m->ctl, bs.pofs, bs.pkey, bs.pidx};
-  P.gr = GroupArgs{epoch, m->ctl, bs.pofs, bs.pkey, bs.pidx, bs.leader, bs.prevw, bs.lastw};
+  P.gr = GroupArgs{ops, keys, q, epoch, s.B, s.R, m->ctl, bs.leader, bs.prevw, bs.lastw, bs.fpair, bs.rpair, bs.rows};
 
   FetchArgs& fa = P.fa;
   fa.ctl = m->ctl;
   fa.ops = ops;
   fa.keys = keys;
   fa.leader = bs.leader;
+  fa.fpair = bs.fpair;
+  fa.rows = bs.rows;
   fa.q = q;
   fa.epoch = epoch;
   fa.B = s.B;
@@ -1292,7 +1276,6 @@ int run_access(bolt_map* m, const uint8_t* ops, const uint64_t* keys, const void
   const AccessPlan* none = nullptr;
   {
     TimedScope ts(m->timer, kkAccDedup, st);
-    hipLaunchKernelGGL(k_acc_part<false>, dim3(1), dim3(1024), 0, st, P.pt, none);
     hipLaunchKernelGGL(k_acc_group<false>, dim3(kParts), dim3(kDedupNT), 0, st, P.gr, none);
   }
   {
@@ -1344,7 +1327,6 @@ int run_access_many(bolt_map* const* maps, const bolt_batch* batches, uint32_t c
     return BOLT_EHIP;
   }
   const uint32_t C = count;
-  hipLaunchKernelGGL(k_acc_part<true>, dim3(1, C), dim3(1024), 0, st, plans[0].pt, tab);
   hipLaunchKernelGGL(k_acc_group<true>, dim3(kParts, C), dim3(kDedupNT), 0, st, plans[0].gr, tab);
   hipLaunchKernelGGL(k_acc_fetch<true>, dim3((qmax + 3) / 4, C), dim3(256), 0, st, plans[0].fa, tab);
   hipLaunchKernelGGL(k_acc_resolve<true>, dim3((qmax + 255) / 256, C), dim3(256), 0, st, plans[0].rv, tab);
