@@ -72,6 +72,8 @@ def run_mode(args, wl, dev_t, B, torch, observable):
     d_keys, d_vals, d_ops, d_qk, d_qv, d_out, d_st, bounds = dev_t
     obs = B.BOLT_OBS_HOST_PINNED if observable == "host" else B.BOLT_OBS_DEVICE
     p = B.params(wl.cap, vs, observable=obs)
+    if args.graphs:
+        p.flags |= B.BOLT_F_GRAPHS
     sz = B.sizes_of(p)
     sz["vs"] = vs
     sz["host"] = observable == "host"
@@ -200,6 +202,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-batches", type=int, default=512)
     ap.add_argument("--no-multi", action="store_true", help="skip the 64-map batched figures")
+    ap.add_argument("--graphs", action="store_true", help="maps replay captured graphs per batch-size class")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the default network schedules")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving figures")
     ap.add_argument("--serve-seconds", type=float, default=3.0, help="steady window of each open-loop serving run")
     ap.add_argument("--copy-calib", type=int, default=0,
@@ -237,6 +241,14 @@ def main():
         del src, dst
         log("copy calibration: %d MiB device-to-device" % args.copy_calib)
 
+    tuned = None
+    if not args.no_autotune:  # schedules of the sort and expansion networks, outside the timed regions
+        t0 = time.time()
+        B.check(B.autotune(1 << 25), "bolt_autotune")
+        torch.cuda.synchronize()
+        tuned = {"seconds": round(time.time() - t0, 2), "table": B.tune_table()}
+        log("autotune: %.1fs %s" % (tuned["seconds"], [(e["log2_n"], e["sort_tile_log"], e["sort_pass_strides"],
+                                                         e["expand_pass_stages"]) for e in tuned["table"]]))
     main_res = run_mode(args, wl, dev_t, B, torch, args.observable)
     other = None
     if not args.single_mode:
@@ -289,6 +301,7 @@ def main():
         "roofline_sort": roofline_sort,
         "kernels": ks,
         "other_observable_mode": other,
+        "autotune": tuned,
         "multi_map": multi,
         "serving": serving,
         "cpu_baseline": cpu,

@@ -72,6 +72,8 @@ enum { BOLT_OBS_HOST_PINNED = 0, BOLT_OBS_DEVICE = 1 };
 #define BOLT_F_TRACE 1u     /* record every observable access (tests; costs a little time) */
 #define BOLT_F_FIXED_KEY 2u /* use params.key as the PRF key instead of fresh OS randomness */
 #define BOLT_F_TIMING 4u    /* time every kernel class with HIP events on its stream (benchmarks) */
+#define BOLT_F_GRAPHS 8u    /* run one-map batches by replaying a HIP graph captured once per power-of-two batch
+                               size (fewer host launch calls; results identical).  Not with TRACE or TIMING. */
 
 #define BOLT_MAX_BATCH 8192u /* most commands in one access call */
 
@@ -363,6 +365,40 @@ int bolt_server_reset_stats(bolt_server* srv);
 /* Stops the loop, waits for the device and frees every map of the server.
  * Requests still pending are abandoned.  NULL is a no-op. */
 int bolt_server_destroy(bolt_server* srv);
+
+/* ---------------------------------------------------------------------
+ * Autotuning of the network schedules.
+ *
+ * Per array-length class 2^L (and device), the sort's tile (2^11, 2^12 or
+ * 2^13 elements; the last runs in registers), the strides fused per global
+ * sort pass (1..4) and the stages fused per global expansion pass (1..4).
+ * Defaults: 13, 4, 4.  No choice changes any result, and every network's
+ * memory accesses still depend on the array length alone; only speed
+ * differs.  The table is per process and device.
+ * --------------------------------------------------------------------- */
+
+typedef struct {
+  uint32_t log2_n;             /* the length class */
+  uint32_t sort_tile_log;      /* 11..13 */
+  uint32_t sort_pass_strides;  /* 1..4 */
+  uint32_t expand_pass_stages; /* 1..4 */
+  float sort_ms, expand_ms;    /* measured time of the chosen schedules */
+} bolt_tune_entry;
+
+/* Tunes the classes 2^14 .. 2^ceil(log2 n_max) (at most 2^28) on the
+ * current device by timing every candidate on scratch arrays (it allocates
+ * about 24 n_max bytes while it runs and synchronises the stream).  With a
+ * cache_path: a cache file written earlier for this device is loaded
+ * instead of tuning; otherwise the results are written there. */
+int bolt_autotune(uint64_t n_max, const char* cache_path, void* hip_stream);
+
+/* Reads the tuned entries of the current device (*n = how many there are). */
+int bolt_tune_get(bolt_tune_entry* host_out, uint32_t cap, uint32_t* n);
+
+/* Sets entries by hand (for example to test every schedule), and resets
+ * the current device's table to the defaults. */
+int bolt_tune_set(const bolt_tune_entry* host_in, uint32_t n);
+int bolt_tune_reset(void);
 
 /* ---------------------------------------------------------------------
  * Device primitives of the path, exported so each can be checked alone.

@@ -20,7 +20,7 @@ BOLT_OK, BOLT_EINVAL, BOLT_ENOMEM, BOLT_EDUPKEY, BOLT_EOVERFLOW, BOLT_EFULL, BOL
 BOLT_OP_GET, BOLT_OP_PUT, BOLT_OP_DEL = 0, 1, 2
 BOLT_ST_ABSENT, BOLT_ST_FOUND, BOLT_ST_UPDATED, BOLT_ST_INSERTED, BOLT_ST_DELETED = 0, 1, 1, 2, 3
 BOLT_OBS_HOST_PINNED, BOLT_OBS_DEVICE = 0, 1
-BOLT_F_TRACE, BOLT_F_FIXED_KEY, BOLT_F_TIMING = 1, 2, 4
+BOLT_F_TRACE, BOLT_F_FIXED_KEY, BOLT_F_TIMING, BOLT_F_GRAPHS = 1, 2, 4, 8
 BOLT_MAX_BATCH = 8192
 BOLT_ETIMEOUT = -8
 BOLT_SRV_WAITING, BOLT_SRV_BUILDING, BOLT_SRV_RESIDENT, BOLT_SRV_CLOSED, BOLT_SRV_FAILED = 0, 1, 2, 3, 4
@@ -88,6 +88,11 @@ class bolt_server_stats(C.Structure):
         return {n: getattr(self, n) for n, _ in self._fields_}
 
 
+class bolt_tune_entry(C.Structure):
+    _fields_ = [("log2_n", C.c_uint32), ("sort_tile_log", C.c_uint32), ("sort_pass_strides", C.c_uint32),
+                ("expand_pass_stages", C.c_uint32), ("sort_ms", C.c_float), ("expand_ms", C.c_float)]
+
+
 TRACE_DTYPE = np.dtype([("batch", "<u4"), ("kind", "<u4"), ("page", "<u8")])
 
 # (name, restype, argtypes) of every entry point in include/bolt.h
@@ -130,6 +135,10 @@ _SIGS = [
     ("bolt_server_get_stats", _I, [_P, C.POINTER(bolt_server_stats)]),
     ("bolt_server_reset_stats", _I, [_P]),
     ("bolt_server_destroy", _I, [_P]),
+    ("bolt_autotune", _I, [_U64, C.c_char_p, _P]),
+    ("bolt_tune_get", _I, [C.POINTER(bolt_tune_entry), _U32, C.POINTER(_U32)]),
+    ("bolt_tune_set", _I, [C.POINTER(bolt_tune_entry), _U32]),
+    ("bolt_tune_reset", _I, []),
     ("bolt_prf", _I, [_P, _U8, _P, _U64, _P, _P]),
     ("bolt_sort_u64", _I, [_P, _U64, _P]),
     ("bolt_expand_u64", _I, [_P, _P, _U64, _P]),
@@ -433,6 +442,27 @@ class Server:
 
     def reset_stats(self):
         check(bolt_server_reset_stats(self.h), "bolt_server_reset_stats")
+
+
+def autotune(n_max: int, cache_path=None, stream=None) -> int:
+    """Tunes (or loads from cache_path) the network schedules up to arrays of n_max."""
+    path = None if cache_path is None else os.fsencode(cache_path)
+    return bolt_autotune(n_max, path, _stream(stream))
+
+
+def tune_table() -> list:
+    arr = (bolt_tune_entry * 64)()
+    n = C.c_uint32()
+    check(bolt_tune_get(arr, 64, C.byref(n)), "bolt_tune_get")
+    return [{f: getattr(arr[i], f) for f, _ in bolt_tune_entry._fields_} for i in range(min(n.value, 64))]
+
+
+def tune_set(entries) -> int:
+    arr = (bolt_tune_entry * max(1, len(entries)))()
+    for i, e in enumerate(entries):
+        arr[i] = bolt_tune_entry(e["log2_n"], e["sort_tile_log"], e["sort_pass_strides"], e["expand_pass_stages"],
+                                 e.get("sort_ms", 0.0), e.get("expand_ms", 0.0))
+    return bolt_tune_set(arr, len(entries))
 
 
 def prf(key: bytes, domain: int, x, out, stream=None) -> int:

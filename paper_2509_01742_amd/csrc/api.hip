@@ -92,6 +92,10 @@ void free_all(bolt_map* m) {
   m->allocs.clear();
   if (m->obs_host) (void)hipHostFree(m->obs_host);
   m->obs_host = nullptr;
+  for (hipGraphExec_t& g : m->gexec) {
+    if (g) (void)hipGraphExecDestroy(g);
+    g = nullptr;
+  }
   if (m->side) (void)hipStreamDestroy(m->side);
   if (m->ev_fork) (void)hipEventDestroy(m->ev_fork);
   if (m->ev_join) (void)hipEventDestroy(m->ev_join);
@@ -183,6 +187,7 @@ int bolt_create(const bolt_params* p, void* hip_stream, bolt_map** out) {
   int rc = derive(p, &s);
   if (rc) return rc;
   if ((p->flags & BOLT_F_TRACE) && p->trace_words == 0) return BOLT_EINVAL;
+  if ((p->flags & BOLT_F_GRAPHS) && (p->flags & (BOLT_F_TRACE | BOLT_F_TIMING))) return BOLT_EINVAL;
   bolt_map* m = new (std::nothrow) bolt_map();
   if (!m) return BOLT_ENOMEM;
   m->p = *p;

@@ -158,6 +158,13 @@ __device__ __forceinline__ uint32_t ld_acq32(const uint32_t* p) {
 
 __device__ __forceinline__ void set_err(Ctl* ctl, uint32_t bits) { atomicOr(&ctl->err, bits); }
 
+// Smallest l with 2^l >= n.
+__host__ __device__ __forceinline__ uint32_t ilog2_ceil(uint64_t n) {
+  uint32_t l = 0;
+  while ((1ull << l) < n) ++l;
+  return l;
+}
+
 // Adds `flag` (0/1) of every active lane to *ctr with one atomic per wave.
 __device__ __forceinline__ void wave_count(uint32_t* ctr, bool flag) {
   const uint64_t bal = __ballot(flag);

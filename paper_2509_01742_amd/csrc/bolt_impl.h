@@ -126,6 +126,10 @@ struct bolt_map {
   // back to the caller's stream with the two events.
   hipStream_t side;
   hipEvent_t ev_fork, ev_join;
+  // BOLT_F_GRAPHS: one access plan on the device, and the graph of the
+  // access pipeline captured per batch-size class ceil(log2 q) = 0..13.
+  void* gplan;
+  hipGraphExec_t gexec[14];
 };
 
 namespace bolt {
@@ -140,7 +144,18 @@ struct NetSeg {
   uint64_t n;
 };
 
+// Schedule of the network kernels for arrays of length class 2^log2n:
+// sort tile 2^sort_tile_log (11..13), strides per global sort pass
+// (1..4), stages per global expansion pass (1..4).  Defaults 13 / 4 / 4;
+// bolt_autotune measures and replaces them.  No choice changes a result.
+struct NetTune {
+  uint32_t sort_tile_log, sort_fmax, exp_fmax;
+};
+NetTune net_tune(uint32_t log2n);
+
 void launch_bitonic_sort(uint64_t* a, uint64_t n, hipStream_t st, KernelTimer* tm = nullptr);
+void launch_bitonic_sort_with(uint64_t* a, uint64_t n, hipStream_t st, uint32_t tile_log, uint32_t fmax);
+uint64_t* launch_expand_with(uint64_t* a, uint64_t* tmp, uint64_t m, hipStream_t st, uint32_t fmax);
 void launch_bitonic_sort_many(const NetSeg* segs, uint32_t count, uint64_t nmax, hipStream_t st);
 void launch_expand(uint64_t* a, uint64_t* tmp, uint64_t m, hipStream_t st, KernelTimer* tm = nullptr);
 // As launch_expand without the final copy: returns the buffer holding the result.

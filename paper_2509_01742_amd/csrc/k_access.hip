@@ -1269,10 +1269,53 @@ static void plan_access(bolt_map* m, const uint8_t* ops, const uint64_t* keys, c
   m->batches++;
 }
 
+// The access pipeline for up to qmax commands of the maps of a device plan
+// table (count of them), every phase one launch.
+static void launch_many(const AccessPlan& p0, const AccessPlan* tab, uint32_t C, uint32_t qmax, uint64_t lds,
+                        bool any_fast, bool any_slow, hipStream_t st) {
+  hipLaunchKernelGGL(k_acc_group<true>, dim3(kParts, C), dim3(kDedupNT), 0, st, p0.gr, tab);
+  hipLaunchKernelGGL(k_acc_fetch<true>, dim3((qmax + 3) / 4, C), dim3(256), 0, st, p0.fa, tab);
+  hipLaunchKernelGGL(k_acc_resolve<true>, dim3((qmax + 255) / 256, C), dim3(256), 0, st, p0.rv, tab);
+  if (any_fast) hipLaunchKernelGGL(k_acc_place<true>, dim3((qmax + 255) / 256, C), dim3(256), 0, st, p0.pa, tab);
+  if (any_slow) hipLaunchKernelGGL(k_acc_remap<true>, dim3(1, C), dim3(kRemapNT), 0, st, p0.ra, tab);
+  hipLaunchKernelGGL(k_acc_writeback<true>, dim3(3 * qmax, C), dim3(64), lds, st, p0.wa, tab);
+  hipLaunchKernelGGL(k_acc_finish<true>, dim3((qmax + 255) / 256, C), dim3(256), 0, st, p0.fn, tab);
+}
+
+// One-map batch through a graph captured for its size class: the call's
+// arguments go to the device plan, then the class's graph replays the
+// pipeline (grids sized for the class; each kernel stops at the plan's q).
+static int run_access_graph(bolt_map* m, AccessPlan& P, hipStream_t st) {
+  uint32_t cls = 0;
+  while ((1u << cls) < P.q) ++cls;
+  if (!m->gplan) {
+    if (hipMalloc(&m->gplan, sizeof(AccessPlan)) != hipSuccess) return BOLT_ENOMEM;
+    m->allocs.push_back(m->gplan);
+  }
+  AccessPlan* tab = static_cast<AccessPlan*>(m->gplan);
+  if (!m->gexec[cls]) {
+    // both remap forms are in the graph; the plan's flags pick one per call
+    hipStream_t cs = m->side;
+    hipGraph_t g = nullptr;
+    if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) return BOLT_EHIP;
+    launch_many(P, tab, 1, 1u << cls, P.wb_lds, true, true, cs);
+    if (hipStreamEndCapture(cs, &g) != hipSuccess || !g) return BOLT_EHIP;
+    hipGraphExec_t ex = nullptr;
+    const hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return BOLT_EHIP;
+    m->gexec[cls] = ex;
+  }
+  if (hipMemcpyAsync(tab, &P, sizeof(AccessPlan), hipMemcpyHostToDevice, st) != hipSuccess) return BOLT_EHIP;
+  if (hipGraphLaunch(m->gexec[cls], st) != hipSuccess) return BOLT_EHIP;
+  return BOLT_OK;
+}
+
 int run_access(bolt_map* m, const uint8_t* ops, const uint64_t* keys, const void* vals_in, void* vals_out,
                uint8_t* status, uint32_t q, hipStream_t st) {
   AccessPlan P;
   plan_access(m, ops, keys, vals_in, vals_out, status, q, st, P);
+  if (m->p.flags & BOLT_F_GRAPHS) return run_access_graph(m, P, st);
   const AccessPlan* none = nullptr;
   {
     TimedScope ts(m->timer, kkAccDedup, st);
@@ -1326,14 +1369,7 @@ int run_access_many(bolt_map* const* maps, const bolt_batch* batches, uint32_t c
     (void)hipFreeAsync(tab, st);
     return BOLT_EHIP;
   }
-  const uint32_t C = count;
-  hipLaunchKernelGGL(k_acc_group<true>, dim3(kParts, C), dim3(kDedupNT), 0, st, plans[0].gr, tab);
-  hipLaunchKernelGGL(k_acc_fetch<true>, dim3((qmax + 3) / 4, C), dim3(256), 0, st, plans[0].fa, tab);
-  hipLaunchKernelGGL(k_acc_resolve<true>, dim3((qmax + 255) / 256, C), dim3(256), 0, st, plans[0].rv, tab);
-  if (any_fast) hipLaunchKernelGGL(k_acc_place<true>, dim3((qmax + 255) / 256, C), dim3(256), 0, st, plans[0].pa, tab);
-  if (any_slow) hipLaunchKernelGGL(k_acc_remap<true>, dim3(1, C), dim3(kRemapNT), 0, st, plans[0].ra, tab);
-  hipLaunchKernelGGL(k_acc_writeback<true>, dim3(3 * qmax, C), dim3(64), lds, st, plans[0].wa, tab);
-  hipLaunchKernelGGL(k_acc_finish<true>, dim3((qmax + 255) / 256, C), dim3(256), 0, st, plans[0].fn, tab);
+  launch_many(plans[0], tab, count, qmax, lds, any_fast, any_slow, st);
   (void)hipFreeAsync(tab, st);
   return hipGetLastError() == hipSuccess ? BOLT_OK : BOLT_EHIP;
 }

@@ -124,14 +124,8 @@ __device__ __forceinline__ void cmpex(uint64_t& x, uint64_t& y, bool asc) {
   y = asc ? hi : lo;
 }
 
-__host__ __device__ __forceinline__ uint32_t ilog2_ceil(uint64_t n) {
-  uint32_t l = 0;
-  while ((1ull << l) < n) ++l;
-  return l;
-}
 
-constexpr int kSortLogT = 13;  // 8192-element tiles (64 KiB of LDS for the transposes)
-constexpr int kSortFMax = 4;
+constexpr int kSortLogT = 13;  // largest tile: 8192 elements (64 KiB of LDS for the transposes)
 
 // ---- tile of 8192 elements, 512 threads, 16 elements per thread --------
 //
@@ -346,7 +340,7 @@ __global__ __launch_bounds__(kRegNT, 4) void k_bitonic_tile(uint64_t* __restrict
     const NetSeg g = segs[blockIdx.y];
     const uint32_t L = ilog2_ceil(g.n);
     if (mode == 1 && L < k_log) return;  // whole block: this array is shorter
-    logt = L < (uint32_t)kSortLogT ? L : (uint32_t)kSortLogT;
+    logt = L < logt1 ? L : logt1;  // logt1: the schedule's tile (at most kSortLogT)
     if (blockIdx.x >= (g.n >> logt)) return;
     a = g.a;
   }
@@ -390,13 +384,15 @@ __global__ __launch_bounds__(256) void k_bitonic_global(uint64_t* __restrict__ a
 }
 
 // One sort schedule for one array (segs == nullptr) or for `count` arrays
-// of the device table `segs` whose longest has length nmax.
+// of the device table `segs` whose longest has length nmax: tiles of
+// 2^tile_log elements (11..13; 13 runs in registers), then up to fmax
+// strides per global pass.  Every choice sorts the same way.
 template <bool MULTI>
 static void sort_schedule(uint64_t* a, uint64_t nmax, const NetSeg* segs, uint32_t count, hipStream_t st,
-                          KernelTimer* tm) {
+                          KernelTimer* tm, uint32_t tile_log, uint32_t fmax) {
   if (nmax < 2) return;
   const uint32_t L = ilog2_ceil(nmax);
-  const uint32_t logt = L < (uint32_t)kSortLogT ? L : (uint32_t)kSortLogT;
+  const uint32_t logt = L < tile_log ? L : tile_log;
   const uint64_t tiles = nmax >> logt;
   {
     TimedScope ts(tm, kkSortTile, st);
@@ -407,7 +403,7 @@ static void sort_schedule(uint64_t* a, uint64_t nmax, const NetSeg* segs, uint32
     int jl = (int)k_log - 1;
     while (jl >= (int)logt) {
       int F = jl - (int)logt + 1;
-      if (F > kSortFMax) F = kSortFMax;
+      if (F > (int)fmax) F = (int)fmax;
       TimedScope ts(tm, kkSortGlobal, st);
       const dim3 grid((uint32_t)(((nmax >> F) + 255) / 256), count), block(256);
       switch (F) {
@@ -425,11 +421,17 @@ static void sort_schedule(uint64_t* a, uint64_t nmax, const NetSeg* segs, uint32
 }
 
 void launch_bitonic_sort(uint64_t* a, uint64_t n, hipStream_t st, KernelTimer* tm) {
-  sort_schedule<false>(a, n, nullptr, 1, st, tm);
+  const NetTune t = net_tune(ilog2_ceil(n));
+  sort_schedule<false>(a, n, nullptr, 1, st, tm, t.sort_tile_log, t.sort_fmax);
+}
+
+void launch_bitonic_sort_with(uint64_t* a, uint64_t n, hipStream_t st, uint32_t tile_log, uint32_t fmax) {
+  sort_schedule<false>(a, n, nullptr, 1, st, nullptr, tile_log, fmax);
 }
 
 void launch_bitonic_sort_many(const NetSeg* segs, uint32_t count, uint64_t nmax, hipStream_t st) {
-  if (count) sort_schedule<true>(nullptr, nmax, segs, count, st, nullptr);
+  const NetTune t = net_tune(ilog2_ceil(nmax));
+  if (count) sort_schedule<true>(nullptr, nmax, segs, count, st, nullptr, t.sort_tile_log, t.sort_fmax);
 }
 
 // ---------------------------------------------------------------------------
@@ -559,7 +561,7 @@ __global__ __launch_bounds__(1024) void k_expand_tile(const uint64_t* __restrict
 // in the scratch buffer (tmp, or each entry's b).
 template <bool MULTI>
 static bool expand_schedule(uint64_t* a, uint64_t* tmp, uint64_t mmax, const NetSeg* segs, uint32_t count,
-                            hipStream_t st, KernelTimer* tm) {
+                            hipStream_t st, KernelTimer* tm, uint32_t fmax) {
   if (mmax < 2) return false;
   int top = 0;
   while ((2ull << top) <= mmax - 1) ++top;
@@ -569,7 +571,7 @@ static bool expand_schedule(uint64_t* a, uint64_t* tmp, uint64_t mmax, const Net
   int j = top;
   while (j >= kExpLow) {  // global passes, up to 4 stages each
     int F = j - kExpLow + 1;
-    if (F > 4) F = 4;
+    if (F > (int)fmax) F = (int)fmax;
     TimedScope ts(tm, kkExpand, st);
     const uint32_t jlow = (uint32_t)(j - F + 1);
     const uint64_t hl = 1ull << jlow;
@@ -598,7 +600,7 @@ static bool expand_schedule(uint64_t* a, uint64_t* tmp, uint64_t mmax, const Net
 }
 
 uint64_t* launch_expand_inplace(uint64_t* a, uint64_t* tmp, uint64_t m, hipStream_t st, KernelTimer* tm) {
-  return expand_schedule<false>(a, tmp, m, nullptr, 1, st, tm) ? tmp : a;
+  return expand_schedule<false>(a, tmp, m, nullptr, 1, st, tm, net_tune(ilog2_ceil(m)).exp_fmax) ? tmp : a;
 }
 
 void launch_expand(uint64_t* a, uint64_t* tmp, uint64_t m, hipStream_t st, KernelTimer* tm) {
@@ -607,7 +609,13 @@ void launch_expand(uint64_t* a, uint64_t* tmp, uint64_t m, hipStream_t st, Kerne
 }
 
 bool launch_expand_many(const NetSeg* segs, uint32_t count, uint64_t mmax, hipStream_t st) {
-  return count ? expand_schedule<true>(nullptr, nullptr, mmax, segs, count, st, nullptr) : false;
+  return count ? expand_schedule<true>(nullptr, nullptr, mmax, segs, count, st, nullptr,
+                                       net_tune(ilog2_ceil(mmax)).exp_fmax)
+               : false;
+}
+
+uint64_t* launch_expand_with(uint64_t* a, uint64_t* tmp, uint64_t m, hipStream_t st, uint32_t fmax) {
+  return expand_schedule<false>(a, tmp, m, nullptr, 1, st, nullptr, fmax) ? tmp : a;
 }
 
 }  // namespace bolt

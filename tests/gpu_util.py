@@ -26,7 +26,7 @@ def host_u64(t):
 class Twin:
     """A GPU map and an oracle map with the same parameters and key."""
 
-    def __init__(self, cap, vs, key=bytes(range(32)), trace=True, observable=0, **kw):
+    def __init__(self, cap, vs, key=bytes(range(32)), trace=True, observable=0, flags=0, **kw):
         import paper_2509_01742_amd as B
 
         okw = {}
@@ -34,9 +34,8 @@ class Twin:
                      ("pm_keys_per_row", "kpr"), ("pm_row_slots", "W")):
             if a in kw:
                 okw[b] = kw[a]
-        flags = B.BOLT_F_TRACE if trace else 0
         self.p = B.params(cap, vs, key=key, observable=observable, **kw)
-        self.p.flags |= flags
+        self.p.flags |= (B.BOLT_F_TRACE if trace else 0) | flags
         self.g = B.Map(self.p)
         self.o = O.OracleMap(cap, vs, key=key, trace=trace, **okw)
         self.vs = vs

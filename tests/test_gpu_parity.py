@@ -265,3 +265,44 @@ def test_access_capacity_errors():
     assert t.build(np.zeros(0, np.uint64), np.zeros((0, 8), np.uint8)) == (0, 0, 0)
     (rc_o, _, _), (rc_g, st, _, _) = t.access(np.ones(8, np.uint8), synth.keys(8, 4), np.zeros((8, 8), np.uint8))
     assert rc_o == O.EOVERFLOW and st == B.BOLT_EOVERFLOW
+
+
+@pytest.mark.parametrize("observable", [0, 1])
+def test_access_parity_through_captured_graphs(observable):
+    """BOLT_F_GRAPHS: every batch replays the graph of its size class.  Sizes
+    cross the one-round / several-round threshold and revisit classes, and an
+    eager map's batches run between the replays; every replay is checked."""
+    import paper_2509_01742_amd as B
+
+    t = Twin(1 << 15, 16, trace=False, observable=observable, flags=B.BOLT_F_GRAPHS)
+    e = Twin(1 << 12, 8, trace=False)  # eager work between the replays
+    k, v = workload(30000, 16, 77)
+    ke, ve = workload(3000, 8, 78)
+    assert t.build(k, v) == (0, 0, 0) and e.build(ke, ve) == (0, 0, 0)
+    rng = np.random.default_rng(99)
+    fresh = synth.keys(40000, 4243, offset=10**8)
+    present = set(int(x) for x in k)
+    pe = set(int(x) for x in ke)
+    sizes = [1, 1, 2, 3, 64, 65, 128, 129, 5, 4096, 8192, 100, 1, 2000, 4095, 7, 8192, 3]
+    for b, q in enumerate(sizes):
+        ops, keys, vals = _mixed_batch(rng, present, fresh, q, 16)
+        if len(present) > (1 << 15) - q:
+            ops[ops == 1] = 2
+        (rc_o, vo_o, st_o), (rc_g, st, vo_g, st_g) = t.access(ops, keys, vals)
+        assert rc_o == 0 and rc_g == 0 and st == 0, (b, q, rc_o, rc_g, st)
+        assert np.array_equal(st_g, st_o) and np.array_equal(vo_g, vo_o), (b, q)
+        for op, key in zip(ops.tolist(), keys.tolist()):
+            if op == 1:
+                present.add(int(key))
+            elif op == 2:
+                present.discard(int(key))
+        opse, kse, vse = _mixed_batch(rng, pe, fresh, 50, 8)
+        (rc_o, vo_o, st_o), (rc_g, st, vo_g, st_g) = e.access(opse, kse, vse)
+        assert rc_o == 0 and rc_g == 0 and np.array_equal(vo_g, vo_o)
+        for op, key in zip(opse.tolist(), kse.tolist()):
+            if op == 1:
+                pe.add(int(key))
+            elif op == 2:
+                pe.discard(int(key))
+    t.assert_same_state(trace=False)
+    e.assert_same_state(trace=False)
