@@ -417,35 +417,83 @@ __global__ __launch_bounds__(kDedupNT) void k_acc_group(GroupArgs a1, const Acce
       }
     }
   }
-  // this partition's commands, in index order (the order does not matter:
-  // they are sorted next)
-  uint32_t mine = 0;
+  // this partition's commands, gathered in index order (1024 indexes per
+  // chunk: a ballot per wave, the wave counts' prefix per chunk)
+  __shared__ uint32_t wcnt[kDedupNT / 64];
+  const uint32_t lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  uint32_t base = 0;
   bool bad = false;
-#pragma unroll
-  for (uint32_t u = 0; u < kMaxBatch / kDedupNT; ++u) {
-    const uint32_t i = threadIdx.x + u * kDedupNT;
+  for (uint32_t c0 = 0; c0 < qall; c0 += kDedupNT) {
+    const uint32_t i = c0 + threadIdx.x;
+    uint64_t key = 0;
+    uint32_t op = 0;
+    bool mine = false;
     if (i < qall) {
-      mine += part_of(keys[i]) == part;
-      bad |= ops[i] > 2;
+      key = keys[i];
+      op = ops[i];
+      bad |= op > 2;
+      mine = part_of(key) == part;
     }
-  }
-  if (__any(bad) && (threadIdx.x & 63) == 0) a.ctl->reject = a.epoch;  // same value from every writer
-  uint32_t at = block_excl<kDedupNT, false>(mine, &tot);
+    const uint64_t bal = __ballot(mine);
+    if (lane == 0) wcnt[wid] = (uint32_t)__popcll(bal);
+    __syncthreads();
+    uint32_t off = base, all = 0;
 #pragma unroll
-  for (uint32_t u = 0; u < kMaxBatch / kDedupNT; ++u) {
-    const uint32_t i = threadIdx.x + u * kDedupNT;
-    if (i < qall) {
-      const uint64_t key = keys[i];
-      if (part_of(key) == part) {
-        skey[at] = key;
-        sidx[at] = (i << 2) | (ops[i] & 3u);  // ordering by this payload is ordering by index
-        ++at;
+    for (uint32_t w = 0; w < kDedupNT / 64; ++w) {
+      const uint32_t c = wcnt[w];
+      off += w < wid ? c : 0;
+      all += c;
+    }
+    if (mine) {
+      const uint32_t at = off + (uint32_t)__popcll(bal & ((1ull << lane) - 1));
+      skey[at] = key;
+      sidx[at] = (i << 2) | (op & 3u);  // ordering by this payload is ordering by index
+    }
+    base += all;
+    __syncthreads();  // wcnt is rewritten by the next chunk
+  }
+  if (__any(bad) && lane == 0) a.ctl->reject = a.epoch;  // the same value from every writer
+  const uint32_t q = base;  // commands in this partition
+  if (q == 0) return;       // whole block
+  if (q <= kDedupNT) {
+    // One thread per command, in index order: every thread reads the
+    // partition's entries 0 .. q-1 in turn (the same LDS word across a wave,
+    // a broadcast), so the first entry of its key is its leader, the last
+    // PUT/DEL before it is its previous write, and for a leader the last
+    // PUT/DEL of the key in the whole batch is its last write.
+    const uint32_t j = threadIdx.x;
+    if ((j & ~63u) >= q) return;  // a wave with no command of the partition
+    const uint64_t key = j < q ? skey[j] : 0;
+    const uint32_t me = j < q ? sidx[j] >> 2 : 0;
+    uint32_t lead = kNone, pw = kNone, lw = kNone;
+    for (uint32_t e0 = 0; e0 < q; e0 += 8) {  // eight entries' loads in flight at once
+      uint64_t ke[8];
+      uint32_t pe[8];
+#pragma unroll
+      for (uint32_t t = 0; t < 8; ++t) {
+        ke[t] = skey[e0 + t];  // entries past q (stale LDS) are masked below
+        pe[t] = sidx[e0 + t];
+      }
+#pragma unroll
+      for (uint32_t t = 0; t < 8; ++t) {
+        const uint32_t e = e0 + t;
+        if (e < q && ke[t] == key) {
+          if (e <= j && lead == kNone) lead = pe[t] >> 2;
+          if (pe[t] & 3u) {
+            lw = pe[t] >> 2;
+            if (e < j) pw = lw;
+          }
+        }
       }
     }
+    if (j < q) {
+      leader[me] = lead;
+      prevw[me] = pw;
+      if (lead == me) lastw[me] = lw;
+    }
+    return;
   }
-  __syncthreads();
-  const uint32_t q = tot;  // commands in this partition
-  if (q == 0) return;      // whole block
+  // Larger partitions (hot keys): sort the (key, index) pairs.
   uint32_t npad = 1;
   while (npad < q) npad <<= 1;
   uint64_t k[kDedupPer];
