@@ -279,9 +279,13 @@ __device__ __forceinline__ void tile_high_steps(uint64_t (&v)[kRegE], uint64_t* 
 __device__ __forceinline__ void tile_sort_regs(uint64_t* __restrict__ a, uint64_t base, int mode, uint32_t k_log,
                                                uint64_t* lds) {
   const uint32_t t = threadIdx.x;
+  // one uniform tile pointer and 32-bit element offsets: each load and store
+  // needs one offset register, not a 64-bit address
+  char* __restrict__ tile = reinterpret_cast<char*>(a + base);
+  const uint32_t tb = t * 8u;  // byte offset of register 0
   uint64_t v[kRegE];
 #pragma unroll
-  for (int r = 0; r < kRegE; ++r) v[r] = a[base + (uint32_t)r * kRegNT + t];
+  for (int r = 0; r < kRegE; ++r) v[r] = *reinterpret_cast<const uint64_t*>(tile + (tb + (uint32_t)r * kRegNT * 8u));
   const uint64_t hi = base + (uint64_t)t * kRegE;
   if (mode == 0) {
     rows_to_cols(v, lds, t);
@@ -296,8 +300,12 @@ __device__ __forceinline__ void tile_sort_regs(uint64_t* __restrict__ a, uint64_
     col_stages<14, 8>(v, h, t);
   }
   cols_to_rows(v, lds, t);
+  // An empty register constraint on the offset: the store addresses are
+  // formed here, not kept live (and spilled) since the loads.
+  uint32_t tb2 = tb;
+  asm volatile("" : "+v"(tb2));
 #pragma unroll
-  for (int r = 0; r < kRegE; ++r) a[base + (uint32_t)r * kRegNT + t] = v[r];
+  for (int r = 0; r < kRegE; ++r) *reinterpret_cast<uint64_t*>(tile + (tb2 + (uint32_t)r * kRegNT * 8u)) = v[r];
 }
 
 // LDS stages on one tile of T = 2^logt <= 8192 elements, one stage per
