@@ -237,6 +237,9 @@ def main():
     ap.add_argument("--no-multi", action="store_true", help="skip the 64-map batched figures")
     ap.add_argument("--graphs", action="store_true", help="maps replay captured graphs per batch-size class")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default network schedules")
+    ap.add_argument("--dynamics", type=int, default=0, metavar="ACCESSES",
+                    help="instead of the benchmark: the bound validation of Sec. 4.3 over this many accesses per "
+                         "configuration (the paper uses 10^9)")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving figures")
     ap.add_argument("--serve-seconds", type=float, default=3.0, help="steady window of each open-loop serving run")
     ap.add_argument("--copy-calib", type=int, default=0,
@@ -253,6 +256,11 @@ def main():
     import synth
 
     torch.cuda.set_device(0)
+    if args.dynamics:
+        res = run_dynamics(B, torch, args.dynamics)
+        print(json.dumps({"metric": "bound validation (Sec. 4.3): largest bin load, HBM-bin items and stash over a "
+                                    "long uniform access stream", "dynamics": res}), flush=True)
+        return
     dev = torch.device("cuda:0")
     n = 1 << args.n_log2
     t0 = time.time()
@@ -562,6 +570,77 @@ def run_serving(B, seconds=3.0, rot_seconds=2.0, warm=1.0, pool=1 << 16, seed=0x
                             "rotation": rotation, "drain_s": round(lag, 3), "warmup_s": warm})
         log("serving at %.1fx: %s" % (frac, json.dumps(out["runs"][-1])))
     srv.close()
+    return out
+
+
+def run_dynamics(B, torch, accesses, log2n=20, batch=4096, seed=0xB0170000 + 61):
+    """The paper's validation of the bin, HBM and stash bounds (Sec. 4.3,
+    "Dimensions in practice"), on the GPU with the batched path: N = 2^log2n
+    keys, `accesses` uniform random GETs over them in batches of `batch`,
+    for c in {8, 16} and alpha in {0.01, 0.2, 0.5}, device observable store,
+    BOLT_F_WATCH tracking the largest bin load and the HBM-bin items at
+    every batch end.  The bounds are Claim 4.2 (l_max = Z), Claim 4.3
+    (K c + l_max sqrt(K ln N)) and Claim 4.4 ((1 + alpha) M / 2 +
+    l_max sqrt(M ln N)), O() constants 1.  The query stream cycles through
+    a pool of 2048 random batches drawn once per configuration."""
+    import math
+
+    import synth
+
+    n = 1 << log2n
+    dev = torch.device("cuda:0")
+    keys = synth.keys(n, seed)
+    vals = synth.values(n, 8, seed + 1)
+    dk = torch.from_numpy(keys.view(np.int64)).to(dev)
+    dv = torch.from_numpy(vals).to(dev)
+    g = torch.Generator(device=dev)
+    pool = 2048
+    out = {"workload": "N=2^%d keys, %d uniform random GETs in batches of %d, device observable store" % (
+        log2n, accesses, batch), "configs": []}
+    ops = torch.zeros(batch, dtype=torch.uint8, device=dev)
+    vin = torch.zeros((batch, 8), dtype=torch.uint8, device=dev)
+    vout = torch.zeros((batch, 8), dtype=torch.uint8, device=dev)
+    st = torch.zeros(batch, dtype=torch.uint8, device=dev)
+    nb = accesses // batch
+    for c in (8, 16):
+        for alpha_pm in (10, 200, 500):
+            g.manual_seed(seed + 1000 * c + alpha_pm)
+            qk = dk[torch.randint(0, n, (pool, batch), device=dev, generator=g)]
+            p = B.params(n, 8, c=c, alpha_permille=alpha_pm, observable=B.BOLT_OBS_DEVICE)
+            p.flags |= B.BOLT_F_WATCH
+            m = B.Map(p)
+            B.check(m.build(dk, dv), "bolt_build")
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for b in range(nb):
+                B.check(m.access(ops, qk[b % pool], vin, vout, st), "bolt_access_batch")
+                if b % 4096 == 4095:
+                    torch.cuda.synchronize()
+            torch.cuda.synchronize()
+            secs = time.perf_counter() - t0
+            B.check(m.status(), "status")
+            sz = m.sizes
+            s_ = m.stats()
+            K, M, Z = sz["K"], sz["M"], sz["Z"]
+            a = alpha_pm / 1000.0
+            b43 = K * c + Z * math.sqrt(K * math.log(n))
+            b44 = (1 + a) * M / 2 + Z * math.sqrt(M * math.log(n))
+            ent = {"c": c, "alpha": a, "accesses": nb * batch, "seconds": round(secs, 2),
+                   "ops_per_s": round(nb * batch / secs, 1), "K": K, "M": M,
+                   "bin_load": {"max": s_["load_highwater"], "bound": Z, "slack": Z - s_["load_highwater"],
+                                "rel_slack": round((Z - s_["load_highwater"]) / Z, 4)},
+                   "hbm_load": {"max": s_["hbm_load_highwater"], "bound": round(b43, 1),
+                                "slack": round(b43 - s_["hbm_load_highwater"], 1),
+                                "rel_slack": round((b43 - s_["hbm_load_highwater"]) / b43, 4)},
+                   "stash": {"max": s_["stash_highwater"], "bound": round(b44, 1),
+                             "slack": round(b44 - s_["stash_highwater"], 1),
+                             "rel_slack": round((b44 - s_["stash_highwater"]) / b44, 4),
+                             "max_fraction_of_N": round(s_["stash_highwater"] / n, 4)},
+                   "max_row": s_["max_row"], "row_slots": p.pm_row_slots}
+            out["configs"].append(ent)
+            log("dynamics c=%d alpha=%.2f: %s" % (c, a, json.dumps(ent)))
+            m.close()
+            del qk
     return out
 
 

@@ -72,6 +72,8 @@ enum { BOLT_OBS_HOST_PINNED = 0, BOLT_OBS_DEVICE = 1 };
 #define BOLT_F_TRACE 1u     /* record every observable access (tests; costs a little time) */
 #define BOLT_F_FIXED_KEY 2u /* use params.key as the PRF key instead of fresh OS randomness */
 #define BOLT_F_TIMING 4u    /* time every kernel class with HIP events on its stream (benchmarks) */
+#define BOLT_F_WATCH 16u    /* after every batch, record the largest bin load and the items held by the HBM bins,
+                               with their high-water marks (dynamics validation; one small kernel per batch) */
 #define BOLT_F_GRAPHS 8u    /* run one-map batches by replaying a HIP graph captured once per power-of-two batch
                                size (fewer host launch calls; results identical).  Not with TRACE or TIMING. */
 
@@ -203,6 +205,9 @@ typedef struct {
   uint64_t stash_highwater; /* largest stash_live seen at the end of a batch */
   uint32_t max_load;        /* largest bin load now */
   uint32_t max_row;         /* fullest position-map row now */
+  uint32_t load_highwater;  /* BOLT_F_WATCH: largest bin load seen at a batch end (else 0) */
+  uint64_t hbm_load;        /* BOLT_F_WATCH: items in the K HBM bins at the last batch end */
+  uint64_t hbm_load_highwater; /* BOLT_F_WATCH: largest hbm_load seen */
 } bolt_stats;
 int bolt_get_stats(bolt_map* m, bolt_stats* out);
 

@@ -20,7 +20,7 @@ BOLT_OK, BOLT_EINVAL, BOLT_ENOMEM, BOLT_EDUPKEY, BOLT_EOVERFLOW, BOLT_EFULL, BOL
 BOLT_OP_GET, BOLT_OP_PUT, BOLT_OP_DEL = 0, 1, 2
 BOLT_ST_ABSENT, BOLT_ST_FOUND, BOLT_ST_UPDATED, BOLT_ST_INSERTED, BOLT_ST_DELETED = 0, 1, 1, 2, 3
 BOLT_OBS_HOST_PINNED, BOLT_OBS_DEVICE = 0, 1
-BOLT_F_TRACE, BOLT_F_FIXED_KEY, BOLT_F_TIMING, BOLT_F_GRAPHS = 1, 2, 4, 8
+BOLT_F_TRACE, BOLT_F_FIXED_KEY, BOLT_F_TIMING, BOLT_F_GRAPHS, BOLT_F_WATCH = 1, 2, 4, 8, 16
 BOLT_MAX_BATCH = 8192
 BOLT_ETIMEOUT = -8
 BOLT_SRV_WAITING, BOLT_SRV_BUILDING, BOLT_SRV_RESIDENT, BOLT_SRV_CLOSED, BOLT_SRV_FAILED = 0, 1, 2, 3, 4
@@ -53,7 +53,8 @@ class bolt_sizes(C.Structure):
 
 class bolt_stats(C.Structure):
     _fields_ = [("live", C.c_uint64), ("steps", C.c_uint64), ("batches", C.c_uint64), ("stash_live", C.c_uint64),
-                ("stash_highwater", C.c_uint64), ("max_load", C.c_uint32), ("max_row", C.c_uint32)]
+                ("stash_highwater", C.c_uint64), ("max_load", C.c_uint32), ("max_row", C.c_uint32),
+                ("load_highwater", C.c_uint32), ("hbm_load", C.c_uint64), ("hbm_load_highwater", C.c_uint64)]
 
     def as_dict(self):
         return {n: int(getattr(self, n)) for n, _ in self._fields_}

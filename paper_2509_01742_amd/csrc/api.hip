@@ -462,6 +462,9 @@ int bolt_get_stats(bolt_map* m, bolt_stats* out) {
   uint32_t mr = 0;
   for (uint32_t v : mk) mr = std::max(mr, (uint32_t)__builtin_popcount(v));
   out->max_row = mr;
+  out->load_highwater = c.load_hw;
+  out->hbm_load = c.hbm_load;
+  out->hbm_load_highwater = c.hbm_hw;
   return BOLT_OK;
 }
 

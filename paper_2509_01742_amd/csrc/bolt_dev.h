@@ -32,7 +32,9 @@ struct Ctl {
   uint32_t b_place;      // items placed by the current batch
   uint32_t b_ins;        // keys inserted by the current batch
   uint32_t b_del;        // keys deleted by the current batch
-  uint32_t pad;
+  uint32_t load_hw;      // BOLT_F_WATCH: largest bin load seen at a batch end
+  uint64_t hbm_load;     // BOLT_F_WATCH: items in the HBM bins at the last batch end
+  uint64_t hbm_hw;       // BOLT_F_WATCH: largest hbm_load seen
 };
 
 // ---------------------------------------------------------------------------

@@ -1317,6 +1317,41 @@ static void plan_access(bolt_map* m, const uint8_t* ops, const uint64_t* keys, c
   m->batches++;
 }
 
+// BOLT_F_WATCH: the largest bin load and the items in the K HBM bins at the
+// end of a batch, with their high-water marks (one workgroup).
+__global__ __launch_bounds__(1024) void k_acc_watch(const uint32_t* __restrict__ load, uint64_t B, uint64_t K,
+                                                    Ctl* ctl) {
+  __shared__ uint32_t smax[16];
+  __shared__ uint64_t ssum[16];
+  uint32_t mx = 0;
+  uint64_t sum = 0;
+  for (uint64_t b = threadIdx.x; b < B; b += 1024) {
+    const uint32_t l = load[b];
+    mx = l > mx ? l : mx;
+    sum += b < K ? l : 0;
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const uint32_t om = __shfl_xor(mx, off, 64);
+    mx = om > mx ? om : mx;
+    sum += __shfl_xor(sum, off, 64);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    smax[threadIdx.x >> 6] = mx;
+    ssum[threadIdx.x >> 6] = sum;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < 16; ++w) {
+      mx = smax[w] > mx ? smax[w] : mx;
+      sum += ssum[w];
+    }
+    if (mx > ctl->load_hw) ctl->load_hw = mx;
+    ctl->hbm_load = sum;
+    if (sum > ctl->hbm_hw) ctl->hbm_hw = sum;
+  }
+}
+
 // The access pipeline for up to qmax commands of the maps of a device plan
 // table (count of them), every phase one launch.
 static void launch_many(const AccessPlan& p0, const AccessPlan* tab, uint32_t C, uint32_t qmax, uint64_t lds,
@@ -1363,7 +1398,12 @@ int run_access(bolt_map* m, const uint8_t* ops, const uint64_t* keys, const void
                uint8_t* status, uint32_t q, hipStream_t st) {
   AccessPlan P;
   plan_access(m, ops, keys, vals_in, vals_out, status, q, st, P);
-  if (m->p.flags & BOLT_F_GRAPHS) return run_access_graph(m, P, st);
+  if (m->p.flags & BOLT_F_GRAPHS) {
+    const int rc = run_access_graph(m, P, st);
+    if (rc == BOLT_OK && (m->p.flags & BOLT_F_WATCH))
+      hipLaunchKernelGGL(k_acc_watch, dim3(1), dim3(1024), 0, st, m->load, m->s.B, m->s.K, m->ctl);
+    return rc;
+  }
   const AccessPlan* none = nullptr;
   {
     TimedScope ts(m->timer, kkAccDedup, st);
@@ -1392,6 +1432,8 @@ int run_access(bolt_map* m, const uint8_t* ops, const uint64_t* keys, const void
     TimedScope ts(m->timer, kkAccMisc, st);
     hipLaunchKernelGGL(k_acc_finish<false>, dim3((q + 255) / 256), dim3(256), 0, st, P.fn, none);
   }
+  if (m->p.flags & BOLT_F_WATCH)
+    hipLaunchKernelGGL(k_acc_watch, dim3(1), dim3(1024), 0, st, m->load, m->s.B, m->s.K, m->ctl);
   return hipGetLastError() == hipSuccess ? BOLT_OK : BOLT_EHIP;
 }
 
@@ -1418,6 +1460,10 @@ int run_access_many(bolt_map* const* maps, const bolt_batch* batches, uint32_t c
     return BOLT_EHIP;
   }
   launch_many(plans[0], tab, count, qmax, lds, any_fast, any_slow, st);
+  for (uint32_t i = 0; i < count; ++i)
+    if (maps[i]->p.flags & BOLT_F_WATCH)
+      hipLaunchKernelGGL(k_acc_watch, dim3(1), dim3(1024), 0, st, maps[i]->load, maps[i]->s.B, maps[i]->s.K,
+                         maps[i]->ctl);
   (void)hipFreeAsync(tab, st);
   return hipGetLastError() == hipSuccess ? BOLT_OK : BOLT_EHIP;
 }

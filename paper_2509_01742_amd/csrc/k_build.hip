@@ -169,6 +169,9 @@ __global__ void k_ctl_init(Ctl* ctl) {
   ctl->b_place = 0;
   ctl->b_ins = 0;
   ctl->b_del = 0;
+  ctl->load_hw = 0;
+  ctl->hbm_load = 0;
+  ctl->hbm_hw = 0;
 }
 
 void launch_map_init(bolt_map* m, hipStream_t st) {

@@ -306,3 +306,39 @@ def test_access_parity_through_captured_graphs(observable):
                 pe.discard(int(key))
     t.assert_same_state(trace=False)
     e.assert_same_state(trace=False)
+
+
+def test_watch_marks_follow_every_batch():
+    """BOLT_F_WATCH: after each batch the map reports the largest bin load
+    and the items of its HBM bins, with high-water marks; checked against the
+    loads read back after every batch, with the state still the oracle's."""
+    import paper_2509_01742_amd as B
+
+    t = Twin(1 << 14, 8, trace=False, flags=B.BOLT_F_WATCH, alpha_permille=300)
+    k, v = workload(15000, 8, 91)
+    assert t.build(k, v) == (0, 0, 0)
+    K = t.g.sizes["K"]
+    rng = np.random.default_rng(5)
+    fresh = synth.keys(20000, 4244, offset=10**8)
+    present = set(int(x) for x in k)
+    hw_load = hw_hbm = 0
+    for b in range(12):
+        q = int(rng.integers(1, 3000))
+        ops, keys, vals = _mixed_batch(rng, present, fresh, q, 8)
+        if len(present) > (1 << 14) - q:
+            ops[ops == 1] = 2
+        (rc_o, vo_o, st_o), (rc_g, st, vo_g, st_g) = t.access(ops, keys, vals)
+        assert rc_o == 0 and rc_g == 0 and st == 0 and np.array_equal(vo_g, vo_o)
+        for op, key in zip(ops.tolist(), keys.tolist()):
+            if op == 1:
+                present.add(int(key))
+            elif op == 2:
+                present.discard(int(key))
+        ld = t.g.loads().astype(np.int64)
+        hw_load = max(hw_load, int(ld.max()))
+        hbm = int(ld[:K].sum())
+        hw_hbm = max(hw_hbm, hbm)
+        s = t.g.stats()
+        assert s["hbm_load"] == hbm and s["hbm_load_highwater"] == hw_hbm, b
+        assert s["load_highwater"] == hw_load and s["max_load"] == int(ld.max()), b
+    t.assert_same_state(trace=False)
