@@ -612,21 +612,26 @@ def run_dynamics(B, torch, accesses, log2n=20, batch=4096, seed=0xB0170000 + 61)
             B.check(m.build(dk, dv), "bolt_build")
             torch.cuda.synchronize()
             t0 = time.perf_counter()
+            overflow_at = None
+            done = 0
             for b in range(nb):
                 B.check(m.access(ops, qk[b % pool], vin, vout, st), "bolt_access_batch")
-                if b % 4096 == 4095:
-                    torch.cuda.synchronize()
+                done += 1
+                if b % 4096 == 4095 or b == nb - 1:
+                    rc = m.status()  # synchronises; a capacity error poisons the map
+                    if rc != 0:
+                        overflow_at = {"error": B._NAMES.get(rc, rc), "within_accesses": done * batch}
+                        break
             torch.cuda.synchronize()
             secs = time.perf_counter() - t0
-            B.check(m.status(), "status")
             sz = m.sizes
-            s_ = m.stats()
+            s_ = m.stats()  # a poisoned map still reports its counters and watch marks
             K, M, Z = sz["K"], sz["M"], sz["Z"]
             a = alpha_pm / 1000.0
             b43 = K * c + Z * math.sqrt(K * math.log(n))
             b44 = (1 + a) * M / 2 + Z * math.sqrt(M * math.log(n))
-            ent = {"c": c, "alpha": a, "accesses": nb * batch, "seconds": round(secs, 2),
-                   "ops_per_s": round(nb * batch / secs, 1), "K": K, "M": M,
+            ent = {"c": c, "alpha": a, "accesses": done * batch, "seconds": round(secs, 2),
+                   "ops_per_s": round(done * batch / secs, 1), "K": K, "M": M, "overflow": overflow_at,
                    "bin_load": {"max": s_["load_highwater"], "bound": Z, "slack": Z - s_["load_highwater"],
                                 "rel_slack": round((Z - s_["load_highwater"]) / Z, 4)},
                    "hbm_load": {"max": s_["hbm_load_highwater"], "bound": round(b43, 1),
