@@ -98,6 +98,10 @@ def _load():
     lib.or_pm_copy.restype = C.c_uint64
     lib.or_pm_max_row.argtypes = [P]
     lib.or_pm_max_row.restype = C.c_uint32
+    lib.or_chacha20_block.argtypes = [P, C.c_uint32, P, P]
+    lib.or_poly1305.argtypes = [P, P, C.c_uint64, P]
+    lib.or_aead_seal.argtypes = [P, P, P, C.c_uint64, P, C.c_uint64, P, P]
+    lib.or_aead_open.argtypes = [P, P, P, C.c_uint64, P, C.c_uint64, P, P]
     _lib = lib
     return lib
 
@@ -129,6 +133,39 @@ def prf(key: bytes, domain: int, x: int) -> tuple:
     kb = (C.c_uint8 * 32).from_buffer_copy(key)
     lib.or_prf(kb, domain, x, w)
     return tuple(int(v) for v in w)
+
+
+def _buf(b: bytes):
+    return (C.c_uint8 * max(1, len(b))).from_buffer_copy(b or b"\0")
+
+
+def chacha20_block(key: bytes, counter: int, nonce: bytes) -> bytes:
+    """One ChaCha20 block (RFC 8439, Sec. 2.3)."""
+    out = (C.c_uint8 * 64)()
+    _load().or_chacha20_block(_buf(key), counter, _buf(nonce), out)
+    return bytes(out)
+
+
+def poly1305(key: bytes, msg: bytes) -> bytes:
+    """Poly1305 tag of msg under a 32-byte one-time key (RFC 8439, Sec. 2.5)."""
+    tag = (C.c_uint8 * 16)()
+    _load().or_poly1305(_buf(key), _buf(msg), len(msg), tag)
+    return bytes(tag)
+
+
+def aead_seal(key: bytes, nonce: bytes, aad: bytes, pt: bytes) -> tuple:
+    """AEAD_CHACHA20_POLY1305 (RFC 8439, Sec. 2.8): (ciphertext, tag)."""
+    ct = (C.c_uint8 * max(1, len(pt)))()
+    tag = (C.c_uint8 * 16)()
+    _load().or_aead_seal(_buf(key), _buf(nonce), _buf(aad), len(aad), _buf(pt), len(pt), ct, tag)
+    return bytes(ct)[:len(pt)], bytes(tag)
+
+
+def aead_open(key: bytes, nonce: bytes, aad: bytes, ct: bytes, tag: bytes):
+    """The plain text, or None when the tag does not check."""
+    pt = (C.c_uint8 * max(1, len(ct)))()
+    rc = _load().or_aead_open(_buf(key), _buf(nonce), _buf(aad), len(aad), _buf(ct), len(ct), _buf(tag), pt)
+    return None if rc else bytes(pt)[:len(ct)]
 
 
 def pair(w0: int, w1: int, B: int) -> tuple:

@@ -184,6 +184,152 @@ void or_pair(uint64_t w0, uint64_t w1, uint64_t B, uint32_t* p1, uint32_t* p2) {
 }
 
 /* ------------------------------------------------------------------ */
+/* 1b. ChaCha20 and Poly1305 (RFC 8439): the authenticated encryption   */
+/*     that seals observable pages (the paper assumes pages encrypted   */
+/*     with authentication, Sec. 3 and Sec. 5.1 step 4).                */
+/* ------------------------------------------------------------------ */
+
+static uint32_t or_rotl32(uint32_t x, int n) { return (x << n) | (x >> (32 - n)); }
+
+/* The ChaCha quarter round on four words of the state (RFC 8439, 2.1). */
+static void or_quarter(uint32_t* s, int a, int b, int c, int d) {
+  s[a] += s[b]; s[d] ^= s[a]; s[d] = or_rotl32(s[d], 16);
+  s[c] += s[d]; s[b] ^= s[c]; s[b] = or_rotl32(s[b], 12);
+  s[a] += s[b]; s[d] ^= s[a]; s[d] = or_rotl32(s[d], 8);
+  s[c] += s[d]; s[b] ^= s[c]; s[b] = or_rotl32(s[b], 7);
+}
+
+/* One 64-byte ChaCha20 block: constants, key, block counter, nonce; ten
+ * double rounds (columns, then diagonals); the input added back (2.3). */
+void or_chacha20_block(const uint8_t key[32], uint32_t counter, const uint8_t nonce[12], uint8_t out[64]) {
+  uint32_t in[16], x[16];
+  in[0] = 0x61707865u; in[1] = 0x3320646eu; in[2] = 0x79622d32u; in[3] = 0x6b206574u; /* "expand 32-byte k" */
+  for (int i = 0; i < 8; ++i) in[4 + i] = or_le32(key + 4 * i);
+  in[12] = counter;
+  for (int i = 0; i < 3; ++i) in[13 + i] = or_le32(nonce + 4 * i);
+  memcpy(x, in, sizeof(x));
+  for (int r = 0; r < 10; ++r) {
+    or_quarter(x, 0, 4, 8, 12); or_quarter(x, 1, 5, 9, 13); or_quarter(x, 2, 6, 10, 14); or_quarter(x, 3, 7, 11, 15);
+    or_quarter(x, 0, 5, 10, 15); or_quarter(x, 1, 6, 11, 12); or_quarter(x, 2, 7, 8, 13); or_quarter(x, 3, 4, 9, 14);
+  }
+  for (int i = 0; i < 16; ++i) {
+    const uint32_t v = x[i] + in[i];
+    out[4 * i] = (uint8_t)v; out[4 * i + 1] = (uint8_t)(v >> 8);
+    out[4 * i + 2] = (uint8_t)(v >> 16); out[4 * i + 3] = (uint8_t)(v >> 24);
+  }
+}
+
+/* data XOR the key stream of blocks counter, counter + 1, ... (2.4). */
+static void or_chacha20_xor(const uint8_t key[32], uint32_t counter, const uint8_t nonce[12], const uint8_t* in,
+                            uint8_t* out, uint64_t len) {
+  uint8_t ks[64];
+  for (uint64_t off = 0; off < len; off += 64, ++counter) {
+    or_chacha20_block(key, counter, nonce, ks);
+    for (uint64_t j = 0; j < 64 && off + j < len; ++j) out[off + j] = in[off + j] ^ ks[j];
+  }
+}
+
+/* Poly1305 (2.5): h = (h + block + 2^(8 len)) * r mod 2^130 - 5 over the
+ * 16-byte blocks, then tag = (h + s) mod 2^128.  Numbers in five 26-bit
+ * limbs; products folded with 2^130 = 5 (mod p). */
+void or_poly1305(const uint8_t key[32], const uint8_t* msg, uint64_t len, uint8_t tag[16]) {
+  const uint32_t M26 = 0x3ffffff;
+  uint8_t rb[16];
+  memcpy(rb, key, 16);
+  rb[3] &= 15; rb[7] &= 15; rb[11] &= 15; rb[15] &= 15; /* clamp */
+  rb[4] &= 252; rb[8] &= 252; rb[12] &= 252;
+  uint64_t rlo = or_le64(rb), rhi = or_le64(rb + 8);
+  uint64_t r[5] = {rlo & M26, (rlo >> 26) & M26, ((rlo >> 52) | (rhi << 12)) & M26, (rhi >> 14) & M26, rhi >> 40};
+  uint64_t h[5] = {0, 0, 0, 0, 0};
+  for (uint64_t off = 0; off < len; off += 16) {
+    uint8_t blk[17] = {0};
+    const uint64_t n = len - off < 16 ? len - off : 16;
+    memcpy(blk, msg + off, n);
+    blk[n] = 1; /* the bit just above the block's bytes */
+    const uint64_t lo = or_le64(blk), mi = or_le64(blk + 8), top = blk[16];
+    h[0] += lo & M26;
+    h[1] += (lo >> 26) & M26;
+    h[2] += ((lo >> 52) | (mi << 12)) & M26;
+    h[3] += (mi >> 14) & M26;
+    h[4] += (mi >> 40) | (top << 24);
+    uint64_t d[9] = {0};
+    for (int i = 0; i < 5; ++i)
+      for (int j = 0; j < 5; ++j) d[i + j] += h[i] * r[j];
+    for (int k = 8; k >= 5; --k) d[k - 5] += 5 * d[k]; /* 2^130 = 5 mod p */
+    uint64_t c = 0;
+    for (int k = 0; k < 5; ++k) {
+      d[k] += c;
+      c = d[k] >> 26;
+      h[k] = d[k] & M26;
+    }
+    h[0] += 5 * c;
+    h[1] += h[0] >> 26;
+    h[0] &= M26;
+  }
+  /* carry until every limb is below 2^26 (h < 2^130), then h mod p:
+   * subtract p when h >= p, that is when h + 5 reaches 2^130 */
+  uint64_t c = 0;
+  for (int it = 0; it < 4; ++it) {
+    c = 0;
+    for (int k = 0; k < 5; ++k) {
+      h[k] += c;
+      c = h[k] >> 26;
+      h[k] &= M26;
+    }
+    h[0] += 5 * c;
+  }
+  uint64_t g[5];
+  c = 5;
+  for (int k = 0; k < 5; ++k) {
+    g[k] = h[k] + c;
+    c = g[k] >> 26;
+    g[k] &= M26;
+  }
+  if (c) memcpy(h, g, sizeof(h)); /* h + 5 reached 2^130: h >= p */
+  const uint64_t hlo = h[0] | (h[1] << 26) | (h[2] << 52);
+  const uint64_t hhi = (h[2] >> 12) | (h[3] << 14) | (h[4] << 40);
+  const uint64_t slo = or_le64(key + 16), shi = or_le64(key + 24);
+  const uint64_t tlo = hlo + slo;
+  const uint64_t thi = hhi + shi + (tlo < hlo);
+  or_put_le64(tag, tlo);
+  or_put_le64(tag + 8, thi);
+}
+
+/* AEAD_CHACHA20_POLY1305 (2.8): one-time Poly1305 key from block 0, text
+ * encrypted from block 1, tag over aad || pad || ct || pad || LE64 lengths. */
+static void or_aead_mac(const uint8_t key[32], const uint8_t nonce[12], const uint8_t* aad, uint64_t aad_len,
+                        const uint8_t* ct, uint64_t len, uint8_t tag[16]) {
+  uint8_t blk0[64];
+  or_chacha20_block(key, 0, nonce, blk0);
+  const uint64_t pa = (aad_len + 15) / 16 * 16, pc = (len + 15) / 16 * 16;
+  uint8_t* mac = calloc(pa + pc + 16, 1);
+  if (aad_len) memcpy(mac, aad, aad_len);
+  if (len) memcpy(mac + pa, ct, len);
+  or_put_le64(mac + pa + pc, aad_len);
+  or_put_le64(mac + pa + pc + 8, len);
+  or_poly1305(blk0, mac, pa + pc + 16, tag);
+  free(mac);
+}
+
+void or_aead_seal(const uint8_t key[32], const uint8_t nonce[12], const uint8_t* aad, uint64_t aad_len,
+                  const uint8_t* pt, uint64_t len, uint8_t* ct, uint8_t tag[16]) {
+  or_chacha20_xor(key, 1, nonce, pt, ct, len);
+  or_aead_mac(key, nonce, aad, aad_len, ct, len, tag);
+}
+
+/* 0 and the plain text when the tag checks, -1 (and nothing written) when not. */
+int or_aead_open(const uint8_t key[32], const uint8_t nonce[12], const uint8_t* aad, uint64_t aad_len,
+                 const uint8_t* ct, uint64_t len, const uint8_t tag[16], uint8_t* pt) {
+  uint8_t want[16];
+  or_aead_mac(key, nonce, aad, aad_len, ct, len, want);
+  uint8_t diff = 0;
+  for (int i = 0; i < 16; ++i) diff |= (uint8_t)(want[i] ^ tag[i]);
+  if (diff) return -1;
+  or_chacha20_xor(key, 1, nonce, ct, pt, len);
+  return 0;
+}
+
+/* ------------------------------------------------------------------ */
 /* 2. Parameters                                                        */
 /* ------------------------------------------------------------------ */
 
