@@ -28,6 +28,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 
 OK, EINVAL, ENOMEM, EDUPKEY, EOVERFLOW, EFULL, ESTATE, EBROKEN = 0, -1, -2, -3, -4, -5, -7, -99
+ETAMPER = -9
 GET, PUT, DEL = 0, 1, 2
 ST_ABSENT, ST_FOUND, ST_UPDATED, ST_INSERTED, ST_DELETED = 0, 1, 1, 2, 3
 NONE32 = 0xFFFFFFFF
@@ -99,6 +100,11 @@ def _load():
     lib.or_pm_max_row.argtypes = [P]
     lib.or_pm_max_row.restype = C.c_uint32
     lib.or_chacha20_block.argtypes = [P, C.c_uint32, P, P]
+    lib.or_set_seal.argtypes = [P]
+    for name in ("or_tags_ptr", "or_ver_ptr"):
+        getattr(lib, name).argtypes = [P]
+        getattr(lib, name).restype = C.c_void_p
+    lib.or_obs_raw.argtypes = [P, C.c_uint64, P, C.c_int]
     lib.or_poly1305.argtypes = [P, P, C.c_uint64, P]
     lib.or_aead_seal.argtypes = [P, P, P, C.c_uint64, P, C.c_uint64, P, P]
     lib.or_aead_open.argtypes = [P, P, P, C.c_uint64, P, C.c_uint64, P, P]
@@ -290,7 +296,7 @@ class PlainMap:
 
 class OracleMap:
     def __init__(self, cap, vs, c=8, alpha_pm=200, bin_slots=0, d=4, kpr=16, W=32, key=bytes(32),
-                 trace=False):
+                 trace=False, seal=False):
         lib = _load()
         kb = (C.c_uint8 * 32).from_buffer_copy(bytes(key))
         self._h = lib.or_create(cap, vs, c, alpha_pm, bin_slots, d, kpr, W, kb, 1 if trace else 0)
@@ -298,6 +304,33 @@ class OracleMap:
             raise ValueError("invalid parameters")
         self._lib = lib
         self.s = lib.or_get_sizes(self._h).contents.as_dict()
+        self.sealed = bool(seal)
+        if seal and lib.or_set_seal(self._h):
+            raise ValueError("sealing")
+
+    def tags(self) -> np.ndarray:
+        """(M, 16) Poly1305 tags of the sealed pages."""
+        M = self.s["M"]
+        p = self._lib.or_tags_ptr(self._h)
+        return np.ctypeslib.as_array(C.cast(p, C.POINTER(C.c_uint8)), shape=(M * 16,)).reshape(M, 16).copy()
+
+    def versions(self) -> np.ndarray:
+        M = self.s["M"]
+        p = self._lib.or_ver_ptr(self._h)
+        return np.ctypeslib.as_array(C.cast(p, C.POINTER(C.c_uint64)), shape=(M,)).copy()
+
+    def raw_page(self, page: int) -> bytes:
+        """An adversary's read of a sealed page and its tag."""
+        buf = (C.c_uint8 * (self.s["page_bytes"] + 16))()
+        if self._lib.or_obs_raw(self._h, page, buf, 0):
+            raise ValueError("raw page")
+        return bytes(buf)
+
+    def put_raw_page(self, page: int, data: bytes):
+        """An adversary's write of a page and tag (for example an old copy)."""
+        buf = (C.c_uint8 * len(data)).from_buffer_copy(data)
+        if self._lib.or_obs_raw(self._h, page, buf, 1):
+            raise ValueError("raw page")
 
     def close(self):
         if self._h:

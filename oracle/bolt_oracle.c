@@ -511,7 +511,8 @@ int or_compact(const uint8_t* keep, const uint32_t* payload, uint64_t m, uint32_
 /* ------------------------------------------------------------------ */
 
 enum { OR_OK = 0, OR_EINVAL = -1, OR_ENOMEM = -2, OR_EDUPKEY = -3, OR_EOVERFLOW = -4, OR_EFULL = -5,
-       OR_ESTATE = -7, OR_EBROKEN = -99 /* internal inconsistency: an oracle bug */ };
+       OR_ESTATE = -7, OR_ETAMPER = -9 /* a sealed page failed its check */,
+       OR_EBROKEN = -99 /* internal inconsistency: an oracle bug */ };
 enum { OR_GET = 0, OR_PUT = 1, OR_DEL = 2 };
 enum { OR_ST_ABSENT = 0, OR_ST_FOUND = 1, OR_ST_UPDATED = 1, OR_ST_INSERTED = 2, OR_ST_DELETED = 3 };
 
@@ -547,6 +548,11 @@ typedef struct {
   int trace_on;
   or_trace_rec* trace;
   uint64_t trace_n, trace_cap;
+  /* sealing of the observable pages (optional) */
+  int seal_on, tampered;
+  uint8_t seal_key[32]; /* PRF(domain 4, 0) as 32 bytes */
+  uint8_t* tags;        /* M * 16: the pages' Poly1305 tags, observable */
+  uint64_t* ver;        /* M: each page's write count, in trusted memory */
 } or_map;
 
 static void or_trace_add(or_map* m, uint32_t kind, uint64_t page) {
@@ -561,15 +567,73 @@ static void or_trace_add(or_map* m, uint32_t kind, uint64_t page) {
   m->trace_n++;
 }
 
-/* The only two functions that touch the observable store. */
+/* The nonce of a sealed page: LE32(page index) || LE64(its write count). */
+static void or_page_nonce(uint64_t page, uint64_t ver, uint8_t nonce[12]) {
+  nonce[0] = (uint8_t)page; nonce[1] = (uint8_t)(page >> 8);
+  nonce[2] = (uint8_t)(page >> 16); nonce[3] = (uint8_t)(page >> 24);
+  or_put_le64(nonce + 4, ver);
+}
+
+/* The only two functions that touch the observable store.  With sealing,
+ * a page is written as ChaCha20-Poly1305 of its bytes under the nonce of
+ * its next write count, and read back only if its tag checks under the
+ * count kept in trusted memory (so a changed, moved or replayed page is
+ * refused; the map then fails with OR_ETAMPER). */
 static void or_obs_read(or_map* m, uint64_t page, uint8_t* dst) {
   or_trace_add(m, 0, page);
-  memcpy(dst, m->obs + page * m->s.page_bytes, m->s.page_bytes);
+  const uint8_t* src = m->obs + page * m->s.page_bytes;
+  if (!m->seal_on) {
+    memcpy(dst, src, m->s.page_bytes);
+    return;
+  }
+  uint8_t nonce[12];
+  or_page_nonce(page, m->ver[page], nonce);
+  if (or_aead_open(m->seal_key, nonce, NULL, 0, src, m->s.page_bytes, m->tags + 16 * page, dst)) {
+    m->tampered = 1;
+    memset(dst, 0, m->s.page_bytes);
+  }
 }
 
 static void or_obs_write(or_map* m, uint64_t page, const uint8_t* src) {
   or_trace_add(m, 1, page);
-  memcpy(m->obs + page * m->s.page_bytes, src, m->s.page_bytes);
+  uint8_t* dst = m->obs + page * m->s.page_bytes;
+  if (!m->seal_on) {
+    memcpy(dst, src, m->s.page_bytes);
+    return;
+  }
+  uint8_t nonce[12];
+  or_page_nonce(page, ++m->ver[page], nonce);
+  or_aead_seal(m->seal_key, nonce, NULL, 0, src, m->s.page_bytes, dst, m->tags + 16 * page);
+}
+
+/* Turns sealing on (before the build): key = PRF(domain 4, 0). */
+int or_set_seal(or_map* m) {
+  if (m->built || m->seal_on) return OR_EINVAL;
+  uint64_t w[4];
+  or_prf(m->prf_key, 4, 0, w);
+  for (int j = 0; j < 4; ++j) or_put_le64(m->seal_key + 8 * j, w[j]);
+  m->tags = calloc(m->s.M ? m->s.M : 1, 16);
+  m->ver = calloc(m->s.M ? m->s.M : 1, sizeof(uint64_t));
+  m->seal_on = 1;
+  return OR_OK;
+}
+
+uint8_t* or_tags_ptr(or_map* m) { return m->tags; }
+uint64_t* or_ver_ptr(or_map* m) { return m->ver; }
+
+/* What an adversary holding the observable store can do: read or write a
+ * page with its tag (page_bytes + 16 bytes), or flip bits of one byte. */
+int or_obs_raw(or_map* m, uint64_t page, uint8_t* buf, int write) {
+  if (!m->seal_on || page >= m->s.M) return OR_EINVAL;
+  uint8_t* pg = m->obs + page * m->s.page_bytes;
+  if (write) {
+    memcpy(pg, buf, m->s.page_bytes);
+    memcpy(m->tags + 16 * page, buf + m->s.page_bytes, 16);
+  } else {
+    memcpy(buf, pg, m->s.page_bytes);
+    memcpy(buf + m->s.page_bytes, m->tags + 16 * page, 16);
+  }
+  return OR_OK;
 }
 
 or_map* or_create(uint64_t cap, uint32_t vs, uint32_t c, uint32_t alpha_pm, uint32_t bin_slots, uint32_t d,
@@ -598,6 +662,7 @@ void or_destroy(or_map* m) {
   free(m->obs); free(m->hbm); free(m->load); free(m->rows); free(m->rowcnt);
   free(m->st_key); free(m->st_val); free(m->st_dest); free(m->st_next); free(m->st_head);
   free(m->trace);
+  free(m->tags); free(m->ver);
   free(m);
 }
 
@@ -1114,6 +1179,10 @@ int or_access(or_map* m, const uint8_t* ops, const uint64_t* keys, const uint8_t
   free(r1); free(r2); free(fetched); free(page); free(ord); free(chosen);
   free(ins_key); free(ins_p1); free(ins_p2);
   m->ctr += q;
+  if (m->tampered) {
+    m->poisoned = 1;
+    return OR_ETAMPER;
+  }
   if (broken) {
     m->poisoned = 1;
     return OR_EBROKEN;

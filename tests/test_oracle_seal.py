@@ -9,6 +9,7 @@ import numpy as np
 import pytest
 
 import oracle as O
+from oracle import OK
 
 _name = ctypes.util.find_library("crypto")
 pytestmark = pytest.mark.skipif(_name is None, reason="no libcrypto to pin against")
@@ -108,3 +109,90 @@ def test_open_rejects_any_change():
     other = bytearray(nonce)
     other[4] ^= 1  # another version of the same page
     assert O.aead_open(key, bytes(other), b"", ct, tag) is None
+
+
+# ------------------------------------------------------------------ sealed map
+
+def _maps(cap=3000, n=2500, vs=16, seed=3):
+    import synth
+
+    k, v = synth.keys(n, seed), synth.values(n, vs, seed + 1)
+    plain = O.OracleMap(cap, vs, key=bytes(range(32)), trace=True)
+    sealed = O.OracleMap(cap, vs, key=bytes(range(32)), trace=True, seal=True)
+    assert plain.build(k, v) == 0 and sealed.build(k, v) == 0
+    return plain, sealed, k
+
+
+def _open_all(m):
+    """Every observable page of a sealed oracle map, opened with its key."""
+    key = b"".join(int(w).to_bytes(8, "little") for w in O.prf(bytes(range(32)), 4, 0))
+    obs, tags, ver = m.observable(), m.tags(), m.versions()
+    out = []
+    for p in range(obs.shape[0]):
+        nonce = int(p).to_bytes(4, "little") + int(ver[p]).to_bytes(8, "little")
+        pt = O.aead_open(key, nonce, b"", obs[p].tobytes(), tags[p].tobytes())
+        assert pt is not None, p
+        out.append(np.frombuffer(pt, dtype=np.uint8))
+    return np.stack(out)
+
+
+def test_sealed_map_is_the_plain_map_under_the_seal():
+    """Sealing changes the bytes in the store, not the procedure: the same
+    answers, the same trace, and every page opens to the unsealed map's page
+    with the version that counts its writes."""
+    plain, sealed, k = _maps()
+    rng = np.random.default_rng(4)
+    for b in range(12):
+        q = int(rng.integers(1, 400))
+        ops = rng.choice([0, 1, 2], size=q, p=[0.6, 0.3, 0.1]).astype(np.uint8)
+        keys = k[rng.integers(0, k.size, q)]
+        vals = rng.integers(0, 256, (q, 16), dtype=np.uint8)
+        ra, va, sa = plain.access(ops, keys, vals)
+        rb, vb, sb = sealed.access(ops, keys, vals)
+        assert ra == rb == 0 and np.array_equal(va, vb) and np.array_equal(sa, sb)
+    assert np.array_equal(plain.trace(), sealed.trace())
+    assert np.array_equal(_open_all(sealed), plain.observable())
+    assert not np.array_equal(sealed.observable(), plain.observable())
+    tr = sealed.trace()
+    writes = np.bincount(tr["page"][tr["kind"] == 1].astype(np.int64), minlength=sealed.s["M"])
+    assert np.array_equal(sealed.versions(), writes)  # one more per write, from the build's 1
+
+
+def _read_all(m, k):
+    """A batch that reads the pages of many keys."""
+    q = min(2000, k.size)
+    return m.access(np.zeros(q, np.uint8), k[:q], np.zeros((q, m.s["vs"]), np.uint8))[0]
+
+
+@pytest.mark.parametrize("where", ["page", "tag"])
+def test_sealed_map_refuses_a_changed_page(where):
+    _, sealed, k = _maps()
+    pb = sealed.s["page_bytes"]
+    raw = bytearray(sealed.raw_page(5))
+    raw[17 if where == "page" else pb + 3] ^= 0x40
+    sealed.put_raw_page(5, bytes(raw))
+    rc = OK
+    for _ in range(50):  # until some batch reads page 5
+        rc = _read_all(sealed, k)
+        if rc != OK:
+            break
+    assert rc == O.ETAMPER
+    assert _read_all(sealed, k) == O.ESTATE  # poisoned
+
+
+def test_sealed_map_refuses_a_replayed_page():
+    _, sealed, k = _maps()
+    old = [sealed.raw_page(p) for p in range(sealed.s["M"])]
+    v0 = sealed.versions()
+    rc = _read_all(sealed, k)  # rewrites every page it read
+    assert rc == OK
+    moved = np.nonzero(sealed.versions() != v0)[0]
+    assert moved.size > 0
+    p = int(moved[0])
+    sealed.put_raw_page(p, old[p])  # the page as it was one write ago: a valid old seal
+    rc = OK
+    for _ in range(50):
+        rc = _read_all(sealed, k)
+        if rc != OK:
+            break
+    assert rc == O.ETAMPER
