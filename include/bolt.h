@@ -48,7 +48,8 @@ enum {
   BOLT_EFULL = -5,     /* live keys would exceed the capacity (or the trace log is full) */
   BOLT_EHIP = -6,      /* a HIP runtime call failed */
   BOLT_ESTATE = -7,    /* the map is poisoned by an earlier device-side error */
-  BOLT_ETIMEOUT = -8   /* a server wait ended before the work did */
+  BOLT_ETIMEOUT = -8,  /* a server wait ended before the work did */
+  BOLT_ETAMPER = -9    /* BOLT_F_SEAL: an observable page or its tag was changed or replayed */
 };
 
 /* Operation codes of a command <opcode | key | payload> (Sec. 5.1 step 2).
@@ -74,6 +75,9 @@ enum { BOLT_OBS_HOST_PINNED = 0, BOLT_OBS_DEVICE = 1 };
 #define BOLT_F_TIMING 4u    /* time every kernel class with HIP events on its stream (benchmarks) */
 #define BOLT_F_WATCH 16u    /* after every batch, record the largest bin load and the items held by the HBM bins,
                                with their high-water marks (dynamics validation; one small kernel per batch) */
+#define BOLT_F_SEAL 32u     /* seal every observable page: ChaCha20-Poly1305 (RFC 8439) under the nonce
+                               LE32(page) || LE64(its write count, kept in HBM); a page read whose tag does
+                               not check poisons the map with BOLT_ETAMPER.  Pages up to 8 KiB. */
 #define BOLT_F_GRAPHS 8u    /* run one-map batches by replaying a HIP graph captured once per power-of-two batch
                                size (fewer host launch calls; results identical).  Not with TRACE or TIMING. */
 
@@ -185,6 +189,16 @@ typedef struct {
  * per-map launch cost that dominates small maps and small batches.  A map
  * may appear once per call.  Batches with q = 0 are skipped. */
 int bolt_access_many(bolt_map* const* maps, const bolt_batch* batches, uint32_t count, void* hip_stream);
+
+/* BOLT_F_SEAL maps: the tags (M x 16 bytes, observable, beside the pages)
+ * and the write count of every page (M x u64, in HBM). */
+int bolt_tags_snapshot(bolt_map* m, void* host_buf, uint64_t cap);
+int bolt_versions_snapshot(bolt_map* m, uint64_t* host_buf, uint64_t cap);
+
+/* BOLT_F_SEAL maps: what an adversary holding the observable store can do,
+ * for tests.  Reads (write = 0) or overwrites (write = 1) page `page` and its
+ * tag: host_buf holds page_bytes + 16 bytes.  Synchronises first. */
+int bolt_observable_raw(bolt_map* m, uint64_t page, void* host_buf, int write);
 
 /* Frees every resource of the map after waiting for its work.  NULL is a no-op. */
 int bolt_destroy(bolt_map* m);

@@ -20,13 +20,15 @@ BOLT_OK, BOLT_EINVAL, BOLT_ENOMEM, BOLT_EDUPKEY, BOLT_EOVERFLOW, BOLT_EFULL, BOL
 BOLT_OP_GET, BOLT_OP_PUT, BOLT_OP_DEL = 0, 1, 2
 BOLT_ST_ABSENT, BOLT_ST_FOUND, BOLT_ST_UPDATED, BOLT_ST_INSERTED, BOLT_ST_DELETED = 0, 1, 1, 2, 3
 BOLT_OBS_HOST_PINNED, BOLT_OBS_DEVICE = 0, 1
-BOLT_F_TRACE, BOLT_F_FIXED_KEY, BOLT_F_TIMING, BOLT_F_GRAPHS, BOLT_F_WATCH = 1, 2, 4, 8, 16
+BOLT_F_TRACE, BOLT_F_FIXED_KEY, BOLT_F_TIMING, BOLT_F_GRAPHS, BOLT_F_WATCH, BOLT_F_SEAL = 1, 2, 4, 8, 16, 32
 BOLT_MAX_BATCH = 8192
 BOLT_ETIMEOUT = -8
+BOLT_ETAMPER = -9
 BOLT_SRV_WAITING, BOLT_SRV_BUILDING, BOLT_SRV_RESIDENT, BOLT_SRV_CLOSED, BOLT_SRV_FAILED = 0, 1, 2, 3, 4
 
 _NAMES = {0: "BOLT_OK", -1: "BOLT_EINVAL", -2: "BOLT_ENOMEM", -3: "BOLT_EDUPKEY", -4: "BOLT_EOVERFLOW",
-          -5: "BOLT_EFULL", -6: "BOLT_EHIP", -7: "BOLT_ESTATE", -8: "BOLT_ETIMEOUT"}
+          -5: "BOLT_EFULL", -6: "BOLT_EHIP", -7: "BOLT_ESTATE", -8: "BOLT_ETIMEOUT",
+          -9: "BOLT_ETAMPER"}
 
 
 class BoltError(RuntimeError):
@@ -117,6 +119,9 @@ _SIGS = [
     ("bolt_trace_clear", _I, [_P]),
     ("bolt_observable_snapshot", _I, [_P, _P, _U64]),
     ("bolt_hbm_snapshot", _I, [_P, _P, _U64]),
+    ("bolt_tags_snapshot", _I, [_P, _P, _U64]),
+    ("bolt_versions_snapshot", _I, [_P, _P, _U64]),
+    ("bolt_observable_raw", _I, [_P, _U64, _P, _I]),
     ("bolt_loads_snapshot", _I, [_P, _P, _U64]),
     ("bolt_stash_snapshot", _I, [_P, _P, _P, _P, _U64, C.POINTER(_U64)]),
     ("bolt_pm_snapshot", _I, [_P, _P, _P, _P, _P, _U64, C.POINTER(_U64)]),
@@ -291,6 +296,31 @@ class Map:
         out = np.zeros((M, pb), dtype=np.uint8)
         check(bolt_observable_snapshot(self.h, out.ctypes.data_as(C.c_void_p), out.nbytes), "observable_snapshot")
         return out
+
+    def tags(self) -> np.ndarray:
+        """BOLT_F_SEAL: (M, 16) tags of the sealed observable pages."""
+        M = self.sizes["M"]
+        out = np.zeros((M, 16), dtype=np.uint8)
+        check(bolt_tags_snapshot(self.h, out.ctypes.data_as(C.c_void_p), out.size), "tags_snapshot")
+        return out
+
+    def versions(self) -> np.ndarray:
+        """BOLT_F_SEAL: each observable page's write count."""
+        M = self.sizes["M"]
+        out = np.zeros(M, dtype=np.uint64)
+        check(bolt_versions_snapshot(self.h, out.ctypes.data_as(C.c_void_p), M), "versions_snapshot")
+        return out
+
+    def raw_page(self, page: int) -> bytes:
+        """BOLT_F_SEAL: an adversary's read of a sealed page and its tag."""
+        buf = (C.c_uint8 * (self.sizes["page_bytes"] + 16))()
+        check(bolt_observable_raw(self.h, page, buf, 0), "observable_raw")
+        return bytes(buf)
+
+    def put_raw_page(self, page: int, data: bytes):
+        """BOLT_F_SEAL: an adversary's write of a page and its tag."""
+        buf = (C.c_uint8 * len(data)).from_buffer_copy(data)
+        check(bolt_observable_raw(self.h, page, buf, 1), "observable_raw")
 
     def hbm_bins(self) -> np.ndarray:
         K, pb = self.sizes["K"], self.sizes["page_bytes"]

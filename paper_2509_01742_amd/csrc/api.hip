@@ -19,6 +19,7 @@ namespace {
 
 constexpr uint32_t kMaxZ = 62;  // keys of a page must sit in its first 64 words
 constexpr uint64_t kMaxPageBytes = 32 * 1024;  // one page is staged in a write-back wave's LDS
+constexpr uint64_t kMaxSealedPage = 8 * 1024;  // four pages per fetch workgroup are opened in LDS
 
 int derive(const bolt_params* p, Sizes* s) {
   if (!p || p->capacity < 2 || p->value_bytes == 0 || p->value_bytes % 8 || p->value_bytes > 4096) return BOLT_EINVAL;
@@ -67,7 +68,8 @@ uint64_t scratch_bytes(const Sizes& s) {
 uint64_t device_bytes(const bolt_params* p, const Sizes& s) {
   uint64_t b = sizeof(Ctl);
   b += s.K * s.page_bytes;
-  if (p->observable == BOLT_OBS_DEVICE) b += s.M * s.page_bytes;
+  if (p->observable == BOLT_OBS_DEVICE) b += s.M * (s.page_bytes + ((p->flags & BOLT_F_SEAL) ? 16 : 0));
+  if (p->flags & BOLT_F_SEAL) b += s.M * 8;  // write counts
   b += s.B * 4;                      // load
   b += s.R * s.W * 16 + s.R * 4;     // position map
   b += s.P * (8 + s.vs + 4 + 4) + s.PW * 8;  // stash pool + bitmap
@@ -110,6 +112,7 @@ int map_check(bolt_map* m) {
 }
 
 int err_code(uint32_t bits) {
+  if (bits & kErrTamper) return BOLT_ETAMPER;
   if (bits & kErrBroken) return BOLT_EOVERFLOW;  // never expected: reported as a capacity failure
   if (bits & kErrOverflow) return BOLT_EOVERFLOW;
   if (bits & kErrDup) return BOLT_EDUPKEY;
@@ -176,7 +179,7 @@ int bolt_footprint(const bolt_params* p, uint64_t* hbm_bytes, uint64_t* obs_byte
   int rc = derive(p, &s);
   if (rc) return rc;
   if (hbm_bytes) *hbm_bytes = device_bytes(p, s);
-  if (obs_bytes) *obs_bytes = s.M * s.page_bytes;
+  if (obs_bytes) *obs_bytes = s.M * (s.page_bytes + ((p->flags & BOLT_F_SEAL) ? 16 : 0));
   return BOLT_OK;
 }
 
@@ -188,6 +191,7 @@ int bolt_create(const bolt_params* p, void* hip_stream, bolt_map** out) {
   if (rc) return rc;
   if ((p->flags & BOLT_F_TRACE) && p->trace_words == 0) return BOLT_EINVAL;
   if ((p->flags & BOLT_F_GRAPHS) && (p->flags & (BOLT_F_TRACE | BOLT_F_TIMING))) return BOLT_EINVAL;
+  if ((p->flags & BOLT_F_SEAL) && s.page_bytes > kMaxSealedPage) return BOLT_EINVAL;
   bolt_map* m = new (std::nothrow) bolt_map();
   if (!m) return BOLT_ENOMEM;
   m->p = *p;
@@ -251,8 +255,9 @@ int bolt_create(const bolt_params* p, void* hip_stream, bolt_map** out) {
     m->tlog_cap = p->trace_words;
     rc = dalloc(m, &m->tlog, m->tlog_cap * 4);
   }
+  if (!rc && (p->flags & BOLT_F_SEAL)) rc = dalloc(m, &m->pver, s.M * 8);
   if (!rc) {
-    const uint64_t ob = s.M * s.page_bytes;
+    const uint64_t ob = s.M * s.page_bytes + ((p->flags & BOLT_F_SEAL) ? s.M * 16 : 0);  // pages, then tags
     if (p->observable == BOLT_OBS_DEVICE) {
       rc = dalloc(m, &m->obs, ob);
     } else {
@@ -267,6 +272,7 @@ int bolt_create(const bolt_params* p, void* hip_stream, bolt_map** out) {
       }
     }
   }
+  if (!rc && (p->flags & BOLT_F_SEAL)) m->tags = m->obs + s.M * s.page_bytes;
   if (rc) {
     free_all(m);
     delete m;
@@ -525,6 +531,56 @@ int bolt_observable_snapshot(bolt_map* m, void* host_buf, uint64_t cap) {
     return BOLT_OK;
   }
   return hipMemcpy(host_buf, m->obs, bytes, hipMemcpyDeviceToHost) == hipSuccess ? BOLT_OK : BOLT_EHIP;
+}
+
+int bolt_tags_snapshot(bolt_map* m, void* host_buf, uint64_t cap) {
+  if (!m || !host_buf || !m->tags) return BOLT_EINVAL;
+  const uint64_t bytes = m->s.M * 16;
+  if (cap < bytes) return BOLT_EINVAL;
+  Ctl c;
+  int rc = sync_and_read(m, &c);
+  if (rc) return rc;
+  if (m->obs_host) {
+    memcpy(host_buf, m->obs_host + m->s.M * m->s.page_bytes, bytes);
+    return BOLT_OK;
+  }
+  return hipMemcpy(host_buf, m->tags, bytes, hipMemcpyDeviceToHost) == hipSuccess ? BOLT_OK : BOLT_EHIP;
+}
+
+int bolt_versions_snapshot(bolt_map* m, uint64_t* host_buf, uint64_t cap) {
+  if (!m || !host_buf || !m->pver || cap < m->s.M) return BOLT_EINVAL;
+  Ctl c;
+  int rc = sync_and_read(m, &c);
+  if (rc) return rc;
+  return hipMemcpy(host_buf, m->pver, m->s.M * 8, hipMemcpyDeviceToHost) == hipSuccess ? BOLT_OK : BOLT_EHIP;
+}
+
+int bolt_observable_raw(bolt_map* m, uint64_t page, void* host_buf, int write) {
+  if (!m || !host_buf || !m->tags || page >= m->s.M) return BOLT_EINVAL;
+  Ctl c;
+  int rc = sync_and_read(m, &c);
+  if (rc) return rc;
+  const uint64_t pb = m->s.page_bytes;
+  uint8_t* buf = static_cast<uint8_t*>(host_buf);
+  uint8_t* pg = m->obs + page * pb;
+  uint8_t* tg = m->tags + page * 16;
+  if (m->obs_host) {  // pinned memory: the host's own view
+    pg = m->obs_host + page * pb;
+    tg = m->obs_host + m->s.M * pb + page * 16;
+    if (write) {
+      memcpy(pg, buf, pb);
+      memcpy(tg, buf + pb, 16);
+    } else {
+      memcpy(buf, pg, pb);
+      memcpy(buf + pb, tg, 16);
+    }
+    return BOLT_OK;
+  }
+  const hipMemcpyKind k = write ? hipMemcpyHostToDevice : hipMemcpyDeviceToHost;
+  if (hipMemcpy(write ? (void*)pg : buf, write ? (const void*)buf : pg, pb, k) != hipSuccess) return BOLT_EHIP;
+  if (hipMemcpy(write ? (void*)tg : buf + pb, write ? (const void*)(buf + pb) : tg, 16, k) != hipSuccess)
+    return BOLT_EHIP;
+  return BOLT_OK;
 }
 
 int bolt_hbm_snapshot(bolt_map* m, void* host_buf, uint64_t cap) {

@@ -19,10 +19,12 @@ constexpr uint32_t kErrFull = 2u;      // live keys beyond capacity
 constexpr uint32_t kErrDup = 4u;       // duplicate build keys
 constexpr uint32_t kErrBroken = 8u;    // internal inconsistency (a library bug)
 constexpr uint32_t kErrTrace = 16u;    // trace log full (not sticky for the map)
+constexpr uint32_t kErrTamper = 32u;   // a sealed page failed its check
 
 // State that kernels of one map read and update on the device.
 struct Ctl {
   uint32_t hkey[8];      // BLAKE2s chaining value after the padded key block
+  uint32_t skey[8];      // page-sealing key: PRF(domain 4, 0) as eight LE words
   uint32_t err;          // sticky error bits
   uint32_t reject;       // current batch rejected (bad op code)
   uint64_t steps;        // tape counter s
@@ -146,6 +148,7 @@ __device__ __forceinline__ void pair_of(uint64_t w0, uint64_t w1, uint64_t B, ui
 constexpr uint32_t kDomPair = 1;  // a key's two bins at build time
 constexpr uint32_t kDomRows = 2;  // a key's position-map rows
 constexpr uint32_t kDomTape = 3;  // step s: fetch pair F(s) and remap pair R(s)
+constexpr uint32_t kDomSeal = 4;  // x = 0: the key that seals observable pages
 
 // ---------------------------------------------------------------------------
 // Small helpers.

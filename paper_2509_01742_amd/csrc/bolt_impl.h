@@ -130,6 +130,9 @@ struct bolt_map {
   // access pipeline captured per batch-size class ceil(log2 q) = 0..13.
   void* gplan;
   hipGraphExec_t gexec[14];
+  // BOLT_F_SEAL: tags beside the observable pages, write counts in HBM
+  uint8_t* tags;    // [M * 16], observable (device address)
+  uint64_t* pver;   // [M]
 };
 
 namespace bolt {

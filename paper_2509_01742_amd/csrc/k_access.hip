@@ -30,6 +30,7 @@
 #include <vector>
 
 #include "bolt_impl.h"
+#include "seal_dev.h"
 
 namespace bolt {
 
@@ -81,6 +82,8 @@ struct FetchArgs {
   uint2* rpair;
   uint32_t* tlog_r;  // [2q] or null
   Ctl* ctlw;
+  const uint64_t* tags;  // BOLT_F_SEAL: [M][2] page tags, else null
+  const uint64_t* pver;  // BOLT_F_SEAL: [M] page write counts
 };
 
 struct ResolveArgs {
@@ -182,6 +185,8 @@ struct WbArgs {
   uint64_t* st_used;
   uint32_t* freed;   // [kFreeBuckets] entries freed, summed by finish
   uint32_t* tlog_w;  // [3q] or null
+  uint64_t* tags;    // BOLT_F_SEAL: [M][2] page tags, else null
+  uint64_t* pver;    // BOLT_F_SEAL: [M] page write counts
 };
 
 struct FinishArgs {
@@ -209,7 +214,8 @@ struct AccessPlan {
   WbArgs wa;
   FinishArgs fn;
   uint32_t q, fast;
-  uint64_t wb_lds;
+  uint64_t wb_lds;     // dynamic LDS of the write-back
+  uint64_t fetch_lds;  // dynamic LDS of the fetch (sealed maps)
 };
 
 #define BOLT_PICK(T, field) const T& a = MULTI ? tab[blockIdx.y].field : a1
@@ -552,7 +558,7 @@ __global__ __launch_bounds__(kDedupNT) void k_acc_group(GroupArgs a1, const Acce
 
 
 
-template <bool MULTI>
+template <bool MULTI, bool SEALED>
 __global__ __launch_bounds__(256) void k_acc_fetch(FetchArgs a1, const AccessPlan* tab) {
   BOLT_PICK(FetchArgs, fa);
   const uint32_t lane = threadIdx.x & 63;
@@ -602,6 +608,29 @@ __global__ __launch_bounds__(256) void k_acc_fetch(FetchArgs a1, const AccessPla
     }
     const uint64_t* src = host ? a.obs + (uint64_t)(b - a.K) * a.pw : a.hbm + (uint64_t)b * a.pw;
     uint64_t* stg = a.stage + (uint64_t)slot * a.pw;
+    if (SEALED && a.tags && host) {
+      // Sealed page: copy it into this wave's LDS, check its tag under the
+      // write count kept in HBM, and decrypt it there; the rest reads the
+      // plain page from LDS.
+      extern __shared__ uint64_t fdyn[];
+      uint64_t* pg = fdyn + (uint64_t)(threadIdx.x >> 6) * a.pw;
+      for (uint64_t w = lane; w < a.pw; w += 64) pg[w] = src[w];
+      wave_sync();
+      const uint32_t page = b - (uint32_t)a.K;
+      const uint64_t ver = a.pver[page];
+      uint32_t key[8], otk[8], tag[4];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) key[j] = a.ctl->skey[j];
+      poly_key(key, page, (uint32_t)ver, (uint32_t)(ver >> 32), otk);
+      poly_page_tag(pg, (uint32_t)a.pw, otk, tag);
+      const bool ok = a.tags[2 * (uint64_t)page] == ((uint64_t)tag[0] | ((uint64_t)tag[1] << 32)) &&
+                      a.tags[2 * (uint64_t)page + 1] == ((uint64_t)tag[2] | ((uint64_t)tag[3] << 32));
+      if (!ok && lane == 0) set_err(a.ctlw, kErrTamper);
+      wave_sync();
+      chacha_page_xor(pg, (uint32_t)a.pw, key, page, (uint32_t)ver, (uint32_t)(ver >> 32));
+      wave_sync();
+      src = pg;
+    }
     const uint64_t v0 = lane < a.pw ? src[lane] : 0;
     if (host && lane < a.pw) stg[lane] = v0;
     // find the key among the page's slots (lanes 1..Z hold the keys)
@@ -1025,6 +1054,9 @@ __global__ __launch_bounds__(64) void k_acc_writeback(WbArgs a1, const AccessPla
   }
   __syncthreads();
   uint64_t* dst = host ? a.obs + (uint64_t)(b - a.K) * a.pw : a.hbm + (uint64_t)b * a.pw;
+  // sealed map, observable page: compose it in LDS after the item lists
+  const bool seal = a.tags && host;
+  uint64_t* out = seal ? reinterpret_cast<uint64_t*>(reinterpret_cast<char*>(dyn) + wb_lds_bytes(a.pw)) : dst;
   for (uint64_t w = lane; w < a.pw; w += 64) {
     uint64_t v = 0;
     if (w == 0) {
@@ -1041,7 +1073,25 @@ __global__ __launch_bounds__(64) void k_acc_writeback(WbArgs a1, const AccessPla
                                  : old[1 + a.Z + (uint64_t)from * a.vw + o];
       }
     }
-    dst[w] = v;
+    out[w] = v;
+  }
+  if (seal) {  // encrypt in LDS under the page's next write count, tag, write
+    const uint32_t page = b - (uint32_t)a.K;
+    const uint64_t ver = a.pver[page] + 1;
+    uint32_t key[8], otk[8], tag[4];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) key[j] = a.ctl->skey[j];
+    __syncthreads();
+    chacha_page_xor(out, (uint32_t)a.pw, key, page, (uint32_t)ver, (uint32_t)(ver >> 32));
+    __syncthreads();
+    poly_key(key, page, (uint32_t)ver, (uint32_t)(ver >> 32), otk);
+    poly_page_tag(out, (uint32_t)a.pw, otk, tag);
+    for (uint64_t w = lane; w < a.pw; w += 64) dst[w] = out[w];
+    if (lane == 0) {
+      a.tags[2 * (uint64_t)page] = (uint64_t)tag[0] | ((uint64_t)tag[1] << 32);
+      a.tags[2 * (uint64_t)page + 1] = (uint64_t)tag[2] | ((uint64_t)tag[3] << 32);
+      a.pver[page] = ver;
+    }
   }
   // free every listed entry (its value was read above)
   for (uint32_t l = lane; l < cnt; l += 64) {
@@ -1133,7 +1183,8 @@ static void plan_access(bolt_map* m, const uint8_t* ops, const uint64_t* keys, c
   memset(&P, 0, sizeof(P));
   P.q = q;
   P.fast = fast ? 1 : 0;
-  P.wb_lds = wb_lds_bytes(s.page_bytes / 8);
+  P.wb_lds = wb_lds_bytes(s.page_bytes / 8) + (m->tags ? s.page_bytes : 0);
+  P.fetch_lds = m->tags ? 4 * s.page_bytes : 0;
   const uint32_t vw = s.vs / 8;
   const uint64_t* vin = reinterpret_cast<const uint64_t*>(vals_in);
   const uint64_t* fval = reinterpret_cast<const uint64_t*>(bs.fval);
@@ -1180,6 +1231,8 @@ static void plan_access(bolt_map* m, const uint8_t* ops, const uint64_t* keys, c
   fa.rpair = bs.rpair;
   fa.tlog_r = tlog_r;
   fa.ctlw = m->ctl;
+  fa.tags = reinterpret_cast<const uint64_t*>(m->tags);
+  fa.pver = m->pver;
 
   ResolveArgs& rv = P.rv;
   rv.ctl = m->ctl;
@@ -1299,6 +1352,8 @@ static void plan_access(bolt_map* m, const uint8_t* ops, const uint64_t* keys, c
   wa.st_used = m->st_used;
   wa.freed = bs.freed;
   wa.tlog_w = tlog_w;
+  wa.tags = reinterpret_cast<uint64_t*>(m->tags);
+  wa.pver = m->pver;
 
   FinishArgs& fn = P.fn;
   fn.ctl = m->ctl;
@@ -1355,9 +1410,12 @@ __global__ __launch_bounds__(1024) void k_acc_watch(const uint32_t* __restrict__
 // The access pipeline for up to qmax commands of the maps of a device plan
 // table (count of them), every phase one launch.
 static void launch_many(const AccessPlan& p0, const AccessPlan* tab, uint32_t C, uint32_t qmax, uint64_t lds,
-                        bool any_fast, bool any_slow, hipStream_t st) {
+                        uint64_t fetch_lds, bool any_fast, bool any_slow, hipStream_t st) {
   hipLaunchKernelGGL(k_acc_group<true>, dim3(kParts, C), dim3(kDedupNT), 0, st, p0.gr, tab);
-  hipLaunchKernelGGL(k_acc_fetch<true>, dim3((qmax + 3) / 4, C), dim3(256), 0, st, p0.fa, tab);
+  if (fetch_lds)  // a sealed map among them
+    hipLaunchKernelGGL((k_acc_fetch<true, true>), dim3((qmax + 3) / 4, C), dim3(256), fetch_lds, st, p0.fa, tab);
+  else
+    hipLaunchKernelGGL((k_acc_fetch<true, false>), dim3((qmax + 3) / 4, C), dim3(256), 0, st, p0.fa, tab);
   hipLaunchKernelGGL(k_acc_resolve<true>, dim3((qmax + 255) / 256, C), dim3(256), 0, st, p0.rv, tab);
   if (any_fast) hipLaunchKernelGGL(k_acc_place<true>, dim3((qmax + 255) / 256, C), dim3(256), 0, st, p0.pa, tab);
   if (any_slow) hipLaunchKernelGGL(k_acc_remap<true>, dim3(1, C), dim3(kRemapNT), 0, st, p0.ra, tab);
@@ -1381,7 +1439,7 @@ static int run_access_graph(bolt_map* m, AccessPlan& P, hipStream_t st) {
     hipStream_t cs = m->side;
     hipGraph_t g = nullptr;
     if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) return BOLT_EHIP;
-    launch_many(P, tab, 1, 1u << cls, P.wb_lds, true, true, cs);
+    launch_many(P, tab, 1, 1u << cls, P.wb_lds, P.fetch_lds, true, true, cs);
     if (hipStreamEndCapture(cs, &g) != hipSuccess || !g) return BOLT_EHIP;
     hipGraphExec_t ex = nullptr;
     const hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
@@ -1411,7 +1469,10 @@ int run_access(bolt_map* m, const uint8_t* ops, const uint64_t* keys, const void
   }
   {
     TimedScope ts(m->timer, kkAccFetch, st);
-    hipLaunchKernelGGL(k_acc_fetch<false>, dim3((q + 3) / 4), dim3(256), 0, st, P.fa, none);
+    if (P.fetch_lds)
+      hipLaunchKernelGGL((k_acc_fetch<false, true>), dim3((q + 3) / 4), dim3(256), P.fetch_lds, st, P.fa, none);
+    else
+      hipLaunchKernelGGL((k_acc_fetch<false, false>), dim3((q + 3) / 4), dim3(256), 0, st, P.fa, none);
   }
   {
     TimedScope ts(m->timer, kkAccResolve, st);
@@ -1442,13 +1503,14 @@ int run_access(bolt_map* m, const uint8_t* ops, const uint64_t* keys, const void
 int run_access_many(bolt_map* const* maps, const bolt_batch* batches, uint32_t count, hipStream_t st) {
   std::vector<AccessPlan> plans(count);
   uint32_t qmax = 0;
-  uint64_t lds = 0;
+  uint64_t lds = 0, flds = 0;
   bool any_fast = false, any_slow = false;
   for (uint32_t i = 0; i < count; ++i) {
     const bolt_batch& b = batches[i];
     plan_access(maps[i], b.d_ops, b.d_keys, b.d_vals_in, b.d_vals_out, b.d_status, b.q, st, plans[i]);
     qmax = b.q > qmax ? b.q : qmax;
     lds = plans[i].wb_lds > lds ? plans[i].wb_lds : lds;
+    flds = plans[i].fetch_lds > flds ? plans[i].fetch_lds : flds;
     any_fast |= plans[i].fast != 0;
     any_slow |= plans[i].fast == 0;
   }
@@ -1459,7 +1521,7 @@ int run_access_many(bolt_map* const* maps, const bolt_batch* batches, uint32_t c
     (void)hipFreeAsync(tab, st);
     return BOLT_EHIP;
   }
-  launch_many(plans[0], tab, count, qmax, lds, any_fast, any_slow, st);
+  launch_many(plans[0], tab, count, qmax, lds, flds, any_fast, any_slow, st);
   for (uint32_t i = 0; i < count; ++i)
     if (maps[i]->p.flags & BOLT_F_WATCH)
       hipLaunchKernelGGL(k_acc_watch, dim3(1), dim3(1024), 0, st, maps[i]->load, maps[i]->s.B, maps[i]->s.K,

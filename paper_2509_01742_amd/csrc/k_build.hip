@@ -19,6 +19,7 @@
 #include <vector>
 
 #include "bolt_impl.h"
+#include "seal_dev.h"
 
 namespace bolt {
 
@@ -74,6 +75,8 @@ struct BuildPlan {
   uint64_t* hbm;
   uint64_t* obs;
   uint32_t* tlog;  // write-out trace (M words) or null
+  uint64_t* tags;  // BOLT_F_SEAL: [M][2] page tags (observable), else null
+  uint64_t* pver;  // BOLT_F_SEAL: [M] page write counts
   uint32_t* load;
   uint64_t* pm_key;
   uint2* pm_pair;
@@ -339,10 +342,9 @@ __global__ __launch_bounds__(256) void k_writeout(BOLT_PLAN_ARGS, uint32_t flip)
     key_rank[wid][rank] = key;
   }
   __syncthreads();
-  if (!active) return;
   const uint64_t pw = P.pw;
-  uint64_t* dst = b < P.K ? P.hbm + b * pw : P.obs + (b - P.K) * pw;
-  for (uint64_t w = lane; w < pw; w += 64) {
+  // word w of the bin's canonical page
+  auto word = [&](uint64_t w) -> uint64_t {
     uint64_t v = 0;
     if (w == 0) {
       v = cnt >= 64 ? kNone64 : ((1ull << cnt) - 1);
@@ -354,9 +356,44 @@ __global__ __launch_bounds__(256) void k_writeout(BOLT_PLAN_ARGS, uint32_t flip)
       uint32_t j = (uint32_t)(off / vw), o = (uint32_t)(off % vw);
       v = j < cnt ? P.vals[(uint64_t)by_rank[wid][j] * vw + o] : 0;
     }
-    dst[w] = v;
+    return v;
+  };
+  uint64_t* dst = b < P.K ? P.hbm + b * pw : P.obs + (b - P.K) * pw;
+  if (!P.tags) {  // unsealed map (the same for the whole block)
+    if (!active) return;
+    for (uint64_t w = lane; w < pw; w += 64) dst[w] = word(w);
+    if (P.tlog && b >= P.K && lane == 0) P.tlog[b - P.K] = (uint32_t)(b - P.K);
+    return;
   }
-  if (P.tlog && b >= P.K && lane == 0) P.tlog[b - P.K] = (uint32_t)(b - P.K);
+  // Sealed map: an observable page is composed in LDS, encrypted there,
+  // tagged, and written once (write count 1).  HBM bins stay plain.
+  extern __shared__ uint64_t wdyn[];
+  uint64_t* pg = wdyn + (uint64_t)wid * pw;
+  const bool seal = active && b >= P.K;  // the same for the whole wave
+  if (active) {
+    if (seal)
+      for (uint64_t w = lane; w < pw; w += 64) pg[w] = word(w);
+    else
+      for (uint64_t w = lane; w < pw; w += 64) dst[w] = word(w);
+  }
+  __syncthreads();
+  uint32_t skey[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) skey[j] = P.ctl->skey[j];
+  const uint32_t page = (uint32_t)(b - P.K);
+  if (seal) chacha_page_xor(pg, (uint32_t)pw, skey, page, 1u, 0u);
+  __syncthreads();
+  if (!seal) return;
+  uint32_t otk[8], tag[4];
+  poly_key(skey, page, 1u, 0u, otk);
+  poly_page_tag(pg, (uint32_t)pw, otk, tag);
+  for (uint64_t w = lane; w < pw; w += 64) dst[w] = pg[w];
+  if (lane == 0) {
+    P.tags[2 * (uint64_t)page] = (uint64_t)tag[0] | ((uint64_t)tag[1] << 32);
+    P.tags[2 * (uint64_t)page + 1] = (uint64_t)tag[2] | ((uint64_t)tag[3] << 32);
+    P.pver[page] = 1;
+    if (P.tlog) P.tlog[page] = page;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -504,6 +541,8 @@ static void plan_build(bolt_map* m, const uint64_t* keys, const void* vals, uint
   P.nbs = (uint32_t)((s.B + kScanChunk - 1) / kScanChunk);
   P.hbm = reinterpret_cast<uint64_t*>(m->hbm);
   P.obs = reinterpret_cast<uint64_t*>(m->obs);
+  P.tags = reinterpret_cast<uint64_t*>(m->tags);
+  P.pver = m->pver;
   P.load = m->load;
   P.pm_key = m->pm_key;
   P.pm_pair = m->pm_pair;
@@ -626,8 +665,11 @@ static void build_launches(const std::vector<BuildPlan>& plans, const BuildPlan*
     flip = launch_expand_inplace(p1.elem, p1.tmp, p1.BZ, st, tm) != p1.elem ? 1 : 0;
   // a6
   {
+    uint64_t lds = 0;  // sealed maps: four pages per workgroup in LDS
+    for (const BuildPlan& P : plans)
+      if (P.tags) lds = std::max(lds, 4 * P.pw * 8);
     TimedScope ts(tm, kkWriteout, st);
-    BL(k_writeout, blocks_for(B, 4), 256, flip);
+    hipLaunchKernelGGL(k_writeout<MULTI>, dim3(blocks_for(B, 4), C), dim3(256), lds, st, p1, tab, flip);
   }
   // duplicate keys (the tag buffer is free after the write-out)
   if (n) {

@@ -71,6 +71,14 @@ __global__ void k_prf_key_setup(Ctl* ctl, uint4 k0, uint4 k1) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   uint32_t kw[8] = {k0.x, k0.y, k0.z, k0.w, k1.x, k1.y, k1.z, k1.w};
   b2s_key_block(kw, ctl->hkey);
+  uint32_t hk[8];
+  for (int j = 0; j < 8; ++j) hk[j] = ctl->hkey[j];
+  uint64_t w[4];
+  prf4(hk, kDomSeal, 0, w);
+  for (int j = 0; j < 4; ++j) {
+    ctl->skey[2 * j] = (uint32_t)w[j];
+    ctl->skey[2 * j + 1] = (uint32_t)(w[j] >> 32);
+  }
 }
 
 __global__ void k_prf_array(const Ctl* ctl, uint32_t domain, const uint64_t* __restrict__ x, uint64_t n,

@@ -26,7 +26,7 @@ def host_u64(t):
 class Twin:
     """A GPU map and an oracle map with the same parameters and key."""
 
-    def __init__(self, cap, vs, key=bytes(range(32)), trace=True, observable=0, flags=0, **kw):
+    def __init__(self, cap, vs, key=bytes(range(32)), trace=True, observable=0, flags=0, seal=False, **kw):
         import paper_2509_01742_amd as B
 
         okw = {}
@@ -35,9 +35,10 @@ class Twin:
             if a in kw:
                 okw[b] = kw[a]
         self.p = B.params(cap, vs, key=key, observable=observable, **kw)
-        self.p.flags |= (B.BOLT_F_TRACE if trace else 0) | flags
+        self.p.flags |= (B.BOLT_F_TRACE if trace else 0) | flags | (B.BOLT_F_SEAL if seal else 0)
         self.g = B.Map(self.p)
-        self.o = O.OracleMap(cap, vs, key=key, trace=trace, **okw)
+        self.o = O.OracleMap(cap, vs, key=key, trace=trace, seal=seal, **okw)
+        self.seal = seal
         self.vs = vs
         self.B = B
 
@@ -64,6 +65,9 @@ class Twin:
     def assert_same_state(self, trace=True):
         g, o = self.g, self.o
         assert np.array_equal(g.observable(), o.observable()), "observable pages differ"
+        if self.seal:
+            assert np.array_equal(g.tags(), o.tags()), "page tags differ"
+            assert np.array_equal(g.versions(), o.versions()), "page write counts differ"
         assert np.array_equal(g.hbm_bins(), o.hbm_bins()), "HBM bins differ"
         assert np.array_equal(g.loads(), o.loads()), "bin loads differ"
         assert g.stash() == o.stash(), "stash differs"
