@@ -67,13 +67,15 @@ def kernel_bytes(cls, sz, n, npad, n_ops, host_roles):
     return None, None
 
 
-def run_mode(args, wl, dev_t, B, torch, observable):
+def run_mode(args, wl, dev_t, B, torch, observable, seal=False):
     n, vs = wl.n, wl.vs
     d_keys, d_vals, d_ops, d_qk, d_qv, d_out, d_st, bounds = dev_t
     obs = B.BOLT_OBS_HOST_PINNED if observable == "host" else B.BOLT_OBS_DEVICE
     p = B.params(wl.cap, vs, observable=obs)
     if args.graphs:
         p.flags |= B.BOLT_F_GRAPHS
+    if seal:
+        p.flags |= B.BOLT_F_SEAL
     sz = B.sizes_of(p)
     sz["vs"] = vs
     sz["host"] = observable == "host"
@@ -82,7 +84,7 @@ def run_mode(args, wl, dev_t, B, torch, observable):
     t0 = time.time()
     maps = [B.Map(p) for _ in range(nsteps)]
     pt = B.params(wl.cap, vs, observable=obs)
-    pt.flags |= B.BOLT_F_TIMING
+    pt.flags |= B.BOLT_F_TIMING | (B.BOLT_F_SEAL if seal else 0)
     tmap = B.Map(pt)
     torch.cuda.synchronize()
     log("[%s] created %d maps (%.1fs); footprint hbm=%.2f GiB obs=%.2f GiB" % (
@@ -237,6 +239,7 @@ def main():
     ap.add_argument("--no-multi", action="store_true", help="skip the 64-map batched figures")
     ap.add_argument("--graphs", action="store_true", help="maps replay captured graphs per batch-size class")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default network schedules")
+    ap.add_argument("--no-seal", action="store_true", help="skip the sealed-store figures")
     ap.add_argument("--dynamics", type=int, default=0, metavar="ACCESSES",
                     help="instead of the benchmark: the bound validation of Sec. 4.3 over this many accesses per "
                          "configuration (the paper uses 10^9)")
@@ -307,6 +310,17 @@ def main():
     roofline = roofline_of(main_res, dominant, args.observable)
     roofline_sort = roofline_of(main_res, "sort_global", args.observable)
 
+    sealed = None
+    if not args.no_seal:  # the same workload with every observable page sealed (ChaCha20-Poly1305)
+        sres = run_mode(args, wl, dev_t, B, torch, args.observable, seal=True)
+        sealed = {"observable": args.observable, "ops_per_s": round(sres["ops_per_s"], 1),
+                  "build_keys_per_s": round(sres["build_keys_per_s"], 1),
+                  "batch_latency_ms": {"p50": round(sres["lat_p50"], 4), "p99": round(sres["lat_p99"], 4)},
+                  "relative_to_plain": {"ops": round(sres["ops_per_s"] / main_res["ops_per_s"], 4),
+                                        "build": round(sres["build_keys_per_s"] / main_res["build_keys_per_s"], 4)},
+                  "kernels": {c: sres["kernels"][c] for c in ("acc_fetch", "acc_writeback", "page_writeout")
+                              if c in sres["kernels"]}}
+        log("sealed: %s" % json.dumps({k: v for k, v in sealed.items() if k != "kernels"}))
     serving = None
     if not args.no_serving:
         serving = run_serving(B, seconds=args.serve_seconds)
@@ -343,6 +357,7 @@ def main():
         "kernels": ks,
         "other_observable_mode": other,
         "autotune": tuned,
+        "sealed": sealed,
         "multi_map": multi,
         "serving": serving,
         "cpu_baseline": cpu,

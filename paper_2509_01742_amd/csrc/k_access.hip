@@ -618,16 +618,16 @@ __global__ __launch_bounds__(256) void k_acc_fetch(FetchArgs a1, const AccessPla
       wave_sync();
       const uint32_t page = b - (uint32_t)a.K;
       const uint64_t ver = a.pver[page];
-      uint32_t key[8], otk[8], tag[4];
+      uint32_t key[8], ks[16], otk[8], tag[4];
 #pragma unroll
       for (int j = 0; j < 8; ++j) key[j] = a.ctl->skey[j];
-      poly_key(key, page, (uint32_t)ver, (uint32_t)(ver >> 32), otk);
+      chacha_first_pass(key, page, (uint32_t)ver, (uint32_t)(ver >> 32), ks, otk);
       poly_page_tag(pg, (uint32_t)a.pw, otk, tag);
       const bool ok = a.tags[2 * (uint64_t)page] == ((uint64_t)tag[0] | ((uint64_t)tag[1] << 32)) &&
                       a.tags[2 * (uint64_t)page + 1] == ((uint64_t)tag[2] | ((uint64_t)tag[3] << 32));
       if (!ok && lane == 0) set_err(a.ctlw, kErrTamper);
       wave_sync();
-      chacha_page_xor(pg, (uint32_t)a.pw, key, page, (uint32_t)ver, (uint32_t)(ver >> 32));
+      chacha_page_xor(pg, (uint32_t)a.pw, ks, key, page, (uint32_t)ver, (uint32_t)(ver >> 32));
       wave_sync();
       src = pg;
     }
@@ -1078,13 +1078,13 @@ __global__ __launch_bounds__(64) void k_acc_writeback(WbArgs a1, const AccessPla
   if (seal) {  // encrypt in LDS under the page's next write count, tag, write
     const uint32_t page = b - (uint32_t)a.K;
     const uint64_t ver = a.pver[page] + 1;
-    uint32_t key[8], otk[8], tag[4];
+    uint32_t key[8], ks[16], otk[8], tag[4];
 #pragma unroll
     for (int j = 0; j < 8; ++j) key[j] = a.ctl->skey[j];
+    chacha_first_pass(key, page, (uint32_t)ver, (uint32_t)(ver >> 32), ks, otk);
     __syncthreads();
-    chacha_page_xor(out, (uint32_t)a.pw, key, page, (uint32_t)ver, (uint32_t)(ver >> 32));
+    chacha_page_xor(out, (uint32_t)a.pw, ks, key, page, (uint32_t)ver, (uint32_t)(ver >> 32));
     __syncthreads();
-    poly_key(key, page, (uint32_t)ver, (uint32_t)(ver >> 32), otk);
     poly_page_tag(out, (uint32_t)a.pw, otk, tag);
     for (uint64_t w = lane; w < a.pw; w += 64) dst[w] = out[w];
     if (lane == 0) {

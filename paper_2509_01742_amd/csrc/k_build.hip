@@ -381,11 +381,13 @@ __global__ __launch_bounds__(256) void k_writeout(BOLT_PLAN_ARGS, uint32_t flip)
 #pragma unroll
   for (int j = 0; j < 8; ++j) skey[j] = P.ctl->skey[j];
   const uint32_t page = (uint32_t)(b - P.K);
-  if (seal) chacha_page_xor(pg, (uint32_t)pw, skey, page, 1u, 0u);
+  uint32_t ks[16], otk[8], tag[4];
+  if (seal) {
+    chacha_first_pass(skey, page, 1u, 0u, ks, otk);
+    chacha_page_xor(pg, (uint32_t)pw, ks, skey, page, 1u, 0u);
+  }
   __syncthreads();
   if (!seal) return;
-  uint32_t otk[8], tag[4];
-  poly_key(skey, page, 1u, 0u, otk);
   poly_page_tag(pg, (uint32_t)pw, otk, tag);
   for (uint64_t w = lane; w < pw; w += 64) dst[w] = pg[w];
   if (lane == 0) {

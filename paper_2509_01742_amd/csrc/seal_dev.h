@@ -211,29 +211,39 @@ __device__ __forceinline__ void poly_page_tag(const uint64_t* ct, uint32_t ct_wo
   tag[3] = (uint32_t)(thi >> 32);
 }
 
-// XOR of the page (LDS, u64 words) with its key stream, in place: lane l
-// takes the 64-byte chunks l, l + 64, ... (block counter = chunk + 1).
-__device__ __forceinline__ void chacha_page_xor(uint64_t* page, uint32_t words, const uint32_t key[8], uint32_t n0,
-                                                uint32_t n1, uint32_t n2) {
+// Key-stream block `lane` of a page, in one pass over the wave: lane 0's
+// block 0 gives the one-time Poly1305 key (returned to every lane in otk),
+// lane l >= 1 keeps block l for the page's 64-byte chunk l - 1.
+__device__ __forceinline__ void chacha_first_pass(const uint32_t key[8], uint32_t n0, uint32_t n1, uint32_t n2,
+                                                  uint32_t ks[16], uint32_t otk[8]) {
   const uint32_t lane = threadIdx.x & 63;
-  for (uint32_t ch = lane; ch * 8 < words; ch += 64) {
-    uint32_t ks[16];
-    chacha_block(key, ch + 1, n0, n1, n2, ks);
+  chacha_block(key, lane, n0, n1, n2, ks);
+#pragma unroll
+  for (int j = 0; j < 8; ++j) otk[j] = (uint32_t)__shfl((int)ks[j], 0, 64);
+}
+
+// XOR of the page (LDS, u64 words) with its key stream, in place: chunk
+// c - 1 with block c; lane l's first block (c = l) comes from the first
+// pass, blocks c = l + 64, l + 128, ... of longer pages are computed here.
+__device__ __forceinline__ void chacha_page_xor(uint64_t* page, uint32_t words, const uint32_t ks[16],
+                                                const uint32_t key[8], uint32_t n0, uint32_t n1, uint32_t n2) {
+  const uint32_t lane = threadIdx.x & 63;
+  if (lane >= 1 && (lane - 1) * 8 < words) {
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
-      const uint32_t w = ch * 8 + j;
+      const uint32_t w = (lane - 1) * 8 + j;
       if (w < words) page[w] ^= (uint64_t)ks[2 * j] | ((uint64_t)ks[2 * j + 1] << 32);
     }
   }
-}
-
-// The one-time Poly1305 key: the first 32 bytes of key-stream block 0.
-__device__ __forceinline__ void poly_key(const uint32_t key[8], uint32_t n0, uint32_t n1, uint32_t n2,
-                                         uint32_t otk[8]) {
-  uint32_t b0[16];
-  chacha_block(key, 0, n0, n1, n2, b0);
+  for (uint32_t c = lane + 64; (c - 1) * 8 < words; c += 64) {
+    uint32_t kb[16];
+    chacha_block(key, c, n0, n1, n2, kb);
 #pragma unroll
-  for (int j = 0; j < 8; ++j) otk[j] = b0[j];
+    for (int j = 0; j < 8; ++j) {
+      const uint32_t w = (c - 1) * 8 + j;
+      if (w < words) page[w] ^= (uint64_t)kb[2 * j] | ((uint64_t)kb[2 * j + 1] << 32);
+    }
+  }
 }
 
 }  // namespace bolt
