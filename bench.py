@@ -30,15 +30,18 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E
 LINK_PEAK_GBS = 64.0    # PCIe 5.0 x16, per direction
+PEAKS = {"hbm": HBM_PEAK_GBS, "host_link": LINK_PEAK_GBS, "host_link_duplex": 2 * LINK_PEAK_GBS}
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def kernel_bytes(cls, sz, n, npad, n_ops, host_roles):
+def kernel_bytes(cls, sz, n, npad, n_ops, host_roles, send_share=0.0):
     """Algorithmic bytes of ONE launch of a kernel class on the resource that
-    bounds it.
+    bounds it.  `send_share` is the fraction of fetch launches that also
+    write the previous batch's rebuilt pages (pinned store, batches of 256
+    commands or more): those launches use both directions of the link.
 
     sort passes (HBM): read + write every 8-byte tag, 16 B x npad.
     expansion passes (HBM): read + write every 8-byte slot, 16 B x B*Z.
@@ -46,9 +49,13 @@ def kernel_bytes(cls, sz, n, npad, n_ops, host_roles):
       mode); in device mode also the K HBM bins, the N keys + values and the
       B*Z slots read (HBM).
     fetch, per batch: the observable pages read, about 2 (1 - alpha) per
-      command (host link); in device mode both whole bins of every command.
-    write-back, per batch: every observable page read is written once (host
-      link); in device mode it is also read back from the stage.
+      command (host link), plus the previous batch's pages written when it
+      carries their send (both directions of the link); in device mode both
+      whole bins of every command.
+    send on its own (flush), per batch: every observable page read is
+      written back once (host link); in device mode also read from the outbox.
+    rebuild (compose), per batch: each page read is read from the stage and
+      written to the outbox (HBM).
     """
     pb, B, Z, K, M, vs = sz["page_bytes"], sz["B"], sz["Z"], sz["K"], sz["M"], sz["vs"]
     host = sz["host"]
@@ -61,9 +68,13 @@ def kernel_bytes(cls, sz, n, npad, n_ops, host_roles):
             return M * pb, "host_link"
         return B * pb + n * (8 + vs) + B * Z * 8, "hbm"
     if cls == "acc_fetch":
-        return (host_roles * pb, "host_link") if host else (2 * n_ops * pb, "hbm")
-    if cls == "acc_writeback":
+        if not host:
+            return 2 * n_ops * pb, "hbm"
+        return (host_roles * pb * (1 + send_share), "host_link_duplex" if send_share else "host_link")
+    if cls == "acc_ship":
         return (host_roles * pb, "host_link") if host else (2 * host_roles * pb, "hbm")
+    if cls == "acc_compose":
+        return 2 * host_roles * pb, "hbm"
     return None, None
 
 
@@ -99,6 +110,8 @@ def run_mode(args, wl, dev_t, B, torch, observable, seal=False):
         for bi in range(nb):
             a, b = int(bounds[bi]), int(bounds[bi + 1])
             B.check(m.access(d_ops[a:b], d_qk[a:b], d_qv[a:b], d_out[a:b], d_st[a:b]), "bolt_access_batch")
+            if bi == nb - 1:  # the last batch's rebuilt pages reach the store inside the step
+                B.check(m.flush(), "bolt_flush")
             evs[bi + 2].record(stream)
         return evs
 
@@ -155,10 +168,11 @@ def run_mode(args, wl, dev_t, B, torch, observable, seal=False):
         if cnt == 0:
             continue
         ent = {"launches": cnt, "total_ms": round(ms, 3), "avg_us": round(1e3 * ms / cnt, 2)}
-        per, bound = kernel_bytes(cls, sz, n, npad, n_ops / nb, host_roles / nb)
+        send_share = (nb - 1) / nb if (sz["host"] and n_ops / nb >= 256) else 0.0
+        per, bound = kernel_bytes(cls, sz, n, npad, n_ops / nb, host_roles / nb, send_share)
         if per is not None:
             gbs = per / (ms / cnt / 1e3) / 1e9
-            peak = LINK_PEAK_GBS if bound == "host_link" else HBM_PEAK_GBS
+            peak = PEAKS[bound]
             ent.update({"bytes_per_launch": int(per), "achieved_GBps": round(gbs, 1), "bound": bound,
                         "frac_of_peak": round(gbs / peak, 4)})
         kernels[cls] = ent
@@ -181,8 +195,9 @@ def run_mode(args, wl, dev_t, B, torch, observable, seal=False):
 
 # kernel class -> (kernel in the rocprofv3 counter summary, sources it is built from)
 PROFILED = {
-    "acc_writeback": ("bolt::k_acc_writeback<false>", ("k_access.hip", "bolt_dev.h", "bolt_impl.h")),
-    "acc_fetch": ("bolt::k_acc_fetch<false>", ("k_access.hip", "bolt_dev.h", "bolt_impl.h")),
+    "acc_ship": ("bolt::k_acc_ship<false>", ("k_access.hip", "bolt_dev.h", "bolt_impl.h")),
+    "acc_compose": ("bolt::k_acc_compose<false>", ("k_access.hip", "bolt_dev.h", "bolt_impl.h")),
+    "acc_fetch": ("bolt::k_acc_fetch<false, false>", ("k_access.hip", "bolt_dev.h", "bolt_impl.h")),
     "sort_global": ("bolt::k_bitonic_global<4, false>", ("k_prim.hip", "bolt_dev.h", "bolt_impl.h")),
     "sort_merge": ("bolt::k_bitonic_tile<false>", ("k_prim.hip", "bolt_dev.h", "bolt_impl.h")),
     "page_writeout": ("bolt::k_writeout<false>", ("k_build.hip", "bolt_dev.h", "bolt_impl.h")),
@@ -216,7 +231,7 @@ def roofline_of(res, cls, mode):
     k = res["kernels"].get(cls)
     if not k or "achieved_GBps" not in k:
         return None
-    peak = LINK_PEAK_GBS if k["bound"] == "host_link" else HBM_PEAK_GBS
+    peak = PEAKS[k["bound"]]
     return {"bound": k["bound"], "kernel": cls, "achieved": k["achieved_GBps"], "peak": peak, "unit": "GB/s",
             "frac": round(k["achieved_GBps"] / peak, 4), "traffic": measured_traffic(cls, mode),
             "bytes_per_launch": k["bytes_per_launch"], "avg_launch_us": k["avg_us"], "launches": k["launches"]}
@@ -318,7 +333,7 @@ def main():
                   "batch_latency_ms": {"p50": round(sres["lat_p50"], 4), "p99": round(sres["lat_p99"], 4)},
                   "relative_to_plain": {"ops": round(sres["ops_per_s"] / main_res["ops_per_s"], 4),
                                         "build": round(sres["build_keys_per_s"] / main_res["build_keys_per_s"], 4)},
-                  "kernels": {c: sres["kernels"][c] for c in ("acc_fetch", "acc_writeback", "page_writeout")
+                  "kernels": {c: sres["kernels"][c] for c in ("acc_fetch", "acc_compose", "acc_ship", "page_writeout")
                               if c in sres["kernels"]}}
         log("sealed: %s" % json.dumps({k: v for k, v in sealed.items() if k != "kernels"}))
     serving = None

@@ -26,6 +26,11 @@
  *     call except bolt_destroy returns BOLT_ESTATE.
  *   - Keys are any 64-bit values.  Values are value_bytes bytes each, rows of
  *     a row-major [q][value_bytes] array.
+ *   - The observable pages a batch rewrites (Sec. 5.1 step 5) are rebuilt in
+ *     HBM and written to the store during the map's next batch, while that
+ *     batch reads its own pages (the host link carries both directions at
+ *     once); bolt_flush writes them at once.  Answers never depend on it, and
+ *     every call below that reads the store, and bolt_status, flush first.
  */
 #ifndef BOLT_H
 #define BOLT_H
@@ -199,6 +204,12 @@ int bolt_versions_snapshot(bolt_map* m, uint64_t* host_buf, uint64_t cap);
  * for tests.  Reads (write = 0) or overwrites (write = 1) page `page` and its
  * tag: host_buf holds page_bytes + 16 bytes.  Synchronises first. */
 int bolt_observable_raw(bolt_map* m, uint64_t page, void* host_buf, int write);
+
+/* Writes the observable pages rebuilt by the map's last batch to the store
+ * (a no-op when there are none), ordered on hip_stream, which must be the
+ * stream of the map's last call or ordered after it.  Needed only where the
+ * store itself is read from outside the library. */
+int bolt_flush(bolt_map* m, void* hip_stream);
 
 /* Frees every resource of the map after waiting for its work.  NULL is a no-op. */
 int bolt_destroy(bolt_map* m);

@@ -113,6 +113,7 @@ _SIGS = [
     ("bolt_put_batch", _I, [_P, _P, _P, _U32, _P, _P]),
     ("bolt_destroy", _I, [_P]),
     ("bolt_status", _I, [_P]),
+    ("bolt_flush", _I, [_P, _P]),
     ("bolt_map_sizes", _I, [_P, C.POINTER(bolt_sizes)]),
     ("bolt_get_stats", _I, [_P, C.POINTER(bolt_stats)]),
     ("bolt_trace_read", _I, [_P, _P, _U64, C.POINTER(_U64)]),
@@ -258,6 +259,9 @@ class Map:
 
     def put(self, keys, vals, status, stream=None) -> int:
         return bolt_put_batch(self.h, _dptr(keys), _dptr(vals), keys.numel(), _dptr(status), _stream(stream))
+
+    def flush(self, stream=None) -> int:
+        return bolt_flush(self.h, _stream(stream))
 
     # --- state ----------------------------------------------------------
     def status(self) -> int:

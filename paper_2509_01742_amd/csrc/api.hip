@@ -62,7 +62,8 @@ int derive(const bolt_params* p, Sizes* s) {
 
 uint64_t scratch_bytes(const Sizes& s) {
   const uint64_t Q = kMaxBatch;
-  return Q * 4 * 13 + Q * s.vs + Q * 8 + 3 * Q * 4 + 2 * Q * s.page_bytes + 2 * Q * s.vs + 2 * Q + Q * 24 + 256 * 4;
+  return Q * 4 * 13 + Q * s.vs + Q * 8 + 3 * Q * 4 + 2 * Q * s.page_bytes + 2 * Q * s.vs + 2 * Q + Q * 24 + 256 * 4 +
+         2 * Q * s.page_bytes + 2 * Q * 4;  // outbox + the page each of its slots sends
 }
 
 uint64_t device_bytes(const bolt_params* p, const Sizes& s) {
@@ -75,6 +76,7 @@ uint64_t device_bytes(const bolt_params* p, const Sizes& s) {
   b += s.P * (8 + s.vs + 4 + 4) + s.PW * 8;  // stash pool + bitmap
   b += s.B * 4 + s.B * 2 * s.Z * 4;  // reverse index
   b += s.B * 16;                     // claim + rmask
+  b += s.M * 8;                      // last rebuild of each observable page
   b += scratch_bytes(s);
   if (p->flags & BOLT_F_TRACE) b += p->trace_words * 4;
   return b;
@@ -105,6 +107,13 @@ void free_all(bolt_map* m) {
   m->ev_fork = m->ev_join = nullptr;
 }
 
+// Sends the last batch's pages to the store and waits for the map's stream.
+int sync_map(bolt_map* m) {
+  if (flush_ship(m, m->last_stream)) return BOLT_EHIP;
+  if (hipStreamSynchronize(m->last_stream) != hipSuccess) return BOLT_EHIP;
+  return BOLT_OK;
+}
+
 int map_check(bolt_map* m) {
   if (!m) return BOLT_EINVAL;
   if (m->poisoned) return BOLT_ESTATE;
@@ -122,7 +131,7 @@ int err_code(uint32_t bits) {
 
 int sync_and_read(bolt_map* m, Ctl* host) {
   if (hipSetDevice(m->device) != hipSuccess) return BOLT_EHIP;
-  if (hipStreamSynchronize(m->last_stream) != hipSuccess) return BOLT_EHIP;
+  if (sync_map(m)) return BOLT_EHIP;
   if (hipMemcpy(host, m->ctl, sizeof(Ctl), hipMemcpyDeviceToHost) != hipSuccess) return BOLT_EHIP;
   uint32_t bits = host->err & ~kErrTrace;
   if (bits && !m->poisoned) {
@@ -242,6 +251,9 @@ int bolt_create(const bolt_params* p, void* hip_stream, bolt_map** out) {
   rc = rc ? rc : dalloc(m, &b.rpair, Q * 8);
   rc = rc ? rc : dalloc(m, &b.cand_bin, 3 * Q * 4);
   rc = rc ? rc : dalloc(m, &b.stage, 2 * Q * s.page_bytes);
+  rc = rc ? rc : dalloc(m, &b.outbox, 2 * Q * s.page_bytes);
+  rc = rc ? rc : dalloc(m, &b.ship_page, 2 * Q * 4);
+  rc = rc ? rc : dalloc(m, &m->wslot, s.M * 8);
   rc = rc ? rc : dalloc(m, &b.fin, Q * 4);
   rc = rc ? rc : dalloc(m, &b.chosen, Q * 4);
   rc = rc ? rc : dalloc(m, &b.rowsel, Q * 4);
@@ -295,6 +307,7 @@ int bolt_create(const bolt_params* p, void* hip_stream, bolt_map** out) {
   }
   launch_map_init(m, st);
   (void)hipMemsetAsync(m->bs.freed, 0, 256 * 4, st);
+  (void)hipMemsetAsync(m->wslot, 0, s.M * 8, st);  // epoch 0: no page rebuilt yet
 
   hipLaunchKernelGGL(k_fill_u8, dim3((uint32_t)((Q + 255) / 256)), dim3(256), 0, st, m->get_ops, Q, (uint8_t)0);
   hipLaunchKernelGGL(k_fill_u8, dim3((uint32_t)((Q + 255) / 256)), dim3(256), 0, st, m->put_ops, Q, (uint8_t)1);
@@ -427,12 +440,20 @@ int bolt_put_batch(bolt_map* m, const uint64_t* d_keys, const void* d_vals, uint
 int bolt_destroy(bolt_map* m) {
   if (!m) return BOLT_OK;
   (void)hipSetDevice(m->device);
-  (void)hipStreamSynchronize(m->last_stream);
+  (void)hipStreamSynchronize(m->last_stream);  // pages still to be sent die with the map
   if (m->side) (void)hipStreamSynchronize(m->side);
   delete m->timer;
   free_all(m);
   delete m;
   return BOLT_OK;
+}
+
+int bolt_flush(bolt_map* m, void* hip_stream) {
+  if (!m) return BOLT_EINVAL;
+  hipStream_t st = (hipStream_t)hip_stream;
+  if (hipSetDevice(m->device) != hipSuccess) return BOLT_EHIP;
+  m->last_stream = st;
+  return flush_ship(m, st);
 }
 
 int bolt_status(bolt_map* m) {
@@ -564,6 +585,9 @@ int bolt_observable_raw(bolt_map* m, uint64_t page, void* host_buf, int write) {
   uint8_t* buf = static_cast<uint8_t*>(host_buf);
   uint8_t* pg = m->obs + page * pb;
   uint8_t* tg = m->tags + page * 16;
+  // A page changed from the host is read back from the store, not from the
+  // outbox of the last batch's rebuilt pages.
+  if (write) m->ov_off = true;
   if (m->obs_host) {  // pinned memory: the host's own view
     pg = m->obs_host + page * pb;
     tg = m->obs_host + m->s.M * pb + page * 16;
@@ -666,7 +690,7 @@ int bolt_pm_snapshot(bolt_map* m, uint64_t* host_rows, uint64_t* host_keys, uint
 
 int bolt_kernel_times(bolt_map* m, bolt_kernel_time* host_out, uint32_t cap, uint32_t* n) {
   if (!m || !n || !m->timer) return BOLT_EINVAL;
-  if (hipSetDevice(m->device) != hipSuccess || hipStreamSynchronize(m->last_stream) != hipSuccess) return BOLT_EHIP;
+  if (hipSetDevice(m->device) != hipSuccess || sync_map(m)) return BOLT_EHIP;
   if (m->timer->collect()) return BOLT_EHIP;
   for (uint32_t i = 0; i < (uint32_t)kkCount && i < cap && host_out; ++i) {
     memset(&host_out[i], 0, sizeof(host_out[i]));
@@ -680,7 +704,7 @@ int bolt_kernel_times(bolt_map* m, bolt_kernel_time* host_out, uint32_t cap, uin
 
 int bolt_kernel_times_reset(bolt_map* m) {
   if (!m || !m->timer) return BOLT_EINVAL;
-  if (hipSetDevice(m->device) != hipSuccess || hipStreamSynchronize(m->last_stream) != hipSuccess) return BOLT_EHIP;
+  if (hipSetDevice(m->device) != hipSuccess || sync_map(m)) return BOLT_EHIP;
   if (m->timer->collect()) return BOLT_EHIP;
   m->timer->reset();
   return BOLT_OK;

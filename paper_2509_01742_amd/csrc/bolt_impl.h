@@ -24,6 +24,8 @@ struct BatchScratch {
   uint2* rpair;       // [Q] remap pair R(s) of each command
   uint32_t* cand_bin; // [3Q] bin each write-back candidate slot would rewrite, or kNone
   uint8_t* stage;     // [2Q * page_bytes] copies of the observable pages read
+  uint8_t* outbox;    // [2Q * page_bytes] observable pages rebuilt by the write-back, by slot
+  uint32_t* ship_page;  // [2Q] observable page each write-back slot sends to the store, or kNone
   uint32_t* fin;      // [Q] (leaders) bit 0 present at the end, bit 1 found in the map
   uint32_t* chosen;   // [Q] (leaders placed) bin chosen by P2C
   uint32_t* rowsel;   // [Q] (keys inserted) position-map row chosen
@@ -42,7 +44,7 @@ struct TraceSeg {
 // Kernel classes timed with HIP events when a map has BOLT_F_TIMING.
 enum KernelId {
   kkSortTile, kkSortGlobal, kkSortMerge, kkPairs, kkP2C, kkScan, kkExpand, kkWriteout, kkPmBuild, kkDupcheck,
-  kkBuildMisc, kkAccDedup, kkAccFetch, kkAccResolve, kkAccRemap, kkAccWriteback, kkAccMisc, kkCount
+  kkBuildMisc, kkAccDedup, kkAccFetch, kkAccResolve, kkAccRemap, kkAccCompose, kkAccShip, kkAccMisc, kkCount
 };
 extern const char* const kKernelNames[kkCount];
 
@@ -133,6 +135,16 @@ struct bolt_map {
   // BOLT_F_SEAL: tags beside the observable pages, write counts in HBM
   uint8_t* tags;    // [M * 16], observable (device address)
   uint64_t* pver;   // [M]
+  // The write-back rebuilds a batch's observable pages in HBM (the outbox);
+  // they go to the store during the next batch's fetch, whose workgroups
+  // read pages over the link while these write (both directions at once),
+  // or when bolt_flush or a reader of the store asks.  wslot[p] holds
+  // (batch epoch << 32 | outbox slot) of the last rebuild of page p, so that
+  // fetch takes such a page from the outbox (it still reads the store's
+  // copy, for the same trace).
+  uint64_t* wslot;  // [M]
+  uint32_t ship_q;  // commands of the batch whose pages are still to be sent, 0 = none
+  bool ov_off;        // next batch: no outbox pages (the store was changed from the host)
 };
 
 namespace bolt {
@@ -173,5 +185,7 @@ int run_build_many(bolt_map* const* maps, const uint64_t* const* keys, const voi
 int run_access(bolt_map* m, const uint8_t* ops, const uint64_t* keys, const void* vals_in, void* vals_out,
                uint8_t* status, uint32_t q, hipStream_t st);
 int run_access_many(bolt_map* const* maps, const bolt_batch* batches, uint32_t count, hipStream_t st);
+// Sends the rebuilt pages of the map's last batch to the store, if any.
+int flush_ship(bolt_map* m, hipStream_t st);
 
 }  // namespace bolt

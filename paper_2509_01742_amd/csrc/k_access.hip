@@ -48,6 +48,18 @@ struct GroupArgs {
   uint4* rows;
 };
 
+// The send of a batch's rebuilt observable pages to the store.
+struct ShipArgs {
+  const Ctl* ctl;
+  uint32_t q;
+  uint64_t pw;
+  const uint32_t* ship_page;
+  const uint64_t* outbox;
+  uint64_t* obs;
+  uint64_t* tags;  // BOLT_F_SEAL: [M][2] page tags, else null
+  uint64_t* pver;  // BOLT_F_SEAL: [M] page write counts
+};
+
 struct FetchArgs {
   const Ctl* ctl;
   const uint8_t* ops;
@@ -84,6 +96,11 @@ struct FetchArgs {
   Ctl* ctlw;
   const uint64_t* tags;  // BOLT_F_SEAL: [M][2] page tags, else null
   const uint64_t* pver;  // BOLT_F_SEAL: [M] page write counts
+  const uint64_t* wslot;   // [M] last rebuild of each page: epoch << 32 | outbox slot
+  const uint64_t* outbox;  // [2Q][pw] the previous batch's rebuilt pages
+  uint32_t ov_epoch;       // epoch whose rebuilt pages the outbox holds, 0 = none
+  ShipArgs ship;           // the previous batch's send (ship.q = 0: none) ...
+  uint32_t ship_blocks;    // ... by the first ship_blocks workgroups
 };
 
 struct ResolveArgs {
@@ -175,7 +192,6 @@ struct WbArgs {
   const uint64_t* claim;
   uint64_t* rmask;
   const uint64_t* stage;
-  uint64_t* obs;
   uint64_t* hbm;
   uint32_t* rev_cnt;
   const uint32_t* rev_idx;
@@ -183,11 +199,17 @@ struct WbArgs {
   const uint64_t* st_val;
   uint32_t* st_dead;
   uint64_t* st_used;
-  uint32_t* freed;   // [kFreeBuckets] entries freed, summed by finish
-  uint32_t* tlog_w;  // [3q] or null
-  uint64_t* tags;    // BOLT_F_SEAL: [M][2] page tags, else null
-  uint64_t* pver;    // BOLT_F_SEAL: [M] page write counts
+  uint32_t* freed;      // [kFreeBuckets] entries freed, summed by finish
+  uint32_t* tlog_w;     // [3q] or null
+  uint64_t* outbox;     // [2Q][pw] rebuilt observable pages, by slot
+  uint32_t* ship_page;  // [2Q] page each slot sends, or kNone
+  uint64_t* wslot;      // [M]
+  uint32_t direct;      // 1: write observable pages to the store here (no send)
+  uint64_t* obs;        // direct: the store
+  uint64_t* tags;       // direct, BOLT_F_SEAL: [M][2] page tags, else null
+  uint64_t* pver;       // direct, BOLT_F_SEAL: [M] page write counts
 };
+
 
 struct FinishArgs {
   Ctl* ctl;
@@ -215,7 +237,7 @@ struct AccessPlan {
   FinishArgs fn;
   uint32_t q, fast;
   uint64_t wb_lds;     // dynamic LDS of the write-back
-  uint64_t fetch_lds;  // dynamic LDS of the fetch (sealed maps)
+  uint64_t fetch_lds;  // dynamic LDS of the fetch (sealed maps; a send it carries uses the same)
 };
 
 #define BOLT_PICK(T, field) const T& a = MULTI ? tab[blockIdx.y].field : a1
@@ -553,6 +575,57 @@ __global__ __launch_bounds__(kDedupNT) void k_acc_group(GroupArgs a1, const Acce
 }
 
 // ---------------------------------------------------------------------------
+// send of rebuilt observable pages
+// ---------------------------------------------------------------------------
+
+// The send of a batch's rebuilt observable pages to the store: wave `wave`
+// of `waves` takes fetch slots wave, wave + waves, ...  Plain maps copy the
+// page; sealed maps encrypt it in the wave's LDS page `pg` under the page's
+// next write count, tag it, and write page and tag.
+__device__ __forceinline__ void ship_slots(const ShipArgs& a, uint32_t wave, uint32_t waves, uint64_t* pg) {
+  const uint32_t lane = threadIdx.x & 63;
+  uint32_t key[8];
+  if (a.tags) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) key[j] = a.ctl->skey[j];
+  }
+  for (uint32_t s = wave; s < 2 * a.q; s += waves) {
+    const uint32_t page = a.ship_page[s];
+    if (page == kNone) continue;  // whole wave
+    const uint64_t* src = a.outbox + (uint64_t)s * a.pw;
+    uint64_t* dst = a.obs + (uint64_t)page * a.pw;
+    if (!a.tags) {
+      for (uint64_t w = lane; w < a.pw; w += 64) dst[w] = src[w];
+      continue;
+    }
+    for (uint64_t w = lane; w < a.pw; w += 64) pg[w] = src[w];
+    const uint64_t ver = a.pver[page] + 1;
+    uint32_t tag[4];
+    seal_page(pg, (uint32_t)a.pw, key, page, ver, dst, tag);
+    if (lane == 0) {
+      a.tags[2 * (uint64_t)page] = (uint64_t)tag[0] | ((uint64_t)tag[1] << 32);
+      a.tags[2 * (uint64_t)page + 1] = (uint64_t)tag[2] | ((uint64_t)tag[3] << 32);
+      a.pver[page] = ver;
+    }
+    wave_sync();  // the wave's LDS page is reused by its next slot
+  }
+}
+
+// Workgroups (of 4 waves) of a send: one per 8 commands, at most 256, so
+// that the fetch it rides with keeps most of the device.
+constexpr uint32_t kShipMaxBlocks = 256;
+__host__ __device__ constexpr uint32_t ship_blocks_for(uint32_t q) {
+  return q == 0 ? 0 : ((2 * q + 3) / 4 < kShipMaxBlocks ? (2 * q + 3) / 4 : kShipMaxBlocks);
+}
+
+// A send on its own (bolt_flush, readers of the store, many-map calls).
+__global__ __launch_bounds__(256) void k_acc_ship(ShipArgs a) {
+  extern __shared__ uint64_t sdyn[];
+  const uint32_t wv = threadIdx.x >> 6;
+  ship_slots(a, blockIdx.x * 4 + wv, gridDim.x * 4, sdyn + (uint64_t)wv * a.pw);
+}
+
+// ---------------------------------------------------------------------------
 // fetch: one wave per command
 // ---------------------------------------------------------------------------
 
@@ -561,8 +634,14 @@ __global__ __launch_bounds__(kDedupNT) void k_acc_group(GroupArgs a1, const Acce
 template <bool MULTI, bool SEALED>
 __global__ __launch_bounds__(256) void k_acc_fetch(FetchArgs a1, const AccessPlan* tab) {
   BOLT_PICK(FetchArgs, fa);
+  extern __shared__ uint64_t fdyn[];
   const uint32_t lane = threadIdx.x & 63;
-  const uint32_t i = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (!MULTI && blockIdx.x < a.ship_blocks) {  // the previous batch's send
+    ship_slots(a.ship, blockIdx.x * 4 + (threadIdx.x >> 6), a.ship_blocks * 4,
+               fdyn + (uint64_t)(threadIdx.x >> 6) * a.pw);
+    return;
+  }
+  const uint32_t i = (blockIdx.x - (MULTI ? 0 : a.ship_blocks)) * 4 + (threadIdx.x >> 6);
   if (i >= a.q) return;
   if (a.ctl->reject == a.epoch || a.ctl->err) return;
   const uint2 fp = a.fpair[i];  // F(s), from the dedup kernel
@@ -608,11 +687,24 @@ __global__ __launch_bounds__(256) void k_acc_fetch(FetchArgs a1, const AccessPla
     }
     const uint64_t* src = host ? a.obs + (uint64_t)(b - a.K) * a.pw : a.hbm + (uint64_t)b * a.pw;
     uint64_t* stg = a.stage + (uint64_t)slot * a.pw;
-    if (SEALED && a.tags && host) {
+    bool fresh = false;  // rebuilt by the previous batch, whose send may still run
+    if (host && a.ov_epoch) {
+      const uint64_t ws = a.wslot[b - a.K];
+      if ((uint32_t)(ws >> 32) == a.ov_epoch) {
+        // The store's copy is read all the same (the trace does not change),
+        // but the page itself comes from the outbox.
+        const volatile uint64_t* hv = src;
+        uint64_t sink = 0;
+        for (uint64_t w = lane; w < a.pw; w += 64) sink ^= hv[w];
+        (void)sink;
+        src = a.outbox + (uint64_t)(uint32_t)ws * a.pw;
+        fresh = true;
+      }
+    }
+    if (SEALED && a.tags && host && !fresh) {
       // Sealed page: copy it into this wave's LDS, check its tag under the
       // write count kept in HBM, and decrypt it there; the rest reads the
       // plain page from LDS.
-      extern __shared__ uint64_t fdyn[];
       uint64_t* pg = fdyn + (uint64_t)(threadIdx.x >> 6) * a.pw;
       for (uint64_t w = lane; w < a.pw; w += 64) pg[w] = src[w];
       wave_sync();
@@ -991,9 +1083,11 @@ __host__ __device__ constexpr uint64_t wb_lds_bytes(uint64_t pw) { return pw * 8
 // One wave (one workgroup) per candidate slot.  The elected writer copies
 // the bin's old page into LDS (observable pages from the stage the fetch
 // wrote, HBM bins from HBM), so the rebuilt page can be written in place
-// without any device-wide fence.
+// without any device-wide fence.  HBM bins are rebuilt in place; an
+// observable page is rebuilt into the outbox at the writer's slot, for
+// k_acc_ship to send.
 template <bool MULTI>
-__global__ __launch_bounds__(64) void k_acc_writeback(WbArgs a1, const AccessPlan* tab) {
+__global__ __launch_bounds__(64) void k_acc_compose(WbArgs a1, const AccessPlan* tab) {
   BOLT_PICK(WbArgs, wa);
   extern __shared__ uint64_t dyn[];
   uint64_t* old = dyn;
@@ -1002,10 +1096,15 @@ __global__ __launch_bounds__(64) void k_acc_writeback(WbArgs a1, const AccessPla
   uint32_t* by_rank = isrc + kWbItems;
   const uint32_t lane = threadIdx.x;
   const uint32_t s = blockIdx.x;
+  if (lane == 0 && s < 2 * a.q) a.ship_page[s] = kNone;
   if (s >= 3 * a.q || a.ctl->reject == a.epoch || a.ctl->err) return;  // whole block
   const uint32_t b = a.cand_bin[s];
   if (b == kNone || a.claim[b] != claim_tag(a.epoch, s)) return;  // whole block
   const bool host = b >= a.K;
+  if (host && s >= 2 * a.q) {  // observable bins are only claimed by fetch slots
+    if (lane == 0) set_err(a.ctl, kErrBroken);
+    return;
+  }
   const uint64_t* src = host ? a.stage + (uint64_t)s * a.pw : a.hbm + (uint64_t)b * a.pw;
   for (uint64_t w = lane; w < a.pw; w += 64) old[w] = src[w];
   const uint64_t rm = a.rmask[b];
@@ -1053,9 +1152,11 @@ __global__ __launch_bounds__(64) void k_acc_writeback(WbArgs a1, const AccessPla
     by_rank[rank] = lane;
   }
   __syncthreads();
-  uint64_t* dst = host ? a.obs + (uint64_t)(b - a.K) * a.pw : a.hbm + (uint64_t)b * a.pw;
-  // sealed map, observable page: compose it in LDS after the item lists
-  const bool seal = a.tags && host;
+  // HBM bin: in place.  Observable page: to the outbox, or straight to the
+  // store when direct (a sealed one through LDS after the item lists).
+  const bool seal = host && a.direct && a.tags;
+  uint64_t* const dst = host ? (a.direct ? a.obs + (uint64_t)(b - a.K) * a.pw : a.outbox + (uint64_t)s * a.pw)
+                             : a.hbm + (uint64_t)b * a.pw;
   uint64_t* out = seal ? reinterpret_cast<uint64_t*>(reinterpret_cast<char*>(dyn) + wb_lds_bytes(a.pw)) : dst;
   for (uint64_t w = lane; w < a.pw; w += 64) {
     uint64_t v = 0;
@@ -1075,18 +1176,13 @@ __global__ __launch_bounds__(64) void k_acc_writeback(WbArgs a1, const AccessPla
     }
     out[w] = v;
   }
-  if (seal) {  // encrypt in LDS under the page's next write count, tag, write
+  if (seal) {
     const uint32_t page = b - (uint32_t)a.K;
     const uint64_t ver = a.pver[page] + 1;
-    uint32_t key[8], ks[16], otk[8], tag[4];
+    uint32_t key[8], tag[4];
 #pragma unroll
     for (int j = 0; j < 8; ++j) key[j] = a.ctl->skey[j];
-    chacha_first_pass(key, page, (uint32_t)ver, (uint32_t)(ver >> 32), ks, otk);
-    __syncthreads();
-    chacha_page_xor(out, (uint32_t)a.pw, ks, key, page, (uint32_t)ver, (uint32_t)(ver >> 32));
-    __syncthreads();
-    poly_page_tag(out, (uint32_t)a.pw, otk, tag);
-    for (uint64_t w = lane; w < a.pw; w += 64) dst[w] = out[w];
+    seal_page(out, (uint32_t)a.pw, key, page, ver, dst, tag);
     if (lane == 0) {
       a.tags[2 * (uint64_t)page] = (uint64_t)tag[0] | ((uint64_t)tag[1] << 32);
       a.tags[2 * (uint64_t)page + 1] = (uint64_t)tag[2] | ((uint64_t)tag[3] << 32);
@@ -1103,7 +1199,14 @@ __global__ __launch_bounds__(64) void k_acc_writeback(WbArgs a1, const AccessPla
     a.rmask[b] = 0;
     a.rev_cnt[b] = 0;
     if (cnt) atomicAdd(&a.freed[s % kFreeBuckets], cnt);
-    if (host && a.tlog_w) a.tlog_w[s] = (uint32_t)(b - a.K);
+    if (host) {
+      const uint32_t page = b - (uint32_t)a.K;
+      if (!a.direct) {
+        a.ship_page[s] = page;
+        a.wslot[page] = ((uint64_t)a.epoch << 32) | s;
+      }
+      if (a.tlog_w) a.tlog_w[s] = page;
+    }
   }
 }
 
@@ -1157,6 +1260,20 @@ __global__ void k_fill_u32(uint32_t* p, uint64_t n, uint32_t v) {
 }
 
 // ---------------------------------------------------------------------------
+
+// The send of the map's last `q` rebuilt slots.
+static ShipArgs ship_args(bolt_map* m, uint32_t q) {
+  ShipArgs a;
+  a.ctl = m->ctl;
+  a.q = q;
+  a.pw = m->s.page_bytes / 8;
+  a.ship_page = m->bs.ship_page;
+  a.outbox = reinterpret_cast<const uint64_t*>(m->bs.outbox);
+  a.obs = reinterpret_cast<uint64_t*>(m->obs);
+  a.tags = reinterpret_cast<uint64_t*>(m->tags);
+  a.pver = m->pver;
+  return a;
+}
 
 // Fills every kernel argument of one map's batch; reserves its trace words.
 static void plan_access(bolt_map* m, const uint8_t* ops, const uint64_t* keys, const void* vals_in, void* vals_out,
@@ -1233,6 +1350,12 @@ static void plan_access(bolt_map* m, const uint8_t* ops, const uint64_t* keys, c
   fa.ctlw = m->ctl;
   fa.tags = reinterpret_cast<const uint64_t*>(m->tags);
   fa.pver = m->pver;
+  fa.wslot = m->wslot;
+  fa.outbox = reinterpret_cast<const uint64_t*>(bs.outbox);
+  fa.ov_epoch = m->ov_off ? 0 : epoch - 1;
+  m->ov_off = false;
+  fa.ship = ship_args(m, 0);  // run_access hands the previous batch's send to its fetch
+  fa.ship_blocks = 0;
 
   ResolveArgs& rv = P.rv;
   rv.ctl = m->ctl;
@@ -1342,7 +1465,6 @@ static void plan_access(bolt_map* m, const uint8_t* ops, const uint64_t* keys, c
   wa.claim = m->claim;
   wa.rmask = m->rmask;
   wa.stage = reinterpret_cast<const uint64_t*>(bs.stage);
-  wa.obs = reinterpret_cast<uint64_t*>(m->obs);
   wa.hbm = reinterpret_cast<uint64_t*>(m->hbm);
   wa.rev_cnt = m->rev_cnt;
   wa.rev_idx = m->rev_idx;
@@ -1352,8 +1474,14 @@ static void plan_access(bolt_map* m, const uint8_t* ops, const uint64_t* keys, c
   wa.st_used = m->st_used;
   wa.freed = bs.freed;
   wa.tlog_w = tlog_w;
+  wa.outbox = reinterpret_cast<uint64_t*>(bs.outbox);
+  wa.ship_page = bs.ship_page;
+  wa.wslot = m->wslot;
+  wa.direct = 1;  // run_access switches a large host-store batch to the send
+  wa.obs = reinterpret_cast<uint64_t*>(m->obs);
   wa.tags = reinterpret_cast<uint64_t*>(m->tags);
   wa.pver = m->pver;
+
 
   FinishArgs& fn = P.fn;
   fn.ctl = m->ctl;
@@ -1419,8 +1547,22 @@ static void launch_many(const AccessPlan& p0, const AccessPlan* tab, uint32_t C,
   hipLaunchKernelGGL(k_acc_resolve<true>, dim3((qmax + 255) / 256, C), dim3(256), 0, st, p0.rv, tab);
   if (any_fast) hipLaunchKernelGGL(k_acc_place<true>, dim3((qmax + 255) / 256, C), dim3(256), 0, st, p0.pa, tab);
   if (any_slow) hipLaunchKernelGGL(k_acc_remap<true>, dim3(1, C), dim3(kRemapNT), 0, st, p0.ra, tab);
-  hipLaunchKernelGGL(k_acc_writeback<true>, dim3(3 * qmax, C), dim3(64), lds, st, p0.wa, tab);
+  hipLaunchKernelGGL(k_acc_compose<true>, dim3(3 * qmax, C), dim3(64), lds, st, p0.wa, tab);
   hipLaunchKernelGGL(k_acc_finish<true>, dim3((qmax + 255) / 256, C), dim3(256), 0, st, p0.fn, tab);
+}
+
+// Smallest batch whose observable pages are sent during the next batch.
+constexpr uint32_t kDeferMinBatch = 256;
+
+int flush_ship(bolt_map* m, hipStream_t st) {
+  if (!m->ship_q) return BOLT_OK;
+  const ShipArgs a = ship_args(m, m->ship_q);
+  {
+    TimedScope ts(m->timer, kkAccShip, st);
+    hipLaunchKernelGGL(k_acc_ship, dim3(ship_blocks_for(a.q)), dim3(256), m->tags ? 4 * m->s.page_bytes : 0, st, a);
+  }
+  m->ship_q = 0;
+  return hipGetLastError() == hipSuccess ? BOLT_OK : BOLT_EHIP;
 }
 
 // One-map batch through a graph captured for its size class: the call's
@@ -1434,6 +1576,7 @@ static int run_access_graph(bolt_map* m, AccessPlan& P, hipStream_t st) {
     m->allocs.push_back(m->gplan);
   }
   AccessPlan* tab = static_cast<AccessPlan*>(m->gplan);
+  if (flush_ship(m, st)) return BOLT_EHIP;
   if (!m->gexec[cls]) {
     // both remap forms are in the graph; the plan's flags pick one per call
     hipStream_t cs = m->side;
@@ -1467,12 +1610,18 @@ int run_access(bolt_map* m, const uint8_t* ops, const uint64_t* keys, const void
     TimedScope ts(m->timer, kkAccDedup, st);
     hipLaunchKernelGGL(k_acc_group<false>, dim3(kParts), dim3(kDedupNT), 0, st, P.gr, none);
   }
+  // The fetch's first workgroups send the previous batch's rebuilt pages
+  // (device-to-host over the link while the fetch reads host-to-device).
+  P.fa.ship.q = m->ship_q;
+  P.fa.ship_blocks = ship_blocks_for(m->ship_q);
+  m->ship_q = 0;
   {
     TimedScope ts(m->timer, kkAccFetch, st);
+    const dim3 grid(P.fa.ship_blocks + (q + 3) / 4);
     if (P.fetch_lds)
-      hipLaunchKernelGGL((k_acc_fetch<false, true>), dim3((q + 3) / 4), dim3(256), P.fetch_lds, st, P.fa, none);
+      hipLaunchKernelGGL((k_acc_fetch<false, true>), grid, dim3(256), P.fetch_lds, st, P.fa, none);
     else
-      hipLaunchKernelGGL((k_acc_fetch<false, false>), dim3((q + 3) / 4), dim3(256), 0, st, P.fa, none);
+      hipLaunchKernelGGL((k_acc_fetch<false, false>), grid, dim3(256), 0, st, P.fa, none);
   }
   {
     TimedScope ts(m->timer, kkAccResolve, st);
@@ -1485,10 +1634,16 @@ int run_access(bolt_map* m, const uint8_t* ops, const uint64_t* keys, const void
     else
       hipLaunchKernelGGL(k_acc_remap<false>, dim3(1), dim3(kRemapNT), 0, st, P.ra, none);
   }
+  // A large batch on a pinned host store rebuilds its observable pages into
+  // the outbox, and the next batch's fetch (or a flush) sends them.  Small
+  // batches and device stores, with no link time to hide, write them here.
+  const bool defer = m->obs_host && q >= kDeferMinBatch;
+  P.wa.direct = defer ? 0 : 1;
   {
-    TimedScope ts(m->timer, kkAccWriteback, st);
-    hipLaunchKernelGGL(k_acc_writeback<false>, dim3(3 * q), dim3(64), P.wb_lds, st, P.wa, none);
+    TimedScope ts(m->timer, kkAccCompose, st);
+    hipLaunchKernelGGL(k_acc_compose<false>, dim3(3 * q), dim3(64), P.wb_lds, st, P.wa, none);
   }
+  m->ship_q = defer ? q : 0;
   {
     TimedScope ts(m->timer, kkAccMisc, st);
     hipLaunchKernelGGL(k_acc_finish<false>, dim3((q + 255) / 256), dim3(256), 0, st, P.fn, none);
@@ -1507,6 +1662,7 @@ int run_access_many(bolt_map* const* maps, const bolt_batch* batches, uint32_t c
   bool any_fast = false, any_slow = false;
   for (uint32_t i = 0; i < count; ++i) {
     const bolt_batch& b = batches[i];
+    if (flush_ship(maps[i], st)) return BOLT_EHIP;
     plan_access(maps[i], b.d_ops, b.d_keys, b.d_vals_in, b.d_vals_out, b.d_status, b.q, st, plans[i]);
     qmax = b.q > qmax ? b.q : qmax;
     lds = plans[i].wb_lds > lds ? plans[i].wb_lds : lds;

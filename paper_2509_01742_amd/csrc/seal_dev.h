@@ -246,4 +246,19 @@ __device__ __forceinline__ void chacha_page_xor(uint64_t* page, uint32_t words, 
   }
 }
 
+// Seals one plain page held in this wave's LDS (every lane wrote its words
+// before the call): encrypts it in place under (page, write count), writes
+// the cipher text to dst and returns the tag to every lane.
+__device__ __forceinline__ void seal_page(uint64_t* pg, uint32_t words, const uint32_t key[8], uint32_t page,
+                                          uint64_t ver, uint64_t* dst, uint32_t tag[4]) {
+  const uint32_t lane = threadIdx.x & 63;
+  uint32_t ks[16], otk[8];
+  chacha_first_pass(key, page, (uint32_t)ver, (uint32_t)(ver >> 32), ks, otk);
+  wave_sync();
+  chacha_page_xor(pg, words, ks, key, page, (uint32_t)ver, (uint32_t)(ver >> 32));
+  wave_sync();
+  poly_page_tag(pg, words, otk, tag);
+  for (uint32_t w = lane; w < words; w += 64) dst[w] = pg[w];
+}
+
 }  // namespace bolt
