@@ -153,6 +153,7 @@ struct PlaceArgs {
   uint2* pm_pair;
   const uint32_t* pm_mask;
   uint32_t* rowsel;
+  const uint4* rows;  // [Q] position-map rows of each command's key (from the dedup kernel)
 };
 
 struct RemapArgs {
@@ -182,6 +183,7 @@ struct RemapArgs {
   uint64_t* pm_key;
   uint2* pm_pair;
   uint32_t* pm_mask;
+  const uint4* rows;  // [Q] position-map rows of each command's key
 };
 
 struct WbArgs {
@@ -423,6 +425,17 @@ __global__ __launch_bounds__(kDedupNT) void k_acc_group(GroupArgs a1, const Acce
   __shared__ uint32_t sidx[kMaxBatch];
   __shared__ uint32_t tot;
   const uint32_t part = blockIdx.x;
+  // every command's key and op code, loaded at once (one chunk of kDedupNT
+  // per register), in flight while the PRFs below are computed
+  constexpr uint32_t kChunks = kMaxBatch / kDedupNT;
+  uint64_t ckey[kChunks];
+  uint32_t cop[kChunks];
+#pragma unroll
+  for (uint32_t c = 0; c < kChunks; ++c) {
+    const uint32_t i = c * kDedupNT + threadIdx.x;
+    ckey[c] = i < qall ? keys[i] : 0;
+    cop[c] = i < qall ? ops[i] : 0;
+  }
   {  // PRF outputs of this block's slice, two PRFs per command
     const uint32_t cs = (qall + kParts - 1) / kParts;
     const uint32_t i = part * cs + (threadIdx.x >> 1);
@@ -451,14 +464,15 @@ __global__ __launch_bounds__(kDedupNT) void k_acc_group(GroupArgs a1, const Acce
   const uint32_t lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   uint32_t base = 0;
   bool bad = false;
-  for (uint32_t c0 = 0; c0 < qall; c0 += kDedupNT) {
+#pragma unroll
+  for (uint32_t c = 0; c < kChunks; ++c) {
+    const uint32_t c0 = c * kDedupNT;
+    if (c0 >= qall) break;  // the same for the whole block
     const uint32_t i = c0 + threadIdx.x;
-    uint64_t key = 0;
-    uint32_t op = 0;
+    const uint64_t key = ckey[c];
+    const uint32_t op = cop[c];
     bool mine = false;
     if (i < qall) {
-      key = keys[i];
-      op = ops[i];
       bad |= op > 2;
       mine = part_of(key) == part;
     }
@@ -484,40 +498,61 @@ __global__ __launch_bounds__(kDedupNT) void k_acc_group(GroupArgs a1, const Acce
   const uint32_t q = base;  // commands in this partition
   if (q == 0) return;       // whole block
   if (q <= kDedupNT) {
-    // One thread per command, in index order: every thread reads the
-    // partition's entries 0 .. q-1 in turn (the same LDS word across a wave,
-    // a broadcast), so the first entry of its key is its leader, the last
-    // PUT/DEL before it is its previous write, and for a leader the last
-    // PUT/DEL of the key in the whole batch is its last write.
-    const uint32_t j = threadIdx.x;
-    if ((j & ~63u) >= q) return;  // a wave with no command of the partition
-    const uint64_t key = j < q ? skey[j] : 0;
-    const uint32_t me = j < q ? sidx[j] >> 2 : 0;
-    uint32_t lead = kNone, pw = kNone, lw = kNone;
-    for (uint32_t e0 = 0; e0 < q; e0 += 8) {  // eight entries' loads in flight at once
-      uint64_t ke[8];
-      uint32_t pe[8];
+    // In index order, the first entry of a command's key is its leader, the
+    // last PUT/DEL before it its previous write, and for a leader the last
+    // PUT/DEL of the key in the whole batch its last write.  T threads
+    // share each command: thread (r, j) reads the partition's entries
+    // r*L .. r*L+L-1 in turn (the same LDS word across a wave, a broadcast),
+    // and thread (0, j) combines the T partial results in LDS.
+    __shared__ uint32_t part_f[kDedupNT], part_p[kDedupNT], part_l[kDedupNT];
+    const uint32_t qp = (q + 63) & ~63u;  // commands, in whole waves
+    const uint32_t T = kDedupNT / qp;     // 1 .. 16 threads per command
+    const uint32_t r = threadIdx.x / qp, j = threadIdx.x % qp;
+    const uint32_t L = (q + T - 1) / T;
+    const bool act = r < T && j < q;
+    const uint64_t key = act ? skey[j] : 0;
+    uint32_t f = kNone, pw = kNone, lw = kNone;
+    if (r < T && (j & ~63u) < q) {  // waves holding no command skip the scan
+      const uint32_t e_lo = r * L, e_hi = e_lo + L < q ? e_lo + L : q;
+      for (uint32_t e0 = e_lo; e0 < e_hi; e0 += 8) {  // eight entries' loads in flight at once
+        uint64_t ke[8];
+        uint32_t pe[8];
 #pragma unroll
-      for (uint32_t t = 0; t < 8; ++t) {
-        ke[t] = skey[e0 + t];  // entries past q (stale LDS) are masked below
-        pe[t] = sidx[e0 + t];
-      }
+        for (uint32_t t = 0; t < 8; ++t) {
+          ke[t] = skey[e0 + t];  // entries past e_hi (stale LDS) are masked below
+          pe[t] = sidx[e0 + t];
+        }
 #pragma unroll
-      for (uint32_t t = 0; t < 8; ++t) {
-        const uint32_t e = e0 + t;
-        if (e < q && ke[t] == key) {
-          if (e <= j && lead == kNone) lead = pe[t] >> 2;
-          if (pe[t] & 3u) {
-            lw = pe[t] >> 2;
-            if (e < j) pw = lw;
+        for (uint32_t t = 0; t < 8; ++t) {
+          const uint32_t e = e0 + t;
+          if (e < e_hi && ke[t] == key) {
+            if (f == kNone) f = pe[t] >> 2;
+            if (pe[t] & 3u) {
+              lw = pe[t] >> 2;
+              if (e < j) pw = lw;
+            }
           }
         }
       }
     }
-    if (j < q) {
+    if (act) {
+      part_f[threadIdx.x] = f;
+      part_p[threadIdx.x] = pw;
+      part_l[threadIdx.x] = lw;
+    }
+    __syncthreads();
+    if (r == 0 && j < q) {
+      uint32_t lead = kNone, pwc = kNone, lwc = kNone;
+      for (uint32_t rr = 0; rr < T; ++rr) {  // slices in entry order
+        const uint32_t at = rr * qp + j;
+        if (lead == kNone) lead = part_f[at];
+        if (part_p[at] != kNone) pwc = part_p[at];
+        if (part_l[at] != kNone) lwc = part_l[at];
+      }
+      const uint32_t me = sidx[j] >> 2;
       leader[me] = lead;
-      prevw[me] = pw;
-      if (lead == me) lastw[me] = lw;
+      prevw[me] = pwc;
+      if (lead == me) lastw[me] = lwc;
     }
     return;
   }
@@ -906,14 +941,11 @@ __global__ __launch_bounds__(256) void k_acc_place(PlaceArgs a1, const AccessPla
         a.pm_pair[(uint64_t)a.hrow[i] * a.W + a.hslot[i]] = a.rpair[i];
       } else {
         // insert: the least loaded of d rows after this batch's deletes
-        uint64_t g[4];
-        const uint32_t hk[8] = {a.ctl->hkey[0], a.ctl->hkey[1], a.ctl->hkey[2], a.ctl->hkey[3],
-                                a.ctl->hkey[4], a.ctl->hkey[5], a.ctl->hkey[6], a.ctl->hkey[7]};
-        prf4(hk, kDomRows, a.keys[i], g);
-        uint32_t best = (uint32_t)__umul64hi(g[0], a.R);
+        const uint4 rw = a.rows[i];
+        uint32_t best = rw.x;
         uint32_t bc = __popc(a.pm_mask[best]);
         for (uint32_t j = 1; j < a.d; ++j) {
-          const uint32_t r = (uint32_t)__umul64hi(g[j], a.R);
+          const uint32_t r = j == 1 ? rw.y : j == 2 ? rw.z : rw.w;
           const uint32_t c = __popc(a.pm_mask[r]);
           if (c < bc) {
             bc = c;
@@ -1025,19 +1057,16 @@ __global__ __launch_bounds__(kRemapNT) void k_acc_remap(RemapArgs a1, const Acce
   // their start; the least loaded of d rows, ties to the lowest choice
   const uint64_t rsm = (a.R + 15) / 16;
   uint32_t rowsel[kRemapPer];
-  const uint32_t hk0[8] = {a.ctl->hkey[0], a.ctl->hkey[1], a.ctl->hkey[2], a.ctl->hkey[3],
-                           a.ctl->hkey[4], a.ctl->hkey[5], a.ctl->hkey[6], a.ctl->hkey[7]};
   for (uint64_t r0 = 0; r0 < nins; r0 += rsm) {
     uint32_t io = ins0;
     for (uint32_t t = 0; t < kRemapPer; ++t) {
       if ((fin[t] & 3) != 1) continue;
       if (io >= r0 && io < r0 + rsm) {
-        uint64_t g[4];
-        prf4(hk0, kDomRows, a.keys[i0 + t], g);
-        uint32_t best = (uint32_t)__umul64hi(g[0], a.R);
+        const uint4 rw = a.rows[i0 + t];
+        uint32_t best = rw.x;
         uint32_t bc = __popc(ld_acq32(&a.pm_mask[best]));
         for (uint32_t j = 1; j < a.d; ++j) {
-          const uint32_t r = (uint32_t)__umul64hi(g[j], a.R);
+          const uint32_t r = j == 1 ? rw.y : j == 2 ? rw.z : rw.w;
           const uint32_t c = __popc(ld_acq32(&a.pm_mask[r]));
           if (c < bc) {
             bc = c;
@@ -1416,6 +1445,7 @@ static void plan_access(bolt_map* m, const uint8_t* ops, const uint64_t* keys, c
   pa.pm_pair = m->pm_pair;
   pa.pm_mask = m->pm_mask;
   pa.rowsel = bs.rowsel;
+  pa.rows = bs.rows;
 
   RemapArgs& ra = P.ra;
   ra.enabled = !P.fast;
@@ -1452,6 +1482,7 @@ static void plan_access(bolt_map* m, const uint8_t* ops, const uint64_t* keys, c
   ra.pm_key = m->pm_key;
   ra.pm_pair = m->pm_pair;
   ra.pm_mask = m->pm_mask;
+  ra.rows = bs.rows;
 
   WbArgs& wa = P.wa;
   wa.ctl = m->ctl;
