@@ -29,6 +29,8 @@
 
 #include <vector>
 
+#include <mutex>
+
 #include "bolt_impl.h"
 #include "seal_dev.h"
 
@@ -359,33 +361,39 @@ __device__ __forceinline__ void dedup_sort(uint64_t k[kDedupPer], uint32_t x[kDe
             x[e] = ox;
           }
         }
-      } else {
+      } else {  // positions past npad (no LDS for them) are padding, paired with padding
+        if (base < npad) {
 #pragma unroll
-        for (uint32_t e = 0; e < kDedupPer; ++e) {
-          skey[base + e] = k[e];
-          sidx[base + e] = x[e];
+          for (uint32_t e = 0; e < kDedupPer; ++e) {
+            skey[base + e] = k[e];
+            sidx[base + e] = x[e];
+          }
         }
         __syncthreads();
+        if (base < npad) {
 #pragma unroll
-        for (uint32_t e = 0; e < kDedupPer; ++e) {
-          const uint32_t p = base + e;
-          const uint64_t ok = skey[p ^ j];
-          const uint32_t ox = sidx[p ^ j];
-          const bool keep_min = ((p & j) == 0) == ((p & kk) == 0);
-          const bool take = keep_min ? kv_less(ok, ox, k[e], x[e]) : kv_less(k[e], x[e], ok, ox);
-          if (take) {
-            k[e] = ok;
-            x[e] = ox;
+          for (uint32_t e = 0; e < kDedupPer; ++e) {
+            const uint32_t p = base + e;
+            const uint64_t ok = skey[p ^ j];
+            const uint32_t ox = sidx[p ^ j];
+            const bool keep_min = ((p & j) == 0) == ((p & kk) == 0);
+            const bool take = keep_min ? kv_less(ok, ox, k[e], x[e]) : kv_less(k[e], x[e], ok, ox);
+            if (take) {
+              k[e] = ok;
+              x[e] = ox;
+            }
           }
         }
         __syncthreads();
       }
     }
   }
+  if (base < npad) {
 #pragma unroll
-  for (uint32_t e = 0; e < kDedupPer; ++e) {
-    skey[base + e] = k[e];
-    sidx[base + e] = x[e];
+    for (uint32_t e = 0; e < kDedupPer; ++e) {
+      skey[base + e] = k[e];
+      sidx[base + e] = x[e];
+    }
   }
   __syncthreads();
 }
@@ -395,23 +403,39 @@ __device__ __forceinline__ void dedup_sort(uint64_t k[kDedupPer], uint32_t x[kDe
 // sorted and folded by its own workgroup.
 constexpr uint32_t kParts = 64;
 
-__device__ __forceinline__ uint32_t part_of(uint64_t key) {
+__device__ __forceinline__ uint64_t key_mix(uint64_t key) {
   uint64_t x = key;
   x ^= x >> 33;
   x *= 0xFF51AFD7ED558CCDull;
   x ^= x >> 33;
-  return (uint32_t)(x >> 58);  // top 6 bits: kParts = 64
+  return x;
 }
+__device__ __forceinline__ uint32_t part_of(uint64_t key) { return (uint32_t)(key_mix(key) >> 58); }  // kParts = 64
 
-// One workgroup per partition (kParts of them).  First the workgroup
-// computes the PRF outputs of its slice of the commands (the batch split in
-// kParts equal slices, one PRF per thread): the fetch pair F(s) and remap
-// pair R(s) of tape step s, and the key's position-map rows.  Then it picks
-// the commands of its partition out of the whole batch (all commands of a
-// key land in one partition), sorts their (key, index) pairs, and derives
-// for each command its leader (first command of its key), the last PUT/DEL
-// of its key before it, and for each leader the last PUT/DEL of its key in
-// the batch.  A batch with an op code above DEL is marked rejected.
+// Slots of the LDS hash table that folds a partition of up to kDedupNT
+// commands (at most half full).
+constexpr uint32_t kHashSlots = 2 * kDedupNT;
+
+// Workgroups of the dedup kernel that compute PRFs (two per command).
+__host__ __device__ constexpr uint32_t group_prf_blocks(uint32_t q) { return (2 * q + kDedupNT - 1) / kDedupNT; }
+
+// Entries of the dedup kernel's partition arrays for a batch of q commands
+// (the sort of a large partition pads it to a power of two), and its bytes
+// of dynamic LDS.
+__host__ __device__ constexpr uint32_t group_lds_entries(uint32_t q) {
+  uint32_t n = 64;
+  while (n < q) n <<= 1;
+  return n;
+}
+__host__ __device__ constexpr uint64_t group_lds_bytes(uint32_t q) { return 12ull * group_lds_entries(q); }
+
+// One workgroup per partition (kParts of them), then group_prf_blocks(q)
+// workgroups for the PRF outputs, which run beside them.  A partition's
+// workgroup picks the commands of its partition out of the whole batch (all
+// commands of a key land in one partition) and derives for each command its
+// leader (first command of its key), the last PUT/DEL of its key before it,
+// and for each leader the last PUT/DEL of its key in the batch.  A batch
+// with an op code above DEL is marked rejected.
 template <bool MULTI>
 __global__ __launch_bounds__(kDedupNT) void k_acc_group(GroupArgs a1, const AccessPlan* tab) {
   BOLT_PICK(GroupArgs, gr);
@@ -421,12 +445,42 @@ __global__ __launch_bounds__(kDedupNT) void k_acc_group(GroupArgs a1, const Acce
   uint32_t* __restrict__ leader = a.leader;
   uint32_t* __restrict__ prevw = a.prevw;
   uint32_t* __restrict__ lastw = a.lastw;
-  __shared__ uint64_t skey[kMaxBatch];
-  __shared__ uint32_t sidx[kMaxBatch];
+  // the partition's (key, index << 2 | op) entries, in dynamic LDS sized for
+  // the whole batch (a partition may hold every command)
+  extern __shared__ uint64_t gdyn[];
+  uint64_t* const skey = gdyn;
+  uint32_t* const sidx = reinterpret_cast<uint32_t*>(gdyn + group_lds_entries(qall));
   __shared__ uint32_t tot;
   const uint32_t part = blockIdx.x;
-  // every command's key and op code, loaded at once (one chunk of kDedupNT
-  // per register), in flight while the PRFs below are computed
+  const uint32_t lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (part >= kParts) {
+    // The blocks past the partitions compute the PRF outputs, two per
+    // command (thread t: PRF t): the fetch pair F(s) and remap pair R(s) of
+    // tape step s, and the key's position-map rows.
+    const uint32_t t = (part - kParts) * kDedupNT + threadIdx.x;
+    const uint32_t i = t >> 1;
+    if (i >= qall) return;
+    uint32_t hk[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) hk[j] = a.ctl->hkey[j];
+    uint64_t w[4];
+    if ((t & 1) == 0) {
+      prf4(hk, kDomTape, a.ctl->steps + i, w);
+      uint32_t f1, f2, r1, r2;
+      pair_of(w[0], w[1], a.B, f1, f2);
+      pair_of(w[2], w[3], a.B, r1, r2);
+      a.fpair[i] = make_uint2(f1, f2);
+      a.rpair[i] = make_uint2(r1, r2);
+    } else {
+      prf4(hk, kDomRows, keys[i], w);
+      a.rows[i] = make_uint4((uint32_t)__umul64hi(w[0], a.R), (uint32_t)__umul64hi(w[1], a.R),
+                             (uint32_t)__umul64hi(w[2], a.R), (uint32_t)__umul64hi(w[3], a.R));
+    }
+    return;
+  }
+  // This partition's commands, gathered in index order: every command's key
+  // and op code loaded at once (one chunk of kDedupNT per register), a
+  // ballot per wave and chunk, then the (chunk, wave) counts' prefix.
   constexpr uint32_t kChunks = kMaxBatch / kDedupNT;
   uint64_t ckey[kChunks];
   uint32_t cop[kChunks];
@@ -436,123 +490,108 @@ __global__ __launch_bounds__(kDedupNT) void k_acc_group(GroupArgs a1, const Acce
     ckey[c] = i < qall ? keys[i] : 0;
     cop[c] = i < qall ? ops[i] : 0;
   }
-  {  // PRF outputs of this block's slice, two PRFs per command
-    const uint32_t cs = (qall + kParts - 1) / kParts;
-    const uint32_t i = part * cs + (threadIdx.x >> 1);
-    if ((threadIdx.x >> 1) < cs && i < qall) {
-      uint32_t hk[8];
-#pragma unroll
-      for (int j = 0; j < 8; ++j) hk[j] = a.ctl->hkey[j];
-      uint64_t w[4];
-      if ((threadIdx.x & 1) == 0) {
-        prf4(hk, kDomTape, a.ctl->steps + i, w);
-        uint32_t f1, f2, r1, r2;
-        pair_of(w[0], w[1], a.B, f1, f2);
-        pair_of(w[2], w[3], a.B, r1, r2);
-        a.fpair[i] = make_uint2(f1, f2);
-        a.rpair[i] = make_uint2(r1, r2);
-      } else {
-        prf4(hk, kDomRows, keys[i], w);
-        a.rows[i] = make_uint4((uint32_t)__umul64hi(w[0], a.R), (uint32_t)__umul64hi(w[1], a.R),
-                               (uint32_t)__umul64hi(w[2], a.R), (uint32_t)__umul64hi(w[3], a.R));
-      }
-    }
-  }
-  // this partition's commands, gathered in index order (1024 indexes per
-  // chunk: a ballot per wave, the wave counts' prefix per chunk)
-  __shared__ uint32_t wcnt[kDedupNT / 64];
-  const uint32_t lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  uint32_t base = 0;
+  __shared__ uint32_t wcnt[kChunks][kDedupNT / 64];
+  const uint32_t nch = (qall + kDedupNT - 1) / kDedupNT;
+  uint64_t bal[kChunks];
   bool bad = false;
 #pragma unroll
   for (uint32_t c = 0; c < kChunks; ++c) {
-    const uint32_t c0 = c * kDedupNT;
-    if (c0 >= qall) break;  // the same for the whole block
-    const uint32_t i = c0 + threadIdx.x;
-    const uint64_t key = ckey[c];
-    const uint32_t op = cop[c];
-    bool mine = false;
-    if (i < qall) {
-      bad |= op > 2;
-      mine = part_of(key) == part;
-    }
-    const uint64_t bal = __ballot(mine);
-    if (lane == 0) wcnt[wid] = (uint32_t)__popcll(bal);
-    __syncthreads();
+    const uint32_t i = c * kDedupNT + threadIdx.x;
+    const bool mine = i < qall && part_of(ckey[c]) == part;
+    bad |= i < qall && cop[c] > 2;
+    bal[c] = __ballot(mine);
+    if (lane == 0) wcnt[c][wid] = (uint32_t)__popcll(bal[c]);
+  }
+  __syncthreads();
+  uint32_t base = 0;
+#pragma unroll
+  for (uint32_t c = 0; c < kChunks; ++c) {
+    if (c >= nch) break;  // the same for the whole block
     uint32_t off = base, all = 0;
 #pragma unroll
     for (uint32_t w = 0; w < kDedupNT / 64; ++w) {
-      const uint32_t c = wcnt[w];
-      off += w < wid ? c : 0;
-      all += c;
+      const uint32_t n = wcnt[c][w];
+      off += w < wid ? n : 0;
+      all += n;
     }
-    if (mine) {
-      const uint32_t at = off + (uint32_t)__popcll(bal & ((1ull << lane) - 1));
-      skey[at] = key;
-      sidx[at] = (i << 2) | (op & 3u);  // ordering by this payload is ordering by index
+    if ((bal[c] >> lane) & 1) {
+      const uint32_t at = off + (uint32_t)__popcll(bal[c] & ((1ull << lane) - 1));
+      skey[at] = ckey[c];
+      sidx[at] = ((c * kDedupNT + threadIdx.x) << 2) | (cop[c] & 3u);  // ordering by this is ordering by index
     }
     base += all;
-    __syncthreads();  // wcnt is rewritten by the next chunk
   }
+  __syncthreads();
   if (__any(bad) && lane == 0) a.ctl->reject = a.epoch;  // the same value from every writer
   const uint32_t q = base;  // commands in this partition
   if (q == 0) return;       // whole block
   if (q <= kDedupNT) {
-    // In index order, the first entry of a command's key is its leader, the
-    // last PUT/DEL before it its previous write, and for a leader the last
-    // PUT/DEL of the key in the whole batch its last write.  T threads
-    // share each command: thread (r, j) reads the partition's entries
-    // r*L .. r*L+L-1 in turn (the same LDS word across a wave, a broadcast),
-    // and thread (0, j) combines the T partial results in LDS.
-    __shared__ uint32_t part_f[kDedupNT], part_p[kDedupNT], part_l[kDedupNT];
-    const uint32_t qp = (q + 63) & ~63u;  // commands, in whole waves
-    const uint32_t T = kDedupNT / qp;     // 1 .. 16 threads per command
-    const uint32_t r = threadIdx.x / qp, j = threadIdx.x % qp;
-    const uint32_t L = (q + T - 1) / T;
-    const bool act = r < T && j < q;
-    const uint64_t key = act ? skey[j] : 0;
-    uint32_t f = kNone, pw = kNone, lw = kNone;
-    if (r < T && (j & ~63u) < q) {  // waves holding no command skip the scan
-      const uint32_t e_lo = r * L, e_hi = e_lo + L < q ? e_lo + L : q;
-      for (uint32_t e0 = e_lo; e0 < e_hi; e0 += 8) {  // eight entries' loads in flight at once
-        uint64_t ke[8];
-        uint32_t pe[8];
-#pragma unroll
-        for (uint32_t t = 0; t < 8; ++t) {
-          ke[t] = skey[e0 + t];  // entries past e_hi (stale LDS) are masked below
-          pe[t] = sidx[e0 + t];
-        }
-#pragma unroll
-        for (uint32_t t = 0; t < 8; ++t) {
-          const uint32_t e = e0 + t;
-          if (e < e_hi && ke[t] == key) {
-            if (f == kNone) f = pe[t] >> 2;
-            if (pe[t] & 3u) {
-              lw = pe[t] >> 2;
-              if (e < j) pw = lw;
-            }
-          }
-        }
-      }
-    }
-    if (act) {
-      part_f[threadIdx.x] = f;
-      part_p[threadIdx.x] = pw;
-      part_l[threadIdx.x] = lw;
+    // One thread per command, in index order (position e).  The keys go to
+    // the slots of an LDS hash table (a slot holds the position of one of
+    // its key's commands), which gives each key its first command (the
+    // leader of all of them) and its last PUT/DEL (the leader's last
+    // write).  A command's previous write is the last PUT/DEL of its key
+    // before it: within its wave from the ballot of the lanes sharing its
+    // slot, else from the waves before it, swept in order.
+    __shared__ uint32_t htab[kHashSlots];   // position + 1 of a command of the slot's key, 0 = empty
+    __shared__ uint32_t hfirst[kHashSlots];  // first position of the slot's key
+    __shared__ uint32_t hlast[kHashSlots];   // last PUT/DEL position + 1, 0 = none
+    __shared__ uint32_t hrun[kHashSlots];    // the sweep: last PUT/DEL position + 1 in the waves so far
+    for (uint32_t t = threadIdx.x; t < kHashSlots; t += kDedupNT) {
+      htab[t] = 0;
+      hfirst[t] = kNone;
+      hlast[t] = 0;
+      hrun[t] = 0;
     }
     __syncthreads();
-    if (r == 0 && j < q) {
-      uint32_t lead = kNone, pwc = kNone, lwc = kNone;
-      for (uint32_t rr = 0; rr < T; ++rr) {  // slices in entry order
-        const uint32_t at = rr * qp + j;
-        if (lead == kNone) lead = part_f[at];
-        if (part_p[at] != kNone) pwc = part_p[at];
-        if (part_l[at] != kNone) lwc = part_l[at];
+    const uint32_t e = threadIdx.x;
+    const bool real = e < q;
+    const uint64_t key = real ? skey[e] : 0;
+    const uint32_t pe = real ? sidx[e] : 0;
+    const bool isw = real && (pe & 3u);
+    uint32_t slot = kNone;
+    if (real) {
+      // at most q <= kDedupNT < kHashSlots keys: every probe sequence ends
+      uint32_t h = (uint32_t)key_mix(key) & (kHashSlots - 1);
+      for (uint32_t probe = 0; probe < kHashSlots; ++probe) {
+        const uint32_t prev = atomicCAS(&htab[h], 0u, e + 1);
+        if (prev == 0 || skey[prev - 1] == key) {
+          slot = h;
+          break;
+        }
+        h = (h + 1) & (kHashSlots - 1);
       }
-      const uint32_t me = sidx[j] >> 2;
-      leader[me] = lead;
-      prevw[me] = pwc;
-      if (lead == me) lastw[me] = lwc;
+      atomicMin(&hfirst[slot], e);
+      if (isw) atomicMax(&hlast[slot], e + 1);
+    }
+    // lanes of this wave holding the same key, one round per distinct key
+    uint64_t peers = 0;
+    for (uint64_t todo = __ballot(real); todo;) {
+      const uint32_t src = (uint32_t)__builtin_ctzll(todo);
+      const uint32_t ss = (uint32_t)__builtin_amdgcn_readlane((int)slot, (int)src);
+      const bool same = real && slot == ss;
+      const uint64_t m = __ballot(same);
+      if (same) peers = m;
+      todo &= ~m;
+    }
+    const uint64_t kw = peers & __ballot(isw);  // this key's PUT/DELs in the wave
+    const uint64_t below = kw & ((1ull << lane) - 1);
+    uint32_t pwp = below ? (e - lane) + (63 - (uint32_t)__builtin_clzll(below)) + 1 : 0;  // position + 1
+    const bool wave_last_w = isw && (kw >> lane) == 1;  // no later PUT/DEL of the key in the wave
+    const uint32_t nw = (q + 63) / 64;
+    for (uint32_t w = 0; w < nw; ++w) {
+      if (wid == w && real) {
+        if (!pwp) pwp = hrun[slot];
+        if (wave_last_w) hrun[slot] = e + 1;  // after every lane's read: the wave's LDS ops are in order
+      }
+      __syncthreads();
+    }
+    if (real) {
+      const uint32_t me = pe >> 2;
+      const uint32_t f = hfirst[slot];
+      leader[me] = sidx[f] >> 2;
+      prevw[me] = pwp ? sidx[pwp - 1] >> 2 : kNone;
+      if (f == e) lastw[me] = hlast[slot] ? sidx[hlast[slot] - 1] >> 2 : kNone;
     }
     return;
   }
@@ -1568,9 +1607,13 @@ __global__ __launch_bounds__(1024) void k_acc_watch(const uint32_t* __restrict__
 
 // The access pipeline for up to qmax commands of the maps of a device plan
 // table (count of them), every phase one launch.
+static void allow_group_lds();
+
 static void launch_many(const AccessPlan& p0, const AccessPlan* tab, uint32_t C, uint32_t qmax, uint64_t lds,
                         uint64_t fetch_lds, bool any_fast, bool any_slow, hipStream_t st) {
-  hipLaunchKernelGGL(k_acc_group<true>, dim3(kParts, C), dim3(kDedupNT), 0, st, p0.gr, tab);
+  allow_group_lds();
+  hipLaunchKernelGGL(k_acc_group<true>, dim3(kParts + group_prf_blocks(qmax), C), dim3(kDedupNT),
+                     group_lds_bytes(qmax), st, p0.gr, tab);
   if (fetch_lds)  // a sealed map among them
     hipLaunchKernelGGL((k_acc_fetch<true, true>), dim3((qmax + 3) / 4, C), dim3(256), fetch_lds, st, p0.fa, tab);
   else
@@ -1580,6 +1623,18 @@ static void launch_many(const AccessPlan& p0, const AccessPlan* tab, uint32_t C,
   if (any_slow) hipLaunchKernelGGL(k_acc_remap<true>, dim3(1, C), dim3(kRemapNT), 0, st, p0.ra, tab);
   hipLaunchKernelGGL(k_acc_compose<true>, dim3(3 * qmax, C), dim3(64), lds, st, p0.wa, tab);
   hipLaunchKernelGGL(k_acc_finish<true>, dim3((qmax + 255) / 256, C), dim3(256), 0, st, p0.fn, tab);
+}
+
+// The dedup kernel's dynamic LDS reaches 96 KiB for the largest batches.
+static void allow_group_lds() {
+  static std::once_flag once;
+  std::call_once(once, [] {
+    const int bytes = (int)group_lds_bytes(kMaxBatch);
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_acc_group<false>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_acc_group<true>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  });
 }
 
 // Smallest batch whose observable pages are sent during the next batch.
@@ -1637,9 +1692,11 @@ int run_access(bolt_map* m, const uint8_t* ops, const uint64_t* keys, const void
     return rc;
   }
   const AccessPlan* none = nullptr;
+  allow_group_lds();
   {
     TimedScope ts(m->timer, kkAccDedup, st);
-    hipLaunchKernelGGL(k_acc_group<false>, dim3(kParts), dim3(kDedupNT), 0, st, P.gr, none);
+    hipLaunchKernelGGL(k_acc_group<false>, dim3(kParts + group_prf_blocks(q)), dim3(kDedupNT), group_lds_bytes(q), st,
+                       P.gr, none);
   }
   // The fetch's first workgroups send the previous batch's rebuilt pages
   // (device-to-host over the link while the fetch reads host-to-device).
