@@ -143,7 +143,8 @@ struct bolt_map {
   // fetch takes such a page from the outbox (it still reads the store's
   // copy, for the same trace).
   uint64_t* wslot;  // [M]
-  uint32_t ship_q;  // commands of the batch whose pages are still to be sent, 0 = none
+  uint32_t ship_q;     // commands of the batch whose pages are still to be sent, 0 = none
+  uint32_t ship_from;  // its outbox slots [ship_from, 2 ship_q) are still to be sent
   bool ov_off;        // next batch: no outbox pages (the store was changed from the host)
 };
 

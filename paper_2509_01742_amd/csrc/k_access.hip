@@ -36,6 +36,18 @@
 
 namespace bolt {
 
+// The send of a batch's rebuilt observable pages to the store.
+struct ShipArgs {
+  const Ctl* ctl;
+  uint32_t lo, hi;  // the slots [lo, hi) of the batch's outbox
+  uint64_t pw;
+  const uint32_t* ship_page;
+  const uint64_t* outbox;
+  uint64_t* obs;
+  uint64_t* tags;  // BOLT_F_SEAL: [M][2] page tags, else null
+  uint64_t* pver;  // BOLT_F_SEAL: [M] page write counts
+};
+
 struct GroupArgs {
   const uint8_t* ops;
   const uint64_t* keys;
@@ -48,19 +60,10 @@ struct GroupArgs {
   uint2* fpair;
   uint2* rpair;
   uint4* rows;
+  ShipArgs ship;  // a slice of the previous batch's send, by the first ship_blocks workgroups
+  uint32_t ship_blocks;
 };
 
-// The send of a batch's rebuilt observable pages to the store.
-struct ShipArgs {
-  const Ctl* ctl;
-  uint32_t q;
-  uint64_t pw;
-  const uint32_t* ship_page;
-  const uint64_t* outbox;
-  uint64_t* obs;
-  uint64_t* tags;  // BOLT_F_SEAL: [M][2] page tags, else null
-  uint64_t* pver;  // BOLT_F_SEAL: [M] page write counts
-};
 
 struct FetchArgs {
   const Ctl* ctl;
@@ -101,7 +104,7 @@ struct FetchArgs {
   const uint64_t* wslot;   // [M] last rebuild of each page: epoch << 32 | outbox slot
   const uint64_t* outbox;  // [2Q][pw] the previous batch's rebuilt pages
   uint32_t ov_epoch;       // epoch whose rebuilt pages the outbox holds, 0 = none
-  ShipArgs ship;           // the previous batch's send (ship.q = 0: none) ...
+  ShipArgs ship;           // a slice of the previous batch's send ...
   uint32_t ship_blocks;    // ... by the first ship_blocks workgroups
 };
 
@@ -125,6 +128,8 @@ struct ResolveArgs {
   uint32_t* fin;
   uint32_t* chosen;
   uint32_t* pm_mask;
+  ShipArgs ship;  // a slice of the previous batch's send, by the first ship_blocks workgroups
+  uint32_t ship_blocks;
 };
 
 struct PlaceArgs {
@@ -156,6 +161,8 @@ struct PlaceArgs {
   const uint32_t* pm_mask;
   uint32_t* rowsel;
   const uint4* rows;  // [Q] position-map rows of each command's key (from the dedup kernel)
+  ShipArgs ship;  // a slice of the previous batch's send, by the first ship_blocks workgroups
+  uint32_t ship_blocks;
 };
 
 struct RemapArgs {
@@ -226,6 +233,8 @@ struct FinishArgs {
   uint64_t* pm_key;
   uint2* pm_pair;
   uint32_t* pm_mask;
+  ShipArgs ship;  // a slice of the previous batch's send, by the first ship_blocks workgroups
+  uint32_t ship_blocks;
 };
 
 // Every kernel argument of one map's batch.  A multi-map launch reads the
@@ -451,7 +460,8 @@ __global__ __launch_bounds__(kDedupNT) void k_acc_group(GroupArgs a1, const Acce
   uint64_t* const skey = gdyn;
   uint32_t* const sidx = reinterpret_cast<uint32_t*>(gdyn + group_lds_entries(qall));
   __shared__ uint32_t tot;
-  const uint32_t part = blockIdx.x;
+  if (carry_ship<MULTI>(a.ship, a.ship_blocks)) return;
+  const uint32_t part = blockIdx.x - (MULTI ? 0 : a.ship_blocks);
   const uint32_t lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   if (part >= kParts) {
     // The blocks past the partitions compute the PRF outputs, two per
@@ -653,22 +663,23 @@ __global__ __launch_bounds__(kDedupNT) void k_acc_group(GroupArgs a1, const Acce
 // ---------------------------------------------------------------------------
 
 // The send of a batch's rebuilt observable pages to the store: wave `wave`
-// of `waves` takes fetch slots wave, wave + waves, ...  Plain maps copy the
+// of `waves` takes the slots lo + wave, lo + wave + waves, ... below hi.  Plain maps copy the
 // page; sealed maps encrypt it in the wave's LDS page `pg` under the page's
 // next write count, tag it, and write page and tag.
+template <bool SEALED>
 __device__ __forceinline__ void ship_slots(const ShipArgs& a, uint32_t wave, uint32_t waves, uint64_t* pg) {
   const uint32_t lane = threadIdx.x & 63;
   uint32_t key[8];
-  if (a.tags) {
+  if (SEALED) {
 #pragma unroll
     for (int j = 0; j < 8; ++j) key[j] = a.ctl->skey[j];
   }
-  for (uint32_t s = wave; s < 2 * a.q; s += waves) {
+  for (uint32_t s = a.lo + wave; s < a.hi; s += waves) {
     const uint32_t page = a.ship_page[s];
     if (page == kNone) continue;  // whole wave
     const uint64_t* src = a.outbox + (uint64_t)s * a.pw;
     uint64_t* dst = a.obs + (uint64_t)page * a.pw;
-    if (!a.tags) {
+    if (!SEALED) {
       for (uint64_t w = lane; w < a.pw; w += 64) dst[w] = src[w];
       continue;
     }
@@ -685,18 +696,31 @@ __device__ __forceinline__ void ship_slots(const ShipArgs& a, uint32_t wave, uin
   }
 }
 
-// Workgroups (of 4 waves) of a send: one per 8 commands, at most 256, so
-// that the fetch it rides with keeps most of the device.
+// Workgroups (of 4 waves) of a send of n slots: one per 4 slots, at most
+// 256, so that the kernel it rides with keeps most of the device.
 constexpr uint32_t kShipMaxBlocks = 256;
-__host__ __device__ constexpr uint32_t ship_blocks_for(uint32_t q) {
-  return q == 0 ? 0 : ((2 * q + 3) / 4 < kShipMaxBlocks ? (2 * q + 3) / 4 : kShipMaxBlocks);
+__host__ __device__ constexpr uint32_t ship_blocks_for(uint32_t n) {
+  return (n + 3) / 4 < kShipMaxBlocks ? (n + 3) / 4 : kShipMaxBlocks;
+}
+
+// Workgroups [0, ship_blocks) of a kernel that carries a slice of a send
+// (plain maps only: no LDS) do that and nothing else; true for them.
+template <bool MULTI>
+__device__ __forceinline__ bool carry_ship(const ShipArgs& sh, uint32_t ship_blocks) {
+  if (MULTI || blockIdx.x >= ship_blocks) return false;
+  const uint32_t wpb = blockDim.x >> 6;  // waves per workgroup
+  ship_slots<false>(sh, blockIdx.x * wpb + (threadIdx.x >> 6), ship_blocks * wpb, nullptr);
+  return true;
 }
 
 // A send on its own (bolt_flush, readers of the store, many-map calls).
 __global__ __launch_bounds__(256) void k_acc_ship(ShipArgs a) {
   extern __shared__ uint64_t sdyn[];
   const uint32_t wv = threadIdx.x >> 6;
-  ship_slots(a, blockIdx.x * 4 + wv, gridDim.x * 4, sdyn + (uint64_t)wv * a.pw);
+  if (a.tags)
+    ship_slots<true>(a, blockIdx.x * 4 + wv, gridDim.x * 4, sdyn + (uint64_t)wv * a.pw);
+  else
+    ship_slots<false>(a, blockIdx.x * 4 + wv, gridDim.x * 4, nullptr);
 }
 
 // ---------------------------------------------------------------------------
@@ -711,8 +735,8 @@ __global__ __launch_bounds__(256) void k_acc_fetch(FetchArgs a1, const AccessPla
   extern __shared__ uint64_t fdyn[];
   const uint32_t lane = threadIdx.x & 63;
   if (!MULTI && blockIdx.x < a.ship_blocks) {  // the previous batch's send
-    ship_slots(a.ship, blockIdx.x * 4 + (threadIdx.x >> 6), a.ship_blocks * 4,
-               fdyn + (uint64_t)(threadIdx.x >> 6) * a.pw);
+    ship_slots<SEALED>(a.ship, blockIdx.x * 4 + (threadIdx.x >> 6), a.ship_blocks * 4,
+                       fdyn + (uint64_t)(threadIdx.x >> 6) * a.pw);
     return;
   }
   const uint32_t i = (blockIdx.x - (MULTI ? 0 : a.ship_blocks)) * 4 + (threadIdx.x >> 6);
@@ -884,7 +908,8 @@ __device__ __forceinline__ bool pm_claim(uint32_t* pm_mask, uint64_t* pm_key, ui
 template <bool MULTI>
 __global__ __launch_bounds__(256) void k_acc_resolve(ResolveArgs a1, const AccessPlan* tab) {
   BOLT_PICK(ResolveArgs, rv);
-  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (carry_ship<MULTI>(a.ship, a.ship_blocks)) return;
+  const uint32_t i = (blockIdx.x - (MULTI ? 0 : a.ship_blocks)) * blockDim.x + threadIdx.x;
   const bool live = i < a.q;
   if (a.ctl->reject == a.epoch || a.ctl->err) {
     if (live) {
@@ -955,8 +980,9 @@ __device__ __forceinline__ bool stash_put(uint64_t* st_used, uint64_t PW, uint64
 template <bool MULTI>
 __global__ __launch_bounds__(256) void k_acc_place(PlaceArgs a1, const AccessPlan* tab) {
   BOLT_PICK(PlaceArgs, pa);
+  if (carry_ship<MULTI>(a.ship, a.ship_blocks)) return;
   if (!a.enabled) return;
-  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t i = (blockIdx.x - (MULTI ? 0 : a.ship_blocks)) * blockDim.x + threadIdx.x;
   if (a.ctl->reject == a.epoch || a.ctl->err) return;
   bool placed = false, ins = false;
   if (i < a.q) {
@@ -1287,14 +1313,16 @@ __global__ __launch_bounds__(64) void k_acc_compose(WbArgs a1, const AccessPlan*
 template <bool MULTI>
 __global__ __launch_bounds__(256) void k_acc_finish(FinishArgs a1, const AccessPlan* tab) {
   BOLT_PICK(FinishArgs, fn);
-  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (carry_ship<MULTI>(a.ship, a.ship_blocks)) return;
+  const uint32_t bid = blockIdx.x - (MULTI ? 0 : a.ship_blocks);
+  const uint32_t i = bid * blockDim.x + threadIdx.x;
   if (a.ctl->reject == a.epoch) return;
   const bool ok = !a.ctl->err;
   if (ok && i < a.q && a.rowsel && a.rowsel[i] != kNone) {
     if (!pm_claim(a.pm_mask, a.pm_key, a.pm_pair, a.rowsel[i], a.W, a.keys[i], a.rpair[i]))
       set_err(a.ctl, kErrOverflow);
   }
-  if (blockIdx.x != 0) return;
+  if (bid != 0) return;
   __shared__ uint32_t part[kFreeBuckets];
   part[threadIdx.x] = a.freed[threadIdx.x];
   a.freed[threadIdx.x] = 0;  // ready for the next batch
@@ -1329,11 +1357,12 @@ __global__ void k_fill_u32(uint32_t* p, uint64_t n, uint32_t v) {
 
 // ---------------------------------------------------------------------------
 
-// The send of the map's last `q` rebuilt slots.
-static ShipArgs ship_args(bolt_map* m, uint32_t q) {
+// The send of the outbox slots [lo, hi) of the map's last batch.
+static ShipArgs ship_args(bolt_map* m, uint32_t lo, uint32_t hi) {
   ShipArgs a;
   a.ctl = m->ctl;
-  a.q = q;
+  a.lo = lo;
+  a.hi = hi;
   a.pw = m->s.page_bytes / 8;
   a.ship_page = m->bs.ship_page;
   a.outbox = reinterpret_cast<const uint64_t*>(m->bs.outbox);
@@ -1422,11 +1451,15 @@ static void plan_access(bolt_map* m, const uint8_t* ops, const uint64_t* keys, c
   fa.outbox = reinterpret_cast<const uint64_t*>(bs.outbox);
   fa.ov_epoch = m->ov_off ? 0 : epoch - 1;
   m->ov_off = false;
-  fa.ship = ship_args(m, 0);  // run_access hands the previous batch's send to its fetch
+  fa.ship = ship_args(m, 0, 0);  // run_access hands slices of the previous batch's send to its kernels
   fa.ship_blocks = 0;
+  P.gr.ship = fa.ship;
+  P.gr.ship_blocks = 0;
 
   ResolveArgs& rv = P.rv;
   rv.ctl = m->ctl;
+  rv.ship = ship_args(m, 0, 0);
+  rv.ship_blocks = 0;
   rv.ops = ops;
   rv.vals_in = vin;
   rv.leader = bs.leader;
@@ -1452,6 +1485,8 @@ static void plan_access(bolt_map* m, const uint8_t* ops, const uint64_t* keys, c
   PlaceArgs& pa = P.pa;
   pa.enabled = P.fast;
   pa.ctl = m->ctl;
+  pa.ship = ship_args(m, 0, 0);
+  pa.ship_blocks = 0;
   pa.keys = keys;
   pa.vals_in = vin;
   pa.leader = bs.leader;
@@ -1555,6 +1590,8 @@ static void plan_access(bolt_map* m, const uint8_t* ops, const uint64_t* keys, c
 
   FinishArgs& fn = P.fn;
   fn.ctl = m->ctl;
+  fn.ship = ship_args(m, 0, 0);
+  fn.ship_blocks = 0;
   fn.q = q;
   fn.W = (uint32_t)s.W;
   fn.epoch = epoch;
@@ -1640,14 +1677,24 @@ static void allow_group_lds() {
 // Smallest batch whose observable pages are sent during the next batch.
 constexpr uint32_t kDeferMinBatch = 256;
 
+// Shares (in 64ths of a batch's outbox slots) of the send carried by the
+// batch's own finish and by the next batch's dedup, resolve and place
+// kernels: about what each writes over the link while it runs anyway
+// (4096-command batches, 1 KiB pages).  The next fetch carries the rest.
+// Sealed maps send from the fetch only (the send needs LDS there).
+constexpr uint32_t kShareFinish = 1, kShareGroup = 4, kShareResolve = 2, kSharePlace = 4;
+
 int flush_ship(bolt_map* m, hipStream_t st) {
   if (!m->ship_q) return BOLT_OK;
-  const ShipArgs a = ship_args(m, m->ship_q);
+  const ShipArgs a = ship_args(m, m->ship_from, 2 * m->ship_q);
+  m->ship_q = 0;
+  m->ship_from = 0;
+  if (a.lo >= a.hi) return BOLT_OK;
   {
     TimedScope ts(m->timer, kkAccShip, st);
-    hipLaunchKernelGGL(k_acc_ship, dim3(ship_blocks_for(a.q)), dim3(256), m->tags ? 4 * m->s.page_bytes : 0, st, a);
+    hipLaunchKernelGGL(k_acc_ship, dim3(ship_blocks_for(a.hi - a.lo)), dim3(256), m->tags ? 4 * m->s.page_bytes : 0, st,
+                       a);
   }
-  m->ship_q = 0;
   return hipGetLastError() == hipSuccess ? BOLT_OK : BOLT_EHIP;
 }
 
@@ -1693,16 +1740,35 @@ int run_access(bolt_map* m, const uint8_t* ops, const uint64_t* keys, const void
   }
   const AccessPlan* none = nullptr;
   allow_group_lds();
+  // The previous batch's rebuilt pages still to be sent, in slices: plain
+  // maps spread them over this batch's dedup, resolve and place kernels
+  // (each running anyway), the fetch takes the rest (writes over the link
+  // while it reads).
+  {
+    const uint32_t end = 2 * m->ship_q;
+    uint32_t lo = m->ship_from < end ? m->ship_from : end;
+    auto take = [&](uint32_t share, ShipArgs& a, uint32_t& blocks, uint32_t waves_per_block) {
+      const uint32_t n = end * share / 64, hi = lo + n < end ? lo + n : end;
+      a = ship_args(m, lo, hi);
+      blocks = (hi - lo + waves_per_block - 1) / waves_per_block;
+      if (blocks > kShipMaxBlocks / (waves_per_block / 4)) blocks = kShipMaxBlocks / (waves_per_block / 4);
+      lo = hi;
+    };
+    if (end && !m->tags) {
+      take(kShareGroup, P.gr.ship, P.gr.ship_blocks, kDedupNT / 64);
+      take(kShareResolve, P.rv.ship, P.rv.ship_blocks, 4);
+      if (P.fast) take(kSharePlace, P.pa.ship, P.pa.ship_blocks, 4);
+    }
+    P.fa.ship = ship_args(m, lo, end);
+    P.fa.ship_blocks = ship_blocks_for(end - lo);
+    m->ship_q = 0;
+    m->ship_from = 0;
+  }
   {
     TimedScope ts(m->timer, kkAccDedup, st);
-    hipLaunchKernelGGL(k_acc_group<false>, dim3(kParts + group_prf_blocks(q)), dim3(kDedupNT), group_lds_bytes(q), st,
-                       P.gr, none);
+    hipLaunchKernelGGL(k_acc_group<false>, dim3(P.gr.ship_blocks + kParts + group_prf_blocks(q)), dim3(kDedupNT),
+                       group_lds_bytes(q), st, P.gr, none);
   }
-  // The fetch's first workgroups send the previous batch's rebuilt pages
-  // (device-to-host over the link while the fetch reads host-to-device).
-  P.fa.ship.q = m->ship_q;
-  P.fa.ship_blocks = ship_blocks_for(m->ship_q);
-  m->ship_q = 0;
   {
     TimedScope ts(m->timer, kkAccFetch, st);
     const dim3 grid(P.fa.ship_blocks + (q + 3) / 4);
@@ -1713,12 +1779,12 @@ int run_access(bolt_map* m, const uint8_t* ops, const uint64_t* keys, const void
   }
   {
     TimedScope ts(m->timer, kkAccResolve, st);
-    hipLaunchKernelGGL(k_acc_resolve<false>, dim3((q + 255) / 256), dim3(256), 0, st, P.rv, none);
+    hipLaunchKernelGGL(k_acc_resolve<false>, dim3(P.rv.ship_blocks + (q + 255) / 256), dim3(256), 0, st, P.rv, none);
   }
   {
     TimedScope ts(m->timer, kkAccRemap, st);
     if (P.fast)
-      hipLaunchKernelGGL(k_acc_place<false>, dim3((q + 255) / 256), dim3(256), 0, st, P.pa, none);
+      hipLaunchKernelGGL(k_acc_place<false>, dim3(P.pa.ship_blocks + (q + 255) / 256), dim3(256), 0, st, P.pa, none);
     else
       hipLaunchKernelGGL(k_acc_remap<false>, dim3(1), dim3(kRemapNT), 0, st, P.ra, none);
   }
@@ -1732,9 +1798,16 @@ int run_access(bolt_map* m, const uint8_t* ops, const uint64_t* keys, const void
     hipLaunchKernelGGL(k_acc_compose<false>, dim3(3 * q), dim3(64), P.wb_lds, st, P.wa, none);
   }
   m->ship_q = defer ? q : 0;
+  m->ship_from = 0;
+  if (defer && !m->tags) {  // the finish starts this batch's send
+    const uint32_t hi = 2 * q * kShareFinish / 64;
+    P.fn.ship = ship_args(m, 0, hi);
+    P.fn.ship_blocks = ship_blocks_for(hi);
+    m->ship_from = hi;
+  }
   {
     TimedScope ts(m->timer, kkAccMisc, st);
-    hipLaunchKernelGGL(k_acc_finish<false>, dim3((q + 255) / 256), dim3(256), 0, st, P.fn, none);
+    hipLaunchKernelGGL(k_acc_finish<false>, dim3(P.fn.ship_blocks + (q + 255) / 256), dim3(256), 0, st, P.fn, none);
   }
   if (m->p.flags & BOLT_F_WATCH)
     hipLaunchKernelGGL(k_acc_watch, dim3(1), dim3(1024), 0, st, m->load, m->s.B, m->s.K, m->ctl);
