@@ -255,6 +255,7 @@ def main():
     ap.add_argument("--graphs", action="store_true", help="maps replay captured graphs per batch-size class")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default network schedules")
     ap.add_argument("--no-seal", action="store_true", help="skip the sealed-store figures")
+    ap.add_argument("--no-build-heavy", action="store_true", help="skip the N=2^26 build figures (config 3)")
     ap.add_argument("--dynamics", type=int, default=0, metavar="ACCESSES",
                     help="instead of the benchmark: the bound validation of Sec. 4.3 over this many accesses per "
                          "configuration (the paper uses 10^9)")
@@ -343,6 +344,10 @@ def main():
     if not args.no_multi:
         multi = run_multi(B, torch)
         log("multi-map: %s" % json.dumps(multi))
+    heavy = None
+    if not args.no_build_heavy:
+        heavy = run_build_heavy(B, torch, synth, not args.no_autotune)
+        log("build-heavy: %s" % json.dumps({k: v for k, v in heavy.items() if k != "phases"}))
     cpu = None if args.no_cpu_baseline else cpu_baseline(args.cpu_batches)
     sz = main_res["sizes"]
     out = {
@@ -374,10 +379,98 @@ def main():
         "autotune": tuned,
         "sealed": sealed,
         "multi_map": multi,
+        "build_heavy": heavy,
         "serving": serving,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
+
+
+def run_build_heavy(B, torch, synth, autotune):
+    """Config 3: build of N=2^26 keys with 8-byte values on the pinned store
+    (each build on a fresh map, best of two), its phases from an
+    instrumented build (algorithmic GB/s, the sort passes against HBM peak),
+    then 2^16 uniform GETs in batches of 4096, every answer checked against
+    the build input."""
+    t0 = time.time()
+    wl = synth.config3()
+    dev = torch.device("cuda:0")
+    keys = torch.from_numpy(wl.build_keys.view(np.int64)).to(dev)
+    vals = torch.from_numpy(wl.build_vals).to(dev)
+    log("build-heavy workload %s: n=%d (%.1fs)" % (wl.name, wl.n, time.time() - t0))
+    if autotune:
+        B.check(B.autotune(1 << 27), "bolt_autotune")  # sort class 2^26, expansion class 2^27
+    p = B.params(wl.cap, wl.vs)
+    sz = B.sizes_of(p)
+    sz["vs"] = wl.vs
+    sz["host"] = True
+    npad = 1
+    while npad < wl.n:
+        npad <<= 1
+    ms = []
+    m = None
+    for rep in range(2):
+        if m is not None:
+            m.close()
+        m = B.Map(p)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        B.check(m.build(keys, vals), "bolt_build")
+        e1.record()
+        torch.cuda.synchronize()
+        B.check(m.status(), "build status")
+        ms.append(e0.elapsed_time(e1))
+    # 2^16 uniform GETs, checked against the input
+    order = np.argsort(wl.build_keys)
+    sk, sv = wl.build_keys[order], wl.build_vals[order]
+    got, evs = [], [torch.cuda.Event(enable_timing=True) for _ in range(len(wl.batches) + 1)]
+    evs[0].record()
+    for bi, (ops, qk, qv) in enumerate(wl.batches):
+        q = ops.size
+        out = torch.zeros((q, wl.vs), dtype=torch.uint8, device=dev)
+        st = torch.zeros(q, dtype=torch.uint8, device=dev)
+        B.check(m.access(torch.from_numpy(ops).to(dev), torch.from_numpy(qk.view(np.int64)).to(dev),
+                         torch.from_numpy(qv).to(dev), out, st), "bolt_access_batch")
+        evs[bi + 1].record()
+        got.append((out, st))
+    torch.cuda.synchronize()
+    B.check(m.status(), "get status")
+    n_get = sum(b[0].size for b in wl.batches)
+    get_ms = evs[0].elapsed_time(evs[-1])
+    for (ops, qk, _), (out, st) in zip(wl.batches, got):
+        j = np.searchsorted(sk, qk)
+        if not (st.cpu().numpy() == 1).all() or not np.array_equal(out.cpu().numpy(), sv[j]):
+            raise SystemExit("build-heavy GET answers differ from the build input")
+    m.close()
+    # phases of one instrumented build
+    pt = B.params(wl.cap, wl.vs)
+    pt.flags |= B.BOLT_F_TIMING
+    tm = B.Map(pt)
+    B.check(tm.build(keys, vals), "bolt_build (timed phases)")
+    torch.cuda.synchronize()
+    B.check(tm.status(), "timed build status")
+    phases = {}
+    for cls, (cnt, tot) in sorted(tm.kernel_times().items(), key=lambda kv: -kv[1][1]):
+        if cnt == 0 or cls.startswith("acc"):
+            continue
+        ent = {"launches": cnt, "total_ms": round(tot, 3), "avg_us": round(1e3 * tot / cnt, 2)}
+        per, bound = kernel_bytes(cls, sz, wl.n, npad, 0, 0)
+        if per is not None:
+            gbs = per / (tot / cnt / 1e3) / 1e9
+            ent.update({"bytes_per_launch": int(per), "achieved_GBps": round(gbs, 1), "bound": bound,
+                        "frac_of_peak": round(gbs / PEAKS[bound], 4)})
+        phases[cls] = ent
+    tm.close()
+    best = min(ms)
+    return {"workload": "%s: build of N=2^26 keys with 8-byte values (capacity 2^26), pinned host store; then "
+                        "2^16 uniform GETs of present keys in batches of 4096, every answer checked" % wl.name,
+            "n": wl.n, "Z": sz["Z"], "page_bytes": sz["page_bytes"], "B": sz["B"], "M": sz["M"],
+            "build_ms": round(best, 3), "build_keys_per_s": round(wl.n / (best / 1e3), 1),
+            "builds_ms": [round(x, 3) for x in ms],
+            "get_ops_per_s": round(n_get / (get_ms / 1e3), 1), "gets_checked": n_get,
+            "phases": phases,
+            "sort_pass_frac_of_hbm_peak": phases.get("sort_global", {}).get("frac_of_peak")}
 
 
 def run_multi(B, torch, reps=3):
