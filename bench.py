@@ -198,7 +198,7 @@ PROFILED = {
     "acc_ship": ("bolt::k_acc_ship", ("k_access.hip", "seal_dev.h", "bolt_dev.h", "bolt_impl.h")),
     "acc_compose": ("bolt::k_acc_compose<false>", ("k_access.hip", "seal_dev.h", "bolt_dev.h", "bolt_impl.h")),
     "acc_fetch": ("bolt::k_acc_fetch<false, false>", ("k_access.hip", "seal_dev.h", "bolt_dev.h", "bolt_impl.h")),
-    "sort_global": ("bolt::k_bitonic_global<4, false>", ("k_prim.hip", "bolt_dev.h", "bolt_impl.h")),
+    "sort_global": ("bolt::k_bitonic_global<*, false>", ("k_prim.hip", "bolt_dev.h", "bolt_impl.h")),
     "sort_merge": ("bolt::k_bitonic_tile<false>", ("k_prim.hip", "bolt_dev.h", "bolt_impl.h")),
     "page_writeout": ("bolt::k_writeout<false>", ("k_build.hip", "seal_dev.h", "bolt_dev.h", "bolt_impl.h")),
 }
@@ -219,11 +219,18 @@ def measured_traffic(cls, mode):
         src = os.path.join(ROOT, "paper_2509_01742_amd", "csrc", fn)
         if hashlib.sha256(open(src, "rb").read()).hexdigest()[:16] != prof["sources"].get(fn):
             return None
-    k = prof["modes"].get(mode, {}).get("kernels", {}).get(ent[0])
+    kern = prof["modes"].get(mode, {}).get("kernels", {})
+    if "*" in ent[0]:  # a kernel with several instantiations: the one launched most
+        head, tail = ent[0].split("*")
+        names = [nm for nm in kern if nm.startswith(head) and nm.endswith(tail)]
+        name = max(names, key=lambda nm: kern[nm]["launches"]) if names else None
+    else:
+        name = ent[0]
+    k = kern.get(name) if name else None
     if k is None:
         return None
     return {"fetch_bytes": round(k["fetch_bytes"]), "write_bytes": round(k["write_bytes"]),
-            "bytes": round(k["fetch_bytes"] + k["write_bytes"]), "kernel": ent[0], "grid": k["grid"],
+            "bytes": round(k["fetch_bytes"] + k["write_bytes"]), "kernel": name, "grid": k["grid"],
             "source": "profiles/traffic_plain_omap_n24_v64.md"}
 
 

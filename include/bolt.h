@@ -410,7 +410,7 @@ int bolt_server_destroy(bolt_server* srv);
 typedef struct {
   uint32_t log2_n;             /* the length class */
   uint32_t sort_tile_log;      /* 11..13 */
-  uint32_t sort_pass_strides;  /* 1..4 */
+  uint32_t sort_pass_strides;  /* 1..6 */
   uint32_t expand_pass_stages; /* 1..4 */
   float sort_ms, expand_ms;    /* measured time of the chosen schedules */
 } bolt_tune_entry;

@@ -402,7 +402,7 @@ __global__ __launch_bounds__(256) void k_bitonic_global(uint64_t* __restrict__ a
 // One sort schedule for one array (segs == nullptr) or for `count` arrays
 // of the device table `segs` whose longest has length nmax: tiles of
 // 2^tile_log elements (11..13; 13 runs in registers), then up to fmax
-// strides per global pass.  Every choice sorts the same way.
+// (1..6) strides per global pass.  Every choice sorts the same way.
 template <bool MULTI>
 static void sort_schedule(uint64_t* a, uint64_t nmax, const NetSeg* segs, uint32_t count, hipStream_t st,
                           KernelTimer* tm, uint32_t tile_log, uint32_t fmax) {
@@ -426,7 +426,9 @@ static void sort_schedule(uint64_t* a, uint64_t nmax, const NetSeg* segs, uint32
         case 1: hipLaunchKernelGGL((k_bitonic_global<1, MULTI>), grid, block, 0, st, a, nmax, k_log, (uint32_t)jl, segs); break;
         case 2: hipLaunchKernelGGL((k_bitonic_global<2, MULTI>), grid, block, 0, st, a, nmax, k_log, (uint32_t)jl, segs); break;
         case 3: hipLaunchKernelGGL((k_bitonic_global<3, MULTI>), grid, block, 0, st, a, nmax, k_log, (uint32_t)jl, segs); break;
-        default: hipLaunchKernelGGL((k_bitonic_global<4, MULTI>), grid, block, 0, st, a, nmax, k_log, (uint32_t)jl, segs); break;
+        case 4: hipLaunchKernelGGL((k_bitonic_global<4, MULTI>), grid, block, 0, st, a, nmax, k_log, (uint32_t)jl, segs); break;
+        case 5: hipLaunchKernelGGL((k_bitonic_global<5, MULTI>), grid, block, 0, st, a, nmax, k_log, (uint32_t)jl, segs); break;
+        default: hipLaunchKernelGGL((k_bitonic_global<6, MULTI>), grid, block, 0, st, a, nmax, k_log, (uint32_t)jl, segs); break;
       }
       jl -= F;
     }

@@ -22,6 +22,8 @@ constexpr int kMaxDev = 16;
 constexpr uint32_t kMaxLog = 40;
 constexpr uint32_t kTuneMinLog = 14;  // shorter arrays keep the defaults
 constexpr uint32_t kTuneMaxLog = 28;
+constexpr uint32_t kSortFMax = 6;  // strides per global sort pass: 1..6
+constexpr uint32_t kExpFMax = 4;   // stages per global expansion pass: 1..4
 
 struct Entry {
   NetTune t{13, 4, 4};
@@ -73,7 +75,7 @@ bool load_cache(const char* path, int dev) {
     float sm, em;
     const int r = fscanf(f, "%u %u %u %u %f %f\n", &L, &tl, &fs, &fe, &sm, &em);
     if (r == EOF) break;
-    if (r != 6 || L > kMaxLog || tl < 11 || tl > 13 || fs < 1 || fs > 4 || fe < 1 || fe > 4) {
+    if (r != 6 || L > kMaxLog || tl < 11 || tl > 13 || fs < 1 || fs > kSortFMax || fe < 1 || fe > kExpFMax) {
       ok = false;
       break;
     }
@@ -146,11 +148,11 @@ int tune(uint64_t n_max, hipStream_t st, int dev) {
     const uint64_t n = 1ull << L;
     const int reps = L >= 24 ? 2 : 3;
     Entry best;
-    // sort: tile 2^11..2^13, 1..4 strides per global pass
+    // sort: tile 2^11..2^13, 1..kSortFMax strides per global pass
     hipLaunchKernelGGL(k_tune_fill, dim3((uint32_t)((n + 255) / 256)), dim3(256), 0, st, src, n, 0u);
     float bs = 1e30f;
     for (uint32_t tl = 11; tl <= 13; ++tl)
-      for (uint32_t f = 1; f <= 4; ++f) {
+      for (uint32_t f = 1; f <= kSortFMax; ++f) {
         const float ms = time_best(st, e0, e1, a, src, n, reps, [&] { launch_bitonic_sort_with(a, n, st, tl, f); });
         if (ms < 0) rc = BOLT_EHIP;
         if (ms >= 0 && ms < bs) {
@@ -159,10 +161,10 @@ int tune(uint64_t n_max, hipStream_t st, int dev) {
           best.t.sort_fmax = f;
         }
       }
-    // expansion: 1..4 stages per global pass
+    // expansion: 1..kExpFMax stages per global pass
     hipLaunchKernelGGL(k_tune_fill, dim3((uint32_t)((n + 255) / 256)), dim3(256), 0, st, src, n, 1u);
     float be = 1e30f;
-    for (uint32_t f = 1; f <= 4; ++f) {
+    for (uint32_t f = 1; f <= kExpFMax; ++f) {
       const float ms = time_best(st, e0, e1, a, src, n, reps, [&] { (void)launch_expand_with(a, b, n, st, f); });
       if (ms < 0) rc = BOLT_EHIP;
       if (ms >= 0 && ms < be) {
@@ -231,7 +233,7 @@ int bolt_tune_set(const bolt_tune_entry* in, uint32_t n) {
   for (uint32_t i = 0; i < n; ++i) {
     const bolt_tune_entry& e = in[i];
     if (e.log2_n > kMaxLog || e.sort_tile_log < 11 || e.sort_tile_log > 13 || e.sort_pass_strides < 1 ||
-        e.sort_pass_strides > 4 || e.expand_pass_stages < 1 || e.expand_pass_stages > 4)
+        e.sort_pass_strides > kSortFMax || e.expand_pass_stages < 1 || e.expand_pass_stages > kExpFMax)
       return BOLT_EINVAL;
   }
   const int dev = cur_dev();

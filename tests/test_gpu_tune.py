@@ -62,8 +62,9 @@ def test_every_schedule_is_the_same_network(L):
 
     n = 1 << L
     for tile in (11, 12, 13):
-        for f in (1, 2, 3, 4):
-            assert B.tune_set([dict(log2_n=L, sort_tile_log=tile, sort_pass_strides=f, expand_pass_stages=f)]) == 0
+        for f in (1, 2, 3, 4, 5, 6):
+            assert B.tune_set([dict(log2_n=L, sort_tile_log=tile, sort_pass_strides=f,
+                                    expand_pass_stages=min(f, 4))]) == 0
             _check_sort(B, n, 100 * tile + f)
             _check_expand(B, n - 5, 10 * f + L)  # class 2^L, ragged length
     assert B.bolt_tune_reset() == 0
@@ -81,7 +82,7 @@ def test_autotune_cache_and_tuned_build(tmp_path):
     t1 = B.tune_table()
     assert [e["log2_n"] for e in t1] == [14, 15, 16, 17]
     for e in t1:
-        assert 11 <= e["sort_tile_log"] <= 13 and 1 <= e["sort_pass_strides"] <= 4
+        assert 11 <= e["sort_tile_log"] <= 13 and 1 <= e["sort_pass_strides"] <= 6
         assert 1 <= e["expand_pass_stages"] <= 4 and e["sort_ms"] > 0 and e["expand_ms"] > 0
     assert os.path.getsize(path) > 0
     assert B.bolt_tune_reset() == 0 and B.tune_table() == []
