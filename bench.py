@@ -263,6 +263,7 @@ def main():
     ap.add_argument("--no-autotune", action="store_true", help="keep the default network schedules")
     ap.add_argument("--no-seal", action="store_true", help="skip the sealed-store figures")
     ap.add_argument("--no-build-heavy", action="store_true", help="skip the N=2^26 build figures (config 3)")
+    ap.add_argument("--no-alpha-sweep", action="store_true", help="skip the alpha sweep of the pinned store")
     ap.add_argument("--dynamics", type=int, default=0, metavar="ACCESSES",
                     help="instead of the benchmark: the bound validation of Sec. 4.3 over this many accesses per "
                          "configuration (the paper uses 10^9)")
@@ -351,6 +352,9 @@ def main():
     if not args.no_multi:
         multi = run_multi(B, torch)
         log("multi-map: %s" % json.dumps(multi))
+    sweep = None
+    if not args.no_alpha_sweep and args.observable == "host":
+        sweep = run_alpha_sweep(B, torch, wl, dev_t)
     heavy = None
     if not args.no_build_heavy:
         heavy = run_build_heavy(B, torch, synth, not args.no_autotune)
@@ -387,10 +391,49 @@ def main():
         "sealed": sealed,
         "multi_map": multi,
         "build_heavy": heavy,
+        "alpha_sweep": sweep,
         "serving": serving,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
+
+
+def run_alpha_sweep(B, torch, wl, dev_t, nb_max=64, alphas=(10, 200, 500, 800)):
+    """The paper's alpha sweep (Sec. 6, small and large HBM variants): the
+    headline workload on the pinned store with alpha = K / (K + M) of 1 %,
+    20 %, 50 % and 80 %; each a build plus the first nb_max batches of 4096
+    commands, timed on the launch stream (best of two maps)."""
+    d_keys, d_vals, d_ops, d_qk, d_qv, d_out, d_st, bounds = dev_t
+    nb = min(nb_max, len(bounds) - 1)
+    n_ops = int(bounds[nb])
+    out = []
+    for apm in alphas:
+        p = B.params(wl.cap, wl.vs, alpha_permille=apm)
+        sz = B.sizes_of(p)
+        best = None
+        for _ in range(2):
+            m = B.Map(p)
+            torch.cuda.synchronize()
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+            ev[0].record()
+            B.check(m.build(d_keys, d_vals), "bolt_build")
+            ev[1].record()
+            for bi in range(nb):
+                a, b = int(bounds[bi]), int(bounds[bi + 1])
+                B.check(m.access(d_ops[a:b], d_qk[a:b], d_qv[a:b], d_out[a:b], d_st[a:b]), "bolt_access_batch")
+            B.check(m.flush(), "bolt_flush")
+            ev[2].record()
+            torch.cuda.synchronize()
+            B.check(m.status(), "alpha sweep status")
+            m.close()
+            r = (ev[0].elapsed_time(ev[1]), ev[1].elapsed_time(ev[2]))
+            best = r if best is None or r[1] < best[1] else best
+        out.append({"alpha": apm / 1000, "K": sz["K"], "M": sz["M"], "build_keys_per_s": round(wl.n / (best[0] / 1e3), 1),
+                    "ops_per_s": round(n_ops / (best[1] / 1e3), 1),
+                    "page_bytes_read_per_op": round(2 * sz["page_bytes"] * sz["M"] / sz["B"], 1)})
+        log("alpha %.2f: %s" % (apm / 1000, json.dumps(out[-1])))
+    return {"workload": "%s on the pinned store: build, then %d commands in batches of 4096" % (wl.name, n_ops),
+            "points": out}
 
 
 def run_build_heavy(B, torch, synth, autotune):
