@@ -145,15 +145,16 @@ def run_mode(args, wl, dev_t, B, torch, observable, seal=False):
     # plain per-call form: one command per call, on the last map
     m = maps[-1]
     kpc = min(args.per_call, int(bounds[-1]))
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(kpc + 1)]
-    ev[0].record(stream)
-    for i in range(kpc):
-        B.check(m.access(d_ops[i:i + 1], d_qk[i:i + 1], d_qv[i:i + 1], d_out[i:i + 1], d_st[i:i + 1]), "per-call")
-        ev[i + 1].record(stream)
-    torch.cuda.synchronize()
-    pc_lat = [ev[i].elapsed_time(ev[i + 1]) for i in range(kpc)]
-    pc_ops = kpc / (ev[0].elapsed_time(ev[-1]) / 1e3)
-    B.check(m.status(), "status")
+    if kpc:
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(kpc + 1)]
+        ev[0].record(stream)
+        for i in range(kpc):
+            B.check(m.access(d_ops[i:i + 1], d_qk[i:i + 1], d_qv[i:i + 1], d_out[i:i + 1], d_st[i:i + 1]), "per-call")
+            ev[i + 1].record(stream)
+        torch.cuda.synchronize()
+        pc_lat = [ev[i].elapsed_time(ev[i + 1]) for i in range(kpc)]
+        pc_ops = kpc / (ev[0].elapsed_time(ev[-1]) / 1e3)
+        B.check(m.status(), "status")
     for mm in maps:
         mm.close()
 
@@ -186,7 +187,7 @@ def run_mode(args, wl, dev_t, B, torch, observable, seal=False):
         "lat_p50": float(np.percentile(lat_np, 50)),
         "lat_p99": float(np.percentile(lat_np, 99)),
         "per_call": {"ops_per_s": round(pc_ops, 1), "p50_ms": round(float(np.percentile(pc_lat, 50)), 4),
-                     "p99_ms": round(float(np.percentile(pc_lat, 99)), 4), "calls": kpc},
+                     "p99_ms": round(float(np.percentile(pc_lat, 99)), 4), "calls": kpc} if kpc else None,
         "kernels": kernels,
         "sizes": sz,
         "stats": st,
@@ -325,7 +326,7 @@ def main():
         other = {"observable": other_mode, "ops_per_s": round(o["ops_per_s"], 1),
                  "build_keys_per_s": round(o["build_keys_per_s"], 1),
                  "batch_latency_ms": {"p50": round(o["lat_p50"], 4), "p99": round(o["lat_p99"], 4)},
-                 "per_call_ops_per_s": o["per_call"]["ops_per_s"], "kernels": o["kernels"]}
+                 "per_call_ops_per_s": (o["per_call"] or {}).get("ops_per_s"), "kernels": o["kernels"]}
 
     # the dominant kernel of the headline step (by device time), and the
     # HBM-bound sort pass of the build
