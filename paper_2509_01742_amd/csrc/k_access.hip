@@ -106,6 +106,7 @@ struct FetchArgs {
   uint32_t ov_epoch;       // epoch whose rebuilt pages the outbox holds, 0 = none
   ShipArgs ship;           // a slice of the previous batch's send ...
   uint32_t ship_blocks;    // ... by the first ship_blocks workgroups
+  uint32_t pre_host;       // 1: observable pages are read ahead too (device store)
 };
 
 struct ResolveArgs {
@@ -772,8 +773,33 @@ __global__ __launch_bounds__(256) void k_acc_fetch(FetchArgs a1, const AccessPla
       p2 = pp.y;
     }
   }
-  // value access (Sec. 5.1 step 4): both bins, whole
+  // value access (Sec. 5.1 step 4): both bins, whole.  Plain maps issue
+  // both bins' first page words, stash lists and outbox marks at once
+  // (nothing they read changes during the fetch, but pages the previous
+  // batch rebuilt, which come from the outbox below).  A pinned host
+  // store's pages are read at their turn instead: twice the reads in
+  // flight crowd out the link's other direction, which carries the send.
+  uint64_t pre0[2] = {0, 0}, pre1[2] = {0, 0}, pws[2] = {0, 0};
+  uint32_t pcnt[2] = {0, 0}, pidx[2] = {kNone, kNone};
+  if (!SEALED) {
+#pragma unroll
+    for (uint32_t r = 0; r < 2; ++r) {
+      const uint32_t b = r ? p2 : p1;
+      const bool host = b >= a.K;
+      const uint64_t* src = host ? a.obs + (uint64_t)(b - a.K) * a.pw : a.hbm + (uint64_t)b * a.pw;
+      if (!host || a.pre_host) {
+        pre0[r] = lane < a.pw ? src[lane] : 0;
+        pre1[r] = lane + 64 < a.pw ? src[lane + 64] : 0;
+      }
+      if (host) {
+        pcnt[r] = a.rev_cnt[b];
+        pidx[r] = lane < 2 * a.Z ? a.rev_idx[(uint64_t)b * 2 * a.Z + lane] : kNone;
+        if (a.ov_epoch) pws[r] = a.wslot[b - a.K];
+      }
+    }
+  }
   bool found = false;
+#pragma unroll
   for (uint32_t role = 0; role < 2; ++role) {
     const uint32_t b = role ? p2 : p1;
     const uint32_t slot = 2 * i + role;
@@ -787,7 +813,7 @@ __global__ __launch_bounds__(256) void k_acc_fetch(FetchArgs a1, const AccessPla
     uint64_t* stg = a.stage + (uint64_t)slot * a.pw;
     bool fresh = false;  // rebuilt by the previous batch, whose send may still run
     if (host && a.ov_epoch) {
-      const uint64_t ws = a.wslot[b - a.K];
+      const uint64_t ws = SEALED ? a.wslot[b - a.K] : pws[role];
       if ((uint32_t)(ws >> 32) == a.ov_epoch) {
         // The store's copy is read all the same (the trace does not change),
         // but the page itself comes from the outbox.
@@ -821,7 +847,8 @@ __global__ __launch_bounds__(256) void k_acc_fetch(FetchArgs a1, const AccessPla
       wave_sync();
       src = pg;
     }
-    const uint64_t v0 = lane < a.pw ? src[lane] : 0;
+    const bool pre = !SEALED && !fresh && (!host || a.pre_host);  // the page words loaded above are the page's
+    const uint64_t v0 = pre ? pre0[role] : (lane < a.pw ? src[lane] : 0);
     if (host && lane < a.pw) stg[lane] = v0;
     // find the key among the page's slots (lanes 1..Z hold the keys)
     const bool search = is_leader && hit && !found;
@@ -835,7 +862,7 @@ __global__ __launch_bounds__(256) void k_acc_fetch(FetchArgs a1, const AccessPla
     const uint64_t vlo = 1 + a.Z + (uint64_t)(fslot < 0 ? 0 : fslot) * a.vw;
     if (fslot >= 0 && lane >= vlo && lane < vlo + a.vw) a.fval[(uint64_t)i * a.vw + (lane - vlo)] = v0;
     for (uint64_t wi = lane + 64; wi < a.pw; wi += 64) {
-      const uint64_t v = src[wi];
+      const uint64_t v = (pre && wi < 128) ? pre1[role] : src[wi];
       if (host) stg[wi] = v;
       if (fslot >= 0 && wi >= vlo && wi < vlo + a.vw) a.fval[(uint64_t)i * a.vw + (wi - vlo)] = v;
     }
@@ -847,14 +874,15 @@ __global__ __launch_bounds__(256) void k_acc_fetch(FetchArgs a1, const AccessPla
       }
     } else if (search && host) {
       // the stash items listed for this bin
-      const uint32_t cnt = a.rev_cnt[b] < 2 * a.Z ? a.rev_cnt[b] : 2 * a.Z;
+      const uint32_t cnt_raw = SEALED ? a.rev_cnt[b] : pcnt[role];
+      const uint32_t cnt = cnt_raw < 2 * a.Z ? cnt_raw : 2 * a.Z;
       int fe = -1;
       for (uint32_t base = 0; base < cnt; base += 64) {
         const uint32_t l = base + lane;
         uint32_t e = kNone;
         bool m = false;
         if (l < cnt) {
-          e = a.rev_idx[(uint64_t)b * 2 * a.Z + l];
+          e = (!SEALED && base == 0) ? pidx[role] : a.rev_idx[(uint64_t)b * 2 * a.Z + l];
           m = !a.st_dead[e] && a.st_key[e] == key;
         }
         const uint64_t bal = __ballot(m);
@@ -1193,16 +1221,22 @@ __global__ __launch_bounds__(64) void k_acc_compose(WbArgs a1, const AccessPlan*
   if (lane == 0 && s < 2 * a.q) a.ship_page[s] = kNone;
   if (s >= 3 * a.q || a.ctl->reject == a.epoch || a.ctl->err) return;  // whole block
   const uint32_t b = a.cand_bin[s];
-  if (b == kNone || a.claim[b] != claim_tag(a.epoch, s)) return;  // whole block
+  if (b == kNone) return;  // whole block
   const bool host = b >= a.K;
   if (host && s >= 2 * a.q) {  // observable bins are only claimed by fetch slots
     if (lane == 0) set_err(a.ctl, kErrBroken);
     return;
   }
+  // The election's outcome and the bin's data are loaded together (a slot
+  // that lost the election drops what it read).
+  const uint64_t cl = a.claim[b];
   const uint64_t* src = host ? a.stage + (uint64_t)s * a.pw : a.hbm + (uint64_t)b * a.pw;
   for (uint64_t w = lane; w < a.pw; w += 64) old[w] = src[w];
   const uint64_t rm = a.rmask[b];
-  const uint32_t cnt = a.rev_cnt[b] < 2 * a.Z ? a.rev_cnt[b] : 2 * a.Z;
+  const uint32_t cnt_raw = a.rev_cnt[b];
+  const uint32_t e_spec = lane < 2 * a.Z ? a.rev_idx[(uint64_t)b * 2 * a.Z + lane] : kNone;  // the bin's list row
+  if (cl != claim_tag(a.epoch, s)) return;  // whole block
+  const uint32_t cnt = cnt_raw < 2 * a.Z ? cnt_raw : 2 * a.Z;
   __syncthreads();
   const uint64_t keep = old[0] & ~rm;
   // survivors, in slot order
@@ -1219,7 +1253,7 @@ __global__ __launch_bounds__(64) void k_acc_compose(WbArgs a1, const AccessPlan*
     uint32_t e = kNone;
     bool alive = false;
     if (l < cnt) {
-      e = a.rev_idx[(uint64_t)b * 2 * a.Z + l];
+      e = base == 0 ? e_spec : a.rev_idx[(uint64_t)b * 2 * a.Z + l];
       alive = !a.st_dead[e];
     }
     const uint64_t bal = __ballot(alive);
@@ -1451,6 +1485,7 @@ static void plan_access(bolt_map* m, const uint8_t* ops, const uint64_t* keys, c
   fa.outbox = reinterpret_cast<const uint64_t*>(bs.outbox);
   fa.ov_epoch = m->ov_off ? 0 : epoch - 1;
   m->ov_off = false;
+  fa.pre_host = m->obs_host ? 0 : 1;
   fa.ship = ship_args(m, 0, 0);  // run_access hands slices of the previous batch's send to its kernels
   fa.ship_blocks = 0;
   P.gr.ship = fa.ship;
