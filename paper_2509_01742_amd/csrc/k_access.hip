@@ -1016,21 +1016,21 @@ __global__ __launch_bounds__(256) void k_acc_place(PlaceArgs a1, const AccessPla
   if (i < a.q) {
     a.cand_bin[2 * a.q + i] = kNone;
     a.rowsel[i] = kNone;
-    if (a.leader[i] == i && (a.fin[i] & 1)) {
+    const uint32_t fin = a.leader[i] == i ? a.fin[i] : 0;
+    if (fin & 1) {
+      // Every atomic and load that does not wait on another is issued
+      // first; the capacity checks come last (a failure poisons the map,
+      // whose state is then never read again).
       const uint32_t b = a.chosen[i];
-      const uint32_t old = atomicAdd(&a.load[b], 1u);
-      if (old + 1 > a.Z) set_err(a.ctl, kErrOverflow);
       const uint32_t lw = a.lastw[i];
-      const uint64_t* src = lw != kNone ? a.vals_in + (uint64_t)lw * a.vw : a.fval + (uint64_t)i * a.vw;
-      if (!stash_put(a.st_used, a.PW, a.st_key, a.st_val, a.st_dest, a.st_dead, a.rev_cnt, a.rev_idx, a.Z, a.vw,
-                     a.epoch, i, a.keys[i], src, b))
-        set_err(a.ctl, kErrOverflow);
-      placed = true;
+      const uint64_t key = a.keys[i];
+      const uint32_t old = atomicAdd(&a.load[b], 1u);
+      const uint32_t ls = atomicAdd(&a.rev_cnt[b], 1u);
       if (b < a.K) {  // HBM bins are rebuilt in this batch
         a.cand_bin[2 * a.q + i] = b;
         atomicMax((unsigned long long*)&a.claim[b], (unsigned long long)claim_tag(a.epoch, 2 * a.q + i));
       }
-      if (a.fin[i] & 2) {
+      if (fin & 2) {
         a.pm_pair[(uint64_t)a.hrow[i] * a.W + a.hslot[i]] = a.rpair[i];
       } else {
         // insert: the least loaded of d rows after this batch's deletes
@@ -1048,6 +1048,18 @@ __global__ __launch_bounds__(256) void k_acc_place(PlaceArgs a1, const AccessPla
         a.rowsel[i] = best;
         ins = true;
       }
+      // the item goes to a fresh stash entry listed under bin b
+      const uint32_t e = pool_alloc(a.st_used, a.PW, alloc_hash(a.epoch, i), (uint32_t)a.PW);
+      const uint64_t* src = lw != kNone ? a.vals_in + (uint64_t)lw * a.vw : a.fval + (uint64_t)i * a.vw;
+      if (e != kNone) {
+        a.st_key[e] = key;
+        for (uint32_t x = 0; x < a.vw; ++x) a.st_val[(uint64_t)e * a.vw + x] = src[x];
+        a.st_dest[e] = b;
+        a.st_dead[e] = 0;
+        if (ls < 2 * a.Z) a.rev_idx[(uint64_t)b * 2 * a.Z + ls] = e;
+      }
+      if (old + 1 > a.Z || e == kNone || ls >= 2 * a.Z) set_err(a.ctl, kErrOverflow);
+      placed = true;
     }
   }
   wave_count(&a.ctl->b_place, placed);
