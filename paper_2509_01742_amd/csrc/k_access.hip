@@ -426,8 +426,11 @@ __device__ __forceinline__ uint32_t part_of(uint64_t key) { return (uint32_t)(ke
 // commands (at most half full).
 constexpr uint32_t kHashSlots = 2 * kDedupNT;
 
-// Workgroups of the dedup kernel that compute PRFs (two per command).
-__host__ __device__ constexpr uint32_t group_prf_blocks(uint32_t q) { return (2 * q + kDedupNT - 1) / kDedupNT; }
+// Workgroups of the dedup kernel that compute PRFs, two per command: 256
+// threads of each (one wave per SIMD: a PRF is a long run of dependent
+// integer operations, and waves sharing a SIMD would queue behind each other).
+constexpr uint32_t kPrfPerBlock = 256;
+__host__ __device__ constexpr uint32_t group_prf_blocks(uint32_t q) { return (2 * q + kPrfPerBlock - 1) / kPrfPerBlock; }
 
 // Entries of the dedup kernel's partition arrays for a batch of q commands
 // (the sort of a large partition pads it to a power of two), and its bytes
@@ -468,7 +471,8 @@ __global__ __launch_bounds__(kDedupNT) void k_acc_group(GroupArgs a1, const Acce
     // The blocks past the partitions compute the PRF outputs, two per
     // command (thread t: PRF t): the fetch pair F(s) and remap pair R(s) of
     // tape step s, and the key's position-map rows.
-    const uint32_t t = (part - kParts) * kDedupNT + threadIdx.x;
+    if (threadIdx.x >= kPrfPerBlock) return;
+    const uint32_t t = (part - kParts) * kPrfPerBlock + threadIdx.x;
     const uint32_t i = t >> 1;
     if (i >= qall) return;
     uint32_t hk[8];
@@ -1331,7 +1335,7 @@ __global__ __launch_bounds__(64) void k_acc_compose(WbArgs a1, const AccessPlan*
   }
   // free every listed entry (its value was read above)
   for (uint32_t l = lane; l < cnt; l += 64) {
-    const uint32_t e = a.rev_idx[(uint64_t)b * 2 * a.Z + l];
+    const uint32_t e = l < 64 ? e_spec : a.rev_idx[(uint64_t)b * 2 * a.Z + l];
     a.st_dead[e] = 0;
     pool_free(a.st_used, e);
   }
