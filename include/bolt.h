@@ -242,7 +242,7 @@ int bolt_get_stats(bolt_map* m, bolt_stats* out);
  * --------------------------------------------------------------------- */
 
 /* One observable access.  batch 0 is the build; access batches count from
- * 1.  kind 0 = read of a whole page, 1 = write of a whole page.  Within a
+ * 1 (a rejected batch takes its number and records nothing).  kind 0 = read of a whole page, 1 = write of a whole page.  Within a
  * batch the reads come in command order (two roles per command, HBM bins
  * omitted), then the writes in ascending page order, as one canonical
  * sequence of what the accessor did (the writes of one batch run

@@ -1004,12 +1004,14 @@ int or_access(or_map* m, const uint8_t* ops, const uint64_t* keys, const uint8_t
               uint8_t* status, uint32_t q) {
   if (m->poisoned) return OR_ESTATE;
   if (!m->built) return OR_EINVAL;
+  if (q == 0) return OR_OK;
+  /* a batch with a bad op code keeps its number (as a label of the trace)
+     but changes nothing and records no access */
+  m->batch_no++;
   for (uint32_t i = 0; i < q; ++i)
     if (ops[i] > OR_DEL) return OR_EINVAL;
-  if (q == 0) return OR_OK;
   const or_sizes* s = &m->s;
   uint32_t vs = s->vs;
-  m->batch_no++;
 
   /* leaders: the first occurrence of each key, found by sorting (key, i) */
   or_kidx* kx = malloc(q * sizeof(or_kidx));

@@ -44,7 +44,7 @@ struct TraceSeg {
 // Kernel classes timed with HIP events when a map has BOLT_F_TIMING.
 enum KernelId {
   kkSortTile, kkSortGlobal, kkSortMerge, kkPairs, kkP2C, kkScan, kkExpand, kkWriteout, kkPmBuild, kkDupcheck,
-  kkBuildMisc, kkAccDedup, kkAccFetch, kkAccResolve, kkAccRemap, kkAccCompose, kkAccShip, kkAccMisc, kkCount
+  kkBuildMisc, kkAccDedup, kkAccFetch, kkAccResolve, kkAccRemap, kkAccCompose, kkAccShip, kkAccMisc, kkAccSolo, kkCount
 };
 extern const char* const kKernelNames[kkCount];
 

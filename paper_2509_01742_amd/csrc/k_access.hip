@@ -442,6 +442,29 @@ __host__ __device__ constexpr uint32_t group_lds_entries(uint32_t q) {
 }
 __host__ __device__ constexpr uint64_t group_lds_bytes(uint32_t q) { return 12ull * group_lds_entries(q); }
 
+// PRF t of a batch, two per command i = t / 2: for even t the fetch pair
+// F(s) and remap pair R(s) of tape step s, for odd t the key's position-map
+// rows.
+__device__ __forceinline__ void group_prf(const GroupArgs& a, uint32_t t) {
+  const uint32_t i = t >> 1;
+  uint32_t hk[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) hk[j] = a.ctl->hkey[j];
+  uint64_t w[4];
+  if ((t & 1) == 0) {
+    prf4(hk, kDomTape, a.ctl->steps + i, w);
+    uint32_t f1, f2, r1, r2;
+    pair_of(w[0], w[1], a.B, f1, f2);
+    pair_of(w[2], w[3], a.B, r1, r2);
+    a.fpair[i] = make_uint2(f1, f2);
+    a.rpair[i] = make_uint2(r1, r2);
+  } else {
+    prf4(hk, kDomRows, a.keys[i], w);
+    a.rows[i] = make_uint4((uint32_t)__umul64hi(w[0], a.R), (uint32_t)__umul64hi(w[1], a.R),
+                           (uint32_t)__umul64hi(w[2], a.R), (uint32_t)__umul64hi(w[3], a.R));
+  }
+}
+
 // One workgroup per partition (kParts of them), then group_prf_blocks(q)
 // workgroups for the PRF outputs, which run beside them.  A partition's
 // workgroup picks the commands of its partition out of the whole batch (all
@@ -473,24 +496,7 @@ __global__ __launch_bounds__(kDedupNT) void k_acc_group(GroupArgs a1, const Acce
     // tape step s, and the key's position-map rows.
     if (threadIdx.x >= kPrfPerBlock) return;
     const uint32_t t = (part - kParts) * kPrfPerBlock + threadIdx.x;
-    const uint32_t i = t >> 1;
-    if (i >= qall) return;
-    uint32_t hk[8];
-#pragma unroll
-    for (int j = 0; j < 8; ++j) hk[j] = a.ctl->hkey[j];
-    uint64_t w[4];
-    if ((t & 1) == 0) {
-      prf4(hk, kDomTape, a.ctl->steps + i, w);
-      uint32_t f1, f2, r1, r2;
-      pair_of(w[0], w[1], a.B, f1, f2);
-      pair_of(w[2], w[3], a.B, r1, r2);
-      a.fpair[i] = make_uint2(f1, f2);
-      a.rpair[i] = make_uint2(r1, r2);
-    } else {
-      prf4(hk, kDomRows, keys[i], w);
-      a.rows[i] = make_uint4((uint32_t)__umul64hi(w[0], a.R), (uint32_t)__umul64hi(w[1], a.R),
-                             (uint32_t)__umul64hi(w[2], a.R), (uint32_t)__umul64hi(w[3], a.R));
-    }
+    if ((t >> 1) < qall) group_prf(a, t);
     return;
   }
   // This partition's commands, gathered in index order: every command's key
@@ -734,18 +740,11 @@ __global__ __launch_bounds__(256) void k_acc_ship(ShipArgs a) {
 
 
 
-template <bool MULTI, bool SEALED>
-__global__ __launch_bounds__(256) void k_acc_fetch(FetchArgs a1, const AccessPlan* tab) {
-  BOLT_PICK(FetchArgs, fa);
-  extern __shared__ uint64_t fdyn[];
+// Command i's fetch, by one whole wave (a sealed map decrypts its pages in
+// the wave's LDS page pg).
+template <bool SEALED>
+__device__ __forceinline__ void fetch_cmd(const FetchArgs& a, uint32_t i, uint64_t* pg) {
   const uint32_t lane = threadIdx.x & 63;
-  if (!MULTI && blockIdx.x < a.ship_blocks) {  // the previous batch's send
-    ship_slots<SEALED>(a.ship, blockIdx.x * 4 + (threadIdx.x >> 6), a.ship_blocks * 4,
-                       fdyn + (uint64_t)(threadIdx.x >> 6) * a.pw);
-    return;
-  }
-  const uint32_t i = (blockIdx.x - (MULTI ? 0 : a.ship_blocks)) * 4 + (threadIdx.x >> 6);
-  if (i >= a.q) return;
   if (a.ctl->reject == a.epoch || a.ctl->err) return;
   const uint2 fp = a.fpair[i];  // F(s), from the dedup kernel
   const uint32_t f1 = fp.x, f2 = fp.y;
@@ -833,7 +832,6 @@ __global__ __launch_bounds__(256) void k_acc_fetch(FetchArgs a1, const AccessPla
       // Sealed page: copy it into this wave's LDS, check its tag under the
       // write count kept in HBM, and decrypt it there; the rest reads the
       // plain page from LDS.
-      uint64_t* pg = fdyn + (uint64_t)(threadIdx.x >> 6) * a.pw;
       for (uint64_t w = lane; w < a.pw; w += 64) pg[w] = src[w];
       wave_sync();
       const uint32_t page = b - (uint32_t)a.K;
@@ -911,6 +909,19 @@ __global__ __launch_bounds__(256) void k_acc_fetch(FetchArgs a1, const AccessPla
   }
 }
 
+template <bool MULTI, bool SEALED>
+__global__ __launch_bounds__(256) void k_acc_fetch(FetchArgs a1, const AccessPlan* tab) {
+  BOLT_PICK(FetchArgs, fa);
+  extern __shared__ uint64_t fdyn[];
+  uint64_t* const pg = fdyn + (uint64_t)(threadIdx.x >> 6) * a.pw;
+  if (!MULTI && blockIdx.x < a.ship_blocks) {  // the previous batch's send
+    ship_slots<SEALED>(a.ship, blockIdx.x * 4 + (threadIdx.x >> 6), a.ship_blocks * 4, pg);
+    return;
+  }
+  const uint32_t i = (blockIdx.x - (MULTI ? 0 : a.ship_blocks)) * 4 + (threadIdx.x >> 6);
+  if (i < a.q) fetch_cmd<SEALED>(a, i, pg);
+}
+
 // Claims a free slot of row r for (key, pair); false when the row is full.
 __device__ __forceinline__ bool pm_claim(uint32_t* pm_mask, uint64_t* pm_key, uint2* pm_pair, uint32_t r, uint32_t W,
                                          uint64_t key, uint2 pair) {
@@ -937,11 +948,9 @@ __device__ __forceinline__ bool pm_claim(uint32_t* pm_mask, uint64_t* pm_key, ui
 
 
 
-template <bool MULTI>
-__global__ __launch_bounds__(256) void k_acc_resolve(ResolveArgs a1, const AccessPlan* tab) {
-  BOLT_PICK(ResolveArgs, rv);
-  if (carry_ship<MULTI>(a.ship, a.ship_blocks)) return;
-  const uint32_t i = (blockIdx.x - (MULTI ? 0 : a.ship_blocks)) * blockDim.x + threadIdx.x;
+// Command i's response and, for a leader, its key's final state, by one
+// thread (live: i < q); every lane of the wave calls it.
+__device__ __forceinline__ void resolve_cmd(const ResolveArgs& a, uint32_t i) {
   const bool live = i < a.q;
   if (a.ctl->reject == a.epoch || a.ctl->err) {
     if (live) {
@@ -985,6 +994,13 @@ __global__ __launch_bounds__(256) void k_acc_resolve(ResolveArgs a1, const Acces
   if (a.fast) wave_count(&a.ctl->b_del, del);
 }
 
+template <bool MULTI>
+__global__ __launch_bounds__(256) void k_acc_resolve(ResolveArgs a1, const AccessPlan* tab) {
+  BOLT_PICK(ResolveArgs, rv);
+  if (carry_ship<MULTI>(a.ship, a.ship_blocks)) return;
+  resolve_cmd(a, (blockIdx.x - (MULTI ? 0 : a.ship_blocks)) * blockDim.x + threadIdx.x);
+}
+
 // ---------------------------------------------------------------------------
 // place (one-round case): P2C loads, stash entries, position-map updates and
 // the row of every insert (one thread per command)
@@ -1009,12 +1025,9 @@ __device__ __forceinline__ bool stash_put(uint64_t* st_used, uint64_t PW, uint64
   return true;
 }
 
-template <bool MULTI>
-__global__ __launch_bounds__(256) void k_acc_place(PlaceArgs a1, const AccessPlan* tab) {
-  BOLT_PICK(PlaceArgs, pa);
-  if (carry_ship<MULTI>(a.ship, a.ship_blocks)) return;
-  if (!a.enabled) return;
-  const uint32_t i = (blockIdx.x - (MULTI ? 0 : a.ship_blocks)) * blockDim.x + threadIdx.x;
+// Command i's placement (one-round case), by one thread; every lane of the
+// wave calls it.
+__device__ __forceinline__ void place_cmd(const PlaceArgs& a, uint32_t i) {
   if (a.ctl->reject == a.epoch || a.ctl->err) return;
   bool placed = false, ins = false;
   if (i < a.q) {
@@ -1068,6 +1081,14 @@ __global__ __launch_bounds__(256) void k_acc_place(PlaceArgs a1, const AccessPla
   }
   wave_count(&a.ctl->b_place, placed);
   wave_count(&a.ctl->b_ins, ins);
+}
+
+template <bool MULTI>
+__global__ __launch_bounds__(256) void k_acc_place(PlaceArgs a1, const AccessPlan* tab) {
+  BOLT_PICK(PlaceArgs, pa);
+  if (carry_ship<MULTI>(a.ship, a.ship_blocks)) return;
+  if (!a.enabled) return;
+  place_cmd(a, (blockIdx.x - (MULTI ? 0 : a.ship_blocks)) * blockDim.x + threadIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -1224,20 +1245,18 @@ __host__ __device__ constexpr uint64_t wb_lds_bytes(uint64_t pw) { return pw * 8
 // without any device-wide fence.  HBM bins are rebuilt in place; an
 // observable page is rebuilt into the outbox at the writer's slot, for
 // k_acc_ship to send.
-template <bool MULTI>
-__global__ __launch_bounds__(64) void k_acc_compose(WbArgs a1, const AccessPlan* tab) {
-  BOLT_PICK(WbArgs, wa);
-  extern __shared__ uint64_t dyn[];
+// Candidate slot s's rebuild, by one whole wave with its own dynamic LDS
+// (wb_lds_bytes, plus a page for a sealed map) at dyn.
+__device__ __forceinline__ void compose_slot(const WbArgs& a, uint32_t s, uint64_t* dyn) {
   uint64_t* old = dyn;
   uint64_t* ikey = dyn + a.pw;
   uint32_t* isrc = reinterpret_cast<uint32_t*>(ikey + kWbItems);
   uint32_t* by_rank = isrc + kWbItems;
-  const uint32_t lane = threadIdx.x;
-  const uint32_t s = blockIdx.x;
+  const uint32_t lane = threadIdx.x & 63;
   if (lane == 0 && s < 2 * a.q) a.ship_page[s] = kNone;
-  if (s >= 3 * a.q || a.ctl->reject == a.epoch || a.ctl->err) return;  // whole block
+  if (s >= 3 * a.q || a.ctl->reject == a.epoch || a.ctl->err) return;  // whole wave
   const uint32_t b = a.cand_bin[s];
-  if (b == kNone) return;  // whole block
+  if (b == kNone) return;  // whole wave
   const bool host = b >= a.K;
   if (host && s >= 2 * a.q) {  // observable bins are only claimed by fetch slots
     if (lane == 0) set_err(a.ctl, kErrBroken);
@@ -1251,9 +1270,9 @@ __global__ __launch_bounds__(64) void k_acc_compose(WbArgs a1, const AccessPlan*
   const uint64_t rm = a.rmask[b];
   const uint32_t cnt_raw = a.rev_cnt[b];
   const uint32_t e_spec = lane < 2 * a.Z ? a.rev_idx[(uint64_t)b * 2 * a.Z + lane] : kNone;  // the bin's list row
-  if (cl != claim_tag(a.epoch, s)) return;  // whole block
+  if (cl != claim_tag(a.epoch, s)) return;  // whole wave
   const uint32_t cnt = cnt_raw < 2 * a.Z ? cnt_raw : 2 * a.Z;
-  __syncthreads();
+  wave_sync();
   const uint64_t keep = old[0] & ~rm;
   // survivors, in slot order
   if (lane < a.Z && ((keep >> lane) & 1)) {
@@ -1287,7 +1306,7 @@ __global__ __launch_bounds__(64) void k_acc_compose(WbArgs a1, const AccessPlan*
     if (lane == 0) set_err(a.ctl, kErrOverflow);
     return;
   }
-  __syncthreads();
+  wave_sync();
   // canonical order: ascending key
   if (lane < n_items) {
     const uint64_t mine = ikey[lane];
@@ -1295,7 +1314,7 @@ __global__ __launch_bounds__(64) void k_acc_compose(WbArgs a1, const AccessPlan*
     for (uint32_t j = 0; j < n_items; ++j) rank += ikey[j] < mine || (ikey[j] == mine && j < lane);
     by_rank[rank] = lane;
   }
-  __syncthreads();
+  wave_sync();
   // HBM bin: in place.  Observable page: to the outbox, or straight to the
   // store when direct (a sealed one through LDS after the item lists).
   const bool seal = host && a.direct && a.tags;
@@ -1354,31 +1373,37 @@ __global__ __launch_bounds__(64) void k_acc_compose(WbArgs a1, const AccessPlan*
   }
 }
 
+template <bool MULTI>
+__global__ __launch_bounds__(64) void k_acc_compose(WbArgs a1, const AccessPlan* tab) {
+  BOLT_PICK(WbArgs, wa);
+  extern __shared__ uint64_t dyn[];
+  compose_slot(a, blockIdx.x, dyn);
+}
+
 // ---------------------------------------------------------------------------
 // finish: position-map inserts of the one-round case, then the counters
 // ---------------------------------------------------------------------------
 
 
 
-template <bool MULTI>
-__global__ __launch_bounds__(256) void k_acc_finish(FinishArgs a1, const AccessPlan* tab) {
-  BOLT_PICK(FinishArgs, fn);
-  if (carry_ship<MULTI>(a.ship, a.ship_blocks)) return;
-  const uint32_t bid = blockIdx.x - (MULTI ? 0 : a.ship_blocks);
-  const uint32_t i = bid * blockDim.x + threadIdx.x;
-  if (a.ctl->reject == a.epoch) return;
-  const bool ok = !a.ctl->err;
-  if (ok && i < a.q && a.rowsel && a.rowsel[i] != kNone) {
+// Command i's position-map insert (one-round case).
+__device__ __forceinline__ void finish_cmd(const FinishArgs& a, uint32_t i) {
+  if (i < a.q && a.rowsel && a.rowsel[i] != kNone) {
     if (!pm_claim(a.pm_mask, a.pm_key, a.pm_pair, a.rowsel[i], a.W, a.keys[i], a.rpair[i]))
       set_err(a.ctl, kErrOverflow);
   }
-  if (bid != 0) return;
-  __shared__ uint32_t part[kFreeBuckets];
-  part[threadIdx.x] = a.freed[threadIdx.x];
-  a.freed[threadIdx.x] = 0;  // ready for the next batch
+}
+
+// The batch's counters, by one whole workgroup (ok: no error was set before
+// the inserts); part is kFreeBuckets words of LDS.
+__device__ __forceinline__ void finish_counters(const FinishArgs& a, bool ok, uint32_t* part) {
+  for (uint32_t t = threadIdx.x; t < kFreeBuckets; t += blockDim.x) {
+    part[t] = a.freed[t];
+    a.freed[t] = 0;  // ready for the next batch
+  }
   __syncthreads();
   for (uint32_t h = kFreeBuckets / 2; h > 0; h >>= 1) {
-    if (threadIdx.x < h) part[threadIdx.x] += part[threadIdx.x + h];
+    for (uint32_t t = threadIdx.x; t < h; t += blockDim.x) part[t] += part[t + h];
     __syncthreads();
   }
   if (threadIdx.x == 0) {
@@ -1397,6 +1422,67 @@ __global__ __launch_bounds__(256) void k_acc_finish(FinishArgs a1, const AccessP
     c->b_ins = 0;
     c->b_del = 0;
   }
+}
+
+template <bool MULTI>
+__global__ __launch_bounds__(256) void k_acc_finish(FinishArgs a1, const AccessPlan* tab) {
+  BOLT_PICK(FinishArgs, fn);
+  if (carry_ship<MULTI>(a.ship, a.ship_blocks)) return;
+  const uint32_t bid = blockIdx.x - (MULTI ? 0 : a.ship_blocks);
+  if (a.ctl->reject == a.epoch) return;
+  const bool ok = !a.ctl->err;
+  if (ok) finish_cmd(a, bid * blockDim.x + threadIdx.x);
+  if (bid != 0) return;
+  __shared__ uint32_t part[kFreeBuckets];
+  finish_counters(a, ok, part);
+}
+
+// ---------------------------------------------------------------------------
+// a batch of one command on a plain map, in one workgroup
+// ---------------------------------------------------------------------------
+
+// Three waves run the batched kernels' steps in their order; each step ends
+// with a device-scope fence and a barrier, as the next step reads what this
+// one stored or changed by atomics (the fence also drops the CU's cached
+// copies of lines that atomics changed in L2).  The dedup of one command is
+// trivial; its two PRFs run on waves 1 and 2; fetch, resolve and place on
+// wave 0; the rebuild of candidate slot s on wave s; then the insert and the
+// counters.  A wave's dynamic LDS for the rebuild is wb_stride bytes.
+constexpr uint32_t kSoloNT = 192;
+
+__device__ __forceinline__ void solo_step() {
+  __threadfence();
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(kSoloNT) void k_acc_solo(GroupArgs gr, FetchArgs fa, ResolveArgs rv, PlaceArgs pa,
+                                                      WbArgs wa, FinishArgs fn, uint32_t wb_stride) {
+  extern __shared__ uint64_t sdyn[];
+  __shared__ uint32_t part[kFreeBuckets];
+  const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  if (threadIdx.x == 0) {
+    // the command leads its key; a PUT or DEL is its key's last write
+    const uint8_t op = gr.ops[0];
+    gr.leader[0] = 0;
+    gr.prevw[0] = kNone;
+    gr.lastw[0] = (op & 3u) ? 0 : kNone;
+    if (op > 2) gr.ctl->reject = gr.epoch;
+  }
+  if (lane == 0 && wave >= 1) group_prf(gr, wave - 1);
+  if (fa.tlog_r && threadIdx.x < 5) fa.tlog_r[threadIdx.x] = kNone;  // the batch's trace words
+  solo_step();
+  if (wave == 0) fetch_cmd<false>(fa, 0, nullptr);
+  solo_step();
+  if (wave == 0) resolve_cmd(rv, lane);
+  solo_step();
+  if (wave == 0) place_cmd(pa, lane);
+  solo_step();
+  compose_slot(wa, wave, sdyn + (uint64_t)wave * (wb_stride / 8));
+  solo_step();
+  if (fn.ctl->reject == fn.epoch) return;  // the same for the whole workgroup
+  const bool ok = !fn.ctl->err;
+  if (threadIdx.x == 0 && ok) finish_cmd(fn, 0);
+  finish_counters(fn, ok, part);
 }
 
 // Fill of the trace segment of a batch (no memset nodes in captured graphs).
@@ -1424,7 +1510,7 @@ static ShipArgs ship_args(bolt_map* m, uint32_t lo, uint32_t hi) {
 
 // Fills every kernel argument of one map's batch; reserves its trace words.
 static void plan_access(bolt_map* m, const uint8_t* ops, const uint64_t* keys, const void* vals_in, void* vals_out,
-                        uint8_t* status, uint32_t q, hipStream_t st, AccessPlan& P) {
+                        uint8_t* status, uint32_t q, hipStream_t st, AccessPlan& P, bool fill_trace = true) {
   const Sizes& s = m->s;
   const BatchScratch& bs = m->bs;
   const uint32_t epoch = (uint32_t)(m->batches + 1);
@@ -1439,7 +1525,8 @@ static void plan_access(bolt_map* m, const uint8_t* ops, const uint64_t* keys, c
       TraceSeg g{epoch, m->tlog_used, 2ull * q, 3ull * q};
       m->segs.push_back(g);
       m->tlog_used += words;
-      hipLaunchKernelGGL(k_fill_u32, dim3((uint32_t)((words + 255) / 256)), dim3(256), 0, st, tlog_r, words, kNone);
+      if (fill_trace)
+        hipLaunchKernelGGL(k_fill_u32, dim3((uint32_t)((words + 255) / 256)), dim3(256), 0, st, tlog_r, words, kNone);
     } else {
       m->tlog_lost = true;
     }
@@ -1781,8 +1868,29 @@ static int run_access_graph(bolt_map* m, AccessPlan& P, hipStream_t st) {
 
 int run_access(bolt_map* m, const uint8_t* ops, const uint64_t* keys, const void* vals_in, void* vals_out,
                uint8_t* status, uint32_t q, hipStream_t st) {
+  // A batch of one command on a plain map runs as one workgroup (k_acc_solo,
+  // which also fills its trace words) when three rebuild waves' LDS fits
+  // the default 64 KiB.  One command is always one round (B, R >= 1).
+  const uint32_t wb_stride = (uint32_t)wb_lds_bytes(m->s.page_bytes / 8);
+  const bool solo = q == 1 && !m->tags && !(m->p.flags & BOLT_F_GRAPHS) &&
+                    3ull * wb_stride + 4 * kFreeBuckets <= 65536;
   AccessPlan P;
-  plan_access(m, ops, keys, vals_in, vals_out, status, q, st, P);
+  plan_access(m, ops, keys, vals_in, vals_out, status, q, st, P, !solo);
+  if (solo) {
+    static_assert(sizeof(GroupArgs) + sizeof(FetchArgs) + sizeof(ResolveArgs) + sizeof(PlaceArgs) + sizeof(WbArgs) +
+                          sizeof(FinishArgs) + 8 <= 4096,
+                  "kernel arguments of k_acc_solo");
+    if (flush_ship(m, st)) return BOLT_EHIP;
+    P.wa.direct = 1;
+    {
+      TimedScope ts(m->timer, kkAccSolo, st);
+      hipLaunchKernelGGL(k_acc_solo, dim3(1), dim3(kSoloNT), 3ull * wb_stride, st, P.gr, P.fa, P.rv, P.pa, P.wa,
+                         P.fn, wb_stride);
+    }
+    if (m->p.flags & BOLT_F_WATCH)
+      hipLaunchKernelGGL(k_acc_watch, dim3(1), dim3(1024), 0, st, m->load, m->s.B, m->s.K, m->ctl);
+    return hipGetLastError() == hipSuccess ? BOLT_OK : BOLT_EHIP;
+  }
   if (m->p.flags & BOLT_F_GRAPHS) {
     const int rc = run_access_graph(m, P, st);
     if (rc == BOLT_OK && (m->p.flags & BOLT_F_WATCH))

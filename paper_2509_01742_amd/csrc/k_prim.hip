@@ -9,7 +9,7 @@ namespace bolt {
 const char* const kKernelNames[kkCount] = {
     "sort_tile", "sort_global", "sort_merge", "build_pairs", "p2c_rounds", "loads_scan", "expand", "page_writeout",
     "pm_build", "dup_check", "build_misc", "acc_dedup", "acc_fetch", "acc_resolve", "acc_remap", "acc_compose",
-    "acc_ship", "acc_misc"};
+    "acc_ship", "acc_misc", "acc_solo"};
 
 hipEvent_t KernelTimer::take() {
   if (!pool.empty()) {

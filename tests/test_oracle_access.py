@@ -249,6 +249,16 @@ def test_access_errors():
     assert m2.access(np.zeros(1, np.uint8), k[:1], np.zeros((1, 8), np.uint8))[0] == O.EINVAL  # not built
 
 
+def test_rejected_batch_keeps_its_number_and_records_nothing():
+    m, p, k = _mk(64, 8, 60, 1, trace=True)
+    n0 = m.trace().size
+    assert m.access(np.array([0, 5], np.uint8), k[:2], np.zeros((2, 8), np.uint8))[0] == O.EINVAL
+    assert m.trace().size == n0 and m.ctr == 0
+    assert m.access(np.zeros(1, np.uint8), k[:1], np.zeros((1, 8), np.uint8))[0] == O.OK
+    t = m.trace()[n0:]
+    assert t.size > 0 and (t["batch"] == 2).all()
+
+
 def test_row_overflow_on_insert():
     m = O.OracleMap(256, 8, W=1, kpr=64, key=KEY)  # 4 rows of one slot
     assert m.build(np.zeros(0, np.uint64), np.zeros((0, 8), np.uint8)) == O.OK
