@@ -147,9 +147,10 @@ def run_mode(args, wl, dev_t, B, torch, observable, seal=False):
     kpc = min(args.per_call, int(bounds[-1]))
     if kpc:
         ev = [torch.cuda.Event(enable_timing=True) for _ in range(kpc + 1)]
+        one = [(d_ops[i:i + 1], d_qk[i:i + 1], d_qv[i:i + 1], d_out[i:i + 1], d_st[i:i + 1]) for i in range(kpc)]
         ev[0].record(stream)
         for i in range(kpc):
-            B.check(m.access(d_ops[i:i + 1], d_qk[i:i + 1], d_qv[i:i + 1], d_out[i:i + 1], d_st[i:i + 1]), "per-call")
+            B.check(m.access(*one[i], stream=stream), "per-call")
             ev[i + 1].record(stream)
         torch.cuda.synchronize()
         pc_lat = [ev[i].elapsed_time(ev[i + 1]) for i in range(kpc)]

@@ -176,15 +176,25 @@ for _name, _, _ in _SIGS:
 # marshalling helpers (torch only for device memory and streams)
 # --------------------------------------------------------------------------
 
-def _stream(stream=None):
-    import torch
+_raw_stream = None
 
-    s = stream if stream is not None else torch.cuda.current_stream()
-    return C.c_void_p(s.cuda_stream)
+
+def _stream(stream=None):
+    """The HIP stream handle of `stream`, else of torch's current stream on
+    the current device (read without building a Stream object)."""
+    global _raw_stream
+    if stream is not None:
+        return stream.cuda_stream
+    if _raw_stream is None:
+        import torch
+
+        get, dev = torch._C._cuda_getCurrentRawStream, torch._C._cuda_getDevice
+        _raw_stream = lambda: get(dev())  # noqa: E731
+    return _raw_stream()
 
 
 def _dptr(t):
-    return C.c_void_p(0 if t is None else t.data_ptr())
+    return None if t is None else t.data_ptr()
 
 
 def check(rc: int, what: str) -> int:
@@ -367,8 +377,8 @@ def build_many(maps, inputs, stream=None) -> int:
         raise ValueError("one input per map")
     k = max(n, 1)
     hs = (C.c_void_p * k)(*[m.h for m in maps])
-    ks = (C.c_void_p * k)(*[_dptr(a).value for a, _ in inputs])
-    vs = (C.c_void_p * k)(*[_dptr(b).value for _, b in inputs])
+    ks = (C.c_void_p * k)(*[_dptr(a) for a, _ in inputs])
+    vs = (C.c_void_p * k)(*[_dptr(b) for _, b in inputs])
     ns = (C.c_uint64 * k)(*[0 if a is None else a.numel() for a, _ in inputs])
     return bolt_build_many(hs, ks, vs, ns, n, _stream(stream))
 
@@ -383,8 +393,8 @@ def access_many(maps, batches, stream=None) -> int:
     hs = (C.c_void_p * max(n, 1))(*[m.h for m in maps])
     bs = (bolt_batch * max(n, 1))()
     for i, (ops, keys, vin, vout, status) in enumerate(batches):
-        bs[i] = bolt_batch(_dptr(ops).value, _dptr(keys).value, _dptr(vin).value, _dptr(vout).value,
-                           _dptr(status).value, 0 if ops is None else ops.numel())
+        bs[i] = bolt_batch(_dptr(ops), _dptr(keys), _dptr(vin), _dptr(vout),
+                           _dptr(status), 0 if ops is None else ops.numel())
     return bolt_access_many(hs, bs, n, _stream(stream))
 
 

@@ -741,8 +741,9 @@ __global__ __launch_bounds__(256) void k_acc_ship(ShipArgs a) {
 
 
 // Command i's fetch, by one whole wave (a sealed map decrypts its pages in
-// the wave's LDS page pg).
-template <bool SEALED>
+// the wave's LDS page pg).  EAGER (command i is a leader): each lane loads
+// its rows' mask, keys and pairs at once, one round trip instead of three.
+template <bool SEALED, bool EAGER = false>
 __device__ __forceinline__ void fetch_cmd(const FetchArgs& a, uint32_t i, uint64_t* pg) {
   const uint32_t lane = threadIdx.x & 63;
   if (a.ctl->reject == a.epoch || a.ctl->err) return;
@@ -753,16 +754,27 @@ __device__ __forceinline__ void fetch_cmd(const FetchArgs& a, uint32_t i, uint64
   // key search (Sec. 5.1 step 3): d rows, 16 lanes per row, 2 slots per lane
   bool hit = false;
   uint32_t hrow = 0, hslot = 0, p1 = f1, p2 = f2;
-  if (is_leader) {
+  if (EAGER || is_leader) {
     const uint4 rw = a.rows[i];
     const uint32_t j = lane >> 4;
     const uint32_t row = j == 0 ? rw.x : j == 1 ? rw.y : j == 2 ? rw.z : rw.w;
     const uint32_t s0 = (lane & 15) * 2;
     bool m0 = false, m1 = false;
+    uint2 pp0 = make_uint2(0, 0), pp1 = make_uint2(0, 0);
     if (j < a.d) {
       const uint32_t mk = a.pm_mask[row];
-      if (s0 < a.W && ((mk >> s0) & 1)) m0 = a.pm_key[(uint64_t)row * a.W + s0] == key;
-      if (s0 + 1 < a.W && ((mk >> (s0 + 1)) & 1)) m1 = a.pm_key[(uint64_t)row * a.W + s0 + 1] == key;
+      if (EAGER) {
+        const uint64_t* kr = a.pm_key + (uint64_t)row * a.W;
+        const uint2* pr = a.pm_pair + (uint64_t)row * a.W;
+        const uint64_t k0 = s0 < a.W ? kr[s0] : 0, k1 = s0 + 1 < a.W ? kr[s0 + 1] : 0;
+        if (s0 < a.W) pp0 = pr[s0];
+        if (s0 + 1 < a.W) pp1 = pr[s0 + 1];
+        m0 = s0 < a.W && ((mk >> s0) & 1) && k0 == key;
+        m1 = s0 + 1 < a.W && ((mk >> (s0 + 1)) & 1) && k1 == key;
+      } else {
+        if (s0 < a.W && ((mk >> s0) & 1)) m0 = a.pm_key[(uint64_t)row * a.W + s0] == key;
+        if (s0 + 1 < a.W && ((mk >> (s0 + 1)) & 1)) m1 = a.pm_key[(uint64_t)row * a.W + s0 + 1] == key;
+      }
     }
     const uint64_t bal = __ballot(m0 || m1);
     if (bal) {
@@ -771,9 +783,15 @@ __device__ __forceinline__ void fetch_cmd(const FetchArgs& a, uint32_t i, uint64
       hrow = __shfl(row, src, 64);
       hslot = __shfl(slot, src, 64);
       hit = true;
-      const uint2 pp = a.pm_pair[(uint64_t)hrow * a.W + hslot];
-      p1 = pp.x;
-      p2 = pp.y;
+      if (EAGER) {
+        const uint2 mp = m0 ? pp0 : pp1;
+        p1 = __shfl(mp.x, src, 64);
+        p2 = __shfl(mp.y, src, 64);
+      } else {
+        const uint2 pp = a.pm_pair[(uint64_t)hrow * a.W + hslot];
+        p1 = pp.x;
+        p2 = pp.y;
+      }
     }
   }
   // value access (Sec. 5.1 step 4): both bins, whole.  Plain maps issue
@@ -1394,8 +1412,28 @@ __device__ __forceinline__ void finish_cmd(const FinishArgs& a, uint32_t i) {
   }
 }
 
-// The batch's counters, by one whole workgroup (ok: no error was set before
-// the inserts); part is kFreeBuckets words of LDS.
+// The batch's counter update, by one thread, given the stash entries the
+// rebuild freed (ok: no error was set before the inserts).
+__device__ __forceinline__ void finish_apply(const FinishArgs& a, bool ok, uint64_t freed) {
+  Ctl* c = a.ctl;
+  if (ok) {
+    c->steps += a.q;
+    const uint64_t st = c->stash_live + c->b_place - freed;
+    c->stash_live = st;
+    if (st > c->stash_hw) c->stash_hw = st;
+    if (st > a.stash_bound) c->err |= kErrOverflow;
+    const uint64_t live = c->live + c->b_ins - c->b_del;
+    c->live = live;
+    if (live > a.cap) c->err |= kErrFull;
+  }
+  c->b_place = 0;
+  c->b_ins = 0;
+  c->b_del = 0;
+}
+
+// The batch's counters, by one whole workgroup: the freed buckets summed
+// and cleared; part is kFreeBuckets words of LDS.  Every batch leaves the
+// buckets at zero.
 __device__ __forceinline__ void finish_counters(const FinishArgs& a, bool ok, uint32_t* part) {
   for (uint32_t t = threadIdx.x; t < kFreeBuckets; t += blockDim.x) {
     part[t] = a.freed[t];
@@ -1406,22 +1444,7 @@ __device__ __forceinline__ void finish_counters(const FinishArgs& a, bool ok, ui
     for (uint32_t t = threadIdx.x; t < h; t += blockDim.x) part[t] += part[t + h];
     __syncthreads();
   }
-  if (threadIdx.x == 0) {
-    Ctl* c = a.ctl;
-    if (ok) {
-      c->steps += a.q;
-      const uint64_t st = c->stash_live + c->b_place - part[0];
-      c->stash_live = st;
-      if (st > c->stash_hw) c->stash_hw = st;
-      if (st > a.stash_bound) c->err |= kErrOverflow;
-      const uint64_t live = c->live + c->b_ins - c->b_del;
-      c->live = live;
-      if (live > a.cap) c->err |= kErrFull;
-    }
-    c->b_place = 0;
-    c->b_ins = 0;
-    c->b_del = 0;
-  }
+  if (threadIdx.x == 0) finish_apply(a, ok, part[0]);
 }
 
 template <bool MULTI>
@@ -1442,23 +1465,44 @@ __global__ __launch_bounds__(256) void k_acc_finish(FinishArgs a1, const AccessP
 // ---------------------------------------------------------------------------
 
 // Three waves run the batched kernels' steps in their order; each step ends
-// with a device-scope fence and a barrier, as the next step reads what this
-// one stored or changed by atomics (the fence also drops the CU's cached
-// copies of lines that atomics changed in L2).  The dedup of one command is
+// at a workgroup barrier, which makes what the step stored or changed by
+// atomics in global memory visible to the whole workgroup (all its waves
+// share one CU and its L1).  The dedup of one command is
 // trivial; its two PRFs run on waves 1 and 2; fetch, resolve and place on
-// wave 0; the rebuild of candidate slot s on wave s; then the insert and the
-// counters.  A wave's dynamic LDS for the rebuild is wb_stride bytes.
+// wave 0 (waves 1 and 2 warm L2 for the later steps meanwhile); the rebuild
+// of candidate slot s on wave s; then the insert and the counters.  A
+// wave's dynamic LDS for the rebuild is wb_stride bytes.
 constexpr uint32_t kSoloNT = 192;
 
-__device__ __forceinline__ void solo_step() {
-  __threadfence();
-  __syncthreads();
+__device__ __forceinline__ void solo_step() { __syncthreads(); }
+
+// Waves 1 and 2 while wave 0 fetches: loads of lines that the later steps
+// read or change by atomics, so that they find them in L2 rather than HBM.
+// The values are folded into one word, stored only if it equals a constant
+// (which changes nothing even then).
+__device__ __forceinline__ void solo_warm(const FetchArgs& fa, const PlaceArgs& pa, uint32_t wave, uint32_t lane) {
+  uint64_t acc = 0;
+  if (wave == 1) {
+    // the stash pool word the place step tries first
+    if (lane == 0) acc ^= pa.st_used[alloc_hash(pa.epoch, 0) % pa.PW];
+  } else {
+    // both bins of the remap pair: load, list, claim, removal mask, HBM page
+    const uint2 rp = fa.rpair[0];
+#pragma unroll
+    for (uint32_t r = 0; r < 2; ++r) {
+      const uint32_t b = r ? rp.y : rp.x;
+      if (lane == 0) acc ^= fa.load[b] ^ fa.rev_cnt[b] ^ fa.claim[b] ^ fa.rmask[b];
+      if (lane < 2 * fa.Z) acc ^= fa.rev_idx[(uint64_t)b * 2 * fa.Z + lane];
+      if (b < fa.K)
+        for (uint64_t w = lane; w < fa.pw; w += 64) acc ^= fa.hbm[(uint64_t)b * fa.pw + w];
+    }
+  }
+  if (acc == 0x5D1F0C9B7A3E6421ull) set_err(fa.ctlw, 0);
 }
 
 __global__ __launch_bounds__(kSoloNT) void k_acc_solo(GroupArgs gr, FetchArgs fa, ResolveArgs rv, PlaceArgs pa,
                                                       WbArgs wa, FinishArgs fn, uint32_t wb_stride) {
   extern __shared__ uint64_t sdyn[];
-  __shared__ uint32_t part[kFreeBuckets];
   const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   if (threadIdx.x == 0) {
     // the command leads its key; a PUT or DEL is its key's last write
@@ -1471,7 +1515,10 @@ __global__ __launch_bounds__(kSoloNT) void k_acc_solo(GroupArgs gr, FetchArgs fa
   if (lane == 0 && wave >= 1) group_prf(gr, wave - 1);
   if (fa.tlog_r && threadIdx.x < 5) fa.tlog_r[threadIdx.x] = kNone;  // the batch's trace words
   solo_step();
-  if (wave == 0) fetch_cmd<false>(fa, 0, nullptr);
+  if (wave == 0)
+    fetch_cmd<false, true>(fa, 0, nullptr);
+  else
+    solo_warm(fa, pa, wave, lane);
   solo_step();
   if (wave == 0) resolve_cmd(rv, lane);
   solo_step();
@@ -1479,10 +1526,16 @@ __global__ __launch_bounds__(kSoloNT) void k_acc_solo(GroupArgs gr, FetchArgs fa
   solo_step();
   compose_slot(wa, wave, sdyn + (uint64_t)wave * (wb_stride / 8));
   solo_step();
-  if (fn.ctl->reject == fn.epoch) return;  // the same for the whole workgroup
-  const bool ok = !fn.ctl->err;
-  if (threadIdx.x == 0 && ok) finish_cmd(fn, 0);
-  finish_counters(fn, ok, part);
+  // the insert and the counters; the rebuild of slot s adds to bucket s only
+  if (threadIdx.x == 0 && fn.ctl->reject != fn.epoch) {
+    const bool ok = !fn.ctl->err;
+    if (ok) finish_cmd(fn, 0);
+    const uint64_t freed = (uint64_t)fn.freed[0] + fn.freed[1] + fn.freed[2];
+    fn.freed[0] = 0;
+    fn.freed[1] = 0;
+    fn.freed[2] = 0;
+    finish_apply(fn, ok, freed);
+  }
 }
 
 // Fill of the trace segment of a batch (no memset nodes in captured graphs).
@@ -1882,6 +1935,7 @@ int run_access(bolt_map* m, const uint8_t* ops, const uint64_t* keys, const void
                   "kernel arguments of k_acc_solo");
     if (flush_ship(m, st)) return BOLT_EHIP;
     P.wa.direct = 1;
+    P.fa.pre_host = 1;  // no send shares the link: both pages are read at once
     {
       TimedScope ts(m->timer, kkAccSolo, st);
       hipLaunchKernelGGL(k_acc_solo, dim3(1), dim3(kSoloNT), 3ull * wb_stride, st, P.gr, P.fa, P.rv, P.pa, P.wa,
