@@ -1264,7 +1264,9 @@ __host__ __device__ constexpr uint64_t wb_lds_bytes(uint64_t pw) { return pw * 8
 // observable page is rebuilt into the outbox at the writer's slot, for
 // k_acc_ship to send.
 // Candidate slot s's rebuild, by one whole wave with its own dynamic LDS
-// (wb_lds_bytes, plus a page for a sealed map) at dyn.
+// (wb_lds_bytes, plus a page for a sealed map) at dyn.  MAY_SEAL = false
+// leaves out the sealing of directly written pages (plain maps only).
+template <bool MAY_SEAL>
 __device__ __forceinline__ void compose_slot(const WbArgs& a, uint32_t s, uint64_t* dyn) {
   uint64_t* old = dyn;
   uint64_t* ikey = dyn + a.pw;
@@ -1335,7 +1337,7 @@ __device__ __forceinline__ void compose_slot(const WbArgs& a, uint32_t s, uint64
   wave_sync();
   // HBM bin: in place.  Observable page: to the outbox, or straight to the
   // store when direct (a sealed one through LDS after the item lists).
-  const bool seal = host && a.direct && a.tags;
+  const bool seal = MAY_SEAL && host && a.direct && a.tags;
   uint64_t* const dst = host ? (a.direct ? a.obs + (uint64_t)(b - a.K) * a.pw : a.outbox + (uint64_t)s * a.pw)
                              : a.hbm + (uint64_t)b * a.pw;
   uint64_t* out = seal ? reinterpret_cast<uint64_t*>(reinterpret_cast<char*>(dyn) + wb_lds_bytes(a.pw)) : dst;
@@ -1391,11 +1393,19 @@ __device__ __forceinline__ void compose_slot(const WbArgs& a, uint32_t s, uint64
   }
 }
 
-template <bool MULTI>
+// One wave (one workgroup) per candidate slot; wave n of the launch takes
+// slot s(n).  The remap slots [2q, 3q) come first (n < q): most have no bin
+// and end at once, which frees wave slots early for the fetch slots [0, 2q)
+// (n in [q, 3q)).  Launched last, they waited for the first round of fetch
+// slots to end: a batch's 3q waves exceed what the device holds at once.
+// SEALED: some map of the launch seals its store.
+template <bool MULTI, bool SEALED>
 __global__ __launch_bounds__(64) void k_acc_compose(WbArgs a1, const AccessPlan* tab) {
   BOLT_PICK(WbArgs, wa);
   extern __shared__ uint64_t dyn[];
-  compose_slot(a, blockIdx.x, dyn);
+  const uint32_t n = blockIdx.x;
+  const uint32_t s = n < a.q ? 2 * a.q + n : (n < 3 * a.q ? n - a.q : n);
+  compose_slot<SEALED>(a, s, dyn);
 }
 
 // ---------------------------------------------------------------------------
@@ -1524,7 +1534,7 @@ __global__ __launch_bounds__(kSoloNT) void k_acc_solo(GroupArgs gr, FetchArgs fa
   solo_step();
   if (wave == 0) place_cmd(pa, lane);
   solo_step();
-  compose_slot(wa, wave, sdyn + (uint64_t)wave * (wb_stride / 8));
+  compose_slot<false>(wa, wave, sdyn + (uint64_t)wave * (wb_stride / 8));
   solo_step();
   // the insert and the counters; the rebuild of slot s adds to bucket s only
   if (threadIdx.x == 0 && fn.ctl->reject != fn.epoch) {
@@ -1849,7 +1859,10 @@ static void launch_many(const AccessPlan& p0, const AccessPlan* tab, uint32_t C,
   hipLaunchKernelGGL(k_acc_resolve<true>, dim3((qmax + 255) / 256, C), dim3(256), 0, st, p0.rv, tab);
   if (any_fast) hipLaunchKernelGGL(k_acc_place<true>, dim3((qmax + 255) / 256, C), dim3(256), 0, st, p0.pa, tab);
   if (any_slow) hipLaunchKernelGGL(k_acc_remap<true>, dim3(1, C), dim3(kRemapNT), 0, st, p0.ra, tab);
-  hipLaunchKernelGGL(k_acc_compose<true>, dim3(3 * qmax, C), dim3(64), lds, st, p0.wa, tab);
+  if (fetch_lds)  // a sealed map among them
+    hipLaunchKernelGGL((k_acc_compose<true, true>), dim3(3 * qmax, C), dim3(64), lds, st, p0.wa, tab);
+  else
+    hipLaunchKernelGGL((k_acc_compose<true, false>), dim3(3 * qmax, C), dim3(64), lds, st, p0.wa, tab);
   hipLaunchKernelGGL(k_acc_finish<true>, dim3((qmax + 255) / 256, C), dim3(256), 0, st, p0.fn, tab);
 }
 
@@ -2008,7 +2021,10 @@ int run_access(bolt_map* m, const uint8_t* ops, const uint64_t* keys, const void
   P.wa.direct = defer ? 0 : 1;
   {
     TimedScope ts(m->timer, kkAccCompose, st);
-    hipLaunchKernelGGL(k_acc_compose<false>, dim3(3 * q), dim3(64), P.wb_lds, st, P.wa, none);
+    if (m->tags)
+      hipLaunchKernelGGL((k_acc_compose<false, true>), dim3(3 * q), dim3(64), P.wb_lds, st, P.wa, none);
+    else
+      hipLaunchKernelGGL((k_acc_compose<false, false>), dim3(3 * q), dim3(64), P.wb_lds, st, P.wa, none);
   }
   m->ship_q = defer ? q : 0;
   m->ship_from = 0;
