@@ -408,6 +408,71 @@ __device__ __forceinline__ void dedup_sort(uint64_t k[kDedupPer], uint32_t x[kDe
   __syncthreads();
 }
 
+// ---------------------------------------------------------------------------
+// send of rebuilt observable pages
+// ---------------------------------------------------------------------------
+
+// The send of a batch's rebuilt observable pages to the store: wave `wave`
+// of `waves` takes the slots lo + wave, lo + wave + waves, ... below hi.  Plain maps copy the
+// page; sealed maps encrypt it in the wave's LDS page `pg` under the page's
+// next write count, tag it, and write page and tag.
+template <bool SEALED>
+__device__ __forceinline__ void ship_slots(const ShipArgs& a, uint32_t wave, uint32_t waves, uint64_t* pg) {
+  const uint32_t lane = threadIdx.x & 63;
+  uint32_t key[8];
+  if (SEALED) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) key[j] = a.ctl->skey[j];
+  }
+  for (uint32_t s = a.lo + wave; s < a.hi; s += waves) {
+    const uint32_t page = a.ship_page[s];
+    if (page == kNone) continue;  // whole wave
+    const uint64_t* src = a.outbox + (uint64_t)s * a.pw;
+    uint64_t* dst = a.obs + (uint64_t)page * a.pw;
+    if (!SEALED) {
+      for (uint64_t w = lane; w < a.pw; w += 64) dst[w] = src[w];
+      continue;
+    }
+    for (uint64_t w = lane; w < a.pw; w += 64) pg[w] = src[w];
+    const uint64_t ver = a.pver[page] + 1;
+    uint32_t tag[4];
+    seal_page(pg, (uint32_t)a.pw, key, page, ver, dst, tag);
+    if (lane == 0) {
+      a.tags[2 * (uint64_t)page] = (uint64_t)tag[0] | ((uint64_t)tag[1] << 32);
+      a.tags[2 * (uint64_t)page + 1] = (uint64_t)tag[2] | ((uint64_t)tag[3] << 32);
+      a.pver[page] = ver;
+    }
+    wave_sync();  // the wave's LDS page is reused by its next slot
+  }
+}
+
+// Workgroups (of 4 waves) of a send of n slots: one per 4 slots, at most
+// 256, so that the kernel it rides with keeps most of the device.
+constexpr uint32_t kShipMaxBlocks = 256;
+__host__ __device__ constexpr uint32_t ship_blocks_for(uint32_t n) {
+  return (n + 3) / 4 < kShipMaxBlocks ? (n + 3) / 4 : kShipMaxBlocks;
+}
+
+// Workgroups [0, ship_blocks) of a kernel that carries a slice of a send
+// (plain maps only: no LDS) do that and nothing else; true for them.
+template <bool MULTI>
+__device__ __forceinline__ bool carry_ship(const ShipArgs& sh, uint32_t ship_blocks) {
+  if (MULTI || blockIdx.x >= ship_blocks) return false;
+  const uint32_t wpb = blockDim.x >> 6;  // waves per workgroup
+  ship_slots<false>(sh, blockIdx.x * wpb + (threadIdx.x >> 6), ship_blocks * wpb, nullptr);
+  return true;
+}
+
+// A send on its own (bolt_flush, readers of the store, many-map calls).
+__global__ __launch_bounds__(256) void k_acc_ship(ShipArgs a) {
+  extern __shared__ uint64_t sdyn[];
+  const uint32_t wv = threadIdx.x >> 6;
+  if (a.tags)
+    ship_slots<true>(a, blockIdx.x * 4 + wv, gridDim.x * 4, sdyn + (uint64_t)wv * a.pw);
+  else
+    ship_slots<false>(a, blockIdx.x * 4 + wv, gridDim.x * 4, nullptr);
+}
+
 // Commands are first split into kParts partitions by a hash of their key
 // (all commands of a key land in one partition); each partition is then
 // sorted and folded by its own workgroup.
@@ -667,71 +732,6 @@ __global__ __launch_bounds__(kDedupNT) void k_acc_group(GroupArgs a1, const Acce
       lastw[lead] = (wl != 0 && wl >= start) ? (sidx[wl - 1] >> 2) : kNone;
     }
   }
-}
-
-// ---------------------------------------------------------------------------
-// send of rebuilt observable pages
-// ---------------------------------------------------------------------------
-
-// The send of a batch's rebuilt observable pages to the store: wave `wave`
-// of `waves` takes the slots lo + wave, lo + wave + waves, ... below hi.  Plain maps copy the
-// page; sealed maps encrypt it in the wave's LDS page `pg` under the page's
-// next write count, tag it, and write page and tag.
-template <bool SEALED>
-__device__ __forceinline__ void ship_slots(const ShipArgs& a, uint32_t wave, uint32_t waves, uint64_t* pg) {
-  const uint32_t lane = threadIdx.x & 63;
-  uint32_t key[8];
-  if (SEALED) {
-#pragma unroll
-    for (int j = 0; j < 8; ++j) key[j] = a.ctl->skey[j];
-  }
-  for (uint32_t s = a.lo + wave; s < a.hi; s += waves) {
-    const uint32_t page = a.ship_page[s];
-    if (page == kNone) continue;  // whole wave
-    const uint64_t* src = a.outbox + (uint64_t)s * a.pw;
-    uint64_t* dst = a.obs + (uint64_t)page * a.pw;
-    if (!SEALED) {
-      for (uint64_t w = lane; w < a.pw; w += 64) dst[w] = src[w];
-      continue;
-    }
-    for (uint64_t w = lane; w < a.pw; w += 64) pg[w] = src[w];
-    const uint64_t ver = a.pver[page] + 1;
-    uint32_t tag[4];
-    seal_page(pg, (uint32_t)a.pw, key, page, ver, dst, tag);
-    if (lane == 0) {
-      a.tags[2 * (uint64_t)page] = (uint64_t)tag[0] | ((uint64_t)tag[1] << 32);
-      a.tags[2 * (uint64_t)page + 1] = (uint64_t)tag[2] | ((uint64_t)tag[3] << 32);
-      a.pver[page] = ver;
-    }
-    wave_sync();  // the wave's LDS page is reused by its next slot
-  }
-}
-
-// Workgroups (of 4 waves) of a send of n slots: one per 4 slots, at most
-// 256, so that the kernel it rides with keeps most of the device.
-constexpr uint32_t kShipMaxBlocks = 256;
-__host__ __device__ constexpr uint32_t ship_blocks_for(uint32_t n) {
-  return (n + 3) / 4 < kShipMaxBlocks ? (n + 3) / 4 : kShipMaxBlocks;
-}
-
-// Workgroups [0, ship_blocks) of a kernel that carries a slice of a send
-// (plain maps only: no LDS) do that and nothing else; true for them.
-template <bool MULTI>
-__device__ __forceinline__ bool carry_ship(const ShipArgs& sh, uint32_t ship_blocks) {
-  if (MULTI || blockIdx.x >= ship_blocks) return false;
-  const uint32_t wpb = blockDim.x >> 6;  // waves per workgroup
-  ship_slots<false>(sh, blockIdx.x * wpb + (threadIdx.x >> 6), ship_blocks * wpb, nullptr);
-  return true;
-}
-
-// A send on its own (bolt_flush, readers of the store, many-map calls).
-__global__ __launch_bounds__(256) void k_acc_ship(ShipArgs a) {
-  extern __shared__ uint64_t sdyn[];
-  const uint32_t wv = threadIdx.x >> 6;
-  if (a.tags)
-    ship_slots<true>(a, blockIdx.x * 4 + wv, gridDim.x * 4, sdyn + (uint64_t)wv * a.pw);
-  else
-    ship_slots<false>(a, blockIdx.x * 4 + wv, gridDim.x * 4, nullptr);
 }
 
 // ---------------------------------------------------------------------------
