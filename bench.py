@@ -198,7 +198,7 @@ def run_mode(args, wl, dev_t, B, torch, observable, seal=False):
 # kernel class -> (kernel in the rocprofv3 counter summary, sources it is built from)
 PROFILED = {
     "acc_ship": ("bolt::k_acc_ship", ("k_access.hip", "seal_dev.h", "bolt_dev.h", "bolt_impl.h")),
-    "acc_compose": ("bolt::k_acc_compose<false>", ("k_access.hip", "seal_dev.h", "bolt_dev.h", "bolt_impl.h")),
+    "acc_compose": ("bolt::k_acc_compose<false, false>", ("k_access.hip", "seal_dev.h", "bolt_dev.h", "bolt_impl.h")),
     "acc_fetch": ("bolt::k_acc_fetch<false, false>", ("k_access.hip", "seal_dev.h", "bolt_dev.h", "bolt_impl.h")),
     "sort_global": ("bolt::k_bitonic_global<*, false>", ("k_prim.hip", "bolt_dev.h", "bolt_impl.h")),
     "sort_merge": ("bolt::k_bitonic_tile<false>", ("k_prim.hip", "bolt_dev.h", "bolt_impl.h")),
