@@ -63,7 +63,7 @@ int derive(const bolt_params* p, Sizes* s) {
 uint64_t scratch_bytes(const Sizes& s) {
   const uint64_t Q = kMaxBatch;
   return Q * 4 * 13 + Q * s.vs + Q * 8 + 3 * Q * 4 + 2 * Q * s.page_bytes + 2 * Q * s.vs + 2 * Q + Q * 24 + 256 * 4 +
-         2 * Q * s.page_bytes + 2 * Q * 4;  // outbox + the page each of its slots sends
+         2 * (2 * Q * s.page_bytes + 2 * Q * 4);  // two outbox halves + the page each of their slots sends
 }
 
 uint64_t device_bytes(const bolt_params* p, const Sizes& s) {
@@ -251,8 +251,8 @@ int bolt_create(const bolt_params* p, void* hip_stream, bolt_map** out) {
   rc = rc ? rc : dalloc(m, &b.rpair, Q * 8);
   rc = rc ? rc : dalloc(m, &b.cand_bin, 3 * Q * 4);
   rc = rc ? rc : dalloc(m, &b.stage, 2 * Q * s.page_bytes);
-  rc = rc ? rc : dalloc(m, &b.outbox, 2 * Q * s.page_bytes);
-  rc = rc ? rc : dalloc(m, &b.ship_page, 2 * Q * 4);
+  rc = rc ? rc : dalloc(m, &b.outbox, 2 * 2 * Q * s.page_bytes);
+  rc = rc ? rc : dalloc(m, &b.ship_page, 2 * 2 * Q * 4);
   rc = rc ? rc : dalloc(m, &m->wslot, s.M * 8);
   rc = rc ? rc : dalloc(m, &b.fin, Q * 4);
   rc = rc ? rc : dalloc(m, &b.chosen, Q * 4);

@@ -24,8 +24,9 @@ struct BatchScratch {
   uint2* rpair;       // [Q] remap pair R(s) of each command
   uint32_t* cand_bin; // [3Q] bin each write-back candidate slot would rewrite, or kNone
   uint8_t* stage;     // [2Q * page_bytes] copies of the observable pages read
-  uint8_t* outbox;    // [2Q * page_bytes] observable pages rebuilt by the write-back, by slot
-  uint32_t* ship_page;  // [2Q] observable page each write-back slot sends to the store, or kNone
+  uint8_t* outbox;    // [2][2Q * page_bytes] observable pages rebuilt by the write-back, by slot; a batch uses
+                      // half (epoch & 1), so it rebuilds while the previous batch's half is still being sent
+  uint32_t* ship_page;  // [2][2Q] observable page each write-back slot sends to the store, or kNone
   uint32_t* fin;      // [Q] (leaders) bit 0 present at the end, bit 1 found in the map
   uint32_t* chosen;   // [Q] (leaders placed) bin chosen by P2C
   uint32_t* rowsel;   // [Q] (keys inserted) position-map row chosen
@@ -145,6 +146,7 @@ struct bolt_map {
   uint64_t* wslot;  // [M]
   uint32_t ship_q;     // commands of the batch whose pages are still to be sent, 0 = none
   uint32_t ship_from;  // its outbox slots [ship_from, 2 ship_q) are still to be sent
+  uint32_t ship_half;  // its half of the outbox (its epoch & 1)
   bool ov_off;        // next batch: no outbox pages (the store was changed from the host)
 };
 

@@ -213,13 +213,15 @@ struct WbArgs {
   uint64_t* st_used;
   uint32_t* freed;      // [kFreeBuckets] entries freed, summed by finish
   uint32_t* tlog_w;     // [3q] or null
-  uint64_t* outbox;     // [2Q][pw] rebuilt observable pages, by slot
-  uint32_t* ship_page;  // [2Q] page each slot sends, or kNone
+  uint64_t* outbox;     // [2Q][pw] rebuilt observable pages, by slot (this batch's half)
+  uint32_t* ship_page;  // [2Q] page each slot sends, or kNone (this batch's half)
   uint64_t* wslot;      // [M]
   uint32_t direct;      // 1: write observable pages to the store here (no send)
   uint64_t* obs;        // direct: the store
   uint64_t* tags;       // direct, BOLT_F_SEAL: [M][2] page tags, else null
   uint64_t* pver;       // direct, BOLT_F_SEAL: [M] page write counts
+  ShipArgs ship;  // a slice of the previous batch's send, by the first ship_blocks workgroups
+  uint32_t ship_blocks;
 };
 
 
@@ -1398,12 +1400,15 @@ __device__ __forceinline__ void compose_slot(const WbArgs& a, uint32_t s, uint64
 // and end at once, which frees wave slots early for the fetch slots [0, 2q)
 // (n in [q, 3q)).  Launched last, they waited for the first round of fetch
 // slots to end: a batch's 3q waves exceed what the device holds at once.
-// SEALED: some map of the launch seals its store.
+// The first ship_blocks workgroups send a slice of the previous batch's
+// pages (from the other half of the outbox).  SEALED: some map of the
+// launch seals its store.
 template <bool MULTI, bool SEALED>
 __global__ __launch_bounds__(64) void k_acc_compose(WbArgs a1, const AccessPlan* tab) {
   BOLT_PICK(WbArgs, wa);
   extern __shared__ uint64_t dyn[];
-  const uint32_t n = blockIdx.x;
+  if (carry_ship<MULTI>(a.ship, a.ship_blocks)) return;
+  const uint32_t n = blockIdx.x - (MULTI ? 0 : a.ship_blocks);
   const uint32_t s = n < a.q ? 2 * a.q + n : (n < 3 * a.q ? n - a.q : n);
   compose_slot<SEALED>(a, s, dyn);
 }
@@ -1563,8 +1568,8 @@ static ShipArgs ship_args(bolt_map* m, uint32_t lo, uint32_t hi) {
   a.lo = lo;
   a.hi = hi;
   a.pw = m->s.page_bytes / 8;
-  a.ship_page = m->bs.ship_page;
-  a.outbox = reinterpret_cast<const uint64_t*>(m->bs.outbox);
+  a.ship_page = m->bs.ship_page + (uint64_t)m->ship_half * 2 * kMaxBatch;
+  a.outbox = reinterpret_cast<const uint64_t*>(m->bs.outbox) + (uint64_t)m->ship_half * 2 * kMaxBatch * a.pw;
   a.obs = reinterpret_cast<uint64_t*>(m->obs);
   a.tags = reinterpret_cast<uint64_t*>(m->tags);
   a.pver = m->pver;
@@ -1648,7 +1653,8 @@ static void plan_access(bolt_map* m, const uint8_t* ops, const uint64_t* keys, c
   fa.tags = reinterpret_cast<const uint64_t*>(m->tags);
   fa.pver = m->pver;
   fa.wslot = m->wslot;
-  fa.outbox = reinterpret_cast<const uint64_t*>(bs.outbox);
+  // the previous batch's half of the outbox (the pages it rebuilt)
+  fa.outbox = reinterpret_cast<const uint64_t*>(bs.outbox) + (uint64_t)((epoch - 1) & 1) * 2 * kMaxBatch * fa.pw;
   fa.ov_epoch = m->ov_off ? 0 : epoch - 1;
   m->ov_off = false;
   fa.pre_host = m->obs_host ? 0 : 1;
@@ -1780,8 +1786,10 @@ static void plan_access(bolt_map* m, const uint8_t* ops, const uint64_t* keys, c
   wa.st_used = m->st_used;
   wa.freed = bs.freed;
   wa.tlog_w = tlog_w;
-  wa.outbox = reinterpret_cast<uint64_t*>(bs.outbox);
-  wa.ship_page = bs.ship_page;
+  wa.outbox = reinterpret_cast<uint64_t*>(bs.outbox) + (uint64_t)(epoch & 1) * 2 * kMaxBatch * (s.page_bytes / 8);
+  wa.ship_page = bs.ship_page + (uint64_t)(epoch & 1) * 2 * kMaxBatch;
+  wa.ship = ship_args(m, 0, 0);  // run_access hands it a slice of the previous batch's send
+  wa.ship_blocks = 0;
   wa.wslot = m->wslot;
   wa.direct = 1;  // run_access switches a large host-store batch to the send
   wa.obs = reinterpret_cast<uint64_t*>(m->obs);
@@ -1882,11 +1890,13 @@ static void allow_group_lds() {
 constexpr uint32_t kDeferMinBatch = 256;
 
 // Shares (in 64ths of a batch's outbox slots) of the send carried by the
-// batch's own finish and by the next batch's dedup, resolve and place
-// kernels: about what each writes over the link while it runs anyway
-// (4096-command batches, 1 KiB pages).  The next fetch carries the rest.
-// Sealed maps send from the fetch only (the send needs LDS there).
-constexpr uint32_t kShareFinish = 1, kShareGroup = 4, kShareResolve = 2, kSharePlace = 4;
+// batch's own finish and by the next batch's dedup, resolve, place and
+// rebuild kernels: about what each writes over the link while it runs
+// anyway (4096-command batches, 1 KiB pages).  The next fetch carries the
+// rest.  The next rebuild writes the other half of the outbox.  Sealed maps
+// send from the fetch only (the send needs LDS there).
+constexpr uint32_t kShareFinish = 1, kShareGroup = 4, kShareResolve = 2, kSharePlace = 4, kShareCompose = 8;
+constexpr uint32_t kShipComposeWaves = 256;  // waves of the rebuild launch that send
 
 int flush_ship(bolt_map* m, hipStream_t st) {
   if (!m->ship_q) return BOLT_OK;
@@ -1966,6 +1976,11 @@ int run_access(bolt_map* m, const uint8_t* ops, const uint64_t* keys, const void
   }
   const AccessPlan* none = nullptr;
   allow_group_lds();
+  // A large batch on a pinned host store rebuilds its observable pages into
+  // its half of the outbox, and the next batch's kernels (or a flush) send
+  // them.  Small batches and device stores, with no link time to hide, write
+  // them from the rebuild.
+  const bool defer = m->obs_host && q >= kDeferMinBatch;
   // The previous batch's rebuilt pages still to be sent, in slices: plain
   // maps spread them over this batch's dedup, resolve and place kernels
   // (each running anyway), the fetch takes the rest (writes over the link
@@ -1973,17 +1988,22 @@ int run_access(bolt_map* m, const uint8_t* ops, const uint64_t* keys, const void
   {
     const uint32_t end = 2 * m->ship_q;
     uint32_t lo = m->ship_from < end ? m->ship_from : end;
-    auto take = [&](uint32_t share, ShipArgs& a, uint32_t& blocks, uint32_t waves_per_block) {
+    auto take = [&](uint32_t share, ShipArgs& a, uint32_t& blocks, uint32_t waves_per_block, uint32_t max_waves) {
       const uint32_t n = end * share / 64, hi = lo + n < end ? lo + n : end;
       a = ship_args(m, lo, hi);
       blocks = (hi - lo + waves_per_block - 1) / waves_per_block;
-      if (blocks > kShipMaxBlocks / (waves_per_block / 4)) blocks = kShipMaxBlocks / (waves_per_block / 4);
+      if (blocks > max_waves / waves_per_block) blocks = max_waves / waves_per_block;
       lo = hi;
     };
     if (end && !m->tags) {
-      take(kShareGroup, P.gr.ship, P.gr.ship_blocks, kDedupNT / 64);
-      take(kShareResolve, P.rv.ship, P.rv.ship_blocks, 4);
-      if (P.fast) take(kSharePlace, P.pa.ship, P.pa.ship_blocks, 4);
+      take(kShareGroup, P.gr.ship, P.gr.ship_blocks, kDedupNT / 64, 4 * kShipMaxBlocks);
+      take(kShareResolve, P.rv.ship, P.rv.ship_blocks, 4, 4 * kShipMaxBlocks);
+      if (P.fast) take(kSharePlace, P.pa.ship, P.pa.ship_blocks, 4, 4 * kShipMaxBlocks);
+      // The rebuild's one-wave workgroups, a few slots per wave (its own
+      // waves already fill the device); only when this batch rebuilds into
+      // the outbox: a rebuild that writes the store itself could race the
+      // slice on a page both write.
+      if (defer) take(kShareCompose, P.wa.ship, P.wa.ship_blocks, 1, kShipComposeWaves);
     }
     P.fa.ship = ship_args(m, lo, end);
     P.fa.ship_blocks = ship_blocks_for(end - lo);
@@ -2014,20 +2034,18 @@ int run_access(bolt_map* m, const uint8_t* ops, const uint64_t* keys, const void
     else
       hipLaunchKernelGGL(k_acc_remap<false>, dim3(1), dim3(kRemapNT), 0, st, P.ra, none);
   }
-  // A large batch on a pinned host store rebuilds its observable pages into
-  // the outbox, and the next batch's fetch (or a flush) sends them.  Small
-  // batches and device stores, with no link time to hide, write them here.
-  const bool defer = m->obs_host && q >= kDeferMinBatch;
   P.wa.direct = defer ? 0 : 1;
   {
     TimedScope ts(m->timer, kkAccCompose, st);
     if (m->tags)
       hipLaunchKernelGGL((k_acc_compose<false, true>), dim3(3 * q), dim3(64), P.wb_lds, st, P.wa, none);
     else
-      hipLaunchKernelGGL((k_acc_compose<false, false>), dim3(3 * q), dim3(64), P.wb_lds, st, P.wa, none);
+      hipLaunchKernelGGL((k_acc_compose<false, false>), dim3(P.wa.ship_blocks + 3 * q), dim3(64), P.wb_lds, st,
+                         P.wa, none);
   }
   m->ship_q = defer ? q : 0;
   m->ship_from = 0;
+  m->ship_half = P.fa.epoch & 1;  // the half this batch rebuilt its pages into
   if (defer && !m->tags) {  // the finish starts this batch's send
     const uint32_t hi = 2 * q * kShareFinish / 64;
     P.fn.ship = ship_args(m, 0, hi);
