@@ -107,3 +107,28 @@ def test_deferred_pages_then_many_map_calls():
     for t in twins:
         assert t.g.status() == 0
         t.assert_same_state()
+
+
+def test_alternating_halves_with_hot_keys():
+    """Batches that rebuild into alternate halves of the outbox (and small
+    ones that write the store themselves) over a few hot keys, so that
+    consecutive batches rebuild the same pages while the previous batch's
+    are still being sent; no flush until the end."""
+    import torch
+
+    t = Twin(8192, 16)
+    k, v = workload(7500, 16, 4500)
+    assert t.build(k, v) == (0, 0, 0)
+    hot = k[:40]
+    rng = np.random.default_rng(4501)
+    sizes = [4096, 4096, 300, 255, 4096, 1, 2048, 256, 4096, 4096, 100, 4096]
+    for b, q in enumerate(sizes):
+        pick = np.where(rng.random(q) < 0.5, hot[rng.integers(0, hot.size, q)], k[rng.integers(0, k.size, q)])
+        ops = rng.choice([0, 1, 2], size=q, p=[0.5, 0.4, 0.1]).astype(np.uint8)
+        vals = rng.integers(0, 256, (q, 16), dtype=np.uint8)
+        rc_o, vo_o, st_o = t.o.access(ops, pick.astype(np.uint64), vals)
+        rc, out, st = _launch(t, ops, pick.astype(np.uint64), vals)
+        torch.cuda.synchronize()
+        assert rc_o == 0 and rc == 0, (b, rc_o, rc)
+        assert np.array_equal(st.cpu().numpy(), st_o) and np.array_equal(out.cpu().numpy(), vo_o), b
+    t.assert_same_state()
