@@ -32,6 +32,14 @@ HBM_PEAK_GBS = 8000.0   # MI355X HBM3E
 LINK_PEAK_GBS = 64.0    # PCIe 5.0 x16, per direction
 PEAKS = {"hbm": HBM_PEAK_GBS, "host_link": LINK_PEAK_GBS, "host_link_duplex": 2 * LINK_PEAK_GBS}
 
+# Share of a batch's page send that the next batch's fetch writes, for a plain
+# map: the library's other kernels carry slices (in 64ths: the batch's own
+# finish 1, the next dedup 4, resolve 2, place 4 and rebuild 8).  A sealed
+# map's fetch writes all of it.  tests/test_bench_host.py checks these
+# against the library's source.
+SEND_SLICES_64 = {"finish": 1, "group": 4, "resolve": 2, "place": 4, "compose": 8}
+FETCH_SEND_FRACTION = (64 - sum(SEND_SLICES_64.values())) / 64
+
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
@@ -39,8 +47,8 @@ def log(*a):
 
 def kernel_bytes(cls, sz, n, npad, n_ops, host_roles, send_share=0.0):
     """Algorithmic bytes of ONE launch of a kernel class on the resource that
-    bounds it.  `send_share` is the fraction of fetch launches that also
-    write the previous batch's rebuilt pages (pinned store, batches of 256
+    bounds it.  `send_share` is the fraction of the previous batch's rebuilt
+    pages that an average fetch launch writes (pinned store, batches of 256
     commands or more): those launches use both directions of the link.
 
     sort passes (HBM): read + write every 8-byte tag, 16 B x npad.
@@ -170,7 +178,8 @@ def run_mode(args, wl, dev_t, B, torch, observable, seal=False):
         if cnt == 0:
             continue
         ent = {"launches": cnt, "total_ms": round(ms, 3), "avg_us": round(1e3 * ms / cnt, 2)}
-        send_share = (nb - 1) / nb if (sz["host"] and n_ops / nb >= 256) else 0.0
+        carried = 1.0 if seal else FETCH_SEND_FRACTION
+        send_share = carried * (nb - 1) / nb if (sz["host"] and n_ops / nb >= 256) else 0.0
         per, bound = kernel_bytes(cls, sz, n, npad, n_ops / nb, host_roles / nb, send_share)
         if per is not None:
             gbs = per / (ms / cnt / 1e3) / 1e9
