@@ -1482,11 +1482,11 @@ __global__ __launch_bounds__(256) void k_acc_finish(FinishArgs a1, const AccessP
 // Three waves run the batched kernels' steps in their order; each step ends
 // at a workgroup barrier, which makes what the step stored or changed by
 // atomics in global memory visible to the whole workgroup (all its waves
-// share one CU and its L1).  The dedup of one command is
-// trivial; its two PRFs run on waves 1 and 2; fetch, resolve and place on
-// wave 0 (waves 1 and 2 warm L2 for the later steps meanwhile); the rebuild
-// of candidate slot s on wave s; then the insert and the counters.  A
-// wave's dynamic LDS for the rebuild is wb_stride bytes.
+// share one CU and its L1).  The dedup of one command is trivial; its two
+// PRFs run on waves 1 and 2; fetch, resolve and place on wave 0 (waves 1
+// and 2 warm L2 for the later steps meanwhile); the rebuild of candidate
+// slot s on wave s; then the insert and the counters.  A wave's dynamic LDS
+// for the rebuild is wb_stride bytes.
 constexpr uint32_t kSoloNT = 192;
 
 __device__ __forceinline__ void solo_step() { __syncthreads(); }
