@@ -133,3 +133,26 @@ def test_single_commands_without_trace():
     assert t.build(k, v) == (0, 0, 0)
     _stream(t, k, synth.keys(100, 52, offset=10**9), 200, 53)
     t.assert_same_state(trace=False)
+
+
+def test_timed_map_counts_the_one_command_kernel():
+    """BOLT_F_TIMING: a one-command batch is one launch of its own kernel
+    class, a larger batch one launch of each batched kernel; answers and
+    state as without timing."""
+    import paper_2509_01742_amd as B
+
+    t = Twin(2048, 16, flags=B.BOLT_F_TIMING)
+    k, v = workload(1500, 16, 61)
+    assert t.build(k, v) == (0, 0, 0)
+    t.g.kernel_times_reset()
+    _stream(t, k, synth.keys(50, 62, offset=10**9), 3, 63)
+    rng = np.random.default_rng(64)
+    ops = rng.choice([0, 1], size=300, p=[0.8, 0.2]).astype(np.uint8)
+    keys = k[rng.integers(0, k.size, 300)]
+    (rc_o, vo_o, st_o), (rc_g, st, vo_g, st_g) = t.access(ops, keys, rng.integers(0, 256, (300, 16), dtype=np.uint8))
+    assert rc_o == 0 and rc_g == 0 and st == 0
+    assert np.array_equal(st_g, st_o) and np.array_equal(vo_g, vo_o)
+    times = t.g.kernel_times()
+    assert times["acc_solo"][0] == 3
+    assert times["acc_fetch"][0] == 1 and times["acc_dedup"][0] == 1 and times["acc_compose"][0] == 1
+    t.assert_same_state()
