@@ -84,7 +84,12 @@ enum { BOLT_OBS_HOST_PINNED = 0, BOLT_OBS_DEVICE = 1 };
                                LE32(page) || LE64(its write count, kept in HBM); a page read whose tag does
                                not check poisons the map with BOLT_ETAMPER.  Pages up to 8 KiB. */
 #define BOLT_F_GRAPHS 8u    /* run one-map batches by replaying a HIP graph captured once per power-of-two batch
-                               size (fewer host launch calls; results identical).  Not with TRACE or TIMING. */
+                               size (fewer host launch calls; results identical).  Not with TIMING. */
+#define BOLT_F_SEAL_KEY_REUSE 64u /* tests only: allow BOLT_F_SEAL together with BOLT_F_FIXED_KEY.  The page key
+                               derives from the PRF key and every build starts the write counts at 1, so two maps
+                               sealed under one fixed key (or a map re-created with its key) encrypt with the same
+                               key streams and Poly1305 keys: their pages leak XORs of plain texts and accept
+                               forged tags.  Without this flag bolt_create refuses SEAL with FIXED_KEY. */
 
 #define BOLT_MAX_BATCH 8192u /* most commands in one access call */
 

@@ -59,7 +59,17 @@ def _load():
         from . import build as _build
 
         _build.build()
-    lib = C.CDLL(_LIB_PATH)
+    _lib = _configure(C.CDLL(_LIB_PATH))
+    return _lib
+
+
+def load_variant(path: str):
+    """Loads another build of the oracle's C source (the tests compile
+    copies with a planted mistake, to show that the pins catch it)."""
+    return _configure(C.CDLL(path))
+
+
+def _configure(lib):
     P, U8P, U32P, U64P = C.c_void_p, C.POINTER(C.c_uint8), C.POINTER(C.c_uint32), C.POINTER(C.c_uint64)
     lib.or_blake2s.argtypes = [P, C.c_uint32, P, C.c_uint32, P, C.c_uint64]
     lib.or_prf.argtypes = [P, C.c_uint8, C.c_uint64, P]
@@ -108,7 +118,6 @@ def _load():
     lib.or_poly1305.argtypes = [P, P, C.c_uint64, P]
     lib.or_aead_seal.argtypes = [P, P, P, C.c_uint64, P, C.c_uint64, P, P]
     lib.or_aead_open.argtypes = [P, P, P, C.c_uint64, P, C.c_uint64, P, P]
-    _lib = lib
     return lib
 
 
@@ -296,8 +305,8 @@ class PlainMap:
 
 class OracleMap:
     def __init__(self, cap, vs, c=8, alpha_pm=200, bin_slots=0, d=4, kpr=16, W=32, key=bytes(32),
-                 trace=False, seal=False):
-        lib = _load()
+                 trace=False, seal=False, lib=None):
+        lib = lib if lib is not None else _load()
         kb = (C.c_uint8 * 32).from_buffer_copy(bytes(key))
         self._h = lib.or_create(cap, vs, c, alpha_pm, bin_slots, d, kpr, W, kb, 1 if trace else 0)
         if not self._h:
@@ -396,6 +405,26 @@ class OracleMap:
         b = np.zeros(max(1, n), np.uint32)
         self._lib.or_pm_copy(self._h, _ptr(r), _ptr(k), _ptr(a), _ptr(b), n)
         return sorted((int(r[i]), int(k[i]), int(a[i]), int(b[i])) for i in range(n))
+
+    def stash_arrays(self):
+        """The stash as arrays (key u64[n], dest bin u32[n], values u8[n, vs]),
+        unsorted: for comparisons at sizes where a list of tuples is slow."""
+        n = int(self._lib.or_stash_copy(self._h, None, None, None, 0))
+        vs = self.s["vs"]
+        k, d = np.zeros(max(1, n), np.uint64), np.zeros(max(1, n), np.uint32)
+        v = np.zeros(max(1, n) * vs, np.uint8)
+        self._lib.or_stash_copy(self._h, _ptr(k), _ptr(d), _ptr(v), n)
+        return k[:n], d[:n], v[:n * vs].reshape(n, vs)
+
+    def pmap_arrays(self):
+        """The position map as arrays (row u64[n], key u64[n], p1 u32[n],
+        p2 u32[n]), unsorted."""
+        n = int(self._lib.or_pm_copy(self._h, None, None, None, None, 0))
+        m = max(1, n)
+        r, k = np.zeros(m, np.uint64), np.zeros(m, np.uint64)
+        a, b = np.zeros(m, np.uint32), np.zeros(m, np.uint32)
+        self._lib.or_pm_copy(self._h, _ptr(r), _ptr(k), _ptr(a), _ptr(b), n)
+        return r[:n], k[:n], a[:n], b[:n]
 
     def pm_max_row(self) -> int:
         return int(self._lib.or_pm_max_row(self._h))

@@ -21,6 +21,7 @@ BOLT_OP_GET, BOLT_OP_PUT, BOLT_OP_DEL = 0, 1, 2
 BOLT_ST_ABSENT, BOLT_ST_FOUND, BOLT_ST_UPDATED, BOLT_ST_INSERTED, BOLT_ST_DELETED = 0, 1, 1, 2, 3
 BOLT_OBS_HOST_PINNED, BOLT_OBS_DEVICE = 0, 1
 BOLT_F_TRACE, BOLT_F_FIXED_KEY, BOLT_F_TIMING, BOLT_F_GRAPHS, BOLT_F_WATCH, BOLT_F_SEAL = 1, 2, 4, 8, 16, 32
+BOLT_F_SEAL_KEY_REUSE = 64
 BOLT_MAX_BATCH = 8192
 BOLT_ETIMEOUT = -8
 BOLT_ETAMPER = -9
@@ -368,6 +369,33 @@ class Map:
                                a.ctypes.data_as(C.c_void_p), b.ctypes.data_as(C.c_void_p), n.value, C.byref(n)),
               "pm_snapshot")
         return sorted((int(r[i]), int(k[i]), int(a[i]), int(b[i])) for i in range(int(n.value)))
+
+    def stash_arrays(self):
+        """The stash as arrays (key u64[n], dest bin u32[n], values u8[n, vs]),
+        in the library's pool order."""
+        n = C.c_uint64()
+        check(bolt_stash_snapshot(self.h, None, None, None, 0, C.byref(n)), "stash_snapshot")
+        k = np.zeros(max(1, n.value), np.uint64)
+        b = np.zeros(max(1, n.value), np.uint32)
+        v = np.zeros(max(1, n.value) * self.vs, np.uint8)
+        check(bolt_stash_snapshot(self.h, k.ctypes.data_as(C.c_void_p), b.ctypes.data_as(C.c_void_p),
+                                  v.ctypes.data_as(C.c_void_p), n.value, C.byref(n)), "stash_snapshot")
+        c = int(n.value)
+        return k[:c], b[:c], v[:c * self.vs].reshape(c, self.vs)
+
+    def pmap_arrays(self):
+        """The position map as arrays (row u64[n], key u64[n], p1 u32[n],
+        p2 u32[n]), in the library's slot order."""
+        n = C.c_uint64()
+        check(bolt_pm_snapshot(self.h, None, None, None, None, 0, C.byref(n)), "pm_snapshot")
+        m = max(1, n.value)
+        r, k = np.zeros(m, np.uint64), np.zeros(m, np.uint64)
+        a, b = np.zeros(m, np.uint32), np.zeros(m, np.uint32)
+        check(bolt_pm_snapshot(self.h, r.ctypes.data_as(C.c_void_p), k.ctypes.data_as(C.c_void_p),
+                               a.ctypes.data_as(C.c_void_p), b.ctypes.data_as(C.c_void_p), n.value, C.byref(n)),
+              "pm_snapshot")
+        c = int(n.value)
+        return r[:c], k[:c], a[:c], b[:c]
 
 
 def build_many(maps, inputs, stream=None) -> int:

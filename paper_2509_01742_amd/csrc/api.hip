@@ -199,7 +199,10 @@ int bolt_create(const bolt_params* p, void* hip_stream, bolt_map** out) {
   int rc = derive(p, &s);
   if (rc) return rc;
   if ((p->flags & BOLT_F_TRACE) && p->trace_words == 0) return BOLT_EINVAL;
-  if ((p->flags & BOLT_F_GRAPHS) && (p->flags & (BOLT_F_TRACE | BOLT_F_TIMING))) return BOLT_EINVAL;
+  if ((p->flags & BOLT_F_GRAPHS) && (p->flags & BOLT_F_TIMING)) return BOLT_EINVAL;
+  // a fixed key would repeat the sealed store's key streams across maps
+  if ((p->flags & BOLT_F_SEAL) && (p->flags & BOLT_F_FIXED_KEY) && !(p->flags & BOLT_F_SEAL_KEY_REUSE))
+    return BOLT_EINVAL;
   if ((p->flags & BOLT_F_SEAL) && s.page_bytes > kMaxSealedPage) return BOLT_EINVAL;
   bolt_map* m = new (std::nothrow) bolt_map();
   if (!m) return BOLT_ENOMEM;

@@ -35,7 +35,9 @@ class Twin:
             if a in kw:
                 okw[b] = kw[a]
         self.p = B.params(cap, vs, key=key, observable=observable, **kw)
-        self.p.flags |= (B.BOLT_F_TRACE if trace else 0) | flags | (B.BOLT_F_SEAL if seal else 0)
+        # a sealed twin shares its fixed key with the oracle: a test-only reuse of the page key
+        self.p.flags |= (B.BOLT_F_TRACE if trace else 0) | flags | (
+            (B.BOLT_F_SEAL | B.BOLT_F_SEAL_KEY_REUSE) if seal else 0)
         self.g = B.Map(self.p)
         self.o = O.OracleMap(cap, vs, key=key, trace=trace, seal=seal, **okw)
         self.seal = seal

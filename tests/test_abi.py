@@ -77,3 +77,15 @@ def test_null_map_calls_are_rejected():
     assert B.bolt_build(None, None, None, 0, None) == B.BOLT_EINVAL
     assert B.bolt_access_batch(None, None, None, None, None, None, 1, None) == B.BOLT_EINVAL
     assert B.bolt_sort_u64(None, 4, None) == B.BOLT_EINVAL
+
+
+def test_sealing_under_a_fixed_key_needs_the_reuse_flag():
+    """A fixed PRF key fixes the page key, so sealed maps sharing it would
+    repeat key streams: bolt_create refuses that unless the caller says the
+    reuse is meant (tests only).  The check comes before any device call."""
+    import paper_2509_01742_amd as B
+
+    p = B.params(1024, 8, key=bytes(32))
+    p.flags |= B.BOLT_F_SEAL
+    h = C.c_void_p()
+    assert B.bolt_create(C.byref(p), None, C.byref(h)) == B.BOLT_EINVAL and not h.value

@@ -271,10 +271,12 @@ def test_access_capacity_errors():
 def test_access_parity_through_captured_graphs(observable):
     """BOLT_F_GRAPHS: every batch replays the graph of its size class.  Sizes
     cross the one-round / several-round threshold and revisit classes, and an
-    eager map's batches run between the replays; every replay is checked."""
+    eager map's batches run between the replays; every replay is checked, and
+    at the end the state and the whole trace of the replayed map (grids sized
+    for the class, each kernel stopping at the plan's q)."""
     import paper_2509_01742_amd as B
 
-    t = Twin(1 << 15, 16, trace=False, observable=observable, flags=B.BOLT_F_GRAPHS)
+    t = Twin(1 << 15, 16, observable=observable, flags=B.BOLT_F_GRAPHS)
     e = Twin(1 << 12, 8, trace=False)  # eager work between the replays
     k, v = workload(30000, 16, 77)
     ke, ve = workload(3000, 8, 78)
@@ -304,7 +306,7 @@ def test_access_parity_through_captured_graphs(observable):
                 pe.add(int(key))
             elif op == 2:
                 pe.discard(int(key))
-    t.assert_same_state(trace=False)
+    t.assert_same_state()  # the replays' trace too
     e.assert_same_state(trace=False)
 
 

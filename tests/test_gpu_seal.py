@@ -158,8 +158,8 @@ def test_sealed_and_plain_maps_together():
                                                                                          st_o)
     for t in twins:
         t.assert_same_state()
-    g = Twin(4096, 16, seal=True, trace=False, flags=B.BOLT_F_GRAPHS)
+    g = Twin(4096, 16, seal=True, flags=B.BOLT_F_GRAPHS)
     k, v = workload(3500, 16, 777)
     assert g.build(k, v) == (0, 0, 0)
     _run(g, k, 4096, 16, 8, 1000, 31)
-    g.assert_same_state(trace=False)
+    g.assert_same_state()
