@@ -458,6 +458,18 @@ int bolt_sort_u64(uint64_t* d_data, uint64_t n, void* hip_stream);
  * d_tmp[m] is scratch.  Results are undefined if the targets break the rule. */
 int bolt_expand_u64(uint64_t* d_elems, uint64_t* d_tmp, uint64_t m, void* hip_stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the
+ * expansion of bolt_expand_u64 without the d_tmp argument.  Its scratch is
+ * a static device array of BOLT_NOALLOC_EXPAND_MAX elements (16 MiB) that
+ * each GPU the library runs on holds until the process ends; the call
+ * itself allocates and frees nothing.  m > BOLT_NOALLOC_EXPAND_MAX (or
+ * m == 0, or a null d_elems) returns BOLT_EINVAL.  All calls on one GPU
+ * share that GPU's scratch: calls ordered on one stream are safe, calls
+ * that overlap on one GPU (different streams, several threads) race. */
+#define BOLT_NOALLOC_EXPAND_MAX (1ull << 21)
+int bolt_expand_u64_noalloc(uint64_t* d_elems, uint64_t m, void* hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

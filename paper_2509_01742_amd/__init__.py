@@ -23,6 +23,7 @@ BOLT_OBS_HOST_PINNED, BOLT_OBS_DEVICE = 0, 1
 BOLT_F_TRACE, BOLT_F_FIXED_KEY, BOLT_F_TIMING, BOLT_F_GRAPHS, BOLT_F_WATCH, BOLT_F_SEAL = 1, 2, 4, 8, 16, 32
 BOLT_F_SEAL_KEY_REUSE = 64
 BOLT_MAX_BATCH = 8192
+BOLT_NOALLOC_EXPAND_MAX = 1 << 21
 BOLT_ETIMEOUT = -8
 BOLT_ETAMPER = -9
 BOLT_SRV_WAITING, BOLT_SRV_BUILDING, BOLT_SRV_RESIDENT, BOLT_SRV_CLOSED, BOLT_SRV_FAILED = 0, 1, 2, 3, 4
@@ -150,6 +151,7 @@ _SIGS = [
     ("bolt_prf", _I, [_P, _U8, _P, _U64, _P, _P]),
     ("bolt_sort_u64", _I, [_P, _U64, _P]),
     ("bolt_expand_u64", _I, [_P, _P, _U64, _P]),
+    ("bolt_expand_u64_noalloc", _I, [_P, _U64, _P]),
 ]
 EXPORTED = [s[0] for s in _SIGS]
 
@@ -550,3 +552,7 @@ def sort_u64(data, stream=None) -> int:
 
 def expand_u64(elems, tmp, stream=None) -> int:
     return bolt_expand_u64(_dptr(elems), _dptr(tmp), elems.numel(), _stream(stream))
+
+
+def expand_u64_noalloc(elems, stream=None) -> int:
+    return bolt_expand_u64_noalloc(_dptr(elems), elems.numel(), _stream(stream))

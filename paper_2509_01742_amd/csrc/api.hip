@@ -7,6 +7,7 @@
 #include <sys/random.h>
 
 #include <algorithm>
+#include <mutex>
 #include <new>
 
 #include <vector>
@@ -713,6 +714,35 @@ int bolt_kernel_times_reset(bolt_map* m) {
   return BOLT_OK;
 }
 
+}  // extern "C"
+
+// Scratch of the allocation-free expansion: one static array per device,
+// held until the process ends.  In host code `scratch` names a host-side
+// stand-in, so its device address is looked up once per device (with that
+// device current) and only that address is handed to kernels.
+static __device__ __align__(256) uint64_t scratch[BOLT_NOALLOC_EXPAND_MAX];
+
+namespace {
+constexpr int kScratchDevices = 64;
+std::mutex g_scratch_mu;
+uint64_t* g_scratch_ptr[kScratchDevices];
+}  // namespace
+
+static int noalloc_scratch(uint64_t** out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kScratchDevices) return BOLT_EHIP;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return BOLT_EHIP;
+    g_scratch_ptr[dev] = static_cast<uint64_t*>(ptr);
+  }
+  *out = g_scratch_ptr[dev];
+  return BOLT_OK;
+}
+
+extern "C" {
+
 int bolt_prf(const uint8_t* host_key, uint8_t domain, const uint64_t* d_x, uint64_t n, uint64_t* d_out,
              void* hip_stream) {
   if (!host_key || (n && (!d_x || !d_out))) return BOLT_EINVAL;
@@ -735,6 +765,16 @@ int bolt_sort_u64(uint64_t* d_data, uint64_t n, void* hip_stream) {
 int bolt_expand_u64(uint64_t* d_elems, uint64_t* d_tmp, uint64_t m, void* hip_stream) {
   if (!d_elems || !d_tmp || m == 0 || m > (1ull << 32)) return BOLT_EINVAL;
   launch_expand(d_elems, d_tmp, m, (hipStream_t)hip_stream);
+  return hipGetLastError() == hipSuccess ? BOLT_OK : BOLT_EHIP;
+}
+
+int bolt_expand_u64_noalloc(uint64_t* d_elems, uint64_t m, void* hip_stream) {
+  if (!d_elems || m == 0) return BOLT_EINVAL;
+  if (m > BOLT_NOALLOC_EXPAND_MAX) return BOLT_EINVAL;  // larger than the static scratch
+  uint64_t* tmp = nullptr;
+  const int rc = noalloc_scratch(&tmp);
+  if (rc) return rc;
+  launch_expand(d_elems, tmp, m, (hipStream_t)hip_stream);
   return hipGetLastError() == hipSuccess ? BOLT_OK : BOLT_EHIP;
 }
 
