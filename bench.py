@@ -810,7 +810,7 @@ def run_dynamics(B, torch, accesses, log2n=20, batch=4096, seed=0xB0170000 + 61)
             secs = time.perf_counter() - t0
             sz = m.sizes
             s_ = m.stats()  # a poisoned map still reports its counters and watch marks
-            K, M, Z = sz["K"], sz["M"], sz["Z"]
+            K, M, Z = sz["K"], sz["M"], sz["lmax"]  # the bounds use l_max (the pages hold Z >= l_max)
             a = alpha_pm / 1000.0
             b43 = K * c + Z * math.sqrt(K * math.log(n))
             b44 = (1 + a) * M / 2 + Z * math.sqrt(M * math.log(n))

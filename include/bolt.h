@@ -98,7 +98,8 @@ typedef struct {
   uint32_t value_bytes;    /* vs: bytes per value, a multiple of 8; a page (8 + Z (8 + vs) bytes) must fit 32 KiB */
   uint32_t c;              /* mean bin load N/(K+M) (Claim 4.2); the paper's default is 8 */
   uint32_t alpha_permille; /* alpha = K/(K+M) in 1/1000 (Claim 4.4); default 200, below 1000 */
-  uint32_t bin_slots;      /* Z, items per bin; 0 = c + ceil(log2 ceil(log2 N_max)) + 1 (Claim 4.2) */
+  uint32_t bin_slots;      /* Z, items per bin; 0 = l_max = c + ceil(log2 ceil(log2 N_max)) + 1 (Claim 4.2), plus
+                              one when B <= 64 * BOLT_MAX_BATCH (a batch can fill 1/64 of a placement round) */
   uint32_t pm_choices;     /* d, position-map rows a key may use (Sec. 5.2); 1..4, default 4 */
   uint32_t pm_keys_per_row;/* N_max / rows of the position map (Sec. 5.2); default 16 */
   uint32_t pm_row_slots;   /* slots per position-map row, 1..32; default 32 */
@@ -116,8 +117,9 @@ typedef struct {
   uint64_t Z;           /* items per bin (page capacity) */
   uint64_t page_bytes;  /* bytes per page: u64 valid mask, Z keys, Z values, zero pad to 128 */
   uint64_t pm_rows;     /* position-map rows = ceil(N_max / pm_keys_per_row) */
-  uint64_t stash_bound; /* ceil((1 + alpha) M / 2 + Z sqrt(M ln N_max)) (Claim 4.4, constant 1) */
+  uint64_t stash_bound; /* ceil((1 + alpha) M / 2 + l_max sqrt(M ln N_max)) (Claim 4.4, constant 1) */
   uint64_t stash_pool;  /* stash entries allocated: stash_bound + BOLT_MAX_BATCH */
+  uint64_t lmax;        /* l_max = c + ceil(log2 ceil(log2 N_max)) + 1, the bound of Claim 4.2 (constant 1) */
 } bolt_sizes;
 
 /* Fills p with the paper's defaults (c = 8, alpha = 0.2, d = 4, 16 keys per

@@ -39,7 +39,7 @@ class _Sizes(C.Structure):
         ("cap", C.c_uint64), ("vs", C.c_uint32), ("c", C.c_uint32), ("alpha_pm", C.c_uint32),
         ("Z", C.c_uint32), ("d", C.c_uint32), ("kpr", C.c_uint32), ("W", C.c_uint32),
         ("B", C.c_uint64), ("K", C.c_uint64), ("M", C.c_uint64), ("R_pm", C.c_uint64),
-        ("page_bytes", C.c_uint64), ("stash_bound", C.c_uint64),
+        ("page_bytes", C.c_uint64), ("stash_bound", C.c_uint64), ("lmax", C.c_uint32),
     ]
 
     def as_dict(self) -> dict:

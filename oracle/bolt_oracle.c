@@ -346,6 +346,7 @@ typedef struct {
   uint64_t R_pm;       /* position-map rows */
   uint64_t page_bytes; /* bytes per page and per HBM bin */
   uint64_t stash_bound;/* Claim 4.4 with the O() constant set to 1 */
+  uint32_t lmax;       /* l_max of Claim 4.2 with the O() constant set to 1 */
 } or_sizes;
 
 static uint32_t or_ceil_log2(uint64_t x) {
@@ -392,12 +393,18 @@ int or_sizing(uint64_t cap, uint32_t vs, uint32_t c, uint32_t alpha_pm, uint32_t
   s->K = (uint64_t)alpha_pm * s->B / 1000;
   s->M = s->B - s->K;
   /* l_max = c + O(log2 log2 N) with the constant 1 (Claim 4.2). */
-  s->Z = bin_slots ? bin_slots : c + or_ceil_log2(or_ceil_log2(cap)) + 1;
+  s->lmax = c + or_ceil_log2(or_ceil_log2(cap)) + 1;
+  /* The default capacity is l_max, plus one slot when a batch can fill a
+   * sizeable part of a placement round: batches place their keys in rounds
+   * that all see the loads at the round's start, and a round of B/64 keys
+   * or more (B <= 64 * 8192, the largest batch) lifts the tail of the bin
+   * loads by one over one-at-a-time placement. */
+  s->Z = bin_slots ? bin_slots : s->lmax + (s->B <= 64ull * 8192 ? 1 : 0);
   if (s->Z == 0 || s->Z > 64) return -1;
   s->R_pm = (cap + kpr - 1) / kpr;
   uint64_t raw = 8 + 8ull * s->Z + (uint64_t)vs * s->Z;
   s->page_bytes = (raw + 127) / 128 * 128;
-  s->stash_bound = or_stash_bound(s->M, alpha_pm, s->Z, cap);
+  s->stash_bound = or_stash_bound(s->M, alpha_pm, s->lmax, cap);
   return 0;
 }
 

@@ -49,7 +49,8 @@ class bolt_params(C.Structure):
 
 
 class bolt_sizes(C.Structure):
-    _fields_ = [(n, C.c_uint64) for n in ("B", "K", "M", "Z", "page_bytes", "pm_rows", "stash_bound", "stash_pool")]
+    _fields_ = [(n, C.c_uint64) for n in ("B", "K", "M", "Z", "page_bytes", "pm_rows", "stash_bound", "stash_pool",
+                                          "lmax")]
 
     def as_dict(self):
         return {n: int(getattr(self, n)) for n, _ in self._fields_}

@@ -39,7 +39,12 @@ int derive(const bolt_params* p, Sizes* s) {
   while ((1ull << l1) < p->capacity) ++l1;
   uint32_t l2 = 0;
   while ((1u << l2) < l1) ++l2;
-  z.Z = p->bin_slots ? p->bin_slots : p->c + l2 + 1;  // l_max of Claim 4.2 with constant 1
+  z.lmax = p->c + l2 + 1;  // l_max of Claim 4.2 with constant 1
+  // Default capacity: l_max, plus one slot when the largest batch fills at
+  // least 1/64 of the bins in one placement round (B <= 64 * 8192).  Keys of
+  // a round all choose on the loads at the round's start, which lifts the
+  // tail of the bin loads by one over one-at-a-time placement at such fills.
+  z.Z = p->bin_slots ? p->bin_slots : z.lmax + (z.B <= 64ull * kMaxBatch ? 1 : 0);
   if (z.Z == 0 || z.Z > kMaxZ) return BOLT_EINVAL;
   z.W = p->pm_row_slots;
   z.d = p->pm_choices;
@@ -48,7 +53,7 @@ int derive(const bolt_params* p, Sizes* s) {
   z.page_bytes = (raw + 127) / 128 * 128;
   if (z.page_bytes > kMaxPageBytes) return BOLT_EINVAL;
   double a = (double)p->alpha_permille / 1000.0;
-  double x = (1.0 + a) * (double)z.M / 2.0 + (double)z.Z * sqrt((double)z.M * log((double)p->capacity));
+  double x = (1.0 + a) * (double)z.M / 2.0 + (double)z.lmax * sqrt((double)z.M * log((double)p->capacity));
   z.stash_bound = (uint64_t)ceil(x);
   z.P = z.stash_bound + kMaxBatch;
   z.BZ = z.B * z.Z;
@@ -180,6 +185,7 @@ int bolt_sizes_of(const bolt_params* p, bolt_sizes* out) {
     out->pm_rows = s.R;
     out->stash_bound = s.stash_bound;
     out->stash_pool = s.P;
+    out->lmax = s.lmax;
   }
   return BOLT_OK;
 }

@@ -83,7 +83,7 @@ struct TimedScope {
 };
 
 struct Sizes {
-  uint64_t cap, B, K, M, Z, W, d, R, page_bytes, stash_bound, P, BZ, PW;
+  uint64_t cap, B, K, M, Z, W, d, R, page_bytes, stash_bound, P, BZ, PW, lmax;
   uint32_t vs;
 };
 

@@ -30,6 +30,7 @@ def test_library_exports_every_declared_symbol():
 @pytest.mark.parametrize("cap,vs,kw", [
     (1 << 16, 8, {}), ((1 << 24) + (1 << 16), 64, {}), (1 << 26, 8, {}), (1000, 16, dict(alpha_permille=0)),
     (12345, 24, dict(alpha_permille=999, c=4)), (1 << 20, 8, dict(c=16)), (4096, 8, dict(bin_slots=20)),
+    (1 << 22, 64, {}), ((1 << 22) + 8, 64, {}), (1 << 23, 8, dict(c=16)),
     (777, 8, dict(pm_keys_per_row=4, pm_row_slots=8, pm_choices=2))])
 def test_sizes_agree_with_oracle(cap, vs, kw):
     import paper_2509_01742_amd as B
@@ -38,8 +39,8 @@ def test_sizes_agree_with_oracle(cap, vs, kw):
     s = B.sizes_of(p)
     o = O.sizing(cap, vs, c=p.c, alpha_pm=p.alpha_permille, bin_slots=p.bin_slots, d=p.pm_choices,
                  kpr=p.pm_keys_per_row, W=p.pm_row_slots)
-    assert (s["B"], s["K"], s["M"], s["Z"], s["page_bytes"], s["pm_rows"], s["stash_bound"]) == (
-        o["B"], o["K"], o["M"], o["Z"], o["page_bytes"], o["R_pm"], o["stash_bound"])
+    assert (s["B"], s["K"], s["M"], s["Z"], s["page_bytes"], s["pm_rows"], s["stash_bound"], s["lmax"]) == (
+        o["B"], o["K"], o["M"], o["Z"], o["page_bytes"], o["R_pm"], o["stash_bound"], o["lmax"])
     assert s["stash_pool"] == s["stash_bound"] + B.BOLT_MAX_BATCH
 
 

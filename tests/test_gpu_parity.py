@@ -310,10 +310,22 @@ def test_access_parity_through_captured_graphs(observable):
     e.assert_same_state(trace=False)
 
 
+def _oracle_marks(o, K, marks):
+    """The bound marks after a batch, from the oracle's state: the largest
+    bin load, the items of the K HBM bins, their high-water marks, and the
+    stash high-water mark."""
+    ld = o.loads().astype(np.int64)
+    hbm = int(ld[:K].sum())
+    marks["load_hw"] = max(marks.get("load_hw", 0), int(ld.max()))
+    marks["hbm_hw"] = max(marks.get("hbm_hw", 0), hbm)
+    return int(ld.max()), hbm
+
+
 def test_watch_marks_follow_every_batch():
     """BOLT_F_WATCH: after each batch the map reports the largest bin load
-    and the items of its HBM bins, with high-water marks; checked against the
-    loads read back after every batch, with the state still the oracle's."""
+    and the items of its HBM bins, with high-water marks.  Every mark is
+    compared after every batch with the same quantities computed from the
+    oracle's loads, and the stash high-water mark with the oracle's."""
     import paper_2509_01742_amd as B
 
     t = Twin(1 << 14, 8, trace=False, flags=B.BOLT_F_WATCH, alpha_permille=300)
@@ -323,7 +335,7 @@ def test_watch_marks_follow_every_batch():
     rng = np.random.default_rng(5)
     fresh = synth.keys(20000, 4244, offset=10**8)
     present = set(int(x) for x in k)
-    hw_load = hw_hbm = 0
+    marks = {}
     for b in range(12):
         q = int(rng.integers(1, 3000))
         ops, keys, vals = _mixed_batch(rng, present, fresh, q, 8)
@@ -336,11 +348,41 @@ def test_watch_marks_follow_every_batch():
                 present.add(int(key))
             elif op == 2:
                 present.discard(int(key))
-        ld = t.g.loads().astype(np.int64)
-        hw_load = max(hw_load, int(ld.max()))
-        hbm = int(ld[:K].sum())
-        hw_hbm = max(hw_hbm, hbm)
+        mx, hbm = _oracle_marks(t.o, K, marks)
         s = t.g.stats()
-        assert s["hbm_load"] == hbm and s["hbm_load_highwater"] == hw_hbm, b
-        assert s["load_highwater"] == hw_load and s["max_load"] == int(ld.max()), b
+        assert s["hbm_load"] == hbm and s["hbm_load_highwater"] == marks["hbm_hw"], b
+        assert s["load_highwater"] == marks["load_hw"] and s["max_load"] == mx, b
+        assert s["stash_highwater"] == t.o.stash_highwater, b
+    t.assert_same_state(trace=False)
+
+
+@pytest.mark.parametrize("c,alpha", [(8, 200), (16, 500), (16, 10)])
+def test_dynamics_marks_match_the_oracle(c, alpha):
+    """The bound validation's setting (Sec. 4.3, dimensions in practice) at a
+    size the oracle runs in seconds: N = 2^16 keys, a long stream of uniform
+    GETs in batches of 4096 on the device store; after every batch the
+    GPU's marks (largest bin load, HBM-bin items, their high-water marks,
+    the stash high-water mark) equal those of the oracle's state, and at the
+    end the whole state does."""
+    import paper_2509_01742_amd as B
+
+    n = 1 << 16
+    t = Twin(n, 8, trace=False, observable=B.BOLT_OBS_DEVICE, flags=B.BOLT_F_WATCH, c=c, alpha_permille=alpha)
+    k, v = workload(n, 8, 300 + c + alpha)
+    assert t.build(k, v) == (0, 0, 0)
+    K = t.g.sizes["K"]
+    rng = np.random.default_rng(c * 1000 + alpha)
+    marks = {}  # high-water marks over batch ends (the build's loads are not among them)
+    ops = np.zeros(4096, np.uint8)
+    vals = np.zeros((4096, 8), np.uint8)
+    for b in range(48):
+        keys = k[rng.integers(0, n, 4096)]
+        (rc_o, vo_o, st_o), (rc_g, st, vo_g, st_g) = t.access(ops, keys, vals)
+        assert rc_o == 0 and rc_g == 0 and st == 0 and np.array_equal(vo_g, vo_o) and (st_g == 1).all()
+        mx, hbm = _oracle_marks(t.o, K, marks)
+        s = t.g.stats()
+        assert (s["max_load"], s["load_highwater"], s["hbm_load"], s["hbm_load_highwater"]) == (
+            mx, marks["load_hw"], hbm, marks["hbm_hw"]), b
+        assert s["stash_highwater"] == t.o.stash_highwater and s["stash_live"] == t.o.stash_live, b
+        assert mx <= t.g.sizes["Z"] and t.o.stash_highwater <= t.g.sizes["stash_bound"]
     t.assert_same_state(trace=False)

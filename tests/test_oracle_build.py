@@ -139,7 +139,7 @@ def test_max_load_at_2_20_within_lmax():
     k, v = _data(n, 8, 5)
     assert m.build(k, v, mode=1) == O.OK
     mx = int(m.loads().max())
-    assert mx <= m.s["Z"] == 14
+    assert mx <= m.s["lmax"] == 14
     assert mx >= 10  # P2C, not a perfect spread
 
 

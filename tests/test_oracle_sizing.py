@@ -25,9 +25,22 @@ def _table():
 def test_bin_capacity_matches_slack_table(c, lmax):
     t = _table()
     s = O.sizing(t["N"], 8, c=c, alpha_pm=200)
-    assert s["Z"] == lmax
+    assert s["lmax"] == lmax
     for abs_slack, rel in t["c"][str(c)]["bin_load"]:
-        assert abs(abs_slack / s["Z"] - rel) < 0.0015
+        assert abs(abs_slack / s["lmax"] - rel) < 0.0015
+    # at N = 2^20 a batch fills a sizeable part of a placement round
+    # (B <= 2^19): the default capacity keeps one slot above l_max
+    assert s["B"] <= 1 << 19 and s["Z"] == lmax + 1
+
+
+def test_default_capacity_margin_follows_the_round_fill():
+    """One slot above l_max exactly when B <= 64 * 8192 (the largest batch
+    then fills at least 1/64 of the bins in one placement round)."""
+    for cap, c in ((1 << 16, 8), (1 << 20, 16), (1 << 22, 8), ((1 << 22) + 8, 8), (1 << 23, 16), (1 << 24, 8),
+                   ((1 << 24) + (1 << 16), 8), (1 << 26, 8)):
+        s = O.sizing(cap, 8, c=c)
+        assert s["Z"] == s["lmax"] + (1 if s["B"] <= 64 * 8192 else 0), (cap, c)
+        assert O.sizing(cap, 8, c=c, bin_slots=s["lmax"])["Z"] == s["lmax"]  # an explicit capacity is kept
 
 
 @pytest.mark.parametrize("c", [8, 16])
@@ -37,7 +50,7 @@ def test_hbm_load_bound_matches_slack_table(c):
     t = _table()
     N = t["N"]
     B = N / c
-    lmax = O.sizing(N, 8, c=c)["Z"]
+    lmax = O.sizing(N, 8, c=c)["lmax"]
     for alpha, (abs_slack, rel) in zip(t["alphas"], t["c"][str(c)]["hbm_load"]):
         bound = O.claim43_bound(alpha * B, c, lmax, N)
         emp = bound - abs_slack
@@ -54,7 +67,7 @@ def test_stash_bound_matches_slack_table(c):
     t = _table()
     N = t["N"]
     B = N / c
-    lmax = O.sizing(N, 8, c=c)["Z"]
+    lmax = O.sizing(N, 8, c=c)["lmax"]
     for alpha, (abs_slack, rel) in zip(t["alphas"], t["c"][str(c)]["stash"]):
         M = (1 - alpha) * B
         bound = O.claim44_bound(M, alpha, lmax, N)
@@ -66,7 +79,7 @@ def test_integer_stash_bound_is_claim44_rounded_up():
     for cap, vs, alpha in ((1 << 16, 8, 200), ((1 << 24) + (1 << 16), 64, 200), (1 << 26, 8, 200),
                            (1 << 20, 8, 10), (1 << 20, 8, 500), (1000, 8, 0)):
         s = O.sizing(cap, vs, alpha_pm=alpha)
-        exact = O.claim44_bound(s["M"], alpha / 1000, s["Z"], cap)
+        exact = O.claim44_bound(s["M"], alpha / 1000, s["lmax"], cap)
         assert s["stash_bound"] == math.ceil(exact)
 
 
@@ -89,7 +102,8 @@ def test_claim52_example():
 
 def test_sizing_formulas_on_configs():
     s = O.sizing(1 << 16, 8)
-    assert (s["B"], s["K"], s["M"], s["Z"], s["page_bytes"], s["R_pm"]) == (8192, 1638, 6554, 13, 256, 4096)
+    assert (s["B"], s["K"], s["M"], s["lmax"], s["Z"], s["page_bytes"], s["R_pm"]) == (
+        8192, 1638, 6554, 13, 14, 256, 4096)
     s = O.sizing((1 << 24) + (1 << 16), 64)
     assert (s["B"], s["K"], s["M"], s["Z"], s["page_bytes"]) == (2105344, 421068, 1684276, 14, 1024)
     s = O.sizing(1 << 26, 8)
