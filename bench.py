@@ -833,13 +833,40 @@ def run_dynamics(B, torch, accesses, log2n=20, batch=4096, seed=0xB0170000 + 61)
     return out
 
 
-def cpu_baseline(n_batches):
-    """The oracle (single thread, as it stands) on a bounded sample: the same
-    workload scaled to N=2^20 (64-byte values, Zipf 0.99, 5 % absent, 90/10),
-    its build plus n_batches batches of 4096."""
+def host_cpu():
+    """The host's core count (all of them and those this process may use)
+    and CPU model, from the kernel's own tables."""
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.lower().startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        usable = os.cpu_count()
+    return {"nproc": os.cpu_count(), "usable_cores": usable, "model": model,
+            "omp_num_threads": os.environ.get("OMP_NUM_THREADS")}
+
+
+def cpu_baseline(n_batches, full_batches=64):
+    """CPU baselines on the GPU machine's host cores, as they stand:
+    * the oracle (O2, scalar C, one thread) on a bounded sample: the same
+      workload scaled to N=2^20 (64-byte values, Zipf 0.99, 5 % absent,
+      90/10), its build plus n_batches batches of 4096 (the headline
+      baseline);
+    * the same oracle built with OpenMP over all usable cores, on the real
+      config-2 size (N=2^24 + 2^16 capacity): build plus full_batches
+      batches of 4096;
+    * the plain definition O1 (a C hash table, one thread) on the same
+      full-size workload."""
     import oracle as O
     import synth
 
+    host = host_cpu()
     n = 1 << 20
     wl = synth.config2(n=n, n_ops=n_batches * 4096, batch=4096, headroom=1 << 16)
     m = O.OracleMap(wl.cap, wl.vs, key=bytes(range(32)))
@@ -851,10 +878,47 @@ def cpu_baseline(n_batches):
         rc, _, _ = m.access(ops, ks, vs_)
         assert rc == 0
     tq = time.perf_counter() - t
-    return {"value": round(wl.n_ops / tq, 1), "unit": "ops/s", "cores": 1, "kind": "oracle",
+    m.close()
+    del wl
+    log("cpu baseline: oracle, one thread, N=2^20: build %.1fs, %d batches %.1fs" % (tb, n_batches, tq))
+
+    full = synth.config2(n_batches=full_batches)
+    om = O.OracleMap(full.cap, full.vs, key=bytes(range(32)), lib=O.load_openmp())
+    t = time.perf_counter()
+    assert om.build(full.build_keys, full.build_vals) == 0
+    otb = time.perf_counter() - t
+    t = time.perf_counter()
+    for ops, ks, vs_ in full.batches:
+        assert om.access(ops, ks, vs_)[0] == 0
+    otq = time.perf_counter() - t
+    om.close()
+    log("cpu baseline: oracle with OpenMP, N=2^24: build %.1fs, %d batches %.1fs" % (otb, full_batches, otq))
+
+    pc = O.PlainMapC(full.cap, full.vs)
+    t = time.perf_counter()
+    assert pc.build(full.build_keys, full.build_vals) == 0
+    ptb = time.perf_counter() - t
+    t = time.perf_counter()
+    for ops, ks, vs_ in full.batches:
+        assert pc.access(ops, ks, vs_)[0] == 0
+    ptq = time.perf_counter() - t
+    pc.close()
+    n_full = full.n_ops
+    return {"value": round(n_batches * 4096 / tq, 1), "unit": "ops/s", "cores": 1, "kind": "oracle",
             "build_keys_per_s": round(n / tb, 1),
             "sample": "oracle (scalar C, one thread) on the same workload scaled to N=2^20: build of 2^20 keys "
-                      "(%.1fs) then %d batches of 4096 commands (%.1fs)" % (tb, n_batches, tq)}
+                      "(%.1fs) then %d batches of 4096 commands (%.1fs)" % (tb, n_batches, tq),
+            "host": host,
+            "openmp": {"ops_per_s": round(n_full / otq, 1), "build_keys_per_s": round(full.n / otb, 1),
+                       "cores": host["usable_cores"] if not host["omp_num_threads"] else
+                       min(host["usable_cores"], int(host["omp_num_threads"])),
+                       "kind": "oracle built with OpenMP",
+                       "sample": "config 2 at full size: build of 2^24 keys (%.1fs) then %d batches of 4096 "
+                                 "commands (%.1fs)" % (otb, full_batches, otq)},
+            "plain_o1": {"ops_per_s": round(n_full / ptq, 1), "build_keys_per_s": round(full.n / ptb, 1),
+                         "cores": 1, "kind": "plain definition (C hash table, not oblivious)",
+                         "sample": "config 2 at full size: 2^24 inserts (%.2fs) then %d batches of 4096 "
+                                   "commands (%.2fs)" % (ptb, full_batches, ptq)}}
 
 
 if __name__ == "__main__":

@@ -85,6 +85,8 @@ enum { BOLT_OBS_HOST_PINNED = 0, BOLT_OBS_DEVICE = 1 };
                                not check poisons the map with BOLT_ETAMPER.  Pages up to 8 KiB. */
 #define BOLT_F_GRAPHS 8u    /* run one-map batches by replaying a HIP graph captured once per power-of-two batch
                                size (fewer host launch calls; results identical).  Not with TIMING. */
+#define BOLT_F_SEAL_CMDS 128u /* commands and responses cross the host sealed: bolt_access_sealed and
+                               bolt_server_submit_sealed take ChaCha20-Poly1305 records under params.session_key */
 #define BOLT_F_SEAL_KEY_REUSE 64u /* tests only: allow BOLT_F_SEAL together with BOLT_F_FIXED_KEY.  The page key
                                derives from the PRF key and every build starts the write counts at 1, so two maps
                                sealed under one fixed key (or a map re-created with its key) encrypt with the same
@@ -107,6 +109,10 @@ typedef struct {
   uint32_t flags;          /* BOLT_F_* */
   uint64_t trace_words;    /* capacity of the trace log in 32-bit words (BOLT_F_TRACE) */
   uint8_t key[32];         /* PRF key when BOLT_F_FIXED_KEY is set */
+  uint8_t session_key[32]; /* BOLT_F_SEAL_CMDS: the key the user and the map share for command and response
+                              records.  It stands in for a key provisioned into the device by attestation,
+                              which the paper assumes and does not build; it is copied to device memory at
+                              bolt_create. */
 } bolt_params;
 
 /* Sizes the library derives from the parameters (all integers). */
@@ -387,6 +393,18 @@ int bolt_server_submit(bolt_server* srv, uint32_t map_id, const uint8_t* host_op
                        const void* host_vals_in, void* host_vals_out, uint8_t* host_status, uint32_t q,
                        uint64_t arrival_ns, uint64_t* ticket);
 
+/* A sealed request for a map opened with BOLT_F_SEAL_CMDS (Sec. 3 and
+ * Sec. 5.1: the host relays only sealed commands and results): q command
+ * records in, q response records out (host buffers, valid until the
+ * request completes; layout under bolt_access_sealed).  The map's k-th
+ * sealed request is request number k of its session.  Such maps take no
+ * plain requests (bolt_server_submit returns BOLT_EINVAL for them).  The
+ * host cannot read the op codes: a record with one above BOLT_OP_DEL
+ * rejects the coalesced batch it runs in, and a record that fails its tag
+ * poisons the map (its requests then fail with BOLT_ETAMPER). */
+int bolt_server_submit_sealed(bolt_server* srv, uint32_t map_id, const void* host_req_records, uint32_t q,
+                              void* host_resp_records, uint64_t arrival_ns, uint64_t* ticket);
+
 /* *result = 1 while the request is pending, else its return code. */
 int bolt_server_poll(bolt_server* srv, uint64_t ticket, int* result);
 
@@ -436,6 +454,40 @@ int bolt_tune_get(bolt_tune_entry* host_out, uint32_t cap, uint32_t* n);
  * the current device's table to the defaults. */
 int bolt_tune_set(const bolt_tune_entry* host_in, uint32_t n);
 int bolt_tune_reset(void);
+
+/* ---------------------------------------------------------------------
+ * Sealed commands and responses (BOLT_F_SEAL_CMDS).  The user's commands
+ * reach the map encrypted and its responses leave encrypted, so the host
+ * that relays them sees only their number and sizes (Sec. 3, threat model;
+ * Sec. 5.1, the decode module opens commands and the response module seals
+ * results).  Every command and every response is its own fixed-length
+ * ChaCha20-Poly1305 (RFC 8439) record under the session key:
+ *   command i of request seq   plain  LE64(op) || LE64(key) || value[vs]
+ *                              nonce  LE32(i) || LE64(seq)
+ *   its response               plain  LE64(status) || value[vs]
+ *                              nonce  LE32(i | 2^31) || LE64(seq)
+ *   both                       associated data LE64(q), q = the request's commands
+ *   record                     cipher text || 16-byte tag
+ * A command record is 32 + vs bytes, a response record 24 + vs.  Requests
+ * of a map are numbered 1, 2, ... in the order the map runs them (the count
+ * lives in device memory), so a replayed, reordered, truncated or changed
+ * request fails its tags: it is then rejected whole (nothing changes, every
+ * response status 0xFF) and the map is poisoned with BOLT_ETAMPER.
+ * --------------------------------------------------------------------- */
+
+/* Runs one sealed request of q commands (1..BOLT_MAX_BATCH): d_req holds q
+ * command records, d_resp receives q response records (device memory,
+ * caller-owned).  Stream-ordered like bolt_access_batch. */
+int bolt_access_sealed(bolt_map* m, const void* d_req, uint32_t q, void* d_resp, void* hip_stream);
+
+/* Client side (host memory, no device work): seals q commands as request
+ * number seq into q command records, and opens q response records of
+ * request seq (BOLT_ETAMPER if any fails its tag; its fields are then
+ * zero).  value_bytes is the map's vs. */
+int bolt_seal_requests(const uint8_t* session_key, uint64_t seq, uint32_t q, uint32_t value_bytes,
+                       const uint8_t* ops, const uint64_t* keys, const void* vals, void* out_records);
+int bolt_open_responses(const uint8_t* session_key, uint64_t seq, uint32_t q, uint32_t value_bytes,
+                        const void* records, uint8_t* status, void* vals);
 
 /* ---------------------------------------------------------------------
  * Device primitives of the path, exported so each can be checked alone.

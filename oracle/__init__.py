@@ -63,6 +63,17 @@ def _load():
     return _lib
 
 
+def load_openmp():
+    """The same oracle built with OpenMP (the parallel CPU baseline); its
+    thread count follows OMP_NUM_THREADS."""
+    path = os.path.join(_HERE, "liboracle_omp.so")
+    if not os.path.exists(path):
+        from . import build as _build
+
+        _build.build()
+    return _configure(C.CDLL(path))
+
+
 def load_variant(path: str):
     """Loads another build of the oracle's C source (the tests compile
     copies with a planted mistake, to show that the pins catch it)."""
@@ -118,6 +129,19 @@ def _configure(lib):
     lib.or_poly1305.argtypes = [P, P, C.c_uint64, P]
     lib.or_aead_seal.argtypes = [P, P, P, C.c_uint64, P, C.c_uint64, P, P]
     lib.or_aead_open.argtypes = [P, P, P, C.c_uint64, P, C.c_uint64, P, P]
+    lib.or_plain_create.argtypes = [C.c_uint64, C.c_uint32]
+    lib.or_plain_create.restype = C.c_void_p
+    lib.or_plain_destroy.argtypes = [P]
+    lib.or_plain_build.argtypes = [P, P, P, C.c_uint64]
+    lib.or_plain_access.argtypes = [P, P, P, P, P, P, C.c_uint32]
+    lib.or_plain_size.argtypes = [P]
+    lib.or_plain_size.restype = C.c_uint64
+    lib.or_cmd_seal.argtypes = [P, C.c_uint64, C.c_uint32, C.c_uint32, P, P, P, P]
+    lib.or_cmd_open.argtypes = [P, C.c_uint64, C.c_uint32, C.c_uint32, P, P, P, P]
+    lib.or_cmd_open.restype = C.c_uint32
+    lib.or_resp_seal.argtypes = [P, C.c_uint64, C.c_uint32, C.c_uint32, P, P, P]
+    lib.or_resp_open.argtypes = [P, C.c_uint64, C.c_uint32, C.c_uint32, P, P, P]
+    lib.or_resp_open.restype = C.c_uint32
     return lib
 
 
@@ -181,6 +205,47 @@ def aead_open(key: bytes, nonce: bytes, aad: bytes, ct: bytes, tag: bytes):
     pt = (C.c_uint8 * max(1, len(ct)))()
     rc = _load().or_aead_open(_buf(key), _buf(nonce), _buf(aad), len(aad), _buf(ct), len(ct), _buf(tag), pt)
     return None if rc else bytes(pt)[:len(ct)]
+
+
+def cmd_seal(key: bytes, seq: int, ops, keys, vals, vs: int) -> np.ndarray:
+    """q command records (q x (32 + vs) bytes) of request seq."""
+    o = np.ascontiguousarray(ops, dtype=np.uint8)
+    k = np.ascontiguousarray(keys, dtype=np.uint64)
+    v = np.ascontiguousarray(vals, dtype=np.uint8).reshape(-1)
+    q = o.size
+    out = np.zeros((max(1, q), 32 + vs), dtype=np.uint8)
+    _load().or_cmd_seal(_buf(key), seq, q, vs, _ptr(o), _ptr(k), _ptr(v) if v.size else None, _ptr(out))
+    return out[:q]
+
+
+def cmd_open(key: bytes, seq: int, records, vs: int):
+    """(failures, ops, keys, vals) of q command records."""
+    r = np.ascontiguousarray(records, dtype=np.uint8).reshape(-1, 32 + vs)
+    q = r.shape[0]
+    o, k = np.zeros(max(1, q), np.uint8), np.zeros(max(1, q), np.uint64)
+    v = np.zeros((max(1, q), vs), np.uint8)
+    bad = _load().or_cmd_open(_buf(key), seq, q, vs, _ptr(r), _ptr(o), _ptr(k), _ptr(v))
+    return int(bad), o[:q], k[:q], v[:q]
+
+
+def resp_seal(key: bytes, seq: int, status, vals, vs: int) -> np.ndarray:
+    """q response records (q x (24 + vs) bytes) of request seq."""
+    st = np.ascontiguousarray(status, dtype=np.uint8)
+    v = np.ascontiguousarray(vals, dtype=np.uint8).reshape(-1)
+    q = st.size
+    out = np.zeros((max(1, q), 24 + vs), dtype=np.uint8)
+    _load().or_resp_seal(_buf(key), seq, q, vs, _ptr(st), _ptr(v) if v.size else None, _ptr(out))
+    return out[:q]
+
+
+def resp_open(key: bytes, seq: int, records, vs: int):
+    """(failures, status, vals) of q response records."""
+    r = np.ascontiguousarray(records, dtype=np.uint8).reshape(-1, 24 + vs)
+    q = r.shape[0]
+    st = np.zeros(max(1, q), np.uint8)
+    v = np.zeros((max(1, q), vs), np.uint8)
+    bad = _load().or_resp_open(_buf(key), seq, q, vs, _ptr(r), _ptr(st), _ptr(v))
+    return int(bad), st[:q], v[:q]
 
 
 def pair(w0: int, w1: int, B: int) -> tuple:
@@ -297,6 +362,47 @@ class PlainMap:
             else:
                 raise ValueError("bad op")
         return out, st
+
+
+class PlainMapC:
+    """The same definition as PlainMap, as a C hash table (the timed plain
+    baseline)."""
+
+    def __init__(self, cap: int, vs: int):
+        self._lib = _load()
+        self.vs = vs
+        self._h = self._lib.or_plain_create(cap, vs)
+        if not self._h:
+            raise MemoryError("plain map")
+
+    def close(self):
+        if self._h:
+            self._lib.or_plain_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def build(self, keys, vals) -> int:
+        k = np.ascontiguousarray(keys, dtype=np.uint64)
+        v = np.ascontiguousarray(vals, dtype=np.uint8).reshape(-1)
+        return int(self._lib.or_plain_build(self._h, _ptr(k), _ptr(v), k.size))
+
+    def access(self, ops, keys, vals_in):
+        o = np.ascontiguousarray(ops, dtype=np.uint8)
+        k = np.ascontiguousarray(keys, dtype=np.uint64)
+        q = o.size
+        vi = np.ascontiguousarray(vals_in, dtype=np.uint8).reshape(-1)
+        vo = np.zeros(max(1, q * self.vs), np.uint8)
+        st = np.zeros(max(1, q), np.uint8)
+        rc = int(self._lib.or_plain_access(self._h, _ptr(o), _ptr(k), _ptr(vi), _ptr(vo), _ptr(st), q))
+        return rc, vo[:q * self.vs].reshape(q, self.vs), st[:q]
+
+    def __len__(self):
+        return int(self._lib.or_plain_size(self._h))
 
 
 # --------------------------------------------------------------------------

@@ -12,6 +12,8 @@
  *   1. BLAKE2s-256 with a key (RFC 7693).  It is the keyed PRF that stands in
  *      for the unnamed hash of Sec. 5.1 step 3 and for random_remap() of
  *      Alg. 1.
+ *   1b, 1c. ChaCha20-Poly1305 (RFC 8439), which seals observable pages
+ *      and the command and response records of sealed requests.
  *   2. Parameter derivation: bins (Sec. 4.1), bin capacity (Claim 4.2), stash
  *      bound (Claim 4.4), position-map rows (Sec. 5.2, "decomposed HBM
  *      storage").
@@ -21,6 +23,15 @@
  *      as an oblivious procedure) and batched access (Alg. 1 with the module
  *      order of Sec. 5.1).  Every access to the observable store goes
  *      through one pair of functions that also records it.
+ *   5. The plain definition of the answers (O1) as a C hash table, the
+ *      timed plain baseline.
+ *
+ * Built with -fopenmp, the same source is the parallel CPU baseline of the
+ * same procedure: the loops whose iterations are independent (the network
+ * stages, the PRFs of a build or a batch, the placement choices of a round,
+ * the page write-out when no trace is kept) carry OpenMP pragmas, which the
+ * plain single-thread build ignores.  The results do not depend on it (the
+ * tests compare the two builds).
  *
  * Readings of points where the paper is silent (all listed in the design
  * notes of the repository):
@@ -330,6 +341,114 @@ int or_aead_open(const uint8_t key[32], const uint8_t nonce[12], const uint8_t* 
 }
 
 /* ------------------------------------------------------------------ */
+/* 1c. Sealed command and response records                              */
+/* ------------------------------------------------------------------ */
+
+/* The user's instructions reach the map encrypted, and its results leave
+ * encrypted (Sec. 3, threat model: the host only relays them; Sec. 5.1,
+ * the decode module opens instructions, the response module seals
+ * results).  Every command and every response is its own fixed-length
+ * ChaCha20-Poly1305 record under the session key:
+ *   command i of request seq:  plain  LE64(op) || LE64(key) || value[vs]
+ *                              nonce  LE32(i) || LE64(seq)
+ *   its response:              plain  LE64(status) || value[vs]
+ *                              nonce  LE32(i | 2^31) || LE64(seq)
+ *   associated data of both:   LE64(q), the request's command count
+ *   record                     cipher text || 16-byte tag
+ * Requests of a session are numbered 1, 2, ... in the order the map runs
+ * them, so a replayed, reordered, truncated or changed request fails its
+ * tags. */
+
+static void or_rec_nonce(uint32_t dir, uint32_t i, uint64_t seq, uint8_t nonce[12]) {
+  uint32_t w = i | (dir << 31);
+  nonce[0] = (uint8_t)w; nonce[1] = (uint8_t)(w >> 8); nonce[2] = (uint8_t)(w >> 16); nonce[3] = (uint8_t)(w >> 24);
+  or_put_le64(nonce + 4, seq);
+}
+
+/* Seals q commands into q records of 32 + vs bytes (the client's side). */
+void or_cmd_seal(const uint8_t key[32], uint64_t seq, uint32_t q, uint32_t vs, const uint8_t* ops,
+                 const uint64_t* keys, const uint8_t* vals, uint8_t* out) {
+  uint8_t aad[8], nonce[12];
+  or_put_le64(aad, q);
+  uint8_t* plain = malloc(16 + vs);
+  for (uint32_t i = 0; i < q; ++i) {
+    or_put_le64(plain, ops[i]);
+    or_put_le64(plain + 8, keys[i]);
+    memcpy(plain + 16, vals + (size_t)i * vs, vs);
+    or_rec_nonce(0, i, seq, nonce);
+    uint8_t* rec = out + (size_t)i * (32 + vs);
+    or_aead_seal(key, nonce, aad, 8, plain, 16 + vs, rec, rec + 16 + vs);
+  }
+  free(plain);
+}
+
+/* Opens q command records; returns how many failed their tag (their
+ * fields are then zero, with op 0xFF). */
+uint32_t or_cmd_open(const uint8_t key[32], uint64_t seq, uint32_t q, uint32_t vs, const uint8_t* recs,
+                     uint8_t* ops, uint64_t* keys, uint8_t* vals) {
+  uint8_t aad[8], nonce[12];
+  or_put_le64(aad, q);
+  uint8_t* plain = malloc(16 + vs);
+  uint32_t bad = 0;
+  for (uint32_t i = 0; i < q; ++i) {
+    const uint8_t* rec = recs + (size_t)i * (32 + vs);
+    or_rec_nonce(0, i, seq, nonce);
+    if (or_aead_open(key, nonce, aad, 8, rec, 16 + vs, rec + 16 + vs, plain)) {
+      bad++;
+      ops[i] = 0xFF;
+      keys[i] = 0;
+      memset(vals + (size_t)i * vs, 0, vs);
+      continue;
+    }
+    uint64_t op = or_le64(plain);
+    ops[i] = op > 0xFF ? 0xFF : (uint8_t)op;
+    keys[i] = or_le64(plain + 8);
+    memcpy(vals + (size_t)i * vs, plain + 16, vs);
+  }
+  free(plain);
+  return bad;
+}
+
+/* Seals q responses into q records of 24 + vs bytes (the map's side). */
+void or_resp_seal(const uint8_t key[32], uint64_t seq, uint32_t q, uint32_t vs, const uint8_t* status,
+                  const uint8_t* vals, uint8_t* out) {
+  uint8_t aad[8], nonce[12];
+  or_put_le64(aad, q);
+  uint8_t* plain = malloc(8 + vs);
+  for (uint32_t i = 0; i < q; ++i) {
+    or_put_le64(plain, status[i]);
+    memcpy(plain + 8, vals + (size_t)i * vs, vs);
+    or_rec_nonce(1, i, seq, nonce);
+    uint8_t* rec = out + (size_t)i * (24 + vs);
+    or_aead_seal(key, nonce, aad, 8, plain, 8 + vs, rec, rec + 8 + vs);
+  }
+  free(plain);
+}
+
+/* Opens q response records (the client's side); returns the failures. */
+uint32_t or_resp_open(const uint8_t key[32], uint64_t seq, uint32_t q, uint32_t vs, const uint8_t* recs,
+                      uint8_t* status, uint8_t* vals) {
+  uint8_t aad[8], nonce[12];
+  or_put_le64(aad, q);
+  uint8_t* plain = malloc(8 + vs);
+  uint32_t bad = 0;
+  for (uint32_t i = 0; i < q; ++i) {
+    const uint8_t* rec = recs + (size_t)i * (24 + vs);
+    or_rec_nonce(1, i, seq, nonce);
+    if (or_aead_open(key, nonce, aad, 8, rec, 8 + vs, rec + 8 + vs, plain)) {
+      bad++;
+      status[i] = 0;
+      memset(vals + (size_t)i * vs, 0, vs);
+      continue;
+    }
+    status[i] = (uint8_t)or_le64(plain);
+    memcpy(vals + (size_t)i * vs, plain + 8, vs);
+  }
+  free(plain);
+  return bad;
+}
+
+/* ------------------------------------------------------------------ */
 /* 2. Parameters                                                        */
 /* ------------------------------------------------------------------ */
 
@@ -420,6 +539,7 @@ int or_bitonic_sort_u64(uint64_t* a, uint64_t n) {
   if (n & (n - 1)) return -1;
   for (uint64_t k = 2; k <= n; k <<= 1)
     for (uint64_t j = k >> 1; j > 0; j >>= 1)
+#pragma omp parallel for if (n >= 4096)
       for (uint64_t i = 0; i < n; ++i) {
         uint64_t l = i ^ j;
         if (l <= i) continue;
@@ -461,6 +581,7 @@ int or_expand(const uint32_t* target, const uint32_t* payload, uint64_t n, uint6
   }
   for (int j = or_shift_top(m); j >= 0; --j) {
     uint64_t h = 1ull << j;
+#pragma omp parallel for reduction(min : rc) if (m >= 4096)
     for (uint64_t p = 0; p < m; ++p) {
       int stay = ct[p] != OR_NONE && !(((uint64_t)ct[p] - p) & h);
       int arrive = p >= h && ct[p - h] != OR_NONE && ((((uint64_t)ct[p - h] - (p - h)) & h) != 0);
@@ -756,6 +877,7 @@ static int or_pm_insert_rounds(or_map* m, uint64_t n, const uint64_t* keys, cons
   int over = 0;
   for (uint64_t r0 = 0; r0 < n; r0 += rs) {
     uint64_t r1 = r0 + rs < n ? r0 + rs : n;
+#pragma omp parallel for
     for (uint64_t i = r0; i < r1; ++i) {
       uint64_t rows[8] = {0};
       or_pm_rows(m, keys[i], rows);
@@ -839,6 +961,7 @@ int or_build(or_map* m, const uint64_t* keys, const uint8_t* vals, uint64_t n, i
 
   /* a1: two distinct random bins per key (Sec. 4.1: "each data item is
    * initially assigned to two uniformly chosen random bins"). */
+#pragma omp parallel for
   for (uint64_t i = 0; i < n; ++i) {
     uint64_t w[4];
     or_prf(m->prf_key, 1, keys[i], w);
@@ -848,6 +971,7 @@ int or_build(or_map* m, const uint64_t* keys, const uint8_t* vals, uint64_t n, i
   uint64_t rs = (s->B + 15) / 16;
   for (uint64_t r0 = 0; r0 < n; r0 += rs) {
     uint64_t r1 = r0 + rs < n ? r0 + rs : n;
+#pragma omp parallel for
     for (uint64_t i = r0; i < r1; ++i) dest[i] = m->load[p2[i]] < m->load[p1[i]] ? p2[i] : p1[i];
     for (uint64_t i = r0; i < r1; ++i) m->load[dest[i]]++;
   }
@@ -895,21 +1019,30 @@ int or_build(or_map* m, const uint64_t* keys, const uint8_t* vals, uint64_t n, i
       free(fill);
     }
     /* a6: write every bin as a canonical page: HBM bins, then observable
-     * pages 0..M-1 in order. */
-    for (uint64_t b = 0; b < s->B; ++b) {
-      bin.n = 0;
-      for (uint32_t j = 0; j < s->Z; ++j) {
-        uint32_t i = slot_src[b * s->Z + j];
-        if (i == OR_NONE) continue;
-        bin.key[bin.n] = keys[i];
-        memcpy(bin.val + (size_t)bin.n * s->vs, vals + (size_t)i * s->vs, s->vs);
-        bin.n++;
+     * pages 0..M-1 in order (in parallel only when no trace is kept). */
+#pragma omp parallel if (!m->trace_on)
+    {
+      or_bin wbin;
+      or_bin_alloc(m, &wbin);
+      uint8_t* wpage = malloc(s->page_bytes);
+#pragma omp for
+      for (uint64_t b = 0; b < s->B; ++b) {
+        wbin.n = 0;
+        for (uint32_t j = 0; j < s->Z; ++j) {
+          uint32_t i = slot_src[b * s->Z + j];
+          if (i == OR_NONE) continue;
+          wbin.key[wbin.n] = keys[i];
+          memcpy(wbin.val + (size_t)wbin.n * s->vs, vals + (size_t)i * s->vs, s->vs);
+          wbin.n++;
+        }
+        or_encode(m, &wbin, wpage);
+        if (b < s->K)
+          memcpy(m->hbm + b * s->page_bytes, wpage, s->page_bytes);
+        else
+          or_obs_write(m, b - s->K, wpage);
       }
-      or_encode(m, &bin, page);
-      if (b < s->K)
-        memcpy(m->hbm + b * s->page_bytes, page, s->page_bytes);
-      else
-        or_obs_write(m, b - s->K, page);
+      or_bin_free(&wbin);
+      free(wpage);
     }
     free(slot_src);
     /* a7: position map (key -> p1, p2), d-choice rows in rounds. */
@@ -920,7 +1053,9 @@ int or_build(or_map* m, const uint64_t* keys, const uint8_t* vals, uint64_t n, i
     rc = OR_EOVERFLOW;
   } else {
     /* duplicate keys: a key found more than once among its rows */
-    for (uint64_t i = 0; i < n && rc == OR_OK; ++i) {
+    int dup = 0;
+#pragma omp parallel for reduction(| : dup)
+    for (uint64_t i = 0; i < n; ++i) {
       uint64_t rows[8] = {0};
       or_pm_rows(m, keys[i], rows);
       uint32_t hits = 0;
@@ -930,8 +1065,9 @@ int or_build(or_map* m, const uint64_t* keys, const uint8_t* vals, uint64_t n, i
         if (seen) continue;
         for (uint32_t e = 0; e < m->rowcnt[rows[j]]; ++e) hits += m->rows[rows[j] * s->W + e].key == keys[i];
       }
-      if (hits > 1) rc = OR_EDUPKEY;
+      dup |= hits > 1;
     }
+    if (dup) rc = OR_EDUPKEY;
   }
   or_bin_free(&bin);
   free(page); free(p1); free(p2); free(dest);
@@ -1047,19 +1183,24 @@ int or_access(or_map* m, const uint8_t* ops, const uint64_t* keys, const uint8_t
   uint8_t* page = malloc(s->page_bytes);
   int broken = 0;
 
+  /* Each command's tape pairs, and each leader's position-map entry (the
+   * map does not change until every command has run). */
+  uint32_t* f1 = malloc(q * sizeof(uint32_t));
+  uint32_t* f2 = malloc(q * sizeof(uint32_t));
+#pragma omp parallel for
+  for (uint32_t i = 0; i < q; ++i) {
+    uint64_t w[4];
+    or_prf(m->prf_key, 3, m->ctr + i, w);
+    or_pair(w[0], w[1], s->B, &f1[i], &f2[i]);  /* F(s): pair for dummy reads */
+    or_pair(w[2], w[3], s->B, &r1[i], &r2[i]); /* R(s): new pair on remap */
+    if (leader[i] == i) hit[i] = (uint8_t)or_pm_lookup(m, keys[i], &hrow[i], &hidx[i]);
+  }
+
   /* Steps 2-4 and 6 of Sec. 5.1, one command at a time. */
   for (uint32_t i = 0; i < q; ++i) {
-    uint64_t st = m->ctr + i;
-    uint64_t w[4];
-    or_prf(m->prf_key, 3, st, w);
-    uint32_t f1, f2;
-    or_pair(w[0], w[1], s->B, &f1, &f2); /* F(s): pair for dummy reads */
-    or_pair(w[2], w[3], s->B, &r1[i], &r2[i]); /* R(s): new pair on remap */
     uint64_t k = keys[i];
-    int is_leader = leader[i] == i;
-    uint32_t pr[2] = {f1, f2};
-    if (is_leader && or_pm_lookup(m, k, &hrow[i], &hidx[i])) {
-      hit[i] = 1;
+    uint32_t pr[2] = {f1[i], f2[i]};
+    if (hit[i]) {
       pr[0] = m->rows[hrow[i] * s->W + hidx[i]].p1;
       pr[1] = m->rows[hrow[i] * s->W + hidx[i]].p2;
     }
@@ -1108,6 +1249,7 @@ int or_access(or_map* m, const uint8_t* ops, const uint64_t* keys, const uint8_t
     if (leader[i] == i && present[i]) ord[nplace++] = i;
   for (uint64_t o0 = 0; o0 < nplace; o0 += rs) {
     uint64_t o1 = o0 + rs < nplace ? o0 + rs : nplace;
+#pragma omp parallel for
     for (uint64_t o = o0; o < o1; ++o) {
       uint32_t i = ord[o];
       chosen[o] = m->load[r2[i]] < m->load[r1[i]] ? r2[i] : r1[i];
@@ -1185,7 +1327,7 @@ int or_access(or_map* m, const uint8_t* ops, const uint64_t* keys, const uint8_t
   for (uint64_t x = 0; x < ws.n; ++x) or_bin_free(&ws.work[x]);
   free(ws.work); free(ws.bin_of); free(ws.slot);
   free(kx); free(leader); free(hit); free(present); free(cur); free(hrow); free(hidx);
-  free(r1); free(r2); free(fetched); free(page); free(ord); free(chosen);
+  free(r1); free(r2); free(f1); free(f2); free(fetched); free(page); free(ord); free(chosen);
   free(ins_key); free(ins_p1); free(ins_p2);
   m->ctr += q;
   if (m->tampered) {
@@ -1207,6 +1349,130 @@ int or_access(or_map* m, const uint8_t* ops, const uint64_t* keys, const uint8_t
   }
   return OR_OK;
 }
+
+/* ------------------------------------------------------------------ */
+/* 5. The plain definition of the answers (O1), in C                    */
+/* ------------------------------------------------------------------ */
+
+/* A non-oblivious dictionary with the Get / Put / Delete semantics of
+ * Sec. 2.1 (delete = a tombstone put): an open-addressing hash table with
+ * linear probing and backward-shift deletion.  It gives the same answers
+ * as the Python dictionary of oracle/__init__.py (the tests check that)
+ * and serves as the timed plain baseline. */
+typedef struct {
+  uint64_t mask, n;
+  uint32_t vs;
+  uint64_t* key;
+  uint8_t* used;
+  uint8_t* val;
+} or_plain;
+
+static uint64_t or_plain_hash(uint64_t k) { /* SplitMix64 finalizer */
+  k ^= k >> 30;
+  k *= 0xBF58476D1CE4E5B9ull;
+  k ^= k >> 27;
+  k *= 0x94D049BB133111EBull;
+  return k ^ (k >> 31);
+}
+
+or_plain* or_plain_create(uint64_t cap, uint32_t vs) {
+  or_plain* p = calloc(1, sizeof(or_plain));
+  if (!p) return NULL;
+  uint64_t size = 16;
+  while (size < 2 * cap + 2) size <<= 1;
+  p->mask = size - 1;
+  p->vs = vs;
+  p->key = calloc(size, sizeof(uint64_t));
+  p->used = calloc(size, 1);
+  p->val = calloc(size, vs);
+  if (!p->key || !p->used || !p->val) {
+    free(p->key); free(p->used); free(p->val); free(p);
+    return NULL;
+  }
+  return p;
+}
+
+void or_plain_destroy(or_plain* p) {
+  if (!p) return;
+  free(p->key); free(p->used); free(p->val); free(p);
+}
+
+/* The slot holding k, or the empty slot where it would go. */
+static uint64_t or_plain_slot(const or_plain* p, uint64_t k) {
+  uint64_t i = or_plain_hash(k) & p->mask;
+  while (p->used[i] && p->key[i] != k) i = (i + 1) & p->mask;
+  return i;
+}
+
+static void or_plain_erase(or_plain* p, uint64_t i) {
+  p->used[i] = 0;
+  p->n--;
+  uint64_t j = i;
+  for (;;) { /* shift back later members of the cluster that may fill the hole */
+    j = (j + 1) & p->mask;
+    if (!p->used[j]) return;
+    uint64_t h = or_plain_hash(p->key[j]) & p->mask;
+    /* j's entry may move to i when its home h is not cyclically in (i, j] */
+    int in_range = i <= j ? (h > i && h <= j) : (h > i || h <= j);
+    if (in_range) continue;
+    p->key[i] = p->key[j];
+    memcpy(p->val + i * p->vs, p->val + j * p->vs, p->vs);
+    p->used[i] = 1;
+    p->used[j] = 0;
+    i = j;
+  }
+}
+
+/* Inserts (returns 0) or refuses when the table is at its capacity (-1). */
+static int or_plain_put(or_plain* p, uint64_t k, const uint8_t* v, int* inserted) {
+  uint64_t i = or_plain_slot(p, k);
+  *inserted = !p->used[i];
+  if (*inserted) {
+    if (2 * (p->n + 1) > p->mask + 1) return -1;
+    p->used[i] = 1;
+    p->key[i] = k;
+    p->n++;
+  }
+  memcpy(p->val + i * p->vs, v, p->vs);
+  return 0;
+}
+
+int or_plain_build(or_plain* p, const uint64_t* keys, const uint8_t* vals, uint64_t n) {
+  for (uint64_t i = 0; i < n; ++i) {
+    int ins;
+    if (or_plain_put(p, keys[i], vals + i * p->vs, &ins)) return OR_EFULL;
+    if (!ins) return OR_EDUPKEY;
+  }
+  return OR_OK;
+}
+
+/* The commands in order: GET answers (found, value) or (absent, zeros);
+ * PUT answers updated or inserted; DEL answers deleted or absent. */
+int or_plain_access(or_plain* p, const uint8_t* ops, const uint64_t* keys, const uint8_t* vals_in, uint8_t* vals_out,
+                    uint8_t* status, uint32_t q) {
+  for (uint32_t i = 0; i < q; ++i)
+    if (ops[i] > OR_DEL) return OR_EINVAL;
+  for (uint32_t i = 0; i < q; ++i) {
+    uint64_t s = or_plain_slot(p, keys[i]);
+    int had = p->used[s];
+    uint8_t* vo = vals_out + (size_t)i * p->vs;
+    memset(vo, 0, p->vs);
+    if (ops[i] == OR_GET) {
+      status[i] = had ? OR_ST_FOUND : OR_ST_ABSENT;
+      if (had) memcpy(vo, p->val + s * p->vs, p->vs);
+    } else if (ops[i] == OR_PUT) {
+      int ins;
+      if (or_plain_put(p, keys[i], vals_in + (size_t)i * p->vs, &ins)) return OR_EFULL;
+      status[i] = ins ? OR_ST_INSERTED : OR_ST_UPDATED;
+    } else {
+      status[i] = had ? OR_ST_DELETED : OR_ST_ABSENT;
+      if (had) or_plain_erase(p, s);
+    }
+  }
+  return OR_OK;
+}
+
+uint64_t or_plain_size(const or_plain* p) { return p->n; }
 
 /* --- state readout (tests) ---------------------------------------- */
 

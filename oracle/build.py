@@ -1,4 +1,6 @@
-"""Compiles the oracle's C source into oracle/liboracle.so (test infrastructure)."""
+"""Compiles the oracle's C source (test infrastructure): oracle/liboracle.so,
+single-threaded, and oracle/liboracle_omp.so, the same source with OpenMP
+(the parallel CPU baseline)."""
 import os
 import subprocess
 import sys
@@ -6,13 +8,18 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 
 
-def build() -> str:
+def _gcc(out, extra):
     src = os.path.join(HERE, "bolt_oracle.c")
-    out = os.path.join(HERE, "liboracle.so")
     tmp = out + ".tmp%d" % os.getpid()
-    cmd = ["gcc", "-O2", "-std=c11", "-Wall", "-shared", "-fPIC", "-o", tmp, src, "-lm"]
+    cmd = ["gcc", "-O2", "-std=c11", "-Wall", "-shared", "-fPIC"] + extra + ["-o", tmp, src, "-lm"]
     subprocess.run(cmd, check=True)
     os.replace(tmp, out)
+    return out
+
+
+def build() -> str:
+    out = _gcc(os.path.join(HERE, "liboracle.so"), ["-Wno-unknown-pragmas"])
+    _gcc(os.path.join(HERE, "liboracle_omp.so"), ["-fopenmp"])
     return out
 
 

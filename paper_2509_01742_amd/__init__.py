@@ -22,6 +22,7 @@ BOLT_ST_ABSENT, BOLT_ST_FOUND, BOLT_ST_UPDATED, BOLT_ST_INSERTED, BOLT_ST_DELETE
 BOLT_OBS_HOST_PINNED, BOLT_OBS_DEVICE = 0, 1
 BOLT_F_TRACE, BOLT_F_FIXED_KEY, BOLT_F_TIMING, BOLT_F_GRAPHS, BOLT_F_WATCH, BOLT_F_SEAL = 1, 2, 4, 8, 16, 32
 BOLT_F_SEAL_KEY_REUSE = 64
+BOLT_F_SEAL_CMDS = 128
 BOLT_MAX_BATCH = 8192
 BOLT_NOALLOC_EXPAND_MAX = 1 << 21
 BOLT_ETIMEOUT = -8
@@ -45,6 +46,7 @@ class bolt_params(C.Structure):
         ("alpha_permille", C.c_uint32), ("bin_slots", C.c_uint32), ("pm_choices", C.c_uint32),
         ("pm_keys_per_row", C.c_uint32), ("pm_row_slots", C.c_uint32), ("observable", C.c_uint32),
         ("flags", C.c_uint32), ("trace_words", C.c_uint64), ("key", C.c_uint8 * 32),
+        ("session_key", C.c_uint8 * 32),
     ]
 
 
@@ -113,6 +115,9 @@ _SIGS = [
     ("bolt_access_many", _I, [_P, _P, _U32, _P]),
     ("bolt_build_many", _I, [_P, _P, _P, _P, _U32, _P]),
     ("bolt_get_batch", _I, [_P, _P, _U32, _P, _P, _P]),
+    ("bolt_access_sealed", _I, [_P, _P, _U32, _P, _P]),
+    ("bolt_seal_requests", _I, [_P, _U64, _U32, _U32, _P, _P, _P, _P]),
+    ("bolt_open_responses", _I, [_P, _U64, _U32, _U32, _P, _P, _P]),
     ("bolt_put_batch", _I, [_P, _P, _P, _U32, _P, _P]),
     ("bolt_destroy", _I, [_P]),
     ("bolt_status", _I, [_P]),
@@ -139,6 +144,7 @@ _SIGS = [
     ("bolt_server_map_state", _I, [_P, _U32, C.POINTER(_I), C.POINTER(_I)]),
     ("bolt_server_map", _P, [_P, _U32]),
     ("bolt_server_submit", _I, [_P, _U32, _P, _P, _P, _P, _P, _U32, _U64, C.POINTER(_U64)]),
+    ("bolt_server_submit_sealed", _I, [_P, _U32, _P, _U32, _P, _U64, C.POINTER(_U64)]),
     ("bolt_server_poll", _I, [_P, _U64, C.POINTER(_I)]),
     ("bolt_server_wait", _I, [_P, _U64, _U32]),
     ("bolt_server_drain", _I, [_P, _U32]),
@@ -216,11 +222,42 @@ def params(capacity: int, value_bytes: int, **kw) -> bolt_params:
         assert len(key) == 32
         C.memmove(p.key, key, 32)
         p.flags |= BOLT_F_FIXED_KEY
+    skey = kw.pop("session_key", None)
+    if skey is not None:
+        skey = bytes(skey)
+        assert len(skey) == 32
+        C.memmove(p.session_key, skey, 32)
+        p.flags |= BOLT_F_SEAL_CMDS
     for k, v in kw.items():
         if not hasattr(p, k):
             raise TypeError("unknown parameter %s" % k)
         setattr(p, k, v)
     return p
+
+
+def seal_requests(session_key: bytes, seq: int, ops, keys, vals, vs: int) -> np.ndarray:
+    """Client side: q command records (q x (32 + vs) bytes) of request seq."""
+    o = np.ascontiguousarray(ops, dtype=np.uint8)
+    k = np.ascontiguousarray(keys, dtype=np.uint64)
+    v = np.ascontiguousarray(vals, dtype=np.uint8)
+    q = o.size
+    out = np.zeros((q, 32 + vs), dtype=np.uint8)
+    kb = (C.c_uint8 * 32).from_buffer_copy(bytes(session_key))
+    check(bolt_seal_requests(kb, seq, q, vs, o.ctypes.data_as(C.c_void_p), k.ctypes.data_as(C.c_void_p),
+                             v.ctypes.data_as(C.c_void_p), out.ctypes.data_as(C.c_void_p)), "bolt_seal_requests")
+    return out
+
+
+def open_responses(session_key: bytes, seq: int, records, vs: int):
+    """Client side: (rc, status u8[q], values u8[q, vs]) of q response records."""
+    r = np.ascontiguousarray(records, dtype=np.uint8).reshape(-1, 24 + vs)
+    q = r.shape[0]
+    st = np.zeros(max(1, q), dtype=np.uint8)
+    vo = np.zeros((max(1, q), vs), dtype=np.uint8)
+    kb = (C.c_uint8 * 32).from_buffer_copy(bytes(session_key))
+    rc = bolt_open_responses(kb, seq, q, vs, r.ctypes.data_as(C.c_void_p), st.ctypes.data_as(C.c_void_p),
+                             vo.ctypes.data_as(C.c_void_p))
+    return rc, st[:q], vo[:q]
 
 
 def sizes_of(p: bolt_params) -> dict:
@@ -267,6 +304,12 @@ class Map:
         q = ops.numel()
         return bolt_access_batch(self.h, _dptr(ops), _dptr(keys), _dptr(vals_in), _dptr(vals_out), _dptr(status),
                                  q, _stream(stream))
+
+    def access_sealed(self, req, resp, stream=None) -> int:
+        """One sealed request: req / resp device tensors of q command and q
+        response records."""
+        q = req.numel() // (32 + self.vs)
+        return bolt_access_sealed(self.h, _dptr(req), q, _dptr(resp), _stream(stream))
 
     def get(self, keys, vals_out, found, stream=None) -> int:
         return bolt_get_batch(self.h, _dptr(keys), keys.numel(), _dptr(vals_out), _dptr(found), _stream(stream))
@@ -491,6 +534,20 @@ class Server:
             return rc, None, None
         self._live[t.value] = (ops, keys, vals_in, vout, st)
         return t.value, vout, st
+
+    def submit_sealed(self, mid: int, records, vs: int, arrival_ns: int = 0):
+        """Queues one sealed request (q command records); returns (ticket,
+        response records), the latter filled when the request completes."""
+        rec = np.ascontiguousarray(records, dtype=np.uint8).reshape(-1, 32 + vs)
+        q = rec.shape[0]
+        resp = np.zeros((q, 24 + vs), np.uint8)
+        t = C.c_uint64()
+        rc = bolt_server_submit_sealed(self.h, mid, rec.ctypes.data_as(C.c_void_p), q,
+                                       resp.ctypes.data_as(C.c_void_p), arrival_ns, C.byref(t))
+        if rc != BOLT_OK:
+            return rc, None
+        self._live[t.value] = (rec, resp)
+        return t.value, resp
 
     def poll(self, ticket: int) -> int:
         r = C.c_int()

@@ -5,7 +5,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SOURCES = ["api.hip", "k_prim.hip", "k_build.hip", "k_access.hip", "serve.hip", "tune.hip"]
+SOURCES = ["api.hip", "k_prim.hip", "k_build.hip", "k_access.hip", "k_record.hip", "serve.hip", "tune.hip"]
 LIB = os.path.join(HERE, "libbolt.so")
 
 

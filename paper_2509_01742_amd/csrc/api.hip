@@ -13,6 +13,7 @@
 #include <vector>
 
 #include "bolt_impl.h"
+#include "record_dev.h"
 
 using namespace bolt;
 
@@ -278,6 +279,13 @@ int bolt_create(const bolt_params* p, void* hip_stream, bolt_map** out) {
     rc = dalloc(m, &m->tlog, m->tlog_cap * 4);
   }
   if (!rc && (p->flags & BOLT_F_SEAL)) rc = dalloc(m, &m->pver, s.M * 8);
+  if (!rc && (p->flags & BOLT_F_SEAL_CMDS)) {
+    rc = dalloc(m, &m->sc_ops, Q);
+    rc = rc ? rc : dalloc(m, &m->sc_keys, Q * 8);
+    rc = rc ? rc : dalloc(m, &m->sc_vin, Q * s.vs);
+    rc = rc ? rc : dalloc(m, &m->sc_vout, Q * s.vs);
+    rc = rc ? rc : dalloc(m, &m->sc_st, Q);
+  }
   if (!rc) {
     const uint64_t ob = s.M * s.page_bytes + ((p->flags & BOLT_F_SEAL) ? s.M * 16 : 0);  // pages, then tags
     if (p->observable == BOLT_OBS_DEVICE) {
@@ -316,6 +324,8 @@ int bolt_create(const bolt_params* p, void* hip_stream, bolt_map** out) {
     }
   }
   launch_map_init(m, st);
+  if (p->flags & BOLT_F_SEAL_CMDS)  // the session key goes to device memory (the pageable copy completes here)
+    (void)hipMemcpyAsync(m->ctl->ckey, p->session_key, 32, hipMemcpyHostToDevice, st);
   (void)hipMemsetAsync(m->bs.freed, 0, 256 * 4, st);
   (void)hipMemsetAsync(m->wslot, 0, s.M * 8, st);  // epoch 0: no page rebuilt yet
 
@@ -416,6 +426,22 @@ int bolt_access_many(bolt_map* const* maps, const bolt_batch* batches, uint32_t 
     return run_access(live[0], work[0].d_ops, work[0].d_keys, work[0].d_vals_in, work[0].d_vals_out,
                       work[0].d_status, work[0].q, st);
   return run_access_many(live.data(), work.data(), (uint32_t)live.size(), st);
+}
+
+int bolt_access_sealed(bolt_map* m, const void* d_req, uint32_t q, void* d_resp, void* hip_stream) {
+  int rc = map_check(m);
+  if (rc) return rc;
+  if (!m->built || !(m->p.flags & BOLT_F_SEAL_CMDS) || q == 0 || q > kMaxBatch || !d_req || !d_resp)
+    return BOLT_EINVAL;
+  if (((uintptr_t)d_req | (uintptr_t)d_resp) & 7) return BOLT_EINVAL;
+  hipStream_t st = (hipStream_t)hip_stream;
+  m->last_stream = st;
+  if (hipSetDevice(m->device) != hipSuccess) return BOLT_EHIP;
+  launch_rec_open(m, d_req, q, nullptr, 1, m->sc_ops, m->sc_keys, m->sc_vin, st);
+  rc = run_access(m, m->sc_ops, m->sc_keys, m->sc_vin, m->sc_vout, m->sc_st, q, st);
+  if (rc) return rc;
+  launch_rec_seal(m, d_resp, q, nullptr, 1, m->sc_st, m->sc_vout, st);
+  return hipGetLastError() == hipSuccess ? BOLT_OK : BOLT_EHIP;
 }
 
 int bolt_get_batch(bolt_map* m, const uint64_t* d_keys, uint32_t q, void* d_vals_out, uint8_t* d_found,
@@ -718,6 +744,71 @@ int bolt_kernel_times_reset(bolt_map* m) {
   if (m->timer->collect()) return BOLT_EHIP;
   m->timer->reset();
   return BOLT_OK;
+}
+
+// ---- client side of sealed requests (host code) ----
+
+static void key_words(const uint8_t* k, uint32_t w[8]) {
+  for (int j = 0; j < 8; ++j)
+    w[j] = (uint32_t)k[4 * j] | ((uint32_t)k[4 * j + 1] << 8) | ((uint32_t)k[4 * j + 2] << 16) |
+           ((uint32_t)k[4 * j + 3] << 24);
+}
+
+static uint64_t ld64(const uint8_t* p) {
+  uint64_t v;
+  memcpy(&v, p, 8);
+  return v;
+}
+
+static void st64(uint8_t* p, uint64_t v) { memcpy(p, &v, 8); }
+
+int bolt_seal_requests(const uint8_t* session_key, uint64_t seq, uint32_t q, uint32_t value_bytes,
+                       const uint8_t* ops, const uint64_t* keys, const void* vals, void* out_records) {
+  if (!session_key || value_bytes == 0 || value_bytes % 8) return BOLT_EINVAL;
+  if (q && (!ops || !keys || !vals || !out_records)) return BOLT_EINVAL;
+  uint32_t key[8];
+  key_words(session_key, key);
+  const uint32_t vw = value_bytes / 8, words = 2 + vw;
+  const uint8_t* v = static_cast<const uint8_t*>(vals);
+  for (uint32_t i = 0; i < q; ++i) {
+    uint8_t* rec = static_cast<uint8_t*>(out_records) + (uint64_t)i * (words + 2) * 8;
+    RecStream ks{key, i, (uint32_t)seq, (uint32_t)(seq >> 32)};
+    st64(rec, (uint64_t)ops[i] ^ ks.word(0));
+    st64(rec + 8, keys[i] ^ ks.word(1));
+    for (uint32_t w = 0; w < vw; ++w) st64(rec + 8 * (2 + w), ld64(v + ((uint64_t)i * vw + w) * 8) ^ ks.word(2 + w));
+    uint32_t otk[8], tag[4];
+    rec_otk(key, i, seq, otk);
+    rec_tag(otk, q, words, [&](uint32_t w) { return ld64(rec + 8 * w); }, tag);
+    memcpy(rec + 8 * words, tag, 16);
+  }
+  return BOLT_OK;
+}
+
+int bolt_open_responses(const uint8_t* session_key, uint64_t seq, uint32_t q, uint32_t value_bytes,
+                        const void* records, uint8_t* status, void* vals) {
+  if (!session_key || value_bytes == 0 || value_bytes % 8) return BOLT_EINVAL;
+  if (q && (!records || !status || !vals)) return BOLT_EINVAL;
+  uint32_t key[8];
+  key_words(session_key, key);
+  const uint32_t vw = value_bytes / 8, words = 1 + vw;
+  uint8_t* v = static_cast<uint8_t*>(vals);
+  int rc = BOLT_OK;
+  for (uint32_t i = 0; i < q; ++i) {
+    const uint8_t* rec = static_cast<const uint8_t*>(records) + (uint64_t)i * (words + 2) * 8;
+    uint32_t otk[8], tag[4];
+    rec_otk(key, i | kRespDir, seq, otk);
+    rec_tag(otk, q, words, [&](uint32_t w) { return ld64(rec + 8 * w); }, tag);
+    if (memcmp(tag, rec + 8 * words, 16) != 0) {
+      rc = BOLT_ETAMPER;
+      status[i] = 0;
+      memset(v + (uint64_t)i * value_bytes, 0, value_bytes);
+      continue;
+    }
+    RecStream ks{key, i | kRespDir, (uint32_t)seq, (uint32_t)(seq >> 32)};
+    status[i] = (uint8_t)(ld64(rec) ^ ks.word(0));
+    for (uint32_t w = 0; w < vw; ++w) st64(v + ((uint64_t)i * vw + w) * 8, ld64(rec + 8 * (1 + w)) ^ ks.word(1 + w));
+  }
+  return rc;
 }
 
 }  // extern "C"

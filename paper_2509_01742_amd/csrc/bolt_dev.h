@@ -37,6 +37,8 @@ struct Ctl {
   uint32_t load_hw;      // BOLT_F_WATCH: largest bin load seen at a batch end
   uint64_t hbm_load;     // BOLT_F_WATCH: items in the HBM bins at the last batch end
   uint64_t hbm_hw;       // BOLT_F_WATCH: largest hbm_load seen
+  uint32_t ckey[8];      // BOLT_F_SEAL_CMDS: session key of the command and response records
+  uint64_t seq;          // BOLT_F_SEAL_CMDS: sealed requests run so far (the next is seq + 1)
 };
 
 // ---------------------------------------------------------------------------

@@ -119,6 +119,13 @@ struct bolt_map {
   uint8_t* get_ops;   // [Q] all BOLT_OP_GET (bolt_get_batch)
   uint8_t* put_ops;   // [Q] all BOLT_OP_PUT (bolt_put_batch)
   uint8_t* discard;   // [2Q * vs] unused inputs / outputs of those wrappers
+  // BOLT_F_SEAL_CMDS: the opened commands and the plain responses of a
+  // sealed request (device memory only)
+  uint8_t* sc_ops;    // [Q]
+  uint64_t* sc_keys;  // [Q]
+  uint8_t* sc_vin;    // [Q * vs]
+  uint8_t* sc_vout;   // [Q * vs]
+  uint8_t* sc_st;     // [Q]
   std::vector<void*> allocs;  // every hipMalloc of this map
   bool built, poisoned;
   int sticky;
@@ -190,5 +197,13 @@ int run_access(bolt_map* m, const uint8_t* ops, const uint64_t* keys, const void
 int run_access_many(bolt_map* const* maps, const bolt_batch* batches, uint32_t count, hipStream_t st);
 // Sends the rebuilt pages of the map's last batch to the store, if any.
 int flush_ship(bolt_map* m, hipStream_t st);
+// Sealed requests (k_record.hip): commands t of a call (requests starting
+// at tab[r], nreq of them; tab null = one request of q) opened into plain
+// arrays, and responses sealed from them; the seal also advances the
+// map's request count past the call.
+void launch_rec_open(bolt_map* m, const void* recs, uint32_t q, const uint32_t* tab, uint32_t nreq, uint8_t* ops,
+                     uint64_t* keys, void* vals, hipStream_t st);
+void launch_rec_seal(bolt_map* m, void* out, uint32_t q, const uint32_t* tab, uint32_t nreq, const uint8_t* status,
+                     const void* vals, hipStream_t st);
 
 }  // namespace bolt

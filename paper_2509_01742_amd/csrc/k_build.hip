@@ -175,6 +175,7 @@ __global__ void k_ctl_init(Ctl* ctl) {
   ctl->load_hw = 0;
   ctl->hbm_load = 0;
   ctl->hbm_hw = 0;
+  ctl->seq = 0;
 }
 
 void launch_map_init(bolt_map* m, hipStream_t st) {

@@ -10,7 +10,7 @@
 
 namespace bolt {
 
-__device__ __forceinline__ uint32_t rotl32(uint32_t x, int n) { return __builtin_rotateleft32(x, n); }
+__host__ __device__ __forceinline__ uint32_t rotl32(uint32_t x, int n) { return __builtin_rotateleft32(x, n); }
 
 // Orders the LDS writes of one wave's lanes before that wave's later LDS
 // reads (a page staged by some lanes and read by others).
@@ -34,7 +34,7 @@ __device__ __forceinline__ void wave_sync() {
 
 // One ChaCha20 block (16 words): "expand 32-byte k", key, counter, nonce;
 // ten double rounds; the input added back.
-__device__ __forceinline__ void chacha_block(const uint32_t key[8], uint32_t counter, uint32_t n0, uint32_t n1,
+__host__ __device__ __forceinline__ void chacha_block(const uint32_t key[8], uint32_t counter, uint32_t n0, uint32_t n1,
                                              uint32_t n2, uint32_t out[16]) {
   const uint32_t c0 = 0x61707865u, c1 = 0x3320646eu, c2 = 0x79622d32u, c3 = 0x6b206574u;
   uint32_t x0 = c0, x1 = c1, x2 = c2, x3 = c3;
@@ -76,7 +76,7 @@ constexpr uint32_t kM26 = 0x3ffffffu;
 
 // c = a * b mod p, partly reduced (limbs below 2^26, the second a little
 // above).  Limbs of a and b below 2^28: every partial sum stays below 2^62.
-__device__ __forceinline__ void fe_mul(const uint32_t a[5], const uint32_t b[5], uint32_t c[5]) {
+__host__ __device__ __forceinline__ void fe_mul(const uint32_t a[5], const uint32_t b[5], uint32_t c[5]) {
   const uint64_t b1 = 5ull * b[1], b2 = 5ull * b[2], b3 = 5ull * b[3], b4 = 5ull * b[4];
   uint64_t d0 = (uint64_t)a[0] * b[0] + a[1] * b4 + a[2] * b3 + a[3] * b2 + a[4] * b1;
   uint64_t d1 = (uint64_t)a[0] * b[1] + (uint64_t)a[1] * b[0] + a[2] * b4 + a[3] * b3 + a[4] * b2;
@@ -98,7 +98,7 @@ __device__ __forceinline__ void fe_mul(const uint32_t a[5], const uint32_t b[5],
 }
 
 // Four little-endian words (128 bits) as limbs, plus `top` at bit 128.
-__device__ __forceinline__ void fe_from128(uint32_t w0, uint32_t w1, uint32_t w2, uint32_t w3, uint32_t top,
+__host__ __device__ __forceinline__ void fe_from128(uint32_t w0, uint32_t w1, uint32_t w2, uint32_t w3, uint32_t top,
                                            uint32_t c[5]) {
   c[0] = w0 & kM26;
   c[1] = ((w0 >> 26) | (w1 << 6)) & kM26;

@@ -24,6 +24,11 @@
 //               sequential semantics), so they do not depend on what else
 //               runs beside it.
 //   latency     completion time minus the arrival time given at submit.
+//   sealing     a map created with BOLT_F_SEAL_CMDS takes only sealed
+//               requests: the host stages their command records and the
+//               response records come back, so plain commands and results
+//               exist only in device memory.  Its requests are numbered in
+//               submission order (the order the map runs them).
 #include <string.h>
 #include <time.h>
 
@@ -60,6 +65,8 @@ struct Req {
   uint8_t* status;
   uint32_t q;
   uint64_t t_arr;
+  const uint8_t* rec_in;  // sealed request: its command records (else null)
+  uint8_t* rec_out;       // and where its response records go
 };
 
 // kQueued: admitted, waiting for the builder; kRetiring: its resources are
@@ -67,17 +74,26 @@ struct Req {
 enum MapState { kWaiting, kQueued, kBuilding, kResident, kRetiring, kClosed, kFailed };
 
 // Command staging of one map: [ops Q][keys Q][vals_in Q*vs][vals_out Q*vs]
-// [status Q][error word].
+// [status Q][error word], and for a sealed map [request starts Q+1]
+// [command records Q*(32+vs)][response records Q*(24+vs)].  A sealed map's
+// host staging uses only the error word and the sealed part.
 struct Stage {
   uint8_t* base = nullptr;
   uint64_t off_keys = 0, off_vin = 0, off_vout = 0, off_st = 0, off_err = 0, bytes = 0;
-  void layout(uint32_t Q, uint32_t vs) {
+  uint64_t off_tab = 0, off_req = 0, off_resp = 0;
+  void layout(uint32_t Q, uint32_t vs, bool sealed) {
     off_keys = (Q + 255) & ~255ull;
     off_vin = off_keys + (uint64_t)Q * 8;
     off_vout = off_vin + (uint64_t)Q * vs;
     off_st = off_vout + (uint64_t)Q * vs;
     off_err = (off_st + Q + 7) & ~7ull;
     bytes = off_err + 8;
+    if (sealed) {
+      off_tab = bytes;
+      off_req = (off_tab + 4ull * (Q + 1) + 255) & ~255ull;
+      off_resp = off_req + (uint64_t)Q * (32 + vs);
+      bytes = off_resp + (uint64_t)Q * (24 + vs);
+    }
   }
 };
 
@@ -85,6 +101,7 @@ struct SMap {
   uint32_t id = 0;
   bolt_params p{};
   uint32_t vs = 0;
+  bool sealed = false;  // BOLT_F_SEAL_CMDS: sealed requests only
   MapState state = kWaiting;
   bool closing = false;
   bool busy = false;
@@ -150,7 +167,7 @@ uint64_t map_footprint(const bolt_params* p, uint32_t Q) {
   uint64_t hbm = 0;
   if (bolt_footprint(p, &hbm, nullptr) != BOLT_OK) return 0;
   Stage s;
-  s.layout(Q, p->value_bytes);
+  s.layout(Q, p->value_bytes, (p->flags & BOLT_F_SEAL_CMDS) != 0);
   return hbm + s.bytes;
 }
 
@@ -239,8 +256,8 @@ int prepare(bolt_server* s, SMap* sm, hipStream_t st) {
   int rc = bolt_create(&sm->p, st, &sm->m);
   if (rc) return rc;
   const uint32_t Q = s->prm.max_batch;
-  sm->host.layout(Q, sm->vs);
-  sm->dev.layout(Q, sm->vs);
+  sm->host.layout(Q, sm->vs, sm->sealed);
+  sm->dev.layout(Q, sm->vs, sm->sealed);
   if (hipHostMalloc((void**)&sm->host.base, sm->host.bytes, hipHostMallocDefault) != hipSuccess) return BOLT_ENOMEM;
   if (hipMalloc((void**)&sm->dev.base, sm->dev.bytes) != hipSuccess) return BOLT_ENOMEM;
   if (sm->n) {
@@ -352,7 +369,9 @@ bool reap(bolt_server* s) {
       }
       uint64_t at = 0;
       for (const Req& r : pt.reqs) {
-        if (rc == BOLT_OK) {
+        if (rc == BOLT_OK && r.rec_out) {
+          memcpy(r.rec_out, sm->host.base + sm->host.off_resp + at * (24 + sm->vs), (size_t)r.q * (24 + sm->vs));
+        } else if (rc == BOLT_OK) {
           memcpy(r.vout, sm->host.base + sm->host.off_vout + at * sm->vs, (size_t)r.q * sm->vs);
           memcpy(r.status, sm->host.base + sm->host.off_st + at, r.q);
         }
@@ -410,21 +429,39 @@ bool launch(bolt_server* s) {
     SMap* sm = pt.map;
     uint8_t* h = sm->host.base;
     memset(h + sm->host.off_err, 0, 8);
-    uint64_t at = 0;
-    for (const Req& r : pt.reqs) {  // commands into the pinned staging, in FIFO order
-      memcpy(h + at, r.ops, r.q);
-      memcpy(h + sm->host.off_keys + at * 8, r.keys, (size_t)r.q * 8);
-      memcpy(h + sm->host.off_vin + at * sm->vs, r.vin, (size_t)r.q * sm->vs);
-      at += r.q;
-    }
     uint8_t* d = sm->dev.base;
-    // ops, keys and values in one copy each (the staging keeps them apart)
-    if (hipMemcpyAsync(d, h, pt.q, hipMemcpyHostToDevice, st) != hipSuccess ||
-        hipMemcpyAsync(d + sm->dev.off_keys, h + sm->host.off_keys, (size_t)pt.q * 8, hipMemcpyHostToDevice, st) !=
-            hipSuccess ||
-        hipMemcpyAsync(d + sm->dev.off_vin, h + sm->host.off_vin, (size_t)pt.q * sm->vs, hipMemcpyHostToDevice,
-                       st) != hipSuccess)
-      rc = BOLT_EHIP;
+    uint64_t at = 0;
+    if (sm->sealed) {  // command records and request starts into the staging; the device opens them
+      uint32_t* tab = reinterpret_cast<uint32_t*>(h + sm->host.off_tab);
+      uint32_t nreq = 0;
+      for (const Req& r : pt.reqs) {
+        tab[nreq++] = (uint32_t)at;
+        memcpy(h + sm->host.off_req + at * (32 + sm->vs), r.rec_in, (size_t)r.q * (32 + sm->vs));
+        at += r.q;
+      }
+      tab[nreq] = (uint32_t)at;
+      if (hipMemcpyAsync(d + sm->dev.off_tab, h + sm->host.off_tab, 4ull * (nreq + 1), hipMemcpyHostToDevice, st) !=
+              hipSuccess ||
+          hipMemcpyAsync(d + sm->dev.off_req, h + sm->host.off_req, (size_t)pt.q * (32 + sm->vs),
+                         hipMemcpyHostToDevice, st) != hipSuccess)
+        rc = BOLT_EHIP;
+      launch_rec_open(sm->m, d + sm->dev.off_req, pt.q, reinterpret_cast<const uint32_t*>(d + sm->dev.off_tab), nreq,
+                      d, reinterpret_cast<uint64_t*>(d + sm->dev.off_keys), d + sm->dev.off_vin, st);
+    } else {
+      for (const Req& r : pt.reqs) {  // commands into the pinned staging, in FIFO order
+        memcpy(h + at, r.ops, r.q);
+        memcpy(h + sm->host.off_keys + at * 8, r.keys, (size_t)r.q * 8);
+        memcpy(h + sm->host.off_vin + at * sm->vs, r.vin, (size_t)r.q * sm->vs);
+        at += r.q;
+      }
+      // ops, keys and values in one copy each (the staging keeps them apart)
+      if (hipMemcpyAsync(d, h, pt.q, hipMemcpyHostToDevice, st) != hipSuccess ||
+          hipMemcpyAsync(d + sm->dev.off_keys, h + sm->host.off_keys, (size_t)pt.q * 8, hipMemcpyHostToDevice, st) !=
+              hipSuccess ||
+          hipMemcpyAsync(d + sm->dev.off_vin, h + sm->host.off_vin, (size_t)pt.q * sm->vs, hipMemcpyHostToDevice,
+                         st) != hipSuccess)
+        rc = BOLT_EHIP;
+    }
     ms.push_back(sm->m);
     bs.push_back(bolt_batch{d, reinterpret_cast<const uint64_t*>(d + sm->dev.off_keys), d + sm->dev.off_vin,
                             d + sm->dev.off_vout, d + sm->dev.off_st, pt.q});
@@ -434,12 +471,21 @@ bool launch(bolt_server* s) {
   if (rc == BOLT_OK) {
     for (Part& pt : gr->parts) {
       SMap* sm = pt.map;
-      if (hipMemcpyAsync(sm->host.base + sm->host.off_vout, sm->dev.base + sm->dev.off_vout, (size_t)pt.q * sm->vs,
-                         hipMemcpyDeviceToHost, st) != hipSuccess ||
-          hipMemcpyAsync(sm->host.base + sm->host.off_st, sm->dev.base + sm->dev.off_st, pt.q, hipMemcpyDeviceToHost,
-                         st) != hipSuccess ||
-          hipMemcpyAsync(sm->host.base + sm->host.off_err, &sm->m->ctl->err, 4, hipMemcpyDeviceToHost, st) !=
-              hipSuccess)
+      uint8_t* d = sm->dev.base;
+      if (sm->sealed) {  // responses sealed on the device; only their records cross to the host
+        launch_rec_seal(sm->m, d + sm->dev.off_resp, pt.q, reinterpret_cast<const uint32_t*>(d + sm->dev.off_tab),
+                        (uint32_t)pt.reqs.size(), d + sm->dev.off_st, d + sm->dev.off_vout, st);
+        if (hipMemcpyAsync(sm->host.base + sm->host.off_resp, d + sm->dev.off_resp, (size_t)pt.q * (24 + sm->vs),
+                           hipMemcpyDeviceToHost, st) != hipSuccess)
+          rc = BOLT_EHIP;
+      } else if (hipMemcpyAsync(sm->host.base + sm->host.off_vout, d + sm->dev.off_vout, (size_t)pt.q * sm->vs,
+                                hipMemcpyDeviceToHost, st) != hipSuccess ||
+                 hipMemcpyAsync(sm->host.base + sm->host.off_st, d + sm->dev.off_st, pt.q, hipMemcpyDeviceToHost,
+                                st) != hipSuccess) {
+        rc = BOLT_EHIP;
+      }
+      if (hipMemcpyAsync(sm->host.base + sm->host.off_err, &sm->m->ctl->err, 4, hipMemcpyDeviceToHost, st) !=
+          hipSuccess)
         rc = BOLT_EHIP;
     }
   }
@@ -537,6 +583,7 @@ int bolt_server_open_map(bolt_server* s, const bolt_params* p, const uint64_t* h
   if (!sm) return BOLT_ENOMEM;
   sm->p = *p;
   sm->vs = p->value_bytes;
+  sm->sealed = (p->flags & BOLT_F_SEAL_CMDS) != 0;
   sm->n = n;
   sm->footprint = fp;
   if (n) {  // the build input goes to pinned memory now, so its copy to the device is a plain DMA later
@@ -597,13 +644,39 @@ int bolt_server_submit(bolt_server* s, uint32_t map_id, const uint8_t* host_ops,
     std::lock_guard<std::mutex> g(s->mu);
     if (map_id >= s->maps.size()) return BOLT_EINVAL;
     SMap* sm = s->maps[map_id];
-    if (q > s->prm.max_batch || sm->closing || sm->state == kClosed) return BOLT_EINVAL;
+    if (q > s->prm.max_batch || sm->closing || sm->state == kClosed || sm->sealed) return BOLT_EINVAL;
     if (sm->err || sm->state == kFailed) return BOLT_ESTATE;
     // a bad op code would reject the whole coalesced batch: refuse it here
     for (uint32_t i = 0; i < q; ++i)
       if (host_ops[i] > BOLT_OP_DEL) return BOLT_EINVAL;
     Req r{(uint64_t)s->results.size(), host_ops, host_keys, static_cast<const uint8_t*>(host_vals_in),
-          static_cast<uint8_t*>(host_vals_out), host_status, q, arrival_ns ? arrival_ns : now_ns()};
+          static_cast<uint8_t*>(host_vals_out), host_status, q, arrival_ns ? arrival_ns : now_ns(), nullptr,
+          nullptr};
+    s->results.push_back(kPending);
+    sm->queue.push_back(r);
+    s->queued++;
+    s->outstanding++;
+    s->st_submitted++;
+    s->st_queue_peak = std::max(s->st_queue_peak, s->queued);
+    s->st_first_arr = std::min(s->st_first_arr, r.t_arr);
+    *ticket = r.ticket;
+  }
+  s->cv_work.notify_one();
+  return BOLT_OK;
+}
+
+int bolt_server_submit_sealed(bolt_server* s, uint32_t map_id, const void* host_req_records, uint32_t q,
+                              void* host_resp_records, uint64_t arrival_ns, uint64_t* ticket) {
+  if (!s || !ticket || q == 0 || !host_req_records || !host_resp_records) return BOLT_EINVAL;
+  {
+    std::lock_guard<std::mutex> g(s->mu);
+    if (map_id >= s->maps.size()) return BOLT_EINVAL;
+    SMap* sm = s->maps[map_id];
+    if (q > s->prm.max_batch || sm->closing || sm->state == kClosed || !sm->sealed) return BOLT_EINVAL;
+    if (sm->err || sm->state == kFailed) return BOLT_ESTATE;
+    Req r{(uint64_t)s->results.size(), nullptr, nullptr, nullptr, nullptr, nullptr, q,
+          arrival_ns ? arrival_ns : now_ns(), static_cast<const uint8_t*>(host_req_records),
+          static_cast<uint8_t*>(host_resp_records)};
     s->results.push_back(kPending);
     sm->queue.push_back(r);
     s->queued++;

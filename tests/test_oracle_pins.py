@@ -261,8 +261,11 @@ MUTANTS = {
     "remap_from_fetch_words": [("or_pair(w[2], w[3], s->B, &r1[i], &r2[i]);",
                                 "or_pair(w[0], w[1], s->B, &r1[i], &r2[i]);")],
     # repeated keys read the mapped pair again instead of a fresh one
-    "repeats_read_mapped_pair": [("if (is_leader && or_pm_lookup(m, k, &hrow[i], &hidx[i])) {",
-                                  "if (or_pm_lookup(m, k, &hrow[i], &hidx[i])) {")],
+    "repeats_read_mapped_pair": [
+        ("    if (hit[i]) {\n      pr[0] = m->rows[hrow[i] * s->W + hidx[i]].p1;\n"
+         "      pr[1] = m->rows[hrow[i] * s->W + hidx[i]].p2;\n    }",
+         "    if (hit[leader[i]]) {\n      pr[0] = m->rows[hrow[leader[i]] * s->W + hidx[leader[i]]].p1;\n"
+         "      pr[1] = m->rows[hrow[leader[i]] * s->W + hidx[leader[i]]].p2;\n    }")],
 }
 
 
