@@ -40,6 +40,7 @@ class _Sizes(C.Structure):
         ("Z", C.c_uint32), ("d", C.c_uint32), ("kpr", C.c_uint32), ("W", C.c_uint32),
         ("B", C.c_uint64), ("K", C.c_uint64), ("M", C.c_uint64), ("R_pm", C.c_uint64),
         ("page_bytes", C.c_uint64), ("stash_bound", C.c_uint64), ("lmax", C.c_uint32),
+        ("hbm_bound", C.c_uint64),
     ]
 
     def as_dict(self) -> dict:
@@ -122,6 +123,9 @@ def _configure(lib):
     lib.or_pm_max_row.restype = C.c_uint32
     lib.or_chacha20_block.argtypes = [P, C.c_uint32, P, P]
     lib.or_set_seal.argtypes = [P]
+    lib.or_set_decomposed.argtypes = [P]
+    lib.or_hbm_live.argtypes = [P]
+    lib.or_hbm_live.restype = C.c_uint64
     for name in ("or_tags_ptr", "or_ver_ptr"):
         getattr(lib, name).argtypes = [P]
         getattr(lib, name).restype = C.c_void_p
@@ -411,7 +415,7 @@ class PlainMapC:
 
 class OracleMap:
     def __init__(self, cap, vs, c=8, alpha_pm=200, bin_slots=0, d=4, kpr=16, W=32, key=bytes(32),
-                 trace=False, seal=False, lib=None):
+                 trace=False, seal=False, lib=None, decomposed=False):
         lib = lib if lib is not None else _load()
         kb = (C.c_uint8 * 32).from_buffer_copy(bytes(key))
         self._h = lib.or_create(cap, vs, c, alpha_pm, bin_slots, d, kpr, W, kb, 1 if trace else 0)
@@ -422,6 +426,9 @@ class OracleMap:
         self.sealed = bool(seal)
         if seal and lib.or_set_seal(self._h):
             raise ValueError("sealing")
+        self.decomposed = bool(decomposed)
+        if decomposed and lib.or_set_decomposed(self._h):
+            raise ValueError("decomposed")
 
     def tags(self) -> np.ndarray:
         """(M, 16) Poly1305 tags of the sealed pages."""
@@ -556,6 +563,11 @@ class OracleMap:
     @property
     def stash_live(self):
         return int(self._lib.or_stash_live(self._h))
+
+    @property
+    def hbm_live(self):
+        """Items of the HBM bins held in the value pool (decomposed store)."""
+        return int(self._lib.or_hbm_live(self._h))
 
     @property
     def stash_highwater(self):

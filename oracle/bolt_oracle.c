@@ -466,6 +466,7 @@ typedef struct {
   uint64_t page_bytes; /* bytes per page and per HBM bin */
   uint64_t stash_bound;/* Claim 4.4 with the O() constant set to 1 */
   uint32_t lmax;       /* l_max of Claim 4.2 with the O() constant set to 1 */
+  uint64_t hbm_bound;  /* Claim 4.3 with the O() constant set to 1: items the K HBM bins may hold */
 } or_sizes;
 
 static uint32_t or_ceil_log2(uint64_t x) {
@@ -524,6 +525,7 @@ int or_sizing(uint64_t cap, uint32_t vs, uint32_t c, uint32_t alpha_pm, uint32_t
   uint64_t raw = 8 + 8ull * s->Z + (uint64_t)vs * s->Z;
   s->page_bytes = (raw + 127) / 128 * 128;
   s->stash_bound = or_stash_bound(s->M, alpha_pm, s->lmax, cap);
+  s->hbm_bound = (uint64_t)ceil(or_claim43_bound((double)s->K, (double)c, (double)s->lmax, (double)cap));
   return 0;
 }
 
@@ -670,7 +672,11 @@ typedef struct {
   int64_t* st_next;
   int64_t* st_head;    /* B */
   uint64_t st_cap, st_used, st_live;
+  uint64_t hbm_live;   /* entries destined for HBM bins (decomposed layout only) */
   int64_t st_free;     /* free list of pool entries */
+  /* decomposed HBM store (Sec. 5.2): the items of HBM bins live in the
+   * same value pool as the stash, listed under their bin; no HBM pages */
+  int decomposed;
   uint64_t ctr, live, batch_no, stash_hw;
   int built, poisoned;
   int trace_on;
@@ -743,6 +749,15 @@ int or_set_seal(or_map* m) {
   m->tags = calloc(m->s.M ? m->s.M : 1, 16);
   m->ver = calloc(m->s.M ? m->s.M : 1, sizeof(uint64_t));
   m->seal_on = 1;
+  return OR_OK;
+}
+
+/* Turns on the decomposed HBM store (before the build): the items of the
+ * K HBM bins are kept as value-pool entries listed under their bin (the
+ * reverse index the stash already uses), not as dummy-padded pages. */
+int or_set_decomposed(or_map* m) {
+  if (m->built) return OR_EINVAL;
+  m->decomposed = 1;
   return OR_OK;
 }
 
@@ -929,6 +944,7 @@ static int64_t or_stash_push(or_map* m, uint64_t key, const uint8_t* val, uint32
   m->st_next[e] = m->st_head[dest];
   m->st_head[dest] = e;
   m->st_live++;
+  if (dest < m->s.K) m->hbm_live++;
   return e;
 }
 
@@ -941,6 +957,7 @@ static void or_stash_remove(or_map* m, int64_t e) {
   m->st_next[e] = m->st_free;
   m->st_free = e;
   m->st_live--;
+  if (b < m->s.K) m->hbm_live--;
 }
 
 /* --- build -------------------------------------------------------- */
@@ -1035,6 +1052,7 @@ int or_build(or_map* m, const uint64_t* keys, const uint8_t* vals, uint64_t n, i
           memcpy(wbin.val + (size_t)wbin.n * s->vs, vals + (size_t)i * s->vs, s->vs);
           wbin.n++;
         }
+        if (b < s->K && m->decomposed) continue; /* pushed to the value pool below */
         or_encode(m, &wbin, wpage);
         if (b < s->K)
           memcpy(m->hbm + b * s->page_bytes, wpage, s->page_bytes);
@@ -1044,6 +1062,13 @@ int or_build(or_map* m, const uint64_t* keys, const uint8_t* vals, uint64_t n, i
       or_bin_free(&wbin);
       free(wpage);
     }
+    if (m->decomposed) /* the HBM bins' items into the value pool, bin by bin */
+      for (uint64_t b = 0; b < s->K; ++b)
+        for (uint32_t j = 0; j < s->Z; ++j) {
+          uint32_t i = slot_src[b * s->Z + j];
+          if (i != OR_NONE) or_stash_push(m, keys[i], vals + (size_t)i * s->vs, (uint32_t)b);
+        }
+    if (m->hbm_live > s->hbm_bound) over = 1;
     free(slot_src);
     /* a7: position map (key -> p1, p2), d-choice rows in rounds. */
     if (or_pm_insert_rounds(m, n, keys, p1, p2)) over = 1;
@@ -1262,12 +1287,12 @@ int or_access(or_map* m, const uint8_t* ops, const uint64_t* keys, const uint8_t
     for (uint32_t o = 0; o < nplace; ++o) {
       uint32_t i = ord[o];
       uint64_t b = chosen[o];
-      if (b < s->K) { /* HBM bin: insert directly */
+      if (b < s->K && !m->decomposed) { /* HBM bin: insert directly */
         or_bin* wb = or_work_get(m, &ws, b, m->hbm + b * s->page_bytes);
         wb->key[wb->n] = keys[i];
         memcpy(wb->val + (size_t)wb->n * vs, cur + (size_t)i * vs, vs);
         wb->n++;
-      } else { /* host bin: into the eviction stash */
+      } else { /* host bin (or any bin of a decomposed store): into the value pool */
         or_stash_push(m, keys[i], cur + (size_t)i * vs, (uint32_t)b);
       }
     }
@@ -1319,9 +1344,11 @@ int or_access(or_map* m, const uint8_t* ops, const uint64_t* keys, const uint8_t
       or_obs_write(m, fetched[f], page);
     }
     for (uint64_t x = 0; x < ws.n; ++x) /* HBM bins: no observable access */
-      if (ws.bin_of[x] < s->K) or_encode(m, &ws.work[x], m->hbm + ws.bin_of[x] * s->page_bytes);
-    if (m->st_live > s->stash_bound) over = 1;
-    if (m->st_live > m->stash_hw) m->stash_hw = m->st_live;
+      if (ws.bin_of[x] < s->K && !m->decomposed) or_encode(m, &ws.work[x], m->hbm + ws.bin_of[x] * s->page_bytes);
+    uint64_t host_live = m->st_live - m->hbm_live; /* the stash proper: items bound for host pages */
+    if (host_live > s->stash_bound) over = 1;
+    if (m->hbm_live > s->hbm_bound) over = 1;
+    if (host_live > m->stash_hw) m->stash_hw = host_live;
   }
 
   for (uint64_t x = 0; x < ws.n; ++x) or_bin_free(&ws.work[x]);
@@ -1482,7 +1509,8 @@ const uint8_t* or_hbm_ptr(const or_map* m) { return m->hbm; }
 const uint32_t* or_load_ptr(const or_map* m) { return m->load; }
 uint64_t or_ctr(const or_map* m) { return m->ctr; }
 uint64_t or_live(const or_map* m) { return m->live; }
-uint64_t or_stash_live(const or_map* m) { return m->st_live; }
+uint64_t or_stash_live(const or_map* m) { return m->st_live - m->hbm_live; }
+uint64_t or_hbm_live(const or_map* m) { return m->hbm_live; }
 uint64_t or_stash_highwater(const or_map* m) { return m->stash_hw; }
 uint64_t or_trace_len(const or_map* m) { return m->trace_n; }
 
