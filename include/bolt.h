@@ -87,6 +87,9 @@ enum { BOLT_OBS_HOST_PINNED = 0, BOLT_OBS_DEVICE = 1 };
                                size (fewer host launch calls; results identical).  Not with TIMING. */
 #define BOLT_F_SEAL_CMDS 128u /* commands and responses cross the host sealed: bolt_access_sealed and
                                bolt_server_submit_sealed take ChaCha20-Poly1305 records under params.session_key */
+#define BOLT_F_DECOMPOSED 256u /* the decomposed HBM store of Sec. 5.2: the HBM bins' items are value-pool
+                               entries listed under their bin (the reverse index), allocated from a free-address
+                               ring; no dummy-padded HBM pages.  Results, pages and trace as without it. */
 #define BOLT_F_SEAL_KEY_REUSE 64u /* tests only: allow BOLT_F_SEAL together with BOLT_F_FIXED_KEY.  The page key
                                derives from the PRF key and every build starts the write counts at 1, so two maps
                                sealed under one fixed key (or a map re-created with its key) encrypt with the same
@@ -124,8 +127,9 @@ typedef struct {
   uint64_t page_bytes;  /* bytes per page: u64 valid mask, Z keys, Z values, zero pad to 128 */
   uint64_t pm_rows;     /* position-map rows = ceil(N_max / pm_keys_per_row) */
   uint64_t stash_bound; /* ceil((1 + alpha) M / 2 + l_max sqrt(M ln N_max)) (Claim 4.4, constant 1) */
-  uint64_t stash_pool;  /* stash entries allocated: stash_bound + BOLT_MAX_BATCH */
+  uint64_t stash_pool;  /* value-pool entries: stash_bound + BOLT_MAX_BATCH, plus hbm_bound when decomposed */
   uint64_t lmax;        /* l_max = c + ceil(log2 ceil(log2 N_max)) + 1, the bound of Claim 4.2 (constant 1) */
+  uint64_t hbm_bound;   /* ceil(K c + l_max sqrt(K ln N_max)): items the HBM bins may hold (Claim 4.3) */
 } bolt_sizes;
 
 /* Fills p with the paper's defaults (c = 8, alpha = 0.2, d = 4, 16 keys per

@@ -23,6 +23,7 @@ BOLT_OBS_HOST_PINNED, BOLT_OBS_DEVICE = 0, 1
 BOLT_F_TRACE, BOLT_F_FIXED_KEY, BOLT_F_TIMING, BOLT_F_GRAPHS, BOLT_F_WATCH, BOLT_F_SEAL = 1, 2, 4, 8, 16, 32
 BOLT_F_SEAL_KEY_REUSE = 64
 BOLT_F_SEAL_CMDS = 128
+BOLT_F_DECOMPOSED = 256
 BOLT_MAX_BATCH = 8192
 BOLT_NOALLOC_EXPAND_MAX = 1 << 21
 BOLT_ETIMEOUT = -8
@@ -52,7 +53,7 @@ class bolt_params(C.Structure):
 
 class bolt_sizes(C.Structure):
     _fields_ = [(n, C.c_uint64) for n in ("B", "K", "M", "Z", "page_bytes", "pm_rows", "stash_bound", "stash_pool",
-                                          "lmax")]
+                                          "lmax", "hbm_bound")]
 
     def as_dict(self):
         return {n: int(getattr(self, n)) for n, _ in self._fields_}

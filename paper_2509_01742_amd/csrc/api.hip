@@ -56,7 +56,11 @@ int derive(const bolt_params* p, Sizes* s) {
   double a = (double)p->alpha_permille / 1000.0;
   double x = (1.0 + a) * (double)z.M / 2.0 + (double)z.lmax * sqrt((double)z.M * log((double)p->capacity));
   z.stash_bound = (uint64_t)ceil(x);
-  z.P = z.stash_bound + kMaxBatch;
+  // Claim 4.3 with constant 1: items the K HBM bins may hold
+  z.hbm_bound = (uint64_t)ceil((double)z.K * (double)p->c +
+                               (double)z.lmax * sqrt((double)z.K * log((double)p->capacity)));
+  // the value pool: stash entries, plus the HBM bins' items in a decomposed store
+  z.P = z.stash_bound + kMaxBatch + ((p->flags & BOLT_F_DECOMPOSED) ? z.hbm_bound : 0);
   z.BZ = z.B * z.Z;
   z.PW = (z.P + 63) / 64;
   if (z.BZ >= (1ull << 32) || z.P >= (1ull << 32)) return BOLT_EINVAL;
@@ -75,7 +79,9 @@ uint64_t scratch_bytes(const Sizes& s) {
 
 uint64_t device_bytes(const bolt_params* p, const Sizes& s) {
   uint64_t b = sizeof(Ctl);
-  b += s.K * s.page_bytes;
+  const bool decomp = (p->flags & BOLT_F_DECOMPOSED) != 0;
+  if (!decomp) b += s.K * s.page_bytes;  // HBM bins as pages
+  else b += s.P * 4;                     // the free-address ring
   if (p->observable == BOLT_OBS_DEVICE) b += s.M * (s.page_bytes + ((p->flags & BOLT_F_SEAL) ? 16 : 0));
   if (p->flags & BOLT_F_SEAL) b += s.M * 8;  // write counts
   b += s.B * 4;                      // load
@@ -187,6 +193,7 @@ int bolt_sizes_of(const bolt_params* p, bolt_sizes* out) {
     out->stash_bound = s.stash_bound;
     out->stash_pool = s.P;
     out->lmax = s.lmax;
+    out->hbm_bound = s.hbm_bound;
   }
   return BOLT_OK;
 }
@@ -236,7 +243,10 @@ int bolt_create(const bolt_params* p, void* hip_stream, bolt_map** out) {
   const uint64_t Q = kMaxBatch;
   rc = BOLT_OK;
   rc = rc ? rc : dalloc(m, &m->ctl, sizeof(Ctl));
-  rc = rc ? rc : dalloc(m, &m->hbm, s.K * s.page_bytes);
+  if (p->flags & BOLT_F_DECOMPOSED)  // no HBM pages: the ring of the value pool instead
+    rc = rc ? rc : dalloc(m, &m->ring, s.P * 4);
+  else
+    rc = rc ? rc : dalloc(m, &m->hbm, s.K * s.page_bytes);
   rc = rc ? rc : dalloc(m, &m->load, s.B * 4);
   rc = rc ? rc : dalloc(m, &m->pm_key, s.R * s.W * 8);
   rc = rc ? rc : dalloc(m, &m->pm_pair, s.R * s.W * 8);
@@ -651,6 +661,10 @@ int bolt_hbm_snapshot(bolt_map* m, void* host_buf, uint64_t cap) {
   int rc = sync_and_read(m, &c);
   if (rc) return rc;
   if (!bytes) return BOLT_OK;
+  if (!m->hbm) {  // decomposed store: no HBM pages, every bin reads as empty
+    memset(host_buf, 0, bytes);
+    return BOLT_OK;
+  }
   return hipMemcpy(host_buf, m->hbm, bytes, hipMemcpyDeviceToHost) == hipSuccess ? BOLT_OK : BOLT_EHIP;
 }
 
@@ -679,7 +693,18 @@ int bolt_stash_snapshot(bolt_map* m, uint64_t* host_keys, uint32_t* host_bins, v
       hipMemcpy(val.data(), m->st_val, s.P * s.vs, hipMemcpyDeviceToHost) != hipSuccess)
     return BOLT_EHIP;
   std::vector<uint8_t> is_free(s.P, 0);
-  for (uint64_t e = 0; e < s.P; ++e) is_free[e] = !((used[e >> 6] >> (e & 63)) & 1);
+  if (m->ring) {  // decomposed store: the free entries are those in the ring's free range, each once
+    std::vector<uint32_t> ring(s.P);
+    if (hipMemcpy(ring.data(), m->ring, s.P * 4, hipMemcpyDeviceToHost) != hipSuccess) return BOLT_EHIP;
+    if (c.ring_tail < c.ring_head || c.ring_tail - c.ring_head > s.P) return BOLT_ESTATE;
+    for (uint64_t j = c.ring_head; j < c.ring_tail; ++j) {
+      const uint32_t e = ring[j % s.P];
+      if (e >= s.P || is_free[e]) return BOLT_ESTATE;  // the ring lost its shape (a library bug)
+      is_free[e] = 1;
+    }
+  } else {
+    for (uint64_t e = 0; e < s.P; ++e) is_free[e] = !((used[e >> 6] >> (e & 63)) & 1);
+  }
   uint64_t k = 0;
   for (uint64_t e = 0; e < s.P; ++e) {
     if (is_free[e]) continue;

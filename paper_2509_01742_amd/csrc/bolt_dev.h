@@ -39,6 +39,17 @@ struct Ctl {
   uint64_t hbm_hw;       // BOLT_F_WATCH: largest hbm_load seen
   uint32_t ckey[8];      // BOLT_F_SEAL_CMDS: session key of the command and response records
   uint64_t seq;          // BOLT_F_SEAL_CMDS: sealed requests run so far (the next is seq + 1)
+  // BOLT_F_DECOMPOSED: the free-address ring of the value pool and the
+  // pool's HBM-bin items.  Ring positions [ring_head, ring_tail) hold the
+  // free entries (modulo the pool size); a batch takes ring_take of them
+  // from the head and returns ring_give at the tail, both folded in at its
+  // end.
+  uint64_t ring_head, ring_tail;
+  uint32_t ring_take, ring_give;
+  uint64_t pool_live;    // pool entries in use at the end of the last batch (stash plus HBM-bin items)
+  uint64_t hbm_live;     // of which items of HBM bins
+  uint32_t b_hbm_in;     // items the current batch placed in HBM bins
+  uint32_t b_hbm_rm;     // items the current batch removed from HBM bins
 };
 
 // ---------------------------------------------------------------------------
@@ -199,6 +210,32 @@ __device__ __forceinline__ uint32_t pool_alloc(uint64_t* used, uint64_t nwords, 
 
 __device__ __forceinline__ void pool_free(uint64_t* used, uint32_t e) {
   atomicAnd((unsigned long long*)&used[e >> 6], ~(1ull << (e & 63)));
+}
+
+// The free-address ring of a decomposed store (Sec. 5.2, "Dynamic HBM
+// management"): entries are taken at the head and returned at the tail.
+// The active lanes of a wave that call these together share one atomic.
+// ring_alloc returns kNone when the ring has no free entry left.
+__device__ __forceinline__ uint32_t ring_alloc(Ctl* ctl, const uint32_t* ring, uint64_t P) {
+  const uint64_t act = __ballot(1);
+  const uint32_t lane = threadIdx.x & 63;
+  const uint32_t first = (uint32_t)__builtin_ctzll(act);
+  uint32_t base = 0;
+  if (lane == first) base = atomicAdd(&ctl->ring_take, (uint32_t)__popcll(act));
+  base = (uint32_t)__shfl((int)base, (int)first, 64);
+  const uint64_t pos = ctl->ring_head + base + __popcll(act & ((1ull << lane) - 1));
+  if (pos >= ctl->ring_tail) return kNone;
+  return ring[pos % P];
+}
+
+__device__ __forceinline__ void ring_free(Ctl* ctl, uint32_t* ring, uint64_t P, uint32_t e) {
+  const uint64_t act = __ballot(1);
+  const uint32_t lane = threadIdx.x & 63;
+  const uint32_t first = (uint32_t)__builtin_ctzll(act);
+  uint32_t base = 0;
+  if (lane == first) base = atomicAdd(&ctl->ring_give, (uint32_t)__popcll(act));
+  base = (uint32_t)__shfl((int)base, (int)first, 64);
+  ring[(ctl->ring_tail + base + __popcll(act & ((1ull << lane) - 1))) % P] = e;
 }
 
 __device__ __forceinline__ uint64_t alloc_hash(uint32_t epoch, uint32_t i) {

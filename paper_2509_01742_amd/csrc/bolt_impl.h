@@ -83,7 +83,7 @@ struct TimedScope {
 };
 
 struct Sizes {
-  uint64_t cap, B, K, M, Z, W, d, R, page_bytes, stash_bound, P, BZ, PW, lmax;
+  uint64_t cap, B, K, M, Z, W, d, R, page_bytes, stash_bound, P, BZ, PW, lmax, hbm_bound;
   uint32_t vs;
 };
 
@@ -97,7 +97,8 @@ struct bolt_map {
   bolt::Ctl* ctl;
   uint8_t* obs;       // M pages (device pointer; maps pinned host memory in host mode)
   uint8_t* obs_host;  // host pointer of the pinned store, or null
-  uint8_t* hbm;       // K HBM bins
+  uint8_t* hbm;       // K HBM bins (null in a decomposed store)
+  uint32_t* ring;     // BOLT_F_DECOMPOSED: [P] the value pool's free-address ring, else null
   uint32_t* load;     // [B]
   uint64_t* pm_key;   // [R * W]
   uint2* pm_pair;     // [R * W]

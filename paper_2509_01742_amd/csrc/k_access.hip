@@ -107,6 +107,7 @@ struct FetchArgs {
   ShipArgs ship;           // a slice of the previous batch's send ...
   uint32_t ship_blocks;    // ... by the first ship_blocks workgroups
   uint32_t pre_host;       // 1: observable pages are read ahead too (device store)
+  uint32_t decomp;         // BOLT_F_DECOMPOSED: an HBM bin is only its list (no page)
 };
 
 struct ResolveArgs {
@@ -164,6 +165,9 @@ struct PlaceArgs {
   const uint4* rows;  // [Q] position-map rows of each command's key (from the dedup kernel)
   ShipArgs ship;  // a slice of the previous batch's send, by the first ship_blocks workgroups
   uint32_t ship_blocks;
+  uint32_t decomp;  // BOLT_F_DECOMPOSED: entries come from the free-address ring
+  uint32_t* ring;
+  uint64_t P;
 };
 
 struct RemapArgs {
@@ -194,6 +198,9 @@ struct RemapArgs {
   uint2* pm_pair;
   uint32_t* pm_mask;
   const uint4* rows;  // [Q] position-map rows of each command's key
+  uint32_t decomp;    // BOLT_F_DECOMPOSED: entries come from the free-address ring
+  uint32_t* ring;
+  uint64_t P;
 };
 
 struct WbArgs {
@@ -206,7 +213,7 @@ struct WbArgs {
   const uint64_t* stage;
   uint64_t* hbm;
   uint32_t* rev_cnt;
-  const uint32_t* rev_idx;
+  uint32_t* rev_idx;
   const uint64_t* st_key;
   const uint64_t* st_val;
   uint32_t* st_dead;
@@ -222,13 +229,16 @@ struct WbArgs {
   uint64_t* pver;       // direct, BOLT_F_SEAL: [M] page write counts
   ShipArgs ship;  // a slice of the previous batch's send, by the first ship_blocks workgroups
   uint32_t ship_blocks;
+  uint32_t decomp;  // BOLT_F_DECOMPOSED: HBM bins keep their items listed; frees go to the ring
+  uint32_t* ring;
+  uint64_t P;
 };
 
 
 struct FinishArgs {
   Ctl* ctl;
   uint32_t q, W, epoch;
-  uint64_t cap, stash_bound;
+  uint64_t cap, stash_bound, hbm_bound;
   const uint32_t* rowsel;
   const uint64_t* keys;
   const uint2* rpair;
@@ -809,16 +819,17 @@ __device__ __forceinline__ void fetch_cmd(const FetchArgs& a, uint32_t i, uint64
     for (uint32_t r = 0; r < 2; ++r) {
       const uint32_t b = r ? p2 : p1;
       const bool host = b >= a.K;
+      const bool pooled = a.decomp && !host;  // decomposed HBM bin: its list only
       const uint64_t* src = host ? a.obs + (uint64_t)(b - a.K) * a.pw : a.hbm + (uint64_t)b * a.pw;
-      if (!host || a.pre_host) {
+      if (!pooled && (!host || a.pre_host)) {
         pre0[r] = lane < a.pw ? src[lane] : 0;
         pre1[r] = lane + 64 < a.pw ? src[lane + 64] : 0;
       }
-      if (host) {
+      if (host || pooled) {
         pcnt[r] = a.rev_cnt[b];
         pidx[r] = lane < 2 * a.Z ? a.rev_idx[(uint64_t)b * 2 * a.Z + lane] : kNone;
-        if (a.ov_epoch) pws[r] = a.wslot[b - a.K];
       }
+      if (host && a.ov_epoch) pws[r] = a.wslot[b - a.K];
     }
   }
   bool found = false;
@@ -869,8 +880,9 @@ __device__ __forceinline__ void fetch_cmd(const FetchArgs& a, uint32_t i, uint64
       wave_sync();
       src = pg;
     }
+    const bool pooled = a.decomp && !host;  // no page: it reads as empty
     const bool pre = !SEALED && !fresh && (!host || a.pre_host);  // the page words loaded above are the page's
-    const uint64_t v0 = pre ? pre0[role] : (lane < a.pw ? src[lane] : 0);
+    const uint64_t v0 = pooled ? 0 : (pre ? pre0[role] : (lane < a.pw ? src[lane] : 0));
     if (host && lane < a.pw) stg[lane] = v0;
     // find the key among the page's slots (lanes 1..Z hold the keys)
     const bool search = is_leader && hit && !found;
@@ -883,7 +895,7 @@ __device__ __forceinline__ void fetch_cmd(const FetchArgs& a, uint32_t i, uint64
     }
     const uint64_t vlo = 1 + a.Z + (uint64_t)(fslot < 0 ? 0 : fslot) * a.vw;
     if (fslot >= 0 && lane >= vlo && lane < vlo + a.vw) a.fval[(uint64_t)i * a.vw + (lane - vlo)] = v0;
-    for (uint64_t wi = lane + 64; wi < a.pw; wi += 64) {
+    for (uint64_t wi = lane + 64; !pooled && wi < a.pw; wi += 64) {
       const uint64_t v = (pre && wi < 128) ? pre1[role] : src[wi];
       if (host) stg[wi] = v;
       if (fslot >= 0 && wi >= vlo && wi < vlo + a.vw) a.fval[(uint64_t)i * a.vw + (wi - vlo)] = v;
@@ -894,8 +906,8 @@ __device__ __forceinline__ void fetch_cmd(const FetchArgs& a, uint32_t i, uint64
         atomicOr((unsigned long long*)&a.rmask[b], (unsigned long long)(1ull << fslot));
         atomicSub(&a.load[b], 1u);
       }
-    } else if (search && host) {
-      // the stash items listed for this bin
+    } else if (search && (host || pooled)) {
+      // the stash items listed for this bin (all of a decomposed HBM bin's items)
       const uint32_t cnt_raw = SEALED ? a.rev_cnt[b] : pcnt[role];
       const uint32_t cnt = cnt_raw < 2 * a.Z ? cnt_raw : 2 * a.Z;
       int fe = -1;
@@ -916,6 +928,7 @@ __device__ __forceinline__ void fetch_cmd(const FetchArgs& a, uint32_t i, uint64
         if (lane == 0) {
           a.st_dead[fe] = 1;
           atomicSub(&a.load[b], 1u);
+          if (pooled) atomicAdd(&a.ctlw->b_hbm_rm, 1u);
         }
       }
     }
@@ -1029,11 +1042,17 @@ __global__ __launch_bounds__(256) void k_acc_resolve(ResolveArgs a1, const Acces
 
 
 // Stores an item in a fresh stash entry listed under bin b.
-__device__ __forceinline__ bool stash_put(uint64_t* st_used, uint64_t PW, uint64_t* st_key, uint64_t* st_val,
-                                          uint32_t* st_dest, uint32_t* st_dead, uint32_t* rev_cnt,
-                                          uint32_t* rev_idx, uint32_t Z, uint32_t vw, uint32_t epoch, uint32_t i,
-                                          uint64_t key, const uint64_t* val, uint32_t b) {
-  const uint32_t e = pool_alloc(st_used, PW, alloc_hash(epoch, i), (uint32_t)PW);
+__device__ __forceinline__ bool stash_put(const RemapArgs& a, uint32_t i, uint64_t key, const uint64_t* val,
+                                          uint32_t b) {
+  uint64_t* const st_key = a.st_key;
+  uint64_t* const st_val = a.st_val;
+  uint32_t* const st_dest = a.st_dest;
+  uint32_t* const st_dead = a.st_dead;
+  uint32_t* const rev_cnt = a.rev_cnt;
+  uint32_t* const rev_idx = a.rev_idx;
+  const uint32_t Z = a.Z, vw = a.vw;
+  const uint32_t e = a.decomp ? ring_alloc(a.ctl, a.ring, a.P) : pool_alloc(a.st_used, a.PW, alloc_hash(a.epoch, i),
+                                                                             (uint32_t)a.PW);
   if (e == kNone) return false;
   st_key[e] = key;
   for (uint32_t x = 0; x < vw; ++x) st_val[(uint64_t)e * vw + x] = val[x];
@@ -1049,7 +1068,7 @@ __device__ __forceinline__ bool stash_put(uint64_t* st_used, uint64_t PW, uint64
 // wave calls it.
 __device__ __forceinline__ void place_cmd(const PlaceArgs& a, uint32_t i) {
   if (a.ctl->reject == a.epoch || a.ctl->err) return;
-  bool placed = false, ins = false;
+  bool placed = false, ins = false, to_hbm = false;
   if (i < a.q) {
     a.cand_bin[2 * a.q + i] = kNone;
     a.rowsel[i] = kNone;
@@ -1063,10 +1082,11 @@ __device__ __forceinline__ void place_cmd(const PlaceArgs& a, uint32_t i) {
       const uint64_t key = a.keys[i];
       const uint32_t old = atomicAdd(&a.load[b], 1u);
       const uint32_t ls = atomicAdd(&a.rev_cnt[b], 1u);
-      if (b < a.K) {  // HBM bins are rebuilt in this batch
+      if (b < a.K && !a.decomp) {  // HBM bins are rebuilt in this batch
         a.cand_bin[2 * a.q + i] = b;
         atomicMax((unsigned long long*)&a.claim[b], (unsigned long long)claim_tag(a.epoch, 2 * a.q + i));
       }
+      to_hbm = a.decomp && b < a.K;  // a decomposed HBM bin keeps the entry listed
       if (fin & 2) {
         a.pm_pair[(uint64_t)a.hrow[i] * a.W + a.hslot[i]] = a.rpair[i];
       } else {
@@ -1086,7 +1106,8 @@ __device__ __forceinline__ void place_cmd(const PlaceArgs& a, uint32_t i) {
         ins = true;
       }
       // the item goes to a fresh stash entry listed under bin b
-      const uint32_t e = pool_alloc(a.st_used, a.PW, alloc_hash(a.epoch, i), (uint32_t)a.PW);
+      const uint32_t e = a.decomp ? ring_alloc(a.ctl, a.ring, a.P)
+                                  : pool_alloc(a.st_used, a.PW, alloc_hash(a.epoch, i), (uint32_t)a.PW);
       const uint64_t* src = lw != kNone ? a.vals_in + (uint64_t)lw * a.vw : a.fval + (uint64_t)i * a.vw;
       if (e != kNone) {
         a.st_key[e] = key;
@@ -1101,6 +1122,7 @@ __device__ __forceinline__ void place_cmd(const PlaceArgs& a, uint32_t i) {
   }
   wave_count(&a.ctl->b_place, placed);
   wave_count(&a.ctl->b_ins, ins);
+  if (a.decomp) wave_count(&a.ctl->b_hbm_in, to_hbm);
 }
 
 template <bool MULTI>
@@ -1183,10 +1205,9 @@ __global__ __launch_bounds__(kRemapNT) void k_acc_remap(RemapArgs a1, const Acce
     const uint32_t b = chosen[t];
     const uint32_t lw = a.lastw[i];
     const uint64_t* src = lw != kNone ? a.vals_in + (uint64_t)lw * a.vw : a.fval + (uint64_t)i * a.vw;
-    if (!stash_put(a.st_used, a.PW, a.st_key, a.st_val, a.st_dest, a.st_dead, a.rev_cnt, a.rev_idx, a.Z, a.vw,
-                   a.epoch, i, a.keys[i], src, b))
-      set_err(a.ctl, kErrOverflow);
-    if (b < a.K) {  // HBM bins are rebuilt in this batch
+    if (!stash_put(a, i, a.keys[i], src, b)) set_err(a.ctl, kErrOverflow);
+    if (a.decomp && b < a.K) atomicAdd(&a.ctl->b_hbm_in, 1u);  // listed under its HBM bin for good
+    if (b < a.K && !a.decomp) {  // HBM bins are rebuilt in this batch
       a.cand_bin[2 * a.q + i] = b;
       atomicMax((unsigned long long*)&a.claim[b], (unsigned long long)claim_tag(a.epoch, 2 * a.q + i));
     }
@@ -1287,8 +1308,9 @@ __device__ __forceinline__ void compose_slot(const WbArgs& a, uint32_t s, uint64
   // The election's outcome and the bin's data are loaded together (a slot
   // that lost the election drops what it read).
   const uint64_t cl = a.claim[b];
+  const bool pooled = a.decomp && !host;  // a decomposed HBM bin: its list only
   const uint64_t* src = host ? a.stage + (uint64_t)s * a.pw : a.hbm + (uint64_t)b * a.pw;
-  for (uint64_t w = lane; w < a.pw; w += 64) old[w] = src[w];
+  for (uint64_t w = lane; w < a.pw; w += 64) old[w] = pooled ? 0 : src[w];
   const uint64_t rm = a.rmask[b];
   const uint32_t cnt_raw = a.rev_cnt[b];
   const uint32_t e_spec = lane < 2 * a.Z ? a.rev_idx[(uint64_t)b * 2 * a.Z + lane] : kNone;  // the bin's list row
@@ -1329,6 +1351,32 @@ __device__ __forceinline__ void compose_slot(const WbArgs& a, uint32_t s, uint64
     return;
   }
   wave_sync();
+  if (pooled) {
+    // A decomposed HBM bin keeps its live entries listed (the first n_alive
+    // list positions, all below 64, were read into e_spec before) and
+    // returns the dead ones to the ring.
+    uint32_t ndead = 0;
+    for (uint32_t base = 0; base < cnt; base += 64) {
+      const uint32_t l = base + lane;
+      bool dead = false;
+      if (l < cnt) {
+        const uint32_t e = base == 0 ? e_spec : a.rev_idx[(uint64_t)b * 2 * a.Z + l];
+        dead = a.st_dead[e] != 0;
+        if (dead) {
+          a.st_dead[e] = 0;
+          ring_free(a.ctl, a.ring, a.P, e);
+        }
+      }
+      ndead += __popcll(__ballot(dead));
+    }
+    if (lane < n_alive) a.rev_idx[(uint64_t)b * 2 * a.Z + lane] = isrc[lane] & 0x7FFFFFFFu;
+    if (lane == 0) {
+      a.rmask[b] = 0;
+      a.rev_cnt[b] = n_alive;
+      if (ndead) atomicAdd(&a.freed[s % kFreeBuckets], ndead);
+    }
+    return;
+  }
   // canonical order: ascending key
   if (lane < n_items) {
     const uint64_t mine = ikey[lane];
@@ -1378,7 +1426,10 @@ __device__ __forceinline__ void compose_slot(const WbArgs& a, uint32_t s, uint64
   for (uint32_t l = lane; l < cnt; l += 64) {
     const uint32_t e = l < 64 ? e_spec : a.rev_idx[(uint64_t)b * 2 * a.Z + l];
     a.st_dead[e] = 0;
-    pool_free(a.st_used, e);
+    if (a.decomp)
+      ring_free(a.ctl, a.ring, a.P, e);
+    else
+      pool_free(a.st_used, e);
   }
   if (lane == 0) {
     a.rmask[b] = 0;
@@ -1433,10 +1484,16 @@ __device__ __forceinline__ void finish_apply(const FinishArgs& a, bool ok, uint6
   Ctl* c = a.ctl;
   if (ok) {
     c->steps += a.q;
-    const uint64_t st = c->stash_live + c->b_place - freed;
+    // pool entries in use: the stash proper plus, in a decomposed store,
+    // the HBM bins' items (hbm_live stays 0 otherwise)
+    const uint64_t pool = c->pool_live + c->b_place - freed;
+    c->pool_live = pool;
+    const uint64_t hbm = c->hbm_live + c->b_hbm_in - c->b_hbm_rm;
+    c->hbm_live = hbm;
+    const uint64_t st = pool - hbm;
     c->stash_live = st;
     if (st > c->stash_hw) c->stash_hw = st;
-    if (st > a.stash_bound) c->err |= kErrOverflow;
+    if (st > a.stash_bound || hbm > a.hbm_bound) c->err |= kErrOverflow;
     const uint64_t live = c->live + c->b_ins - c->b_del;
     c->live = live;
     if (live > a.cap) c->err |= kErrFull;
@@ -1444,6 +1501,12 @@ __device__ __forceinline__ void finish_apply(const FinishArgs& a, bool ok, uint6
   c->b_place = 0;
   c->b_ins = 0;
   c->b_del = 0;
+  c->ring_head += c->ring_take;  // the ring: this batch's takes and returns
+  c->ring_tail += c->ring_give;
+  c->ring_take = 0;
+  c->ring_give = 0;
+  c->b_hbm_in = 0;
+  c->b_hbm_rm = 0;
 }
 
 // The batch's counters, by one whole workgroup: the freed buckets summed
@@ -1508,7 +1571,7 @@ __device__ __forceinline__ void solo_warm(const FetchArgs& fa, const PlaceArgs& 
       const uint32_t b = r ? rp.y : rp.x;
       if (lane == 0) acc ^= fa.load[b] ^ fa.rev_cnt[b] ^ fa.claim[b] ^ fa.rmask[b];
       if (lane < 2 * fa.Z) acc ^= fa.rev_idx[(uint64_t)b * 2 * fa.Z + lane];
-      if (b < fa.K)
+      if (b < fa.K && !fa.decomp)
         for (uint64_t w = lane; w < fa.pw; w += 64) acc ^= fa.hbm[(uint64_t)b * fa.pw + w];
     }
   }
@@ -1658,6 +1721,8 @@ static void plan_access(bolt_map* m, const uint8_t* ops, const uint64_t* keys, c
   fa.ov_epoch = m->ov_off ? 0 : epoch - 1;
   m->ov_off = false;
   fa.pre_host = m->obs_host ? 0 : 1;
+  const uint32_t decomp = (m->p.flags & BOLT_F_DECOMPOSED) ? 1 : 0;
+  fa.decomp = decomp;
   fa.ship = ship_args(m, 0, 0);  // run_access hands slices of the previous batch's send to its kernels
   fa.ship_blocks = 0;
   P.gr.ship = fa.ship;
@@ -1727,6 +1792,9 @@ static void plan_access(bolt_map* m, const uint8_t* ops, const uint64_t* keys, c
   pa.pm_mask = m->pm_mask;
   pa.rowsel = bs.rowsel;
   pa.rows = bs.rows;
+  pa.decomp = decomp;
+  pa.ring = m->ring;
+  pa.P = s.P;
 
   RemapArgs& ra = P.ra;
   ra.enabled = !P.fast;
@@ -1764,6 +1832,9 @@ static void plan_access(bolt_map* m, const uint8_t* ops, const uint64_t* keys, c
   ra.pm_pair = m->pm_pair;
   ra.pm_mask = m->pm_mask;
   ra.rows = bs.rows;
+  ra.decomp = decomp;
+  ra.ring = m->ring;
+  ra.P = s.P;
 
   WbArgs& wa = P.wa;
   wa.ctl = m->ctl;
@@ -1795,6 +1866,9 @@ static void plan_access(bolt_map* m, const uint8_t* ops, const uint64_t* keys, c
   wa.obs = reinterpret_cast<uint64_t*>(m->obs);
   wa.tags = reinterpret_cast<uint64_t*>(m->tags);
   wa.pver = m->pver;
+  wa.decomp = decomp;
+  wa.ring = m->ring;
+  wa.P = s.P;
 
 
   FinishArgs& fn = P.fn;
@@ -1806,6 +1880,7 @@ static void plan_access(bolt_map* m, const uint8_t* ops, const uint64_t* keys, c
   fn.epoch = epoch;
   fn.cap = s.cap;
   fn.stash_bound = s.stash_bound;
+  fn.hbm_bound = decomp ? s.hbm_bound : ~0ull;
   fn.rowsel = fast ? bs.rowsel : nullptr;
   fn.keys = keys;
   fn.rpair = bs.rpair;

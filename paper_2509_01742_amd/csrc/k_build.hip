@@ -81,6 +81,17 @@ struct BuildPlan {
   uint64_t* pm_key;
   uint2* pm_pair;
   uint32_t* pm_mask;
+  // BOLT_F_DECOMPOSED: the HBM bins' items go to the value pool, listed
+  // under their bin, and the pool's free-address ring starts after them
+  uint32_t decomp;
+  uint64_t pool, hbm_bound;
+  uint32_t* ring;
+  uint64_t* st_key;
+  uint64_t* st_val;
+  uint32_t* st_dest;
+  uint32_t* st_dead;
+  uint32_t* rev_cnt;
+  uint32_t* rev_idx;
   // scratch
   uint2* pair;      // [n]
   uint32_t* dest;   // [n]
@@ -176,6 +187,14 @@ __global__ void k_ctl_init(Ctl* ctl) {
   ctl->hbm_load = 0;
   ctl->hbm_hw = 0;
   ctl->seq = 0;
+  ctl->ring_head = 0;
+  ctl->ring_tail = 0;
+  ctl->ring_take = 0;
+  ctl->ring_give = 0;
+  ctl->pool_live = 0;
+  ctl->hbm_live = 0;
+  ctl->b_hbm_in = 0;
+  ctl->b_hbm_rm = 0;
 }
 
 void launch_map_init(bolt_map* m, hipStream_t st) {
@@ -359,9 +378,32 @@ __global__ __launch_bounds__(256) void k_writeout(BOLT_PLAN_ARGS, uint32_t flip)
     }
     return v;
   };
-  uint64_t* dst = b < P.K ? P.hbm + b * pw : P.obs + (b - P.K) * pw;
+  // A decomposed store keeps an HBM bin's items as value-pool entries
+  // start[b] + rank (the bins' loads scanned, so HBM bin b's items follow
+  // those of bins 0..b-1), listed under the bin; it has no HBM pages.
+  const bool pooled = P.decomp && b < P.K;  // the same for the whole wave
+  auto pool_write = [&]() {
+    for (uint32_t j = lane; j < cnt; j += 64) {
+      const uint64_t e = (uint64_t)P.start[b] + j;
+      if (e >= P.pool) {  // more items than the pool holds: reported, nothing written
+        set_err(P.ctl, kErrOverflow);
+        continue;
+      }
+      P.st_key[e] = key_rank[wid][j];
+      for (uint32_t o = 0; o < vw; ++o) P.st_val[e * vw + o] = P.vals[(uint64_t)by_rank[wid][j] * vw + o];
+      P.st_dest[e] = (uint32_t)b;
+      P.st_dead[e] = 0;
+      P.rev_idx[b * 2 * Z + j] = (uint32_t)e;
+    }
+    if (lane == 0) P.rev_cnt[b] = cnt;
+  };
+  uint64_t* dst = b < P.K ? (pooled ? nullptr : P.hbm + b * pw) : P.obs + (b - P.K) * pw;
   if (!P.tags) {  // unsealed map (the same for the whole block)
     if (!active) return;
+    if (pooled) {
+      pool_write();
+      return;
+    }
     for (uint64_t w = lane; w < pw; w += 64) dst[w] = word(w);
     if (P.tlog && b >= P.K && lane == 0) P.tlog[b - P.K] = (uint32_t)(b - P.K);
     return;
@@ -374,6 +416,8 @@ __global__ __launch_bounds__(256) void k_writeout(BOLT_PLAN_ARGS, uint32_t flip)
   if (active) {
     if (seal)
       for (uint64_t w = lane; w < pw; w += 64) pg[w] = word(w);
+    else if (pooled)
+      pool_write();
     else
       for (uint64_t w = lane; w < pw; w += 64) dst[w] = word(w);
   }
@@ -499,6 +543,29 @@ __global__ void k_build_finish(BOLT_PLAN_ARGS) {
   P.ctl->steps = 0;
 }
 
+// Decomposed store: the free-address ring holds the pool entries the HBM
+// bins' items left free, in address order (H = items of the HBM bins, the
+// scanned load at bin K; K < B, so start[K] exists).
+template <bool MULTI>
+__global__ void k_ring_init(BOLT_PLAN_ARGS) {
+  BOLT_PLAN;
+  if (!P.decomp) return;
+  const uint64_t H = P.start[P.K];
+  const uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < P.pool) P.ring[j] = H + j < P.pool ? (uint32_t)(H + j) : kNone;
+  if (j == 0) {
+    Ctl* c = P.ctl;
+    c->ring_head = 0;
+    c->ring_tail = H < P.pool ? P.pool - H : 0;
+    c->ring_take = 0;
+    c->ring_give = 0;
+    c->pool_live = H;
+    c->hbm_live = H;
+    c->stash_live = 0;
+    if (H > P.hbm_bound) set_err(c, kErrOverflow);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Host side: plans, one scratch arena per call, and the launch sequence
 // shared by the one-map and the many-map forms.
@@ -550,6 +617,16 @@ static void plan_build(bolt_map* m, const uint64_t* keys, const void* vals, uint
   P.pm_key = m->pm_key;
   P.pm_pair = m->pm_pair;
   P.pm_mask = m->pm_mask;
+  P.decomp = (m->p.flags & BOLT_F_DECOMPOSED) ? 1 : 0;
+  P.pool = s.P;
+  P.hbm_bound = s.hbm_bound;
+  P.ring = m->ring;
+  P.st_key = m->st_key;
+  P.st_val = reinterpret_cast<uint64_t*>(m->st_val);
+  P.st_dest = m->st_dest;
+  P.st_dead = m->st_dead;
+  P.rev_cnt = m->rev_cnt;
+  P.rev_idx = m->rev_idx;
   auto take = [&arena](uint64_t bytes) {
     uint8_t* p = arena;
     arena += align256(bytes);
@@ -673,6 +750,15 @@ static void build_launches(const std::vector<BuildPlan>& plans, const BuildPlan*
       if (P.tags) lds = std::max(lds, 4 * P.pw * 8);
     TimedScope ts(tm, kkWriteout, st);
     hipLaunchKernelGGL(k_writeout<MULTI>, dim3(blocks_for(B, 4), C), dim3(256), lds, st, p1, tab, flip);
+  }
+  {
+    uint64_t pool = 0;  // decomposed stores only
+    for (const BuildPlan& P : plans)
+      if (P.decomp) pool = std::max(pool, P.pool);
+    if (pool) {
+      TimedScope ts(tm, kkBuildMisc, st);
+      BL(k_ring_init, blocks_for(pool, NT), NT);
+    }
   }
   // duplicate keys (the tag buffer is free after the write-out)
   if (n) {

@@ -26,7 +26,8 @@ def host_u64(t):
 class Twin:
     """A GPU map and an oracle map with the same parameters and key."""
 
-    def __init__(self, cap, vs, key=bytes(range(32)), trace=True, observable=0, flags=0, seal=False, **kw):
+    def __init__(self, cap, vs, key=bytes(range(32)), trace=True, observable=0, flags=0, seal=False,
+                 decomposed=False, **kw):
         import paper_2509_01742_amd as B
 
         okw = {}
@@ -37,9 +38,9 @@ class Twin:
         self.p = B.params(cap, vs, key=key, observable=observable, **kw)
         # a sealed twin shares its fixed key with the oracle: a test-only reuse of the page key
         self.p.flags |= (B.BOLT_F_TRACE if trace else 0) | flags | (
-            (B.BOLT_F_SEAL | B.BOLT_F_SEAL_KEY_REUSE) if seal else 0)
+            (B.BOLT_F_SEAL | B.BOLT_F_SEAL_KEY_REUSE) if seal else 0) | (B.BOLT_F_DECOMPOSED if decomposed else 0)
         self.g = B.Map(self.p)
-        self.o = O.OracleMap(cap, vs, key=key, trace=trace, seal=seal, **okw)
+        self.o = O.OracleMap(cap, vs, key=key, trace=trace, seal=seal, decomposed=decomposed, **okw)
         self.seal = seal
         self.vs = vs
         self.B = B

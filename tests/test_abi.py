@@ -39,9 +39,16 @@ def test_sizes_agree_with_oracle(cap, vs, kw):
     s = B.sizes_of(p)
     o = O.sizing(cap, vs, c=p.c, alpha_pm=p.alpha_permille, bin_slots=p.bin_slots, d=p.pm_choices,
                  kpr=p.pm_keys_per_row, W=p.pm_row_slots)
-    assert (s["B"], s["K"], s["M"], s["Z"], s["page_bytes"], s["pm_rows"], s["stash_bound"], s["lmax"]) == (
-        o["B"], o["K"], o["M"], o["Z"], o["page_bytes"], o["R_pm"], o["stash_bound"], o["lmax"])
+    assert (s["B"], s["K"], s["M"], s["Z"], s["page_bytes"], s["pm_rows"], s["stash_bound"], s["lmax"],
+            s["hbm_bound"]) == (o["B"], o["K"], o["M"], o["Z"], o["page_bytes"], o["R_pm"], o["stash_bound"],
+                                o["lmax"], o["hbm_bound"])
     assert s["stash_pool"] == s["stash_bound"] + B.BOLT_MAX_BATCH
+    pd = B.params(cap, vs, **kw)
+    pd.flags |= B.BOLT_F_DECOMPOSED  # the pool also holds the HBM bins' items; no HBM pages
+    sd = B.sizes_of(pd)
+    assert sd["stash_pool"] == s["stash_bound"] + B.BOLT_MAX_BATCH + s["hbm_bound"]
+    if s["K"] and vs >= 32:  # a pool entry costs key + value + 12 bytes, a page slot key + value
+        assert B.footprint(pd)[0] < B.footprint(p)[0]
 
 
 @pytest.mark.parametrize("kw", [dict(capacity=1), dict(value_bytes=12), dict(value_bytes=0),
