@@ -86,7 +86,7 @@ def kernel_bytes(cls, sz, n, npad, n_ops, host_roles, send_share=0.0):
     return None, None
 
 
-def run_mode(args, wl, dev_t, B, torch, observable, seal=False):
+def run_mode(args, wl, dev_t, B, torch, observable, seal=False, decomposed=False):
     n, vs = wl.n, wl.vs
     d_keys, d_vals, d_ops, d_qk, d_qv, d_out, d_st, bounds = dev_t
     obs = B.BOLT_OBS_HOST_PINNED if observable == "host" else B.BOLT_OBS_DEVICE
@@ -95,6 +95,8 @@ def run_mode(args, wl, dev_t, B, torch, observable, seal=False):
         p.flags |= B.BOLT_F_GRAPHS
     if seal:
         p.flags |= B.BOLT_F_SEAL
+    if decomposed:
+        p.flags |= B.BOLT_F_DECOMPOSED
     sz = B.sizes_of(p)
     sz["vs"] = vs
     sz["host"] = observable == "host"
@@ -103,7 +105,7 @@ def run_mode(args, wl, dev_t, B, torch, observable, seal=False):
     t0 = time.time()
     maps = [B.Map(p) for _ in range(nsteps)]
     pt = B.params(wl.cap, vs, observable=obs)
-    pt.flags |= B.BOLT_F_TIMING | (B.BOLT_F_SEAL if seal else 0)
+    pt.flags |= B.BOLT_F_TIMING | (B.BOLT_F_SEAL if seal else 0) | (B.BOLT_F_DECOMPOSED if decomposed else 0)
     tmap = B.Map(pt)
     torch.cuda.synchronize()
     log("[%s] created %d maps (%.1fs); footprint hbm=%.2f GiB obs=%.2f GiB" % (
@@ -279,7 +281,9 @@ def main():
                     help="instead of the benchmark: the bound validation of Sec. 4.3 over this many accesses per "
                          "configuration (the paper uses 10^9)")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving figures")
-    ap.add_argument("--serve-seconds", type=float, default=3.0, help="steady window of each open-loop serving run")
+    ap.add_argument("--serve-seconds", type=float, default=60.0,
+                    help="steady window of each open-loop serving run (config 5: 60 s)")
+    ap.add_argument("--no-decomposed", action="store_true", help="skip the decomposed-HBM-store figures")
     ap.add_argument("--copy-calib", type=int, default=0,
                     help="MiB of a plain device copy run first (scales profiler byte counters)")
     args = ap.parse_args()
@@ -356,9 +360,24 @@ def main():
                   "kernels": {c: sres["kernels"][c] for c in ("acc_fetch", "acc_compose", "acc_ship", "page_writeout")
                               if c in sres["kernels"]}}
         log("sealed: %s" % json.dumps({k: v for k, v in sealed.items() if k != "kernels"}))
+    decomp = None
+    if not args.no_decomposed:  # the decomposed HBM store (Sec. 5.2) on the same workload
+        dres = run_mode(args, wl, dev_t, B, torch, args.observable, decomposed=True)
+        pp = B.params(wl.cap, wl.vs)
+        pd = B.params(wl.cap, wl.vs)
+        pd.flags |= B.BOLT_F_DECOMPOSED
+        decomp = {"observable": args.observable, "ops_per_s": round(dres["ops_per_s"], 1),
+                  "build_keys_per_s": round(dres["build_keys_per_s"], 1),
+                  "batch_latency_ms": {"p50": round(dres["lat_p50"], 4), "p99": round(dres["lat_p99"], 4)},
+                  "relative_to_pages": {"ops": round(dres["ops_per_s"] / main_res["ops_per_s"], 4),
+                                        "build": round(dres["build_keys_per_s"] / main_res["build_keys_per_s"], 4)},
+                  "hbm_bytes": {"pages": B.footprint(pp)[0], "decomposed": B.footprint(pd)[0]},
+                  "config5_admitted_under_budget": serving_admission(B)}
+        log("decomposed: %s" % json.dumps(decomp))
     serving = None
     if not args.no_serving:
         serving = run_serving(B, seconds=args.serve_seconds)
+        serving["sealed_commands"] = run_serving_sealed(B)
     multi = None
     if not args.no_multi:
         multi = run_multi(B, torch)
@@ -400,6 +419,7 @@ def main():
         "other_observable_mode": other,
         "autotune": tuned,
         "sealed": sealed,
+        "decomposed": decomp,
         "multi_map": multi,
         "build_heavy": heavy,
         "alpha_sweep": sweep,
@@ -574,13 +594,19 @@ def run_multi(B, torch, reps=3):
         torch.cuda.synchronize()
         tb_one.append(time.perf_counter() - t)
         for _ in range(3):
+            # both forms include the write of every rebuilt page (a deferred
+            # send is flushed inside the timed region)
             t = time.perf_counter()
             B.check(B.access_many(ms, bts), "bolt_access_many")
+            for m in ms:
+                B.check(m.flush(), "bolt_flush")
             torch.cuda.synchronize()
             ta_many.append(time.perf_counter() - t)
             t = time.perf_counter()
             for m, b in zip(ones, bts):
                 B.check(m.access(*b), "bolt_access_batch")
+            for m in ones:
+                B.check(m.flush(), "bolt_flush")
             torch.cuda.synchronize()
             ta_one.append(time.perf_counter() - t)
         for m in ms + ones:
@@ -600,7 +626,100 @@ def run_multi(B, torch, reps=3):
                    "access_many": round(1e3 * med(ta_many), 3), "access_per_call": round(1e3 * med(ta_one), 3)}}
 
 
-def run_serving(B, seconds=3.0, rot_seconds=2.0, warm=1.0, pool=1 << 16, seed=0xB0170000 + 55):
+def serving_admission(B):
+    """How many of config 5's sixteen maps (in open order) the serving budget
+    admits at once, with pages in HBM bins and with the decomposed store.
+    The budget is the one run_serving uses: the first twelve maps' page
+    footprints."""
+    import synth
+
+    ns = [n for n, _, _, _ in synth.config5_maps()]
+
+    def fp(n, dec):
+        p = B.params(n, 64)
+        if dec:
+            p.flags |= B.BOLT_F_DECOMPOSED
+        return B.server_footprint(p)
+
+    budget = sum(fp(n, False) for n in ns[:12])
+    out = {"budget_bytes": budget}
+    for dec in (False, True):
+        used, k = 0, 0
+        for n in ns:
+            if used + fp(n, dec) > budget:
+                break
+            used += fp(n, dec)
+            k += 1
+        out["decomposed" if dec else "pages"] = {"maps_admitted": k,
+                                                  "bytes_all_16": int(sum(fp(n, dec) for n in ns))}
+    return out
+
+
+def run_serving_sealed(B, n_req=4000, seed=0xB0170000 + 56):
+    """Sealed commands on the serving path: the sixteen config-5 maps (all
+    resident) created with a session key, a backlog of n_req requests
+    sealed beforehand by the client helper (a map's k-th request sealed as
+    request k), drained as fast as the loop goes; against the same backlog
+    in plain commands on plain maps."""
+    import synth
+
+    rng = np.random.Generator(np.random.PCG64(seed))
+    skey = bytes((5 * i + 1) & 255 for i in range(32))
+    specs = synth.config5_maps()
+    vs = 64
+    reqs = []
+    for _ in range(n_req):
+        j = int(rng.integers(0, len(specs)))
+        q = int(min(4096, max(1, int(2 ** (12 * rng.random())))))
+        n, k = specs[j][0], specs[j][1]
+        keys = k[rng.integers(0, n, q)]
+        ops = np.where(rng.random(q) < 0.1, 1, 0).astype(np.uint8)
+        reqs.append((j, ops, keys, rng.integers(0, 256, (q, vs), dtype=np.uint8)))
+    out = {"workload": "16 config-5 maps resident; a backlog of %d requests (sizes floor(2^(12u)), 90/10, uniform "
+                       "present keys)" % n_req}
+    one_ops, one_vals = np.zeros(1, np.uint8), np.zeros((1, vs), np.uint8)
+    for mode in ("plain", "sealed"):
+        sealed = mode == "sealed"
+        srv = B.Server(streams=4)
+        ids = [srv.open_map(B.params(n, vs, **({"session_key": skey} if sealed else {})), k, v)
+               for n, k, v, _ in specs]
+        # one request per map first: every map is resident before the clock starts
+        for j in range(len(specs)):
+            if sealed:
+                srv.submit_sealed(ids[j], B.seal_requests(skey, 1, one_ops, specs[j][1][:1], one_vals, vs), vs)
+            else:
+                srv.submit(ids[j], one_ops, specs[j][1][:1], one_vals)
+        B.check(srv.drain(300000), "drain")
+        recs = None
+        if sealed:  # the client seals the backlog as requests 2, 3, ... of each map
+            seq = [1] * len(specs)
+            t = time.perf_counter()
+            recs = []
+            for j, ops, keys, vals in reqs:
+                seq[j] += 1
+                recs.append(B.seal_requests(skey, seq[j], ops, keys, vals, vs))
+            out["client_seal_s"] = round(time.perf_counter() - t, 2)
+        srv.reset_stats()
+        now = B.bolt_now_ns()
+        for r, (j, ops, keys, vals) in enumerate(reqs):
+            if sealed:
+                srv.submit_sealed(ids[j], recs[r], vs, arrival_ns=now)
+            else:
+                srv.submit(ids[j], ops, keys, vals, arrival_ns=now)
+        B.check(srv.drain(300000), "drain")
+        st = srv.stats()
+        if st["failed"] or st["completed"] != n_req:
+            raise SystemExit("sealed serving: %d of %d requests failed" % (st["failed"], n_req))
+        out[mode] = {"req_per_s": round(st["completed"] / st["span_s"], 1),
+                     "ops_per_s": round(st["commands"] / st["span_s"], 1),
+                     "mean_group_maps": round(st["mean_group_maps"], 2)}
+        srv.close()
+    out["sealed_relative_to_plain"] = round(out["sealed"]["ops_per_s"] / out["plain"]["ops_per_s"], 4)
+    log("serving, sealed commands: %s" % json.dumps(out))
+    return out
+
+
+def run_serving(B, seconds=60.0, rot_seconds=2.0, warm=1.0, pool=1 << 16, seed=0xB0170000 + 55):
     """Sixteen maps (N log-uniform in 2^16..2^24, 64-byte values) behind the
     serving loop.  The HBM budget holds twelve of them at a time: each run
     serves twelve maps for its first half, then closes four and lets four
@@ -724,10 +843,14 @@ def run_serving(B, seconds=3.0, rot_seconds=2.0, warm=1.0, pool=1 << 16, seed=0x
                     "mean_group_commands": round(st["mean_group_commands"], 1),
                     "maps_admitted": st["maps_admitted"], "hbm_peak_bytes": st["hbm_peak"]}
 
+        next_note = start + int(10e9)
         while True:
             t += int(rng.exponential(1.0 / rate) * 1e9)
             if t >= t_end:
                 break
+            if t >= next_note:  # a progress line every ten seconds of the run
+                log("serving at %.1fx: %.0f s of %.0f s" % (frac, (t - start) / 1e9, (t_end - start) / 1e9))
+                next_note += int(10e9)
             if phase == 0 and t >= t_warm:
                 while B.bolt_now_ns() < t_warm:
                     pass

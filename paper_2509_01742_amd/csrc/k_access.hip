@@ -947,11 +947,14 @@ __global__ __launch_bounds__(256) void k_acc_fetch(FetchArgs a1, const AccessPla
   BOLT_PICK(FetchArgs, fa);
   extern __shared__ uint64_t fdyn[];
   uint64_t* const pg = fdyn + (uint64_t)(threadIdx.x >> 6) * a.pw;
-  if (!MULTI && blockIdx.x < a.ship_blocks) {  // the previous batch's send
-    ship_slots<SEALED>(a.ship, blockIdx.x * 4 + (threadIdx.x >> 6), a.ship_blocks * 4, pg);
+  if (blockIdx.x < a.ship_blocks) {  // the previous batch's send (in a many-map launch, this map's)
+    if (SEALED && a.ship.tags)
+      ship_slots<true>(a.ship, blockIdx.x * 4 + (threadIdx.x >> 6), a.ship_blocks * 4, pg);
+    else
+      ship_slots<false>(a.ship, blockIdx.x * 4 + (threadIdx.x >> 6), a.ship_blocks * 4, nullptr);
     return;
   }
-  const uint32_t i = (blockIdx.x - (MULTI ? 0 : a.ship_blocks)) * 4 + (threadIdx.x >> 6);
+  const uint32_t i = (blockIdx.x - a.ship_blocks) * 4 + (threadIdx.x >> 6);
   if (i < a.q) fetch_cmd<SEALED>(a, i, pg);
 }
 
@@ -1931,14 +1934,16 @@ __global__ __launch_bounds__(1024) void k_acc_watch(const uint32_t* __restrict__
 static void allow_group_lds();
 
 static void launch_many(const AccessPlan& p0, const AccessPlan* tab, uint32_t C, uint32_t qmax, uint64_t lds,
-                        uint64_t fetch_lds, bool any_fast, bool any_slow, hipStream_t st) {
+                        uint64_t fetch_lds, bool any_fast, bool any_slow, hipStream_t st, uint32_t ship_max = 0) {
   allow_group_lds();
   hipLaunchKernelGGL(k_acc_group<true>, dim3(kParts + group_prf_blocks(qmax), C), dim3(kDedupNT),
                      group_lds_bytes(qmax), st, p0.gr, tab);
+  // each map's first ship_blocks workgroups of the fetch send its previous batch's pages
+  const dim3 fgrid(ship_max + (qmax + 3) / 4, C);
   if (fetch_lds)  // a sealed map among them
-    hipLaunchKernelGGL((k_acc_fetch<true, true>), dim3((qmax + 3) / 4, C), dim3(256), fetch_lds, st, p0.fa, tab);
+    hipLaunchKernelGGL((k_acc_fetch<true, true>), fgrid, dim3(256), fetch_lds, st, p0.fa, tab);
   else
-    hipLaunchKernelGGL((k_acc_fetch<true, false>), dim3((qmax + 3) / 4, C), dim3(256), 0, st, p0.fa, tab);
+    hipLaunchKernelGGL((k_acc_fetch<true, false>), fgrid, dim3(256), 0, st, p0.fa, tab);
   hipLaunchKernelGGL(k_acc_resolve<true>, dim3((qmax + 63) / 64, C), dim3(64), 0, st, p0.rv, tab);
   if (any_fast) hipLaunchKernelGGL(k_acc_place<true>, dim3((qmax + 63) / 64, C), dim3(64), 0, st, p0.pa, tab);
   if (any_slow) hipLaunchKernelGGL(k_acc_remap<true>, dim3(1, C), dim3(kRemapNT), 0, st, p0.ra, tab);
@@ -2140,13 +2145,28 @@ int run_access(bolt_map* m, const uint8_t* ops, const uint64_t* keys, const void
 // all of them (map = blockIdx.y).  The plans go to the device in one copy.
 int run_access_many(bolt_map* const* maps, const bolt_batch* batches, uint32_t count, hipStream_t st) {
   std::vector<AccessPlan> plans(count);
-  uint32_t qmax = 0;
+  uint32_t qmax = 0, ship_max = 0;
   uint64_t lds = 0, flds = 0;
   bool any_fast = false, any_slow = false;
+  std::vector<uint8_t> defer(count, 0);
   for (uint32_t i = 0; i < count; ++i) {
     const bolt_batch& b = batches[i];
-    if (flush_ship(maps[i], st)) return BOLT_EHIP;
-    plan_access(maps[i], b.d_ops, b.d_keys, b.d_vals_in, b.d_vals_out, b.d_status, b.q, st, plans[i]);
+    bolt_map* m = maps[i];
+    // The map's previous batch's pages still to be sent go out from this
+    // launch's fetch, beside its reads (as in one-map batches).
+    ShipArgs pending = ship_args(m, m->ship_from, 2 * m->ship_q);
+    const bool has_pending = m->ship_q && m->ship_from < 2 * m->ship_q;
+    m->ship_q = 0;
+    m->ship_from = 0;
+    plan_access(m, b.d_ops, b.d_keys, b.d_vals_in, b.d_vals_out, b.d_status, b.q, st, plans[i]);
+    if (has_pending) {
+      plans[i].fa.ship = pending;
+      plans[i].fa.ship_blocks = ship_blocks_for(pending.hi - pending.lo);
+      ship_max = plans[i].fa.ship_blocks > ship_max ? plans[i].fa.ship_blocks : ship_max;
+    }
+    // a large batch on a pinned store rebuilds its pages into its outbox half
+    defer[i] = m->obs_host && b.q >= kDeferMinBatch;
+    plans[i].wa.direct = defer[i] ? 0 : 1;
     qmax = b.q > qmax ? b.q : qmax;
     lds = plans[i].wb_lds > lds ? plans[i].wb_lds : lds;
     flds = plans[i].fetch_lds > flds ? plans[i].fetch_lds : flds;
@@ -2160,7 +2180,12 @@ int run_access_many(bolt_map* const* maps, const bolt_batch* batches, uint32_t c
     (void)hipFreeAsync(tab, st);
     return BOLT_EHIP;
   }
-  launch_many(plans[0], tab, count, qmax, lds, flds, any_fast, any_slow, st);
+  launch_many(plans[0], tab, count, qmax, lds, flds, any_fast, any_slow, st, ship_max);
+  for (uint32_t i = 0; i < count; ++i) {
+    maps[i]->ship_q = defer[i] ? batches[i].q : 0;
+    maps[i]->ship_from = 0;
+    maps[i]->ship_half = plans[i].fa.epoch & 1;  // the half this batch rebuilt its pages into
+  }
   for (uint32_t i = 0; i < count; ++i)
     if (maps[i]->p.flags & BOLT_F_WATCH)
       hipLaunchKernelGGL(k_acc_watch, dim3(1), dim3(1024), 0, st, maps[i]->load, maps[i]->s.B, maps[i]->s.K,
