@@ -232,7 +232,11 @@ int bolt_flush(bolt_map* m, void* hip_stream);
 int bolt_destroy(bolt_map* m);
 
 /* Synchronises the map's last stream and returns BOLT_OK or the sticky
- * device-side error (BOLT_EOVERFLOW before BOLT_EDUPKEY before BOLT_EFULL). */
+ * device-side error (BOLT_ETAMPER before BOLT_EOVERFLOW before BOLT_EDUPKEY
+ * before BOLT_EFULL).  Overflow is the event Sec. 4.3 bounds (a bin above
+ * its capacity, the stash above the Claim 4.4 bound, a position-map row
+ * full): the paper accepts it as rare data loss; here it is never silent
+ * and poisons the map. */
 int bolt_status(bolt_map* m);
 
 /* Derived sizes of an existing map. */
@@ -271,14 +275,22 @@ typedef struct {
 } bolt_trace_rec;
 
 /* Copies up to cap records of the trace recorded since create (or the last
- * clear) into host_recs; *n receives the total count.  Returns BOLT_EINVAL if
- * the map was created without BOLT_F_TRACE, BOLT_EFULL if the log filled up
- * and records were lost. */
+ * clear) into host_recs; *n receives the total count.  The trace is what an
+ * adversary watching the observable store sees (Def. 3.1; the simulator of
+ * Claim 4.1): one record per page read or written, in the canonical order
+ * of each batch (reads by command and role, then the writes by ascending
+ * page; the build writes pages 0..M-1).  Returns BOLT_EINVAL if the map was
+ * created without BOLT_F_TRACE, BOLT_EFULL if the log filled up and records
+ * were lost. */
 int bolt_trace_read(bolt_map* m, bolt_trace_rec* host_recs, uint64_t cap, uint64_t* n);
 int bolt_trace_clear(bolt_map* m);
 
-/* Raw state: the M observable pages, the K HBM bins, the B bin loads (u32).
- * cap is the size of the host buffer in bytes; it must hold the whole array. */
+/* Raw state, for tests: the M observable pages (the untrusted host memory
+ * of Sec. 3, after any pending page writes reach it), the K HBM bins (zeros
+ * for a decomposed store, which has no HBM pages), the B bin loads (u32;
+ * load(b) counts the bin's items and the stash items bound for it, the
+ * quantity P2C compares, Sec. 4.1).  cap is the size of the host buffer in
+ * bytes; it must hold the whole array. */
 int bolt_observable_snapshot(bolt_map* m, void* host_buf, uint64_t cap);
 int bolt_hbm_snapshot(bolt_map* m, void* host_buf, uint64_t cap);
 int bolt_loads_snapshot(bolt_map* m, uint32_t* host_buf, uint64_t cap);

@@ -407,6 +407,13 @@ int bolt_access_batch(bolt_map* m, const uint8_t* d_ops, const uint64_t* d_keys,
 }
 
 int bolt_access_many(bolt_map* const* maps, const bolt_batch* batches, uint32_t count, void* hip_stream) {
+  return access_many(maps, batches, count, hip_stream, false);
+}
+
+}  // extern "C"
+
+int bolt::access_many(bolt_map* const* maps, const bolt_batch* batches, uint32_t count, void* hip_stream,
+                      bool defer_pages) {
   if (count == 0) return BOLT_OK;
   if (!maps || !batches) return BOLT_EINVAL;
   std::vector<bolt_map*> live;
@@ -435,8 +442,10 @@ int bolt_access_many(bolt_map* const* maps, const bolt_batch* batches, uint32_t 
   if (live.size() == 1)
     return run_access(live[0], work[0].d_ops, work[0].d_keys, work[0].d_vals_in, work[0].d_vals_out,
                       work[0].d_status, work[0].q, st);
-  return run_access_many(live.data(), work.data(), (uint32_t)live.size(), st);
+  return run_access_many(live.data(), work.data(), (uint32_t)live.size(), st, defer_pages);
 }
+
+extern "C" {
 
 int bolt_access_sealed(bolt_map* m, const void* d_req, uint32_t q, void* d_resp, void* hip_stream) {
   int rc = map_check(m);

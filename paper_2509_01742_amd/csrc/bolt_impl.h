@@ -195,7 +195,15 @@ int run_build_many(bolt_map* const* maps, const uint64_t* const* keys, const voi
                    uint32_t count, hipStream_t st);
 int run_access(bolt_map* m, const uint8_t* ops, const uint64_t* keys, const void* vals_in, void* vals_out,
                uint8_t* status, uint32_t q, hipStream_t st);
-int run_access_many(bolt_map* const* maps, const bolt_batch* batches, uint32_t count, hipStream_t st);
+// defer_pages: large batches on pinned stores rebuild their pages into the
+// outbox, sent by each map's next batch (or a flush); else the rebuild
+// writes them.  The pages pending from each map's previous batch always go
+// out from this launch's fetch.
+int run_access_many(bolt_map* const* maps, const bolt_batch* batches, uint32_t count, hipStream_t st,
+                    bool defer_pages);
+// bolt_access_many's checks and dispatch, with the page-send choice above.
+int access_many(bolt_map* const* maps, const bolt_batch* batches, uint32_t count, void* hip_stream,
+                bool defer_pages);
 // Sends the rebuilt pages of the map's last batch to the store, if any.
 int flush_ship(bolt_map* m, hipStream_t st);
 // Sealed requests (k_record.hip): commands t of a call (requests starting

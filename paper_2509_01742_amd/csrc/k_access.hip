@@ -2143,7 +2143,8 @@ int run_access(bolt_map* m, const uint8_t* ops, const uint64_t* keys, const void
 
 // One batch for each of `count` distinct maps, every phase one launch for
 // all of them (map = blockIdx.y).  The plans go to the device in one copy.
-int run_access_many(bolt_map* const* maps, const bolt_batch* batches, uint32_t count, hipStream_t st) {
+int run_access_many(bolt_map* const* maps, const bolt_batch* batches, uint32_t count, hipStream_t st,
+                    bool defer_pages) {
   std::vector<AccessPlan> plans(count);
   uint32_t qmax = 0, ship_max = 0;
   uint64_t lds = 0, flds = 0;
@@ -2164,8 +2165,9 @@ int run_access_many(bolt_map* const* maps, const bolt_batch* batches, uint32_t c
       plans[i].fa.ship_blocks = ship_blocks_for(pending.hi - pending.lo);
       ship_max = plans[i].fa.ship_blocks > ship_max ? plans[i].fa.ship_blocks : ship_max;
     }
-    // a large batch on a pinned store rebuilds its pages into its outbox half
-    defer[i] = m->obs_host && b.q >= kDeferMinBatch;
+    // a large batch on a pinned store rebuilds its pages into its outbox half,
+    // when the caller runs more batches of these maps soon (serving)
+    defer[i] = defer_pages && m->obs_host && b.q >= kDeferMinBatch;
     plans[i].wa.direct = defer[i] ? 0 : 1;
     qmax = b.q > qmax ? b.q : qmax;
     lds = plans[i].wb_lds > lds ? plans[i].wb_lds : lds;

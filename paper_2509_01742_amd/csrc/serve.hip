@@ -467,7 +467,8 @@ bool launch(bolt_server* s) {
                             d + sm->dev.off_vout, d + sm->dev.off_st, pt.q});
     sm->busy = true;
   }
-  if (rc == BOLT_OK) rc = bolt_access_many(ms.data(), bs.data(), (uint32_t)ms.size(), st);
+  // a map's next group sends the pages this one rebuilds (beside its reads)
+  if (rc == BOLT_OK) rc = access_many(ms.data(), bs.data(), (uint32_t)ms.size(), st, true);
   if (rc == BOLT_OK) {
     for (Part& pt : gr->parts) {
       SMap* sm = pt.map;
