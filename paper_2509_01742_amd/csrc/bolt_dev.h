@@ -213,9 +213,9 @@ __device__ __forceinline__ void pool_free(uint64_t* used, uint32_t e) {
 }
 
 // The free-address ring of a decomposed store (Sec. 5.2, "Dynamic HBM
-// management"): entries are taken at the head and returned at the tail.
-// The active lanes of a wave that call these together share one atomic.
-// ring_alloc returns kNone when the ring has no free entry left.
+// management"): entries are taken at the head (the active lanes of a wave
+// that call this together share one atomic) and returned at the tail by
+// the batch's finish.  ring_alloc returns kNone when no free entry is left.
 __device__ __forceinline__ uint32_t ring_alloc(Ctl* ctl, const uint32_t* ring, uint64_t P) {
   const uint64_t act = __ballot(1);
   const uint32_t lane = threadIdx.x & 63;
@@ -228,15 +228,6 @@ __device__ __forceinline__ uint32_t ring_alloc(Ctl* ctl, const uint32_t* ring, u
   return ring[pos % P];
 }
 
-__device__ __forceinline__ void ring_free(Ctl* ctl, uint32_t* ring, uint64_t P, uint32_t e) {
-  const uint64_t act = __ballot(1);
-  const uint32_t lane = threadIdx.x & 63;
-  const uint32_t first = (uint32_t)__builtin_ctzll(act);
-  uint32_t base = 0;
-  if (lane == first) base = atomicAdd(&ctl->ring_give, (uint32_t)__popcll(act));
-  base = (uint32_t)__shfl((int)base, (int)first, 64);
-  ring[(ctl->ring_tail + base + __popcll(act & ((1ull << lane) - 1))) % P] = e;
-}
 
 __device__ __forceinline__ uint64_t alloc_hash(uint32_t epoch, uint32_t i) {
   uint64_t x = ((uint64_t)epoch << 32) ^ (uint64_t)(i + 1) * 0x9E3779B97F4A7C15ull;

@@ -33,6 +33,8 @@ struct BatchScratch {
   uint32_t* freed;    // [256] stash entries freed this batch, in buckets
   uint2* fpair;       // [Q] fetch pair F(s) of each command
   uint4* rows;        // [Q] position-map rows of each command's key
+  uint32_t* rfree;    // BOLT_F_DECOMPOSED: [3Q][2Z] pool entries each rebuild slot returns to the ring
+  uint32_t* rfree_n;  // BOLT_F_DECOMPOSED: [3Q] how many
 };
 
 struct TraceSeg {

@@ -229,9 +229,9 @@ struct WbArgs {
   uint64_t* pver;       // direct, BOLT_F_SEAL: [M] page write counts
   ShipArgs ship;  // a slice of the previous batch's send, by the first ship_blocks workgroups
   uint32_t ship_blocks;
-  uint32_t decomp;  // BOLT_F_DECOMPOSED: HBM bins keep their items listed; frees go to the ring
-  uint32_t* ring;
-  uint64_t P;
+  uint32_t decomp;  // BOLT_F_DECOMPOSED: HBM bins keep their items listed; frees are staged for the ring
+  uint32_t* rfree;    // [3Q][2Z] entries each rebuild slot returns to the ring
+  uint32_t* rfree_n;  // [3Q] how many
 };
 
 
@@ -248,6 +248,12 @@ struct FinishArgs {
   uint32_t* pm_mask;
   ShipArgs ship;  // a slice of the previous batch's send, by the first ship_blocks workgroups
   uint32_t ship_blocks;
+  uint32_t decomp;          // BOLT_F_DECOMPOSED: the finish appends the staged frees to the ring
+  uint32_t Z2;              // 2Z, the stride of rfree
+  uint32_t* ring;
+  uint64_t P;
+  const uint32_t* rfree;    // [3Q][2Z]
+  const uint32_t* rfree_n;  // [3Q]
 };
 
 // Every kernel argument of one map's batch.  A multi-map launch reads the
@@ -1300,6 +1306,7 @@ __device__ __forceinline__ void compose_slot(const WbArgs& a, uint32_t s, uint64
   uint32_t* by_rank = isrc + kWbItems;
   const uint32_t lane = threadIdx.x & 63;
   if (lane == 0 && s < 2 * a.q) a.ship_page[s] = kNone;
+  if (lane == 0 && s < 3 * a.q && a.decomp) a.rfree_n[s] = 0;  // this slot returns nothing unless it rebuilds
   if (s >= 3 * a.q || a.ctl->reject == a.epoch || a.ctl->err) return;  // whole wave
   const uint32_t b = a.cand_bin[s];
   if (b == kNone) return;  // whole wave
@@ -1362,20 +1369,21 @@ __device__ __forceinline__ void compose_slot(const WbArgs& a, uint32_t s, uint64
     for (uint32_t base = 0; base < cnt; base += 64) {
       const uint32_t l = base + lane;
       bool dead = false;
+      uint32_t e = kNone;
       if (l < cnt) {
-        const uint32_t e = base == 0 ? e_spec : a.rev_idx[(uint64_t)b * 2 * a.Z + l];
+        e = base == 0 ? e_spec : a.rev_idx[(uint64_t)b * 2 * a.Z + l];
         dead = a.st_dead[e] != 0;
-        if (dead) {
-          a.st_dead[e] = 0;
-          ring_free(a.ctl, a.ring, a.P, e);
-        }
+        if (dead) a.st_dead[e] = 0;
       }
-      ndead += __popcll(__ballot(dead));
+      const uint64_t bal = __ballot(dead);
+      if (dead) a.rfree[(uint64_t)s * 2 * a.Z + ndead + __popcll(bal & ((1ull << lane) - 1))] = e;
+      ndead += __popcll(bal);
     }
     if (lane < n_alive) a.rev_idx[(uint64_t)b * 2 * a.Z + lane] = isrc[lane] & 0x7FFFFFFFu;
     if (lane == 0) {
       a.rmask[b] = 0;
       a.rev_cnt[b] = n_alive;
+      a.rfree_n[s] = ndead;
       if (ndead) atomicAdd(&a.freed[s % kFreeBuckets], ndead);
     }
     return;
@@ -1430,11 +1438,12 @@ __device__ __forceinline__ void compose_slot(const WbArgs& a, uint32_t s, uint64
     const uint32_t e = l < 64 ? e_spec : a.rev_idx[(uint64_t)b * 2 * a.Z + l];
     a.st_dead[e] = 0;
     if (a.decomp)
-      ring_free(a.ctl, a.ring, a.P, e);
+      a.rfree[(uint64_t)s * 2 * a.Z + l] = e;  // staged; the finish returns it to the ring
     else
       pool_free(a.st_used, e);
   }
   if (lane == 0) {
+    if (a.decomp) a.rfree_n[s] = cnt;
     a.rmask[b] = 0;
     a.rev_cnt[b] = 0;
     if (cnt) atomicAdd(&a.freed[s % kFreeBuckets], cnt);
@@ -1516,6 +1525,22 @@ __device__ __forceinline__ void finish_apply(const FinishArgs& a, bool ok, uint6
 // and cleared; part is kFreeBuckets words of LDS.  Every batch leaves the
 // buckets at zero.
 __device__ __forceinline__ void finish_counters(const FinishArgs& a, bool ok, uint32_t* part) {
+  if (a.decomp) {  // (the plan's flag: the same for the whole workgroup)
+    // the entries the rebuild slots staged go to the ring's tail, in slot
+    // order (one workgroup of 256 threads: a scan of the slots' counts)
+    const uint32_t n3 = 3 * a.q, per = (n3 + 255) / 256, s0 = threadIdx.x * per;
+    uint32_t mine = 0;
+    for (uint32_t s = s0; s < s0 + per && s < n3; ++s) mine += a.rfree_n[s];
+    __shared__ uint32_t tot;
+    uint32_t off = block_excl<256, false>(mine, &tot);
+    const uint64_t tail = a.ctl->ring_tail;
+    for (uint32_t s = s0; s < s0 + per && s < n3; ++s) {
+      const uint32_t n = a.rfree_n[s];
+      for (uint32_t j = 0; j < n; ++j) a.ring[(tail + off + j) % a.P] = a.rfree[(uint64_t)s * a.Z2 + j];
+      off += n;
+    }
+    if (threadIdx.x == 0) a.ctl->ring_give = tot;
+  }
   for (uint32_t t = threadIdx.x; t < kFreeBuckets; t += blockDim.x) {
     part[t] = a.freed[t];
     a.freed[t] = 0;  // ready for the next batch
@@ -1615,6 +1640,13 @@ __global__ __launch_bounds__(kSoloNT) void k_acc_solo(GroupArgs gr, FetchArgs fa
     fn.freed[0] = 0;
     fn.freed[1] = 0;
     fn.freed[2] = 0;
+    if (fn.decomp) {  // the three slots' staged frees go to the ring
+      uint32_t give = 0;
+      for (uint32_t s = 0; s < 3; ++s)
+        for (uint32_t j = 0; j < fn.rfree_n[s]; ++j)
+          fn.ring[(fn.ctl->ring_tail + give++) % fn.P] = fn.rfree[(uint64_t)s * fn.Z2 + j];
+      fn.ctl->ring_give = give;
+    }
     finish_apply(fn, ok, freed);
   }
 }
@@ -1870,8 +1902,8 @@ static void plan_access(bolt_map* m, const uint8_t* ops, const uint64_t* keys, c
   wa.tags = reinterpret_cast<uint64_t*>(m->tags);
   wa.pver = m->pver;
   wa.decomp = decomp;
-  wa.ring = m->ring;
-  wa.P = s.P;
+  wa.rfree = bs.rfree;
+  wa.rfree_n = bs.rfree_n;
 
 
   FinishArgs& fn = P.fn;
@@ -1884,6 +1916,12 @@ static void plan_access(bolt_map* m, const uint8_t* ops, const uint64_t* keys, c
   fn.cap = s.cap;
   fn.stash_bound = s.stash_bound;
   fn.hbm_bound = decomp ? s.hbm_bound : ~0ull;
+  fn.decomp = decomp;
+  fn.Z2 = (uint32_t)(2 * s.Z);
+  fn.ring = m->ring;
+  fn.P = s.P;
+  fn.rfree = bs.rfree;
+  fn.rfree_n = bs.rfree_n;
   fn.rowsel = fast ? bs.rowsel : nullptr;
   fn.keys = keys;
   fn.rpair = bs.rpair;
