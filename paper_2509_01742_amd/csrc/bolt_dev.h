@@ -50,6 +50,8 @@ struct Ctl {
   uint64_t hbm_live;     // of which items of HBM bins
   uint32_t b_hbm_in;     // items the current batch placed in HBM bins
   uint32_t b_hbm_rm;     // items the current batch removed from HBM bins
+  uint32_t fin_done;     // BOLT_F_DECOMPOSED: finish workgroups done with their share of the ring returns
+  uint32_t pad0;
 };
 
 // ---------------------------------------------------------------------------

@@ -1525,22 +1525,6 @@ __device__ __forceinline__ void finish_apply(const FinishArgs& a, bool ok, uint6
 // and cleared; part is kFreeBuckets words of LDS.  Every batch leaves the
 // buckets at zero.
 __device__ __forceinline__ void finish_counters(const FinishArgs& a, bool ok, uint32_t* part) {
-  if (a.decomp) {  // (the plan's flag: the same for the whole workgroup)
-    // the entries the rebuild slots staged go to the ring's tail, in slot
-    // order (one workgroup of 256 threads: a scan of the slots' counts)
-    const uint32_t n3 = 3 * a.q, per = (n3 + 255) / 256, s0 = threadIdx.x * per;
-    uint32_t mine = 0;
-    for (uint32_t s = s0; s < s0 + per && s < n3; ++s) mine += a.rfree_n[s];
-    __shared__ uint32_t tot;
-    uint32_t off = block_excl<256, false>(mine, &tot);
-    const uint64_t tail = a.ctl->ring_tail;
-    for (uint32_t s = s0; s < s0 + per && s < n3; ++s) {
-      const uint32_t n = a.rfree_n[s];
-      for (uint32_t j = 0; j < n; ++j) a.ring[(tail + off + j) % a.P] = a.rfree[(uint64_t)s * a.Z2 + j];
-      off += n;
-    }
-    if (threadIdx.x == 0) a.ctl->ring_give = tot;
-  }
   for (uint32_t t = threadIdx.x; t < kFreeBuckets; t += blockDim.x) {
     part[t] = a.freed[t];
     a.freed[t] = 0;  // ready for the next batch
@@ -1553,6 +1537,69 @@ __device__ __forceinline__ void finish_counters(const FinishArgs& a, bool ok, ui
   if (threadIdx.x == 0) finish_apply(a, ok, part[0]);
 }
 
+// Decomposed store: workgroup bid of nb returns its share of the entries
+// the rebuild slots staged to the ring's tail.  The 3q slots are split into
+// nb contiguous ranges of at most kRetChunk slots (3q <= 768 nb for every
+// launch: nb >= q / 256); entries go to the ring in slot order, so a range
+// starts after every entry of the slots before it (summed here, each
+// workgroup on its own).  The range's slot offsets go to LDS and each
+// thread then copies every 256th entry, so no thread waits on a chain of
+// loads.  The workgroup adds its count to ring_give.
+constexpr uint32_t kRetChunk = 768;
+
+__device__ __forceinline__ void ring_return(const FinishArgs& a, uint32_t bid, uint32_t nb) {
+  const uint32_t n3 = 3 * a.q, per_wg = (n3 + nb - 1) / nb;
+  const uint32_t lo = bid * per_wg < n3 ? bid * per_wg : n3, hi = lo + per_wg < n3 ? lo + per_wg : n3;
+  __shared__ uint32_t pre[kRetChunk + 1];
+  __shared__ uint32_t tot;
+  if (hi - lo > kRetChunk) {  // not reached by the launches above
+    if (threadIdx.x == 0) set_err(a.ctl, kErrOverflow);
+    return;
+  }
+  // entries of the slots before the range: eight loads in flight per thread
+  uint32_t acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  uint32_t s = threadIdx.x;
+  for (; s + 7 * 256 < lo; s += 8 * 256) {
+#pragma unroll
+    for (int k = 0; k < 8; ++k) acc[k] += a.rfree_n[s + k * 256];
+  }
+  for (; s < lo; s += 256) acc[0] += a.rfree_n[s];
+  uint32_t before = 0;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) before += acc[k];
+  block_excl<256, false>(before, &tot);
+  const uint64_t at = a.ctl->ring_tail + tot;  // the tail moves only when the last workgroup is done
+  // the range's counts, three consecutive slots per thread, and their offsets
+  const uint32_t len = hi - lo, s0 = threadIdx.x * 3;
+  uint32_t c[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) c[k] = s0 + k < len ? a.rfree_n[lo + s0 + k] : 0;
+  uint32_t off = block_excl<256, false>(c[0] + c[1] + c[2], &tot);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    if (s0 + k < len) pre[s0 + k] = off;
+    off += c[k];
+  }
+  const uint32_t total = tot;
+  if (threadIdx.x == 0) pre[len] = total;
+  __syncthreads();
+  for (uint32_t i = threadIdx.x; i < total; i += 256) {
+    // the slot x with pre[x] <= i < pre[x + 1]: the last offset <= i
+    uint32_t x = 0, span = len;
+    while (span > 0) {
+      const uint32_t h = span >> 1;
+      if (pre[x + h + 1] <= i) {
+        x += h + 1;
+        span -= h + 1;
+      } else {
+        span = h;
+      }
+    }
+    a.ring[(at + i) % a.P] = a.rfree[(uint64_t)(lo + x) * a.Z2 + (i - pre[x])];
+  }
+  if (threadIdx.x == 0 && total) atomicAdd(&a.ctl->ring_give, total);
+}
+
 template <bool MULTI>
 __global__ __launch_bounds__(256) void k_acc_finish(FinishArgs a1, const AccessPlan* tab) {
   BOLT_PICK(FinishArgs, fn);
@@ -1561,8 +1608,24 @@ __global__ __launch_bounds__(256) void k_acc_finish(FinishArgs a1, const AccessP
   if (a.ctl->reject == a.epoch) return;
   const bool ok = !a.ctl->err;
   if (ok) finish_cmd(a, bid * blockDim.x + threadIdx.x);
-  if (bid != 0) return;
   __shared__ uint32_t part[kFreeBuckets];
+  if (!a.decomp) {  // (the plan's flag: the same for the whole workgroup)
+    if (bid == 0) finish_counters(a, ok, part);
+    return;
+  }
+  // Every workgroup returns its share of the staged entries; the last one
+  // done (a counter, no waiting) applies the batch's counters, when every
+  // share is in the ring and ring_give is whole.
+  const uint32_t nb = gridDim.x - (MULTI ? 0 : a.ship_blocks);
+  ring_return(a, bid, nb);
+  __threadfence();
+  __syncthreads();
+  __shared__ uint32_t last;
+  if (threadIdx.x == 0) last = atomicAdd(&a.ctl->fin_done, 1u) == nb - 1;
+  __syncthreads();
+  if (!last) return;
+  __threadfence();
+  if (threadIdx.x == 0) a.ctl->fin_done = 0;
   finish_counters(a, ok, part);
 }
 

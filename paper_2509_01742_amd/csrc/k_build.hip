@@ -195,6 +195,8 @@ __global__ void k_ctl_init(Ctl* ctl) {
   ctl->hbm_live = 0;
   ctl->b_hbm_in = 0;
   ctl->b_hbm_rm = 0;
+  ctl->fin_done = 0;
+  ctl->pad0 = 0;
 }
 
 void launch_map_init(bolt_map* m, hipStream_t st) {
