@@ -495,30 +495,57 @@ __device__ __forceinline__ bool exp_pick(const NetSeg* segs, uint32_t flip, cons
   return m >= 1;  // a one-element array is copied through unchanged
 }
 
-// Stages jlow + F - 1 .. jlow in one pass.  Thread = (residue r, block of
-// 2^F coordinates c0..); coordinate c is position c * 2^jlow + r.
+// Stages jlow + F - 1 .. jlow in one pass.  Coordinate c is position
+// c * 2^jlow + r for residue r.  A wave takes 64 consecutive residues and a
+// group of 2^F consecutive coordinates (its outputs); it also needs the
+// 2^F - 1 coordinates to the left (elements arriving from there).  The four
+// waves of a workgroup take four consecutive groups of the same residues,
+// so each wave hands the inputs of its last 2^F - 1 coordinates to the next
+// wave through LDS, and only wave 0 loads its left part from memory: the
+// pass reads about 1.2 times what it writes instead of 2 (2^jlow >= 64).
 template <int F, bool MULTI>
 __global__ __launch_bounds__(256) void k_expand_fused(const uint64_t* __restrict__ in1, uint64_t* __restrict__ out1,
                                                       uint64_t m1, uint32_t jlow, const NetSeg* segs, uint32_t flip) {
   const uint64_t* in = in1;
   uint64_t* out = out1;
   uint64_t m = m1;
-  if (!exp_pick<MULTI>(segs, flip, in, out, m)) return;
+  if (!exp_pick<MULTI>(segs, flip, in, out, m)) return;  // whole block
   constexpr int NB = 1 << F;      // outputs per thread
   constexpr int NW = 2 * NB - 1;  // window: NB - 1 to the left
+  __shared__ uint64_t halo[3][NB - 1][64];
   const uint64_t hl = 1ull << jlow;
-  const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const uint64_t r = t & (hl - 1);
-  const uint64_t c0 = (t >> jlow) * NB;
+  const uint32_t lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const uint64_t rchunks = hl >> 6;
+  const uint64_t r = (blockIdx.x % rchunks) * 64 + lane;
+  const uint64_t c0 = ((blockIdx.x / rchunks) * 4 + w) * NB;
   const uint64_t ncoord = (m + hl - 1) >> jlow;
-  if (c0 >= ncoord || r >= m) return;
+  const bool act = c0 < ncoord && r < m;  // no return before the barrier
   uint64_t v[NW];
 #pragma unroll
-  for (int k = 0; k < NW; ++k) {
-    const int64_t c = (int64_t)c0 - (NB - 1) + k;
-    const uint64_t pos = (uint64_t)c * hl + r;
-    v[k] = (c >= 0 && pos < m) ? in[pos] : kNone64;
+  for (int k = NB - 1; k < NW; ++k) {
+    const uint64_t pos = (c0 + (k - (NB - 1))) * hl + r;
+    v[k] = (act && pos < m) ? in[pos] : kNone64;
   }
+  if (w < 3) {
+#pragma unroll
+    for (int j = 0; j < NB - 1; ++j) halo[w][j][lane] = v[NB + j];
+  }
+  if (w == 0) {
+#pragma unroll
+    for (int k = 0; k < NB - 1; ++k) {
+      const int64_t c = (int64_t)c0 - (NB - 1) + k;
+      const uint64_t pos = (uint64_t)c * hl + r;
+      v[k] = (act && c >= 0 && pos < m) ? in[pos] : kNone64;
+    }
+  }
+  __syncthreads();
+  if (w > 0) {
+    // the previous wave's coordinates c0 - NB + 1 .. c0 - 1 (it is active
+    // whenever this one is: same residues, lower coordinates)
+#pragma unroll
+    for (int k = 0; k < NB - 1; ++k) v[k] = halo[w - 1][k][lane];
+  }
+  if (!act) return;
 #pragma unroll
   for (int f = F - 1; f >= 0; --f) {
     const int d = 1 << f;
@@ -594,10 +621,10 @@ static bool expand_schedule(uint64_t* a, uint64_t* tmp, uint64_t mmax, const Net
     if (F > (int)fmax) F = (int)fmax;
     TimedScope ts(tm, kkExpand, st);
     const uint32_t jlow = (uint32_t)(j - F + 1);
-    const uint64_t hl = 1ull << jlow;
+    const uint64_t hl = 1ull << jlow;  // >= 2^kExpLow: whole waves of residues
     const uint64_t ncoord = (mmax + hl - 1) >> jlow;
-    const uint64_t threads = ((ncoord + (1u << F) - 1) >> F) * hl;
-    const dim3 grid((uint32_t)((threads + 255) / 256), count), block(256);
+    const uint64_t groups = (ncoord + (1u << F) - 1) >> F;  // of 2^F coordinates, four per workgroup
+    const dim3 grid((uint32_t)(((groups + 3) / 4) * (hl >> 6)), count), block(256);
     switch (F) {
       case 1: hipLaunchKernelGGL((k_expand_fused<1, MULTI>), grid, block, 0, st, src, dst, mmax, jlow, segs, flip); break;
       case 2: hipLaunchKernelGGL((k_expand_fused<2, MULTI>), grid, block, 0, st, src, dst, mmax, jlow, segs, flip); break;
