@@ -475,6 +475,7 @@ void launch_bitonic_sort_many(const NetSeg* segs, uint32_t count, uint64_t nmax,
 // ---------------------------------------------------------------------------
 
 constexpr int kExpLow = 10;
+static_assert(kExpLow >= 8, "the fused expansion passes take whole workgroups of 256 residues");
 constexpr uint32_t kExpTile = 4096;
 constexpr uint32_t kExpHalo = 1u << kExpLow;
 
@@ -498,14 +499,18 @@ __device__ __forceinline__ bool exp_pick(const NetSeg* segs, uint32_t flip, cons
 // Stages jlow + F - 1 .. jlow in one pass.  Coordinate c is position
 // c * 2^jlow + r for residue r.  A wave takes 64 consecutive residues and a
 // group of 2^F consecutive coordinates (its outputs); it also needs the
-// 2^F - 1 coordinates to the left (elements arriving from there).  The four
-// waves of a workgroup take four consecutive groups of the same residues,
-// so each wave hands the inputs of its last 2^F - 1 coordinates to the next
-// wave through LDS, and only wave 0 loads its left part from memory: the
-// pass reads about 1.2 times what it writes instead of 2 (2^jlow >= 64).
+// 2^F - 1 coordinates to the left (elements arriving from there).  With
+// `share` (four groups or more), the four waves of a workgroup take four
+// consecutive groups of the same residues, so each wave hands the inputs of
+// its last 2^F - 1 coordinates to the next wave through LDS and only wave 0
+// loads its left part from memory: the pass reads about 1.2 times what it
+// writes instead of 2.  Without (the top passes, fewer groups than waves),
+// the four waves take four consecutive residue chunks of one group and load
+// their own left parts.  2^jlow >= 256: whole workgroups of residues.
 template <int F, bool MULTI>
 __global__ __launch_bounds__(256) void k_expand_fused(const uint64_t* __restrict__ in1, uint64_t* __restrict__ out1,
-                                                      uint64_t m1, uint32_t jlow, const NetSeg* segs, uint32_t flip) {
+                                                      uint64_t m1, uint32_t jlow, const NetSeg* segs, uint32_t flip,
+                                                      uint32_t share) {
   const uint64_t* in = in1;
   uint64_t* out = out1;
   uint64_t m = m1;
@@ -516,8 +521,15 @@ __global__ __launch_bounds__(256) void k_expand_fused(const uint64_t* __restrict
   const uint64_t hl = 1ull << jlow;
   const uint32_t lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const uint64_t rchunks = hl >> 6;
-  const uint64_t r = (blockIdx.x % rchunks) * 64 + lane;
-  const uint64_t c0 = ((blockIdx.x / rchunks) * 4 + w) * NB;
+  uint64_t r, c0;
+  if (share) {
+    r = (blockIdx.x % rchunks) * 64 + lane;
+    c0 = ((blockIdx.x / rchunks) * 4 + w) * NB;
+  } else {
+    const uint64_t rq = rchunks >> 2;
+    r = ((blockIdx.x % rq) * 4 + w) * 64 + lane;
+    c0 = (blockIdx.x / rq) * NB;
+  }
   const uint64_t ncoord = (m + hl - 1) >> jlow;
   const bool act = c0 < ncoord && r < m;  // no return before the barrier
   uint64_t v[NW];
@@ -526,11 +538,11 @@ __global__ __launch_bounds__(256) void k_expand_fused(const uint64_t* __restrict
     const uint64_t pos = (c0 + (k - (NB - 1))) * hl + r;
     v[k] = (act && pos < m) ? in[pos] : kNone64;
   }
-  if (w < 3) {
+  if (share && w < 3) {
 #pragma unroll
     for (int j = 0; j < NB - 1; ++j) halo[w][j][lane] = v[NB + j];
   }
-  if (w == 0) {
+  if (!share || w == 0) {
 #pragma unroll
     for (int k = 0; k < NB - 1; ++k) {
       const int64_t c = (int64_t)c0 - (NB - 1) + k;
@@ -539,7 +551,7 @@ __global__ __launch_bounds__(256) void k_expand_fused(const uint64_t* __restrict
     }
   }
   __syncthreads();
-  if (w > 0) {
+  if (share && w > 0) {
     // the previous wave's coordinates c0 - NB + 1 .. c0 - 1 (it is active
     // whenever this one is: same residues, lower coordinates)
 #pragma unroll
@@ -621,15 +633,17 @@ static bool expand_schedule(uint64_t* a, uint64_t* tmp, uint64_t mmax, const Net
     if (F > (int)fmax) F = (int)fmax;
     TimedScope ts(tm, kkExpand, st);
     const uint32_t jlow = (uint32_t)(j - F + 1);
-    const uint64_t hl = 1ull << jlow;  // >= 2^kExpLow: whole waves of residues
+    const uint64_t hl = 1ull << jlow;  // >= 2^kExpLow: whole workgroups of residues
     const uint64_t ncoord = (mmax + hl - 1) >> jlow;
-    const uint64_t groups = (ncoord + (1u << F) - 1) >> F;  // of 2^F coordinates, four per workgroup
-    const dim3 grid((uint32_t)(((groups + 3) / 4) * (hl >> 6)), count), block(256);
+    const uint64_t groups = (ncoord + (1u << F) - 1) >> F;  // of 2^F coordinates
+    const uint32_t share = groups >= 4 ? 1 : 0;  // four groups per workgroup, else four residue chunks
+    const uint64_t blocks = share ? ((groups + 3) / 4) * (hl >> 6) : groups * (hl >> 8);
+    const dim3 grid((uint32_t)blocks, count), block(256);
     switch (F) {
-      case 1: hipLaunchKernelGGL((k_expand_fused<1, MULTI>), grid, block, 0, st, src, dst, mmax, jlow, segs, flip); break;
-      case 2: hipLaunchKernelGGL((k_expand_fused<2, MULTI>), grid, block, 0, st, src, dst, mmax, jlow, segs, flip); break;
-      case 3: hipLaunchKernelGGL((k_expand_fused<3, MULTI>), grid, block, 0, st, src, dst, mmax, jlow, segs, flip); break;
-      default: hipLaunchKernelGGL((k_expand_fused<4, MULTI>), grid, block, 0, st, src, dst, mmax, jlow, segs, flip); break;
+      case 1: hipLaunchKernelGGL((k_expand_fused<1, MULTI>), grid, block, 0, st, src, dst, mmax, jlow, segs, flip, share); break;
+      case 2: hipLaunchKernelGGL((k_expand_fused<2, MULTI>), grid, block, 0, st, src, dst, mmax, jlow, segs, flip, share); break;
+      case 3: hipLaunchKernelGGL((k_expand_fused<3, MULTI>), grid, block, 0, st, src, dst, mmax, jlow, segs, flip, share); break;
+      default: hipLaunchKernelGGL((k_expand_fused<4, MULTI>), grid, block, 0, st, src, dst, mmax, jlow, segs, flip, share); break;
     }
     uint64_t* t = src;
     src = dst;
