@@ -86,7 +86,7 @@ def kernel_bytes(cls, sz, n, npad, n_ops, host_roles, send_share=0.0):
     return None, None
 
 
-def run_mode(args, wl, dev_t, B, torch, observable, seal=False, decomposed=False, seq=False):
+def run_mode(args, wl, dev_t, B, torch, observable, seal=False, decomposed=False):
     n, vs = wl.n, wl.vs
     d_keys, d_vals, d_ops, d_qk, d_qv, d_out, d_st, bounds = dev_t
     obs = B.BOLT_OBS_HOST_PINNED if observable == "host" else B.BOLT_OBS_DEVICE
@@ -111,18 +111,8 @@ def run_mode(args, wl, dev_t, B, torch, observable, seal=False, decomposed=False
     log("[%s] created %d maps (%.1fs); footprint hbm=%.2f GiB obs=%.2f GiB" % (
         observable, nsteps + 1, time.time() - t0, B.footprint(p)[0] / 2**30, B.footprint(p)[1] / 2**30))
     nb = len(bounds) - 1
-    qs = [int(bounds[i + 1] - bounds[i]) for i in range(nb)]
 
     def run_step(m):
-        if seq:  # every batch in one call: each batch's dedup beside the batch before it
-            evs = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
-            evs[0].record(stream)
-            B.check(m.build(d_keys, d_vals), "bolt_build")
-            evs[1].record(stream)
-            B.check(m.access_seq(d_ops, d_qk, d_qv, d_out, d_st, qs), "bolt_access_seq")
-            B.check(m.flush(), "bolt_flush")
-            evs[2].record(stream)
-            return evs
         evs = [torch.cuda.Event(enable_timing=True) for _ in range(nb + 2)]
         evs[0].record(stream)
         B.check(m.build(d_keys, d_vals), "bolt_build")
@@ -199,7 +189,7 @@ def run_mode(args, wl, dev_t, B, torch, observable, seal=False, decomposed=False
             ent.update({"bytes_per_launch": int(per), "achieved_GBps": round(gbs, 1), "bound": bound,
                         "frac_of_peak": round(gbs / peak, 4)})
         kernels[cls] = ent
-    lat_np = np.array(lat) if lat and not seq else np.zeros(1)
+    lat_np = np.array(lat)
     return {
         "ops_per_s": n_ops * K / (sum(query_ms) / 1e3),
         "build_keys_per_s": n * K / (sum(build_ms) / 1e3),

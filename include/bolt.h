@@ -174,23 +174,6 @@ int bolt_build(bolt_map* m, const uint64_t* d_keys, const void* d_vals, uint64_t
 int bolt_access_batch(bolt_map* m, const uint8_t* d_ops, const uint64_t* d_keys, const void* d_vals_in,
                       void* d_vals_out, uint8_t* d_status, uint32_t q, void* hip_stream);
 
-/* Runs nb >= 1 batches of one map in order, with exactly the answers,
- * statuses, state and trace of nb calls of bolt_access_batch.  Batch b is
- * the host_q[b] commands (1..BOLT_MAX_BATCH each) that follow batch b - 1's
- * in d_ops, d_keys, d_vals_in, d_vals_out and d_status, each of which holds
- * the sum of host_q (same layout and alignment as bolt_access_batch).  The
- * steps of a batch that depend only on its commands (the in-batch dedup and
- * the key hashes) run on the map's own stream beside the previous batch's
- * fetch .. finish, as the modules of Sec. 5.1 (decode, key search, value
- * access, remap, respond) work on different commands at once; only the
- * tape positions the next batch starts at are taken ahead, on the guess
- * that the current batch is accepted (a rejected batch takes none: its
- * successor then re-derives its tape pairs).  Stream-ordered on hip_stream
- * like bolt_access_batch; host_q is read before the call returns.  An empty
- * batch, nb = 0 or a null host_q return BOLT_EINVAL with nothing run. */
-int bolt_access_seq(bolt_map* m, const uint8_t* d_ops, const uint64_t* d_keys, const void* d_vals_in,
-                    void* d_vals_out, uint8_t* d_status, const uint32_t* host_q, uint32_t nb, void* hip_stream);
-
 /* q GETs: d_vals_out[q][vs] gets each value (zeros when absent), d_found[q]
  * gets 1 when the key was present and 0 otherwise. */
 int bolt_get_batch(bolt_map* m, const uint64_t* d_keys, uint32_t q, void* d_vals_out, uint8_t* d_found,

@@ -113,7 +113,6 @@ _SIGS = [
     ("bolt_create", _I, [C.POINTER(bolt_params), _P, C.POINTER(_P)]),
     ("bolt_build", _I, [_P, _P, _P, _U64, _P]),
     ("bolt_access_batch", _I, [_P, _P, _P, _P, _P, _P, _U32, _P]),
-    ("bolt_access_seq", _I, [_P, _P, _P, _P, _P, _P, C.POINTER(_U32), _U32, _P]),
     ("bolt_access_many", _I, [_P, _P, _U32, _P]),
     ("bolt_build_many", _I, [_P, _P, _P, _P, _U32, _P]),
     ("bolt_get_batch", _I, [_P, _P, _U32, _P, _P, _P]),
@@ -306,13 +305,6 @@ class Map:
         q = ops.numel()
         return bolt_access_batch(self.h, _dptr(ops), _dptr(keys), _dptr(vals_in), _dptr(vals_out), _dptr(status),
                                  q, _stream(stream))
-
-    def access_seq(self, ops, keys, vals_in, vals_out, status, qs, stream=None) -> int:
-        """Batches of qs[0], qs[1], ... commands, one after another in the
-        arrays (the arguments of access, holding sum(qs) commands)."""
-        arr = (_U32 * max(1, len(qs)))(*[int(x) for x in qs])
-        return bolt_access_seq(self.h, _dptr(ops), _dptr(keys), _dptr(vals_in), _dptr(vals_out), _dptr(status), arr,
-                               len(qs), _stream(stream))
 
     def access_sealed(self, req, resp, stream=None) -> int:
         """One sealed request: req / resp device tensors of q command and q

@@ -74,8 +74,7 @@ int derive(const bolt_params* p, Sizes* s) {
 uint64_t scratch_bytes(const Sizes& s) {
   const uint64_t Q = kMaxBatch;
   return Q * 4 * 13 + Q * s.vs + Q * 8 + 3 * Q * 4 + 2 * Q * s.page_bytes + 2 * Q * s.vs + 2 * Q + Q * 24 + 256 * 4 +
-         2 * (2 * Q * s.page_bytes + 2 * Q * 4) +  // two outbox halves + the page each of their slots sends
-         Q * (3 * 4 + 8 + 24);  // the dedup's outputs (leader, prevw, lastw, F, R, rows): a second half
+         2 * (2 * Q * s.page_bytes + 2 * Q * 4);  // two outbox halves + the page each of their slots sends
 }
 
 uint64_t device_bytes(const bolt_params* p, const Sizes& s) {
@@ -117,10 +116,6 @@ void free_all(bolt_map* m) {
   if (m->side) (void)hipStreamDestroy(m->side);
   if (m->ev_fork) (void)hipEventDestroy(m->ev_fork);
   if (m->ev_join) (void)hipEventDestroy(m->ev_join);
-  for (hipEvent_t& e : m->ev_seq) {
-    if (e) (void)hipEventDestroy(e);
-    e = nullptr;
-  }
   m->side = nullptr;
   m->ev_fork = m->ev_join = nullptr;
 }
@@ -266,15 +261,15 @@ int bolt_create(const bolt_params* p, void* hip_stream, bolt_map** out) {
   rc = rc ? rc : dalloc(m, &m->claim, s.B * 8);
   rc = rc ? rc : dalloc(m, &m->rmask, s.B * 8);
   BatchScratch& b = m->bs;
-  rc = rc ? rc : dalloc(m, &b.leader, 2 * Q * 4);
-  rc = rc ? rc : dalloc(m, &b.prevw, 2 * Q * 4);
-  rc = rc ? rc : dalloc(m, &b.lastw, 2 * Q * 4);
+  rc = rc ? rc : dalloc(m, &b.leader, Q * 4);
+  rc = rc ? rc : dalloc(m, &b.prevw, Q * 4);
+  rc = rc ? rc : dalloc(m, &b.lastw, Q * 4);
   rc = rc ? rc : dalloc(m, &b.hit, Q * 4);
   rc = rc ? rc : dalloc(m, &b.hrow, Q * 4);
   rc = rc ? rc : dalloc(m, &b.hslot, Q * 4);
   rc = rc ? rc : dalloc(m, &b.found, Q * 4);
   rc = rc ? rc : dalloc(m, &b.fval, Q * s.vs);
-  rc = rc ? rc : dalloc(m, &b.rpair, 2 * Q * 8);
+  rc = rc ? rc : dalloc(m, &b.rpair, Q * 8);
   rc = rc ? rc : dalloc(m, &b.cand_bin, 3 * Q * 4);
   rc = rc ? rc : dalloc(m, &b.stage, 2 * Q * s.page_bytes);
   rc = rc ? rc : dalloc(m, &b.outbox, 2 * 2 * Q * s.page_bytes);
@@ -284,8 +279,8 @@ int bolt_create(const bolt_params* p, void* hip_stream, bolt_map** out) {
   rc = rc ? rc : dalloc(m, &b.chosen, Q * 4);
   rc = rc ? rc : dalloc(m, &b.rowsel, Q * 4);
   rc = rc ? rc : dalloc(m, &b.freed, 256 * 4);
-  rc = rc ? rc : dalloc(m, &b.fpair, 2 * Q * 8);
-  rc = rc ? rc : dalloc(m, &b.rows, 2 * Q * 16);
+  rc = rc ? rc : dalloc(m, &b.fpair, Q * 8);
+  rc = rc ? rc : dalloc(m, &b.rows, Q * 16);
   if (p->flags & BOLT_F_DECOMPOSED) {
     rc = rc ? rc : dalloc(m, &b.rfree, 3 * Q * 2 * s.Z * 4);
     rc = rc ? rc : dalloc(m, &b.rfree_n, 3 * Q * 4);
@@ -327,9 +322,7 @@ int bolt_create(const bolt_params* p, void* hip_stream, bolt_map** out) {
     delete m;
     return rc;
   }
-  bool evs_ok = true;
-  for (hipEvent_t& e : m->ev_seq) evs_ok = evs_ok && hipEventCreateWithFlags(&e, hipEventDisableTiming) == hipSuccess;
-  if (!evs_ok || hipStreamCreateWithFlags(&m->side, hipStreamNonBlocking) != hipSuccess ||
+  if (hipStreamCreateWithFlags(&m->side, hipStreamNonBlocking) != hipSuccess ||
       hipEventCreateWithFlags(&m->ev_fork, hipEventDisableTiming) != hipSuccess ||
       hipEventCreateWithFlags(&m->ev_join, hipEventDisableTiming) != hipSuccess) {
     free_all(m);
@@ -415,21 +408,6 @@ int bolt_access_batch(bolt_map* m, const uint8_t* d_ops, const uint64_t* d_keys,
   m->last_stream = st;
   if (hipSetDevice(m->device) != hipSuccess) return BOLT_EHIP;
   return run_access(m, d_ops, d_keys, d_vals_in, d_vals_out, d_status, q, st);
-}
-
-int bolt_access_seq(bolt_map* m, const uint8_t* d_ops, const uint64_t* d_keys, const void* d_vals_in,
-                    void* d_vals_out, uint8_t* d_status, const uint32_t* host_q, uint32_t nb, void* hip_stream) {
-  int rc = map_check(m);
-  if (rc) return rc;
-  if (!m->built || nb == 0 || !host_q) return BOLT_EINVAL;
-  for (uint32_t b = 0; b < nb; ++b)
-    if (host_q[b] == 0 || host_q[b] > kMaxBatch) return BOLT_EINVAL;
-  if (!d_ops || !d_keys || !d_vals_in || !d_vals_out || !d_status) return BOLT_EINVAL;
-  if (((uintptr_t)d_keys | (uintptr_t)d_vals_in | (uintptr_t)d_vals_out) & 7) return BOLT_EINVAL;
-  hipStream_t st = (hipStream_t)hip_stream;
-  m->last_stream = st;
-  if (hipSetDevice(m->device) != hipSuccess) return BOLT_EHIP;
-  return run_access_seq(m, d_ops, d_keys, d_vals_in, d_vals_out, d_status, host_q, nb, st);
 }
 
 int bolt_access_many(bolt_map* const* maps, const bolt_batch* batches, uint32_t count, void* hip_stream) {

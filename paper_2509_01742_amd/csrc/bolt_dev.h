@@ -26,7 +26,7 @@ struct Ctl {
   uint32_t hkey[8];      // BLAKE2s chaining value after the padded key block
   uint32_t skey[8];      // page-sealing key: PRF(domain 4, 0) as eight LE words
   uint32_t err;          // sticky error bits
-  uint32_t reject[2];    // [epoch & 1]: the epoch of the last batch of that parity with a bad op code
+  uint32_t reject;       // current batch rejected (bad op code)
   uint64_t steps;        // tape counter s
   uint64_t live;         // keys present
   uint64_t stash_live;   // stash pool entries in use at the end of the last batch
@@ -52,10 +52,6 @@ struct Ctl {
   uint32_t b_hbm_rm;     // items the current batch removed from HBM bins
   uint32_t fin_done;     // BOLT_F_DECOMPOSED: finish workgroups done with their share of the ring returns
   uint32_t pad0;
-  // Batch sequences (bolt_access_seq): spec[e & 1] is the tape position at
-  // which batch e's dedup, run beside batch e - 1, starts its commands (the
-  // steps after batch e - 2 plus batch e - 1's commands).
-  uint64_t spec[2];
 };
 
 // ---------------------------------------------------------------------------

@@ -13,17 +13,15 @@ namespace bolt {
 
 // Scratch of one access batch, sized for BOLT_MAX_BATCH commands.
 struct BatchScratch {
-  // The dedup's outputs (leader, prevw, lastw, rpair, fpair, rows) have two
-  // halves of Q, a batch using half (epoch & 1).
-  uint32_t* leader;   // [2][Q] index of the first command with the same key
-  uint32_t* prevw;    // [2][Q] last PUT/DEL of the same key before this command, or kNone
-  uint32_t* lastw;    // [2][Q] (leaders) last PUT/DEL of the key in the batch, or kNone
+  uint32_t* leader;   // [Q] index of the first command with the same key
+  uint32_t* prevw;    // [Q] last PUT/DEL of the same key before this command, or kNone
+  uint32_t* lastw;    // [Q] (leaders) last PUT/DEL of the key in the batch, or kNone
   uint32_t* hit;      // [Q] (leaders) key found in the position map
   uint32_t* hrow;     // [Q] (leaders) its row
   uint32_t* hslot;    // [Q] (leaders) its slot in the row
   uint32_t* found;    // [Q] (leaders) item found in one of the two bins
   uint8_t* fval;      // [Q * vs] (leaders) the value found
-  uint2* rpair;       // [2][Q] remap pair R(s) of each command
+  uint2* rpair;       // [Q] remap pair R(s) of each command
   uint32_t* cand_bin; // [3Q] bin each write-back candidate slot would rewrite, or kNone
   uint8_t* stage;     // [2Q * page_bytes] copies of the observable pages read
   uint8_t* outbox;    // [2][2Q * page_bytes] observable pages rebuilt by the write-back, by slot; a batch uses
@@ -33,8 +31,8 @@ struct BatchScratch {
   uint32_t* chosen;   // [Q] (leaders placed) bin chosen by P2C
   uint32_t* rowsel;   // [Q] (keys inserted) position-map row chosen
   uint32_t* freed;    // [256] stash entries freed this batch, in buckets
-  uint2* fpair;       // [2][Q] fetch pair F(s) of each command
-  uint4* rows;        // [2][Q] position-map rows of each command's key
+  uint2* fpair;       // [Q] fetch pair F(s) of each command
+  uint4* rows;        // [Q] position-map rows of each command's key
   uint32_t* rfree;    // BOLT_F_DECOMPOSED: [3Q][2Z] pool entries each rebuild slot returns to the ring
   uint32_t* rfree_n;  // BOLT_F_DECOMPOSED: [3Q] how many
 };
@@ -141,10 +139,6 @@ struct bolt_map {
   // back to the caller's stream with the two events.
   hipStream_t side;
   hipEvent_t ev_fork, ev_join;
-  // bolt_access_seq: a batch's dedup runs on `side` beside the previous
-  // batch; ev_seq[0] marks the call's start, [1 + parity] a dedup's end,
-  // [3 + parity] a batch's end.
-  hipEvent_t ev_seq[5];
   // BOLT_F_GRAPHS: one access plan on the device, and the graph of the
   // access pipeline captured per batch-size class ceil(log2 q) = 0..13.
   void* gplan;
@@ -203,10 +197,6 @@ int run_build_many(bolt_map* const* maps, const uint64_t* const* keys, const voi
                    uint32_t count, hipStream_t st);
 int run_access(bolt_map* m, const uint8_t* ops, const uint64_t* keys, const void* vals_in, void* vals_out,
                uint8_t* status, uint32_t q, hipStream_t st);
-// nb batches of one map in order (batch b: qs[b] commands after batch b - 1's
-// in every array), each batch's dedup beside the previous batch's steps.
-int run_access_seq(bolt_map* m, const uint8_t* ops, const uint64_t* keys, const void* vals_in, void* vals_out,
-                   uint8_t* status, const uint32_t* qs, uint32_t nb, hipStream_t st);
 // defer_pages: large batches on pinned stores rebuild their pages into the
 // outbox, sent by each map's next batch (or a flush); else the rebuild
 // writes them.  The pages pending from each map's previous batch always go

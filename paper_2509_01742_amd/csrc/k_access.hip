@@ -62,7 +62,6 @@ struct GroupArgs {
   uint4* rows;
   ShipArgs ship;  // a slice of the previous batch's send, by the first ship_blocks workgroups
   uint32_t ship_blocks;
-  uint32_t spec;  // 1: tape positions start at ctl->spec[epoch & 1] (a batch sequence), else at ctl->steps
 };
 
 
@@ -109,7 +108,6 @@ struct FetchArgs {
   uint32_t ship_blocks;    // ... by the first ship_blocks workgroups
   uint32_t pre_host;       // 1: observable pages are read ahead too (device store)
   uint32_t decomp;         // BOLT_F_DECOMPOSED: an HBM bin is only its list (no page)
-  uint32_t spec;           // the dedup took its tape positions from ctl->spec[epoch & 1]
 };
 
 struct ResolveArgs {
@@ -256,8 +254,6 @@ struct FinishArgs {
   uint64_t P;
   const uint32_t* rfree;    // [3Q][2Z]
   const uint32_t* rfree_n;  // [3Q]
-  uint32_t spec_next;       // a batch sequence: set ctl->spec[epoch & 1] for the batch after next ...
-  uint32_t next_q;          // ... as the steps after this batch plus the next batch's commands
 };
 
 // Every kernel argument of one map's batch.  A multi-map launch reads the
@@ -539,8 +535,7 @@ __device__ __forceinline__ void group_prf(const GroupArgs& a, uint32_t t) {
   for (int j = 0; j < 8; ++j) hk[j] = a.ctl->hkey[j];
   uint64_t w[4];
   if ((t & 1) == 0) {
-    const uint64_t base = a.spec ? a.ctl->spec[a.epoch & 1] : a.ctl->steps;
-    prf4(hk, kDomTape, base + i, w);
+    prf4(hk, kDomTape, a.ctl->steps + i, w);
     uint32_t f1, f2, r1, r2;
     pair_of(w[0], w[1], a.B, f1, f2);
     pair_of(w[2], w[3], a.B, r1, r2);
@@ -631,7 +626,7 @@ __global__ __launch_bounds__(kDedupNT) void k_acc_group(GroupArgs a1, const Acce
     base += all;
   }
   __syncthreads();
-  if (__any(bad) && lane == 0) a.ctl->reject[a.epoch & 1] = a.epoch;  // the same value from every writer
+  if (__any(bad) && lane == 0) a.ctl->reject = a.epoch;  // the same value from every writer
   const uint32_t q = base;  // commands in this partition
   if (q == 0) return;       // whole block
   if (q <= kDedupNT) {
@@ -769,27 +764,8 @@ __global__ __launch_bounds__(kDedupNT) void k_acc_group(GroupArgs a1, const Acce
 template <bool SEALED, bool EAGER = false>
 __device__ __forceinline__ void fetch_cmd(const FetchArgs& a, uint32_t i, uint64_t* pg) {
   const uint32_t lane = threadIdx.x & 63;
-  if (a.ctl->reject[a.epoch & 1] == a.epoch || a.ctl->err) return;
-  uint2 fp = a.fpair[i];  // F(s), from the dedup kernel
-  if (a.spec) {
-    // In a batch sequence the dedup ran beside the previous batch and took
-    // the tape positions after it.  If that batch was rejected (its
-    // commands took none), F(s) and R(s) are redone at the real position
-    // (the later kernels read R(s) from rpair).
-    const uint64_t s0 = a.ctl->steps;
-    if (s0 != a.ctl->spec[a.epoch & 1]) {
-      uint32_t hk[8];
-#pragma unroll
-      for (int j = 0; j < 8; ++j) hk[j] = a.ctl->hkey[j];
-      uint64_t w[4];
-      prf4(hk, kDomTape, s0 + i, w);
-      uint32_t f1, f2, r1, r2;
-      pair_of(w[0], w[1], a.B, f1, f2);
-      pair_of(w[2], w[3], a.B, r1, r2);
-      fp = make_uint2(f1, f2);
-      if (lane == 0) a.rpair[i] = make_uint2(r1, r2);
-    }
-  }
+  if (a.ctl->reject == a.epoch || a.ctl->err) return;
+  const uint2 fp = a.fpair[i];  // F(s), from the dedup kernel
   const uint32_t f1 = fp.x, f2 = fp.y;
   const uint64_t key = a.keys[i];
   const bool is_leader = a.leader[i] == i;
@@ -1018,7 +994,7 @@ __device__ __forceinline__ bool pm_claim(uint32_t* pm_mask, uint64_t* pm_key, ui
 // thread (live: i < q); every lane of the wave calls it.
 __device__ __forceinline__ void resolve_cmd(const ResolveArgs& a, uint32_t i) {
   const bool live = i < a.q;
-  if (a.ctl->reject[a.epoch & 1] == a.epoch || a.ctl->err) {
+  if (a.ctl->reject == a.epoch || a.ctl->err) {
     if (live) {
       a.status[i] = 0xFF;
       for (uint32_t o = 0; o < a.vw; ++o) a.vals_out[(uint64_t)i * a.vw + o] = 0;
@@ -1100,7 +1076,7 @@ __device__ __forceinline__ bool stash_put(const RemapArgs& a, uint32_t i, uint64
 // Command i's placement (one-round case), by one thread; every lane of the
 // wave calls it.
 __device__ __forceinline__ void place_cmd(const PlaceArgs& a, uint32_t i) {
-  if (a.ctl->reject[a.epoch & 1] == a.epoch || a.ctl->err) return;
+  if (a.ctl->reject == a.epoch || a.ctl->err) return;
   bool placed = false, ins = false, to_hbm = false;
   if (i < a.q) {
     a.cand_bin[2 * a.q + i] = kNone;
@@ -1181,7 +1157,7 @@ __global__ __launch_bounds__(kRemapNT) void k_acc_remap(RemapArgs a1, const Acce
   if (!a.enabled) return;
   __shared__ uint32_t tot;
   __shared__ uint32_t s_skip;
-  if (threadIdx.x == 0) s_skip = (a.ctl->reject[a.epoch & 1] == a.epoch || a.ctl->err) ? 1 : 0;
+  if (threadIdx.x == 0) s_skip = (a.ctl->reject == a.epoch || a.ctl->err) ? 1 : 0;
   __syncthreads();
   if (s_skip) return;
   const uint32_t i0 = threadIdx.x * kRemapPer;
@@ -1331,7 +1307,7 @@ __device__ __forceinline__ void compose_slot(const WbArgs& a, uint32_t s, uint64
   const uint32_t lane = threadIdx.x & 63;
   if (lane == 0 && s < 2 * a.q) a.ship_page[s] = kNone;
   if (lane == 0 && s < 3 * a.q && a.decomp) a.rfree_n[s] = 0;  // this slot returns nothing unless it rebuilds
-  if (s >= 3 * a.q || a.ctl->reject[a.epoch & 1] == a.epoch || a.ctl->err) return;  // whole wave
+  if (s >= 3 * a.q || a.ctl->reject == a.epoch || a.ctl->err) return;  // whole wave
   const uint32_t b = a.cand_bin[s];
   if (b == kNone) return;  // whole wave
   const bool host = b >= a.K;
@@ -1543,7 +1519,6 @@ __device__ __forceinline__ void finish_apply(const FinishArgs& a, bool ok, uint6
   c->ring_give = 0;
   c->b_hbm_in = 0;
   c->b_hbm_rm = 0;
-  if (a.spec_next) c->spec[a.epoch & 1] = c->steps + a.next_q;
 }
 
 // The batch's counters, by one whole workgroup: the freed buckets summed
@@ -1630,7 +1605,7 @@ __global__ __launch_bounds__(256) void k_acc_finish(FinishArgs a1, const AccessP
   BOLT_PICK(FinishArgs, fn);
   if (carry_ship<MULTI>(a.ship, a.ship_blocks)) return;
   const uint32_t bid = blockIdx.x - (MULTI ? 0 : a.ship_blocks);
-  if (a.ctl->reject[a.epoch & 1] == a.epoch) return;
+  if (a.ctl->reject == a.epoch) return;
   const bool ok = !a.ctl->err;
   if (ok) finish_cmd(a, bid * blockDim.x + threadIdx.x);
   __shared__ uint32_t part[kFreeBuckets];
@@ -1704,7 +1679,7 @@ __global__ __launch_bounds__(kSoloNT) void k_acc_solo(GroupArgs gr, FetchArgs fa
     gr.leader[0] = 0;
     gr.prevw[0] = kNone;
     gr.lastw[0] = (op & 3u) ? 0 : kNone;
-    if (op > 2) gr.ctl->reject[gr.epoch & 1] = gr.epoch;
+    if (op > 2) gr.ctl->reject = gr.epoch;
   }
   if (lane == 0 && wave >= 1) group_prf(gr, wave - 1);
   if (fa.tlog_r && threadIdx.x < 5) fa.tlog_r[threadIdx.x] = kNone;  // the batch's trace words
@@ -1721,7 +1696,7 @@ __global__ __launch_bounds__(kSoloNT) void k_acc_solo(GroupArgs gr, FetchArgs fa
   compose_slot<false>(wa, wave, sdyn + (uint64_t)wave * (wb_stride / 8));
   solo_step();
   // the insert and the counters; the rebuild of slot s adds to bucket s only
-  if (threadIdx.x == 0 && fn.ctl->reject[fn.epoch & 1] != fn.epoch) {
+  if (threadIdx.x == 0 && fn.ctl->reject != fn.epoch) {
     const bool ok = !fn.ctl->err;
     if (ok) finish_cmd(fn, 0);
     const uint64_t freed = (uint64_t)fn.freed[0] + fn.freed[1] + fn.freed[2];
@@ -1768,15 +1743,6 @@ static void plan_access(bolt_map* m, const uint8_t* ops, const uint64_t* keys, c
   const Sizes& s = m->s;
   const BatchScratch& bs = m->bs;
   const uint32_t epoch = (uint32_t)(m->batches + 1);
-  // the dedup's outputs alternate between two halves by batch parity, so
-  // that a batch sequence can run a batch's dedup beside the one before it
-  const uint64_t half = (uint64_t)(epoch & 1) * kMaxBatch;
-  uint32_t* const leader = bs.leader + half;
-  uint32_t* const prevw = bs.prevw + half;
-  uint32_t* const lastw = bs.lastw + half;
-  uint2* const fpair = bs.fpair + half;
-  uint2* const rpair = bs.rpair + half;
-  uint4* const rows = bs.rows + half;
   const bool fast = q <= (s.B + 15) / 16 && q <= (s.R + 15) / 16;
   uint32_t* tlog_r = nullptr;
   uint32_t* tlog_w = nullptr;
@@ -1803,15 +1769,15 @@ static void plan_access(bolt_map* m, const uint8_t* ops, const uint64_t* keys, c
   const uint64_t* vin = reinterpret_cast<const uint64_t*>(vals_in);
   const uint64_t* fval = reinterpret_cast<const uint64_t*>(bs.fval);
 
-  P.gr = GroupArgs{ops, keys, q, epoch, s.B, s.R, m->ctl, leader, prevw, lastw, fpair, rpair, rows};
+  P.gr = GroupArgs{ops, keys, q, epoch, s.B, s.R, m->ctl, bs.leader, bs.prevw, bs.lastw, bs.fpair, bs.rpair, bs.rows};
 
   FetchArgs& fa = P.fa;
   fa.ctl = m->ctl;
   fa.ops = ops;
   fa.keys = keys;
-  fa.leader = leader;
-  fa.fpair = fpair;
-  fa.rows = rows;
+  fa.leader = bs.leader;
+  fa.fpair = bs.fpair;
+  fa.rows = bs.rows;
   fa.q = q;
   fa.epoch = epoch;
   fa.B = s.B;
@@ -1842,7 +1808,7 @@ static void plan_access(bolt_map* m, const uint8_t* ops, const uint64_t* keys, c
   fa.hslot = bs.hslot;
   fa.found = bs.found;
   fa.fval = reinterpret_cast<uint64_t*>(bs.fval);
-  fa.rpair = rpair;
+  fa.rpair = bs.rpair;
   fa.tlog_r = tlog_r;
   fa.ctlw = m->ctl;
   fa.tags = reinterpret_cast<const uint64_t*>(m->tags);
@@ -1866,15 +1832,15 @@ static void plan_access(bolt_map* m, const uint8_t* ops, const uint64_t* keys, c
   rv.ship_blocks = 0;
   rv.ops = ops;
   rv.vals_in = vin;
-  rv.leader = leader;
-  rv.prevw = prevw;
-  rv.lastw = lastw;
+  rv.leader = bs.leader;
+  rv.prevw = bs.prevw;
+  rv.lastw = bs.lastw;
   rv.hit = bs.hit;
   rv.hrow = bs.hrow;
   rv.hslot = bs.hslot;
   rv.found = bs.found;
   rv.fval = fval;
-  rv.rpair = rpair;
+  rv.rpair = bs.rpair;
   rv.load = m->load;
   rv.q = q;
   rv.vw = vw;
@@ -1893,14 +1859,14 @@ static void plan_access(bolt_map* m, const uint8_t* ops, const uint64_t* keys, c
   pa.ship_blocks = 0;
   pa.keys = keys;
   pa.vals_in = vin;
-  pa.leader = leader;
-  pa.lastw = lastw;
+  pa.leader = bs.leader;
+  pa.lastw = bs.lastw;
   pa.fin = bs.fin;
   pa.chosen = bs.chosen;
   pa.hrow = bs.hrow;
   pa.hslot = bs.hslot;
   pa.fval = fval;
-  pa.rpair = rpair;
+  pa.rpair = bs.rpair;
   pa.q = q;
   pa.epoch = epoch;
   pa.Z = (uint32_t)s.Z;
@@ -1923,7 +1889,7 @@ static void plan_access(bolt_map* m, const uint8_t* ops, const uint64_t* keys, c
   pa.pm_pair = m->pm_pair;
   pa.pm_mask = m->pm_mask;
   pa.rowsel = bs.rowsel;
-  pa.rows = rows;
+  pa.rows = bs.rows;
   pa.decomp = decomp;
   pa.ring = m->ring;
   pa.P = s.P;
@@ -1933,13 +1899,13 @@ static void plan_access(bolt_map* m, const uint8_t* ops, const uint64_t* keys, c
   ra.ctl = m->ctl;
   ra.keys = keys;
   ra.vals_in = vin;
-  ra.leader = leader;
-  ra.lastw = lastw;
+  ra.leader = bs.leader;
+  ra.lastw = bs.lastw;
   ra.fin = bs.fin;
   ra.hrow = bs.hrow;
   ra.hslot = bs.hslot;
   ra.fval = fval;
-  ra.rpair = rpair;
+  ra.rpair = bs.rpair;
   ra.q = q;
   ra.epoch = epoch;
   ra.Z = (uint32_t)s.Z;
@@ -1963,7 +1929,7 @@ static void plan_access(bolt_map* m, const uint8_t* ops, const uint64_t* keys, c
   ra.pm_key = m->pm_key;
   ra.pm_pair = m->pm_pair;
   ra.pm_mask = m->pm_mask;
-  ra.rows = rows;
+  ra.rows = bs.rows;
   ra.decomp = decomp;
   ra.ring = m->ring;
   ra.P = s.P;
@@ -2021,7 +1987,7 @@ static void plan_access(bolt_map* m, const uint8_t* ops, const uint64_t* keys, c
   fn.rfree_n = bs.rfree_n;
   fn.rowsel = fast ? bs.rowsel : nullptr;
   fn.keys = keys;
-  fn.rpair = rpair;
+  fn.rpair = bs.rpair;
   fn.freed = bs.freed;
   fn.pm_key = m->pm_key;
   fn.pm_pair = m->pm_pair;
@@ -2159,10 +2125,6 @@ static int run_access_graph(bolt_map* m, AccessPlan& P, hipStream_t st) {
   return BOLT_OK;
 }
 
-static void take_slices(bolt_map* m, AccessPlan& P, bool defer, bool group_slice);
-static void launch_group(bolt_map* m, const AccessPlan& P, uint32_t q, hipStream_t st);
-static void launch_after_group(bolt_map* m, AccessPlan& P, uint32_t q, bool defer, hipStream_t st);
-
 int run_access(bolt_map* m, const uint8_t* ops, const uint64_t* keys, const void* vals_in, void* vals_out,
                uint8_t* status, uint32_t q, hipStream_t st) {
   // A batch of one command on a plain map runs as one workgroup (k_acc_solo,
@@ -2195,126 +2157,47 @@ int run_access(bolt_map* m, const uint8_t* ops, const uint64_t* keys, const void
       hipLaunchKernelGGL(k_acc_watch, dim3(1), dim3(1024), 0, st, m->load, m->s.B, m->s.K, m->ctl);
     return rc;
   }
+  const AccessPlan* none = nullptr;
   allow_group_lds();
   // A large batch on a pinned host store rebuilds its observable pages into
   // its half of the outbox, and the next batch's kernels (or a flush) send
   // them.  Small batches and device stores, with no link time to hide, write
   // them from the rebuild.
   const bool defer = m->obs_host && q >= kDeferMinBatch;
-  take_slices(m, P, defer, true);
-  launch_group(m, P, q, st);
-  launch_after_group(m, P, q, defer, st);
-  return hipGetLastError() == hipSuccess ? BOLT_OK : BOLT_EHIP;
-}
-
-// Sets ctl->spec[slot] to the tape position after the current one plus q
-// (the first batch of a sequence: the second batch's dedup starts there).
-__global__ void k_spec_init(Ctl* ctl, uint32_t slot, uint32_t q) { ctl->spec[slot] = ctl->steps + q; }
-
-int run_access_seq(bolt_map* m, const uint8_t* ops, const uint64_t* keys, const void* vals_in, void* vals_out,
-                   uint8_t* status, const uint32_t* qs, uint32_t nb, hipStream_t st) {
-  // Batches of a sequence run one after another as separate batches do,
-  // except that batch b + 1's dedup and PRFs run on the map's side stream
-  // beside batch b's fetch .. finish.  Its outputs use the other half of the
-  // dedup buffers (by batch parity), its reject flag the other slot, and
-  // its tape positions start where batch b's end, if batch b is accepted;
-  // the fetch redoes the tape pairs when it was not.  The side stream waits
-  // for batch b - 1's end (the half and slot it reuses) and the main stream
-  // for the dedup before batch b + 1's fetch.
-  if (nb == 1 || (m->p.flags & BOLT_F_GRAPHS)) {
-    uint64_t off = 0;
-    for (uint32_t b = 0; b < nb; ++b) {
-      const int rc = run_access(m, ops + off, keys + off, reinterpret_cast<const uint8_t*>(vals_in) + off * m->s.vs,
-                                reinterpret_cast<uint8_t*>(vals_out) + off * m->s.vs, status + off, qs[b], st);
-      if (rc) return rc;
-      off += qs[b];
+  // The previous batch's rebuilt pages still to be sent, in slices: plain
+  // maps spread them over this batch's dedup, resolve and place kernels
+  // (each running anyway), the fetch takes the rest (writes over the link
+  // while it reads).
+  {
+    const uint32_t end = 2 * m->ship_q;
+    uint32_t lo = m->ship_from < end ? m->ship_from : end;
+    auto take = [&](uint32_t share, ShipArgs& a, uint32_t& blocks, uint32_t waves_per_block, uint32_t max_waves) {
+      const uint32_t n = end * share / 64, hi = lo + n < end ? lo + n : end;
+      a = ship_args(m, lo, hi);
+      blocks = (hi - lo + waves_per_block - 1) / waves_per_block;
+      if (blocks > max_waves / waves_per_block) blocks = max_waves / waves_per_block;
+      lo = hi;
+    };
+    if (end && !m->tags) {
+      take(kShareGroup, P.gr.ship, P.gr.ship_blocks, kDedupNT / 64, 4 * kShipMaxBlocks);
+      take(kShareResolve, P.rv.ship, P.rv.ship_blocks, 1, 4 * kShipMaxBlocks);
+      if (P.fast) take(kSharePlace, P.pa.ship, P.pa.ship_blocks, 1, 4 * kShipMaxBlocks);
+      // The rebuild's one-wave workgroups, a few slots per wave (its own
+      // waves already fill the device); only when this batch rebuilds into
+      // the outbox: a rebuild that writes the store itself could race the
+      // slice on a page both write.
+      if (defer) take(kShareCompose, P.wa.ship, P.wa.ship_blocks, 1, kShipComposeWaves);
     }
-    return BOLT_OK;
+    P.fa.ship = ship_args(m, lo, end);
+    P.fa.ship_blocks = ship_blocks_for(end - lo);
+    m->ship_q = 0;
+    m->ship_from = 0;
   }
-  allow_group_lds();
-  const uint64_t vs = m->s.vs;
-  auto plan_at = [&](uint64_t off, uint32_t q, AccessPlan& P) {
-    plan_access(m, ops + off, keys + off, reinterpret_cast<const uint8_t*>(vals_in) + off * vs,
-                reinterpret_cast<uint8_t*>(vals_out) + off * vs, status + off, q, st, P);
-  };
-  AccessPlan cur, nxt;
-  uint64_t off = 0;
-  plan_at(0, qs[0], cur);
-  hipLaunchKernelGGL(k_spec_init, dim3(1), dim3(1), 0, st, m->ctl, (cur.fa.epoch + 1) & 1, qs[0]);
-  (void)hipEventRecord(m->ev_seq[0], st);
-  bool defer = m->obs_host && qs[0] >= kDeferMinBatch;
-  take_slices(m, cur, defer, true);
-  launch_group(m, cur, qs[0], st);
-  for (uint32_t b = 0; b < nb; ++b) {
-    const uint32_t q = qs[b], e = cur.fa.epoch;
-    if (b > 0) {
-      (void)hipStreamWaitEvent(st, m->ev_seq[1 + (e & 1)], 0);
-      defer = m->obs_host && q >= kDeferMinBatch;
-      take_slices(m, cur, defer, false);
-    }
-    if (b + 1 < nb) {  // batch b + 2's dedup starts after batch b + 1's commands
-      cur.fn.spec_next = 1;
-      cur.fn.next_q = qs[b + 1];
-    }
-    launch_after_group(m, cur, q, defer, st);
-    (void)hipEventRecord(m->ev_seq[3 + (e & 1)], st);
-    off += q;
-    if (b + 1 < nb) {
-      plan_at(off, qs[b + 1], nxt);
-      nxt.gr.spec = 1;
-      nxt.fa.spec = 1;
-      (void)hipStreamWaitEvent(m->side, b == 0 ? m->ev_seq[0] : m->ev_seq[3 + ((e - 1) & 1)], 0);
-      launch_group(m, nxt, qs[b + 1], m->side);
-      (void)hipEventRecord(m->ev_seq[1 + ((e + 1) & 1)], m->side);
-      cur = nxt;
-    }
+  {
+    TimedScope ts(m->timer, kkAccDedup, st);
+    hipLaunchKernelGGL(k_acc_group<false>, dim3(P.gr.ship_blocks + kParts + group_prf_blocks(q)), dim3(kDedupNT),
+                       group_lds_bytes(q), st, P.gr, none);
   }
-  return hipGetLastError() == hipSuccess ? BOLT_OK : BOLT_EHIP;
-}
-
-// Splits the previous batch's rebuilt pages still to be sent into slices:
-// plain maps spread them over this batch's dedup (when `group_slice`),
-// resolve, place and rebuild kernels (each running anyway), the fetch takes
-// the rest (writes over the link while it reads).
-static void take_slices(bolt_map* m, AccessPlan& P, bool defer, bool group_slice) {
-  const uint32_t end = 2 * m->ship_q;
-  uint32_t lo = m->ship_from < end ? m->ship_from : end;
-  auto take = [&](uint32_t share, ShipArgs& a, uint32_t& blocks, uint32_t waves_per_block, uint32_t max_waves) {
-    const uint32_t n = end * share / 64, hi = lo + n < end ? lo + n : end;
-    a = ship_args(m, lo, hi);
-    blocks = (hi - lo + waves_per_block - 1) / waves_per_block;
-    if (blocks > max_waves / waves_per_block) blocks = max_waves / waves_per_block;
-    lo = hi;
-  };
-  if (end && !m->tags) {
-    if (group_slice) take(kShareGroup, P.gr.ship, P.gr.ship_blocks, kDedupNT / 64, 4 * kShipMaxBlocks);
-    take(kShareResolve, P.rv.ship, P.rv.ship_blocks, 1, 4 * kShipMaxBlocks);
-    if (P.fast) take(kSharePlace, P.pa.ship, P.pa.ship_blocks, 1, 4 * kShipMaxBlocks);
-    // The rebuild's one-wave workgroups, a few slots per wave (its own
-    // waves already fill the device); only when this batch rebuilds into
-    // the outbox: a rebuild that writes the store itself could race the
-    // slice on a page both write.
-    if (defer) take(kShareCompose, P.wa.ship, P.wa.ship_blocks, 1, kShipComposeWaves);
-  }
-  P.fa.ship = ship_args(m, lo, end);
-  P.fa.ship_blocks = ship_blocks_for(end - lo);
-  m->ship_q = 0;
-  m->ship_from = 0;
-}
-
-// The dedup and PRFs of a batch (state-independent but for the tape
-// position).
-static void launch_group(bolt_map* m, const AccessPlan& P, uint32_t q, hipStream_t st) {
-  const AccessPlan* none = nullptr;
-  TimedScope ts(m->timer, kkAccDedup, st);
-  hipLaunchKernelGGL(k_acc_group<false>, dim3(P.gr.ship_blocks + kParts + group_prf_blocks(q)), dim3(kDedupNT),
-                     group_lds_bytes(q), st, P.gr, none);
-}
-
-// The steps of a batch after its dedup: fetch, resolve, place, rebuild,
-// finish.
-static void launch_after_group(bolt_map* m, AccessPlan& P, uint32_t q, bool defer, hipStream_t st) {
-  const AccessPlan* none = nullptr;
   {
     TimedScope ts(m->timer, kkAccFetch, st);
     const dim3 grid(P.fa.ship_blocks + (q + 3) / 4);
@@ -2358,6 +2241,7 @@ static void launch_after_group(bolt_map* m, AccessPlan& P, uint32_t q, bool defe
   }
   if (m->p.flags & BOLT_F_WATCH)
     hipLaunchKernelGGL(k_acc_watch, dim3(1), dim3(1024), 0, st, m->load, m->s.B, m->s.K, m->ctl);
+  return hipGetLastError() == hipSuccess ? BOLT_OK : BOLT_EHIP;
 }
 
 // One batch for each of `count` distinct maps, every phase one launch for

@@ -175,8 +175,7 @@ __global__ void k_pool_init(uint64_t* used, uint64_t P, uint64_t PW) {
 __global__ void k_ctl_init(Ctl* ctl) {
   if (threadIdx.x || blockIdx.x) return;
   ctl->err = 0;
-  ctl->reject[0] = 0;
-  ctl->reject[1] = 0;
+  ctl->reject = 0;
   ctl->steps = 0;
   ctl->live = 0;
   ctl->stash_live = 0;
@@ -198,8 +197,6 @@ __global__ void k_ctl_init(Ctl* ctl) {
   ctl->b_hbm_rm = 0;
   ctl->fin_done = 0;
   ctl->pad0 = 0;
-  ctl->spec[0] = 0;
-  ctl->spec[1] = 0;
 }
 
 void launch_map_init(bolt_map* m, hipStream_t st) {
