@@ -284,6 +284,7 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=60.0,
                     help="steady window of each open-loop serving run (config 5: 60 s)")
     ap.add_argument("--no-decomposed", action="store_true", help="skip the decomposed-HBM-store figures")
+    ap.add_argument("--no-config1", action="store_true", help="skip the N=2^16 per-call figures (config 1)")
     ap.add_argument("--copy-calib", type=int, default=0,
                     help="MiB of a plain device copy run first (scales profiler byte counters)")
     args = ap.parse_args()
@@ -389,6 +390,10 @@ def main():
     if not args.no_build_heavy:
         heavy = run_build_heavy(B, torch, synth, not args.no_autotune)
         log("build-heavy: %s" % json.dumps({k: v for k, v in heavy.items() if k != "phases"}))
+    cfg1 = None
+    if not args.no_config1:
+        cfg1 = run_config1(B, torch, with_oracle=not args.no_cpu_baseline)
+        log("config 1: %s" % json.dumps(cfg1))
     cpu = None if args.no_cpu_baseline else cpu_baseline(args.cpu_batches)
     sz = main_res["sizes"]
     out = {
@@ -424,9 +429,91 @@ def main():
         "build_heavy": heavy,
         "alpha_sweep": sweep,
         "serving": serving,
+        "config1_per_call": cfg1,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
+
+
+def run_config1(B, torch, with_oracle=True):
+    """Config 1: a map of N=2^16 u64 keys and values, built once, then 2^14
+    single GETs (90 % present, 10 % absent) and 2^12 single PUTs over present
+    keys.  Per-call form: each command its own call, HIP events between calls
+    on the launch stream (latency per command, ops/s over the whole run).
+    Batched form: the same commands in order, in batches of 4096, on a fresh
+    map.  Every answer of both forms is checked against a dictionary run of
+    the commands.  The oracle runs the same commands one call each on the
+    host (one thread)."""
+    import synth
+
+    wl = synth.config1()
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    ops = np.concatenate([b[0] for b in wl.batches])
+    keys = np.concatenate([b[1] for b in wl.batches])
+    vals = np.concatenate([b[2] for b in wl.batches])
+    nq = ops.size
+    # expected answers: the dictionary semantics, commands in order
+    d = {int(k): bytes(v) for k, v in zip(wl.build_keys.tolist(), wl.build_vals)}
+    want_st = np.zeros(nq, np.uint8)
+    want_v = np.zeros((nq, wl.vs), np.uint8)
+    for i in range(nq):
+        k = int(keys[i])
+        if ops[i] == 0:
+            if k in d:
+                want_st[i] = 1
+                want_v[i] = np.frombuffer(d[k], np.uint8)
+        else:
+            want_st[i] = 1 if k in d else 2
+            d[k] = bytes(vals[i])
+    d_keys = torch.from_numpy(wl.build_keys.view(np.int64)).to(dev)
+    d_vals = torch.from_numpy(wl.build_vals).to(dev)
+    d_ops = torch.from_numpy(ops).to(dev)
+    d_qk = torch.from_numpy(keys.view(np.int64)).to(dev)
+    d_qv = torch.from_numpy(vals).to(dev)
+    out = {"workload": "plain-omap-n16: N=2^16 u64 keys and values, pinned store; 2^14 single GETs (90 %% present, "
+                       "10 %% absent) then 2^12 single PUTs over present keys (%d commands), every answer checked "
+                       "against a dictionary" % nq}
+    for form in ("per_call", "batched"):
+        m = B.Map(B.params(wl.n, wl.vs))
+        B.check(m.build(d_keys, d_vals), "bolt_build")
+        d_out = torch.zeros((nq, wl.vs), dtype=torch.uint8, device=dev)
+        d_st = torch.zeros(nq, dtype=torch.uint8, device=dev)
+        torch.cuda.synchronize()
+        step = 1 if form == "per_call" else 4096
+        cuts = list(range(0, nq, step)) + [nq]
+        sl = [(d_ops[a:b], d_qk[a:b], d_qv[a:b], d_out[a:b], d_st[a:b]) for a, b in zip(cuts[:-1], cuts[1:])]
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(len(sl) + 1)]
+        ev[0].record(stream)
+        for i, a in enumerate(sl):
+            B.check(m.access(*a, stream=stream), "config 1 access")
+            ev[i + 1].record(stream)
+        B.check(m.flush(), "bolt_flush")
+        torch.cuda.synchronize()
+        B.check(m.status(), "config 1 status")
+        if not (np.array_equal(d_st.cpu().numpy(), want_st) and np.array_equal(d_out.cpu().numpy(), want_v)):
+            raise SystemExit("config 1: answers differ from the dictionary (%s)" % form)
+        total = ev[0].elapsed_time(ev[-1])
+        lat = np.array([ev[i].elapsed_time(ev[i + 1]) for i in range(len(sl))])
+        out[form] = {"calls": len(sl), "ops_per_s": round(nq / (total / 1e3), 1),
+                     "p50_ms": round(float(np.percentile(lat, 50)), 4),
+                     "p99_ms": round(float(np.percentile(lat, 99)), 4), "answers_checked": nq}
+        m.close()
+    out["batched_over_per_call"] = round(out["batched"]["ops_per_s"] / out["per_call"]["ops_per_s"], 2)
+    if with_oracle:
+        import oracle as O
+
+        t0 = time.perf_counter()
+        om = O.OracleMap(wl.n, wl.vs, key=bytes(range(32)))
+        assert om.build(wl.build_keys, wl.build_vals) == 0
+        t1 = time.perf_counter()
+        for b in wl.batches:
+            om.access(*b)
+        t2 = time.perf_counter()
+        out["cpu_oracle"] = {"kind": "oracle", "cores": 1, "build_s": round(t1 - t0, 3), "commands_s": round(t2 - t1, 3),
+                             "ops_per_s": round(nq / (t2 - t1), 1),
+                             "sample": "the whole config: build of 2^16 keys, then the %d commands one call each" % nq}
+    return out
 
 
 def run_alpha_sweep(B, torch, wl, dev_t, nb_max=64, alphas=(10, 200, 500, 800)):
