@@ -442,7 +442,7 @@ int bolt_server_destroy(bolt_server* srv);
  *
  * Per array-length class 2^L (and device), the sort's tile (2^11, 2^12 or
  * 2^13 elements; the last runs in registers), the strides fused per global
- * sort pass (1..4) and the stages fused per global expansion pass (1..4).
+ * sort pass (1..6) and the stages fused per global expansion pass (1..4).
  * Defaults: 13, 4, 4.  No choice changes any result, and every network's
  * memory accesses still depend on the array length alone; only speed
  * differs.  The table is per process and device.
