@@ -81,7 +81,7 @@ uint64_t device_bytes(const bolt_params* p, const Sizes& s) {
   uint64_t b = sizeof(Ctl);
   const bool decomp = (p->flags & BOLT_F_DECOMPOSED) != 0;
   if (!decomp) b += s.K * s.page_bytes;                       // HBM bins as pages
-  else b += s.P * 4 + 3ull * kMaxBatch * (2 * s.Z + 1) * 4;  // the free-address ring, staged frees
+  else b += s.P * 4 + 3ull * kMaxBatch * (2 * s.Z * 4 + 1);  // the free-address ring, staged frees
   if (p->observable == BOLT_OBS_DEVICE) b += s.M * (s.page_bytes + ((p->flags & BOLT_F_SEAL) ? 16 : 0));
   if (p->flags & BOLT_F_SEAL) b += s.M * 8;  // write counts
   b += s.B * 4;                      // load
@@ -283,7 +283,7 @@ int bolt_create(const bolt_params* p, void* hip_stream, bolt_map** out) {
   rc = rc ? rc : dalloc(m, &b.rows, Q * 16);
   if (p->flags & BOLT_F_DECOMPOSED) {
     rc = rc ? rc : dalloc(m, &b.rfree, 3 * Q * 2 * s.Z * 4);
-    rc = rc ? rc : dalloc(m, &b.rfree_n, 3 * Q * 4);
+    rc = rc ? rc : dalloc(m, &b.rfree_n, 3 * Q);
   }
   rc = rc ? rc : dalloc(m, &m->get_ops, Q);
   rc = rc ? rc : dalloc(m, &m->put_ops, Q);

@@ -34,7 +34,7 @@ struct BatchScratch {
   uint2* fpair;       // [Q] fetch pair F(s) of each command
   uint4* rows;        // [Q] position-map rows of each command's key
   uint32_t* rfree;    // BOLT_F_DECOMPOSED: [3Q][2Z] pool entries each rebuild slot returns to the ring
-  uint32_t* rfree_n;  // BOLT_F_DECOMPOSED: [3Q] how many
+  uint8_t* rfree_n;   // BOLT_F_DECOMPOSED: [3Q] how many (bytes: at most 2Z <= 124)
 };
 
 struct TraceSeg {

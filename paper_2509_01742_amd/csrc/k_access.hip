@@ -231,7 +231,7 @@ struct WbArgs {
   uint32_t ship_blocks;
   uint32_t decomp;  // BOLT_F_DECOMPOSED: HBM bins keep their items listed; frees are staged for the ring
   uint32_t* rfree;    // [3Q][2Z] entries each rebuild slot returns to the ring
-  uint32_t* rfree_n;  // [3Q] how many
+  uint8_t* rfree_n;   // [3Q] how many (at most 2Z <= 124)
 };
 
 
@@ -253,7 +253,7 @@ struct FinishArgs {
   uint32_t* ring;
   uint64_t P;
   const uint32_t* rfree;    // [3Q][2Z]
-  const uint32_t* rfree_n;  // [3Q]
+  const uint8_t* rfree_n;   // [3Q], 16-byte aligned
 };
 
 // Every kernel argument of one map's batch.  A multi-map launch reads the
@@ -1383,7 +1383,7 @@ __device__ __forceinline__ void compose_slot(const WbArgs& a, uint32_t s, uint64
     if (lane == 0) {
       a.rmask[b] = 0;
       a.rev_cnt[b] = n_alive;
-      a.rfree_n[s] = ndead;
+      a.rfree_n[s] = (uint8_t)ndead;
       if (ndead) atomicAdd(&a.freed[s % kFreeBuckets], ndead);
     }
     return;
@@ -1443,7 +1443,7 @@ __device__ __forceinline__ void compose_slot(const WbArgs& a, uint32_t s, uint64
       pool_free(a.st_used, e);
   }
   if (lane == 0) {
-    if (a.decomp) a.rfree_n[s] = cnt;
+    if (a.decomp) a.rfree_n[s] = (uint8_t)cnt;
     a.rmask[b] = 0;
     a.rev_cnt[b] = 0;
     if (cnt) atomicAdd(&a.freed[s % kFreeBuckets], cnt);
@@ -1556,17 +1556,24 @@ __device__ __forceinline__ void ring_return(const FinishArgs& a, uint32_t bid, u
     if (threadIdx.x == 0) set_err(a.ctl, kErrOverflow);
     return;
   }
-  // entries of the slots before the range: eight loads in flight per thread
-  uint32_t acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-  uint32_t s = threadIdx.x;
-  for (; s + 7 * 256 < lo; s += 8 * 256) {
+  // entries of the slots before the range: the counts are bytes, summed
+  // sixteen per load, four loads in flight per thread
+  const uint4* c16 = reinterpret_cast<const uint4*>(a.rfree_n);
+  auto bytes4 = [](uint32_t x) {
+    const uint32_t v = (x & 0x00FF00FFu) + ((x >> 8) & 0x00FF00FFu);
+    return (v & 0xFFFFu) + (v >> 16);
+  };
+  auto bytes16 = [&](const uint4 v) { return bytes4(v.x) + bytes4(v.y) + bytes4(v.z) + bytes4(v.w); };
+  const uint32_t full = lo >> 4;
+  uint32_t acc[4] = {0, 0, 0, 0};
+  uint32_t ci = threadIdx.x;
+  for (; ci + 3 * 256 < full; ci += 4 * 256) {
 #pragma unroll
-    for (int k = 0; k < 8; ++k) acc[k] += a.rfree_n[s + k * 256];
+    for (int k = 0; k < 4; ++k) acc[k] += bytes16(c16[ci + k * 256]);
   }
-  for (; s < lo; s += 256) acc[0] += a.rfree_n[s];
-  uint32_t before = 0;
-#pragma unroll
-  for (int k = 0; k < 8; ++k) before += acc[k];
+  for (; ci < full; ci += 256) acc[0] += bytes16(c16[ci]);
+  for (uint32_t s = (full << 4) + threadIdx.x; s < lo; s += 256) acc[1] += a.rfree_n[s];
+  const uint32_t before = acc[0] + acc[1] + acc[2] + acc[3];
   block_excl<256, false>(before, &tot);
   const uint64_t at = a.ctl->ring_tail + tot;  // the tail moves only when the last workgroup is done
   // the range's counts, three consecutive slots per thread, and their offsets
