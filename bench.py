@@ -285,6 +285,8 @@ def main():
                     help="steady window of each open-loop serving run (config 5: 60 s)")
     ap.add_argument("--no-decomposed", action="store_true", help="skip the decomposed-HBM-store figures")
     ap.add_argument("--no-config1", action="store_true", help="skip the N=2^16 per-call figures (config 1)")
+    ap.add_argument("--build-heavy-only", action="store_true",
+                    help="run only config 3 (the N=2^26 build), for counter profiles")
     ap.add_argument("--copy-calib", type=int, default=0,
                     help="MiB of a plain device copy run first (scales profiler byte counters)")
     args = ap.parse_args()
@@ -305,6 +307,16 @@ def main():
                                     "long uniform access stream", "dynamics": res}), flush=True)
         return
     dev = torch.device("cuda:0")
+    if args.build_heavy_only:  # config 3 alone (for counter profiles of the N=2^26 build)
+        if args.copy_calib:
+            src = torch.empty(args.copy_calib << 20, dtype=torch.uint8, device=dev).fill_(1)
+            torch.empty_like(src).copy_(src)
+            torch.cuda.synchronize()
+            del src
+            log("copy calibration: %d MiB device-to-device" % args.copy_calib)
+        heavy = run_build_heavy(B, torch, synth, not args.no_autotune)
+        print(json.dumps({"metric": "build keys/s at N=2^26 (config 3)", "build_heavy": heavy}), flush=True)
+        return
     n = 1 << args.n_log2
     t0 = time.time()
     wl = synth.config2(n=n, n_ops=args.ops, batch=args.batch)
