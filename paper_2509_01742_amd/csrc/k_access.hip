@@ -1148,6 +1148,10 @@ __global__ __launch_bounds__(256) void k_acc_place(PlaceArgs a1, const AccessPla
 
 constexpr uint32_t kRemapNT = 1024;
 constexpr uint32_t kRemapPer = kMaxBatch / kRemapNT;
+// Maps of at most this many bins keep their loads in LDS through the P2C
+// rounds of a several-round batch (a round holds ceil(B/16) keys, so small
+// maps run many rounds: up to 1024 for a batch of 8192 on 128 bins).
+constexpr uint32_t kRemapLdsBins = 8192;
 
 
 
@@ -1179,8 +1183,17 @@ __global__ __launch_bounds__(kRemapNT) void k_acc_remap(RemapArgs a1, const Acce
   block_excl<kRemapNT, false>(ndel_mine, &tot);
   const uint32_t ndel = tot;
   __syncthreads();
-  // P2C in rounds of ceil(B/16) over the post-removal loads (Sec. 5.1 step 5)
+  // P2C in rounds of ceil(B/16) over the post-removal loads (Sec. 5.1 step 5).
+  // A small map's loads live in LDS meanwhile (the only writer of this map's
+  // loads in this launch is this workgroup), and go back at the end.
   const uint64_t rs = (a.B + 15) / 16;
+  __shared__ uint32_t s_load[kRemapLdsBins];
+  const bool lds_loads = a.B <= kRemapLdsBins && nplace > rs;  // the same for the whole workgroup
+  uint32_t* const lp = lds_loads ? s_load : a.load;
+  if (lds_loads) {
+    for (uint32_t b = threadIdx.x; b < a.B; b += kRemapNT) s_load[b] = ld_acq32(&a.load[b]);
+    __syncthreads();
+  }
   uint32_t chosen[kRemapPer];
   for (uint64_t r0 = 0; r0 < nplace; r0 += rs) {
     uint32_t o = place0;
@@ -1188,7 +1201,8 @@ __global__ __launch_bounds__(kRemapNT) void k_acc_remap(RemapArgs a1, const Acce
       if (!(fin[t] & 1)) continue;
       if (o >= r0 && o < r0 + rs) {
         const uint2 rp = a.rpair[i0 + t];
-        const uint32_t l1 = ld_acq32(&a.load[rp.x]), l2 = ld_acq32(&a.load[rp.y]);
+        const uint32_t l1 = lds_loads ? s_load[rp.x] : ld_acq32(&a.load[rp.x]);
+        const uint32_t l2 = lds_loads ? s_load[rp.y] : ld_acq32(&a.load[rp.y]);
         chosen[t] = l2 < l1 ? rp.y : rp.x;
       }
       ++o;
@@ -1198,11 +1212,16 @@ __global__ __launch_bounds__(kRemapNT) void k_acc_remap(RemapArgs a1, const Acce
     for (uint32_t t = 0; t < kRemapPer; ++t) {
       if (!(fin[t] & 1)) continue;
       if (o >= r0 && o < r0 + rs) {
-        const uint32_t old = atomicAdd(&a.load[chosen[t]], 1u);
+        const uint32_t old = atomicAdd(&lp[chosen[t]], 1u);
         if (old + 1 > a.Z) set_err(a.ctl, kErrOverflow);
       }
       ++o;
     }
+    if (!lds_loads) __threadfence();
+    __syncthreads();
+  }
+  if (lds_loads) {
+    for (uint32_t b = threadIdx.x; b < a.B; b += kRemapNT) a.load[b] = s_load[b];
     __threadfence();
     __syncthreads();
   }
