@@ -1150,8 +1150,9 @@ constexpr uint32_t kRemapNT = 1024;
 constexpr uint32_t kRemapPer = kMaxBatch / kRemapNT;
 // Maps of at most this many bins keep their loads in LDS through the P2C
 // rounds of a several-round batch (a round holds ceil(B/16) keys, so small
-// maps run many rounds: up to 1024 for a batch of 8192 on 128 bins).
-constexpr uint32_t kRemapLdsBins = 8192;
+// maps run many rounds: up to 1024 for a batch of 8192 on 128 bins).  With
+// the round list beside it the workgroup stays within 64 KiB of LDS.
+constexpr uint32_t kRemapLdsBins = 7936;
 
 
 
@@ -1195,7 +1196,47 @@ __global__ __launch_bounds__(kRemapNT) void k_acc_remap(RemapArgs a1, const Acce
     __syncthreads();
   }
   uint32_t chosen[kRemapPer];
-  for (uint64_t r0 = 0; r0 < nplace; r0 += rs) {
+  // Rounds of at most 64 keys (maps of at most 1024 bins) run on wave 0
+  // alone, one key per lane, with no workgroup barrier per round: the keys'
+  // pairs (packed, bins < 2^16) go to an LDS list in placement order, the
+  // wave reads a round's loads in one instruction before it adds (a wave's
+  // LDS operations complete in order), and each key's chosen bin goes back
+  // into its list entry for the thread that holds the command.
+  __shared__ uint32_t s_list[kMaxBatch];
+  const bool wave_rounds = lds_loads && rs <= 64;  // the same for the whole workgroup
+  if (wave_rounds) {
+    uint32_t o = place0;
+    for (uint32_t t = 0; t < kRemapPer; ++t) {
+      if (!(fin[t] & 1)) continue;
+      const uint2 rp = a.rpair[i0 + t];
+      s_list[o++] = rp.x | (rp.y << 16);
+    }
+    __syncthreads();
+    if (threadIdx.x < 64) {
+      const uint32_t lane = threadIdx.x;
+      for (uint32_t r0 = 0; r0 < nplace; r0 += (uint32_t)rs) {
+        const uint32_t k = r0 + lane;
+        const bool mine = lane < rs && k < nplace;
+        uint32_t ch = 0;
+        if (mine) {
+          const uint32_t pk = s_list[k], p1 = pk & 0xFFFFu, p2 = pk >> 16;
+          ch = s_load[p2] < s_load[p1] ? p2 : p1;
+        }
+        __builtin_amdgcn_wave_barrier();
+        if (mine) {
+          const uint32_t old = atomicAdd(&s_load[ch], 1u);
+          if (old + 1 > a.Z) set_err(a.ctl, kErrOverflow);
+          s_list[k] = ch;
+        }
+        __builtin_amdgcn_wave_barrier();
+      }
+    }
+    __syncthreads();
+    o = place0;
+    for (uint32_t t = 0; t < kRemapPer; ++t)
+      if (fin[t] & 1) chosen[t] = s_list[o++];
+  }
+  for (uint64_t r0 = 0; r0 < (wave_rounds ? 0 : nplace); r0 += rs) {
     uint32_t o = place0;
     for (uint32_t t = 0; t < kRemapPer; ++t) {
       if (!(fin[t] & 1)) continue;
