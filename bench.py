@@ -242,8 +242,8 @@ def measured_traffic(cls, mode):
     k = kern.get(name) if name else None
     if k is None:
         return None
-    return {"fetch_bytes": round(k["fetch_bytes"]), "write_bytes": round(k["write_bytes"]),
-            "bytes": round(k["fetch_bytes"] + k["write_bytes"]), "kernel": name, "grid": k["grid"],
+    fb, wb = round(k["fetch_bytes"]), round(k["write_bytes"])
+    return {"fetch_bytes": fb, "write_bytes": wb, "bytes": fb + wb, "kernel": name, "grid": k["grid"],
             "source": "profiles/traffic_plain_omap_n24_v64.md"}
 
 
