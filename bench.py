@@ -287,6 +287,8 @@ def main():
     ap.add_argument("--no-config1", action="store_true", help="skip the N=2^16 per-call figures (config 1)")
     ap.add_argument("--build-heavy-only", action="store_true",
                     help="run only config 3 (the N=2^26 build), for counter profiles")
+    ap.add_argument("--multi-only", action="store_true",
+                    help="run only config 4 (64 maps in many-map calls against one-map calls), for kernel profiles")
     ap.add_argument("--copy-calib", type=int, default=0,
                     help="MiB of a plain device copy run first (scales profiler byte counters)")
     args = ap.parse_args()
@@ -316,6 +318,10 @@ def main():
             log("copy calibration: %d MiB device-to-device" % args.copy_calib)
         heavy = run_build_heavy(B, torch, synth, not args.no_autotune)
         print(json.dumps({"metric": "build keys/s at N=2^26 (config 3)", "build_heavy": heavy}), flush=True)
+        return
+    if args.multi_only:  # config 4 alone (for kernel profiles of the many-map calls)
+        print(json.dumps({"metric": "many-map build keys/s and access ops/s (config 4)",
+                          "multi_map": run_multi(B, torch)}), flush=True)
         return
     n = 1 << args.n_log2
     t0 = time.time()

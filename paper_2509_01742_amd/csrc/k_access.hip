@@ -135,7 +135,10 @@ struct ResolveArgs {
 };
 
 struct PlaceArgs {
-  uint32_t enabled;  // this map's batch takes the one-round path
+  // The batch takes the several-round path: k_acc_remap chose the bins and
+  // added the loads (rounds of ceil(B/16)), and puts the inserts in their
+  // rows (rounds of ceil(R/16)) after this kernel.
+  uint32_t several;
   Ctl* ctl;
   const uint64_t* keys;
   const uint64_t* vals_in;
@@ -173,6 +176,7 @@ struct PlaceArgs {
 struct RemapArgs {
   uint32_t enabled;  // this map's batch takes the several-round path
   Ctl* ctl;
+  uint32_t* chosen;  // [Q] each placed key's bin, for k_acc_place
   const uint64_t* keys;
   const uint64_t* vals_in;
   const uint32_t* leader;
@@ -1044,37 +1048,13 @@ __global__ __launch_bounds__(256) void k_acc_resolve(ResolveArgs a1, const Acces
 }
 
 // ---------------------------------------------------------------------------
-// place (one-round case): P2C loads, stash entries, position-map updates and
-// the row of every insert (one thread per command)
+// place: stash entries, position-map updates, and in the one-round case the
+// P2C loads and the row of every insert (one thread per command)
 // ---------------------------------------------------------------------------
 
 
 
-// Stores an item in a fresh stash entry listed under bin b.
-__device__ __forceinline__ bool stash_put(const RemapArgs& a, uint32_t i, uint64_t key, const uint64_t* val,
-                                          uint32_t b) {
-  uint64_t* const st_key = a.st_key;
-  uint64_t* const st_val = a.st_val;
-  uint32_t* const st_dest = a.st_dest;
-  uint32_t* const st_dead = a.st_dead;
-  uint32_t* const rev_cnt = a.rev_cnt;
-  uint32_t* const rev_idx = a.rev_idx;
-  const uint32_t Z = a.Z, vw = a.vw;
-  const uint32_t e = a.decomp ? ring_alloc(a.ctl, a.ring, a.P) : pool_alloc(a.st_used, a.PW, alloc_hash(a.epoch, i),
-                                                                             (uint32_t)a.PW);
-  if (e == kNone) return false;
-  st_key[e] = key;
-  for (uint32_t x = 0; x < vw; ++x) st_val[(uint64_t)e * vw + x] = val[x];
-  st_dest[e] = b;
-  st_dead[e] = 0;
-  const uint32_t ls = atomicAdd(&rev_cnt[b], 1u);
-  if (ls >= 2 * Z) return false;
-  rev_idx[(uint64_t)b * 2 * Z + ls] = e;
-  return true;
-}
-
-// Command i's placement (one-round case), by one thread; every lane of the
-// wave calls it.
+// Command i's placement, by one thread; every lane of the wave calls it.
 __device__ __forceinline__ void place_cmd(const PlaceArgs& a, uint32_t i) {
   if (a.ctl->reject == a.epoch || a.ctl->err) return;
   bool placed = false, ins = false, to_hbm = false;
@@ -1089,7 +1069,7 @@ __device__ __forceinline__ void place_cmd(const PlaceArgs& a, uint32_t i) {
       const uint32_t b = a.chosen[i];
       const uint32_t lw = a.lastw[i];
       const uint64_t key = a.keys[i];
-      const uint32_t old = atomicAdd(&a.load[b], 1u);
+      const uint32_t old = a.several ? 0 : atomicAdd(&a.load[b], 1u);
       const uint32_t ls = atomicAdd(&a.rev_cnt[b], 1u);
       if (b < a.K && !a.decomp) {  // HBM bins are rebuilt in this batch
         a.cand_bin[2 * a.q + i] = b;
@@ -1098,7 +1078,7 @@ __device__ __forceinline__ void place_cmd(const PlaceArgs& a, uint32_t i) {
       to_hbm = a.decomp && b < a.K;  // a decomposed HBM bin keeps the entry listed
       if (fin & 2) {
         a.pm_pair[(uint64_t)a.hrow[i] * a.W + a.hslot[i]] = a.rpair[i];
-      } else {
+      } else if (!a.several) {
         // insert: the least loaded of d rows after this batch's deletes
         const uint4 rw = a.rows[i];
         uint32_t best = rw.x;
@@ -1125,12 +1105,14 @@ __device__ __forceinline__ void place_cmd(const PlaceArgs& a, uint32_t i) {
         a.st_dead[e] = 0;
         if (ls < 2 * a.Z) a.rev_idx[(uint64_t)b * 2 * a.Z + ls] = e;
       }
-      if (old + 1 > a.Z || e == kNone || ls >= 2 * a.Z) set_err(a.ctl, kErrOverflow);
+      if ((!a.several && old + 1 > a.Z) || e == kNone || ls >= 2 * a.Z) set_err(a.ctl, kErrOverflow);
       placed = true;
     }
   }
-  wave_count(&a.ctl->b_place, placed);
-  wave_count(&a.ctl->b_ins, ins);
+  if (!a.several) {  // k_acc_remap counts the several-round path's
+    wave_count(&a.ctl->b_place, placed);
+    wave_count(&a.ctl->b_ins, ins);
+  }
   if (a.decomp) wave_count(&a.ctl->b_hbm_in, to_hbm);
 }
 
@@ -1138,26 +1120,31 @@ template <bool MULTI>
 __global__ __launch_bounds__(256) void k_acc_place(PlaceArgs a1, const AccessPlan* tab) {
   BOLT_PICK(PlaceArgs, pa);
   if (carry_ship<MULTI>(a.ship, a.ship_blocks)) return;
-  if (!a.enabled) return;
   place_cmd(a, (blockIdx.x - (MULTI ? 0 : a.ship_blocks)) * blockDim.x + threadIdx.x);
 }
 
 // ---------------------------------------------------------------------------
-// remap, several rounds (one workgroup): the same steps in round order
+// remap, several rounds (one workgroup): the steps that go in rounds, in
+// round order.  Phase 0: P2C in rounds of ceil(B/16) (each placed key's bin
+// to `chosen`, its load added) and the deletes, before k_acc_place; phase
+// 1: the inserts in rounds of ceil(R/16), after it.
 // ---------------------------------------------------------------------------
 
 constexpr uint32_t kRemapNT = 1024;
 constexpr uint32_t kRemapPer = kMaxBatch / kRemapNT;
-// Maps of at most this many bins keep their loads in LDS through the P2C
-// rounds of a several-round batch (a round holds ceil(B/16) keys, so small
-// maps run many rounds: up to 1024 for a batch of 8192 on 128 bins).  With
-// the round list beside it the workgroup stays within 64 KiB of LDS.
-constexpr uint32_t kRemapLdsBins = 7936;
+// Maps of at most this many bins keep their loads in dynamic LDS through
+// the P2C rounds of a several-round batch (a round holds ceil(B/16) keys, so
+// small maps run many rounds: up to 1024 for a batch of 8192 on 128 bins),
+// and one wave runs the rounds, at most kWaveKeys keys per lane.  With the
+// round list beside it the workgroup holds 128 KiB of LDS.
+constexpr uint32_t kRemapLdsBins = 24576;
+constexpr uint32_t kWaveKeys = (kRemapLdsBins / 16 + 63) / 64;  // 24
 
 
 
 template <bool MULTI>
-__global__ __launch_bounds__(kRemapNT) void k_acc_remap(RemapArgs a1, const AccessPlan* tab) {
+__global__ __launch_bounds__(kRemapNT) void k_acc_remap(RemapArgs a1, const AccessPlan* tab, uint32_t phase,
+                                                         uint32_t lds_bins) {
   BOLT_PICK(RemapArgs, ra);
   if (!a.enabled) return;
   __shared__ uint32_t tot;
@@ -1184,116 +1171,118 @@ __global__ __launch_bounds__(kRemapNT) void k_acc_remap(RemapArgs a1, const Acce
   block_excl<kRemapNT, false>(ndel_mine, &tot);
   const uint32_t ndel = tot;
   __syncthreads();
-  // P2C in rounds of ceil(B/16) over the post-removal loads (Sec. 5.1 step 5).
-  // A small map's loads live in LDS meanwhile (the only writer of this map's
-  // loads in this launch is this workgroup), and go back at the end.
-  const uint64_t rs = (a.B + 15) / 16;
-  __shared__ uint32_t s_load[kRemapLdsBins];
-  const bool lds_loads = a.B <= kRemapLdsBins && nplace > rs;  // the same for the whole workgroup
-  uint32_t* const lp = lds_loads ? s_load : a.load;
-  if (lds_loads) {
-    for (uint32_t b = threadIdx.x; b < a.B; b += kRemapNT) s_load[b] = ld_acq32(&a.load[b]);
-    __syncthreads();
-  }
-  uint32_t chosen[kRemapPer];
-  // Rounds of at most 64 keys (maps of at most 1024 bins) run on wave 0
-  // alone, one key per lane, with no workgroup barrier per round: the keys'
-  // pairs (packed, bins < 2^16) go to an LDS list in placement order, the
-  // wave reads a round's loads in one instruction before it adds (a wave's
-  // LDS operations complete in order), and each key's chosen bin goes back
-  // into its list entry for the thread that holds the command.
-  __shared__ uint32_t s_list[kMaxBatch];
-  const bool wave_rounds = lds_loads && rs <= 64;  // the same for the whole workgroup
-  if (wave_rounds) {
-    uint32_t o = place0;
-    for (uint32_t t = 0; t < kRemapPer; ++t) {
-      if (!(fin[t] & 1)) continue;
-      const uint2 rp = a.rpair[i0 + t];
-      s_list[o++] = rp.x | (rp.y << 16);
-    }
-    __syncthreads();
-    if (threadIdx.x < 64) {
-      const uint32_t lane = threadIdx.x;
-      for (uint32_t r0 = 0; r0 < nplace; r0 += (uint32_t)rs) {
-        const uint32_t k = r0 + lane;
-        const bool mine = lane < rs && k < nplace;
-        uint32_t ch = 0;
-        if (mine) {
-          const uint32_t pk = s_list[k], p1 = pk & 0xFFFFu, p2 = pk >> 16;
-          ch = s_load[p2] < s_load[p1] ? p2 : p1;
-        }
-        __builtin_amdgcn_wave_barrier();
-        if (mine) {
-          const uint32_t old = atomicAdd(&s_load[ch], 1u);
-          if (old + 1 > a.Z) set_err(a.ctl, kErrOverflow);
-          s_list[k] = ch;
-        }
-        __builtin_amdgcn_wave_barrier();
-      }
-    }
-    __syncthreads();
-    o = place0;
-    for (uint32_t t = 0; t < kRemapPer; ++t)
-      if (fin[t] & 1) chosen[t] = s_list[o++];
-  }
-  for (uint64_t r0 = 0; r0 < (wave_rounds ? 0 : nplace); r0 += rs) {
-    uint32_t o = place0;
-    for (uint32_t t = 0; t < kRemapPer; ++t) {
-      if (!(fin[t] & 1)) continue;
-      if (o >= r0 && o < r0 + rs) {
+  if (phase == 0) {
+    // P2C in rounds of ceil(B/16) over the post-removal loads (Sec. 5.1 step 5).
+    const uint64_t rs = (a.B + 15) / 16;
+    uint32_t chosen[kRemapPer];
+    // A map of at most lds_bins bins (the launch's dynamic LDS) keeps its
+    // loads in LDS meanwhile (the only writer of this map's loads in this
+    // launch is this workgroup), and one wave runs the rounds with no
+    // workgroup barrier: the keys' pairs (packed, bins < 2^16) go to an LDS
+    // list in placement order; per round the wave reads the list entries
+    // and the loads of all its keys (at most kWaveKeys per lane), then adds
+    // (a wave's LDS operations complete in order, so every read of a round
+    // sees the loads at its start); each key's chosen bin goes back into its
+    // list entry for the thread that holds the command.
+    extern __shared__ uint32_t s_load[];
+    __shared__ uint32_t s_list[kMaxBatch + 1];  // the last entry takes idle lanes' writes
+    const bool lds_loads = a.B <= lds_bins && nplace > rs;  // the same for the whole workgroup
+    if (lds_loads) {
+      for (uint32_t b = threadIdx.x; b < a.B; b += kRemapNT) s_load[b] = ld_acq32(&a.load[b]);
+      uint32_t o = place0;
+      for (uint32_t t = 0; t < kRemapPer; ++t) {
+        if (!(fin[t] & 1)) continue;
         const uint2 rp = a.rpair[i0 + t];
-        const uint32_t l1 = lds_loads ? s_load[rp.x] : ld_acq32(&a.load[rp.x]);
-        const uint32_t l2 = lds_loads ? s_load[rp.y] : ld_acq32(&a.load[rp.y]);
-        chosen[t] = l2 < l1 ? rp.y : rp.x;
+        s_list[o++] = rp.x | (rp.y << 16);
       }
-      ++o;
+      __syncthreads();
+      if (threadIdx.x < 64) {
+        // Lanes without a key read valid bins (list entries only hold bins),
+        // add zero and write to the spare last list entry.  Adds return
+        // nothing: a bin past Z during the rounds is past it after them, as
+        // loads only grow here, and is found then.
+        const uint32_t lane = threadIdx.x;
+        const uint32_t K = (uint32_t)((rs + 63) / 64);  // the same for the whole wave
+        for (uint32_t r0 = 0; r0 < nplace; r0 += (uint32_t)rs) {
+          uint32_t ch[kWaveKeys];
+          bool mine[kWaveKeys];
+#pragma unroll
+          for (uint32_t j = 0; j < kWaveKeys; ++j) {
+            if (j >= K) break;
+            const uint32_t off = j * 64 + lane, k = r0 + off;
+            mine[j] = off < rs && k < nplace;
+            const uint32_t pk = s_list[mine[j] ? k : kMaxBatch];
+            const uint32_t p1 = mine[j] ? pk & 0xFFFFu : 0, p2 = mine[j] ? pk >> 16 : 0;
+            const uint32_t l1 = s_load[p1], l2 = s_load[p2];
+            ch[j] = l2 < l1 ? p2 : p1;
+          }
+          // every read of the round before any add
+          __builtin_amdgcn_wave_barrier();
+          __builtin_amdgcn_sched_barrier(0);
+          asm volatile("" ::: "memory");
+#pragma unroll
+          for (uint32_t j = 0; j < kWaveKeys; ++j) {
+            if (j >= K) break;
+            atomicAdd(&s_load[ch[j]], mine[j] ? 1u : 0u);
+            s_list[mine[j] ? r0 + j * 64 + lane : kMaxBatch] = ch[j];
+          }
+          __builtin_amdgcn_wave_barrier();
+          __builtin_amdgcn_sched_barrier(0);
+          asm volatile("" ::: "memory");
+        }
+        bool over = false;
+        for (uint32_t b = lane; b < a.B; b += 64) over |= s_load[b] > a.Z;
+        if (over) set_err(a.ctl, kErrOverflow);
+      }
+      __syncthreads();
+      o = place0;
+      for (uint32_t t = 0; t < kRemapPer; ++t)
+        if (fin[t] & 1) chosen[t] = s_list[o++];
+      for (uint32_t b = threadIdx.x; b < a.B; b += kRemapNT) a.load[b] = s_load[b];
+    } else {
+      // The loads in global memory: the workgroup runs the rounds, its
+      // threads' keys of a round read, a barrier, then the adds.
+      for (uint64_t r0 = 0; r0 < nplace; r0 += rs) {
+        uint32_t o = place0;
+        for (uint32_t t = 0; t < kRemapPer; ++t) {
+          if (!(fin[t] & 1)) continue;
+          if (o >= r0 && o < r0 + rs) {
+            const uint2 rp = a.rpair[i0 + t];
+            const uint32_t l1 = ld_acq32(&a.load[rp.x]);
+            const uint32_t l2 = ld_acq32(&a.load[rp.y]);
+            chosen[t] = l2 < l1 ? rp.y : rp.x;
+          }
+          ++o;
+        }
+        __syncthreads();
+        o = place0;
+        for (uint32_t t = 0; t < kRemapPer; ++t) {
+          if (!(fin[t] & 1)) continue;
+          if (o >= r0 && o < r0 + rs) {
+            const uint32_t old = atomicAdd(&a.load[chosen[t]], 1u);
+            if (old + 1 > a.Z) set_err(a.ctl, kErrOverflow);
+          }
+          ++o;
+        }
+        __threadfence();
+        __syncthreads();
+      }
     }
-    __syncthreads();
-    o = place0;
+    // each placed key's bin for k_acc_place (which lists the item under it),
+    // and the deletes, which the inserts of phase 1 see
     for (uint32_t t = 0; t < kRemapPer; ++t) {
-      if (!(fin[t] & 1)) continue;
-      if (o >= r0 && o < r0 + rs) {
-        const uint32_t old = atomicAdd(&lp[chosen[t]], 1u);
-        if (old + 1 > a.Z) set_err(a.ctl, kErrOverflow);
-      }
-      ++o;
+      const uint32_t i = i0 + t;
+      if (fin[t] & 1) a.chosen[i] = chosen[t];
+      if ((fin[t] & 3) == 2) atomicAnd(&a.pm_mask[a.hrow[i]], ~(1u << a.hslot[i]));
     }
-    if (!lds_loads) __threadfence();
-    __syncthreads();
-  }
-  if (lds_loads) {
-    for (uint32_t b = threadIdx.x; b < a.B; b += kRemapNT) a.load[b] = s_load[b];
-    __threadfence();
-    __syncthreads();
-  }
-  // every remapped item goes to the stash pool, listed under its bin
-  for (uint32_t t = 0; t < kRemapPer; ++t) {
-    const uint32_t i = i0 + t;
-    if (i < a.q) a.cand_bin[2 * a.q + i] = kNone;
-    if (!(fin[t] & 1)) continue;
-    const uint32_t b = chosen[t];
-    const uint32_t lw = a.lastw[i];
-    const uint64_t* src = lw != kNone ? a.vals_in + (uint64_t)lw * a.vw : a.fval + (uint64_t)i * a.vw;
-    if (!stash_put(a, i, a.keys[i], src, b)) set_err(a.ctl, kErrOverflow);
-    if (a.decomp && b < a.K) atomicAdd(&a.ctl->b_hbm_in, 1u);  // listed under its HBM bin for good
-    if (b < a.K && !a.decomp) {  // HBM bins are rebuilt in this batch
-      a.cand_bin[2 * a.q + i] = b;
-      atomicMax((unsigned long long*)&a.claim[b], (unsigned long long)claim_tag(a.epoch, 2 * a.q + i));
+    if (threadIdx.x == 0) {
+      a.ctl->b_place = nplace;
+      a.ctl->b_ins = nins;
+      a.ctl->b_del = ndel;
     }
+    return;
   }
-  // position map: new pairs for keys that stay, deletes ...
-  for (uint32_t t = 0; t < kRemapPer; ++t) {
-    const uint32_t i = i0 + t;
-    if (!(fin[t] & 2)) continue;
-    const uint64_t at = (uint64_t)a.hrow[i] * a.W + a.hslot[i];
-    if (fin[t] & 1)
-      a.pm_pair[at] = a.rpair[i];
-    else
-      atomicAnd(&a.pm_mask[a.hrow[i]], ~(1u << a.hslot[i]));
-  }
-  __threadfence();
-  __syncthreads();
-  // ... then inserts, in rounds of ceil(R/16) that see the row loads at
+  // Phase 1: the inserts, in rounds of ceil(R/16) that see the row loads at
   // their start; the least loaded of d rows, ties to the lowest choice
   const uint64_t rsm = (a.R + 15) / 16;
   uint32_t rowsel[kRemapPer];
@@ -1329,11 +1318,6 @@ __global__ __launch_bounds__(kRemapNT) void k_acc_remap(RemapArgs a1, const Acce
     }
     __threadfence();
     __syncthreads();
-  }
-  if (threadIdx.x == 0) {
-    a.ctl->b_place = nplace;
-    a.ctl->b_ins = nins;
-    a.ctl->b_del = ndel;
   }
 }
 
@@ -1920,7 +1904,7 @@ static void plan_access(bolt_map* m, const uint8_t* ops, const uint64_t* keys, c
   rv.pm_mask = m->pm_mask;
 
   PlaceArgs& pa = P.pa;
-  pa.enabled = P.fast;
+  pa.several = !P.fast;
   pa.ctl = m->ctl;
   pa.ship = ship_args(m, 0, 0);
   pa.ship_blocks = 0;
@@ -1964,6 +1948,7 @@ static void plan_access(bolt_map* m, const uint8_t* ops, const uint64_t* keys, c
   RemapArgs& ra = P.ra;
   ra.enabled = !P.fast;
   ra.ctl = m->ctl;
+  ra.chosen = bs.chosen;
   ra.keys = keys;
   ra.vals_in = vin;
   ra.leader = bs.leader;
@@ -2099,11 +2084,16 @@ __global__ __launch_bounds__(1024) void k_acc_watch(const uint32_t* __restrict__
 
 // The access pipeline for up to qmax commands of the maps of a device plan
 // table (count of them), every phase one launch.
-static void allow_group_lds();
+static void allow_big_lds();
+
+// The bins of the map's loads that the several-round remap keeps in LDS
+// (its dynamic LDS is 4 bytes a bin): all of them, or none.
+static uint32_t remap_lds_bins(const bolt_map* m) { return m->s.B <= kRemapLdsBins ? (uint32_t)m->s.B : 0; }
 
 static void launch_many(const AccessPlan& p0, const AccessPlan* tab, uint32_t C, uint32_t qmax, uint64_t lds,
-                        uint64_t fetch_lds, bool any_fast, bool any_slow, hipStream_t st, uint32_t ship_max = 0) {
-  allow_group_lds();
+                        uint64_t fetch_lds, bool any_slow, uint32_t remap_bins, hipStream_t st,
+                        uint32_t ship_max = 0) {
+  allow_big_lds();
   hipLaunchKernelGGL(k_acc_group<true>, dim3(kParts + group_prf_blocks(qmax), C), dim3(kDedupNT),
                      group_lds_bytes(qmax), st, p0.gr, tab);
   // each map's first ship_blocks workgroups of the fetch send its previous batch's pages
@@ -2113,8 +2103,11 @@ static void launch_many(const AccessPlan& p0, const AccessPlan* tab, uint32_t C,
   else
     hipLaunchKernelGGL((k_acc_fetch<true, false>), fgrid, dim3(256), 0, st, p0.fa, tab);
   hipLaunchKernelGGL(k_acc_resolve<true>, dim3((qmax + 63) / 64, C), dim3(64), 0, st, p0.rv, tab);
-  if (any_fast) hipLaunchKernelGGL(k_acc_place<true>, dim3((qmax + 63) / 64, C), dim3(64), 0, st, p0.pa, tab);
-  if (any_slow) hipLaunchKernelGGL(k_acc_remap<true>, dim3(1, C), dim3(kRemapNT), 0, st, p0.ra, tab);
+  if (any_slow)
+    hipLaunchKernelGGL(k_acc_remap<true>, dim3(1, C), dim3(kRemapNT), 4ull * remap_bins, st, p0.ra, tab, 0u,
+                       remap_bins);
+  hipLaunchKernelGGL(k_acc_place<true>, dim3((qmax + 63) / 64, C), dim3(64), 0, st, p0.pa, tab);
+  if (any_slow) hipLaunchKernelGGL(k_acc_remap<true>, dim3(1, C), dim3(kRemapNT), 0, st, p0.ra, tab, 1u, 0u);
   if (fetch_lds)  // a sealed map among them
     hipLaunchKernelGGL((k_acc_compose<true, true>), dim3(3 * qmax, C), dim3(64), lds, st, p0.wa, tab);
   else
@@ -2122,8 +2115,9 @@ static void launch_many(const AccessPlan& p0, const AccessPlan* tab, uint32_t C,
   hipLaunchKernelGGL(k_acc_finish<true>, dim3((qmax + 255) / 256, C), dim3(256), 0, st, p0.fn, tab);
 }
 
-// The dedup kernel's dynamic LDS reaches 96 KiB for the largest batches.
-static void allow_group_lds() {
+// The dedup kernel's dynamic LDS reaches 96 KiB for the largest batches,
+// the several-round remap's 96 KiB for the largest maps it keeps in LDS.
+static void allow_big_lds() {
   static std::once_flag once;
   std::call_once(once, [] {
     const int bytes = (int)group_lds_bytes(kMaxBatch);
@@ -2131,6 +2125,11 @@ static void allow_group_lds() {
                               hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
     (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_acc_group<true>),
                               hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    const int rbytes = (int)(4 * kRemapLdsBins);
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_acc_remap<false>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, rbytes);
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_acc_remap<true>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, rbytes);
   });
 }
 
@@ -2175,11 +2174,11 @@ static int run_access_graph(bolt_map* m, AccessPlan& P, hipStream_t st) {
   AccessPlan* tab = static_cast<AccessPlan*>(m->gplan);
   if (flush_ship(m, st)) return BOLT_EHIP;
   if (!m->gexec[cls]) {
-    // both remap forms are in the graph; the plan's flags pick one per call
+    // the several-round kernels are in the graph too; the plan's flags say whether they run
     hipStream_t cs = m->side;
     hipGraph_t g = nullptr;
     if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) return BOLT_EHIP;
-    launch_many(P, tab, 1, 1u << cls, P.wb_lds, P.fetch_lds, true, true, cs);
+    launch_many(P, tab, 1, 1u << cls, P.wb_lds, P.fetch_lds, true, remap_lds_bins(m), cs);
     if (hipStreamEndCapture(cs, &g) != hipSuccess || !g) return BOLT_EHIP;
     hipGraphExec_t ex = nullptr;
     const hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
@@ -2225,7 +2224,7 @@ int run_access(bolt_map* m, const uint8_t* ops, const uint64_t* keys, const void
     return rc;
   }
   const AccessPlan* none = nullptr;
-  allow_group_lds();
+  allow_big_lds();
   // A large batch on a pinned host store rebuilds its observable pages into
   // its half of the outbox, and the next batch's kernels (or a flush) send
   // them.  Small batches and device stores, with no link time to hide, write
@@ -2279,10 +2278,11 @@ int run_access(bolt_map* m, const uint8_t* ops, const uint64_t* keys, const void
   }
   {
     TimedScope ts(m->timer, kkAccRemap, st);
-    if (P.fast)
-      hipLaunchKernelGGL(k_acc_place<false>, dim3(P.pa.ship_blocks + (q + 63) / 64), dim3(64), 0, st, P.pa, none);
-    else
-      hipLaunchKernelGGL(k_acc_remap<false>, dim3(1), dim3(kRemapNT), 0, st, P.ra, none);
+    if (!P.fast)
+      hipLaunchKernelGGL(k_acc_remap<false>, dim3(1), dim3(kRemapNT), 4ull * remap_lds_bins(m), st, P.ra, none, 0u,
+                         remap_lds_bins(m));
+    hipLaunchKernelGGL(k_acc_place<false>, dim3(P.pa.ship_blocks + (q + 63) / 64), dim3(64), 0, st, P.pa, none);
+    if (!P.fast) hipLaunchKernelGGL(k_acc_remap<false>, dim3(1), dim3(kRemapNT), 0, st, P.ra, none, 1u, 0u);
   }
   P.wa.direct = defer ? 0 : 1;
   {
@@ -2318,7 +2318,8 @@ int run_access_many(bolt_map* const* maps, const bolt_batch* batches, uint32_t c
   std::vector<AccessPlan> plans(count);
   uint32_t qmax = 0, ship_max = 0;
   uint64_t lds = 0, flds = 0;
-  bool any_fast = false, any_slow = false;
+  bool any_slow = false;
+  uint32_t remap_bins = 0;
   std::vector<uint8_t> defer(count, 0);
   for (uint32_t i = 0; i < count; ++i) {
     const bolt_batch& b = batches[i];
@@ -2342,8 +2343,8 @@ int run_access_many(bolt_map* const* maps, const bolt_batch* batches, uint32_t c
     qmax = b.q > qmax ? b.q : qmax;
     lds = plans[i].wb_lds > lds ? plans[i].wb_lds : lds;
     flds = plans[i].fetch_lds > flds ? plans[i].fetch_lds : flds;
-    any_fast |= plans[i].fast != 0;
     any_slow |= plans[i].fast == 0;
+    if (!plans[i].fast) remap_bins = std::max(remap_bins, remap_lds_bins(m));
   }
   AccessPlan* tab = nullptr;
   const size_t bytes = sizeof(AccessPlan) * count;
@@ -2352,7 +2353,7 @@ int run_access_many(bolt_map* const* maps, const bolt_batch* batches, uint32_t c
     (void)hipFreeAsync(tab, st);
     return BOLT_EHIP;
   }
-  launch_many(plans[0], tab, count, qmax, lds, flds, any_fast, any_slow, st, ship_max);
+  launch_many(plans[0], tab, count, qmax, lds, flds, any_slow, remap_bins, st, ship_max);
   for (uint32_t i = 0; i < count; ++i) {
     maps[i]->ship_q = defer[i] ? batches[i].q : 0;
     maps[i]->ship_from = 0;

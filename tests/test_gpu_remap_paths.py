@@ -1,11 +1,11 @@
 """The several-round remap (a batch with more keys to place than one P2C
 round of ceil(B/16) holds; Alg. 1's P2C_load_balance per key, in rounds in
-command order) runs three ways on the GPU, chosen by the map's bin count:
-rounds of at most 64 keys on one wave with the loads in LDS (B <= 1024),
-workgroup rounds with the loads in LDS (B <= 7936), and workgroup rounds on
-the loads in HBM.  Each side of both boundaries, alone and in one many-map
-call, against the oracle bit for bit (answers, pages, HBM bins, loads,
-stash, position map, trace)."""
+command order) runs two ways on the GPU, chosen by the map's bin count: one
+wave with the loads in LDS, one to kWaveKeys keys per lane and round
+(B <= 24576), or the workgroup on the loads in HBM.  Each side of the
+boundaries (one key per lane or two; the largest map kept in LDS and the
+next), alone and in one many-map call, against the oracle bit for bit
+(answers, pages, HBM bins, loads, stash, position map, trace)."""
 import numpy as np
 import pytest
 
@@ -23,9 +23,10 @@ def _cuda():
     import paper_2509_01742_amd  # noqa: F401  (fails loudly when the library is missing)
 
 
-# capacities whose bin count (c = 8) sits on each side of the two boundaries
-CAPS = [(8 * 1024, "one wave, LDS loads"), (8 * 1040, "workgroup, LDS loads"), (8 * 7936, "workgroup, LDS loads"),
-        (8 * 7952, "workgroup, HBM loads")]
+# capacities whose bin count (c = 8) sits on each side of the boundaries
+CAPS = [(8 * 1024, "one key a lane, LDS loads"), (8 * 1040, "two keys a lane, LDS loads"),
+        (8 * 7952, "eight keys a lane, LDS loads"), (8 * 24576, "24 keys a lane, LDS loads"),
+        (8 * 24592, "workgroup, HBM loads")]
 
 
 def _batch(rng, present, fresh, q, vs, cap):
@@ -72,7 +73,7 @@ def test_several_round_remaps_in_one_many_map_call():
     import paper_2509_01742_amd as B
 
     vs = 8
-    specs = [(128 * 8, 0), (1024 * 8, 200), (1040 * 8, 0), (7936 * 8, 500), (7952 * 8, 200), (1 << 17, 0)]
+    specs = [(128 * 8, 0), (1024 * 8, 200), (1040 * 8, 0), (7952 * 8, 500), (24576 * 8, 200), (24592 * 8, 0)]
     twins, present = [], []
     for j, (cap, alpha) in enumerate(specs):
         t = Twin(cap, vs, alpha_permille=alpha, key=bytes((9 * j + i) & 255 for i in range(32)))
