@@ -766,6 +766,8 @@ def run_serving_sealed(B, n_req=4000, seed=0xB0170000 + 56):
     sealed beforehand by the client helper (a map's k-th request sealed as
     request k), drained as fast as the loop goes; against the same backlog
     in plain commands on plain maps."""
+    import ctypes as C
+
     import synth
 
     rng = np.random.Generator(np.random.PCG64(seed))
@@ -804,13 +806,29 @@ def run_serving_sealed(B, n_req=4000, seed=0xB0170000 + 56):
                 seq[j] += 1
                 recs.append(B.seal_requests(skey, seq[j], ops, keys, vals, vs))
             out["client_seal_s"] = round(time.perf_counter() - t, 2)
+        # every request's buffers exist before the clock starts, and the
+        # backlog goes in through the C calls directly, so that the loop finds
+        # it queued rather than trickling in behind the submissions
+        if sealed:
+            bufs = [(np.ascontiguousarray(recs[r], dtype=np.uint8), np.zeros((ops.size, 24 + vs), np.uint8))
+                    for r, (j, ops, keys, vals) in enumerate(reqs)]
+        else:
+            bufs = [(np.ascontiguousarray(ops), np.ascontiguousarray(keys, dtype=np.uint64),
+                     np.ascontiguousarray(vals), np.zeros((ops.size, vs), np.uint8), np.zeros(ops.size, np.uint8))
+                    for j, ops, keys, vals in reqs]
+        tk = C.c_uint64()
         srv.reset_stats()
         now = B.bolt_now_ns()
         for r, (j, ops, keys, vals) in enumerate(reqs):
+            b = bufs[r]
             if sealed:
-                srv.submit_sealed(ids[j], recs[r], vs, arrival_ns=now)
+                rc = B.bolt_server_submit_sealed(srv.h, ids[j], b[0].ctypes.data, ops.size, b[1].ctypes.data, now,
+                                                 C.byref(tk))
             else:
-                srv.submit(ids[j], ops, keys, vals, arrival_ns=now)
+                rc = B.bolt_server_submit(srv.h, ids[j], b[0].ctypes.data, b[1].ctypes.data, b[2].ctypes.data,
+                                          b[3].ctypes.data, b[4].ctypes.data, ops.size, now, C.byref(tk))
+            if rc != 0:
+                raise RuntimeError("submit: %d" % rc)
         B.check(srv.drain(300000), "drain")
         st = srv.stats()
         if st["failed"] or st["completed"] != n_req:
