@@ -192,24 +192,8 @@ __device__ __forceinline__ void wave_count(uint32_t* ctr, bool flag) {
 }
 
 // Stash pool: a bitmap of used entries (bits past the pool size are kept
-// set).  Allocation probes words from a hashed start; every thread claims
-// its own bit with atomicOr, so concurrent allocations do not contend on
-// one counter.  Returns kNone when `max_probe` words are all full.
-__device__ __forceinline__ uint32_t pool_alloc(uint64_t* used, uint64_t nwords, uint64_t start, uint32_t max_probe) {
-  uint64_t w = start % nwords;
-  for (uint32_t probe = 0; probe < max_probe; ++probe) {
-    uint64_t cur = __hip_atomic_load(&used[w], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    while (~cur) {
-      const uint64_t bit = ~cur & (0ull - ~cur);  // lowest clear bit
-      const uint64_t old = atomicOr((unsigned long long*)&used[w], (unsigned long long)bit);
-      if (!(old & bit)) return (uint32_t)(w * 64 + __builtin_ctzll(bit));
-      cur = old | bit;
-    }
-    w = w + 1 == nwords ? 0 : w + 1;
-  }
-  return kNone;
-}
-
+// set).  The place step takes entries a wave at a time (pool_alloc_wave);
+// the rebuild frees them here.
 __device__ __forceinline__ void pool_free(uint64_t* used, uint32_t e) {
   atomicAnd((unsigned long long*)&used[e >> 6], ~(1ull << (e & 63)));
 }

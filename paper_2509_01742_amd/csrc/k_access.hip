@@ -305,6 +305,80 @@ __device__ __forceinline__ uint32_t wave_incl_sum(uint32_t x) {
   return x;
 }
 
+// Position of the k-th (from 0) set bit of x; k < popcount(x).
+__device__ __forceinline__ uint32_t select_set_bit(uint64_t x, uint32_t k) {
+  uint32_t pos = 0;
+#pragma unroll
+  for (uint32_t half = 32; half >= 1; half >>= 1) {
+    const uint32_t c = (uint32_t)__popcll(x & ((1ull << half) - 1));
+    if (k >= c) {
+      k -= c;
+      x >>= half;
+      pos += half;
+    }
+  }
+  return pos;
+}
+
+// Stash-pool entries for the lanes of a wave that want one (every lane of
+// the wave calls this).  The wave reads a window of up to 64 consecutive
+// bitmap words at once, starting at `start`, hands the lanes that still need
+// an entry the free bits of the window in order, and each word's lane sets
+// the bits it handed out with one atomicOr: one atomic per word for the
+// wave, where an atomic per lane would queue dozens on the few lines of a
+// small map's bitmap.  A lane whose bit another wave took first tries again;
+// an empty window moves the wave on.  kNone for a lane only when every word
+// was seen full in a row (no entry is freed while entries are taken).  Each
+// pass takes a bit or moves on, so the loop ends within 65 * nwords + 64.
+__device__ __forceinline__ uint32_t pool_alloc_wave(uint64_t* used, uint64_t nwords, uint64_t start, bool want) {
+  const uint32_t lane = threadIdx.x & 63;
+  const uint64_t below = (1ull << lane) - 1;
+  uint64_t need = __ballot(want);
+  uint32_t got = kNone;
+  const uint32_t span = nwords < 64 ? (uint32_t)nwords : 64u;
+  uint64_t w0 = start % nwords, empty = 0;
+  for (uint64_t it = 0; need && it < 65 * nwords + 64; ++it) {
+    const uint64_t w = (w0 + lane) % nwords;
+    const uint64_t cur = lane < span ? __hip_atomic_load(&used[w], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : ~0ull;
+    const uint32_t fc = (uint32_t)__popcll(~cur);
+    const uint32_t incl = wave_incl_sum(fc), excl = incl - fc;
+    const uint32_t total = (uint32_t)__shfl((int)incl, 63, 64);
+    if (total == 0) {  // the same for the whole wave
+      w0 = (w0 + span) % nwords;
+      empty += span;
+      if (empty >= nwords) break;
+      continue;
+    }
+    empty = 0;
+    // the pending lanes' ranks 0 .. min(npend, total) - 1 go to the words
+    // in order, the lowest free bits of each word first
+    const uint32_t npend = (uint32_t)__popcll(need);
+    const uint32_t g = npend > excl ? (npend - excl < fc ? npend - excl : fc) : 0;
+    uint64_t old = 0;
+    if (g) {
+      const uint32_t top = select_set_bit(~cur, g - 1);
+      const uint64_t mask = ~cur & (top == 63 ? ~0ull : ((2ull << top) - 1));
+      old = atomicOr((unsigned long long*)&used[w], (unsigned long long)mask);
+    }
+    const uint32_t r = (uint32_t)__popcll(need & below);
+    uint32_t j = 0;  // the last lane whose word's ranks start at or below r
+#pragma unroll
+    for (uint32_t step = 32; step >= 1; step >>= 1) {
+      const uint32_t c = j + step;
+      const uint32_t ec = (uint32_t)__shfl((int)excl, (int)(c < 64 ? c : 63), 64);
+      if (c < 64 && ec <= r) j = c;
+    }
+    const uint64_t cur_j = __shfl(cur, (int)j, 64), old_j = __shfl(old, (int)j, 64), w_j = __shfl(w, (int)j, 64);
+    const uint32_t excl_j = (uint32_t)__shfl((int)excl, (int)j, 64);
+    if (((need >> lane) & 1) && r < npend && r < total) {
+      const uint32_t pos = select_set_bit(~cur_j, r - excl_j);
+      if (!((old_j >> pos) & 1)) got = (uint32_t)(w_j * 64 + pos);
+    }
+    need &= ~__ballot(got != kNone);
+  }
+  return got;
+}
+
 // Block-wide exclusive scans over one value per thread (NT threads).
 template <int NT, bool MAX>
 __device__ uint32_t block_excl(uint32_t x, uint32_t* total) {
@@ -1056,21 +1130,23 @@ __global__ __launch_bounds__(256) void k_acc_resolve(ResolveArgs a1, const Acces
 
 // Command i's placement, by one thread; every lane of the wave calls it.
 __device__ __forceinline__ void place_cmd(const PlaceArgs& a, uint32_t i) {
-  if (a.ctl->reject == a.epoch || a.ctl->err) return;
+  if (a.ctl->reject == a.epoch || a.ctl->err) return;  // the same for the whole wave
   bool placed = false, ins = false, to_hbm = false;
+  uint32_t fin = 0, b = 0, lw = kNone, old = 0, ls = 0;
+  uint64_t key = 0;
   if (i < a.q) {
     a.cand_bin[2 * a.q + i] = kNone;
     a.rowsel[i] = kNone;
-    const uint32_t fin = a.leader[i] == i ? a.fin[i] : 0;
+    fin = a.leader[i] == i ? a.fin[i] : 0;
     if (fin & 1) {
       // Every atomic and load that does not wait on another is issued
       // first; the capacity checks come last (a failure poisons the map,
       // whose state is then never read again).
-      const uint32_t b = a.chosen[i];
-      const uint32_t lw = a.lastw[i];
-      const uint64_t key = a.keys[i];
-      const uint32_t old = a.several ? 0 : atomicAdd(&a.load[b], 1u);
-      const uint32_t ls = atomicAdd(&a.rev_cnt[b], 1u);
+      b = a.chosen[i];
+      lw = a.lastw[i];
+      key = a.keys[i];
+      old = a.several ? 0 : atomicAdd(&a.load[b], 1u);
+      ls = atomicAdd(&a.rev_cnt[b], 1u);
       if (b < a.K && !a.decomp) {  // HBM bins are rebuilt in this batch
         a.cand_bin[2 * a.q + i] = b;
         atomicMax((unsigned long long*)&a.claim[b], (unsigned long long)claim_tag(a.epoch, 2 * a.q + i));
@@ -1094,20 +1170,24 @@ __device__ __forceinline__ void place_cmd(const PlaceArgs& a, uint32_t i) {
         a.rowsel[i] = best;
         ins = true;
       }
-      // the item goes to a fresh stash entry listed under bin b
-      const uint32_t e = a.decomp ? ring_alloc(a.ctl, a.ring, a.P)
-                                  : pool_alloc(a.st_used, a.PW, alloc_hash(a.epoch, i), (uint32_t)a.PW);
-      const uint64_t* src = lw != kNone ? a.vals_in + (uint64_t)lw * a.vw : a.fval + (uint64_t)i * a.vw;
-      if (e != kNone) {
-        a.st_key[e] = key;
-        for (uint32_t x = 0; x < a.vw; ++x) a.st_val[(uint64_t)e * a.vw + x] = src[x];
-        a.st_dest[e] = b;
-        a.st_dead[e] = 0;
-        if (ls < 2 * a.Z) a.rev_idx[(uint64_t)b * 2 * a.Z + ls] = e;
-      }
-      if ((!a.several && old + 1 > a.Z) || e == kNone || ls >= 2 * a.Z) set_err(a.ctl, kErrOverflow);
-      placed = true;
     }
+  }
+  // the item goes to a fresh stash entry listed under bin b (the wave takes
+  // its lanes' pool entries together, from a window where its index leads)
+  const uint32_t e_pool =
+      a.decomp ? kNone : pool_alloc_wave(a.st_used, a.PW, alloc_hash(a.epoch, i - (threadIdx.x & 63)), (fin & 1) != 0);
+  if (fin & 1) {
+    const uint32_t e = a.decomp ? ring_alloc(a.ctl, a.ring, a.P) : e_pool;
+    const uint64_t* src = lw != kNone ? a.vals_in + (uint64_t)lw * a.vw : a.fval + (uint64_t)i * a.vw;
+    if (e != kNone) {
+      a.st_key[e] = key;
+      for (uint32_t x = 0; x < a.vw; ++x) a.st_val[(uint64_t)e * a.vw + x] = src[x];
+      a.st_dest[e] = b;
+      a.st_dead[e] = 0;
+      if (ls < 2 * a.Z) a.rev_idx[(uint64_t)b * 2 * a.Z + ls] = e;
+    }
+    if ((!a.several && old + 1 > a.Z) || e == kNone || ls >= 2 * a.Z) set_err(a.ctl, kErrOverflow);
+    placed = true;
   }
   if (!a.several) {  // k_acc_remap counts the several-round path's
     wave_count(&a.ctl->b_place, placed);
