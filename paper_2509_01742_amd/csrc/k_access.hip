@@ -1276,13 +1276,37 @@ __global__ __launch_bounds__(kRemapNT) void k_acc_remap(RemapArgs a1, const Acce
         s_list[o++] = rp.x | (rp.y << 16);
       }
       __syncthreads();
-      if (threadIdx.x < 64) {
-        // Lanes without a key read valid bins (list entries only hold bins),
-        // add zero and write to the spare last list entry.  Adds return
-        // nothing: a bin past Z during the rounds is past it after them, as
-        // loads only grow here, and is found then.
+      const uint32_t K = (uint32_t)((rs + 63) / 64);  // keys a lane per round, the same for the workgroup
+      if (threadIdx.x < 64 && K == 1) {
+        // One key a lane: a round waits on one LDS round trip, its loads;
+        // its list entries were read during the round before.  Lanes without
+        // a key read valid bins (list entries only hold bins), add zero and
+        // write to the spare last list entry.  Adds return nothing: a bin
+        // past Z during the rounds is past it after them, as loads only grow
+        // here, and is found then.
         const uint32_t lane = threadIdx.x;
-        const uint32_t K = (uint32_t)((rs + 63) / 64);  // the same for the whole wave
+        const bool in_round = lane < rs;
+        uint32_t pk = in_round && lane < nplace ? s_list[lane] : 0;
+        __builtin_amdgcn_s_waitcnt(0);  // nothing in flight when the loop starts
+        for (uint32_t r0 = 0; r0 < nplace; r0 += (uint32_t)rs) {
+          const uint32_t k = r0 + lane, kn = k + (uint32_t)rs;
+          const bool mine = in_round && k < nplace;
+          const uint32_t p1 = pk & 0xFFFFu, p2 = pk >> 16;
+          // the next round's entries first: in order, they are back by the
+          // time this round's loads are
+          const uint32_t pk_next = s_list[kn < nplace ? kn : 0];
+          __builtin_amdgcn_sched_barrier(0);
+          const uint32_t l1 = s_load[p1], l2 = s_load[p2];
+          const uint32_t ch = l2 < l1 ? p2 : p1;
+          __builtin_amdgcn_wave_barrier();
+          atomicAdd(&s_load[ch], mine ? 1u : 0u);
+          s_list[mine ? k : kMaxBatch] = ch;
+          __builtin_amdgcn_wave_barrier();
+          pk = in_round ? pk_next : 0;
+        }
+      } else if (threadIdx.x < 64) {
+        // Several keys a lane (the same rules)
+        const uint32_t lane = threadIdx.x;
         for (uint32_t r0 = 0; r0 < nplace; r0 += (uint32_t)rs) {
           uint32_t ch[kWaveKeys];
           bool mine[kWaveKeys];
@@ -1310,15 +1334,19 @@ __global__ __launch_bounds__(kRemapNT) void k_acc_remap(RemapArgs a1, const Acce
           __builtin_amdgcn_sched_barrier(0);
           asm volatile("" ::: "memory");
         }
-        bool over = false;
-        for (uint32_t b = lane; b < a.B; b += 64) over |= s_load[b] > a.Z;
-        if (over) set_err(a.ctl, kErrOverflow);
       }
       __syncthreads();
       o = place0;
       for (uint32_t t = 0; t < kRemapPer; ++t)
         if (fin[t] & 1) chosen[t] = s_list[o++];
-      for (uint32_t b = threadIdx.x; b < a.B; b += kRemapNT) a.load[b] = s_load[b];
+      // the loads go back, and a bin past Z is found on the way
+      bool over = false;
+      for (uint32_t b = threadIdx.x; b < a.B; b += kRemapNT) {
+        const uint32_t l = s_load[b];
+        over |= l > a.Z;
+        a.load[b] = l;
+      }
+      if (over) set_err(a.ctl, kErrOverflow);
     } else {
       // The loads in global memory: the workgroup runs the rounds, its
       // threads' keys of a round read, a barrier, then the adds.
@@ -1336,14 +1364,13 @@ __global__ __launch_bounds__(kRemapNT) void k_acc_remap(RemapArgs a1, const Acce
         }
         __syncthreads();
         o = place0;
+        bool over = false;  // one error report after the adds, so that they issue together
         for (uint32_t t = 0; t < kRemapPer; ++t) {
           if (!(fin[t] & 1)) continue;
-          if (o >= r0 && o < r0 + rs) {
-            const uint32_t old = atomicAdd(&a.load[chosen[t]], 1u);
-            if (old + 1 > a.Z) set_err(a.ctl, kErrOverflow);
-          }
+          if (o >= r0 && o < r0 + rs) over |= atomicAdd(&a.load[chosen[t]], 1u) + 1 > a.Z;
           ++o;
         }
+        if (over) set_err(a.ctl, kErrOverflow);
         __threadfence();
         __syncthreads();
       }
