@@ -84,7 +84,7 @@ uint64_t device_bytes(const bolt_params* p, const Sizes& s) {
   else b += s.P * 4 + 3ull * kMaxBatch * (2 * s.Z * 4 + 1);  // the free-address ring, staged frees
   if (p->observable == BOLT_OBS_DEVICE) b += s.M * (s.page_bytes + ((p->flags & BOLT_F_SEAL) ? 16 : 0));
   if (p->flags & BOLT_F_SEAL) b += s.M * 8;  // write counts
-  b += s.B * 4;                      // load
+  b += s.B * 8;                      // load, and the loads placement starts from
   b += s.R * s.W * 16 + s.R * 4;     // position map
   b += s.P * (8 + s.vs + 4 + 4) + s.PW * 8;  // stash pool + bitmap
   b += s.B * 4 + s.B * 2 * s.Z * 4;  // reverse index
@@ -248,6 +248,7 @@ int bolt_create(const bolt_params* p, void* hip_stream, bolt_map** out) {
   else
     rc = rc ? rc : dalloc(m, &m->hbm, s.K * s.page_bytes);
   rc = rc ? rc : dalloc(m, &m->load, s.B * 4);
+  rc = rc ? rc : dalloc(m, &m->load0, s.B * 4);
   rc = rc ? rc : dalloc(m, &m->pm_key, s.R * s.W * 8);
   rc = rc ? rc : dalloc(m, &m->pm_pair, s.R * s.W * 8);
   rc = rc ? rc : dalloc(m, &m->pm_mask, s.R * 4);

@@ -102,6 +102,7 @@ struct bolt_map {
   uint8_t* hbm;       // K HBM bins (null in a decomposed store)
   uint32_t* ring;     // BOLT_F_DECOMPOSED: [P] the value pool's free-address ring, else null
   uint32_t* load;     // [B]
+  uint32_t* load0;    // [B] the loads a batch's placement starts from (removals in, adds not)
   uint64_t* pm_key;   // [R * W]
   uint2* pm_pair;     // [R * W]
   uint32_t* pm_mask;  // [R] used slots

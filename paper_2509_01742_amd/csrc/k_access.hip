@@ -87,6 +87,7 @@ struct FetchArgs {
   const uint64_t* st_val;
   uint32_t* st_dead;
   uint32_t* load;
+  uint32_t* load0;  // the loads placement starts from: removals go to both
   uint64_t* claim;
   uint64_t* rmask;
   uint64_t* stage;
@@ -108,6 +109,12 @@ struct FetchArgs {
   uint32_t ship_blocks;    // ... by the first ship_blocks workgroups
   uint32_t pre_host;       // 1: observable pages are read ahead too (device store)
   uint32_t decomp;         // BOLT_F_DECOMPOSED: an HBM bin is only its list (no page)
+  // one-round batches: a leader whose key is mapped and absent at the end
+  // of the batch deletes its map entry here (its last PUT/DEL, else whether
+  // it was found, decides), so that every delete is in before placement
+  uint32_t fast;
+  const uint32_t* lastw;
+  uint32_t* pm_mask_w;
 };
 
 struct ResolveArgs {
@@ -123,13 +130,12 @@ struct ResolveArgs {
   const uint32_t* found;
   const uint64_t* fval;
   const uint2* rpair;
-  const uint32_t* load;
+  const uint32_t* load;  // the loads as placement began
   uint32_t q, vw, fast, epoch;
   uint64_t* vals_out;
   uint8_t* status;
   uint32_t* fin;
   uint32_t* chosen;
-  uint32_t* pm_mask;
   ShipArgs ship;  // a slice of the previous batch's send, by the first ship_blocks workgroups
   uint32_t ship_blocks;
 };
@@ -236,6 +242,12 @@ struct WbArgs {
   uint32_t decomp;  // BOLT_F_DECOMPOSED: HBM bins keep their items listed; frees are staged for the ring
   uint32_t* rfree;    // [3Q][2Z] entries each rebuild slot returns to the ring
   uint8_t* rfree_n;   // [3Q] how many (at most 2Z <= 124)
+  // each placed key's bin, whose final load the next batch's placement starts from
+  const uint32_t* leader;
+  const uint32_t* fin;
+  const uint32_t* chosen;
+  const uint32_t* load;
+  uint32_t* load0;
 };
 
 
@@ -989,6 +1001,7 @@ __device__ __forceinline__ void fetch_cmd(const FetchArgs& a, uint32_t i, uint64
       if (lane == 0) {
         atomicOr((unsigned long long*)&a.rmask[b], (unsigned long long)(1ull << fslot));
         atomicSub(&a.load[b], 1u);
+        atomicSub(&a.load0[b], 1u);
       }
     } else if (search && (host || pooled)) {
       // the stash items listed for this bin (all of a decomposed HBM bin's items)
@@ -1012,6 +1025,7 @@ __device__ __forceinline__ void fetch_cmd(const FetchArgs& a, uint32_t i, uint64
         if (lane == 0) {
           a.st_dead[fe] = 1;
           atomicSub(&a.load[b], 1u);
+          atomicSub(&a.load0[b], 1u);
           if (pooled) atomicAdd(&a.ctlw->b_hbm_rm, 1u);
         }
       }
@@ -1023,6 +1037,13 @@ __device__ __forceinline__ void fetch_cmd(const FetchArgs& a, uint32_t i, uint64
     a.hslot[i] = hslot;
     a.found[i] = found;
     if (hit && !found) set_err(a.ctlw, kErrBroken);
+    if (a.fast && hit) {
+      const uint32_t lw = a.lastw[i];
+      if (!(lw != kNone ? a.ops[lw] == 1 : found)) {  // deletes come before the inserts of this batch
+        atomicAnd(&a.pm_mask_w[hrow], ~(1u << hslot));
+        atomicAdd(&a.ctlw->b_del, 1u);
+      }
+    }
   }
 }
 
@@ -1079,7 +1100,6 @@ __device__ __forceinline__ void resolve_cmd(const ResolveArgs& a, uint32_t i) {
     }
     return;
   }
-  bool del = false;
   if (live) {
     const uint32_t L = a.leader[i], w = a.prevw[i];
     const bool present = w != kNone ? a.ops[w] == 1 : a.found[L] != 0;
@@ -1099,19 +1119,12 @@ __device__ __forceinline__ void resolve_cmd(const ResolveArgs& a, uint32_t i) {
       const bool fp = lw != kNone ? a.ops[lw] == 1 : a.found[i] != 0;
       const bool h = a.hit[i] != 0;
       a.fin[i] = (fp ? 1u : 0u) | (h ? 2u : 0u);
-      if (a.fast) {
-        if (fp) {  // P2C over the post-removal loads (one round)
-          const uint2 rp = a.rpair[i];
-          a.chosen[i] = a.load[rp.y] < a.load[rp.x] ? rp.y : rp.x;
-        }
-        if (h && !fp) {  // deletes come before the inserts of this batch
-          atomicAnd(&a.pm_mask[a.hrow[i]], ~(1u << a.hslot[i]));
-          del = true;
-        }
+      if (a.fast && fp) {  // P2C over the post-removal loads (one round)
+        const uint2 rp = a.rpair[i];
+        a.chosen[i] = a.load[rp.y] < a.load[rp.x] ? rp.y : rp.x;
       }
     }
   }
-  if (a.fast) wave_count(&a.ctl->b_del, del);
 }
 
 template <bool MULTI>
@@ -1201,6 +1214,17 @@ __global__ __launch_bounds__(256) void k_acc_place(PlaceArgs a1, const AccessPla
   BOLT_PICK(PlaceArgs, pa);
   if (carry_ship<MULTI>(a.ship, a.ship_blocks)) return;
   place_cmd(a, (blockIdx.x - (MULTI ? 0 : a.ship_blocks)) * blockDim.x + threadIdx.x);
+}
+
+// Resolve and place in one launch (a one-map, one-round batch): each
+// thread's placement needs only its own command's final state and bin,
+// the choices read the loads as placement began (a copy the adds do not
+// touch), and the deletes were made by the fetch.
+__global__ __launch_bounds__(64) void k_acc_settle(ResolveArgs rv, PlaceArgs pa) {
+  if (carry_ship<false>(pa.ship, pa.ship_blocks)) return;
+  const uint32_t i = (blockIdx.x - pa.ship_blocks) * blockDim.x + threadIdx.x;
+  resolve_cmd(rv, i);
+  place_cmd(pa, i);
 }
 
 // ---------------------------------------------------------------------------
@@ -1459,6 +1483,15 @@ __device__ __forceinline__ void compose_slot(const WbArgs& a, uint32_t s, uint64
   if (lane == 0 && s < 2 * a.q) a.ship_page[s] = kNone;
   if (lane == 0 && s < 3 * a.q && a.decomp) a.rfree_n[s] = 0;  // this slot returns nothing unless it rebuilds
   if (s >= 3 * a.q || a.ctl->reject == a.epoch || a.ctl->err) return;  // whole wave
+  // The placement's adds are done: carry them into the copy.  Only a batch
+  // that went through (no reject, no error) has its final states and bins.
+  if (lane == 0 && s >= 2 * a.q) {
+    const uint32_t i = s - 2 * a.q;
+    if (a.leader[i] == i && (a.fin[i] & 1)) {
+      const uint32_t b = a.chosen[i];
+      a.load0[b] = a.load[b];
+    }
+  }
   const uint32_t b = a.cand_bin[s];
   if (b == kNone) return;  // whole wave
   const bool host = b >= a.K;
@@ -1957,6 +1990,10 @@ static void plan_access(bolt_map* m, const uint8_t* ops, const uint64_t* keys, c
   fa.st_val = reinterpret_cast<const uint64_t*>(m->st_val);
   fa.st_dead = m->st_dead;
   fa.load = m->load;
+  fa.load0 = m->load0;
+  fa.fast = fast ? 1 : 0;
+  fa.lastw = bs.lastw;
+  fa.pm_mask_w = m->pm_mask;
   fa.claim = m->claim;
   fa.rmask = m->rmask;
   fa.stage = reinterpret_cast<uint64_t*>(bs.stage);
@@ -1999,7 +2036,7 @@ static void plan_access(bolt_map* m, const uint8_t* ops, const uint64_t* keys, c
   rv.found = bs.found;
   rv.fval = fval;
   rv.rpair = bs.rpair;
-  rv.load = m->load;
+  rv.load = m->load0;  // the choice reads the loads as placement began
   rv.q = q;
   rv.vw = vw;
   rv.fast = P.fast;
@@ -2008,7 +2045,6 @@ static void plan_access(bolt_map* m, const uint8_t* ops, const uint64_t* keys, c
   rv.status = status;
   rv.fin = bs.fin;
   rv.chosen = bs.chosen;
-  rv.pm_mask = m->pm_mask;
 
   PlaceArgs& pa = P.pa;
   pa.several = !P.fast;
@@ -2102,6 +2138,11 @@ static void plan_access(bolt_map* m, const uint8_t* ops, const uint64_t* keys, c
   wa.K = s.K;
   wa.pw = s.page_bytes / 8;
   wa.cand_bin = bs.cand_bin;
+  wa.leader = bs.leader;
+  wa.fin = bs.fin;
+  wa.chosen = bs.chosen;
+  wa.load = m->load;
+  wa.load0 = m->load0;
   wa.claim = m->claim;
   wa.rmask = m->rmask;
   wa.stage = reinterpret_cast<const uint64_t*>(bs.stage);
@@ -2353,8 +2394,10 @@ int run_access(bolt_map* m, const uint8_t* ops, const uint64_t* keys, const void
     };
     if (end && !m->tags) {
       take(kShareGroup, P.gr.ship, P.gr.ship_blocks, kDedupNT / 64, 4 * kShipMaxBlocks);
-      take(kShareResolve, P.rv.ship, P.rv.ship_blocks, 1, 4 * kShipMaxBlocks);
-      if (P.fast) take(kSharePlace, P.pa.ship, P.pa.ship_blocks, 1, 4 * kShipMaxBlocks);
+      if (P.fast)  // resolve and place are one launch
+        take(kShareResolve + kSharePlace, P.pa.ship, P.pa.ship_blocks, 1, 4 * kShipMaxBlocks);
+      else
+        take(kShareResolve, P.rv.ship, P.rv.ship_blocks, 1, 4 * kShipMaxBlocks);
       // The rebuild's one-wave workgroups, a few slots per wave (its own
       // waves already fill the device); only when this batch rebuilds into
       // the outbox: a rebuild that writes the store itself could race the
@@ -2379,17 +2422,19 @@ int run_access(bolt_map* m, const uint8_t* ops, const uint64_t* keys, const void
     else
       hipLaunchKernelGGL((k_acc_fetch<false, false>), grid, dim3(256), 0, st, P.fa, none);
   }
-  {
-    TimedScope ts(m->timer, kkAccResolve, st);
-    hipLaunchKernelGGL(k_acc_resolve<false>, dim3(P.rv.ship_blocks + (q + 63) / 64), dim3(64), 0, st, P.rv, none);
-  }
-  {
+  if (P.fast) {
     TimedScope ts(m->timer, kkAccRemap, st);
-    if (!P.fast)
-      hipLaunchKernelGGL(k_acc_remap<false>, dim3(1), dim3(kRemapNT), 4ull * remap_lds_bins(m), st, P.ra, none, 0u,
-                         remap_lds_bins(m));
+    hipLaunchKernelGGL(k_acc_settle, dim3(P.pa.ship_blocks + (q + 63) / 64), dim3(64), 0, st, P.rv, P.pa);
+  } else {
+    {
+      TimedScope ts(m->timer, kkAccResolve, st);
+      hipLaunchKernelGGL(k_acc_resolve<false>, dim3(P.rv.ship_blocks + (q + 63) / 64), dim3(64), 0, st, P.rv, none);
+    }
+    TimedScope ts(m->timer, kkAccRemap, st);
+    hipLaunchKernelGGL(k_acc_remap<false>, dim3(1), dim3(kRemapNT), 4ull * remap_lds_bins(m), st, P.ra, none, 0u,
+                       remap_lds_bins(m));
     hipLaunchKernelGGL(k_acc_place<false>, dim3(P.pa.ship_blocks + (q + 63) / 64), dim3(64), 0, st, P.pa, none);
-    if (!P.fast) hipLaunchKernelGGL(k_acc_remap<false>, dim3(1), dim3(kRemapNT), 0, st, P.ra, none, 1u, 0u);
+    hipLaunchKernelGGL(k_acc_remap<false>, dim3(1), dim3(kRemapNT), 0, st, P.ra, none, 1u, 0u);
   }
   P.wa.direct = defer ? 0 : 1;
   {

@@ -78,6 +78,7 @@ struct BuildPlan {
   uint64_t* tags;  // BOLT_F_SEAL: [M][2] page tags (observable), else null
   uint64_t* pver;  // BOLT_F_SEAL: [M] page write counts
   uint32_t* load;
+  uint32_t* load0;  // the copy the access path's placement reads
   uint64_t* pm_key;
   uint2* pm_pair;
   uint32_t* pm_mask;
@@ -289,6 +290,7 @@ template <bool MULTI>
 __global__ void k_check_loads(BOLT_PLAN_ARGS) {
   BOLT_PLAN;
   uint64_t b = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (b < P.B) P.load0[b] = P.load[b];
   bool bad = b < P.B && P.load[b] > P.Z;
   if (__any(bad) && (threadIdx.x & 63) == 0) set_err(P.ctl, kErrOverflow);
 }
@@ -616,6 +618,7 @@ static void plan_build(bolt_map* m, const uint64_t* keys, const void* vals, uint
   P.tags = reinterpret_cast<uint64_t*>(m->tags);
   P.pver = m->pver;
   P.load = m->load;
+  P.load0 = m->load0;
   P.pm_key = m->pm_key;
   P.pm_pair = m->pm_pair;
   P.pm_mask = m->pm_mask;
