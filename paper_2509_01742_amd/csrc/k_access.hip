@@ -1089,9 +1089,16 @@ __device__ __forceinline__ bool pm_claim(uint32_t* pm_mask, uint64_t* pm_key, ui
 
 
 
+// What resolve hands a placement in the same thread: the command's final
+// state as place reads it (0 unless it leads its key) and the key's bin.
+struct Settled {
+  uint32_t fin = 0, chosen = 0;
+};
+
 // Command i's response and, for a leader, its key's final state, by one
-// thread (live: i < q); every lane of the wave calls it.
-__device__ __forceinline__ void resolve_cmd(const ResolveArgs& a, uint32_t i) {
+// thread (live: i < q); every lane of the wave calls it.  set, when given,
+// also receives the state and bin (a placement in the same thread).
+__device__ __forceinline__ void resolve_cmd(const ResolveArgs& a, uint32_t i, Settled* set = nullptr) {
   const bool live = i < a.q;
   if (a.ctl->reject == a.epoch || a.ctl->err) {
     if (live) {
@@ -1118,10 +1125,14 @@ __device__ __forceinline__ void resolve_cmd(const ResolveArgs& a, uint32_t i) {
       const uint32_t lw = a.lastw[i];
       const bool fp = lw != kNone ? a.ops[lw] == 1 : a.found[i] != 0;
       const bool h = a.hit[i] != 0;
-      a.fin[i] = (fp ? 1u : 0u) | (h ? 2u : 0u);
+      const uint32_t fin = (fp ? 1u : 0u) | (h ? 2u : 0u);
+      a.fin[i] = fin;
+      if (set) set->fin = fin;
       if (a.fast && fp) {  // P2C over the post-removal loads (one round)
         const uint2 rp = a.rpair[i];
-        a.chosen[i] = a.load[rp.y] < a.load[rp.x] ? rp.y : rp.x;
+        const uint32_t b = a.load[rp.y] < a.load[rp.x] ? rp.y : rp.x;
+        a.chosen[i] = b;
+        if (set) set->chosen = b;
       }
     }
   }
@@ -1142,7 +1153,9 @@ __global__ __launch_bounds__(256) void k_acc_resolve(ResolveArgs a1, const Acces
 
 
 // Command i's placement, by one thread; every lane of the wave calls it.
-__device__ __forceinline__ void place_cmd(const PlaceArgs& a, uint32_t i) {
+// in: the state and bin from resolve_cmd in the same thread (else they are
+// read from the batch's arrays).
+__device__ __forceinline__ void place_cmd(const PlaceArgs& a, uint32_t i, const Settled* in = nullptr) {
   if (a.ctl->reject == a.epoch || a.ctl->err) return;  // the same for the whole wave
   bool placed = false, ins = false, to_hbm = false;
   uint32_t fin = 0, b = 0, lw = kNone, old = 0, ls = 0;
@@ -1150,12 +1163,12 @@ __device__ __forceinline__ void place_cmd(const PlaceArgs& a, uint32_t i) {
   if (i < a.q) {
     a.cand_bin[2 * a.q + i] = kNone;
     a.rowsel[i] = kNone;
-    fin = a.leader[i] == i ? a.fin[i] : 0;
+    fin = in ? in->fin : (a.leader[i] == i ? a.fin[i] : 0);
     if (fin & 1) {
       // Every atomic and load that does not wait on another is issued
       // first; the capacity checks come last (a failure poisons the map,
       // whose state is then never read again).
-      b = a.chosen[i];
+      b = in ? in->chosen : a.chosen[i];
       lw = a.lastw[i];
       key = a.keys[i];
       old = a.several ? 0 : atomicAdd(&a.load[b], 1u);
@@ -1223,8 +1236,9 @@ __global__ __launch_bounds__(256) void k_acc_place(PlaceArgs a1, const AccessPla
 __global__ __launch_bounds__(64) void k_acc_settle(ResolveArgs rv, PlaceArgs pa) {
   if (carry_ship<false>(pa.ship, pa.ship_blocks)) return;
   const uint32_t i = (blockIdx.x - pa.ship_blocks) * blockDim.x + threadIdx.x;
-  resolve_cmd(rv, i);
-  place_cmd(pa, i);
+  Settled st;
+  resolve_cmd(rv, i, &st);
+  place_cmd(pa, i, &st);
 }
 
 // ---------------------------------------------------------------------------
@@ -1880,9 +1894,11 @@ __global__ __launch_bounds__(kSoloNT) void k_acc_solo(GroupArgs gr, FetchArgs fa
   else
     solo_warm(fa, pa, wave, lane);
   solo_step();
-  if (wave == 0) resolve_cmd(rv, lane);
-  solo_step();
-  if (wave == 0) place_cmd(pa, lane);
+  if (wave == 0) {  // resolve and place in the same thread
+    Settled st;
+    resolve_cmd(rv, lane, &st);
+    place_cmd(pa, lane, &st);
+  }
   solo_step();
   compose_slot<false>(wa, wave, sdyn + (uint64_t)wave * (wb_stride / 8));
   solo_step();
